@@ -1,0 +1,321 @@
+/*
+ * gpet.h -- C ABI of the MI355X (gfx950) multi-layer PET Monte Carlo library.
+ *
+ * Monte Carlo transport of back-to-back 511 keV annihilation photon pairs
+ * through an optional voxelized phantom and a parameterized detector
+ * hierarchy panel -> module -> layer -> crystal, followed by a crystal-level
+ * digitizer (per-crystal energy summing, Gaussian energy blurring, energy
+ * window, coincidence sorting).  Method: "Extending gPET for Multi-Layer PET
+ * Simulation", Sec. 2.1 (hierarchy, inputs, layer selection by depth during
+ * in-panel Woodcock transport) and Sec. 2.3 (source, 3 ns coincidence
+ * window, 16 % energy resolution).
+ *
+ * Conventions
+ *  - Units: mm, keV, ps, g/cm^3.  Arithmetic on the GPU is FP32 (event times
+ *    are integer ps).
+ *  - Every call returns gpet_status; GPET_OK is 0, errors are negative and
+ *    gpet_last_error() returns a message for the context.  No C++ exception
+ *    crosses this boundary.
+ *  - Input descriptors (materials, scanner, phantom, source) are HOST memory
+ *    and are copied during the call; the caller keeps ownership.
+ *  - Output buffers (hits, singles, coincidences, tallies) are caller-owned
+ *    DEVICE memory on the context's device, passed as raw pointers plus a
+ *    capacity.  When an output needs more room than its capacity the call
+ *    writes nothing past the capacity, stores the required size in `count`
+ *    and returns GPET_ERR_CAPACITY; a rerun with a larger buffer gives the
+ *    same results (all random numbers come from counter-based Philox streams
+ *    keyed by the seed and the event id).
+ *  - All work is ordered on the context's HIP stream.  gpet_transport and
+ *    gpet_digitize synchronize that stream before returning counts.
+ *  - A context is used by one host thread at a time.
+ *  - The library owns internal device scratch (tables, sort buffers); it is
+ *    freed by gpet_ctx_destroy.
+ */
+#ifndef GPET_H
+#define GPET_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gpet_status;
+#define GPET_OK 0
+#define GPET_ERR_ARG (-1)
+#define GPET_ERR_GEOMETRY (-2)
+#define GPET_ERR_STATE (-3)
+#define GPET_ERR_CAPACITY (-4)
+#define GPET_ERR_HIP (-5)
+#define GPET_ERR_UNSUPPORTED (-6)
+
+#define GPET_MAX_ELEMENTS 8
+#define GPET_MAX_MATERIALS 8
+#define GPET_MAX_LAYERS 4
+#define GPET_MAX_PANELS 64
+#define GPET_MAX_RODS 1024
+
+/* interaction processes a material takes part in (bit mask) */
+#define GPET_PROC_PHOTOELECTRIC 1u
+#define GPET_PROC_COMPTON 2u
+#define GPET_PROC_RAYLEIGH 4u
+
+typedef struct gpet_ctx gpet_ctx;
+
+/* Create a context on HIP device `device`, ordering its work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+gpet_status gpet_ctx_create(int device, void *hip_stream, gpet_ctx **out);
+void gpet_ctx_destroy(gpet_ctx *ctx);
+const char *gpet_last_error(const gpet_ctx *ctx);
+/* Change the stream later work is ordered on. */
+gpet_status gpet_ctx_set_stream(gpet_ctx *ctx, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Materials and physics.  Crystal and inter-crystal interval materials and  */
+/* their densities are detector inputs (Sec. 2.1).  Attenuation per process: */
+/*   Compton       Klein-Nishina per electron,                             */
+/*   photoelectric k_pe * Z^4 / E^3 per atom (E in MeV),                    */
+/*   Rayleigh      k_rayleigh * Z^2 / E^2 per atom,                         */
+/* tabulated on 1 keV nodes 1..511 keV with linear interpolation.           */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double density_g_cm3;  /* nominal density (detector); phantom voxels carry their own */
+  int32_t n_elements;    /* 1..GPET_MAX_ELEMENTS */
+  uint32_t processes;    /* GPET_PROC_* mask */
+  int32_t Z[GPET_MAX_ELEMENTS];
+  double A[GPET_MAX_ELEMENTS];             /* g/mol */
+  double mass_fraction[GPET_MAX_ELEMENTS]; /* sums to 1 */
+} gpet_material;
+
+typedef struct {
+  double k_pe;        /* cm^2 MeV^3 per atom per Z^4 */
+  double k_rayleigh;  /* cm^2 MeV^2 per atom per Z^2 (0 disables Rayleigh) */
+  double e_cut_kev;   /* photons below this energy deposit it locally and stop */
+} gpet_physics;
+
+/* Replaces the material list (ids 0..n-1).  Invalidates geometry and phantom. */
+gpet_status gpet_materials_set(gpet_ctx *ctx, int32_t n, const gpet_material *materials,
+                               const gpet_physics *physics);
+
+/* ---------------------------------------------------------------------- */
+/* Detector geometry (Sec. 2.1, Fig. 1): panels placed in repetition mode    */
+/* (count and rotation step) or non-repetition mode (explicit pose per      */
+/* panel); each panel holds a grid of modules; each module an ordered list  */
+/* of layers along the panel depth; each layer its own crystal array.       */
+/*                                                                          */
+/* Panel-local frame: depth along the panel normal pointing away from the   */
+/* axis (0 at the front face), t tangential, a axial.  The panel box is     */
+/* depth [0, depth_mm) x t [-width/2, width/2) x a [-length/2, length/2).   */
+/* Modules tile the (t, a) face, centred, with gaps between them.  Layer l  */
+/* covers depth [depth0, depth0 + thickness); its crystal (i_t, i_a) lies   */
+/* in the pitch cell starting at offset + i * pitch from the module edge,   */
+/* centred in the cell.  Space in a layer outside its crystals is the       */
+/* layer's interval material; module gaps, inter-layer gaps and the rest of */
+/* the panel are the fill material.  Outside panels and phantom: vacuum.    */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double depth0_mm, thickness_mm;
+  int32_t n_t, n_a;
+  double cryst_t_mm, cryst_a_mm;
+  double pitch_t_mm, pitch_a_mm;
+  double offset_t_mm, offset_a_mm;
+  int32_t crystal_material, interval_material;
+} gpet_layer;
+
+#define GPET_PLACE_REPEAT 0   /* panel k at angle phi0 + 2 pi k / n_panels */
+#define GPET_PLACE_EXPLICIT 1 /* poses[] given per panel */
+
+typedef struct {
+  int32_t placement;
+  int32_t n_panels;                  /* 1..GPET_MAX_PANELS */
+  double radius_mm, phi0_rad, z0_mm; /* repeat mode: front-face distance from the z axis */
+  const double *poses;               /* explicit mode: n_panels x 12 doubles:
+                                        front-face centre xyz, depth axis, t axis, a axis */
+  double depth_mm, width_mm, length_mm;
+  int32_t mod_n_t, mod_n_a;
+  double mod_t_mm, mod_a_mm, gap_t_mm, gap_a_mm;
+  int32_t fill_material;
+  int32_t n_layers; /* 1..GPET_MAX_LAYERS */
+  gpet_layer layers[GPET_MAX_LAYERS];
+} gpet_scanner;
+
+/* Global crystal id (gid) layout:
+ *   gid = panel * crystals_per_panel + module * crystals_per_module
+ *         + layer_base[layer] + i_a * n_t(layer) + i_t,
+ * module = m_a * mod_n_t + m_t. */
+typedef struct {
+  int32_t n_crystals, crystals_per_panel, crystals_per_module;
+  int32_t layer_base[GPET_MAX_LAYERS];
+} gpet_geometry_info;
+
+/* Validates and uploads the scanner.  Errors: GPET_ERR_GEOMETRY for
+ * non-positive sizes, crystals wider than their pitch, layers outside the
+ * panel depth or overlapping, crystal arrays outside the module, or more
+ * than 2^20 crystals; GPET_ERR_STATE if no materials are set. */
+gpet_status gpet_geometry_create(gpet_ctx *ctx, const gpet_scanner *scanner, gpet_geometry_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* Voxelized phantom, transported with Woodcock tracking against the        */
+/* node-wise maximum attenuation over its voxels.  Voxel (ix, iy, iz) is     */
+/* material[(iz*ny + iy)*nx + ix] with density density[...] (g/cm^3); the    */
+/* box is [origin, origin + n*voxel) per axis.  A photon that leaves the box */
+/* does not re-enter it.  Passing NULL removes the phantom (vacuum).         */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz;
+  double voxel_mm[3];
+  double origin_mm[3];
+  const uint8_t *material; /* host */
+  const float *density;    /* host */
+} gpet_phantom;
+
+gpet_status gpet_phantom_set(gpet_ctx *ctx, const gpet_phantom *phantom);
+
+/* ---------------------------------------------------------------------- */
+/* Source (Sec. 2.3): each event is one annihilation at the emission site     */
+/* (no positron range) sending photon A along +d and photon B along -d at     */
+/* 511 keV, d isotropic (BEAM: d fixed).  Event times are uniform on          */
+/* [0, duration_ps) (a fixed number of decays of a constant activity).       */
+/* ---------------------------------------------------------------------- */
+#define GPET_SRC_POINT 0
+#define GPET_SRC_CYLINDERS 1 /* rods (cx, cy, radius, z0, z1), uniform activity density */
+#define GPET_SRC_BEAM 2
+
+typedef struct {
+  int32_t kind;
+  double pos_mm[3];   /* POINT, BEAM */
+  double dir[3];      /* BEAM */
+  int32_t n_rods;     /* CYLINDERS: 1..GPET_MAX_RODS */
+  const double *rods; /* host, n_rods x 5 */
+  uint64_t duration_ps;
+} gpet_source;
+
+gpet_status gpet_source_set(gpet_ctx *ctx, const gpet_source *source);
+
+/* ---------------------------------------------------------------------- */
+/* Transport                                                                 */
+/* ---------------------------------------------------------------------- */
+/* Hit list, one entry per photoelectric or Compton interaction inside a
+ * crystal (Sec. 2.1: each interaction labelled with crystal, layer, module
+ * and panel; all four follow from gid).  SoA device arrays of `capacity`
+ * entries.  Order of entries is unspecified. */
+typedef struct {
+  uint32_t *event;   /* event id */
+  uint32_t *gid;     /* global crystal id */
+  float *edep_kev;   /* deposited energy (includes a below-cutoff remainder) */
+  float *depth_mm;   /* panel-local depth of the interaction */
+  uint64_t *time_ps; /* event time + time of flight, rounded to ps */
+  uint32_t *aux;     /* bit 0 photon (0 = A, 1 = B); bits 1-2 process (1 PE, 2 Compton);
+                        bits 8-31 index of the hit within its photon */
+  uint64_t capacity;
+  uint64_t count;    /* out: hits produced */
+} gpet_hits;
+
+/* Work counters of a transport call (for roofline accounting). */
+typedef struct {
+  uint64_t events, panel_entries, steps, real_interactions, kahn_trials, panel_searches,
+      rng_blocks, capped;
+} gpet_stats;
+
+/* Transport events [first_event, first_event + n_events) with key `seed`.
+ * `instance` enters every random-number counter so that independent runs can
+ * share event ids.  stats may be NULL.  first_event + n_events <= 2^32. */
+gpet_status gpet_transport(gpet_ctx *ctx, uint64_t first_event, uint64_t n_events, uint64_t seed,
+                           uint32_t instance, gpet_hits *hits, gpet_stats *stats);
+
+/* ---------------------------------------------------------------------- */
+/* Digitizer at crystal readout level                                       */
+/*  adder:  hits of one event in one crystal form a single: energy = sum of  */
+/*          deposits, time = earliest hit time, depth = energy-weighted mean;*/
+/*  blur:   E + N(0,1) * fwhm_511 * sqrt(511 E) / 2.3548 (16 % at 511 keV);   */
+/*  window: e_lo <= blurred E <= e_hi;                                       */
+/*  sorter: windowed singles in (time, event, gid) order; a window of        */
+/*          window_ps (inclusive) opens at the earliest unused single and    */
+/*          does not retrigger; exactly two singles in different panels make */
+/*          a coincidence, any other content is discarded.                   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double fwhm_511;    /* relative FWHM at 511 keV (0.16) */
+  double e_lo_kev, e_hi_kev;
+  uint64_t window_ps; /* 3000 */
+  uint64_t seed;      /* key of the blur stream */
+  uint32_t instance;
+  uint64_t first_event, n_events; /* event range the hits came from */
+} gpet_digitizer;
+
+/* Singles in (event, gid) order. */
+typedef struct {
+  uint32_t *event, *gid;
+  float *edep_kev;    /* summed deposit */
+  float *energy_kev;  /* blurred */
+  float *depth_mm;
+  uint64_t *time_ps;
+  uint32_t *in_window;
+  uint64_t capacity;
+  uint64_t count;     /* out */
+} gpet_singles;
+
+/* Coincidences as index pairs into the singles arrays, earlier single first,
+ * ordered by the time of their first single. */
+typedef struct {
+  uint32_t *first, *second;
+  uint64_t capacity;
+  uint64_t count; /* out */
+} gpet_coincidences;
+
+/* Optional histograms (device arrays, accumulated, not cleared). */
+typedef struct {
+  uint32_t *hits_per_crystal;    /* n_crystals */
+  uint32_t *singles_per_crystal; /* n_crystals, in-window singles */
+  uint32_t *energy_spectrum;     /* 700 bins of 1 keV over [0, 700) keV, blurred singles */
+  uint32_t *doi;                 /* doi_bins over the panel depth, hits */
+  int32_t doi_bins;
+} gpet_tallies;
+
+gpet_status gpet_digitize(gpet_ctx *ctx, const gpet_hits *hits, const gpet_digitizer *params,
+                          gpet_singles *singles, gpet_coincidences *coincidences,
+                          gpet_tallies *tallies /* NULL: none */);
+
+/* Kernel timing: when enabled, HIP events bracket the transport kernel and
+ * the digitizer on the context's stream; gpet_timings returns the last
+ * durations in ms: [0] transport kernel, [1] whole digitizer. */
+gpet_status gpet_ctx_enable_timing(gpet_ctx *ctx, int enable);
+gpet_status gpet_timings(gpet_ctx *ctx, float *ms2);
+
+/* ---------------------------------------------------------------------- */
+/* Deterministic check surface (no hidden state; device output buffers).    */
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 blocks for key `seed` and n counters (device, 4 u32 each). */
+gpet_status gpet_philox(gpet_ctx *ctx, uint64_t seed, const uint32_t *ctr4, uint32_t n, uint32_t *out4);
+/* Attenuation tables: mu (n_mat x 4 x 511 floats, 1/mm at nominal density,
+ * processes PE, Compton, Rayleigh, total) and detector majorant (511). */
+gpet_status gpet_tables_get(gpet_ctx *ctx, float *mu_host, float *majorant_host);
+/* Locate n global points (device xyz[3n]); ids6 per point: panel, module,
+ * layer, crystal-in-layer, gid, material (-1 where not applicable). */
+gpet_status gpet_locate(gpet_ctx *ctx, uint32_t n, const float *xyz, int32_t *ids6);
+/* Fixed rays: panel search from o along d (device, 3 floats each), then
+ * locate at t_in + (k + 1/2) step, k < n_samples.  t_in < 0: no panel.
+ * ids6 [n][n_samples][6]; panel -2 marks a sample already outside. */
+gpet_status gpet_ray_locate(gpet_ctx *ctx, uint32_t n, const float *o, const float *d,
+                            int32_t n_samples, float step_mm, float *t_in, int32_t *ids6);
+/* Compton (Kahn) and Rayleigh (Thomson) samplers, sample i on stream 7 / 8. */
+gpet_status gpet_sample_compton(gpet_ctx *ctx, float e_kev, uint32_t n, uint64_t seed,
+                                float *cos_t, float *e_out, int32_t *trials);
+gpet_status gpet_sample_rayleigh(gpet_ctx *ctx, uint32_t n, uint64_t seed, float *cos_t);
+
+/* Traced histories: every vertex of events [first, first + n) with the same
+ * kernel code as gpet_transport.  Per photon (index 2*(e-first) + photon) at
+ * most max_vertices records of 11 int32 (event, photon, kind, region, panel,
+ * gid, material, accept, process, kahn trials, rng block) and 8 floats
+ * (x, y, z, energy, deposit, dx, dy, dz); counts[photon] may exceed
+ * max_vertices (then the rest were dropped).  Kinds: 0 step, 1 enter panel,
+ * 2 exit region, 3 escape, 4 absorbed, 5 enter phantom, 6 emission.  Panel
+ * steps are in the panel-local frame, everything else global. */
+gpet_status gpet_trace(gpet_ctx *ctx, uint64_t first_event, uint32_t n_events, uint64_t seed,
+                       uint32_t instance, int32_t max_vertices, int32_t *vint, float *vflt,
+                       int32_t *counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPET_H */

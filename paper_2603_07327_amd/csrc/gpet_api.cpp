@@ -1,0 +1,631 @@
+// gpet_api.cpp -- the C ABI: context, validation, host-side tables and
+// geometry preparation, and the launches of the transport and digitizer
+// kernels.  Declarations and contracts are in include/gpet.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gpet_internal.hpp"
+
+using namespace gpet;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMec2Kev = 510.99895;
+constexpr double kReCm = 2.8179403262e-13;
+constexpr double kAvogadro = 6.02214076e23;
+
+gpet_status fail(gpet_ctx *c, gpet_status code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+gpet_status hip_check(gpet_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return GPET_OK;
+  return fail(c, GPET_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T> gpet_status upload(gpet_ctx *c, T *&dst, const T *src, size_t n, const char *what) {
+  if (dst) (void)hipFree(dst);
+  dst = nullptr;
+  if (n == 0) return GPET_OK;
+  gpet_status s = hip_check(c, hipMalloc((void **)&dst, n * sizeof(T)), what);
+  if (s) return s;
+  return hip_check(c, hipMemcpy(dst, src, n * sizeof(T), hipMemcpyHostToDevice), what);
+}
+
+// Klein-Nishina total cross-section per electron (barn)
+double klein_nishina_barn(double e_kev) {
+  const double k = e_kev / kMec2Kev;
+  const double lg = std::log1p(2.0 * k);
+  const double b = 1.0 + 2.0 * k;
+  const double part1 = (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / b - lg / k);
+  const double part2 = lg / (2.0 * k) - (1.0 + 3.0 * k) / (b * b);
+  return 2.0 * kPi * kReCm * kReCm * (part1 + part2) * 1e24;
+}
+
+// per-process attenuation per unit density (1/mm per g/cm^3) at e_kev
+void attenuation_per_density(const gpet_material &m, const gpet_physics &ph, double e_kev, double out[3]) {
+  const double e_mev = e_kev * 1e-3;
+  const double sig_e = klein_nishina_barn(e_kev) * 1e-24;
+  double pe = 0.0, co = 0.0, ra = 0.0;
+  for (int j = 0; j < m.n_elements; ++j) {
+    const double atoms_per_g = kAvogadro * m.mass_fraction[j] / m.A[j];
+    const double z = (double)m.Z[j];
+    const double z2 = z * z;
+    co += atoms_per_g * z * sig_e;
+    pe += atoms_per_g * ph.k_pe * z2 * z2 / (e_mev * e_mev * e_mev);
+    ra += atoms_per_g * ph.k_rayleigh * z2 / (e_mev * e_mev);
+  }
+  // cm^2/g -> (1/mm) / (g/cm^3)
+  out[0] = (m.processes & GPET_PROC_PHOTOELECTRIC) ? pe * 0.1 : 0.0;
+  out[1] = (m.processes & GPET_PROC_COMPTON) ? co * 0.1 : 0.0;
+  out[2] = (m.processes & GPET_PROC_RAYLEIGH) ? ra * 0.1 : 0.0;
+}
+
+int bits_for(uint64_t max_value) {
+  int b = 0;
+  while (b < 64 && (max_value >> b) != 0) ++b;
+  return b;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+} // namespace
+
+extern "C" {
+
+gpet_status gpet_ctx_create(int device, void *hip_stream, gpet_ctx **out) {
+  if (!out) return GPET_ERR_ARG;
+  *out = nullptr;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return GPET_ERR_HIP;
+  gpet_ctx *c = new (std::nothrow) gpet_ctx();
+  if (!c) return GPET_ERR_ARG;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return GPET_ERR_HIP;
+  }
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+    c->n_cu = cu;
+  if (hipMalloc((void **)&c->d_ctrl, 16 * sizeof(unsigned long long)) != hipSuccess) {
+    delete c;
+    return GPET_ERR_HIP;
+  }
+  if (hipHostMalloc((void **)&c->h_ctrl, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(c->d_ctrl);
+    delete c;
+    return GPET_ERR_HIP;
+  }
+  *out = c;
+  return GPET_OK;
+}
+
+void gpet_ctx_destroy(gpet_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (void *p : {(void *)c->d_mu, (void *)c->d_mu_mass, (void *)c->d_maj_det, (void *)c->d_maj_ph,
+                  (void *)c->d_pose, (void *)c->d_vmat, (void *)c->d_vden, (void *)c->d_rods,
+                  (void *)c->d_rod_cum, (void *)c->d_ctrl})
+    if (p) (void)hipFree(p);
+  if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+  for (hipEvent_t &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  free_scratch(c->scratch);
+  delete c;
+}
+
+const char *gpet_last_error(const gpet_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+gpet_status gpet_ctx_set_stream(gpet_ctx *c, void *hip_stream) {
+  if (!c) return GPET_ERR_ARG;
+  c->stream = (hipStream_t)hip_stream;
+  return GPET_OK;
+}
+
+gpet_status gpet_materials_set(gpet_ctx *c, int32_t n, const gpet_material *m, const gpet_physics *ph) {
+  if (!c) return GPET_ERR_ARG;
+  if (n < 1 || n > GPET_MAX_MATERIALS || !m || !ph) return fail(c, GPET_ERR_ARG, "materials: bad count or null");
+  if (!(ph->k_pe >= 0) || !(ph->k_rayleigh >= 0) || !(ph->e_cut_kev >= 1.0 && ph->e_cut_kev < 511.0))
+    return fail(c, GPET_ERR_ARG, "materials: physics constants out of range");
+  for (int i = 0; i < n; ++i) {
+    const gpet_material &q = m[i];
+    if (!finite_pos(q.density_g_cm3) || q.n_elements < 1 || q.n_elements > GPET_MAX_ELEMENTS)
+      return fail(c, GPET_ERR_ARG, "materials: bad density or element count");
+    double wsum = 0;
+    for (int j = 0; j < q.n_elements; ++j) {
+      if (q.Z[j] < 1 || q.Z[j] > 118 || !finite_pos(q.A[j]) || !(q.mass_fraction[j] >= 0))
+        return fail(c, GPET_ERR_ARG, "materials: bad element");
+      wsum += q.mass_fraction[j];
+    }
+    if (std::fabs(wsum - 1.0) > 1e-6) return fail(c, GPET_ERR_ARG, "materials: mass fractions must sum to 1");
+  }
+  (void)hipSetDevice(c->device);
+  c->n_mat = n;
+  c->mats.assign(m, m + n);
+  c->phys = *ph;
+  std::vector<float4> mass((size_t)n * kTabStride), nom((size_t)n * kTabStride);
+  c->mu_host.assign((size_t)n * 4 * kNodes, 0.f);
+  c->mu_mass_host.assign((size_t)n * 4 * kNodes, 0.f);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < kTabStride; ++k) {
+      const int node = std::min(k, kNodes - 1);
+      double a[3];
+      attenuation_per_density(m[i], *ph, (double)(node + 1), a);
+      const double rho = m[i].density_g_cm3;
+      mass[(size_t)i * kTabStride + k] = make_float4((float)a[0], (float)a[1], (float)a[2], (float)(a[0] + a[1] + a[2]));
+      nom[(size_t)i * kTabStride + k] =
+          make_float4((float)(rho * a[0]), (float)(rho * a[1]), (float)(rho * a[2]), (float)(rho * (a[0] + a[1] + a[2])));
+      if (k < kNodes) {
+        const float4 f = nom[(size_t)i * kTabStride + k], g = mass[(size_t)i * kTabStride + k];
+        float *dn = &c->mu_host[((size_t)i * 4) * kNodes + k];
+        float *dm = &c->mu_mass_host[((size_t)i * 4) * kNodes + k];
+        dn[0] = f.x; dn[kNodes] = f.y; dn[2 * kNodes] = f.z; dn[3 * kNodes] = f.w;
+        dm[0] = g.x; dm[kNodes] = g.y; dm[2 * kNodes] = g.z; dm[3 * kNodes] = g.w;
+      }
+    }
+  gpet_status s = upload(c, c->d_mu, nom.data(), nom.size(), "materials: upload");
+  if (!s) s = upload(c, c->d_mu_mass, mass.data(), mass.size(), "materials: upload");
+  if (s) return s;
+  // geometry and phantom majorants depend on the material list
+  c->have_geometry = false;
+  if (c->d_vmat) (void)hipFree(c->d_vmat);
+  if (c->d_vden) (void)hipFree(c->d_vden);
+  c->d_vmat = nullptr;
+  c->d_vden = nullptr;
+  c->scene.has_phantom = 0;
+  c->scene.e_cut = (float)ph->e_cut_kev;
+  c->scene.mu = c->d_mu;
+  c->scene.mu_mass = c->d_mu_mass;
+  return GPET_OK;
+}
+
+gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geometry_info *info) {
+  if (!c) return GPET_ERR_ARG;
+  if (!g) return fail(c, GPET_ERR_ARG, "geometry: null scanner");
+  if (c->n_mat == 0) return fail(c, GPET_ERR_STATE, "geometry: set materials first");
+  auto bad = [&](const char *w) { return fail(c, GPET_ERR_GEOMETRY, std::string("geometry: ") + w); };
+  const double eps = 1e-9;
+  if (g->n_panels < 1 || g->n_panels > GPET_MAX_PANELS) return bad("panel count out of range");
+  if (!finite_pos(g->depth_mm) || !finite_pos(g->width_mm) || !finite_pos(g->length_mm)) return bad("panel size");
+  if (g->mod_n_t < 1 || g->mod_n_a < 1 || !finite_pos(g->mod_t_mm) || !finite_pos(g->mod_a_mm) ||
+      !(g->gap_t_mm >= 0) || !(g->gap_a_mm >= 0))
+    return bad("module grid");
+  const double w_mod = g->mod_n_t * g->mod_t_mm + (g->mod_n_t - 1) * g->gap_t_mm;
+  const double l_mod = g->mod_n_a * g->mod_a_mm + (g->mod_n_a - 1) * g->gap_a_mm;
+  if (w_mod > g->width_mm + eps || l_mod > g->length_mm + eps) return bad("modules do not fit the panel");
+  if (g->fill_material < 0 || g->fill_material >= c->n_mat) return bad("fill material");
+  if (g->n_layers < 1 || g->n_layers > GPET_MAX_LAYERS) return bad("layer count");
+  double prev_end = 0.0;
+  int64_t per_module = 0;
+  for (int l = 0; l < g->n_layers; ++l) {
+    const gpet_layer &y = g->layers[l];
+    if (!(y.depth0_mm >= prev_end - eps) || !finite_pos(y.thickness_mm) ||
+        y.depth0_mm + y.thickness_mm > g->depth_mm + eps)
+      return bad("layers must lie in the panel depth, in order, without overlap");
+    if (y.n_t < 1 || y.n_a < 1 || !finite_pos(y.cryst_t_mm) || !finite_pos(y.cryst_a_mm) ||
+        y.pitch_t_mm < y.cryst_t_mm || y.pitch_a_mm < y.cryst_a_mm || !(y.offset_t_mm >= 0) ||
+        !(y.offset_a_mm >= 0))
+      return bad("crystal size, pitch or offset");
+    if (y.offset_t_mm + y.n_t * y.pitch_t_mm > g->mod_t_mm + 1e-6 ||
+        y.offset_a_mm + y.n_a * y.pitch_a_mm > g->mod_a_mm + 1e-6)
+      return bad("crystal array exceeds the module");
+    if (y.crystal_material < 0 || y.crystal_material >= c->n_mat || y.interval_material < 0 ||
+        y.interval_material >= c->n_mat)
+      return bad("layer material");
+    prev_end = y.depth0_mm + y.thickness_mm;
+    per_module += (int64_t)y.n_t * y.n_a;
+  }
+  const int64_t per_panel = per_module * g->mod_n_t * g->mod_n_a;
+  const int64_t total = per_panel * g->n_panels;
+  if (total >= (1 << 20)) return bad("more than 2^20 crystals");
+
+  // panel poses: repetition mode places panel k at angle phi0 + 2 pi k / n
+  std::vector<float> pose((size_t)g->n_panels * 12);
+  for (int k = 0; k < g->n_panels; ++k) {
+    double P[12];
+    if (g->placement == GPET_PLACE_REPEAT) {
+      const double a = g->phi0_rad + 2.0 * kPi * k / g->n_panels;
+      const double ca = std::cos(a), sa = std::sin(a);
+      const double v[12] = {g->radius_mm * ca, g->radius_mm * sa, g->z0_mm, ca, sa, 0.0, -sa, ca, 0.0, 0.0, 0.0, 1.0};
+      std::memcpy(P, v, sizeof(P));
+    } else if (g->placement == GPET_PLACE_EXPLICIT) {
+      if (!g->poses) return bad("explicit placement needs poses");
+      std::memcpy(P, g->poses + 12 * k, sizeof(P));
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const double dot = P[3 + 3 * i] * P[3 + 3 * j] + P[4 + 3 * i] * P[4 + 3 * j] + P[5 + 3 * i] * P[5 + 3 * j];
+          if (std::fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-6) return bad("pose axes are not orthonormal");
+        }
+    } else {
+      return bad("unknown placement mode");
+    }
+    for (int i = 0; i < 12; ++i) pose[(size_t)k * 12 + i] = (float)P[i];
+  }
+  (void)hipSetDevice(c->device);
+  gpet_status s = upload(c, c->d_pose, pose.data(), pose.size(), "geometry: upload");
+  if (s) return s;
+
+  // detector majorant: node-wise maximum over the materials in the panel
+  std::vector<bool> used(c->n_mat, false);
+  used[g->fill_material] = true;
+  for (int l = 0; l < g->n_layers; ++l) used[g->layers[l].crystal_material] = used[g->layers[l].interval_material] = true;
+  std::vector<float> maj(kTabStride, 0.f);
+  c->maj_det_host.assign(kNodes, 0.f);
+  for (int k = 0; k < kTabStride; ++k) {
+    const int node = std::min(k, kNodes - 1);
+    double mx = 0.0;
+    for (int i = 0; i < c->n_mat; ++i)
+      if (used[i]) {
+        double a[3];
+        attenuation_per_density(c->mats[i], c->phys, (double)(node + 1), a);
+        mx = std::max(mx, c->mats[i].density_g_cm3 * (a[0] + a[1] + a[2]));
+      }
+    maj[k] = (float)mx;
+    if (k < kNodes) c->maj_det_host[k] = maj[k];
+  }
+  s = upload(c, c->d_maj_det, maj.data(), maj.size(), "geometry: upload");
+  if (s) return s;
+
+  DevScene &S = c->scene;
+  S.n_panels = g->n_panels;
+  S.depth = (float)g->depth_mm;
+  S.half_w = (float)(0.5 * g->width_mm);
+  S.half_l = (float)(0.5 * g->length_mm);
+  S.pose = c->d_pose;
+  S.mod_n_t = g->mod_n_t;
+  S.mod_n_a = g->mod_n_a;
+  S.mod_t0 = (float)(-0.5 * w_mod);
+  S.mod_a0 = (float)(-0.5 * l_mod);
+  S.mod_step_t = (float)(g->mod_t_mm + g->gap_t_mm);
+  S.mod_step_a = (float)(g->mod_a_mm + g->gap_a_mm);
+  S.mod_t = (float)g->mod_t_mm;
+  S.mod_a = (float)g->mod_a_mm;
+  S.fill = g->fill_material;
+  S.n_layers = g->n_layers;
+  int base = 0;
+  for (int l = 0; l < g->n_layers; ++l) {
+    const gpet_layer &y = g->layers[l];
+    LayerD &d = S.layer[l];
+    d.d0 = (float)y.depth0_mm;
+    d.d1 = (float)(y.depth0_mm + y.thickness_mm);
+    d.off_t = (float)y.offset_t_mm;
+    d.off_a = (float)y.offset_a_mm;
+    d.pitch_t = (float)y.pitch_t_mm;
+    d.pitch_a = (float)y.pitch_a_mm;
+    d.lo_t = (float)(0.5 * (y.pitch_t_mm - y.cryst_t_mm));
+    d.hi_t = (float)(0.5 * (y.pitch_t_mm + y.cryst_t_mm));
+    d.lo_a = (float)(0.5 * (y.pitch_a_mm - y.cryst_a_mm));
+    d.hi_a = (float)(0.5 * (y.pitch_a_mm + y.cryst_a_mm));
+    d.n_t = y.n_t;
+    d.n_a = y.n_a;
+    d.mat_crystal = y.crystal_material;
+    d.mat_interval = y.interval_material;
+    d.base = base;
+    c->info.layer_base[l] = base;
+    base += y.n_t * y.n_a;
+  }
+  S.crystals_per_module = (int)per_module;
+  S.crystals_per_panel = (int)per_panel;
+  S.maj_det = c->d_maj_det;
+  S.mu = c->d_mu;
+  S.mu_mass = c->d_mu_mass;
+  S.e_cut = (float)c->phys.e_cut_kev;
+  c->info.n_crystals = (int32_t)total;
+  c->info.crystals_per_panel = (int32_t)per_panel;
+  c->info.crystals_per_module = (int32_t)per_module;
+  for (int l = g->n_layers; l < GPET_MAX_LAYERS; ++l) c->info.layer_base[l] = -1;
+  c->have_geometry = true;
+  if (info) *info = c->info;
+  return GPET_OK;
+}
+
+gpet_status gpet_phantom_set(gpet_ctx *c, const gpet_phantom *ph) {
+  if (!c) return GPET_ERR_ARG;
+  if (c->n_mat == 0) return fail(c, GPET_ERR_STATE, "phantom: set materials first");
+  (void)hipSetDevice(c->device);
+  DevScene &S = c->scene;
+  if (!ph) {
+    S.has_phantom = 0;
+    return GPET_OK;
+  }
+  if (ph->nx < 1 || ph->ny < 1 || ph->nz < 1 || !ph->material || !ph->density)
+    return fail(c, GPET_ERR_ARG, "phantom: bad dimensions or null arrays");
+  for (int k = 0; k < 3; ++k)
+    if (!finite_pos(ph->voxel_mm[k]) || !std::isfinite(ph->origin_mm[k]))
+      return fail(c, GPET_ERR_ARG, "phantom: bad voxel size or origin");
+  const size_t nv = (size_t)ph->nx * ph->ny * ph->nz;
+  if (nv >= ((size_t)1 << 31)) return fail(c, GPET_ERR_ARG, "phantom: too many voxels");
+  std::vector<double> rmax(c->n_mat, 0.0);
+  for (size_t v = 0; v < nv; ++v) {
+    const int m = ph->material[v];
+    const float r = ph->density[v];
+    if (m >= c->n_mat) return fail(c, GPET_ERR_ARG, "phantom: material id out of range");
+    if (!(r >= 0.0f) || !std::isfinite(r)) return fail(c, GPET_ERR_ARG, "phantom: bad density");
+    rmax[m] = std::max(rmax[m], (double)r);
+  }
+  std::vector<float> maj(kTabStride, 0.f);
+  for (int k = 0; k < kTabStride; ++k) {
+    const int node = std::min(k, kNodes - 1);
+    double mx = 0.0;
+    for (int i = 0; i < c->n_mat; ++i)
+      if (rmax[i] > 0) {
+        double a[3];
+        attenuation_per_density(c->mats[i], c->phys, (double)(node + 1), a);
+        mx = std::max(mx, rmax[i] * (a[0] + a[1] + a[2]));
+      }
+    maj[k] = (float)mx;
+  }
+  if (maj[510] <= 0.f) return fail(c, GPET_ERR_ARG, "phantom: all voxels are void");
+  gpet_status s = upload(c, c->d_vmat, ph->material, nv, "phantom: upload");
+  if (!s) s = upload(c, c->d_vden, ph->density, nv, "phantom: upload");
+  if (!s) s = upload(c, c->d_maj_ph, maj.data(), maj.size(), "phantom: upload");
+  if (s) return s;
+  S.has_phantom = 1;
+  S.nx = ph->nx;
+  S.ny = ph->ny;
+  S.nz = ph->nz;
+  S.ox = (float)ph->origin_mm[0];
+  S.oy = (float)ph->origin_mm[1];
+  S.oz = (float)ph->origin_mm[2];
+  S.vx = (float)ph->voxel_mm[0];
+  S.vy = (float)ph->voxel_mm[1];
+  S.vz = (float)ph->voxel_mm[2];
+  S.bx = (float)(ph->origin_mm[0] + ph->nx * ph->voxel_mm[0]);
+  S.by = (float)(ph->origin_mm[1] + ph->ny * ph->voxel_mm[1]);
+  S.bz = (float)(ph->origin_mm[2] + ph->nz * ph->voxel_mm[2]);
+  S.vmat = c->d_vmat;
+  S.vden = c->d_vden;
+  S.maj_ph = c->d_maj_ph;
+  return GPET_OK;
+}
+
+gpet_status gpet_source_set(gpet_ctx *c, const gpet_source *src) {
+  if (!c) return GPET_ERR_ARG;
+  if (!src) return fail(c, GPET_ERR_ARG, "source: null");
+  if (src->duration_ps == 0) return fail(c, GPET_ERR_ARG, "source: duration must be positive");
+  DevScene &S = c->scene;
+  (void)hipSetDevice(c->device);
+  if (src->kind == GPET_SRC_CYLINDERS) {
+    if (src->n_rods < 1 || src->n_rods > GPET_MAX_RODS || !src->rods) return fail(c, GPET_ERR_ARG, "source: rods");
+    std::vector<float> rods((size_t)src->n_rods * 5), cum(src->n_rods);
+    double acc = 0.0;
+    for (int i = 0; i < src->n_rods; ++i) {
+      const double *r = src->rods + 5 * i;
+      if (!finite_pos(r[2]) || !(r[4] > r[3])) return fail(c, GPET_ERR_ARG, "source: bad rod");
+      acc += r[2] * r[2] * (r[4] - r[3]); // weight by rod volume
+      cum[i] = (float)acc;
+      for (int k = 0; k < 5; ++k) rods[(size_t)i * 5 + k] = (float)r[k];
+    }
+    gpet_status s = upload(c, c->d_rods, rods.data(), rods.size(), "source: upload");
+    if (!s) s = upload(c, c->d_rod_cum, cum.data(), cum.size(), "source: upload");
+    if (s) return s;
+    S.n_rods = src->n_rods;
+    S.rods = c->d_rods;
+    S.rod_cum = c->d_rod_cum;
+    S.rod_total = (float)acc;
+  } else if (src->kind == GPET_SRC_BEAM) {
+    const double n = std::sqrt(src->dir[0] * src->dir[0] + src->dir[1] * src->dir[1] + src->dir[2] * src->dir[2]);
+    if (!(std::fabs(n - 1.0) < 1e-6)) return fail(c, GPET_ERR_ARG, "source: beam direction must be a unit vector");
+  } else if (src->kind != GPET_SRC_POINT) {
+    return fail(c, GPET_ERR_ARG, "source: unknown kind");
+  }
+  S.src_kind = src->kind;
+  S.sx = (float)src->pos_mm[0];
+  S.sy = (float)src->pos_mm[1];
+  S.sz = (float)src->pos_mm[2];
+  S.bdx = (float)src->dir[0];
+  S.bdy = (float)src->dir[1];
+  S.bdz = (float)src->dir[2];
+  S.duration_ps = src->duration_ps;
+  c->have_source = true;
+  return GPET_OK;
+}
+
+static gpet_status ready(gpet_ctx *c) {
+  if (!c) return GPET_ERR_ARG;
+  if (!c->have_geometry) return fail(c, GPET_ERR_STATE, "no geometry (gpet_geometry_create)");
+  if (!c->have_source) return fail(c, GPET_ERR_STATE, "no source (gpet_source_set)");
+  return GPET_OK;
+}
+
+static RunArgs run_args(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance) {
+  RunArgs A{};
+  A.first = (uint32_t)first;
+  A.n = (uint32_t)n;
+  A.k0 = (uint32_t)seed;
+  A.k1 = (uint32_t)(seed >> 32);
+  A.instance = instance;
+  A.work = (uint32_t *)(c->d_ctrl + 0);
+  A.hit_count = c->d_ctrl + 1;
+  A.stats = c->d_ctrl + 2;
+  return A;
+}
+
+gpet_status gpet_transport(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                           gpet_hits *h, gpet_stats *stats) {
+  gpet_status s = ready(c);
+  if (s) return s;
+  if (!h) return fail(c, GPET_ERR_ARG, "transport: null hits");
+  if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "transport: event range");
+  if (h->capacity && (!h->event || !h->gid || !h->edep_kev || !h->depth_mm || !h->time_ps || !h->aux))
+    return fail(c, GPET_ERR_ARG, "transport: null hit array");
+  (void)hipSetDevice(c->device);
+  RunArgs A = run_args(c, first, n, seed, instance);
+  A.h_event = h->event;
+  A.h_gid = h->gid;
+  A.h_edep = h->edep_kev;
+  A.h_depth = h->depth_mm;
+  A.h_time = (unsigned long long *)h->time_ps;
+  A.h_aux = h->aux;
+  A.capacity = h->capacity;
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 20, c->stream);
+  if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
+  if (n) launch_transport(c->scene, A, c->shape, c->n_cu, c->stream);
+  if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
+  s = hip_check(c, hipGetLastError(), "transport: launch");
+  if (s) return s;
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 10 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
+  if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "transport: kernel");
+  if (s) return s;
+  h->count = c->h_ctrl[1];
+  if (c->timing) (void)hipEventElapsedTime(&c->last_ms[0], c->ev[0], c->ev[1]);
+  if (stats) {
+    uint64_t *o = (uint64_t *)stats;
+    for (int k = 0; k < 8; ++k) o[k] = c->h_ctrl[2 + k];
+  }
+  if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "transport: hit capacity too small");
+  return GPET_OK;
+}
+
+gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer *p, gpet_singles *sg,
+                          gpet_coincidences *cc, gpet_tallies *t) {
+  if (!c) return GPET_ERR_ARG;
+  if (!c->have_geometry) return fail(c, GPET_ERR_STATE, "digitize: no geometry");
+  if (!h || !p || !sg || !cc) return fail(c, GPET_ERR_ARG, "digitize: null argument");
+  if (h->count > h->capacity) return fail(c, GPET_ERR_ARG, "digitize: hit count exceeds capacity");
+  if (h->count >= 0xffffffffull) return fail(c, GPET_ERR_UNSUPPORTED, "digitize: more than 2^32 hits");
+  if (!(p->fwhm_511 >= 0) || !(p->e_lo_kev <= p->e_hi_kev)) return fail(c, GPET_ERR_ARG, "digitize: parameters");
+  if (p->n_events == 0 || p->first_event + p->n_events > 0x100000000ull)
+    return fail(c, GPET_ERR_ARG, "digitize: event range");
+  if (t && t->doi && t->doi_bins < 1) return fail(c, GPET_ERR_ARG, "digitize: doi_bins");
+  (void)hipSetDevice(c->device);
+  DigitizeArgs D{};
+  D.n_hits = h->count;
+  D.h_event = h->event;
+  D.h_gid = h->gid;
+  D.h_edep = h->edep_kev;
+  D.h_depth = h->depth_mm;
+  D.h_time = (const unsigned long long *)h->time_ps;
+  D.first_event = (uint32_t)p->first_event;
+  D.event_bits = bits_for(p->n_events - 1);
+  D.gid_bits = bits_for((uint64_t)c->info.n_crystals - 1);
+  D.crystals_per_panel = c->info.crystals_per_panel;
+  D.n_crystals = c->info.n_crystals;
+  D.fwhm_511 = (float)p->fwhm_511;
+  D.e_lo = (float)p->e_lo_kev;
+  D.e_hi = (float)p->e_hi_kev;
+  D.window_ps = p->window_ps;
+  D.k0 = (uint32_t)p->seed;
+  D.k1 = (uint32_t)(p->seed >> 32);
+  D.instance = p->instance;
+  D.panel_depth = c->scene.depth;
+  D.singles = sg;
+  D.coinc = cc;
+  D.tallies = t;
+  if (c->timing) (void)hipEventRecord(c->ev[2], c->stream);
+  const int r = run_digitize(D, c->scratch, c->stream, c->err);
+  if (r != GPET_OK) return r;
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[3], c->stream);
+    (void)hipEventSynchronize(c->ev[3]);
+    (void)hipEventElapsedTime(&c->last_ms[1], c->ev[2], c->ev[3]);
+  }
+  return hip_check(c, hipGetLastError(), "digitize: launch");
+}
+
+gpet_status gpet_ctx_enable_timing(gpet_ctx *c, int enable) {
+  if (!c) return GPET_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  if (enable && !c->ev[0])
+    for (hipEvent_t &e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(c, GPET_ERR_HIP, "timing: event creation failed");
+  c->timing = enable != 0;
+  return GPET_OK;
+}
+
+gpet_status gpet_timings(gpet_ctx *c, float *ms2) {
+  if (!c || !ms2) return GPET_ERR_ARG;
+  ms2[0] = c->last_ms[0];
+  ms2[1] = c->last_ms[1];
+  return GPET_OK;
+}
+
+gpet_status gpet_philox(gpet_ctx *c, uint64_t seed, const uint32_t *ctr4, uint32_t n, uint32_t *out4) {
+  if (!c || (n && (!ctr4 || !out4))) return GPET_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  launch_philox(seed, ctr4, n, out4, c->stream);
+  gpet_status s = hip_check(c, hipGetLastError(), "philox: launch");
+  return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "philox");
+}
+
+gpet_status gpet_tables_get(gpet_ctx *c, float *mu, float *maj) {
+  if (!c) return GPET_ERR_ARG;
+  if (c->n_mat == 0) return fail(c, GPET_ERR_STATE, "tables: no materials");
+  if (mu) std::memcpy(mu, c->mu_host.data(), c->mu_host.size() * sizeof(float));
+  if (maj) {
+    if (!c->have_geometry) return fail(c, GPET_ERR_STATE, "tables: no geometry for the majorant");
+    std::memcpy(maj, c->maj_det_host.data(), kNodes * sizeof(float));
+  }
+  return GPET_OK;
+}
+
+gpet_status gpet_locate(gpet_ctx *c, uint32_t n, const float *xyz, int32_t *ids6) {
+  if (!c) return GPET_ERR_ARG;
+  if (!c->have_geometry) return fail(c, GPET_ERR_STATE, "locate: no geometry");
+  if (n && (!xyz || !ids6)) return fail(c, GPET_ERR_ARG, "locate: null");
+  (void)hipSetDevice(c->device);
+  launch_locate(c->scene, n, xyz, ids6, c->stream);
+  gpet_status s = hip_check(c, hipGetLastError(), "locate: launch");
+  return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "locate");
+}
+
+gpet_status gpet_ray_locate(gpet_ctx *c, uint32_t n, const float *o, const float *d, int32_t ns, float step,
+                            float *t_in, int32_t *ids6) {
+  if (!c) return GPET_ERR_ARG;
+  if (!c->have_geometry) return fail(c, GPET_ERR_STATE, "ray_locate: no geometry");
+  if (ns < 0 || (n && (!o || !d || !t_in || (ns && !ids6)))) return fail(c, GPET_ERR_ARG, "ray_locate: args");
+  (void)hipSetDevice(c->device);
+  launch_ray_locate(c->scene, n, o, d, ns, step, t_in, ids6, c->stream);
+  gpet_status s = hip_check(c, hipGetLastError(), "ray_locate: launch");
+  return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "ray_locate");
+}
+
+gpet_status gpet_sample_compton(gpet_ctx *c, float e, uint32_t n, uint64_t seed, float *cos_t, float *e_out,
+                                int32_t *trials) {
+  if (!c || !(e > 0.0f) || (n && (!cos_t || !e_out))) return c ? fail(c, GPET_ERR_ARG, "compton: args") : GPET_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  launch_compton(e, n, seed, cos_t, e_out, trials, c->stream);
+  gpet_status s = hip_check(c, hipGetLastError(), "compton: launch");
+  return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "compton");
+}
+
+gpet_status gpet_sample_rayleigh(gpet_ctx *c, uint32_t n, uint64_t seed, float *cos_t) {
+  if (!c || (n && !cos_t)) return GPET_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  launch_rayleigh(n, seed, cos_t, c->stream);
+  gpet_status s = hip_check(c, hipGetLastError(), "rayleigh: launch");
+  return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "rayleigh");
+}
+
+gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, uint32_t instance, int32_t maxv,
+                       int32_t *vint, float *vflt, int32_t *counts) {
+  gpet_status s = ready(c);
+  if (s) return s;
+  if (maxv < 1 || !vint || !vflt || !counts) return fail(c, GPET_ERR_ARG, "trace: buffers");
+  if (first + n > 0x100000000ull || n > (1u << 24)) return fail(c, GPET_ERR_ARG, "trace: event range");
+  (void)hipSetDevice(c->device);
+  RunArgs A = run_args(c, first, n, seed, instance);
+  A.capacity = 0;
+  A.vint = vint;
+  A.vflt = vflt;
+  A.vcount = counts;
+  A.max_vertices = maxv;
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 20, c->stream);
+  launch_fill_u32((uint32_t *)counts, 0u, 2 * (size_t)n, c->stream);
+  if (n) launch_trace(c->scene, A, c->stream);
+  s = hip_check(c, hipGetLastError(), "trace: launch");
+  return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "trace");
+}
+
+} // extern "C"

@@ -1,0 +1,461 @@
+"""Python binding of ``libgpet.so`` (C ABI in ``include/gpet.h``).
+
+Argument marshalling only: scene descriptions are packed into the library's
+structs, device buffers are torch tensors on the context's device, and every
+step of the simulation runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is not built, or no GPU is present, construction of a
+:class:`Context` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpet.so")
+
+MAX_EL, MAX_MAT, MAX_LAYERS, MAX_PANELS = 8, 8, 4, 64
+NODES = 511
+
+OK, ERR_ARG, ERR_GEOMETRY, ERR_STATE, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PLACE_REPEAT, PLACE_EXPLICIT = 0, 1
+SRC_POINT, SRC_CYLINDERS, SRC_BEAM = 0, 1, 2
+V_STEP, V_ENTER_PANEL, V_EXIT, V_ESCAPE, V_DEAD, V_ENTER_PHANTOM, V_EMIT = range(7)
+
+STAT_NAMES = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks", "capped")
+
+
+class GpetError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gpet error {code}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("density_g_cm3", C.c_double), ("n_elements", C.c_int32), ("processes", C.c_uint32),
+                ("Z", C.c_int32 * MAX_EL), ("A", C.c_double * MAX_EL), ("mass_fraction", C.c_double * MAX_EL)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("k_pe", C.c_double), ("k_rayleigh", C.c_double), ("e_cut_kev", C.c_double)]
+
+
+class Layer(C.Structure):
+    _fields_ = [("depth0_mm", C.c_double), ("thickness_mm", C.c_double), ("n_t", C.c_int32), ("n_a", C.c_int32),
+                ("cryst_t_mm", C.c_double), ("cryst_a_mm", C.c_double), ("pitch_t_mm", C.c_double),
+                ("pitch_a_mm", C.c_double), ("offset_t_mm", C.c_double), ("offset_a_mm", C.c_double),
+                ("crystal_material", C.c_int32), ("interval_material", C.c_int32)]
+
+
+class Scanner(C.Structure):
+    _fields_ = [("placement", C.c_int32), ("n_panels", C.c_int32), ("radius_mm", C.c_double),
+                ("phi0_rad", C.c_double), ("z0_mm", C.c_double), ("poses", C.POINTER(C.c_double)),
+                ("depth_mm", C.c_double), ("width_mm", C.c_double), ("length_mm", C.c_double),
+                ("mod_n_t", C.c_int32), ("mod_n_a", C.c_int32), ("mod_t_mm", C.c_double),
+                ("mod_a_mm", C.c_double), ("gap_t_mm", C.c_double), ("gap_a_mm", C.c_double),
+                ("fill_material", C.c_int32), ("n_layers", C.c_int32), ("layers", Layer * MAX_LAYERS)]
+
+
+class GeometryInfo(C.Structure):
+    _fields_ = [("n_crystals", C.c_int32), ("crystals_per_panel", C.c_int32),
+                ("crystals_per_module", C.c_int32), ("layer_base", C.c_int32 * MAX_LAYERS)]
+
+
+class Phantom(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("voxel_mm", C.c_double * 3),
+                ("origin_mm", C.c_double * 3), ("material", C.POINTER(C.c_uint8)),
+                ("density", C.POINTER(C.c_float))]
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pos_mm", C.c_double * 3), ("dir", C.c_double * 3),
+                ("n_rods", C.c_int32), ("rods", C.POINTER(C.c_double)), ("duration_ps", C.c_uint64)]
+
+
+class Hits(C.Structure):
+    _fields_ = [("event", C.c_void_p), ("gid", C.c_void_p), ("edep_kev", C.c_void_p), ("depth_mm", C.c_void_p),
+                ("time_ps", C.c_void_p), ("aux", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in STAT_NAMES]
+
+
+class Digitizer(C.Structure):
+    _fields_ = [("fwhm_511", C.c_double), ("e_lo_kev", C.c_double), ("e_hi_kev", C.c_double),
+                ("window_ps", C.c_uint64), ("seed", C.c_uint64), ("instance", C.c_uint32),
+                ("first_event", C.c_uint64), ("n_events", C.c_uint64)]
+
+
+class Singles(C.Structure):
+    _fields_ = [("event", C.c_void_p), ("gid", C.c_void_p), ("edep_kev", C.c_void_p), ("energy_kev", C.c_void_p),
+                ("depth_mm", C.c_void_p), ("time_ps", C.c_void_p), ("in_window", C.c_void_p),
+                ("capacity", C.c_uint64), ("count", C.c_uint64)]
+
+
+class Coincidences(C.Structure):
+    _fields_ = [("first", C.c_void_p), ("second", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_uint64)]
+
+
+class Tallies(C.Structure):
+    _fields_ = [("hits_per_crystal", C.c_void_p), ("singles_per_crystal", C.c_void_p),
+                ("energy_spectrum", C.c_void_p), ("doi", C.c_void_p), ("doi_bins", C.c_int32)]
+
+
+EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_set_stream", "gpet_materials_set",
+           "gpet_geometry_create", "gpet_phantom_set", "gpet_source_set", "gpet_transport", "gpet_digitize",
+           "gpet_philox", "gpet_tables_get", "gpet_locate", "gpet_ray_locate", "gpet_sample_compton",
+           "gpet_sample_rayleigh", "gpet_trace", "gpet_ctx_enable_timing", "gpet_timings")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgpet.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2603_07327_amd.build`")
+    L = C.CDLL(path)
+    P, vp = C.POINTER, C.c_void_p
+    L.gpet_ctx_create.argtypes = [C.c_int, vp, P(vp)]
+    L.gpet_ctx_destroy.argtypes = [vp]
+    L.gpet_ctx_destroy.restype = None
+    L.gpet_last_error.argtypes = [vp]
+    L.gpet_last_error.restype = C.c_char_p
+    L.gpet_ctx_set_stream.argtypes = [vp, vp]
+    L.gpet_materials_set.argtypes = [vp, C.c_int32, P(Material), P(Physics)]
+    L.gpet_geometry_create.argtypes = [vp, P(Scanner), P(GeometryInfo)]
+    L.gpet_phantom_set.argtypes = [vp, P(Phantom)]
+    L.gpet_source_set.argtypes = [vp, P(Source)]
+    L.gpet_transport.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, P(Hits), P(Stats)]
+    L.gpet_digitize.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), P(Tallies)]
+    L.gpet_philox.argtypes = [vp, C.c_uint64, vp, C.c_uint32, vp]
+    L.gpet_tables_get.argtypes = [vp, vp, vp]
+    L.gpet_locate.argtypes = [vp, C.c_uint32, vp, vp]
+    L.gpet_ray_locate.argtypes = [vp, C.c_uint32, vp, vp, C.c_int32, C.c_float, vp, vp]
+    L.gpet_sample_compton.argtypes = [vp, C.c_float, C.c_uint32, C.c_uint64, vp, vp, vp]
+    L.gpet_sample_rayleigh.argtypes = [vp, C.c_uint32, C.c_uint64, vp]
+    L.gpet_trace.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int32, vp, vp, vp]
+    L.gpet_ctx_enable_timing.argtypes = [vp, C.c_int]
+    L.gpet_timings.argtypes = [vp, P(C.c_float)]
+    for name in EXPORTS:
+        if name not in ("gpet_ctx_destroy", "gpet_last_error"):
+            getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class HitList:
+    event: "torch.Tensor"
+    gid: "torch.Tensor"
+    edep_kev: "torch.Tensor"
+    depth_mm: "torch.Tensor"
+    time_ps: "torch.Tensor"
+    aux: "torch.Tensor"
+    count: int
+    first_event: int
+    n_events: int
+
+    def view(self):
+        n = self.count
+        return HitList(self.event[:n], self.gid[:n], self.edep_kev[:n], self.depth_mm[:n], self.time_ps[:n],
+                       self.aux[:n], n, self.first_event, self.n_events)
+
+    def numpy(self):
+        v = self.view()
+        return {k: getattr(v, k).cpu().numpy() for k in ("event", "gid", "edep_kev", "depth_mm", "time_ps", "aux")}
+
+
+@dataclass
+class SingleList:
+    event: "torch.Tensor"
+    gid: "torch.Tensor"
+    edep_kev: "torch.Tensor"
+    energy_kev: "torch.Tensor"
+    depth_mm: "torch.Tensor"
+    time_ps: "torch.Tensor"
+    in_window: "torch.Tensor"
+    count: int
+
+    def numpy(self):
+        n = self.count
+        return {k: getattr(self, k)[:n].cpu().numpy() for k in
+                ("event", "gid", "edep_kev", "energy_kev", "depth_mm", "time_ps", "in_window")}
+
+
+class Context:
+    """One library context on a GPU, ordering work on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the gpet library runs only on the device")
+        self.torch = torch
+        self.L = load_library()
+        self.dev = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.dev)
+        h = C.c_void_p()
+        self._check(self.L.gpet_ctx_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)), "create")
+        self.h = h
+        self.info = None
+        self.scene = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gpet_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what=""):
+        if rc != OK:
+            msg = self.L.gpet_last_error(self.h).decode() if getattr(self, "h", None) else what
+            raise GpetError(rc, msg or what)
+
+    def _empty(self, n, dtype):
+        return self.torch.empty(max(int(n), 1), dtype=dtype, device=self.dev)
+
+    def enable_timing(self, on=True):
+        self._check(self.L.gpet_ctx_enable_timing(self.h, 1 if on else 0))
+
+    def timings(self):
+        """(transport kernel ms, digitizer ms) of the last calls."""
+        out = (C.c_float * 2)()
+        self._check(self.L.gpet_timings(self.h, out))
+        return float(out[0]), float(out[1])
+
+    # ------------------------------------------------------------------ scene
+    def set_scene(self, sc: dict):
+        """Materials, scanner, phantom and source from a scene description."""
+        mats = sc["materials"]
+        arr = (Material * len(mats))()
+        for i, m in enumerate(mats):
+            q = arr[i]
+            q.density_g_cm3 = m["density"]
+            q.n_elements = len(m["Z"])
+            q.processes = m["mask"]
+            for j, (z, a, w) in enumerate(zip(m["Z"], m["A"], m["w"])):
+                q.Z[j], q.A[j], q.mass_fraction[j] = z, a, w
+        ph = sc["physics"]
+        phys = Physics(ph["k_pe"], ph["k_r"], ph["e_cut"])
+        self._check(self.L.gpet_materials_set(self.h, len(mats), arr, C.byref(phys)))
+        self.set_scanner(sc["scanner"])
+        self.set_phantom(sc.get("phantom"))
+        self.set_source(sc["source"])
+        self.scene = sc
+        return self.info
+
+    def set_scanner(self, g: dict):
+        s = Scanner()
+        s.placement = PLACE_EXPLICIT if g["mode"] == "explicit" else PLACE_REPEAT
+        s.n_panels = g["n_panels"]
+        s.radius_mm, s.phi0_rad, s.z0_mm = g["radius"], g["phi0"], g["z0"]
+        keep = None
+        if g["poses"] is not None:
+            keep = np.ascontiguousarray(g["poses"], np.float64)
+            s.poses = keep.ctypes.data_as(C.POINTER(C.c_double))
+        s.depth_mm, s.width_mm, s.length_mm = g["depth"], g["width"], g["length"]
+        s.mod_n_t, s.mod_n_a = g["mod_n_t"], g["mod_n_a"]
+        s.mod_t_mm, s.mod_a_mm, s.gap_t_mm, s.gap_a_mm = g["mod_t"], g["mod_a"], g["gap_t"], g["gap_a"]
+        s.fill_material = g["mat_fill"]
+        s.n_layers = len(g["layers"])
+        for i, y in enumerate(g["layers"]):
+            L = s.layers[i]
+            L.depth0_mm, L.thickness_mm = y["depth0"], y["thick"]
+            L.n_t, L.n_a = y["n_t"], y["n_a"]
+            L.cryst_t_mm, L.cryst_a_mm = y["cryst_t"], y["cryst_a"]
+            L.pitch_t_mm, L.pitch_a_mm = y["pitch_t"], y["pitch_a"]
+            L.offset_t_mm, L.offset_a_mm = y["off_t"], y["off_a"]
+            L.crystal_material, L.interval_material = y["mat_crystal"], y["mat_interval"]
+        info = GeometryInfo()
+        self._check(self.L.gpet_geometry_create(self.h, C.byref(s), C.byref(info)))
+        del keep
+        self.info = info
+        return info
+
+    def set_phantom(self, p):
+        if p is None:
+            self._check(self.L.gpet_phantom_set(self.h, None))
+            return
+        ph = Phantom()
+        ph.nx, ph.ny, ph.nz = p["shape"]
+        for k in range(3):
+            ph.voxel_mm[k] = p["voxel"][k]
+            ph.origin_mm[k] = p["origin"][k]
+        m8 = np.ascontiguousarray(p["mat"], np.uint8)
+        d32 = np.ascontiguousarray(p["dens"], np.float32)
+        ph.material = m8.ctypes.data_as(C.POINTER(C.c_uint8))
+        ph.density = d32.ctypes.data_as(C.POINTER(C.c_float))
+        self._check(self.L.gpet_phantom_set(self.h, C.byref(ph)))
+
+    def set_source(self, src: dict):
+        s = Source()
+        s.kind = src["kind"]
+        for k in range(3):
+            s.pos_mm[k] = src["pos"][k]
+            s.dir[k] = src["dir"][k]
+        keep = None
+        if src["rods"] is not None:
+            keep = np.ascontiguousarray(src["rods"], np.float64)
+            s.n_rods = len(keep)
+            s.rods = keep.ctypes.data_as(C.POINTER(C.c_double))
+        s.duration_ps = int(src["duration_ps"])
+        self._check(self.L.gpet_source_set(self.h, C.byref(s)))
+
+    # -------------------------------------------------------------- transport
+    def alloc_hits(self, capacity: int, first_event=0, n_events=0) -> HitList:
+        t = self.torch
+        return HitList(self._empty(capacity, t.int32), self._empty(capacity, t.int32),
+                       self._empty(capacity, t.float32), self._empty(capacity, t.float32),
+                       self._empty(capacity, t.int64), self._empty(capacity, t.int32), 0, first_event, n_events)
+
+    def transport_into(self, hits: HitList, n_events, seed=0, first=0, instance=0):
+        """Transport into preallocated hits; returns (status, stats dict)."""
+        h = Hits(hits.event.data_ptr(), hits.gid.data_ptr(), hits.edep_kev.data_ptr(), hits.depth_mm.data_ptr(),
+                 hits.time_ps.data_ptr(), hits.aux.data_ptr(), hits.event.numel(), 0)
+        st = Stats()
+        rc = self.L.gpet_transport(self.h, first, n_events, seed, instance, C.byref(h), C.byref(st))
+        hits.count = int(h.count)
+        hits.first_event, hits.n_events = first, n_events
+        if rc not in (OK, ERR_CAPACITY):
+            self._check(rc)
+        return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}
+
+    def transport(self, n_events, seed=0, first=0, instance=0, capacity=None):
+        cap = capacity or max(1024, int(3.5 * n_events))
+        hits = self.alloc_hits(cap)
+        rc, stats = self.transport_into(hits, n_events, seed, first, instance)
+        if rc == ERR_CAPACITY:
+            hits = self.alloc_hits(hits.count)
+            rc, stats = self.transport_into(hits, n_events, seed, first, instance)
+            self._check(rc)
+        return hits, stats
+
+    # -------------------------------------------------------------- digitizer
+    def alloc_singles(self, capacity) -> SingleList:
+        t = self.torch
+        return SingleList(self._empty(capacity, t.int32), self._empty(capacity, t.int32),
+                          self._empty(capacity, t.float32), self._empty(capacity, t.float32),
+                          self._empty(capacity, t.float32), self._empty(capacity, t.int64),
+                          self._empty(capacity, t.int32), 0)
+
+    def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
+                      e_hi=650.0, window_ps=3000, instance=0, tallies=None):
+        h = Hits(hits.event.data_ptr(), hits.gid.data_ptr(), hits.edep_kev.data_ptr(), hits.depth_mm.data_ptr(),
+                 hits.time_ps.data_ptr(), hits.aux.data_ptr(), hits.event.numel(), hits.count)
+        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, hits.first_event, max(1, hits.n_events))
+        s = Singles(*(getattr(singles, k).data_ptr() for k in
+                      ("event", "gid", "edep_kev", "energy_kev", "depth_mm", "time_ps", "in_window")),
+                    singles.event.numel(), 0)
+        cc = Coincidences(coinc[0].data_ptr(), coinc[1].data_ptr(), coinc[0].numel(), 0)
+        tl = None
+        if tallies is not None:
+            tl = Tallies(*(tallies[k].data_ptr() if tallies.get(k) is not None else None for k in
+                           ("hits_per_crystal", "singles_per_crystal", "energy_spectrum", "doi")),
+                         int(tallies["doi"].numel()) if tallies.get("doi") is not None else 0)
+        rc = self.L.gpet_digitize(self.h, C.byref(h), C.byref(dg), C.byref(s), C.byref(cc),
+                                  C.byref(tl) if tl is not None else None)
+        singles.count = int(s.count)
+        if rc not in (OK, ERR_CAPACITY):
+            self._check(rc)
+        return rc, int(cc.count)
+
+    def alloc_tallies(self, doi_bins=200):
+        t = self.torch
+        n = self.info.n_crystals
+        z = lambda k: t.zeros(k, dtype=t.int32, device=self.dev)  # noqa: E731
+        return {"hits_per_crystal": z(n), "singles_per_crystal": z(n), "energy_spectrum": z(700),
+                "doi": z(doi_bins)}
+
+    def digitize(self, hits: HitList, seed=0, tallies=None, **kw):
+        t = self.torch
+        cap = max(1024, hits.count)
+        singles = self.alloc_singles(cap)
+        coinc = (self._empty(cap // 2 + 16, t.int32), self._empty(cap // 2 + 16, t.int32))
+        rc, nc = self.digitize_into(hits, singles, coinc, seed=seed, tallies=tallies, **kw)
+        self._check(rc)
+        return singles, (coinc[0][:nc], coinc[1][:nc])
+
+    # ------------------------------------------------------------ check surface
+    def philox(self, seed: int, ctr: np.ndarray) -> np.ndarray:
+        t = self.torch
+        c = t.from_numpy(np.ascontiguousarray(ctr, np.uint32).view(np.int32).reshape(-1)).to(self.dev)
+        out = t.empty_like(c)
+        self._check(self.L.gpet_philox(self.h, seed, _ptr(c), c.numel() // 4, _ptr(out)))
+        return out.cpu().numpy().view(np.uint32).reshape(-1, 4)
+
+    def tables(self):
+        n = len(self.scene["materials"]) if self.scene else MAX_MAT
+        mu = np.zeros((n, 4, NODES), np.float32)
+        maj = np.zeros(NODES, np.float32)
+        self._check(self.L.gpet_tables_get(self.h, mu.ctypes.data_as(C.c_void_p), maj.ctypes.data_as(C.c_void_p)))
+        return mu, maj
+
+    def locate(self, xyz: np.ndarray) -> np.ndarray:
+        t = self.torch
+        x = t.from_numpy(np.ascontiguousarray(xyz, np.float32).reshape(-1)).to(self.dev)
+        n = x.numel() // 3
+        ids = self._empty(6 * n, t.int32)
+        self._check(self.L.gpet_locate(self.h, n, _ptr(x), _ptr(ids)))
+        return ids[: 6 * n].cpu().numpy().reshape(n, 6)
+
+    def ray_locate(self, o, d, n_samp, step):
+        t = self.torch
+        ot = t.from_numpy(np.ascontiguousarray(o, np.float32).reshape(-1)).to(self.dev)
+        dt = t.from_numpy(np.ascontiguousarray(d, np.float32).reshape(-1)).to(self.dev)
+        n = ot.numel() // 3
+        tin = self._empty(n, t.float32)
+        ids = self._empty(6 * n * n_samp, t.int32)
+        self._check(self.L.gpet_ray_locate(self.h, n, _ptr(ot), _ptr(dt), n_samp, step, _ptr(tin), _ptr(ids)))
+        return tin[:n].cpu().numpy(), ids[: 6 * n * n_samp].cpu().numpy().reshape(n, n_samp, 6)
+
+    def sample_compton(self, e_kev, n, seed=0):
+        t = self.torch
+        c, e, tr = self._empty(n, t.float32), self._empty(n, t.float32), self._empty(n, t.int32)
+        self._check(self.L.gpet_sample_compton(self.h, e_kev, n, seed, _ptr(c), _ptr(e), _ptr(tr)))
+        return c[:n].cpu().numpy(), e[:n].cpu().numpy(), tr[:n].cpu().numpy()
+
+    def sample_rayleigh(self, n, seed=0):
+        c = self._empty(n, self.torch.float32)
+        self._check(self.L.gpet_sample_rayleigh(self.h, n, seed, _ptr(c)))
+        return c[:n].cpu().numpy()
+
+    def trace(self, n_events, seed=0, first=0, instance=0, max_vertices=256):
+        """Traced histories as a numpy structured array in photon order."""
+        t = self.torch
+        np_ = 2 * n_events
+        vi = self._empty(np_ * max_vertices * 11, t.int32)
+        vf = self._empty(np_ * max_vertices * 8, t.float32)
+        cnt = self._empty(np_, t.int32)
+        self._check(self.L.gpet_trace(self.h, first, n_events, seed, instance, max_vertices, _ptr(vi), _ptr(vf),
+                                      _ptr(cnt)))
+        cnt = cnt[:np_].cpu().numpy()
+        if cnt.max(initial=0) > max_vertices:
+            return self.trace(n_events, seed, first, instance, int(cnt.max()))
+        vi = vi[: np_ * max_vertices * 11].cpu().numpy().reshape(np_, max_vertices, 11)
+        vf = vf[: np_ * max_vertices * 8].cpu().numpy().reshape(np_, max_vertices, 8)
+        keep = np.arange(max_vertices)[None, :] < cnt[:, None]
+        ints, flts = vi[keep], vf[keep]
+        names_i = ("event", "photon", "kind", "region", "panel", "gid", "mat", "accept", "process", "trials",
+                   "block")
+        names_f = ("x", "y", "z", "e", "edep", "dx", "dy", "dz")
+        out = np.zeros(len(ints), dtype=[(n, np.int32) for n in names_i] + [(n, np.float32) for n in names_f])
+        for k, n in enumerate(names_i):
+            out[n] = ints[:, k]
+        for k, n in enumerate(names_f):
+            out[n] = flts[:, k]
+        return out

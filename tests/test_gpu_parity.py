@@ -1,0 +1,312 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: bit-exact for integer work (Philox words, crystal/layer labels away from
+boundaries, sorter output on identical inputs); FP32 against FP64 within the
+stated tolerances; Monte Carlo tallies by RNG-matched comparison and by
+statistical tests at independent seeds.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import gpet_inputs as G
+from tests.gpu_util import chi2_two_sample, compare_histories
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _both(ctx, oracle_mod, sc):
+    ctx.set_scene(sc)
+    return oracle_mod.OracleScene(sc)
+
+
+# ---------------------------------------------------------------------------
+# random numbers and physics
+# ---------------------------------------------------------------------------
+def test_philox_bit_exact(ctx, oracle_mod):
+    n = 1 << 20
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:16] = 0
+    ctr[16:32] = 0xFFFFFFFF
+    seed = 0x0123456789ABCDEF
+    assert np.array_equal(ctx.philox(seed, ctr), oracle_mod.philox(seed, ctr))
+
+
+def test_tables_match_fp64_rounded(ctx, oracle_mod):
+    sc = G.small_animal_scene("C", n_events=10)
+    o = _both(ctx, oracle_mod, sc)
+    mu, maj = ctx.tables()
+    for m, mat in enumerate(sc["materials"]):
+        ref = o.mass_table()[m] * mat["density"] / 10.0  # 1/mm, [proc][node]
+        got = mu[m, :3].astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 2 * np.spacing(ref.astype(np.float32)) + 1e-30)
+    np.testing.assert_allclose(maj, o.majorant_det(), rtol=3e-7)
+
+
+@pytest.mark.parametrize("e", [511.0, 340.7, 100.0, 30.0])
+def test_compton_sampler_matched(ctx, oracle_mod, e):
+    n = 200_000
+    cg, eg, tg = ctx.sample_compton(e, n, seed=3)
+    co, eo, to = oracle_mod.sample_compton(e, n, seed=3)
+    same = tg == to
+    assert same.mean() > 0.999
+    # cos(theta) = 1 - (rho - 1)/alpha: FP32 rounding of rho (a few ulp of 1)
+    # is divided by alpha = E/m_e c^2, so the bar is 4 ulp(1)/alpha
+    a = e / 510.99895
+    np.testing.assert_allclose(cg[same], co[same], atol=4 * 2.0**-23 / a)
+    np.testing.assert_allclose(eg[same], eo[same], rtol=2e-6)
+    np.testing.assert_allclose(eg, e / (1.0 + a * (1.0 - cg.astype(np.float64))), rtol=1e-5)
+
+
+def test_rayleigh_sampler_matched(ctx, oracle_mod):
+    n = 200_000
+    np.testing.assert_allclose(ctx.sample_rayleigh(n, seed=5), oracle_mod.sample_rayleigh(n, seed=5), atol=2e-6)
+
+
+# ---------------------------------------------------------------------------
+# geometry
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("design", ["A", "B", "C"])
+def test_locate_bit_exact_off_boundaries(ctx, oracle_mod, design):
+    sc = G.small_animal_scene(design, n_events=10)
+    o = _both(ctx, oracle_mod, sc)
+    P = o.poses()
+    rng = np.random.default_rng(7)
+    n = 200_000
+    g = sc["scanner"]
+    p = rng.integers(0, g["n_panels"], n)
+    loc = np.stack([rng.uniform(-0.5, g["depth"] + 0.5, n), rng.uniform(-g["width"] / 2 - 1, g["width"] / 2 + 1, n),
+                    rng.uniform(-g["length"] / 2 - 1, g["length"] / 2 + 1, n)], 1)
+    xyz = P[p, 0:3] + loc[:, :1] * P[p, 3:6] + loc[:, 1:2] * P[p, 6:9] + loc[:, 2:3] * P[p, 9:12]
+    xyz = xyz.astype(np.float32).astype(np.float64)  # both sides see the same points
+    ids_o, bd = o.locate(xyz)
+    ids_g = ctx.locate(xyz)
+    far = bd > 1e-4
+    assert far.mean() > 0.99
+    assert np.array_equal(ids_g[far], ids_o[far])
+
+
+@pytest.mark.parametrize("case", ["ring8", "C"])
+def test_fixed_rays_bit_exact(ctx, oracle_mod, case):
+    sc = G.ring8_scene(n_events=10) if case == "ring8" else G.small_animal_scene("C", n_events=10)
+    o = _both(ctx, oracle_mod, sc)
+    rng = np.random.default_rng(11)
+    n = 20000
+    org = rng.uniform(-5, 5, (n, 3)).astype(np.float32).astype(np.float64)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = d.astype(np.float32).astype(np.float64)
+    t_o, ids_o, bd = o.ray_locate(org, d, 16, 0.6)
+    t_g, ids_g = ctx.ray_locate(org, d, 16, 0.6)
+    hit = t_o >= 0
+    assert np.array_equal(t_g >= 0, hit)
+    np.testing.assert_allclose(t_g[hit], t_o[hit], rtol=2e-6, atol=1e-5)
+    far = bd > 1e-4
+    assert far[hit].mean() > 0.98
+    assert np.array_equal(ids_g[far], ids_o[far])
+
+
+# ---------------------------------------------------------------------------
+# transport
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom"])
+def test_matched_histories(ctx, oracle_mod, case):
+    if case == "ring8":
+        sc, n = G.ring8_scene(n_events=5000), 5000
+    elif case == "C":
+        sc, n = G.small_animal_scene("C", n_events=5000), 5000
+    else:
+        sc, n = G.hot_rod_scene(n_events=3000), 3000
+    o = _both(ctx, oracle_mod, sc)
+    vo = o.trace(n, seed=1)
+    vg = ctx.trace(n, seed=1)
+    n_ph, n_div, wp, we, fails = compare_histories(vg, vo, o.poses())
+    print(f"{case}: {n_ph} photons, {n_div} diverged, worst pos {wp:.2e}, worst E {we:.2e}")
+    assert not fails, fails[:5]
+    assert n_div <= 0.01 * n_ph
+
+
+def test_energy_conservation_gpu(ctx, oracle_mod):
+    ctx.set_scene(G.small_animal_scene("C", n_events=5000))
+    v = ctx.trace(5000, seed=2)
+    key = v["event"].astype(np.int64) * 2 + v["photon"]
+    dep = np.bincount(key, weights=np.where(v["kind"] == 0, v["edep"], 0.0), minlength=10000)
+    esc = np.bincount(key, weights=np.where(v["kind"] == 3, v["e"], 0.0), minlength=10000)
+    np.testing.assert_allclose(dep + esc, 511.0, atol=1e-3)
+
+
+def _hits_as_oracle(oracle_mod, g):
+    h = np.zeros(len(g["event"]), dtype=np.dtype(oracle_mod.Hit))
+    h["event"] = g["event"].view(np.uint32)
+    h["gid"] = g["gid"].view(np.uint32)
+    h["edep"] = g["edep_kev"]
+    h["depth"] = g["depth_mm"]
+    h["time_ps"] = g["time_ps"].view(np.uint64)
+    h["photon"] = g["aux"].view(np.uint32) & 1
+    h["seq"] = g["aux"].view(np.uint32) >> 8
+    return h
+
+
+def test_digitizer_on_identical_hits(ctx, oracle_mod):
+    """GPU digitizer and oracle digitizer fed the same (GPU-produced) hits."""
+    n = 200_000
+    sc = G.small_animal_scene("C", n_events=n)
+    o = _both(ctx, oracle_mod, sc)
+    hits, _ = ctx.transport(n, seed=5)
+    sg, (ca, cb) = ctx.digitize(hits, seed=6)
+    h = _hits_as_oracle(oracle_mod, hits.numpy())
+    so, co = o.digitize(h, seed=6)
+    s = sg.numpy()
+    assert len(s["event"]) == len(so)
+    assert np.array_equal(s["event"].view(np.uint32), so["event"])
+    assert np.array_equal(s["gid"].view(np.uint32), so["gid"])
+    assert np.array_equal(s["time_ps"].view(np.uint64), so["time_ps"])
+    np.testing.assert_allclose(s["edep_kev"], so["edep"], rtol=1e-6, atol=1e-5)
+    np.testing.assert_allclose(s["depth_mm"], so["depth"], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(s["energy_kev"], so["energy"], rtol=1e-5, atol=1e-3)
+    edge = (np.abs(so["energy"] - 350) < 1e-2) | (np.abs(so["energy"] - 650) < 1e-2)
+    assert np.array_equal(s["in_window"][~edge] != 0, so["in_window"][~edge] != 0)
+    got = set(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
+    ref = set(map(tuple, co.tolist()))
+    assert len(got ^ ref) <= 4 * int(edge.sum())
+    assert len(ref) > 1000
+
+
+@pytest.mark.parametrize("case", ["ring8", "C"])
+def test_tallies_matched_seed(ctx, oracle_mod, case):
+    """Same seed and event ids: sensitivity within 0.5 % relative."""
+    n = 1_000_000 if case == "ring8" else 300_000
+    sc = G.ring8_scene(n_events=n) if case == "ring8" else G.small_animal_scene("C", n_events=n)
+    o = _both(ctx, oracle_mod, sc)
+    hits, st = ctx.transport(n, seed=0)
+    _, (ca, _) = ctx.digitize(hits, seed=0)
+    rh, rst = o.transport(n, seed=0)
+    _, rc = o.digitize(rh, seed=0)
+    print(case, "hits", hits.count, len(rh), "coinc", len(ca), len(rc), st, rst)
+    assert abs(len(ca) - len(rc)) / len(rc) <= 0.005
+    assert abs(hits.count - len(rh)) / len(rh) <= 0.002
+    for k in ("events", "steps", "real", "searches"):
+        assert abs(st[k] - rst[k]) <= 0.002 * rst[k] + 2, k
+
+
+def test_tallies_independent_seeds(ctx, oracle_mod):
+    """Oracle seed 1 against GPU seed 0: per-crystal in-window singles chi-square,
+    KS on blurred single energies, two-proportion z-test on sensitivity."""
+    n = 300_000
+    sc = G.small_animal_scene("C", n_events=n)
+    o = _both(ctx, oracle_mod, sc)
+    hits, _ = ctx.transport(n, seed=0)
+    sg, (ca, _) = ctx.digitize(hits, seed=0)
+    rh, _ = o.transport(n, seed=1)
+    so, rc = o.digitize(rh, seed=1)
+    s = sg.numpy()
+    nc = o.n_crystals
+    hg = np.bincount(s["gid"][s["in_window"] != 0], minlength=nc)
+    ho = np.bincount(so["gid"][so["in_window"] != 0].astype(np.int64), minlength=nc)
+    _, _, p = chi2_two_sample(hg, ho)
+    assert p > 0.01, p
+    sub = np.random.default_rng(0)
+    eg = sub.choice(s["energy_kev"], 100_000, replace=False)
+    eo = sub.choice(so["energy"], 100_000, replace=False)
+    assert stats.ks_2samp(eg, eo).pvalue > 0.01
+    p1, p2 = len(ca) / n, len(rc) / n
+    pp = (len(ca) + len(rc)) / (2 * n)
+    z = (p1 - p2) / math.sqrt(pp * (1 - pp) * 2 / n)
+    assert abs(z) < 4
+
+
+def test_black_ring_gpu(ctx, oracle_mod):
+    sc = G.black_ring_scene(12, 65.0, 24.0, 102.0, 20.0, n_events=2_000_000)
+    ctx.set_scene(sc)
+    n = 2_000_000
+    hits, _ = ctx.transport(n, seed=0)
+    g = hits.numpy()
+    ph = np.zeros((n, 2), bool)
+    ph[g["event"], g["aux"] & 1] = True
+    eta = 0.428965
+    k = (ph[:, 0] & ph[:, 1]).sum()
+    assert abs(k - n * eta) / math.sqrt(n * eta * (1 - eta)) < 4
+
+
+def test_narrow_beam_gpu(ctx, oracle_mod):
+    sc = G.ring8_scene(n_events=10)
+    sc["source"] = G.beam_source((0.0, 0.8, 0.8), (1.0, 0.0, 0.0))
+    o = _both(ctx, oracle_mod, sc)
+    n = 100_000
+    v = ctx.trace(n, seed=0, max_vertices=64)
+    a = v[(v["photon"] == 0) & (v["kind"] == 0) & (v["region"] == 1) & (v["accept"] == 1)]
+    p = math.exp(-o.mu(0, 511.0).sum() * 10.0)
+    k = n - len(np.unique(a["event"]))
+    assert abs(k - n * p) / math.sqrt(n * p * (1 - p)) < 4
+
+
+# ---------------------------------------------------------------------------
+# contracts
+# ---------------------------------------------------------------------------
+def test_determinism_and_chunking(ctx, oracle_mod):
+    n = 100_000
+    ctx.set_scene(G.small_animal_scene("C", n_events=n))
+    h1, _ = ctx.transport(n, seed=9)
+    s1, c1 = ctx.digitize(h1, seed=9)
+    h2, _ = ctx.transport(n, seed=9)
+    s2, c2 = ctx.digitize(h2, seed=9)
+    a, b = s1.numpy(), s2.numpy()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(c1[0].cpu().numpy(), c2[0].cpu().numpy())
+    # [0, k) + [k, n) carries the same hits as [0, n)
+    ha, _ = ctx.transport(40_000, seed=9, first=0)
+    hb, _ = ctx.transport(n - 40_000, seed=9, first=40_000)
+
+    def canon(h):
+        g = h.numpy()
+        key = np.lexsort((g["aux"], g["gid"], g["event"]))
+        return {k: v[key] for k, v in g.items()}
+    w = canon(h1)
+    cat = {k: np.concatenate([ha.numpy()[k], hb.numpy()[k]]) for k in w}
+    key = np.lexsort((cat["aux"], cat["gid"], cat["event"]))
+    for k in w:
+        assert np.array_equal(w[k], cat[k][key]), k
+
+
+def test_capacity_error_and_rerun(ctx, oracle_mod):
+    from paper_2603_07327_amd.gpet import ERR_CAPACITY
+    n = 20_000
+    ctx.set_scene(G.small_animal_scene("C", n_events=n))
+    small = ctx.alloc_hits(100)
+    rc, _ = ctx.transport_into(small, n, seed=4)
+    assert rc == ERR_CAPACITY and small.count > 100
+    big = ctx.alloc_hits(small.count)
+    rc, _ = ctx.transport_into(big, n, seed=4)
+    assert rc == 0 and big.count == small.count
+
+
+def test_edge_cases(ctx, oracle_mod):
+    ctx.set_scene(G.small_animal_scene("C", n_events=10))
+    h, st = ctx.transport(0, seed=1)
+    assert h.count == 0 and st["events"] == 0
+    s, c = ctx.digitize(h, seed=1)
+    assert s.count == 0 and len(c[0]) == 0
+    h, st = ctx.transport(1, seed=1, first=12345)
+    assert st["events"] == 1
+    g = h.numpy()
+    assert np.all(g["event"] == 12345)
+    # a ragged count that is no multiple of the block or wave size
+    h, st = ctx.transport(4097, seed=1, first=3)
+    assert st["events"] == 4097
+    ev = h.numpy()["event"]
+    assert ev.min() >= 3 and ev.max() < 3 + 4097
