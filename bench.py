@@ -30,20 +30,45 @@ import numpy as np  # noqa: E402
 
 import gpet_inputs as G  # noqa: E402
 
-# Algorithmic VALU work per primitive, in VALU lane-operations per lane,
-# quarter-rate instructions (transcendentals, 32-bit integer multiplies,
-# divisions' reciprocal steps) weighted 4.  Counted once from the gfx950
-# assembly of straight-line builds of each primitive.
-UNIT_COST = {"philox": 140, "step": 65, "kahn": 25, "rotation": 35, "slab": 25, "source": 120}
+# Algorithmic VALU work per primitive, in VALU lane-operations per lane, with
+# quarter-rate instructions (32-bit integer multiplies, transcendentals) weighted
+# 4: the weighted instruction counts of straight-line gfx950 builds of each
+# primitive in its division-free form (hardware reciprocal, rsq, sin/cos in
+# revolutions, 64-bit-multiply Philox), minus an empty load/store kernel.
+UNIT_COST = {"philox": 156, "step": 142, "kahn": 38, "rotation": 54, "slab": 88, "source": 18}
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (no packed FP32)
+EVENT_BLOCKS = 3              # Philox blocks of the event stream per annihilation
+TRANSPORT_SOURCES = ("paper_2603_07327_amd/csrc/transport.hip", "paper_2603_07327_amd/csrc/gpet_device.hpp")
 
 
 def algorithmic_work(stats: dict, n_panels: int) -> float:
-    """VALU lane-ops the method needs for a transport launch with these counts."""
-    return (stats["blocks"] * UNIT_COST["philox"] + 3 * stats["events"] * UNIT_COST["philox"]
+    """VALU lane-ops the method needs for a transport launch with these counts:
+    W = N_blocks c_philox + N_steps c_step + N_trials c_kahn + N_scatter c_rot
+        + N_search n_panels c_slab + N_events c_source."""
+    return ((stats["blocks"] + EVENT_BLOCKS * stats["events"]) * UNIT_COST["philox"]
             + stats["steps"] * UNIT_COST["step"] + stats["kahn_trials"] * UNIT_COST["kahn"]
-            + stats["real"] * UNIT_COST["rotation"] + stats["searches"] * n_panels * UNIT_COST["slab"]
+            + stats["scatters"] * UNIT_COST["rotation"] + stats["searches"] * n_panels * UNIT_COST["slab"]
             + stats["events"] * UNIT_COST["source"])
+
+
+def transport_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRANSPORT_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(events_per_launch: int):
+    """HBM bytes per transport launch from the committed counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_transport_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != transport_source_hash():
+        return None
+    return d["bytes_per_event"] * events_per_launch
 
 
 def cpu_baseline(target_s: float = 12.0):
@@ -75,6 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=10_000_000, help="events per design and position")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the event-parallel sharding "
@@ -118,6 +145,12 @@ def main():
             out.append((d, hits.count, singles.count, nc))
         return out
 
+    if args.calib_copy_mib:
+        a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for i in range(args.warmup):
         step(i, False)
     torch.cuda.synchronize()
@@ -140,7 +173,8 @@ def main():
                    "crystals": ctxs[2][1].info.n_crystals, "positions_per_step": 1, "form": "plain"},
         "roofline": {"bound": "alu", "kernel": "k_transport", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK / 1e12, "unit": "TVALU-op/s", "frac": achieved / VALU_PEAK,
-                     "traffic": None, "kernel_ms": avg_ms, "work_per_launch": float(np.mean(work))},
+                     "traffic": measured_traffic(n), "kernel_ms": avg_ms,
+                     "work_per_launch": float(np.mean(work)), "transport_source": transport_source_hash()},
         "last_step": res, "stats_last": stats_last,
     }
     if not args.no_cpu_baseline:

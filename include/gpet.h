@@ -214,7 +214,7 @@ typedef struct {
 /* Work counters of a transport call (for roofline accounting). */
 typedef struct {
   uint64_t events, panel_entries, steps, real_interactions, kahn_trials, panel_searches,
-      rng_blocks, capped;
+      rng_blocks, capped, scatters;
 } gpet_stats;
 
 /* Transport events [first_event, first_event + n_events) with key `seed`.

@@ -350,7 +350,20 @@ static loc_t locate_local(const or_scene *s, int p, const double l[3], double *b
   return r;
 }
 
-/* locate global points: ids6 = (panel, module, layer, crystal, gid, material) */
+/* distance from a local point outside the panel box to the box */
+static double outside_distance(const or_scanner *sc, const double l[3]) {
+  double lo[3] = {0.0, -0.5 * sc->width, -0.5 * sc->length};
+  double hi[3] = {sc->depth, 0.5 * sc->width, 0.5 * sc->length};
+  double q = 0;
+  for (int k = 0; k < 3; k++) {
+    double e = l[k] < lo[k] ? lo[k] - l[k] : (l[k] > hi[k] ? l[k] - hi[k] : 0.0);
+    q += e * e;
+  }
+  return sqrt(q);
+}
+
+/* locate global points: ids6 = (panel, module, layer, crystal, gid, material);
+ * bdist: distance to the nearest boundary (panel faces included) */
 void or_locate(const or_scene *s, int64_t n, const double *xyz, int32_t *ids6, double *bdist) {
   const or_scanner *sc = &s->scan;
   for (int64_t i = 0; i < n; i++) {
@@ -360,11 +373,15 @@ void or_locate(const or_scene *s, int64_t n, const double *xyz, int32_t *ids6, d
     for (int p = 0; p < sc->n_panels; p++) {
       double l[3];
       to_local(sc->pose[p], xyz + 3 * i, l);
-      if (!inside_panel(sc, l)) continue;
+      if (!inside_panel(sc, l)) {
+        double od = outside_distance(sc, l);
+        if (bdist && od < bdist[i]) bdist[i] = od;
+        continue;
+      }
       double b;
       loc_t r = locate_local(s, p, l, &b);
       o[0] = p; o[1] = r.module; o[2] = r.layer; o[3] = r.crystal; o[4] = r.gid; o[5] = r.mat;
-      if (bdist) bdist[i] = b;
+      if (bdist && b < bdist[i]) bdist[i] = b;
       break;
     }
   }

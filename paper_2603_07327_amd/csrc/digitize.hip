@@ -230,19 +230,21 @@ __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t 
   s_time[s] = tm;
 }
 
-__global__ void k_blur(size_t n, const uint32_t *s_ev, const uint32_t *s_gid, const float *s_edep, float *s_energy,
-                       uint32_t *s_win, uint32_t *wflag, uint32_t k0, uint32_t k1, uint32_t inst, float fwhm,
-                       float e_lo, float e_hi, uint32_t *spp, uint32_t *spec, const unsigned long long *s_time,
-                       unsigned long long *tmax) {
+__global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, const uint32_t *s_gid,
+                                              const float *s_edep, float *s_energy, uint32_t *s_win, uint32_t *wflag,
+                                              uint32_t k0, uint32_t k1, uint32_t inst, float fwhm, float e_lo,
+                                              float e_hi, uint32_t *spp, uint32_t *spec,
+                                              const unsigned long long *s_time, unsigned long long *block_max) {
+  __shared__ unsigned long long s_max[4];
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // largest time stamp among windowed singles: wave maximum, one atomic per wave
-  unsigned long long tm = 0;
+  unsigned long long tm = 0; // largest time stamp among windowed singles
   if (i < n) {
+    // normal deviate by Box-Muller from the digitizer stream of (gid, event)
     const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], inst, 3u));
     const float u0 = to_unit(w.x), u1 = to_unit(w.y);
-    const float g = sqrtf(-2.0f * logf(u0)) * cosf(kTwoPi * u1);
+    const float g = sqrtf(-2.0f * logf(u0)) * cos_rev(u1);
     const float E = s_edep[i];
-    const float sig = fwhm * sqrtf(511.0f * E) / 2.354820045f;
+    const float sig = fwhm * sqrtf(511.0f * E) * (1.0f / 2.354820045f);
     const float Eb = E + sig * g;
     const uint32_t in = (Eb >= e_lo && Eb <= e_hi) ? 1u : 0u;
     s_energy[i] = Eb;
@@ -257,7 +259,26 @@ __global__ void k_blur(size_t n, const uint32_t *s_ev, const uint32_t *s_gid, co
     const unsigned long long t = __shfl_xor(tm, o);
     tm = t > tm ? t : tm;
   }
-  if (__lane_id() == 0 && tm) atomicMax(tmax, tm);
+  if (__lane_id() == 0) s_max[threadIdx.x >> 6] = tm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = s_max[0];
+    for (int k = 1; k < 4; ++k) b = s_max[k] > b ? s_max[k] : b;
+    block_max[blockIdx.x] = b;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_max_u64(const unsigned long long *v, size_t n, unsigned long long *out) {
+  __shared__ unsigned long long s[1024];
+  unsigned long long m = 0;
+  for (size_t i = threadIdx.x; i < n; i += 1024) m = v[i] > m ? v[i] : m;
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] = s[threadIdx.x + o] > s[threadIdx.x] ? s[threadIdx.x + o] : s[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
 }
 
 __global__ void k_time_keys(size_t n, const uint32_t *win, const uint32_t *pos, const unsigned long long *s_time,
@@ -405,12 +426,14 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   }
   hipLaunchKernelGGL(k_adder, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_event, D.h_gid, D.h_edep,
                      D.h_depth, D.h_time, S->event, S->gid, S->edep_kev, S->depth_mm, (unsigned long long *)S->time_ps, S->capacity);
-  // 3. blur + window
-  launch_fill_u32((uint32_t *)tmax_dev, 0u, 2, st);
+  // 3. blur + window; per-block maxima of the windowed time stamps go to the
+  //    (now free) second key array, then one block reduces them
   hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, S->edep_kev,
                      S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.instance, D.fwhm_511, D.e_lo, D.e_hi,
-                     T ? T->singles_per_crystal : nullptr, T ? T->energy_spectrum : nullptr, (const unsigned long long *)S->time_ps,
-                     tmax_dev);
+                     T ? T->singles_per_crystal : nullptr, T ? T->energy_spectrum : nullptr,
+                     (const unsigned long long *)S->time_ps, sb.k1);
+  hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
+                     (size_t)grid_for(ns), tmax_dev);
   (void)hipMemcpyAsync(rb + 2, wpos + ns - 1, 4, hipMemcpyDeviceToHost, st);
   exclusive_scan(wpos, ns, sb.scan_tmp, st);
   (void)hipMemcpyAsync(rb + 3, wpos + ns - 1, 4, hipMemcpyDeviceToHost, st);

@@ -114,7 +114,7 @@ void gpet_ctx_destroy(gpet_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (void *p : {(void *)c->d_mu, (void *)c->d_mu_mass, (void *)c->d_maj_det, (void *)c->d_maj_ph,
+  for (void *p : {(void *)c->d_mu, (void *)c->d_mu_mass, (void *)c->d_mu_det, (void *)c->d_maj_det, (void *)c->d_maj_ph,
                   (void *)c->d_pose, (void *)c->d_vmat, (void *)c->d_vden, (void *)c->d_rods,
                   (void *)c->d_rod_cum, (void *)c->d_ctrl})
     if (p) (void)hipFree(p);
@@ -230,27 +230,34 @@ gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geomet
   const int64_t total = per_panel * g->n_panels;
   if (total >= (1 << 20)) return bad("more than 2^20 crystals");
 
-  // panel poses: repetition mode places panel k at angle phi0 + 2 pi k / n
+  // panel poses: repetition mode places panel k at angle phi0 + 2 pi k / n.
+  // Device layout per panel: rows of the local axes (depth, t, a) in global
+  // coordinates, then the front-face centre projected on each axis.
   std::vector<float> pose((size_t)g->n_panels * 12);
   for (int k = 0; k < g->n_panels; ++k) {
-    double P[12];
+    double o[3], ax[9];
     if (g->placement == GPET_PLACE_REPEAT) {
       const double a = g->phi0_rad + 2.0 * kPi * k / g->n_panels;
       const double ca = std::cos(a), sa = std::sin(a);
-      const double v[12] = {g->radius_mm * ca, g->radius_mm * sa, g->z0_mm, ca, sa, 0.0, -sa, ca, 0.0, 0.0, 0.0, 1.0};
-      std::memcpy(P, v, sizeof(P));
+      const double oo[3] = {g->radius_mm * ca, g->radius_mm * sa, g->z0_mm};
+      const double aa[9] = {ca, sa, 0.0, -sa, ca, 0.0, 0.0, 0.0, 1.0};
+      std::memcpy(o, oo, sizeof(o));
+      std::memcpy(ax, aa, sizeof(ax));
     } else if (g->placement == GPET_PLACE_EXPLICIT) {
       if (!g->poses) return bad("explicit placement needs poses");
-      std::memcpy(P, g->poses + 12 * k, sizeof(P));
+      std::memcpy(o, g->poses + 12 * k, sizeof(o));
+      std::memcpy(ax, g->poses + 12 * k + 3, sizeof(ax));
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-          const double dot = P[3 + 3 * i] * P[3 + 3 * j] + P[4 + 3 * i] * P[4 + 3 * j] + P[5 + 3 * i] * P[5 + 3 * j];
+          const double dot = ax[3 * i] * ax[3 * j] + ax[3 * i + 1] * ax[3 * j + 1] + ax[3 * i + 2] * ax[3 * j + 2];
           if (std::fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-6) return bad("pose axes are not orthonormal");
         }
     } else {
       return bad("unknown placement mode");
     }
-    for (int i = 0; i < 12; ++i) pose[(size_t)k * 12 + i] = (float)P[i];
+    float *P = &pose[(size_t)k * 12];
+    for (int i = 0; i < 9; ++i) P[i] = (float)ax[i];
+    for (int i = 0; i < 3; ++i) P[9 + i] = (float)(ax[3 * i] * o[0] + ax[3 * i + 1] * o[1] + ax[3 * i + 2] * o[2]);
   }
   (void)hipSetDevice(c->device);
   gpet_status s = upload(c, c->d_pose, pose.data(), pose.size(), "geometry: upload");
@@ -277,6 +284,34 @@ gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geomet
   s = upload(c, c->d_maj_det, maj.data(), maj.size(), "geometry: upload");
   if (s) return s;
 
+  // detector attenuation rows staged in LDS by the transport kernel: one slot
+  // per distinct material of the panel
+  std::vector<int> slot_of(c->n_mat, -1);
+  std::vector<int> slot_mat;
+  auto slot = [&](int m) {
+    if (slot_of[m] < 0) {
+      slot_of[m] = (int)slot_mat.size();
+      slot_mat.push_back(m);
+    }
+    return slot_of[m];
+  };
+  const int fill_slot = slot(g->fill_material);
+  int slot_c[GPET_MAX_LAYERS], slot_i[GPET_MAX_LAYERS];
+  for (int l = 0; l < g->n_layers; ++l) {
+    slot_c[l] = slot(g->layers[l].crystal_material);
+    slot_i[l] = slot(g->layers[l].interval_material);
+  }
+  if (slot_mat.size() > 4) return fail(c, GPET_ERR_UNSUPPORTED, "geometry: more than 4 distinct detector materials");
+  std::vector<float4> det_rows(slot_mat.size() * kTabStride);
+  for (size_t q = 0; q < slot_mat.size(); ++q)
+    for (int k = 0; k < kTabStride; ++k) {
+      const int node = std::min(k, kNodes - 1);
+      const float *src = &c->mu_host[((size_t)slot_mat[q] * 4) * kNodes + node];
+      det_rows[q * kTabStride + k] = make_float4(src[0], src[kNodes], src[2 * kNodes], src[3 * kNodes]);
+    }
+  s = upload(c, c->d_mu_det, det_rows.data(), det_rows.size(), "geometry: upload");
+  if (s) return s;
+
   DevScene &S = c->scene;
   S.n_panels = g->n_panels;
   S.depth = (float)g->depth_mm;
@@ -289,9 +324,12 @@ gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geomet
   S.mod_a0 = (float)(-0.5 * l_mod);
   S.mod_step_t = (float)(g->mod_t_mm + g->gap_t_mm);
   S.mod_step_a = (float)(g->mod_a_mm + g->gap_a_mm);
+  S.inv_step_t = (float)(1.0 / (g->mod_t_mm + g->gap_t_mm));
+  S.inv_step_a = (float)(1.0 / (g->mod_a_mm + g->gap_a_mm));
   S.mod_t = (float)g->mod_t_mm;
   S.mod_a = (float)g->mod_a_mm;
   S.fill = g->fill_material;
+  S.fill_slot = fill_slot;
   S.n_layers = g->n_layers;
   int base = 0;
   for (int l = 0; l < g->n_layers; ++l) {
@@ -303,6 +341,10 @@ gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geomet
     d.off_a = (float)y.offset_a_mm;
     d.pitch_t = (float)y.pitch_t_mm;
     d.pitch_a = (float)y.pitch_a_mm;
+    d.inv_pitch_t = (float)(1.0 / y.pitch_t_mm);
+    d.inv_pitch_a = (float)(1.0 / y.pitch_a_mm);
+    d.slot_crystal = slot_c[l];
+    d.slot_interval = slot_i[l];
     d.lo_t = (float)(0.5 * (y.pitch_t_mm - y.cryst_t_mm));
     d.hi_t = (float)(0.5 * (y.pitch_t_mm + y.cryst_t_mm));
     d.lo_a = (float)(0.5 * (y.pitch_a_mm - y.cryst_a_mm));
@@ -318,6 +360,8 @@ gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geomet
   S.crystals_per_module = (int)per_module;
   S.crystals_per_panel = (int)per_panel;
   S.maj_det = c->d_maj_det;
+  S.mu_det = c->d_mu_det;
+  S.n_det_slots = (int)slot_mat.size();
   S.mu = c->d_mu;
   S.mu_mass = c->d_mu_mass;
   S.e_cut = (float)c->phys.e_cut_kev;
@@ -378,9 +422,9 @@ gpet_status gpet_phantom_set(gpet_ctx *c, const gpet_phantom *ph) {
   S.ox = (float)ph->origin_mm[0];
   S.oy = (float)ph->origin_mm[1];
   S.oz = (float)ph->origin_mm[2];
-  S.vx = (float)ph->voxel_mm[0];
-  S.vy = (float)ph->voxel_mm[1];
-  S.vz = (float)ph->voxel_mm[2];
+  S.ivx = (float)(1.0 / ph->voxel_mm[0]);
+  S.ivy = (float)(1.0 / ph->voxel_mm[1]);
+  S.ivz = (float)(1.0 / ph->voxel_mm[2]);
   S.bx = (float)(ph->origin_mm[0] + ph->nx * ph->voxel_mm[0]);
   S.by = (float)(ph->origin_mm[1] + ph->ny * ph->voxel_mm[1]);
   S.bz = (float)(ph->origin_mm[2] + ph->nz * ph->voxel_mm[2]);
@@ -469,20 +513,20 @@ gpet_status gpet_transport(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t see
   A.h_time = (unsigned long long *)h->time_ps;
   A.h_aux = h->aux;
   A.capacity = h->capacity;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 20, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 22, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
   if (n) launch_transport(c->scene, A, c->shape, c->n_cu, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
   s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
-  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 10 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 11 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
   if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "transport: kernel");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (c->timing) (void)hipEventElapsedTime(&c->last_ms[0], c->ev[0], c->ev[1]);
   if (stats) {
     uint64_t *o = (uint64_t *)stats;
-    for (int k = 0; k < 8; ++k) o[k] = c->h_ctrl[2 + k];
+    for (int k = 0; k < 9; ++k) o[k] = c->h_ctrl[2 + k];
   }
   if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "transport: hit capacity too small");
   return GPET_OK;
@@ -621,7 +665,7 @@ gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, u
   A.vflt = vflt;
   A.vcount = counts;
   A.max_vertices = maxv;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 20, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 22, c->stream);
   launch_fill_u32((uint32_t *)counts, 0u, 2 * (size_t)n, c->stream);
   if (n) launch_trace(c->scene, A, c->stream);
   s = hip_check(c, hipGetLastError(), "trace: launch");

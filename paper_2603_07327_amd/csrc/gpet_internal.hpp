@@ -21,7 +21,7 @@ struct RunArgs {
   unsigned long long capacity;
   unsigned long long *hit_count; // device
   uint32_t *work;                // device event-fetch counter
-  unsigned long long *stats;     // device, 8 counters (gpet_stats order)
+  unsigned long long *stats;     // device, 9 counters (gpet_stats order)
   // trace mode
   int32_t *vint;
   float *vflt;
@@ -30,9 +30,9 @@ struct RunArgs {
 };
 
 struct LaunchShape {
-  int block = 256;
-  int blocks_per_cu = 8;
+  int blocks_per_cu = 8; // resident-or-queued blocks of 256 lanes per CU
 };
+size_t transport_lds_bytes(int det_slots);
 
 // kernels (transport.hip)
 void launch_transport(const DevScene &S, const RunArgs &A, const LaunchShape &L, int n_cu,
@@ -87,7 +87,7 @@ struct gpet_ctx {
   gpet_physics phys{};
   std::vector<float> mu_host;      // [n_mat][4][kNodes] nominal density
   std::vector<float> mu_mass_host; // [n_mat][4][kNodes] per g/cm^3
-  float4 *d_mu = nullptr, *d_mu_mass = nullptr;
+  float4 *d_mu = nullptr, *d_mu_mass = nullptr, *d_mu_det = nullptr;
   float *d_maj_det = nullptr, *d_maj_ph = nullptr;
   std::vector<float> maj_det_host;
   // geometry
@@ -100,7 +100,7 @@ struct gpet_ctx {
   // source
   bool have_source = false;
   float *d_rods = nullptr, *d_rod_cum = nullptr;
-  // device controls: [0] work (u32 x2), [1] hit count, [2..9] stats
+  // device controls: [0] work (u32 x2), [1] hit count, [2..10] stats
   unsigned long long *d_ctrl = nullptr;
   unsigned long long *h_ctrl = nullptr; // pinned mirror of d_ctrl
   gpet::DevScene scene{};

@@ -1,21 +1,40 @@
 // transport.hip -- photon-pair transport kernel for gfx950.
 //
 // One lane owns one annihilation event at a time and runs it as a small state
-// machine, one action per loop trip: a Woodcock step in the phantom, a panel
-// search, or a Woodcock step inside a panel (paper Sec. 2.1: line-plane
-// projection to the panel, transform to the panel frame, step-by-step
-// transport with the layer chosen from the depth coordinate).  A lane whose
-// event is finished fetches the next event id with one wave-aggregated atomic,
-// so lanes stay busy however long their histories are.  Hits are appended
-// with one wave-aggregated atomic per loop trip into structure-of-arrays
-// outputs.
+// machine, one action per loop trip: an emission step, a Woodcock step in the
+// phantom, a panel search, a Woodcock step inside a panel (paper Sec. 2.1:
+// line-plane projection to the panel, transform to the panel frame,
+// step-by-step transport with the layer chosen from the depth coordinate), a
+// Kahn trial or a Rayleigh angle.
+//
+// Every action that needs random numbers takes exactly one Philox block, drawn
+// at a single call site at the top of the trip, so the costliest primitive runs
+// once per trip with all its lanes together instead of once per divergent
+// branch.  Event ids are handed out per wave in chunks (one atomic per chunk);
+// hits are staged per wave in LDS and written out 64 at a time (one atomic and
+// coalesced stores per flush).  The detector attenuation rows and majorant are
+// staged in LDS at kernel start.
 #include "gpet_internal.hpp"
 
 namespace gpet {
 
-enum : int { P_FETCH = 0, P_PHANTOM = 1, P_SEARCH = 2, P_PANEL = 3, P_DONE = 4 };
+enum : int {
+  P_FETCH = 0, P_EMIT_DIR = 1, P_EMIT_POS = 2, P_EMIT_TIME = 3, P_PHANTOM = 4, P_SEARCH = 5,
+  P_PANEL = 6, P_KAHN = 7, P_RAYLEIGH = 8, P_DONE = 9
+};
 enum : int { V_STEP = 0, V_ENTER_PANEL = 1, V_EXIT = 2, V_ESCAPE = 3, V_DEAD = 4, V_ENTER_PHANTOM = 5,
              V_EMIT = 6 };
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kStage = 128;       // staged hits per wave; flushed when 64 or more are pending
+constexpr uint32_t kChunk = 256;  // event ids taken by a wave per atomic
+
+// LDS bytes of one block for a scene with `slots` detector table rows
+size_t transport_lds_bytes(int slots) {
+  return (size_t)slots * kTabStride * sizeof(float4) + kTabStride * sizeof(float) +
+         (size_t)kWaves * kStage * (4 * 5 + 8);
+}
 
 template <bool TRACE>
 __device__ __forceinline__ void vertex(const RunArgs &A, uint32_t ev, int ph, int kind, int region,
@@ -36,29 +55,77 @@ __device__ __forceinline__ void vertex(const RunArgs &A, uint32_t ev, int ph, in
   }
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+__device__ __forceinline__ unsigned long long count(bool b) { return (unsigned long long)__popcll(__ballot(b)); }
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// per-wave staging area of hits in LDS (structure of arrays)
+struct Stage {
+  uint32_t *ev, *gid, *aux;
+  float *edep, *depth;
+  unsigned long long *time;
+};
+
+// write `cnt` staged hits of this wave to the global SoA arrays
+__device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, uint32_t cnt, int lane) {
+  if (cnt == 0) return;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(A.hit_count, (unsigned long long)cnt);
+  base = __shfl(base, 0);
+  wave_sync_lds();
+  for (uint32_t k = (uint32_t)lane; k < cnt; k += 64) {
+    const unsigned long long i = base + k;
+    if (i < A.capacity) {
+      A.h_event[i] = st.ev[k];
+      A.h_gid[i] = st.gid[k];
+      A.h_edep[i] = st.edep[k];
+      A.h_depth[i] = st.depth[k];
+      A.h_time[i] = st.time[k];
+      A.h_aux[i] = st.aux[k];
+    }
+  }
+  wave_sync_lds();
 }
 
 template <bool TRACE>
-__global__ void __launch_bounds__(256) k_transport(DevScene S, RunArgs A) {
+__global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
+  extern __shared__ float4 lds4[];
   const int lane = (int)__lane_id();
+  const int wave = (int)(threadIdx.x >> 6);
   const uint64_t below = __lanemask_lt();
 
+  // ---- stage the detector attenuation rows and majorant in LDS
+  float4 *s_mu = lds4;
+  float *s_maj = (float *)(lds4 + (size_t)S.n_det_slots * kTabStride);
+  for (int i = threadIdx.x; i < S.n_det_slots * kTabStride; i += kBlock) s_mu[i] = S.mu_det[i];
+  for (int i = threadIdx.x; i < kTabStride; i += kBlock) s_maj[i] = S.maj_det[i];
+  char *stage_base = (char *)(s_maj + kTabStride) + (size_t)wave * kStage * (4 * 5 + 8);
+  Stage st;
+  st.time = (unsigned long long *)stage_base;
+  st.ev = (uint32_t *)(st.time + kStage);
+  st.gid = st.ev + kStage;
+  st.aux = st.gid + kStage;
+  st.edep = (float *)(st.aux + kStage);
+  st.depth = st.edep + kStage;
+  __syncthreads();
+
   int phase = P_FETCH;
-  uint32_t ev = 0;
-  int ph = 0;
+  uint32_t ev = 0, n = 0, sid = 0, seq = 0;
+  int ph = 0, panel = -1, last = -1, steps = 0;
   Vec x{0.f, 0.f, 0.f}, d{0.f, 0.f, 1.f};
   float e = 0.f, L = 0.f;
-  Stream rng{A.k0, A.k1, 0u, A.instance, 0u, 0u};
-  int panel = -1, last = -1, steps = 0;
-  uint32_t seq = 0;
   Vec src{0.f, 0.f, 0.f}, sdir{0.f, 0.f, 1.f};
   unsigned long long t_event = 0;
-  uint32_t c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0,
-           c_blocks = 0, c_capped = 0;
+  // pending interaction (or emission) state
+  float q_u0 = 0.f, q_u1 = 0.f; // azimuth uniform of the pending scatter / rod uniforms
+  int q_gid = -1, q_mat = -1, q_trials = 0, q_back = P_PANEL;
+  // wave-uniform bookkeeping
+  uint32_t chunk_next = 0, chunk_end = 0, staged = 0;
+  unsigned long long c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0,
+                     c_blocks = 0, c_capped = 0, c_scatter = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
   auto start_photon = [&](int which) {
@@ -70,9 +137,8 @@ __global__ void __launch_bounds__(256) k_transport(DevScene S, RunArgs A) {
     seq = 0;
     steps = 0;
     last = -1;
-    rng.event = ev;
-    rng.id = 1u + (uint32_t)which;
-    rng.n = 0;
+    n = 0;
+    sid = 1u + (uint32_t)which;
     vertex<TRACE>(A, ev, ph, V_EMIT, -1, -1, -1, -1, 0, 0, 0, 0, x, e, 0.f, d);
     phase = P_SEARCH;
     if (S.has_phantom) {
@@ -84,84 +150,105 @@ __global__ void __launch_bounds__(256) k_transport(DevScene S, RunArgs A) {
           x = Vec{x.x + t0 * d.x, x.y + t0 * d.y, x.z + t0 * d.z};
           L += t0;
           phase = P_PHANTOM;
-          vertex<TRACE>(A, ev, ph, V_ENTER_PHANTOM, 0, -1, -1, -1, 0, 0, 0, rng.n, x, e, 0.f, d);
+          vertex<TRACE>(A, ev, ph, V_ENTER_PHANTOM, 0, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         }
       }
     }
   };
 
-  // annihilation point, isotropic direction and event time (event stream 0)
-  auto emit = [&]() {
-    Stream r0{A.k0, A.k1, ev, A.instance, 0u, 0u};
-    const float4 a = r0.next();
-    const float4 b = r0.next();
-    const uint4 w = philox(A.k0, A.k1, make_uint4(2u, ev, A.instance, 0u));
-    t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
-    const float ct = 2.0f * a.x - 1.0f, st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-    float sp, cp;
-    sincosf(kTwoPi * a.y, &sp, &cp);
-    sdir = Vec{st * cp, st * sp, ct};
-    src = Vec{S.sx, S.sy, S.sz};
-    if (S.src_kind == 2) {
-      sdir = Vec{S.bdx, S.bdy, S.bdz};
-    } else if (S.src_kind == 1) {
-      const float tgt = a.z * S.rod_total;
-      int i = 0;
-      while (i < S.n_rods - 1 && S.rod_cum[i] < tgt) ++i;
-      const float *rd = S.rods + 5 * i;
-      const float rr = rd[2] * sqrtf(a.w);
-      float ps, pc;
-      sincosf(kTwoPi * b.x, &ps, &pc);
-      src = Vec{rd[0] + rr * pc, rd[1] + rr * ps, rd[3] + b.y * (rd[4] - rd[3])};
-    }
-    ++c_events;
-    start_photon(0);
-  };
-
   for (;;) {
-    // lanes without an event take the next ids, one atomic per wave
+    // ---- lanes without an event take the next ids from the wave's chunk
     const bool need = phase == P_FETCH;
     const uint64_t m = __ballot(need);
     if (m) {
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(A.work, (uint32_t)__popcll(m));
-      base = __shfl(base, leader);
+      const uint32_t k = (uint32_t)__popcll(m);
+      const uint32_t rank = (uint32_t)__popcll(m & below);
+      const uint32_t avail = chunk_end - chunk_next;
+      uint32_t fresh = 0;
+      if (k > avail) { // open a new chunk; the old one's remainder goes first
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(A.work, kChunk);
+        fresh = __builtin_amdgcn_readfirstlane(__shfl(b, 0));
+      }
       if (need) {
-        const uint32_t idx = base + (uint32_t)__popcll(m & below);
+        const uint32_t idx = rank < avail ? chunk_next + rank : fresh + (rank - avail);
         if (idx < A.n) {
           ev = A.first + idx;
-          emit();
+          phase = P_EMIT_DIR;
+          n = 0;
+          sid = 0;
         } else {
           phase = P_DONE;
         }
       }
+      if (k > avail) {
+        chunk_next = fresh + (k - avail);
+        chunk_end = fresh + kChunk;
+      } else {
+        chunk_next += k;
+      }
     }
     if (__ballot(phase != P_DONE) == 0) break;
 
-    bool hit = false, ended = false;
-    uint32_t h_gid = 0, h_aux = 0;
-    float h_edep = 0.f, h_depth = 0.f;
-    unsigned long long h_time = 0;
+    // ---- the one Philox block of this trip
+    const bool draw = phase != P_SEARCH && phase != P_DONE;
+    uint4 w = make_uint4(0u, 0u, 0u, 0u);
+    if (draw) {
+      w = philox(A.k0, A.k1, make_uint4(n, ev, A.instance, sid));
+      ++n;
+    }
+    const float4 r = to_unit4(w);
+    c_blocks += count(draw && sid != 0u);
 
-    if (phase == P_PHANTOM) {
-      const float4 r = rng.next();
-      ++c_blocks;
+    bool hit = false, ended = false;
+    float h_edep = 0.f;
+    int h_proc = 0;
+    bool stepped = false, real = false, searched = false, entered = false, trial = false, scattered = false,
+         capped = false, emitted = false;
+
+    if (phase == P_EMIT_DIR) {
+      // block 0 of the event stream: isotropic direction, two source uniforms
+      const float ct = 2.0f * r.x - 1.0f, stt = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
+      sdir = Vec{stt * cos_rev(r.y), stt * sin_rev(r.y), ct};
+      q_u0 = r.z;
+      q_u1 = r.w;
+      src = Vec{S.sx, S.sy, S.sz};
+      if (S.src_kind == 2) sdir = Vec{S.bdx, S.bdy, S.bdz};
+      if (S.src_kind == 1) {
+        phase = P_EMIT_POS;
+      } else {
+        phase = P_EMIT_TIME; // block 1 is not needed
+        n = 2;
+      }
+    } else if (phase == P_EMIT_POS) {
+      // block 1: point in the chosen rod (rod ~ volume, uniform in its disk and length)
+      const float tgt = q_u0 * S.rod_total;
+      int i = 0;
+      while (i < S.n_rods - 1 && S.rod_cum[i] < tgt) ++i;
+      const float *rd = S.rods + 5 * i;
+      const float rr = rd[2] * hw_sqrt(q_u1);
+      src = Vec{rd[0] + rr * cos_rev(r.x), rd[1] + rr * sin_rev(r.x), rd[3] + r.y * (rd[4] - rd[3])};
+      phase = P_EMIT_TIME;
+    } else if (phase == P_EMIT_TIME) {
+      // block 2: event time uniform on [0, T) from the raw 64-bit word
+      t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
+      emitted = true;
+      start_photon(0);
+    } else if (phase == P_PHANTOM) {
       const Lerp lp = lerp_at(e);
       const float mb = lerp1(S.maj_ph, lp);
-      const float s = -logf(r.x) / mb;
+      const float s = neg_ln(r.x) * rcp(mb);
       const Vec xn{x.x + s * d.x, x.y + s * d.y, x.z + s * d.z};
       const int vox = voxel_of(S, xn);
       if (vox < 0) {
-        vertex<TRACE>(A, ev, ph, V_EXIT, 0, -1, -1, -1, 0, 0, 0, rng.n, x, e, 0.f, d);
+        vertex<TRACE>(A, ev, ph, V_EXIT, 0, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         phase = P_SEARCH;
       } else {
         x = xn;
         L += s;
-        ++c_steps;
+        stepped = true;
         if (++steps > kMaxSteps) {
-          ++c_capped;
-          ended = true;
+          capped = ended = true;
         } else {
           const int mat = S.vmat[vox];
           const float rho = S.vden[vox];
@@ -169,54 +256,51 @@ __global__ void __launch_bounds__(256) k_transport(DevScene S, RunArgs A) {
           const float4 mu = make_float4(rho * mm.x, rho * mm.y, rho * mm.z, 0.f);
           const float mut = mu.x + mu.y + mu.z;
           if (r.y * mb < mut) {
-            ++c_real;
+            real = true;
             const int proc = pick_process(mu, mut, r.z);
-            float edep;
-            int tr;
-            const bool alive = interact(rng, proc, e, d, kTwoPi * r.w, S.e_cut, edep, tr);
-            c_trials += tr;
-            c_blocks += tr + (proc == 3);
-            vertex<TRACE>(A, ev, ph, V_STEP, 0, -1, -1, mat, 1, proc, tr, rng.n, x, e, edep, d);
-            if (!alive) {
-              vertex<TRACE>(A, ev, ph, V_DEAD, 0, -1, -1, mat, 0, proc, 0, rng.n, x, 0.f, 0.f, d);
+            if (proc == 1) {
+              vertex<TRACE>(A, ev, ph, V_STEP, 0, -1, -1, mat, 1, 1, 0, n, x, 0.f, e, d);
+              vertex<TRACE>(A, ev, ph, V_DEAD, 0, -1, -1, mat, 0, 1, 0, n, x, 0.f, 0.f, d);
               ended = true;
+            } else {
+              q_u0 = r.w;
+              q_gid = -1;
+              q_mat = mat;
+              q_trials = 0;
+              q_back = P_PHANTOM;
+              phase = proc == 2 ? P_KAHN : P_RAYLEIGH;
             }
           } else {
-            vertex<TRACE>(A, ev, ph, V_STEP, 0, -1, -1, mat, 0, 0, 0, rng.n, x, e, 0.f, d);
+            vertex<TRACE>(A, ev, ph, V_STEP, 0, -1, -1, mat, 0, 0, 0, n, x, e, 0.f, d);
           }
         }
       }
     } else if (phase == P_SEARCH) {
-      ++c_search;
+      searched = true;
       float ti;
       const int p = panel_search(S, x, d, last, ti);
       if (p < 0) {
-        vertex<TRACE>(A, ev, ph, V_ESCAPE, -1, -1, -1, -1, 0, 0, 0, rng.n, x, e, 0.f, d);
+        vertex<TRACE>(A, ev, ph, V_ESCAPE, -1, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         ended = true;
       } else {
         x = Vec{x.x + ti * d.x, x.y + ti * d.y, x.z + ti * d.z};
         L += ti;
-        ++c_entries;
-        if (++steps > kMaxSteps) { // bounds panel-to-panel hops as well
-          ++c_capped;
-          ended = true;
-        }
-        vertex<TRACE>(A, ev, ph, V_ENTER_PANEL, 1, p, -1, -1, 0, 0, 0, rng.n, x, e, 0.f, d);
+        entered = true;
+        vertex<TRACE>(A, ev, ph, V_ENTER_PANEL, 1, p, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         panel = p;
         const float *P = S.pose + 12 * p;
         x = to_local(P, x);
         d = dir_to_local(P, d);
         phase = P_PANEL;
+        if (++steps > kMaxSteps) capped = ended = true; // bounds panel-to-panel hops as well
       }
     } else if (phase == P_PANEL) {
-      const float4 r = rng.next();
-      ++c_blocks;
       const Lerp lp = lerp_at(e);
-      const float mb = lerp1(S.maj_det, lp);
-      const float s = -logf(r.x) / mb;
+      const float mb = lerp1(s_maj, lp);
+      const float s = neg_ln(r.x) * rcp(mb);
       const Vec xn{x.x + s * d.x, x.y + s * d.y, x.z + s * d.z};
       if (!inside_panel(S, xn)) {
-        vertex<TRACE>(A, ev, ph, V_EXIT, 1, panel, -1, -1, 0, 0, 0, rng.n, x, e, 0.f, d);
+        vertex<TRACE>(A, ev, ph, V_EXIT, 1, panel, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         const float *P = S.pose + 12 * panel;
         x = to_global(P, x);
         d = dir_to_global(P, d);
@@ -225,60 +309,103 @@ __global__ void __launch_bounds__(256) k_transport(DevScene S, RunArgs A) {
       } else {
         x = xn;
         L += s;
-        ++c_steps;
+        stepped = true;
         if (++steps > kMaxSteps) {
-          ++c_capped;
-          ended = true;
+          capped = ended = true;
         } else {
           const Loc lc = locate(S, panel, x);
-          const float4 mu = lerp4(S.mu, lc.mat, lp);
+          const float4 mu = lerp4(s_mu, lc.slot, lp);
           const float mut = mu.x + mu.y + mu.z;
           if (r.y * mb < mut) {
-            ++c_real;
+            real = true;
             const int proc = pick_process(mu, mut, r.z);
-            float edep;
-            int tr;
-            const bool alive = interact(rng, proc, e, d, kTwoPi * r.w, S.e_cut, edep, tr);
-            c_trials += tr;
-            c_blocks += tr + (proc == 3);
-            vertex<TRACE>(A, ev, ph, V_STEP, 1, panel, lc.gid, lc.mat, 1, proc, tr, rng.n, x, e, edep, d);
-            if (lc.gid >= 0 && proc != 3) {
-              hit = true;
-              h_gid = (uint32_t)lc.gid;
-              h_edep = edep;
-              h_depth = x.x;
-              h_time = t_event + (unsigned long long)floorf(L / kCmmPerPs + 0.5f);
-              h_aux = (uint32_t)ph | ((uint32_t)proc << 1) | (seq << 8);
-              ++seq;
-            }
-            if (!alive) {
-              vertex<TRACE>(A, ev, ph, V_DEAD, 1, panel, lc.gid, lc.mat, 0, proc, 0, rng.n, x, 0.f, 0.f, d);
+            q_gid = lc.gid;
+            if (proc == 1) {
+              vertex<TRACE>(A, ev, ph, V_STEP, 1, panel, lc.gid, lc.mat, 1, 1, 0, n, x, 0.f, e, d);
+              vertex<TRACE>(A, ev, ph, V_DEAD, 1, panel, lc.gid, lc.mat, 0, 1, 0, n, x, 0.f, 0.f, d);
+              if (lc.gid >= 0) {
+                hit = true;
+                h_edep = e;
+                h_proc = 1;
+              }
               ended = true;
+            } else {
+              q_u0 = r.w;
+              q_mat = lc.mat;
+              q_trials = 0;
+              q_back = P_PANEL;
+              phase = proc == 2 ? P_KAHN : P_RAYLEIGH;
             }
           } else {
-            vertex<TRACE>(A, ev, ph, V_STEP, 1, panel, lc.gid, lc.mat, 0, 0, 0, rng.n, x, e, 0.f, d);
+            vertex<TRACE>(A, ev, ph, V_STEP, 1, panel, lc.gid, lc.mat, 0, 0, 0, n, x, e, 0.f, d);
           }
         }
       }
+    } else if (phase == P_KAHN) {
+      trial = true;
+      ++q_trials;
+      float c, e1;
+      if (kahn_trial(e, r, c, e1)) {
+        scattered = true;
+        rotate(d, c, q_u0);
+        float edep = e - e1;
+        e = e1;
+        const bool alive = e >= S.e_cut;
+        if (!alive) { // below the cutoff: the rest is deposited here
+          edep += e;
+          e = 0.0f;
+        }
+        const int region = q_back == P_PANEL ? 1 : 0;
+        vertex<TRACE>(A, ev, ph, V_STEP, region, region ? panel : -1, q_gid, q_mat, 1, 2, q_trials, n, x, e,
+                      edep, d);
+        if (region && q_gid >= 0) {
+          hit = true;
+          h_edep = edep;
+          h_proc = 2;
+        }
+        if (!alive) {
+          vertex<TRACE>(A, ev, ph, V_DEAD, region, region ? panel : -1, q_gid, q_mat, 0, 2, 0, n, x, 0.f, 0.f,
+                        d);
+          ended = true;
+        } else {
+          phase = q_back;
+        }
+      }
+    } else if (phase == P_RAYLEIGH) {
+      scattered = true;
+      rotate(d, thomson(r.x), q_u0);
+      const int region = q_back == P_PANEL ? 1 : 0;
+      vertex<TRACE>(A, ev, ph, V_STEP, region, region ? panel : -1, q_gid, q_mat, 1, 3, 0, n, x, e, 0.f, d);
+      phase = q_back;
     }
 
-    // hit append: one atomic per wave and loop trip
+    // ---- work counters (scalar)
+    c_events += count(emitted);
+    c_steps += count(stepped);
+    c_real += count(real);
+    c_search += count(searched);
+    c_entries += count(entered);
+    c_trials += count(trial);
+    c_scatter += count(scattered);
+    c_capped += count(capped);
+
+    // ---- stage hits in LDS; write out 64 or more at a time
     const uint64_t hm = __ballot(hit);
     if (hm) {
-      const int leader = __ffsll((unsigned long long)hm) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(A.hit_count, (unsigned long long)__popcll(hm));
-      base = __shfl(base, leader);
       if (hit) {
-        const unsigned long long i = base + (unsigned long long)__popcll(hm & below);
-        if (i < A.capacity) {
-          A.h_event[i] = ev;
-          A.h_gid[i] = h_gid;
-          A.h_edep[i] = h_edep;
-          A.h_depth[i] = h_depth;
-          A.h_time[i] = h_time;
-          A.h_aux[i] = h_aux;
-        }
+        const uint32_t k = staged + (uint32_t)__popcll(hm & below);
+        st.ev[k] = ev;
+        st.gid[k] = (uint32_t)q_gid;
+        st.edep[k] = h_edep;
+        st.depth[k] = x.x;
+        st.time[k] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
+        st.aux[k] = (uint32_t)ph | ((uint32_t)h_proc << 1) | (seq << 8);
+        ++seq;
+      }
+      staged += (uint32_t)__popcll(hm);
+      if (staged >= 64) {
+        flush_stage(A, st, staged, lane);
+        staged = 0;
       }
     }
     if (ended) {
@@ -286,26 +413,30 @@ __global__ void __launch_bounds__(256) k_transport(DevScene S, RunArgs A) {
       else phase = P_FETCH;
     }
   }
+  flush_stage(A, st, staged, lane);
 
-  const uint32_t cnt[8] = {c_events, c_entries, c_steps, c_real, c_trials, c_search, c_blocks, c_capped};
+  const unsigned long long cnt[9] = {c_events, c_entries, c_steps, c_real, c_trials, c_search, c_blocks,
+                                     c_capped, c_scatter};
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t t = wave_sum(cnt[k]);
-    if (lane == 0 && t) atomicAdd(A.stats + k, (unsigned long long)t);
+    for (int k = 0; k < 9; ++k)
+      if (cnt[k]) atomicAdd(A.stats + k, cnt[k]);
   }
 }
 
 void launch_transport(const DevScene &S, const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st) {
-  const uint64_t need = (A.n + L.block - 1) / L.block;
+  const uint64_t need = (A.n + kBlock - 1) / kBlock;
   uint64_t grid = (uint64_t)n_cu * L.blocks_per_cu;
   if (need < grid) grid = need;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(L.block), 0, st, S, A);
+  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(kBlock), transport_lds_bytes(S.n_det_slots),
+                     st, S, A);
 }
 
 void launch_trace(const DevScene &S, const RunArgs &A, hipStream_t st) {
-  const unsigned grid = (A.n + 255) / 256;
-  hipLaunchKernelGGL(k_transport<true>, dim3(grid ? grid : 1), dim3(256), 0, st, S, A);
+  const unsigned grid = (A.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_transport<true>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(S.n_det_slots),
+                     st, S, A);
 }
 
 // ---------------------------------------------------------------------------

@@ -25,7 +25,8 @@ PLACE_REPEAT, PLACE_EXPLICIT = 0, 1
 SRC_POINT, SRC_CYLINDERS, SRC_BEAM = 0, 1, 2
 V_STEP, V_ENTER_PANEL, V_EXIT, V_ESCAPE, V_DEAD, V_ENTER_PHANTOM, V_EMIT = range(7)
 
-STAT_NAMES = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks", "capped")
+STAT_NAMES = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks", "capped",
+              "scatters")
 
 
 class GpetError(RuntimeError):
