@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=10_000_000, help="events per design and position")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--search-batch", type=int, default=48)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -119,6 +122,7 @@ def main():
         c = Context(0)
         c.set_scene(G.small_animal_scene(d, (0.0, 0.0, 0.0), n_events=n))
         c.enable_timing(True)
+        c.set_launch(args.blocks_per_cu, args.search_batch, args.schedule)
         hits = c.alloc_hits(int(3.2 * n))
         singles = c.alloc_singles(int(2.2 * n))
         coinc = (c._empty(n, torch.int32), c._empty(n, torch.int32))

@@ -292,3 +292,29 @@ def black_ring_scene(n_panels, radius, width, length, depth, n_events=1_000_000,
     lay = [layer(0.0, depth, 1, 1, width, length, width, length)]
     scan = scanner(n_panels, radius, depth, 1, 1, width, length, 0.0, 0.0, lay)
     return scene(mats, physics(rayleigh=False), scan, point_source((0, 0, 0), n_events))
+
+
+def tilted_ring_poses(n_panels=8, radius=40.0, tilt_deg=12.0) -> np.ndarray:
+    """Explicit (non-repetition) panel poses: a ring whose panels are each tilted
+    by ``tilt_deg`` about their own tangential axis, so no axis is global z.
+    Rows: front-face centre, depth axis, t axis, a axis."""
+    out = []
+    tl = math.radians(tilt_deg)
+    for k in range(n_panels):
+        ph = 2 * math.pi * k / n_panels
+        c, s = math.cos(ph), math.sin(ph)
+        radial = np.array([c, s, 0.0])
+        tang = np.array([-s, c, 0.0])
+        z = np.array([0.0, 0.0, 1.0])
+        depth = math.cos(tl) * radial + math.sin(tl) * z
+        axial = -math.sin(tl) * radial + math.cos(tl) * z
+        out.append(np.concatenate([radius * radial, depth, tang, axial]))
+    return np.asarray(out)
+
+
+def tilted_ring_scene(n_events=100_000) -> dict:
+    sc = ring8_scene(n_events=n_events)
+    g = sc["scanner"]
+    sc["scanner"] = scanner(8, 40.0, g["depth"], 1, 1, 12.8, 12.8, 0.0, 0.0, g["layers"],
+                            poses=tilted_ring_poses())
+    return sc

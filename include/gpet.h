@@ -215,6 +215,7 @@ typedef struct {
 typedef struct {
   uint64_t events, panel_entries, steps, real_interactions, kahn_trials, panel_searches,
       rng_blocks, capped, scatters;
+  uint64_t wave_trips; /* loop trips summed over wavefronts (64 lanes each) */
 } gpet_stats;
 
 /* Transport events [first_event, first_event + n_events) with key `seed`.
@@ -275,6 +276,14 @@ typedef struct {
 gpet_status gpet_digitize(gpet_ctx *ctx, const gpet_hits *hits, const gpet_digitizer *params,
                           gpet_singles *singles, gpet_coincidences *coincidences,
                           gpet_tallies *tallies /* NULL: none */);
+
+/* Launch shape of the transport kernel: blocks of 256 lanes per compute unit
+ * (0 = as many as fit); the scheduling of lane actions within a wavefront
+ * (0: every pending action runs each loop trip, with panel searches held until
+ * `search_batch` lanes (1..64) need one; 1: only the action held by the most
+ * lanes runs).  Results do not depend on the shape (every random number is
+ * keyed by event id). */
+gpet_status gpet_ctx_set_launch(gpet_ctx *ctx, int32_t blocks_per_cu, int32_t search_batch, int32_t schedule);
 
 /* Kernel timing: when enabled, HIP events bracket the transport kernel and
  * the digitizer on the context's stream; gpet_timings returns the last

@@ -186,20 +186,180 @@ static bool radix_sort(SortBufs &b, size_t n, int bits, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Bucket sort of (u64 key, u32 value) for keys spread evenly over their range
+// (event ids, event times): count per bucket (key >> shift), scan, scatter by
+// bucket, then sort each bucket (about 256 items) in LDS with a bitonic network
+// ordered by (key, value).  The scatter order inside a bucket depends on
+// atomics; the local sort by (key, value) makes the result deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kLocalSort = 1024; // largest bucket sorted in LDS
+
+// lanes of the wave whose value equals this lane's (one ballot per distinct value)
+__device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
+  uint64_t left = __ballot(valid), mine = 0;
+  while (left) {
+    const int leader = __ffsll((unsigned long long)left) - 1;
+    const uint32_t lv = __shfl(v, leader);
+    const uint64_t m = __ballot(valid && v == lv) & left;
+    if (valid && v == lv) mine = m;
+    left &= ~m;
+  }
+  return mine;
+}
+
+// keys whose bucket lies at or past nb are skipped and flagged (bit 1 of *flag)
+template <bool AGG>
+__global__ void k_bucket_count(const unsigned long long *key, size_t n, int shift, size_t nb, uint32_t *count,
+                               uint32_t *flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned long long kb = i < n ? key[i] >> shift : 0ull;
+  if (i < n && kb >= nb) atomicOr(flag, 2u);
+  const bool valid = i < n && kb < nb;
+  const uint32_t b = valid ? (uint32_t)kb : 0u;
+  if constexpr (AGG) {
+    const uint64_t peers = equal_peers(b, valid);
+    if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[b], (uint32_t)__popcll(peers));
+  } else {
+    if (valid) atomicAdd(&count[b], 1u);
+  }
+}
+
+// cursor holds bucket starts on entry and bucket ends on exit
+template <bool AGG>
+__global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *vin, size_t n, int shift, size_t nb,
+                                 uint32_t *cursor, unsigned long long *kout, uint32_t *vout) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned long long k = i < n ? kin[i] : 0ull;
+  const bool valid = i < n && (k >> shift) < nb;
+  const uint32_t b = valid ? (uint32_t)(k >> shift) : 0u;
+  uint32_t pos = 0;
+  if constexpr (AGG) {
+    const uint64_t below = __lanemask_lt();
+    const uint64_t peers = equal_peers(b, valid);
+    const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : 0;
+    uint32_t base = 0;
+    if (valid && (peers & below) == 0) base = atomicAdd(&cursor[b], (uint32_t)__popcll(peers));
+    base = __shfl(base, leader);
+    pos = base + (uint32_t)__popcll(peers & below);
+  } else {
+    if (valid) pos = atomicAdd(&cursor[b], 1u);
+  }
+  if (valid && pos < n) {
+    kout[pos] = k;
+    vout[pos] = vin[i];
+  }
+}
+
+__device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, unsigned long long kb, uint32_t vb) {
+  return ka < kb || (ka == kb && va < vb);
+}
+
+// one block per bucket; `end` holds bucket ends (the scattered cursor)
+__global__ void __launch_bounds__(256) k_bucket_local_sort(unsigned long long *key, uint32_t *val,
+                                                           const uint32_t *end, uint32_t *overflow) {
+  __shared__ unsigned long long sk[kLocalSort];
+  __shared__ uint32_t sv[kLocalSort];
+  const uint32_t b = blockIdx.x;
+  const uint32_t lo = b ? end[b - 1] : 0u, hi = end[b];
+  const uint32_t size = hi - lo;
+  if (size <= 1) return;
+  if (size > (uint32_t)kLocalSort) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
+  uint32_t P = 2;
+  while (P < size) P <<= 1;
+  for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
+    sk[t] = t < size ? key[lo + t] : ~0ull;
+    sv[t] = t < size ? val[lo + t] : ~0u;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
+        const uint32_t u = t ^ j;
+        if (u > t) {
+          const bool up = (t & k) == 0;
+          const bool swap = up ? pair_less(sk[u], sv[u], sk[t], sv[t]) : pair_less(sk[t], sv[t], sk[u], sv[u]);
+          if (swap) {
+            const unsigned long long tk = sk[t];
+            sk[t] = sk[u];
+            sk[u] = tk;
+            const uint32_t tv = sv[t];
+            sv[t] = sv[u];
+            sv[u] = tv;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) {
+    key[lo + t] = sk[t];
+    val[lo + t] = sv[t];
+  }
+}
+
+static int log2_ceil(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x && b < 63) ++b;
+  return b;
+}
+
+struct BucketBufs {
+  uint32_t *count;        // bucket counters (>= max_buckets words)
+  size_t max_buckets;
+  uint32_t *overflow;     // device flag
+  uint32_t *pinned_flag;  // host mirror
+};
+
+// Sorts (b.k0, b.v0) into (b.k1, b.v1) by (key, value) for keys <= key_max.
+// Returns 0 when sorted, bit 0 when a bucket was too large for LDS, bit 1 when
+// a key exceeded key_max (then (k1, v1) are not sorted).
+template <bool AGG>
+static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, unsigned long long key_max, hipStream_t st,
+                            uint32_t *scan_tmp) {
+  const int key_bits = key_max ? 64 - __builtin_clzll(key_max) : 1;
+  const int want = log2_ceil(n / 256 + 1);
+  int shift = key_bits > want ? key_bits - want : 0;
+  size_t nb = (size_t)(key_max >> shift) + 1;
+  while (nb > bb.max_buckets) {
+    ++shift;
+    nb = (size_t)(key_max >> shift) + 1;
+  }
+  launch_fill_u32(bb.count, 0u, nb, st);
+  launch_fill_u32(bb.overflow, 0u, 1, st);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_bucket_count<AGG>, dim3(g), dim3(256), 0, st, b.k0, n, shift, nb, bb.count, bb.overflow);
+  exclusive_scan(bb.count, nb, scan_tmp, st);
+  hipLaunchKernelGGL(k_bucket_scatter<AGG>, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, shift, nb, bb.count, b.k1,
+                     b.v1);
+  hipLaunchKernelGGL(k_bucket_local_sort, dim3((unsigned)nb), dim3(256), 0, st, b.k1, b.v1, bb.count, bb.overflow);
+  (void)hipMemcpyAsync(bb.pinned_flag, bb.overflow, 4, hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  return *bb.pinned_flag;
+}
+
+// ---------------------------------------------------------------------------
 // digitizer stages
 // ---------------------------------------------------------------------------
-__global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, uint32_t first, int gid_bits,
-                           unsigned long long *key, uint32_t *val) {
+// key = (event - first) | gid | photon | index of the hit within its photon
+// (7 bits, saturated): unique per hit, so the sorted order is fixed
+__global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux, uint32_t first,
+                           int gid_bits, unsigned long long *key, uint32_t *val) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  key[i] = ((unsigned long long)(ev[i] - first) << gid_bits) | gid[i];
+  const uint32_t a = aux[i];
+  const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
+  key[i] = ((((unsigned long long)(ev[i] - first) << gid_bits) | gid[i]) << 8) | low;
   val[i] = (uint32_t)i;
 }
 
+// first hit of each (event, crystal) run
 __global__ void k_heads(size_t n, const unsigned long long *key, uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1u : 0u;
+  flag[i] = (i == 0 || (key[i] >> 8) != (key[i - 1] >> 8)) ? 1u : 0u;
 }
 
 __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t *perm, const uint32_t *seg,
@@ -208,7 +368,8 @@ __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t 
                         float *s_depth, unsigned long long *s_time, uint64_t cap) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (i > 0 && key[i] == key[i - 1]) return;
+  const unsigned long long run = key[i] >> 8;
+  if (i > 0 && (key[i - 1] >> 8) == run) return;
   unsigned long long se = 0, sd = 0, tm = ~0ull;
   size_t j = i;
   do {
@@ -218,7 +379,7 @@ __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t 
     sd += (unsigned long long)((e * depth[h]) * 4294967296.0f);
     tm = min(tm, time[h]);
     ++j;
-  } while (j < n && key[j] == key[i]);
+  } while (j < n && (key[j] >> 8) == run);
   const uint32_t s = seg[i];
   if (s >= cap) return;
   const uint32_t h = perm[i];
@@ -364,9 +525,10 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
 
   // scratch: 2 key + 2 value arrays, 2 flag arrays, radix histogram, scan temp, time maximum
   const size_t tiles = (n + kSortTile - 1) / kSortTile;
-  const size_t scan_words = scan_scratch_words(std::max<size_t>(256 * tiles, n));
+  const size_t max_buckets = n / 128 + 1024;
+  const size_t scan_words = scan_scratch_words(std::max<size_t>(std::max<size_t>(256 * tiles, n), max_buckets));
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 4 + align_up(256 * tiles * 4) +
-                      align_up(scan_words * 4) + 256;
+                      align_up(scan_words * 4) + align_up(max_buckets * 4) + 512;
   if (scr.bytes < need) {
     if (scr.buf) (void)hipFree(scr.buf);
     scr.buf = nullptr;
@@ -397,7 +559,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   sb.hist = (uint32_t *)take(256 * tiles * 4);
   sb.scan_tmp = (uint32_t *)take(scan_words * 4);
   unsigned long long *tmax_dev = (unsigned long long *)take(8);
+  BucketBufs bb;
+  bb.count = (uint32_t *)take(max_buckets * 4);
+  bb.max_buckets = max_buckets;
+  bb.overflow = (uint32_t *)take(8);
   uint32_t *rb = (uint32_t *)scr.pinned; // pinned readback words
+  bb.pinned_flag = rb + 12;
   auto sync = [&](const char *what) {
     if (hipStreamSynchronize(st) != hipSuccess) {
       err = std::string("digitize: stream error ") + what;
@@ -407,11 +574,23 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   };
 
   // 1. sort hits by (event, gid)
-  hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.first_event,
-                     D.gid_bits, sb.k0, sb.v0);
-  const bool f1 = radix_sort(sb, n, D.event_bits + D.gid_bits, st);
-  const unsigned long long *hk = f1 ? sb.k1 : sb.k0;
-  const uint32_t *hp = f1 ? sb.v1 : sb.v0;
+  hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux,
+                     D.first_event, D.gid_bits, sb.k0, sb.v0);
+  const int hit_bits = D.event_bits + D.gid_bits + 8;
+  const unsigned long long hit_max =
+      ((unsigned long long)(D.n_events - 1) << (D.gid_bits + 8)) | ((1ull << (D.gid_bits + 8)) - 1);
+  const unsigned long long *hk = sb.k1;
+  const uint32_t *hp = sb.v1;
+  const uint32_t hflag = bucket_sort<true>(sb, bb, n, hit_max, st, sb.scan_tmp);
+  if (hflag & 2u) {
+    err = "digitize: a hit's event id lies outside [first_event, first_event + n_events)";
+    return GPET_ERR_ARG;
+  }
+  if (hflag) { // a bucket overflowed LDS
+    const bool f1 = radix_sort(sb, n, hit_bits, st);
+    hk = f1 ? sb.k1 : sb.k0;
+    hp = f1 ? sb.v1 : sb.v0;
+  }
   // 2. adder: single index of each run = exclusive scan of run heads
   hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
   (void)hipMemcpyAsync(rb + 0, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
@@ -447,9 +626,16 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   int time_bits = 0;
   while (time_bits < 64 && (tmax >> time_bits) != 0) ++time_bits;
   if (nw == 0) return GPET_OK;
-  const bool f2 = radix_sort(sb, nw, time_bits, st);
-  const unsigned long long *tk = f2 ? sb.k1 : sb.k0;
-  const uint32_t *ti = f2 ? sb.v1 : sb.v0;
+  const unsigned long long *tk = sb.k1;
+  const uint32_t *ti = sb.v1;
+  if (nw > 1 && bucket_sort<false>(sb, bb, nw, tmax, st, sb.scan_tmp) != 0u) {
+    const bool f2 = radix_sort(sb, nw, time_bits, st);
+    tk = f2 ? sb.k1 : sb.k0;
+    ti = f2 ? sb.v1 : sb.v0;
+  } else if (nw == 1) {
+    tk = sb.k0;
+    ti = sb.v0;
+  }
   // 5. coincidences: count per cluster, scan, write
   hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid,
                      (uint32_t)D.crystals_per_panel, D.window_ps, flag);

@@ -314,6 +314,11 @@ gpet_status gpet_geometry_create(gpet_ctx *c, const gpet_scanner *g, gpet_geomet
 
   DevScene &S = c->scene;
   S.n_panels = g->n_panels;
+  S.ring = 1;
+  for (int k = 0; k < g->n_panels; ++k) {
+    const float *P = &pose[(size_t)k * 12];
+    if (P[2] != 0.0f || P[5] != 0.0f || P[6] != 0.0f || P[7] != 0.0f || P[8] != 1.0f || P[11] != pose[11]) S.ring = 0;
+  }
   S.depth = (float)g->depth_mm;
   S.half_w = (float)(0.5 * g->width_mm);
   S.half_l = (float)(0.5 * g->length_mm);
@@ -493,6 +498,8 @@ static RunArgs run_args(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t seed, 
   A.work = (uint32_t *)(c->d_ctrl + 0);
   A.hit_count = c->d_ctrl + 1;
   A.stats = c->d_ctrl + 2;
+  A.search_batch = c->shape.search_batch;
+  A.schedule = c->shape.schedule;
   return A;
 }
 
@@ -513,20 +520,20 @@ gpet_status gpet_transport(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t see
   A.h_time = (unsigned long long *)h->time_ps;
   A.h_aux = h->aux;
   A.capacity = h->capacity;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 22, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 24, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
   if (n) launch_transport(c->scene, A, c->shape, c->n_cu, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
   s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
-  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 11 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 12 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
   if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "transport: kernel");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (c->timing) (void)hipEventElapsedTime(&c->last_ms[0], c->ev[0], c->ev[1]);
   if (stats) {
     uint64_t *o = (uint64_t *)stats;
-    for (int k = 0; k < 9; ++k) o[k] = c->h_ctrl[2 + k];
+    for (int k = 0; k < 10; ++k) o[k] = c->h_ctrl[2 + k];
   }
   if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "transport: hit capacity too small");
   return GPET_OK;
@@ -548,10 +555,12 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
   D.n_hits = h->count;
   D.h_event = h->event;
   D.h_gid = h->gid;
+  D.h_aux = h->aux;
   D.h_edep = h->edep_kev;
   D.h_depth = h->depth_mm;
   D.h_time = (const unsigned long long *)h->time_ps;
   D.first_event = (uint32_t)p->first_event;
+  D.n_events = p->n_events;
   D.event_bits = bits_for(p->n_events - 1);
   D.gid_bits = bits_for((uint64_t)c->info.n_crystals - 1);
   D.crystals_per_panel = c->info.crystals_per_panel;
@@ -576,6 +585,17 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
     (void)hipEventElapsedTime(&c->last_ms[1], c->ev[2], c->ev[3]);
   }
   return hip_check(c, hipGetLastError(), "digitize: launch");
+}
+
+gpet_status gpet_ctx_set_launch(gpet_ctx *c, int32_t blocks_per_cu, int32_t search_batch, int32_t schedule) {
+  if (!c) return GPET_ERR_ARG;
+  if (blocks_per_cu < 0 || blocks_per_cu > 64 || search_batch < 1 || search_batch > 64 || schedule < 0 ||
+      schedule > 1)
+    return fail(c, GPET_ERR_ARG, "launch: blocks_per_cu in 0..64, search_batch in 1..64, schedule 0 or 1");
+  c->shape.blocks_per_cu = blocks_per_cu;
+  c->shape.search_batch = (uint32_t)search_batch;
+  c->shape.schedule = (uint32_t)schedule;
+  return GPET_OK;
 }
 
 gpet_status gpet_ctx_enable_timing(gpet_ctx *c, int enable) {
@@ -665,7 +685,7 @@ gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, u
   A.vflt = vflt;
   A.vcount = counts;
   A.max_vertices = maxv;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 22, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 24, c->stream);
   launch_fill_u32((uint32_t *)counts, 0u, 2 * (size_t)n, c->stream);
   if (n) launch_trace(c->scene, A, c->stream);
   s = hip_check(c, hipGetLastError(), "trace: launch");

@@ -49,6 +49,7 @@ struct LayerD {
 struct DevScene {
   // panels
   int n_panels;
+  int ring; // all panels have axial axis +z and one common axial offset
   float depth, half_w, half_l;
   // n_panels x 12: rows of the local axes (depth, t, a) in global coordinates,
   // then the front-face centre projected on them; local = R x - R o
@@ -219,6 +220,33 @@ __device__ __forceinline__ int panel_search(const DevScene &S, Vec x, Vec d, int
   }
   t_in = bt;
   return best;
+}
+
+// Panel search for rings: every panel's axial axis is +z and all panels share
+// one axial range, so the axial slab is computed once for the ray and the
+// depth/tangential axes need only 2-D dot products (pose rows have zero z).
+__device__ __forceinline__ int panel_search_ring(const DevScene &S, Vec x, Vec d, int exclude, float &t_in) {
+  float tn_a = -INFINITY, tf_a = INFINITY;
+  slab_axis(x.z - S.pose[11], d.z, -S.half_l, S.half_l, tn_a, tf_a);
+  int best = -1;
+  float bt = INFINITY;
+  for (int p = 0; p < S.n_panels; ++p) {
+    const float *P = S.pose + 12 * p;
+    float tn = tn_a, tf = tf_a;
+    slab_axis(x.x * P[0] + x.y * P[1] - P[9], d.x * P[0] + d.y * P[1], 0.0f, S.depth, tn, tf);
+    slab_axis(x.x * P[3] + x.y * P[4] - P[10], d.x * P[3] + d.y * P[4], -S.half_w, S.half_w, tn, tf);
+    const float te = fmaxf(tn, 0.0f);
+    if (tn <= tf && tf > 0.0f && p != exclude && te < bt) {
+      bt = te;
+      best = p;
+    }
+  }
+  t_in = bt;
+  return best;
+}
+
+__device__ __forceinline__ int find_panel(const DevScene &S, Vec x, Vec d, int exclude, float &t_in) {
+  return S.ring ? panel_search_ring(S, x, d, exclude, t_in) : panel_search(S, x, d, exclude, t_in);
 }
 
 struct Loc {

@@ -11,26 +11,39 @@
 
 namespace gpet {
 
-// Device outputs and controls of one transport launch.
+// Device outputs and controls of one transport launch over a table of
+// instances (one instance for a plain run).  Work is handed out in chunks of
+// `chunk` consecutive events of one instance; chunk c of the launch belongs to
+// the instance i with chunk_prefix[i] <= c < chunk_prefix[i + 1].
 struct RunArgs {
-  uint32_t first, n; // event range [first, first + n)
-  uint32_t k0, k1, instance;
-  uint32_t *h_event, *h_gid, *h_aux;
+  const DevScene *scenes;       // n_inst scenes (device)
+  const uint32_t *chunk_prefix; // n_inst + 1 (device)
+  const uint32_t *inst_first;   // first event id of each instance's range (device)
+  const uint32_t *inst_count;   // events of each instance (device)
+  const uint32_t *inst_id;      // instance id used in random-number counters (device)
+  uint32_t n_inst, chunk, total_chunks;
+  uint32_t first, n; // plain runs: event range [first, first + n) (trace indexing)
+  uint32_t k0, k1;
+  uint32_t *h_event, *h_gid, *h_aux, *h_inst;
   float *h_edep, *h_depth;
   unsigned long long *h_time;
   unsigned long long capacity;
   unsigned long long *hit_count; // device
   uint32_t *work;                // device event-fetch counter
-  unsigned long long *stats;     // device, 9 counters (gpet_stats order)
+  unsigned long long *stats;     // device, 10 counters (gpet_stats order)
   // trace mode
   int32_t *vint;
   float *vflt;
   int32_t *vcount;
   int max_vertices;
+  uint32_t search_batch; // lanes of a wave that must wait for a panel search before it runs
+  uint32_t schedule;     // 0: all phases each trip; 1: the most-populated phase only
 };
 
 struct LaunchShape {
-  int blocks_per_cu = 8; // resident-or-queued blocks of 256 lanes per CU
+  int blocks_per_cu = 0;      // blocks of 256 lanes per CU; 0 = the occupancy limit
+  uint32_t search_batch = 48; // see RunArgs::search_batch
+  uint32_t schedule = 0;      // see RunArgs::schedule
 };
 size_t transport_lds_bytes(int det_slots);
 
@@ -55,10 +68,11 @@ struct DigitizeScratch {
 };
 struct DigitizeArgs {
   uint64_t n_hits;
-  const uint32_t *h_event, *h_gid;
+  const uint32_t *h_event, *h_gid, *h_aux;
   const float *h_edep, *h_depth;
   const unsigned long long *h_time;
   uint32_t first_event;
+  uint64_t n_events;
   int gid_bits, event_bits;
   int crystals_per_panel, n_crystals;
   float fwhm_511, e_lo, e_hi;
@@ -100,7 +114,7 @@ struct gpet_ctx {
   // source
   bool have_source = false;
   float *d_rods = nullptr, *d_rod_cum = nullptr;
-  // device controls: [0] work (u32 x2), [1] hit count, [2..10] stats
+  // device controls: [0] work (u32 x2), [1] hit count, [2..11] stats
   unsigned long long *d_ctrl = nullptr;
   unsigned long long *h_ctrl = nullptr; // pinned mirror of d_ctrl
   gpet::DevScene scene{};

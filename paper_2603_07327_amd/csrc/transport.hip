@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
   // wave-uniform bookkeeping
   uint32_t chunk_next = 0, chunk_end = 0, staged = 0;
   unsigned long long c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0,
-                     c_blocks = 0, c_capped = 0, c_scatter = 0;
+                     c_blocks = 0, c_capped = 0, c_scatter = 0, c_trips = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
   auto start_photon = [&](int which) {
@@ -189,9 +189,36 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
       }
     }
     if (__ballot(phase != P_DONE) == 0) break;
+    ++c_trips;
+
+    // ---- which lanes act this trip
+    bool run;
+    if (A.schedule == 0) {
+      // every phase runs; panel searches run in batches: lanes that need one
+      // wait until at least `search_batch` lanes of the wave do, or nothing
+      // else can run
+      const uint64_t sm = __ballot(phase == P_SEARCH);
+      const uint64_t om = __ballot(phase != P_SEARCH && phase != P_DONE);
+      const bool search_now = sm && ((uint32_t)__popcll(sm) >= A.search_batch || om == 0);
+      run = phase != P_DONE && (phase != P_SEARCH || search_now);
+    } else {
+      // only the phase held by the most lanes runs (ties to the later phase),
+      // so each phase body executes with as many lanes as possible
+      int best = P_EMIT_DIR;
+      uint32_t best_n = 0;
+#pragma unroll
+      for (int q = P_EMIT_DIR; q <= P_RAYLEIGH; ++q) {
+        const uint32_t nq = (uint32_t)__popcll(__ballot(phase == q));
+        if (nq >= best_n) {
+          best_n = nq;
+          best = q;
+        }
+      }
+      run = phase == best;
+    }
 
     // ---- the one Philox block of this trip
-    const bool draw = phase != P_SEARCH && phase != P_DONE;
+    const bool draw = run && phase != P_SEARCH;
     uint4 w = make_uint4(0u, 0u, 0u, 0u);
     if (draw) {
       w = philox(A.k0, A.k1, make_uint4(n, ev, A.instance, sid));
@@ -206,7 +233,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
     bool stepped = false, real = false, searched = false, entered = false, trial = false, scattered = false,
          capped = false, emitted = false;
 
-    if (phase == P_EMIT_DIR) {
+    if (!run) {
+      // waits for its phase to be scheduled
+    } else if (phase == P_EMIT_DIR) {
       // block 0 of the event stream: isotropic direction, two source uniforms
       const float ct = 2.0f * r.x - 1.0f, stt = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
       sdir = Vec{stt * cos_rev(r.y), stt * sin_rev(r.y), ct};
@@ -278,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
     } else if (phase == P_SEARCH) {
       searched = true;
       float ti;
-      const int p = panel_search(S, x, d, last, ti);
+      const int p = find_panel(S, x, d, last, ti);
       if (p < 0) {
         vertex<TRACE>(A, ev, ph, V_ESCAPE, -1, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         ended = true;
@@ -415,22 +444,31 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
   }
   flush_stage(A, st, staged, lane);
 
-  const unsigned long long cnt[9] = {c_events, c_entries, c_steps, c_real, c_trials, c_search, c_blocks,
-                                     c_capped, c_scatter};
+  const unsigned long long cnt[10] = {c_events, c_entries, c_steps, c_real, c_trials, c_search, c_blocks,
+                                      c_capped, c_scatter, c_trips};
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
+    for (int k = 0; k < 10; ++k)
       if (cnt[k]) atomicAdd(A.stats + k, cnt[k]);
   }
 }
 
 void launch_transport(const DevScene &S, const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st) {
+  // one resident wave set: as many blocks per CU as the kernel's registers and
+  // LDS allow (unless the shape asks for a given number)
+  const size_t lds = transport_lds_bytes(S.n_det_slots);
+  int per_cu = L.blocks_per_cu;
+  if (per_cu <= 0) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transport<false>, kBlock, lds) != hipSuccess || occ < 1)
+      occ = 4;
+    per_cu = occ;
+  }
   const uint64_t need = (A.n + kBlock - 1) / kBlock;
-  uint64_t grid = (uint64_t)n_cu * L.blocks_per_cu;
+  uint64_t grid = (uint64_t)n_cu * per_cu;
   if (need < grid) grid = need;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(kBlock), transport_lds_bytes(S.n_det_slots),
-                     st, S, A);
+  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(kBlock), lds, st, S, A);
 }
 
 void launch_trace(const DevScene &S, const RunArgs &A, hipStream_t st) {
@@ -494,7 +532,7 @@ __global__ void k_ray_locate(DevScene S, uint32_t n, const float *o, const float
   if (r >= n) return;
   const Vec ro{o[3 * r], o[3 * r + 1], o[3 * r + 2]}, rd{d[3 * r], d[3 * r + 1], d[3 * r + 2]};
   float ti;
-  const int p = panel_search(S, ro, rd, -1, ti);
+  const int p = find_panel(S, ro, rd, -1, ti);
   t_in[r] = p >= 0 ? ti : -1.0f;
   for (int k = 0; k < ns; ++k) {
     int32_t *q = ids6 + 6 * ((size_t)r * ns + k);

@@ -26,7 +26,7 @@ SRC_POINT, SRC_CYLINDERS, SRC_BEAM = 0, 1, 2
 V_STEP, V_ENTER_PANEL, V_EXIT, V_ESCAPE, V_DEAD, V_ENTER_PHANTOM, V_EMIT = range(7)
 
 STAT_NAMES = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks", "capped",
-              "scatters")
+              "scatters", "wave_trips")
 
 
 class GpetError(RuntimeError):
@@ -109,7 +109,8 @@ class Tallies(C.Structure):
 EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_set_stream", "gpet_materials_set",
            "gpet_geometry_create", "gpet_phantom_set", "gpet_source_set", "gpet_transport", "gpet_digitize",
            "gpet_philox", "gpet_tables_get", "gpet_locate", "gpet_ray_locate", "gpet_sample_compton",
-           "gpet_sample_rayleigh", "gpet_trace", "gpet_ctx_enable_timing", "gpet_timings")
+           "gpet_sample_rayleigh", "gpet_trace", "gpet_ctx_enable_timing", "gpet_timings",
+           "gpet_ctx_set_launch")
 
 _lib = None
 
@@ -144,6 +145,7 @@ def load_library(path: str = LIB_PATH):
     L.gpet_trace.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int32, vp, vp, vp]
     L.gpet_ctx_enable_timing.argtypes = [vp, C.c_int]
     L.gpet_timings.argtypes = [vp, P(C.c_float)]
+    L.gpet_ctx_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     for name in EXPORTS:
         if name not in ("gpet_ctx_destroy", "gpet_last_error"):
             getattr(L, name).restype = C.c_int32
@@ -229,6 +231,9 @@ class Context:
 
     def _empty(self, n, dtype):
         return self.torch.empty(max(int(n), 1), dtype=dtype, device=self.dev)
+
+    def set_launch(self, blocks_per_cu=0, search_batch=48, schedule=0):
+        self._check(self.L.gpet_ctx_set_launch(self.h, blocks_per_cu, search_batch, schedule))
 
     def enable_timing(self, on=True):
         self._check(self.L.gpet_ctx_enable_timing(self.h, 1 if on else 0))

@@ -100,9 +100,12 @@ def test_locate_bit_exact_off_boundaries(ctx, oracle_mod, design):
     assert np.array_equal(ids_g[far], ids_o[far])
 
 
-@pytest.mark.parametrize("case", ["ring8", "C"])
+@pytest.mark.parametrize("case", ["ring8", "C", "tilted"])
 def test_fixed_rays_bit_exact(ctx, oracle_mod, case):
-    sc = G.ring8_scene(n_events=10) if case == "ring8" else G.small_animal_scene("C", n_events=10)
+    """Panel search + locate along fixed rays; "tilted" uses explicit poses that
+    are not a ring about z (the general search path)."""
+    sc = {"ring8": lambda: G.ring8_scene(n_events=10), "C": lambda: G.small_animal_scene("C", n_events=10),
+          "tilted": lambda: G.tilted_ring_scene(n_events=10)}[case]()
     o = _both(ctx, oracle_mod, sc)
     rng = np.random.default_rng(11)
     n = 20000
@@ -123,10 +126,12 @@ def test_fixed_rays_bit_exact(ctx, oracle_mod, case):
 # ---------------------------------------------------------------------------
 # transport
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom"])
+@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom", "tilted"])
 def test_matched_histories(ctx, oracle_mod, case):
     if case == "ring8":
         sc, n = G.ring8_scene(n_events=5000), 5000
+    elif case == "tilted":
+        sc, n = G.tilted_ring_scene(n_events=5000), 5000
     elif case == "C":
         sc, n = G.small_animal_scene("C", n_events=5000), 5000
     else:
@@ -184,6 +189,73 @@ def test_digitizer_on_identical_hits(ctx, oracle_mod):
     ref = set(map(tuple, co.tolist()))
     assert len(got ^ ref) <= 4 * int(edge.sum())
     assert len(ref) > 1000
+
+
+def _hitlist(ctx, ev, gid, edep, time_ps, first, n_events):
+    import torch
+    from paper_2603_07327_amd.gpet import HitList
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(ctx.dev)  # noqa: E731
+    n = len(ev)
+    return HitList(t(np.asarray(ev, np.uint32).view(np.int32), np.int32), t(np.asarray(gid, np.uint32).view(np.int32), np.int32),
+                   t(edep, np.float32), t(np.zeros(n), np.float32), t(np.asarray(time_ps, np.int64), np.int64),
+                   t(np.zeros(n, np.int32), np.int32), n, first, n_events)
+
+
+def _oracle_hits(oracle_mod, ev, gid, edep, time_ps):
+    h = np.zeros(len(ev), dtype=np.dtype(oracle_mod.Hit))
+    h["event"], h["gid"], h["edep"], h["time_ps"] = ev, gid, np.float32(edep), time_ps
+    return h
+
+
+@pytest.mark.parametrize("case", ["same_time", "one_event", "random"])
+def test_digitizer_crafted_against_oracle(ctx, oracle_mod, case):
+    """Inputs that push the bucket sort into its fallback (a bucket larger than
+    LDS holds) and a plain random case; singles and coincidences element-wise."""
+    sc = G.small_animal_scene("C", n_events=10)
+    o = _both(ctx, oracle_mod, sc)
+    rng = np.random.default_rng(3)
+    nc = o.n_crystals
+    if case == "same_time":
+        n = 3000
+        ev = np.arange(n)
+        gid = rng.integers(0, nc, n)
+        t = np.full(n, 10**9)
+        t[::7] += rng.integers(0, 5000, len(t[::7]))
+    elif case == "one_event":
+        n = 3000
+        ev = np.full(n, 5)
+        gid = rng.permutation(nc)[:n]
+        t = 10**9 + rng.integers(0, 20000, n)
+    else:
+        n = 50_000
+        ev = np.sort(rng.integers(0, 40_000, n))
+        gid = rng.integers(0, nc, n)
+        t = rng.integers(0, 40_000 * 2000, n)
+    edep = rng.uniform(100, 511, n).astype(np.float32)
+    first, n_ev = 0, int(ev.max()) + 1
+    sg, (ca, cb) = ctx.digitize(_hitlist(ctx, ev, gid, edep, t, first, n_ev), seed=4)
+    so, co = o.digitize(_oracle_hits(oracle_mod, ev, gid, edep, t), seed=4)
+    s = sg.numpy()
+    assert np.array_equal(s["event"].view(np.uint32), so["event"])
+    assert np.array_equal(s["gid"].view(np.uint32), so["gid"])
+    assert np.array_equal(s["time_ps"].view(np.uint64), so["time_ps"])
+    np.testing.assert_allclose(s["edep_kev"], so["edep"], rtol=2e-7, atol=1e-4)
+    edge = (np.abs(so["energy"] - 350) < 1e-2) | (np.abs(so["energy"] - 650) < 1e-2)
+    assert np.array_equal(s["in_window"][~edge] != 0, so["in_window"][~edge] != 0)
+    got = sorted(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
+    ref = sorted(map(tuple, co.tolist()))
+    if not edge.any():
+        assert got == ref
+    else:
+        assert len(set(got) ^ set(ref)) <= 4 * int(edge.sum())
+
+
+def test_digitizer_rejects_events_outside_range(ctx, oracle_mod):
+    from paper_2603_07327_amd.gpet import GpetError
+    ctx.set_scene(G.small_animal_scene("C", n_events=10))
+    h = _hitlist(ctx, [3, 500], [1, 2], np.array([511, 511], np.float32), [0, 10], first=0, n_events=100)
+    with pytest.raises(GpetError):
+        ctx.digitize(h, seed=1)
 
 
 @pytest.mark.parametrize("case", ["ring8", "C"])
@@ -281,6 +353,33 @@ def test_determinism_and_chunking(ctx, oracle_mod):
     key = np.lexsort((cat["aux"], cat["gid"], cat["event"]))
     for k in w:
         assert np.array_equal(w[k], cat[k][key]), k
+
+
+def test_launch_shape_does_not_change_results(ctx, oracle_mod):
+    """Every random number is keyed by event id, so block count, search batching
+    and the lane scheduler leave the hit set (and its digitized output) unchanged."""
+    n = 60_000
+    ctx.set_scene(G.hot_rod_scene(n_events=n))
+
+    def canon(h):
+        g = h.numpy()
+        key = np.lexsort((g["aux"], g["gid"], g["event"]))
+        return {k: v[key] for k, v in g.items()}
+    ref = None
+    for shape in [(0, 32, 0), (2, 1, 0), (3, 64, 0), (0, 32, 1), (1, 16, 1)]:
+        ctx.set_launch(*shape)
+        h, st = ctx.transport(n, seed=21)
+        s, c = ctx.digitize(h, seed=21)
+        cur = (canon(h), s.numpy(), c[0].cpu().numpy(), st["steps"])
+        if ref is None:
+            ref = cur
+            continue
+        for k in ref[0]:
+            assert np.array_equal(ref[0][k], cur[0][k]), (shape, k)
+        for k in ref[1]:
+            assert np.array_equal(ref[1][k], cur[1][k]), (shape, k)
+        assert np.array_equal(ref[2], cur[2]) and ref[3] == cur[3]
+    ctx.set_launch(0, 32, 0)
 
 
 def test_capacity_error_and_rerun(ctx, oracle_mod):
