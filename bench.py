@@ -93,6 +93,112 @@ def cpu_baseline(target_s: float = 12.0):
                       f"{dt:.1f} s"}
 
 
+def batched_form(args):
+    """The batched design sweep (36 designs x 4 source offsets, log-uniform event
+    counts): one persistent transport launch over all instances plus one
+    digitizer pass, against the same instances run one by one through the plain
+    path (one context per design, source switched per instance).  Both forms
+    give identical per-instance coincidence counts (the batch reproduces the
+    plain runs bit for bit), so sensitivities match exactly."""
+    import torch
+
+    from paper_2603_07327_amd.gpet import ERR_CAPACITY, Batch, Context
+
+    mats, phys, inst = G.batch_sweep(n_scale=args.batched_scale, seed=0)
+    total = sum(d["n_events"] for d in inst)
+    ctx = Context(0)
+    ctx.set_materials(mats, phys)
+    ctx.set_phantom(None)
+    ctx.enable_timing(True)
+    b = Batch(ctx, inst)
+    hits = b.alloc_hits(int(3.0 * total))
+    rc, _ = b.transport_into(hits, seed=0)
+    if rc == ERR_CAPACITY:
+        need = hits.count
+        del hits
+        hits = b.alloc_hits(int(1.02 * need) + 1024)
+    tune = b.autotune(hits, seed=0, cache_path=args.autotune_cache,
+                      key=f"sweep144 scale={args.batched_scale} {torch.cuda.get_device_name(0)}")
+    singles = ctx.alloc_singles(hits.count + 1024, instance=True)
+    coinc = (ctx._empty(total // 2 + 1024, torch.int32), ctx._empty(total // 2 + 1024, torch.int32))
+
+    def batch_step(seed):
+        rc, st = b.transport_into(hits, seed=seed)
+        if rc != 0:
+            raise RuntimeError("batched hit capacity too small")
+        rc, nc, per = b.digitize_into(hits, singles, coinc, seed=seed)
+        if rc != 0:
+            raise RuntimeError("batched digitizer capacity too small")
+        return per, st
+
+    batch_step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for k in range(args.steps):
+        per_b, st_b = batch_step(2 + k)
+        kms.append(ctx.timings()[0])
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    last_seed = 1 + args.steps
+    b.close()
+    del hits, singles, coinc
+    ctx.close()
+    torch.cuda.empty_cache()
+
+    # the same instances one by one through the plain path
+    by_design = {}
+    for d in inst:
+        key = d["label"].rsplit("_x", 1)[0]
+        by_design.setdefault(key, []).append(d)
+    plain = []
+    for key, group in by_design.items():
+        c = Context(0)
+        c.set_materials(mats, phys)
+        c.set_scanner(group[0]["scanner"])
+        c.set_phantom(None)
+        nmax = max(d["n_events"] for d in group)
+        h = c.alloc_hits(int(4.0 * nmax))
+        sg = c.alloc_singles(int(4.0 * nmax))
+        cc = (c._empty(nmax, torch.int32), c._empty(nmax, torch.int32))
+        plain.append((c, group, h, sg, cc))
+    per_p = {}
+
+    def plain_pass(seed):
+        for c, group, h, sg, cc in plain:
+            for d in group:
+                c.set_source(d["source"])
+                rc, _ = c.transport_into(h, d["n_events"], seed=seed, first=d["first_event"], instance=d["instance"])
+                if rc != 0:
+                    raise RuntimeError("plain hit capacity too small")
+                rc, nc = c.digitize_into(h, sg, cc, seed=seed, instance=d["instance"])
+                if rc != 0:
+                    raise RuntimeError("plain digitizer capacity too small")
+                per_p[d["instance"]] = nc
+
+    plain_pass(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_pass(last_seed)
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    for c, *_ in plain:
+        c.close()
+    sens_b = np.array([per_b[i] for i in range(len(inst))], np.float64)
+    sens_p = np.array([per_p[d["instance"]] for d in inst], np.float64)
+    rel = np.abs(sens_b - sens_p) / np.maximum(sens_p, 1.0)
+    return {"workload": "batched design sweep: 36 designs (layer thickness 6/8/10/12 mm x offset 0/0.25/0.5 "
+                        "pitch x gap 0/0.2/0.5 mm) x 4 radial source offsets = 144 instances, event counts "
+                        "log-uniform in [1e5, 1e7], one persistent transport launch + one digitizer pass",
+            "instances": len(inst), "events": total, "value": total / dt_b, "unit": "events/s",
+            "ms_per_step": dt_b * 1e3, "transport_kernel_ms": float(np.mean(kms)),
+            "plain_one_by_one": {"value": total / dt_p, "ms": dt_p * 1e3},
+            "speedup_vs_plain": dt_p / dt_b, "sensitivity_max_rel_diff": float(rel.max()),
+            "coincidences": int(sens_b.sum()),
+            "autotune": {k: tune[k] for k in ("blocks_per_cu", "search_batch", "chunk", "ms")},
+            "stats_last": st_b}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +211,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
+    ap.add_argument("--batched-scale", type=float, default=1.0,
+                    help="event-count scale of the batched design sweep (0 skips it)")
+    ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the event-parallel sharding "
@@ -181,10 +290,13 @@ def main():
                      "work_per_launch": float(np.mean(work)), "transport_source": transport_source_hash()},
         "last_step": res, "stats_last": stats_last,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
     for _, c, *_ in ctxs:
         c.close()
+    del ctxs
+    if args.batched_scale > 0:
+        line["batched"] = batched_form(args)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 
 

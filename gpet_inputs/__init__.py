@@ -318,3 +318,39 @@ def tilted_ring_scene(n_events=100_000) -> dict:
     sc["scanner"] = scanner(8, 40.0, g["depth"], 1, 1, 12.8, 12.8, 0.0, 0.0, g["layers"],
                             poses=tilted_ring_poses())
     return sc
+
+
+# Batched design sweep: layer thickness (each of two layers) x inner-layer
+# offset (fraction of the pitch) x inter-layer gap, each design at four radial
+# point-source offsets.
+SWEEP_THICK = (6.0, 8.0, 10.0, 12.0)
+SWEEP_OFFSET = (0.0, 0.25, 0.5)
+SWEEP_GAP = (0.0, 0.2, 0.5)
+SWEEP_SOURCE_X = (0.0, 15.0, 30.0, 45.0)
+
+
+def batch_sweep(n_scale=1.0, seed=0, n_lo=1e5, n_hi=1e7):
+    """Instances of the batched sweep: 36 designs x 4 source offsets = 144.
+
+    Event counts are log-uniform: n_i = round(n_scale * 10^(log10 n_lo + u_i
+    log10(n_hi / n_lo))), u_i from numpy's PCG64 stream of `seed` (at least 1).
+    Returns (materials, physics, instances); an instance is a dict with keys
+    scanner, source, n_events, first_event (0), instance (its index) and label.
+    """
+    mats = [material("lyso", density=7.4), material("air")]
+    u = np.random.default_rng(seed).random(len(SWEEP_THICK) * len(SWEEP_OFFSET) * len(SWEEP_GAP)
+                                           * len(SWEEP_SOURCE_X))
+    a, b = math.log10(n_lo), math.log10(n_hi)
+    out = []
+    i = 0
+    for t in SWEEP_THICK:
+        for o in SWEEP_OFFSET:
+            for g in SWEEP_GAP:
+                scan = small_animal_scanner("X", thick=t, gap=g, offset=o)
+                for x in SWEEP_SOURCE_X:
+                    n = max(1, int(round(n_scale * 10.0 ** (a + u[i] * (b - a)))))
+                    out.append({"scanner": scan, "source": point_source((x, 0.0, 0.0), n), "n_events": n,
+                                "first_event": 0, "instance": i,
+                                "label": f"t{t:g}_o{o:g}_g{g:g}_x{x:g}"})
+                    i += 1
+    return mats, physics(rayleigh=True), out

@@ -207,6 +207,8 @@ typedef struct {
   uint64_t *time_ps; /* event time + time of flight, rounded to ps */
   uint32_t *aux;     /* bit 0 photon (0 = A, 1 = B); bits 1-2 process (1 PE, 2 Compton);
                         bits 8-31 index of the hit within its photon */
+  uint32_t *instance; /* index of the hit's instance in its batch (0 for a plain run);
+                         may be NULL for plain runs, required by gpet_batch_transport */
   uint64_t capacity;
   uint64_t count;    /* out: hits produced */
 } gpet_hits;
@@ -244,7 +246,7 @@ typedef struct {
   uint64_t first_event, n_events; /* event range the hits came from */
 } gpet_digitizer;
 
-/* Singles in (event, gid) order. */
+/* Singles in (instance, event, gid) order. */
 typedef struct {
   uint32_t *event, *gid;
   float *edep_kev;    /* summed deposit */
@@ -252,12 +254,13 @@ typedef struct {
   float *depth_mm;
   uint64_t *time_ps;
   uint32_t *in_window;
+  uint32_t *instance; /* optional (may be NULL): instance index of the single */
   uint64_t capacity;
   uint64_t count;     /* out */
 } gpet_singles;
 
 /* Coincidences as index pairs into the singles arrays, earlier single first,
- * ordered by the time of their first single. */
+ * ordered by (instance, time of their first single). */
 typedef struct {
   uint32_t *first, *second;
   uint64_t capacity;
@@ -276,6 +279,63 @@ typedef struct {
 gpet_status gpet_digitize(gpet_ctx *ctx, const gpet_hits *hits, const gpet_digitizer *params,
                           gpet_singles *singles, gpet_coincidences *coincidences,
                           gpet_tallies *tallies /* NULL: none */);
+
+/* ---------------------------------------------------------------------- */
+/* Batched runs: one persistent transport launch over a table of instances  */
+/* (a design sweep: each instance has its own scanner and source and its    */
+/* own event range), then one digitizer pass over all of their hits.  Waves */
+/* of the launch claim chunks of `chunk` consecutive events of one instance */
+/* from a device counter, so the tail of one instance overlaps the next and */
+/* small instances cost no launch of their own.  Every random number is     */
+/* keyed by (event, instance id), so instance i of a batch reproduces a     */
+/* plain gpet_transport / gpet_digitize run of the same scanner, source,    */
+/* event range and instance id bit for bit.                                 */
+/*                                                                          */
+/* The instances share the context's materials, physics and phantom.  The   */
+/* detector attenuation rows are staged once per launch, so the union of    */
+/* the instances' detector materials may hold at most 4 materials; the      */
+/* detector majorant is the maximum over that union (when it differs from   */
+/* an instance's own majorant, that instance matches a plain run in          */
+/* distribution only).                                                      */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  const gpet_scanner *scanner; /* host */
+  const gpet_source *source;   /* host */
+  uint64_t first_event, n_events; /* first_event + n_events <= 2^32 */
+  uint32_t instance;           /* id entering the random-number counters */
+} gpet_instance;
+
+typedef struct gpet_batch gpet_batch;
+
+/* Validates and uploads n instances (1..65536); descriptors are copied.  The
+ * batch keeps a pointer to ctx: every call but gpet_batch_destroy needs ctx
+ * alive.  Errors as gpet_geometry_create and gpet_source_set, naming the
+ * instance. */
+gpet_status gpet_batch_create(gpet_ctx *ctx, int32_t n, const gpet_instance *instances, gpet_batch **out);
+void gpet_batch_destroy(gpet_batch *batch);
+/* crystal id layout of instance i */
+gpet_status gpet_batch_info(gpet_batch *batch, int32_t i, gpet_geometry_info *info);
+/* Launch shape of the batch (see gpet_ctx_set_launch) and the chunk of events
+ * a wave claims at a time (1..2^20). */
+gpet_status gpet_batch_set_launch(gpet_batch *batch, int32_t blocks_per_cu, int32_t search_batch, uint32_t chunk);
+/* Transports every instance; hits->instance receives the instance index.
+ * Same capacity contract and stats as gpet_transport (summed over instances). */
+gpet_status gpet_batch_transport(gpet_batch *batch, uint64_t seed, gpet_hits *hits, gpet_stats *stats);
+/* Digitizes the hits of a batch; params->first_event, n_events and instance
+ * are ignored (each instance uses its own).  Singles come out in (instance,
+ * event, gid) order and coincidences in (instance, time) order; a window never
+ * spans two instances.  coinc_per_instance (host, n entries, may be NULL)
+ * receives each instance's coincidence count. */
+gpet_status gpet_batch_digitize(gpet_batch *batch, const gpet_hits *hits, const gpet_digitizer *params,
+                                gpet_singles *singles, gpet_coincidences *coincidences,
+                                uint64_t *coinc_per_instance);
+/* Autotuner: times the batch's transport launch (kernel time, HIP events) over
+ * launch shapes and chunk sizes, by coordinate search from the current shape,
+ * and keeps the fastest.  `hits` is scratch output of sufficient capacity.
+ * Writes a JSON summary {"blocks_per_cu", "search_batch", "chunk", "ms",
+ * "trials": [[blocks_per_cu, search_batch, chunk, ms], ...]} into json
+ * (NUL-terminated, truncated to cap bytes; may be NULL). */
+gpet_status gpet_batch_autotune(gpet_batch *batch, uint64_t seed, gpet_hits *hits, char *json, size_t cap);
 
 /* Launch shape of the transport kernel: blocks of 256 lanes per compute unit
  * (0 = as many as fit); the scheduling of lane actions within a wavefront

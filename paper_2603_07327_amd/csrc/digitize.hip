@@ -14,6 +14,7 @@
 //      the cluster's first lane; counts are scanned so that the coincidence
 //      list comes out in a fixed order.
 #include <algorithm>
+#include <cstring>
 
 #include "gpet_internal.hpp"
 
@@ -207,15 +208,35 @@ __device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
   return mine;
 }
 
-// keys whose bucket lies at or past nb are skipped and flagged (bit 1 of *flag)
+// Bucket of a key: instance i = key >> inst_shift owns buckets
+// [base[i], base[i] + count[i]); inside them the bucket grows linearly with the
+// key's local value v = (key >> local_shift) & local_mask (event index or time),
+// so every instance gets buckets in proportion to its item count.
+struct BucketMap {
+  int inst_shift, local_shift;
+  unsigned long long local_mask;
+  const uint32_t *base, *count;
+  const float *scale; // buckets per unit of v
+  uint32_t n_inst, nb;
+};
+
+__device__ __forceinline__ uint32_t bucket_of(const BucketMap &M, unsigned long long key) {
+  const uint32_t i = M.inst_shift < 64 ? (uint32_t)(key >> M.inst_shift) : 0u;
+  if (i >= M.n_inst) return M.nb; // caller treats as out of range
+  const unsigned long long v = (key >> M.local_shift) & M.local_mask;
+  const uint32_t b = min((uint32_t)((float)v * M.scale[i]), M.count[i] - 1u);
+  return M.base[i] + b;
+}
+
+// keys whose bucket falls outside the map are skipped and flagged (bit 1 of *flag)
 template <bool AGG>
-__global__ void k_bucket_count(const unsigned long long *key, size_t n, int shift, size_t nb, uint32_t *count,
+__global__ void k_bucket_count(const unsigned long long *key, size_t n, BucketMap M, uint32_t *count,
                                uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned long long kb = i < n ? key[i] >> shift : 0ull;
-  if (i < n && kb >= nb) atomicOr(flag, 2u);
-  const bool valid = i < n && kb < nb;
-  const uint32_t b = valid ? (uint32_t)kb : 0u;
+  const uint32_t kb = i < n ? bucket_of(M, key[i]) : 0u;
+  if (i < n && kb >= M.nb) atomicOr(flag, 2u);
+  const bool valid = i < n && kb < M.nb;
+  const uint32_t b = valid ? kb : 0u;
   if constexpr (AGG) {
     const uint64_t peers = equal_peers(b, valid);
     if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[b], (uint32_t)__popcll(peers));
@@ -226,12 +247,13 @@ __global__ void k_bucket_count(const unsigned long long *key, size_t n, int shif
 
 // cursor holds bucket starts on entry and bucket ends on exit
 template <bool AGG>
-__global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *vin, size_t n, int shift, size_t nb,
+__global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *vin, size_t n, BucketMap M,
                                  uint32_t *cursor, unsigned long long *kout, uint32_t *vout) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned long long k = i < n ? kin[i] : 0ull;
-  const bool valid = i < n && (k >> shift) < nb;
-  const uint32_t b = valid ? (uint32_t)(k >> shift) : 0u;
+  const uint32_t kb = i < n ? bucket_of(M, k) : 0u;
+  const bool valid = i < n && kb < M.nb;
+  const uint32_t b = valid ? kb : 0u;
   uint32_t pos = 0;
   if constexpr (AGG) {
     const uint64_t below = __lanemask_lt();
@@ -248,6 +270,15 @@ __global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *
     kout[pos] = k;
     vout[pos] = vin[i];
   }
+}
+
+// items per instance (instance = key >> shift)
+__global__ void k_inst_count(const unsigned long long *key, size_t n, int shift, uint32_t n_inst, uint32_t *count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t v = i < n ? (shift < 64 ? (uint32_t)(key[i] >> shift) : 0u) : 0u;
+  const bool valid = i < n && v < n_inst;
+  const uint64_t peers = equal_peers(v, valid);
+  if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[v], (uint32_t)__popcll(peers));
 }
 
 __device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, unsigned long long kb, uint32_t vb) {
@@ -307,33 +338,48 @@ static int log2_ceil(uint64_t x) {
 }
 
 struct BucketBufs {
-  uint32_t *count;        // bucket counters (>= max_buckets words)
+  uint32_t *count;       // bucket counters (>= max_buckets words)
   size_t max_buckets;
-  uint32_t *overflow;     // device flag
-  uint32_t *pinned_flag;  // host mirror
+  uint32_t *overflow;    // device flag
+  uint32_t *map;         // per-instance bucket map (3 words per instance)
+  uint32_t *pinned_flag; // host mirrors
+  uint32_t *pinned_map;
 };
 
-// Sorts (b.k0, b.v0) into (b.k1, b.v1) by (key, value) for keys <= key_max.
+// Sorts (b.k0, b.v0) into (b.k1, b.v1) by (key, value).  `items[i]` is the
+// number of keys of instance i and `range[i]` the extent of their local value.
 // Returns 0 when sorted, bit 0 when a bucket was too large for LDS, bit 1 when
-// a key exceeded key_max (then (k1, v1) are not sorted).
+// a key fell outside the map (then (k1, v1) are not sorted).
 template <bool AGG>
-static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, unsigned long long key_max, hipStream_t st,
-                            uint32_t *scan_tmp) {
-  const int key_bits = key_max ? 64 - __builtin_clzll(key_max) : 1;
-  const int want = log2_ceil(n / 256 + 1);
-  int shift = key_bits > want ? key_bits - want : 0;
-  size_t nb = (size_t)(key_max >> shift) + 1;
-  while (nb > bb.max_buckets) {
-    ++shift;
-    nb = (size_t)(key_max >> shift) + 1;
+static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shift, int local_shift,
+                            unsigned long long local_mask, const std::vector<uint64_t> &items,
+                            const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp) {
+  const size_t ni = items.size();
+  std::vector<uint32_t> base(ni), cnt(ni);
+  std::vector<float> scale(ni);
+  size_t nb = 0;
+  for (size_t i = 0; i < ni; ++i) {
+    const uint64_t c = std::max<uint64_t>(1, (items[i] + 255) / 256);
+    base[i] = (uint32_t)nb;
+    cnt[i] = (uint32_t)c;
+    scale[i] = (float)((double)c / std::max(range[i], 1.0));
+    nb += c;
   }
+  if (nb > bb.max_buckets) return 1u; // let the caller fall back
+  // per-instance map arrays live behind the bucket counters
+  uint32_t *d_base = bb.map, *d_cnt = bb.map + ni;
+  float *d_scale = (float *)(bb.map + 2 * ni);
+  std::memcpy(bb.pinned_map, base.data(), ni * 4);
+  std::memcpy(bb.pinned_map + ni, cnt.data(), ni * 4);
+  std::memcpy(bb.pinned_map + 2 * ni, scale.data(), ni * 4);
+  (void)hipMemcpyAsync(bb.map, bb.pinned_map, 3 * ni * 4, hipMemcpyHostToDevice, st);
+  BucketMap M{inst_shift, local_shift, local_mask, d_base, d_cnt, d_scale, (uint32_t)ni, (uint32_t)nb};
   launch_fill_u32(bb.count, 0u, nb, st);
   launch_fill_u32(bb.overflow, 0u, 1, st);
   const unsigned g = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_bucket_count<AGG>, dim3(g), dim3(256), 0, st, b.k0, n, shift, nb, bb.count, bb.overflow);
+  hipLaunchKernelGGL(k_bucket_count<AGG>, dim3(g), dim3(256), 0, st, b.k0, n, M, bb.count, bb.overflow);
   exclusive_scan(bb.count, nb, scan_tmp, st);
-  hipLaunchKernelGGL(k_bucket_scatter<AGG>, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, shift, nb, bb.count, b.k1,
-                     b.v1);
+  hipLaunchKernelGGL(k_bucket_scatter<AGG>, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, M, bb.count, b.k1, b.v1);
   hipLaunchKernelGGL(k_bucket_local_sort, dim3((unsigned)nb), dim3(256), 0, st, b.k1, b.v1, bb.count, bb.overflow);
   (void)hipMemcpyAsync(bb.pinned_flag, bb.overflow, 4, hipMemcpyDeviceToHost, st);
   (void)hipStreamSynchronize(st);
@@ -343,19 +389,35 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, unsigned long
 // ---------------------------------------------------------------------------
 // digitizer stages
 // ---------------------------------------------------------------------------
-// key = (event - first) | gid | photon | index of the hit within its photon
-// (7 bits, saturated): unique per hit, so the sorted order is fixed
-__global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux, uint32_t first,
-                           int gid_bits, unsigned long long *key, uint32_t *val) {
+// Per-instance constants of the digitizer (device arrays of n_inst entries).
+struct InstTab {
+  const uint32_t *first, *n_events, *cpp, *rng;
+  uint32_t n_inst;
+};
+
+// key = instance | (event - first) | gid | photon | index of the hit within its
+// photon (7 bits, saturated): unique per hit, so the sorted order is fixed.
+// Hits outside their instance's event range are flagged (bit 1 of *flag).
+__global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux,
+                           const uint32_t *hinst, InstTab T, int gid_bits, int inst_shift, unsigned long long *key,
+                           uint32_t *val, uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const uint32_t in = hinst ? hinst[i] : 0u;
   const uint32_t a = aux[i];
   const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
-  key[i] = ((((unsigned long long)(ev[i] - first) << gid_bits) | gid[i]) << 8) | low;
+  uint32_t e = 0;
+  if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in]) {
+    atomicOr(flag, 2u);
+  } else {
+    e = ev[i] - T.first[in];
+  }
+  const unsigned long long inst_bits = inst_shift < 64 ? (unsigned long long)(in < T.n_inst ? in : 0u) << inst_shift : 0ull;
+  key[i] = inst_bits | ((((unsigned long long)e << gid_bits) | gid[i]) << 8) | low;
   val[i] = (uint32_t)i;
 }
 
-// first hit of each (event, crystal) run
+// first hit of each (instance, event, crystal) run
 __global__ void k_heads(size_t n, const unsigned long long *key, uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -364,8 +426,9 @@ __global__ void k_heads(size_t n, const unsigned long long *key, uint32_t *flag)
 
 __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t *perm, const uint32_t *seg,
                         const uint32_t *ev, const uint32_t *gid, const float *edep, const float *depth,
-                        const unsigned long long *time, uint32_t *s_ev, uint32_t *s_gid, float *s_edep,
-                        float *s_depth, unsigned long long *s_time, uint64_t cap) {
+                        const unsigned long long *time, int inst_shift, uint32_t *s_ev, uint32_t *s_gid,
+                        float *s_edep, float *s_depth, unsigned long long *s_time, uint32_t *s_inst_int,
+                        uint32_t *s_inst_out, uint64_t cap) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const unsigned long long run = key[i] >> 8;
@@ -384,24 +447,28 @@ __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t 
   if (s >= cap) return;
   const uint32_t h = perm[i];
   const double E = (double)se * 0x1p-32;
+  const uint32_t in = inst_shift < 64 ? (uint32_t)(key[i] >> inst_shift) : 0u;
   s_ev[s] = ev[h];
   s_gid[s] = gid[h];
   s_edep[s] = (float)E;
   s_depth[s] = se ? (float)((double)sd / (double)se) : 0.0f;
   s_time[s] = tm;
+  s_inst_int[s] = in;
+  if (s_inst_out) s_inst_out[s] = in;
 }
 
 __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, const uint32_t *s_gid,
-                                              const float *s_edep, float *s_energy, uint32_t *s_win, uint32_t *wflag,
-                                              uint32_t k0, uint32_t k1, uint32_t inst, float fwhm, float e_lo,
-                                              float e_hi, uint32_t *spp, uint32_t *spec,
-                                              const unsigned long long *s_time, unsigned long long *block_max) {
+                                              const uint32_t *s_inst, InstTab T, const float *s_edep,
+                                              float *s_energy, uint32_t *s_win, uint32_t *wflag, uint32_t k0,
+                                              uint32_t k1, float fwhm, float e_lo, float e_hi, uint32_t *spp,
+                                              uint32_t *spec, const unsigned long long *s_time,
+                                              unsigned long long *block_max) {
   __shared__ unsigned long long s_max[4];
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long tm = 0; // largest time stamp among windowed singles
   if (i < n) {
-    // normal deviate by Box-Muller from the digitizer stream of (gid, event)
-    const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], inst, 3u));
+    // normal deviate by Box-Muller from the digitizer stream of (gid, event, instance)
+    const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], T.rng[s_inst[i]], 3u));
     const float u0 = to_unit(w.x), u1 = to_unit(w.y);
     const float g = sqrtf(-2.0f * logf(u0)) * cos_rev(u1);
     const float E = s_edep[i];
@@ -442,18 +509,20 @@ __global__ void __launch_bounds__(1024) k_max_u64(const unsigned long long *v, s
   if (threadIdx.x == 0) *out = s[0];
 }
 
+// windowed singles: key = instance | time, value = single index
 __global__ void k_time_keys(size_t n, const uint32_t *win, const uint32_t *pos, const unsigned long long *s_time,
-                            unsigned long long *key, uint32_t *val) {
+                            const uint32_t *s_inst, int time_bits, unsigned long long *key, uint32_t *val) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !win[i] || pos[i] >= n) return;
-  key[pos[i]] = s_time[i];
+  key[pos[i]] = time_bits < 64 ? ((unsigned long long)s_inst[i] << time_bits) | s_time[i] : s_time[i];
   val[pos[i]] = (uint32_t)i;
 }
 
 // coincidences of the cluster starting at sorted position k (k must be a head)
 template <bool WRITE>
 __device__ __forceinline__ uint32_t resolve_cluster(size_t k, size_t n, const unsigned long long *t,
-                                                    const uint32_t *idx, const uint32_t *s_gid, uint32_t cpp,
+                                                    const uint32_t *idx, const uint32_t *s_gid,
+                                                    const uint32_t *s_inst, const uint32_t *cpp_of,
                                                     unsigned long long W, uint32_t *first, uint32_t *second,
                                                     uint32_t out, uint64_t cap) {
   size_t end = k + 1;
@@ -465,6 +534,7 @@ __device__ __forceinline__ uint32_t resolve_cluster(size_t k, size_t n, const un
     while (j < end && t[j] - t[i] <= W) ++j;
     if (j - i == 2) {
       const uint32_t a = idx[i], b = idx[i + 1];
+      const uint32_t cpp = cpp_of[s_inst[a]]; // a window never spans two instances
       if (s_gid[a] / cpp != s_gid[b] / cpp) {
         if (WRITE && out + c < cap) {
           first[out + c] = a;
@@ -479,20 +549,30 @@ __device__ __forceinline__ uint32_t resolve_cluster(size_t k, size_t n, const un
 }
 
 __global__ void k_coinc_count(size_t n, const unsigned long long *t, const uint32_t *idx, const uint32_t *s_gid,
-                              uint32_t cpp, unsigned long long W, uint32_t *cnt) {
+                              const uint32_t *s_inst, const uint32_t *cpp_of, unsigned long long W, uint32_t *cnt) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const bool head = k == 0 || t[k] - t[k - 1] > W;
-  cnt[k] = head ? resolve_cluster<false>(k, n, t, idx, s_gid, cpp, W, nullptr, nullptr, 0, 0) : 0u;
+  cnt[k] = head ? resolve_cluster<false>(k, n, t, idx, s_gid, s_inst, cpp_of, W, nullptr, nullptr, 0, 0) : 0u;
 }
 
 __global__ void k_coinc_write(size_t n, const unsigned long long *t, const uint32_t *idx, const uint32_t *s_gid,
-                              uint32_t cpp, unsigned long long W, const uint32_t *off, uint32_t *first,
-                              uint32_t *second, uint64_t cap) {
+                              const uint32_t *s_inst, const uint32_t *cpp_of, unsigned long long W,
+                              const uint32_t *off, uint32_t *first, uint32_t *second, uint64_t cap) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const bool head = k == 0 || t[k] - t[k - 1] > W;
-  if (head) resolve_cluster<true>(k, n, t, idx, s_gid, cpp, W, first, second, off[k], cap);
+  if (head) resolve_cluster<true>(k, n, t, idx, s_gid, s_inst, cpp_of, W, first, second, off[k], cap);
+}
+
+// coincidences per instance (instance of the first single)
+__global__ void k_coinc_inst(size_t n, const uint32_t *first, const uint32_t *s_inst, uint32_t n_inst,
+                             uint32_t *count) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t v = k < n ? s_inst[first[k]] : 0u;
+  const bool valid = k < n && v < n_inst;
+  const uint64_t peers = equal_peers(v, valid);
+  if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[v], (uint32_t)__popcll(peers));
 }
 
 __global__ void k_hit_tallies(size_t n, const uint32_t *gid, const float *depth, uint32_t *hpc, uint32_t *doi,
@@ -513,6 +593,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::string &err) {
   const size_t n = D.n_hits;
+  const size_t ni = D.first.size();
   gpet_singles *S = D.singles;
   gpet_coincidences *C = D.coinc;
   const gpet_tallies *T = D.tallies;
@@ -521,14 +602,16 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   if (T && (T->hits_per_crystal || T->doi) && n)
     hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
                        T->hits_per_crystal, T->doi, T->doi_bins, D.panel_depth);
+  if (D.coinc_per_inst) std::fill(D.coinc_per_inst, D.coinc_per_inst + ni, 0ull);
   if (n == 0) return hipStreamSynchronize(st) == hipSuccess ? GPET_OK : GPET_ERR_HIP;
 
-  // scratch: 2 key + 2 value arrays, 2 flag arrays, radix histogram, scan temp, time maximum
+  // scratch: 2 key + 2 value arrays, flags, positions, single instances, radix
+  // histogram, scan temp, bucket counters and maps, instance table
   const size_t tiles = (n + kSortTile - 1) / kSortTile;
-  const size_t max_buckets = n / 128 + 1024;
+  const size_t max_buckets = n / 128 + 1024 + 2 * ni;
   const size_t scan_words = scan_scratch_words(std::max<size_t>(std::max<size_t>(256 * tiles, n), max_buckets));
-  const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 4 + align_up(256 * tiles * 4) +
-                      align_up(scan_words * 4) + align_up(max_buckets * 4) + 512;
+  const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
+                      align_up(scan_words * 4) + align_up(max_buckets * 4) + align_up(ni * 4) * 8 + 1024;
   if (scr.bytes < need) {
     if (scr.buf) (void)hipFree(scr.buf);
     scr.buf = nullptr;
@@ -539,9 +622,16 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
     scr.bytes = need;
   }
-  if (!scr.pinned && hipHostMalloc((void **)&scr.pinned, 64, hipHostMallocDefault) != hipSuccess) {
-    err = "digitize: pinned readback allocation failed";
-    return GPET_ERR_HIP;
+  const size_t pinned_bytes = 64 + 4 * ni + 16 * ni;
+  if (scr.pinned_bytes < pinned_bytes) {
+    if (scr.pinned) (void)hipHostFree(scr.pinned);
+    scr.pinned = nullptr;
+    scr.pinned_bytes = 0;
+    if (hipHostMalloc((void **)&scr.pinned, pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+      err = "digitize: pinned readback allocation failed";
+      return GPET_ERR_HIP;
+    }
+    scr.pinned_bytes = pinned_bytes;
   }
   char *p = (char *)scr.buf;
   auto take = [&](size_t bytes) {
@@ -556,15 +646,24 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   sb.v1 = (uint32_t *)take(n * 4);
   uint32_t *flag = (uint32_t *)take(n * 4);
   uint32_t *wpos = (uint32_t *)take(n * 4);
+  uint32_t *s_inst = (uint32_t *)take(n * 4);
   sb.hist = (uint32_t *)take(256 * tiles * 4);
   sb.scan_tmp = (uint32_t *)take(scan_words * 4);
   unsigned long long *tmax_dev = (unsigned long long *)take(8);
+  uint32_t *err_flag = (uint32_t *)take(8);
   BucketBufs bb;
   bb.count = (uint32_t *)take(max_buckets * 4);
   bb.max_buckets = max_buckets;
   bb.overflow = (uint32_t *)take(8);
-  uint32_t *rb = (uint32_t *)scr.pinned; // pinned readback words
+  bb.map = (uint32_t *)take(ni * 4 * 3);
+  uint32_t *d_tab = (uint32_t *)take(ni * 4 * 4); // first, n_events, cpp, rng
+  uint32_t *d_icount = (uint32_t *)take(ni * 4);
+  // pinned host words: [0, 16) scalar readbacks, [16, 16 + ni) per-instance
+  // counts, then 4 ni words for the instance table / bucket map uploads
+  uint32_t *rb = (uint32_t *)scr.pinned;
+  uint32_t *rb_count = rb + 16;
   bb.pinned_flag = rb + 12;
+  bb.pinned_map = rb + 16 + ni;
   auto sync = [&](const char *what) {
     if (hipStreamSynchronize(st) != hipSuccess) {
       err = std::string("digitize: stream error ") + what;
@@ -573,21 +672,58 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     return true;
   };
 
-  // 1. sort hits by (event, gid)
-  hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux,
-                     D.first_event, D.gid_bits, sb.k0, sb.v0);
-  const int hit_bits = D.event_bits + D.gid_bits + 8;
-  const unsigned long long hit_max =
-      ((unsigned long long)(D.n_events - 1) << (D.gid_bits + 8)) | ((1ull << (D.gid_bits + 8)) - 1);
-  const unsigned long long *hk = sb.k1;
-  const uint32_t *hp = sb.v1;
-  const uint32_t hflag = bucket_sort<true>(sb, bb, n, hit_max, st, sb.scan_tmp);
-  if (hflag & 2u) {
-    err = "digitize: a hit's event id lies outside [first_event, first_event + n_events)";
+  // instance table on the device
+  uint32_t *tab = bb.pinned_map; // staged here before any bucket map is
+  for (size_t i = 0; i < ni; ++i) {
+    tab[i] = D.first[i];
+    tab[ni + i] = D.n_events[i];
+    tab[2 * ni + i] = D.cpp[i];
+    tab[3 * ni + i] = D.rng[i];
+  }
+  (void)hipMemcpyAsync(d_tab, tab, ni * 16, hipMemcpyHostToDevice, st);
+  if (!sync("uploading the instance table")) return GPET_ERR_HIP;
+  const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, (uint32_t)ni};
+  uint32_t max_events = 1;
+  for (size_t i = 0; i < ni; ++i) max_events = std::max(max_events, D.n_events[i]);
+  int event_bits = 1;
+  while (event_bits < 32 && ((uint64_t)(max_events - 1) >> event_bits) != 0) ++event_bits;
+  const int hit_shift = D.gid_bits + 8; // local value of a hit key: the event index
+  const int inst_bits = ni > 1 ? log2_ceil(ni) : 0;
+  const int inst_shift = ni > 1 ? event_bits + hit_shift : 64;
+  if (event_bits + hit_shift + inst_bits > 64) {
+    err = "digitize: instance, event and crystal ids do not fit a 64-bit sort key";
     return GPET_ERR_ARG;
   }
-  if (hflag) { // a bucket overflowed LDS
-    const bool f1 = radix_sort(sb, n, hit_bits, st);
+
+  // 1. sort hits by (instance, event, gid, photon, index)
+  launch_fill_u32(err_flag, 0u, 1, st);
+  hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux, D.h_inst, IT,
+                     D.gid_bits, inst_shift, sb.k0, sb.v0, err_flag);
+  std::vector<uint64_t> items(ni, n);
+  if (ni > 1) {
+    launch_fill_u32(d_icount, 0u, ni, st);
+    hipLaunchKernelGGL(k_inst_count, dim3(grid_for(n)), dim3(256), 0, st, sb.k0, n, inst_shift, (uint32_t)ni,
+                       d_icount);
+    (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+  }
+  (void)hipMemcpyAsync(rb + 13, err_flag, 4, hipMemcpyDeviceToHost, st);
+  if (!sync("building hit keys")) return GPET_ERR_HIP;
+  if (rb[13] & 2u) {
+    err = "digitize: a hit's instance or event id lies outside its declared range";
+    return GPET_ERR_ARG;
+  }
+  std::vector<double> range(ni);
+  for (size_t i = 0; i < ni; ++i) {
+    if (ni > 1) items[i] = rb_count[i];
+    range[i] = (double)D.n_events[i];
+  }
+  const unsigned long long ev_mask = (1ull << event_bits) - 1;
+  const unsigned long long *hk = sb.k1;
+  const uint32_t *hp = sb.v1;
+  const uint32_t hflag = bucket_sort<true>(sb, bb, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp);
+  if (hflag) { // a bucket overflowed LDS: sort every key bit instead
+    const int bits = hit_shift + event_bits + inst_bits;
+    const bool f1 = radix_sort(sb, n, bits, st);
     hk = f1 ? sb.k1 : sb.k0;
     hp = f1 ? sb.v1 : sb.v0;
   }
@@ -604,11 +740,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     return GPET_ERR_CAPACITY;
   }
   hipLaunchKernelGGL(k_adder, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_event, D.h_gid, D.h_edep,
-                     D.h_depth, D.h_time, S->event, S->gid, S->edep_kev, S->depth_mm, (unsigned long long *)S->time_ps, S->capacity);
+                     D.h_depth, D.h_time, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
+                     (unsigned long long *)S->time_ps, s_inst, S->instance, S->capacity);
   // 3. blur + window; per-block maxima of the windowed time stamps go to the
   //    (now free) second key array, then one block reduces them
-  hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, S->edep_kev,
-                     S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.instance, D.fwhm_511, D.e_lo, D.e_hi,
+  hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
+                     S->edep_kev, S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
                      T ? T->singles_per_crystal : nullptr, T ? T->energy_spectrum : nullptr,
                      (const unsigned long long *)S->time_ps, sb.k1);
   hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
@@ -617,38 +754,72 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   exclusive_scan(wpos, ns, sb.scan_tmp, st);
   (void)hipMemcpyAsync(rb + 3, wpos + ns - 1, 4, hipMemcpyDeviceToHost, st);
   (void)hipMemcpyAsync(rb + 4, tmax_dev, 8, hipMemcpyDeviceToHost, st);
-  // 4. windowed singles in time order (stable: ties keep (event, gid) order)
-  hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->in_window, wpos,
-                     (const unsigned long long *)S->time_ps, sb.k0, sb.v0);
   if (!sync("after the energy window")) return GPET_ERR_HIP;
   const size_t nw = (size_t)rb[3] + rb[2];
   const unsigned long long tmax = (unsigned long long)rb[4] | ((unsigned long long)rb[5] << 32);
+  // time bits leave room for the window, so keys of two instances differ by more than it
   int time_bits = 0;
-  while (time_bits < 64 && (tmax >> time_bits) != 0) ++time_bits;
-  if (nw == 0) return GPET_OK;
+  while (time_bits < 63 && ((tmax + D.window_ps + 1) >> time_bits) != 0) ++time_bits;
+  if (nw == 0) {
+    if (D.coinc_per_inst) std::fill(D.coinc_per_inst, D.coinc_per_inst + ni, 0ull);
+    return GPET_OK;
+  }
+  if (time_bits + inst_bits > 64) {
+    err = "digitize: instance and time stamp do not fit a 64-bit sort key";
+    return GPET_ERR_ARG;
+  }
+  // 4. windowed singles in (instance, time) order (ties keep (event, gid) order)
+  hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->in_window, wpos,
+                     (const unsigned long long *)S->time_ps, s_inst, ni > 1 ? time_bits : 64, sb.k0, sb.v0);
+  std::vector<uint64_t> witems(ni, nw);
+  if (ni > 1) {
+    launch_fill_u32(d_icount, 0u, ni, st);
+    hipLaunchKernelGGL(k_inst_count, dim3(grid_for(nw)), dim3(256), 0, st, sb.k0, nw, time_bits, (uint32_t)ni,
+                       d_icount);
+    (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+    if (!sync("counting windowed singles")) return GPET_ERR_HIP;
+    for (size_t i = 0; i < ni; ++i) witems[i] = rb_count[i];
+  }
+  std::vector<double> trange(ni, (double)tmax + 1.0);
+  for (size_t i = 0; i < ni; ++i)
+    if (D.duration.size() == ni && D.duration[i]) trange[i] = (double)D.duration[i] + 1048576.0;
   const unsigned long long *tk = sb.k1;
   const uint32_t *ti = sb.v1;
-  if (nw > 1 && bucket_sort<false>(sb, bb, nw, tmax, st, sb.scan_tmp) != 0u) {
-    const bool f2 = radix_sort(sb, nw, time_bits, st);
-    tk = f2 ? sb.k1 : sb.k0;
-    ti = f2 ? sb.v1 : sb.v0;
-  } else if (nw == 1) {
+  const unsigned long long t_mask = time_bits < 64 ? (1ull << time_bits) - 1 : ~0ull;
+  if (nw == 1) {
     tk = sb.k0;
     ti = sb.v0;
+  } else if (bucket_sort<false>(sb, bb, nw, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st, sb.scan_tmp)) {
+    const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
+    tk = f2 ? sb.k1 : sb.k0;
+    ti = f2 ? sb.v1 : sb.v0;
   }
   // 5. coincidences: count per cluster, scan, write
-  hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid,
-                     (uint32_t)D.crystals_per_panel, D.window_ps, flag);
+  hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
+                     D.window_ps, flag);
   (void)hipMemcpyAsync(rb + 6, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
   exclusive_scan(flag, nw, sb.scan_tmp, st);
   (void)hipMemcpyAsync(rb + 7, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
-  hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid,
-                     (uint32_t)D.crystals_per_panel, D.window_ps, flag, C->first, C->second, C->capacity);
+  hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
+                     D.window_ps, flag, C->first, C->second, C->capacity);
   if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
   C->count = (uint64_t)rb[7] + rb[6];
   if (C->count > C->capacity) {
     err = "digitize: coincidence capacity too small";
     return GPET_ERR_CAPACITY;
+  }
+  if (D.coinc_per_inst) {
+    if (ni == 1) {
+      D.coinc_per_inst[0] = C->count;
+    } else {
+      launch_fill_u32(d_icount, 0u, ni, st);
+      if (C->count)
+        hipLaunchKernelGGL(k_coinc_inst, dim3(grid_for(C->count)), dim3(256), 0, st, (size_t)C->count, C->first,
+                           s_inst, (uint32_t)ni, d_icount);
+      (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+      if (!sync("counting coincidences per instance")) return GPET_ERR_HIP;
+      for (size_t i = 0; i < ni; ++i) D.coinc_per_inst[i] = rb_count[i];
+    }
   }
   return GPET_OK;
 }
@@ -656,6 +827,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
 void free_scratch(DigitizeScratch &scr) {
   if (scr.pinned) (void)hipHostFree(scr.pinned);
   scr.pinned = nullptr;
+  scr.pinned_bytes = 0;
   if (scr.buf) (void)hipFree(scr.buf);
   scr.buf = nullptr;
   scr.bytes = 0;

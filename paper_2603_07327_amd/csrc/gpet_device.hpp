@@ -44,8 +44,10 @@ struct LayerD {
   int pad_;
 };
 
-// Everything a kernel needs about the scene, passed by value as a kernel
-// argument (scalar-loaded); large arrays stay in device memory.
+// Everything a kernel needs about one scene (one instance of a batch).  The
+// transport kernel reads it through a wave-uniform pointer in the constant
+// address space, so its fields are scalar loads; large arrays stay in device
+// memory.
 struct DevScene {
   // panels
   int n_panels;
@@ -153,24 +155,25 @@ __device__ __forceinline__ float4 lerp4(const float4 *t, int m, Lerp l) {
 struct Vec {
   float x, y, z;
 };
-__device__ __forceinline__ Vec to_local(const float *P, Vec g) {
+typedef __attribute__((address_space(4))) const float CFloat; // read-only view (scalar loads when uniform)
+template <class PT> __device__ __forceinline__ Vec to_local(PT P, Vec g) {
   return Vec{g.x * P[0] + g.y * P[1] + g.z * P[2] - P[9], g.x * P[3] + g.y * P[4] + g.z * P[5] - P[10],
              g.x * P[6] + g.y * P[7] + g.z * P[8] - P[11]};
 }
-__device__ __forceinline__ Vec dir_to_local(const float *P, Vec d) {
+template <class PT> __device__ __forceinline__ Vec dir_to_local(PT P, Vec d) {
   return Vec{d.x * P[0] + d.y * P[1] + d.z * P[2], d.x * P[3] + d.y * P[4] + d.z * P[5],
              d.x * P[6] + d.y * P[7] + d.z * P[8]};
 }
-__device__ __forceinline__ Vec to_global(const float *P, Vec l) {
+template <class PT> __device__ __forceinline__ Vec to_global(PT P, Vec l) {
   const float a = l.x + P[9], b = l.y + P[10], c = l.z + P[11];
   return Vec{a * P[0] + b * P[3] + c * P[6], a * P[1] + b * P[4] + c * P[7], a * P[2] + b * P[5] + c * P[8]};
 }
-__device__ __forceinline__ Vec dir_to_global(const float *P, Vec l) {
+template <class PT> __device__ __forceinline__ Vec dir_to_global(PT P, Vec l) {
   return Vec{l.x * P[0] + l.y * P[3] + l.z * P[6], l.x * P[1] + l.y * P[4] + l.z * P[7],
              l.x * P[2] + l.y * P[5] + l.z * P[8]};
 }
 
-__device__ __forceinline__ bool inside_panel(const DevScene &S, Vec l) {
+template <class SC> __device__ __forceinline__ bool inside_panel(SC &S, Vec l) {
   return l.x >= 0.0f && l.x < S.depth && l.y >= -S.half_w && l.y < S.half_w && l.z >= -S.half_l &&
          l.z < S.half_l;
 }
@@ -206,12 +209,12 @@ __device__ __forceinline__ bool ray_box(Vec o, Vec d, Vec lo, Vec hi, float &t_e
 
 // Line-plane projection to the panels (Sec. 2.1): nearest panel box along
 // the ray, excluding the panel just left; ties to the lower index.
-__device__ __forceinline__ int panel_search(const DevScene &S, Vec x, Vec d, int exclude, float &t_in) {
+template <class SC> __device__ __forceinline__ int panel_search(SC &S, Vec x, Vec d, int exclude, float &t_in) {
   int best = -1;
   float bt = INFINITY;
   const Vec lo{0.0f, -S.half_w, -S.half_l}, hi{S.depth, S.half_w, S.half_l};
   for (int p = 0; p < S.n_panels; ++p) {
-    const float *P = S.pose + 12 * p;
+    CFloat *P = (CFloat *)(S.pose + 12 * p);
     float te;
     if (ray_box(to_local(P, x), dir_to_local(P, d), lo, hi, te) && p != exclude && te < bt) {
       bt = te;
@@ -225,13 +228,14 @@ __device__ __forceinline__ int panel_search(const DevScene &S, Vec x, Vec d, int
 // Panel search for rings: every panel's axial axis is +z and all panels share
 // one axial range, so the axial slab is computed once for the ray and the
 // depth/tangential axes need only 2-D dot products (pose rows have zero z).
-__device__ __forceinline__ int panel_search_ring(const DevScene &S, Vec x, Vec d, int exclude, float &t_in) {
+template <class SC>
+__device__ __forceinline__ int panel_search_ring(SC &S, Vec x, Vec d, int exclude, float &t_in) {
   float tn_a = -INFINITY, tf_a = INFINITY;
-  slab_axis(x.z - S.pose[11], d.z, -S.half_l, S.half_l, tn_a, tf_a);
+  slab_axis(x.z - ((CFloat *)S.pose)[11], d.z, -S.half_l, S.half_l, tn_a, tf_a);
   int best = -1;
   float bt = INFINITY;
   for (int p = 0; p < S.n_panels; ++p) {
-    const float *P = S.pose + 12 * p;
+    CFloat *P = (CFloat *)(S.pose + 12 * p);
     float tn = tn_a, tf = tf_a;
     slab_axis(x.x * P[0] + x.y * P[1] - P[9], d.x * P[0] + d.y * P[1], 0.0f, S.depth, tn, tf);
     slab_axis(x.x * P[3] + x.y * P[4] - P[10], d.x * P[3] + d.y * P[4], -S.half_w, S.half_w, tn, tf);
@@ -245,7 +249,7 @@ __device__ __forceinline__ int panel_search_ring(const DevScene &S, Vec x, Vec d
   return best;
 }
 
-__device__ __forceinline__ int find_panel(const DevScene &S, Vec x, Vec d, int exclude, float &t_in) {
+template <class SC> __device__ __forceinline__ int find_panel(SC &S, Vec x, Vec d, int exclude, float &t_in) {
   return S.ring ? panel_search_ring(S, x, d, exclude, t_in) : panel_search(S, x, d, exclude, t_in);
 }
 
@@ -253,9 +257,11 @@ struct Loc {
   int mat, slot, module, layer, crystal, gid;
 };
 
+typedef __attribute__((address_space(4))) const DevScene CScene; // constant-address-space view
+
 // Hierarchical locate in panel p at local (depth, t, a): module grid, then
 // the layer selected by depth, then that layer's crystal array.
-__device__ __forceinline__ Loc locate(const DevScene &S, int p, Vec l) {
+template <class SC> __device__ __forceinline__ Loc locate(SC &S, int p, Vec l) {
   Loc r{S.fill, S.fill_slot, -1, -1, -1, -1};
   const float mt = floorf((l.y - S.mod_t0) * S.inv_step_t);
   const float ma = floorf((l.z - S.mod_a0) * S.inv_step_a);
@@ -270,7 +276,7 @@ __device__ __forceinline__ Loc locate(const DevScene &S, int p, Vec l) {
   for (int k = kMaxLayers - 1; k >= 0; --k)
     if (k < S.n_layers && l.x >= S.layer[k].d0 && l.x < S.layer[k].d1) L = k;
   if (L < 0) return r;
-  const LayerD &y = S.layer[L];
+  auto &y = S.layer[L];
   r.layer = L;
   r.mat = y.mat_interval;
   r.slot = y.slot_interval;
@@ -288,7 +294,7 @@ __device__ __forceinline__ Loc locate(const DevScene &S, int p, Vec l) {
 }
 
 // voxel index of a global point, -1 outside the phantom box
-__device__ __forceinline__ int voxel_of(const DevScene &S, Vec x) {
+template <class SC> __device__ __forceinline__ int voxel_of(SC &S, Vec x) {
   const float ix = floorf((x.x - S.ox) * S.ivx);
   const float iy = floorf((x.y - S.oy) * S.ivy);
   const float iz = floorf((x.z - S.oz) * S.ivz);

@@ -47,10 +47,10 @@ struct LaunchShape {
 };
 size_t transport_lds_bytes(int det_slots);
 
-// kernels (transport.hip)
-void launch_transport(const DevScene &S, const RunArgs &A, const LaunchShape &L, int n_cu,
-                      hipStream_t st);
-void launch_trace(const DevScene &S, const RunArgs &A, hipStream_t st);
+// kernels (transport.hip); det_slots is the largest detector material slot
+// count of the launch's scenes (it sizes the LDS tables)
+void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st);
+void launch_trace(const RunArgs &A, int det_slots, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
 void launch_philox(uint64_t seed, const uint32_t *ctr, uint32_t n, uint32_t *out, hipStream_t st);
 void launch_locate(const DevScene &S, uint32_t n, const float *xyz, int32_t *ids6, hipStream_t st);
@@ -64,25 +64,29 @@ void launch_rayleigh(uint32_t n, uint64_t seed, float *c, hipStream_t st);
 struct DigitizeScratch {
   void *buf = nullptr;
   size_t bytes = 0;
-  void *pinned = nullptr; // small pinned host buffer for count readbacks
+  void *pinned = nullptr; // pinned host words for count readbacks and table uploads
+  size_t pinned_bytes = 0;
 };
+// One digitizer pass over the hits of one or more instances.  Instance i owns
+// the event ids [first[i], first[i] + n_events[i]); its hits carry i in h_inst
+// (h_inst may be null when there is one instance).
 struct DigitizeArgs {
-  uint64_t n_hits;
-  const uint32_t *h_event, *h_gid, *h_aux;
-  const float *h_edep, *h_depth;
-  const unsigned long long *h_time;
-  uint32_t first_event;
-  uint64_t n_events;
-  int gid_bits, event_bits;
-  int crystals_per_panel, n_crystals;
-  float fwhm_511, e_lo, e_hi;
-  unsigned long long window_ps;
-  uint32_t k0, k1, instance;
-  float panel_depth;
+  uint64_t n_hits = 0;
+  const uint32_t *h_event = nullptr, *h_gid = nullptr, *h_aux = nullptr, *h_inst = nullptr;
+  const float *h_edep = nullptr, *h_depth = nullptr;
+  const unsigned long long *h_time = nullptr;
+  std::vector<uint32_t> first, n_events, cpp, rng; // per instance: range, crystals per panel, RNG id
+  std::vector<unsigned long long> duration;        // per instance acquisition length in ps (0: unknown)
+  int gid_bits = 1;
+  float fwhm_511 = 0.f, e_lo = 0.f, e_hi = 0.f;
+  unsigned long long window_ps = 0;
+  uint32_t k0 = 0, k1 = 0;
+  float panel_depth = 0.f;
   // outputs
-  gpet_singles *singles;
-  gpet_coincidences *coinc;
-  const gpet_tallies *tallies;
+  gpet_singles *singles = nullptr;
+  gpet_coincidences *coinc = nullptr;
+  const gpet_tallies *tallies = nullptr;
+  unsigned long long *coinc_per_inst = nullptr; // host, one count per instance (optional)
 };
 // returns GPET_OK or an error code; fills counts
 int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::string &err);
@@ -117,11 +121,39 @@ struct gpet_ctx {
   // device controls: [0] work (u32 x2), [1] hit count, [2..11] stats
   unsigned long long *d_ctrl = nullptr;
   unsigned long long *h_ctrl = nullptr; // pinned mirror of d_ctrl
+  // one-instance launch table of plain runs (scene + chunk table) and its
+  // pinned staging area
+  char *d_plain = nullptr, *h_plain = nullptr;
   gpet::DevScene scene{};
   gpet::LaunchShape shape{};
   gpet::DigitizeScratch scratch{};
+  // generations of the material list and phantom; a batch made from this
+  // context refuses to run once either changed (its scenes point at them)
+  uint64_t mat_gen = 0, phantom_gen = 0;
   // optional kernel timing
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float last_ms[2] = {0.f, 0.f};
+};
+
+// A batch of instances (scanner + source + event range + RNG id) transported
+// by one launch.  Device blob: DevScene[n], then the u32 tables chunk_prefix
+// (n + 1), first, count, id (n each), then the shared detector rows and
+// majorant, then per-instance poses and rods.
+struct gpet_batch {
+  gpet_ctx *ctx = nullptr;
+  int device = 0;
+  uint32_t n = 0;
+  std::vector<gpet_geometry_info> info;
+  std::vector<uint32_t> first, count, id, cpp;
+  std::vector<unsigned long long> duration;
+  uint64_t mat_gen = 0, phantom_gen = 0;
+  int det_slots = 0;
+  int gid_bits = 1;
+  uint64_t total_events = 0;
+  uint32_t chunk = 1024;
+  gpet::LaunchShape shape{};
+  char *d_blob = nullptr;
+  uint32_t *d_prefix = nullptr;
+  gpet::RunArgs base{}; // table pointers and controls; hits and seed set per call
 };

@@ -10,7 +10,10 @@
 // Every action that needs random numbers takes exactly one Philox block, drawn
 // at a single call site at the top of the trip, so the costliest primitive runs
 // once per trip with all its lanes together instead of once per divergent
-// branch.  Event ids are handed out per wave in chunks (one atomic per chunk);
+// branch.  The launch covers a table of instances (scanner + source; one for a
+// plain run, many for a batched sweep): waves claim chunks of consecutive events
+// of one instance with one atomic and switch instance only once drained, so the
+// scene stays wave-uniform (scalar loads).
 // hits are staged per wave in LDS and written out 64 at a time (one atomic and
 // coalesced stores per flush).  The detector attenuation rows and majorant are
 // staged in LDS at kernel start.
@@ -28,12 +31,12 @@ enum : int { V_STEP = 0, V_ENTER_PANEL = 1, V_EXIT = 2, V_ESCAPE = 3, V_DEAD = 4
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kStage = 128;       // staged hits per wave; flushed when 64 or more are pending
-constexpr uint32_t kChunk = 256;  // event ids taken by a wave per atomic
+constexpr int kStageBytes = 4 * 6 + 8; // event, gid, aux, instance, edep, depth, time
 
 // LDS bytes of one block for a scene with `slots` detector table rows
 size_t transport_lds_bytes(int slots) {
   return (size_t)slots * kTabStride * sizeof(float4) + kTabStride * sizeof(float) +
-         (size_t)kWaves * kStage * (4 * 5 + 8);
+         (size_t)kWaves * kStage * kStageBytes;
 }
 
 template <bool TRACE>
@@ -64,7 +67,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 // per-wave staging area of hits in LDS (structure of arrays)
 struct Stage {
-  uint32_t *ev, *gid, *aux;
+  uint32_t *ev, *gid, *aux, *inst;
   float *edep, *depth;
   unsigned long long *time;
 };
@@ -85,30 +88,35 @@ __device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, u
       A.h_depth[i] = st.depth[k];
       A.h_time[i] = st.time[k];
       A.h_aux[i] = st.aux[k];
+      if (A.h_inst) A.h_inst[i] = st.inst[k];
     }
   }
   wave_sync_lds();
 }
 
 template <bool TRACE>
-__global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
+__global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   extern __shared__ float4 lds4[];
   const int lane = (int)__lane_id();
   const int wave = (int)(threadIdx.x >> 6);
   const uint64_t below = __lanemask_lt();
 
-  // ---- stage the detector attenuation rows and majorant in LDS
+  // ---- the instances share their materials: stage instance 0's detector
+  //      attenuation rows and majorant in LDS
+  CScene *sp = (CScene *)A.scenes;
+  const int n_slots = sp->n_det_slots;
   float4 *s_mu = lds4;
-  float *s_maj = (float *)(lds4 + (size_t)S.n_det_slots * kTabStride);
-  for (int i = threadIdx.x; i < S.n_det_slots * kTabStride; i += kBlock) s_mu[i] = S.mu_det[i];
-  for (int i = threadIdx.x; i < kTabStride; i += kBlock) s_maj[i] = S.maj_det[i];
-  char *stage_base = (char *)(s_maj + kTabStride) + (size_t)wave * kStage * (4 * 5 + 8);
+  float *s_maj = (float *)(lds4 + (size_t)n_slots * kTabStride);
+  for (int i = threadIdx.x; i < n_slots * kTabStride; i += kBlock) s_mu[i] = sp->mu_det[i];
+  for (int i = threadIdx.x; i < kTabStride; i += kBlock) s_maj[i] = sp->maj_det[i];
+  char *stage_base = (char *)(s_maj + kTabStride) + (size_t)wave * kStage * kStageBytes;
   Stage st;
   st.time = (unsigned long long *)stage_base;
   st.ev = (uint32_t *)(st.time + kStage);
   st.gid = st.ev + kStage;
   st.aux = st.gid + kStage;
-  st.edep = (float *)(st.aux + kStage);
+  st.inst = st.aux + kStage;
+  st.edep = (float *)(st.inst + kStage);
   st.depth = st.edep + kStage;
   __syncthreads();
 
@@ -122,13 +130,16 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
   // pending interaction (or emission) state
   float q_u0 = 0.f, q_u1 = 0.f; // azimuth uniform of the pending scatter / rod uniforms
   int q_gid = -1, q_mat = -1, q_trials = 0, q_back = P_PANEL;
-  // wave-uniform bookkeeping
-  uint32_t chunk_next = 0, chunk_end = 0, staged = 0;
+  // wave-uniform bookkeeping: the instance the wave works on, its current
+  // range of event indices, a claimed next range, and the hit staging count
+  uint32_t inst = 0, inst_rng = A.inst_id[0];
+  uint32_t cur_next = 0, cur_end = 0, pend_inst = 0, pend_next = 0, pend_end = 0, staged = 0;
+  bool have_pend = false, exhausted = false;
   unsigned long long c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0,
                      c_blocks = 0, c_capped = 0, c_scatter = 0, c_trips = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
-  auto start_photon = [&](int which) {
+  auto start_photon = [&](CScene &S, int which) {
     ph = which;
     x = src;
     d = which ? Vec{-sdir.x, -sdir.y, -sdir.z} : sdir;
@@ -157,39 +168,68 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
   };
 
   for (;;) {
-    // ---- lanes without an event take the next ids from the wave's chunk
+    // ---- lanes without an event take the next ids: first from the current
+    //      range, then from a claimed range of the same instance; a range of
+    //      another instance is opened only once the wave has drained
     const bool need = phase == P_FETCH;
     const uint64_t m = __ballot(need);
     if (m) {
       const uint32_t k = (uint32_t)__popcll(m);
-      const uint32_t rank = (uint32_t)__popcll(m & below);
-      const uint32_t avail = chunk_end - chunk_next;
-      uint32_t fresh = 0;
-      if (k > avail) { // open a new chunk; the old one's remainder goes first
-        uint32_t b = 0;
-        if (lane == 0) b = atomicAdd(A.work, kChunk);
-        fresh = __builtin_amdgcn_readfirstlane(__shfl(b, 0));
-      }
-      if (need) {
-        const uint32_t idx = rank < avail ? chunk_next + rank : fresh + (rank - avail);
-        if (idx < A.n) {
-          ev = A.first + idx;
-          phase = P_EMIT_DIR;
-          n = 0;
-          sid = 0;
+      uint32_t avail = cur_end - cur_next;
+      if (k > avail && !have_pend && !exhausted) {
+        uint32_t c = 0;
+        if (lane == 0) c = atomicAdd(A.work, 1u);
+        c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));
+        if (c >= A.total_chunks) {
+          exhausted = true;
         } else {
-          phase = P_DONE;
+          uint32_t lo = 0, hi = A.n_inst; // owner: largest i with chunk_prefix[i] <= c
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A.chunk_prefix[mid] <= c) lo = mid;
+            else hi = mid;
+          }
+          const uint32_t b0 = (c - A.chunk_prefix[lo]) * A.chunk;
+          pend_inst = lo;
+          pend_next = b0;
+          pend_end = min(b0 + A.chunk, A.inst_count[lo]);
+          have_pend = true;
         }
       }
-      if (k > avail) {
-        chunk_next = fresh + (k - avail);
-        chunk_end = fresh + kChunk;
-      } else {
-        chunk_next += k;
+      if (have_pend && pend_inst != inst && __ballot(phase != P_FETCH && phase != P_DONE) == 0 && avail == 0) {
+        inst = pend_inst; // drained: switch the wave to the claimed instance
+        inst_rng = A.inst_id[inst];
+        sp = (CScene *)(A.scenes + inst);
+        cur_next = cur_end = pend_next;
+      }
+      const bool use_pend = have_pend && pend_inst == inst;
+      const uint32_t extra = use_pend ? pend_end - pend_next : 0u;
+      const uint32_t rank = (uint32_t)__popcll(m & below);
+      if (need) {
+        if (rank < avail) {
+          ev = A.inst_first[inst] + cur_next + rank;
+          phase = P_EMIT_DIR;
+        } else if (rank - avail < extra) {
+          ev = A.inst_first[inst] + pend_next + (rank - avail);
+          phase = P_EMIT_DIR;
+        } else if (exhausted && !have_pend) {
+          phase = P_DONE;
+        }
+        n = 0;
+        sid = 0;
+      }
+      const uint32_t take_cur = min(k, avail);
+      cur_next += take_cur;
+      if (use_pend) {
+        const uint32_t take_pend = min(k - take_cur, extra);
+        cur_next = pend_next + take_pend;
+        cur_end = pend_end;
+        have_pend = false;
       }
     }
     if (__ballot(phase != P_DONE) == 0) break;
     ++c_trips;
+    CScene &S = *sp;
 
     // ---- which lanes act this trip
     bool run;
@@ -198,9 +238,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
       // wait until at least `search_batch` lanes of the wave do, or nothing
       // else can run
       const uint64_t sm = __ballot(phase == P_SEARCH);
-      const uint64_t om = __ballot(phase != P_SEARCH && phase != P_DONE);
+      const uint64_t om = __ballot(phase != P_SEARCH && phase != P_DONE && phase != P_FETCH);
       const bool search_now = sm && ((uint32_t)__popcll(sm) >= A.search_batch || om == 0);
-      run = phase != P_DONE && (phase != P_SEARCH || search_now);
+      run = phase != P_DONE && phase != P_FETCH && (phase != P_SEARCH || search_now);
     } else {
       // only the phase held by the most lanes runs (ties to the later phase),
       // so each phase body executes with as many lanes as possible
@@ -221,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
     const bool draw = run && phase != P_SEARCH;
     uint4 w = make_uint4(0u, 0u, 0u, 0u);
     if (draw) {
-      w = philox(A.k0, A.k1, make_uint4(n, ev, A.instance, sid));
+      w = philox(A.k0, A.k1, make_uint4(n, ev, inst_rng, sid));
       ++n;
     }
     const float4 r = to_unit4(w);
@@ -234,7 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
          capped = false, emitted = false;
 
     if (!run) {
-      // waits for its phase to be scheduled
+      // waits for its phase to be scheduled (or for events)
     } else if (phase == P_EMIT_DIR) {
       // block 0 of the event stream: isotropic direction, two source uniforms
       const float ct = 2.0f * r.x - 1.0f, stt = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
@@ -262,7 +302,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
       // block 2: event time uniform on [0, T) from the raw 64-bit word
       t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
       emitted = true;
-      start_photon(0);
+      start_photon(S, 0);
     } else if (phase == P_PHANTOM) {
       const Lerp lp = lerp_at(e);
       const float mb = lerp1(S.maj_ph, lp);
@@ -317,7 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
         entered = true;
         vertex<TRACE>(A, ev, ph, V_ENTER_PANEL, 1, p, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         panel = p;
-        const float *P = S.pose + 12 * p;
+        CFloat *P = (CFloat *)(S.pose + 12 * p);
         x = to_local(P, x);
         d = dir_to_local(P, d);
         phase = P_PANEL;
@@ -330,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
       const Vec xn{x.x + s * d.x, x.y + s * d.y, x.z + s * d.z};
       if (!inside_panel(S, xn)) {
         vertex<TRACE>(A, ev, ph, V_EXIT, 1, panel, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
-        const float *P = S.pose + 12 * panel;
+        CFloat *P = (CFloat *)(S.pose + 12 * panel);
         x = to_global(P, x);
         d = dir_to_global(P, d);
         last = panel;
@@ -429,6 +469,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
         st.depth[k] = x.x;
         st.time[k] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
         st.aux[k] = (uint32_t)ph | ((uint32_t)h_proc << 1) | (seq << 8);
+        st.inst[k] = inst;
         ++seq;
       }
       staged += (uint32_t)__popcll(hm);
@@ -438,7 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
       }
     }
     if (ended) {
-      if (ph == 0) start_photon(1);
+      if (ph == 0) start_photon(S, 1);
       else phase = P_FETCH;
     }
   }
@@ -453,10 +494,10 @@ __global__ void __launch_bounds__(kBlock) k_transport(DevScene S, RunArgs A) {
   }
 }
 
-void launch_transport(const DevScene &S, const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st) {
+void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st) {
   // one resident wave set: as many blocks per CU as the kernel's registers and
   // LDS allow (unless the shape asks for a given number)
-  const size_t lds = transport_lds_bytes(S.n_det_slots);
+  const size_t lds = transport_lds_bytes(det_slots);
   int per_cu = L.blocks_per_cu;
   if (per_cu <= 0) {
     int occ = 0;
@@ -464,17 +505,16 @@ void launch_transport(const DevScene &S, const RunArgs &A, const LaunchShape &L,
       occ = 4;
     per_cu = occ;
   }
-  const uint64_t need = (A.n + kBlock - 1) / kBlock;
+  const uint64_t need = ((uint64_t)A.total_chunks * A.chunk + kBlock - 1) / kBlock;
   uint64_t grid = (uint64_t)n_cu * per_cu;
   if (need < grid) grid = need;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(kBlock), lds, st, S, A);
+  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(kBlock), lds, st, A);
 }
 
-void launch_trace(const DevScene &S, const RunArgs &A, hipStream_t st) {
+void launch_trace(const RunArgs &A, int det_slots, hipStream_t st) {
   const unsigned grid = (A.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_transport<true>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(S.n_det_slots),
-                     st, S, A);
+  hipLaunchKernelGGL(k_transport<true>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(det_slots), st, A);
 }
 
 // ---------------------------------------------------------------------------

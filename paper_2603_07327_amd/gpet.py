@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -78,7 +79,8 @@ class Source(C.Structure):
 
 class Hits(C.Structure):
     _fields_ = [("event", C.c_void_p), ("gid", C.c_void_p), ("edep_kev", C.c_void_p), ("depth_mm", C.c_void_p),
-                ("time_ps", C.c_void_p), ("aux", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_uint64)]
+                ("time_ps", C.c_void_p), ("aux", C.c_void_p), ("instance", C.c_void_p), ("capacity", C.c_uint64),
+                ("count", C.c_uint64)]
 
 
 class Stats(C.Structure):
@@ -94,7 +96,7 @@ class Digitizer(C.Structure):
 class Singles(C.Structure):
     _fields_ = [("event", C.c_void_p), ("gid", C.c_void_p), ("edep_kev", C.c_void_p), ("energy_kev", C.c_void_p),
                 ("depth_mm", C.c_void_p), ("time_ps", C.c_void_p), ("in_window", C.c_void_p),
-                ("capacity", C.c_uint64), ("count", C.c_uint64)]
+                ("instance", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_uint64)]
 
 
 class Coincidences(C.Structure):
@@ -106,11 +108,17 @@ class Tallies(C.Structure):
                 ("energy_spectrum", C.c_void_p), ("doi", C.c_void_p), ("doi_bins", C.c_int32)]
 
 
+class Instance(C.Structure):
+    _fields_ = [("scanner", C.POINTER(Scanner)), ("source", C.POINTER(Source)), ("first_event", C.c_uint64),
+                ("n_events", C.c_uint64), ("instance", C.c_uint32)]
+
+
 EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_set_stream", "gpet_materials_set",
            "gpet_geometry_create", "gpet_phantom_set", "gpet_source_set", "gpet_transport", "gpet_digitize",
            "gpet_philox", "gpet_tables_get", "gpet_locate", "gpet_ray_locate", "gpet_sample_compton",
            "gpet_sample_rayleigh", "gpet_trace", "gpet_ctx_enable_timing", "gpet_timings",
-           "gpet_ctx_set_launch")
+           "gpet_ctx_set_launch", "gpet_batch_create", "gpet_batch_destroy", "gpet_batch_info",
+           "gpet_batch_set_launch", "gpet_batch_transport", "gpet_batch_digitize", "gpet_batch_autotune")
 
 _lib = None
 
@@ -146,8 +154,16 @@ def load_library(path: str = LIB_PATH):
     L.gpet_ctx_enable_timing.argtypes = [vp, C.c_int]
     L.gpet_timings.argtypes = [vp, P(C.c_float)]
     L.gpet_ctx_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    L.gpet_batch_create.argtypes = [vp, C.c_int32, P(Instance), P(vp)]
+    L.gpet_batch_destroy.argtypes = [vp]
+    L.gpet_batch_destroy.restype = None
+    L.gpet_batch_info.argtypes = [vp, C.c_int32, P(GeometryInfo)]
+    L.gpet_batch_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_uint32]
+    L.gpet_batch_transport.argtypes = [vp, C.c_uint64, P(Hits), P(Stats)]
+    L.gpet_batch_digitize.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), vp]
+    L.gpet_batch_autotune.argtypes = [vp, C.c_uint64, P(Hits), C.c_char_p, C.c_size_t]
     for name in EXPORTS:
-        if name not in ("gpet_ctx_destroy", "gpet_last_error"):
+        if name not in ("gpet_ctx_destroy", "gpet_last_error", "gpet_batch_destroy"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -168,15 +184,24 @@ class HitList:
     count: int
     first_event: int
     n_events: int
+    instance: "torch.Tensor | None" = None
 
     def view(self):
         n = self.count
         return HitList(self.event[:n], self.gid[:n], self.edep_kev[:n], self.depth_mm[:n], self.time_ps[:n],
-                       self.aux[:n], n, self.first_event, self.n_events)
+                       self.aux[:n], n, self.first_event, self.n_events,
+                       None if self.instance is None else self.instance[:n])
 
     def numpy(self):
         v = self.view()
-        return {k: getattr(v, k).cpu().numpy() for k in ("event", "gid", "edep_kev", "depth_mm", "time_ps", "aux")}
+        keys = ("event", "gid", "edep_kev", "depth_mm", "time_ps", "aux") + (("instance",) if v.instance is not None
+                                                                            else ())
+        return {k: getattr(v, k).cpu().numpy() for k in keys}
+
+    def struct(self):
+        return Hits(self.event.data_ptr(), self.gid.data_ptr(), self.edep_kev.data_ptr(), self.depth_mm.data_ptr(),
+                    self.time_ps.data_ptr(), self.aux.data_ptr(),
+                    self.instance.data_ptr() if self.instance is not None else None, self.event.numel(), self.count)
 
 
 @dataclass
@@ -189,11 +214,72 @@ class SingleList:
     time_ps: "torch.Tensor"
     in_window: "torch.Tensor"
     count: int
+    instance: "torch.Tensor | None" = None
 
     def numpy(self):
         n = self.count
-        return {k: getattr(self, k)[:n].cpu().numpy() for k in
-                ("event", "gid", "edep_kev", "energy_kev", "depth_mm", "time_ps", "in_window")}
+        keys = ("event", "gid", "edep_kev", "energy_kev", "depth_mm", "time_ps", "in_window")
+        keys += ("instance",) if self.instance is not None else ()
+        return {k: getattr(self, k)[:n].cpu().numpy() for k in keys}
+
+    def struct(self):
+        return Singles(*(getattr(self, k).data_ptr() for k in
+                         ("event", "gid", "edep_kev", "energy_kev", "depth_mm", "time_ps", "in_window")),
+                       self.instance.data_ptr() if self.instance is not None else None, self.event.numel(), 0)
+
+
+def pack_materials(mats, ph):
+    arr = (Material * len(mats))()
+    for i, m in enumerate(mats):
+        q = arr[i]
+        q.density_g_cm3 = m["density"]
+        q.n_elements = len(m["Z"])
+        q.processes = m["mask"]
+        for j, (z, a, w) in enumerate(zip(m["Z"], m["A"], m["w"])):
+            q.Z[j], q.A[j], q.mass_fraction[j] = z, a, w
+    return arr, Physics(ph["k_pe"], ph["k_r"], ph["e_cut"])
+
+
+def pack_scanner(g: dict):
+    """Scanner struct of a scanner description, and the array its poses point into."""
+    s = Scanner()
+    s.placement = PLACE_EXPLICIT if g["mode"] == "explicit" else PLACE_REPEAT
+    s.n_panels = g["n_panels"]
+    s.radius_mm, s.phi0_rad, s.z0_mm = g["radius"], g["phi0"], g["z0"]
+    keep = None
+    if g["poses"] is not None:
+        keep = np.ascontiguousarray(g["poses"], np.float64)
+        s.poses = keep.ctypes.data_as(C.POINTER(C.c_double))
+    s.depth_mm, s.width_mm, s.length_mm = g["depth"], g["width"], g["length"]
+    s.mod_n_t, s.mod_n_a = g["mod_n_t"], g["mod_n_a"]
+    s.mod_t_mm, s.mod_a_mm, s.gap_t_mm, s.gap_a_mm = g["mod_t"], g["mod_a"], g["gap_t"], g["gap_a"]
+    s.fill_material = g["mat_fill"]
+    s.n_layers = len(g["layers"])
+    for i, y in enumerate(g["layers"]):
+        L = s.layers[i]
+        L.depth0_mm, L.thickness_mm = y["depth0"], y["thick"]
+        L.n_t, L.n_a = y["n_t"], y["n_a"]
+        L.cryst_t_mm, L.cryst_a_mm = y["cryst_t"], y["cryst_a"]
+        L.pitch_t_mm, L.pitch_a_mm = y["pitch_t"], y["pitch_a"]
+        L.offset_t_mm, L.offset_a_mm = y["off_t"], y["off_a"]
+        L.crystal_material, L.interval_material = y["mat_crystal"], y["mat_interval"]
+    return s, keep
+
+
+def pack_source(src: dict):
+    """Source struct of a source description, and the array its rods point into."""
+    s = Source()
+    s.kind = src["kind"]
+    for k in range(3):
+        s.pos_mm[k] = src["pos"][k]
+        s.dir[k] = src["dir"][k]
+    keep = None
+    if src["rods"] is not None:
+        keep = np.ascontiguousarray(src["rods"], np.float64)
+        s.n_rods = len(keep)
+        s.rods = keep.ctypes.data_as(C.POINTER(C.c_double))
+    s.duration_ps = int(src["duration_ps"])
+    return s, keep
 
 
 class Context:
@@ -212,8 +298,12 @@ class Context:
         self.h = h
         self.info = None
         self.scene = None
+        self._batches = weakref.WeakSet()
 
     def close(self):
+        """Destroys the context (and first every batch made from it)."""
+        for b in list(getattr(self, "_batches", ())):
+            b.close()
         if getattr(self, "h", None):
             self.L.gpet_ctx_destroy(self.h)
             self.h = None
@@ -247,46 +337,20 @@ class Context:
     # ------------------------------------------------------------------ scene
     def set_scene(self, sc: dict):
         """Materials, scanner, phantom and source from a scene description."""
-        mats = sc["materials"]
-        arr = (Material * len(mats))()
-        for i, m in enumerate(mats):
-            q = arr[i]
-            q.density_g_cm3 = m["density"]
-            q.n_elements = len(m["Z"])
-            q.processes = m["mask"]
-            for j, (z, a, w) in enumerate(zip(m["Z"], m["A"], m["w"])):
-                q.Z[j], q.A[j], q.mass_fraction[j] = z, a, w
-        ph = sc["physics"]
-        phys = Physics(ph["k_pe"], ph["k_r"], ph["e_cut"])
-        self._check(self.L.gpet_materials_set(self.h, len(mats), arr, C.byref(phys)))
+        self.set_materials(sc["materials"], sc["physics"])
         self.set_scanner(sc["scanner"])
         self.set_phantom(sc.get("phantom"))
         self.set_source(sc["source"])
         self.scene = sc
         return self.info
 
+    def set_materials(self, mats, physics):
+        arr, phys = pack_materials(mats, physics)
+        self._check(self.L.gpet_materials_set(self.h, len(mats), arr, C.byref(phys)))
+        self.n_mat = len(mats)
+
     def set_scanner(self, g: dict):
-        s = Scanner()
-        s.placement = PLACE_EXPLICIT if g["mode"] == "explicit" else PLACE_REPEAT
-        s.n_panels = g["n_panels"]
-        s.radius_mm, s.phi0_rad, s.z0_mm = g["radius"], g["phi0"], g["z0"]
-        keep = None
-        if g["poses"] is not None:
-            keep = np.ascontiguousarray(g["poses"], np.float64)
-            s.poses = keep.ctypes.data_as(C.POINTER(C.c_double))
-        s.depth_mm, s.width_mm, s.length_mm = g["depth"], g["width"], g["length"]
-        s.mod_n_t, s.mod_n_a = g["mod_n_t"], g["mod_n_a"]
-        s.mod_t_mm, s.mod_a_mm, s.gap_t_mm, s.gap_a_mm = g["mod_t"], g["mod_a"], g["gap_t"], g["gap_a"]
-        s.fill_material = g["mat_fill"]
-        s.n_layers = len(g["layers"])
-        for i, y in enumerate(g["layers"]):
-            L = s.layers[i]
-            L.depth0_mm, L.thickness_mm = y["depth0"], y["thick"]
-            L.n_t, L.n_a = y["n_t"], y["n_a"]
-            L.cryst_t_mm, L.cryst_a_mm = y["cryst_t"], y["cryst_a"]
-            L.pitch_t_mm, L.pitch_a_mm = y["pitch_t"], y["pitch_a"]
-            L.offset_t_mm, L.offset_a_mm = y["off_t"], y["off_a"]
-            L.crystal_material, L.interval_material = y["mat_crystal"], y["mat_interval"]
+        s, keep = pack_scanner(g)
         info = GeometryInfo()
         self._check(self.L.gpet_geometry_create(self.h, C.byref(s), C.byref(info)))
         del keep
@@ -309,30 +373,22 @@ class Context:
         self._check(self.L.gpet_phantom_set(self.h, C.byref(ph)))
 
     def set_source(self, src: dict):
-        s = Source()
-        s.kind = src["kind"]
-        for k in range(3):
-            s.pos_mm[k] = src["pos"][k]
-            s.dir[k] = src["dir"][k]
-        keep = None
-        if src["rods"] is not None:
-            keep = np.ascontiguousarray(src["rods"], np.float64)
-            s.n_rods = len(keep)
-            s.rods = keep.ctypes.data_as(C.POINTER(C.c_double))
-        s.duration_ps = int(src["duration_ps"])
+        s, keep = pack_source(src)
         self._check(self.L.gpet_source_set(self.h, C.byref(s)))
+        del keep
 
     # -------------------------------------------------------------- transport
-    def alloc_hits(self, capacity: int, first_event=0, n_events=0) -> HitList:
+    def alloc_hits(self, capacity: int, first_event=0, n_events=0, instance=False) -> HitList:
         t = self.torch
         return HitList(self._empty(capacity, t.int32), self._empty(capacity, t.int32),
                        self._empty(capacity, t.float32), self._empty(capacity, t.float32),
-                       self._empty(capacity, t.int64), self._empty(capacity, t.int32), 0, first_event, n_events)
+                       self._empty(capacity, t.int64), self._empty(capacity, t.int32), 0, first_event, n_events,
+                       self._empty(capacity, t.int32) if instance else None)
 
     def transport_into(self, hits: HitList, n_events, seed=0, first=0, instance=0):
         """Transport into preallocated hits; returns (status, stats dict)."""
-        h = Hits(hits.event.data_ptr(), hits.gid.data_ptr(), hits.edep_kev.data_ptr(), hits.depth_mm.data_ptr(),
-                 hits.time_ps.data_ptr(), hits.aux.data_ptr(), hits.event.numel(), 0)
+        h = hits.struct()
+        h.count = 0
         st = Stats()
         rc = self.L.gpet_transport(self.h, first, n_events, seed, instance, C.byref(h), C.byref(st))
         hits.count = int(h.count)
@@ -352,21 +408,19 @@ class Context:
         return hits, stats
 
     # -------------------------------------------------------------- digitizer
-    def alloc_singles(self, capacity) -> SingleList:
+    def alloc_singles(self, capacity, instance=False) -> SingleList:
         t = self.torch
         return SingleList(self._empty(capacity, t.int32), self._empty(capacity, t.int32),
                           self._empty(capacity, t.float32), self._empty(capacity, t.float32),
                           self._empty(capacity, t.float32), self._empty(capacity, t.int64),
-                          self._empty(capacity, t.int32), 0)
+                          self._empty(capacity, t.int32), 0,
+                          self._empty(capacity, t.int32) if instance else None)
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
                       e_hi=650.0, window_ps=3000, instance=0, tallies=None):
-        h = Hits(hits.event.data_ptr(), hits.gid.data_ptr(), hits.edep_kev.data_ptr(), hits.depth_mm.data_ptr(),
-                 hits.time_ps.data_ptr(), hits.aux.data_ptr(), hits.event.numel(), hits.count)
+        h = hits.struct()
         dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, hits.first_event, max(1, hits.n_events))
-        s = Singles(*(getattr(singles, k).data_ptr() for k in
-                      ("event", "gid", "edep_kev", "energy_kev", "depth_mm", "time_ps", "in_window")),
-                    singles.event.numel(), 0)
+        s = singles.struct()
         cc = Coincidences(coinc[0].data_ptr(), coinc[1].data_ptr(), coinc[0].numel(), 0)
         tl = None
         if tallies is not None:
@@ -465,3 +519,123 @@ class Context:
         for k, n in enumerate(names_f):
             out[n] = flts[:, k]
         return out
+
+
+class Batch:
+    """A table of instances (scanner, source, event range, RNG instance id)
+    transported by one persistent launch and digitized in one pass.  The
+    instances share the context's materials and phantom."""
+
+    def __init__(self, ctx: Context, instances):
+        """instances: dicts with keys scanner, source, n_events and optionally
+        first_event (0) and instance (the RNG id; default: the list index)."""
+        self.ctx, self.L = ctx, ctx.L
+        self.n = len(instances)
+        arr = (Instance * self.n)()
+        keep = []
+        for i, d in enumerate(instances):
+            sc, k1 = pack_scanner(d["scanner"])
+            so, k2 = pack_source(d["source"])
+            keep += [sc, so, k1, k2]
+            arr[i].scanner = C.pointer(sc)
+            arr[i].source = C.pointer(so)
+            arr[i].first_event = int(d.get("first_event", 0))
+            arr[i].n_events = int(d["n_events"])
+            arr[i].instance = int(d.get("instance", i))
+        h = C.c_void_p()
+        ctx._check(self.L.gpet_batch_create(ctx.h, self.n, arr, C.byref(h)), "batch")
+        del keep
+        self.h = h
+        ctx._batches.add(self)
+        self.first = np.array([int(d.get("first_event", 0)) for d in instances], np.int64)
+        self.n_events = np.array([int(d["n_events"]) for d in instances], np.int64)
+        self.ids = np.array([int(d.get("instance", i)) for i, d in enumerate(instances)], np.int64)
+        self.infos = []
+        for i in range(self.n):
+            info = GeometryInfo()
+            ctx._check(self.L.gpet_batch_info(self.h, i, C.byref(info)))
+            self.infos.append(info)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gpet_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, blocks_per_cu=0, search_batch=48, chunk=1024):
+        self.ctx._check(self.L.gpet_batch_set_launch(self.h, blocks_per_cu, search_batch, chunk))
+
+    def alloc_hits(self, capacity):
+        return self.ctx.alloc_hits(capacity, 0, int(self.n_events.sum()), instance=True)
+
+    def transport_into(self, hits: HitList, seed=0):
+        h = hits.struct()
+        h.count = 0
+        st = Stats()
+        rc = self.L.gpet_batch_transport(self.h, seed, C.byref(h), C.byref(st))
+        hits.count = int(h.count)
+        if rc not in (OK, ERR_CAPACITY):
+            self.ctx._check(rc)
+        return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}
+
+    def transport(self, seed=0, capacity=None):
+        cap = capacity or max(1024, int(3.5 * self.n_events.sum()))
+        hits = self.alloc_hits(cap)
+        rc, stats = self.transport_into(hits, seed)
+        if rc == ERR_CAPACITY:
+            hits = self.alloc_hits(hits.count)
+            rc, stats = self.transport_into(hits, seed)
+            self.ctx._check(rc)
+        return hits, stats
+
+    def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
+                      e_hi=650.0, window_ps=3000):
+        """Returns (status, coincidence count, coincidences per instance)."""
+        h = hits.struct()
+        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, 0, 0, 1)
+        s = singles.struct()
+        cc = Coincidences(coinc[0].data_ptr(), coinc[1].data_ptr(), coinc[0].numel(), 0)
+        per = np.zeros(self.n, np.uint64)
+        rc = self.L.gpet_batch_digitize(self.h, C.byref(h), C.byref(dg), C.byref(s), C.byref(cc),
+                                        per.ctypes.data_as(C.c_void_p))
+        singles.count = int(s.count)
+        if rc not in (OK, ERR_CAPACITY):
+            self.ctx._check(rc)
+        return rc, int(cc.count), per.astype(np.int64)
+
+    def digitize(self, hits: HitList, seed=0, **kw):
+        t = self.ctx.torch
+        cap = max(1024, hits.count)
+        singles = self.ctx.alloc_singles(cap, instance=True)
+        coinc = (self.ctx._empty(cap // 2 + 16, t.int32), self.ctx._empty(cap // 2 + 16, t.int32))
+        rc, nc, per = self.digitize_into(hits, singles, coinc, seed=seed, **kw)
+        self.ctx._check(rc)
+        return singles, (coinc[0][:nc], coinc[1][:nc]), per
+
+    def autotune(self, hits: HitList, seed=0, cache_path=None, key=None):
+        """Launch shape and chunk size for this batch: read from the JSON cache
+        under `key` if present, else measured by the library's autotuner (and
+        stored).  Returns the chosen settings as a dict."""
+        import json
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if key is not None and key in cache:
+            r = cache[key]
+            self.set_launch(r["blocks_per_cu"], r["search_batch"], r["chunk"])
+            return r
+        buf = C.create_string_buffer(1 << 14)
+        h = hits.struct()
+        self.ctx._check(self.L.gpet_batch_autotune(self.h, seed, C.byref(h), buf, len(buf)))
+        r = json.loads(buf.value.decode())
+        if cache_path and key is not None:
+            cache[key] = r
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1)
+        return r
