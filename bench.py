@@ -199,6 +199,122 @@ def batched_form(args):
             "stats_last": st_b}
 
 
+SURROGATE_FLOP_PER_ENTRY = 2 * (6 * 256 + 3 * 256 * 256 + 256 * 1851)  # forward pass, 6 -> 4 x 256 -> 1851
+
+
+def surrogate_form(args):
+    """The hot-rod phantom workload (design C, water cylinder, six-sector rods)
+    timed with full transport and with the detector-response surrogate, both
+    followed by the full digitizer.  The network (6 -> 4 x 256 -> 1851) is
+    first trained on pairs recorded from separate runs (seed 7); the timed runs
+    use seed 0.  Reported: events/s of both forms, their sensitivities and
+    per-crystal in-window singles chi-square, the share of photons the
+    network took over, training cost, and the network's matrix-core rate."""
+    import torch
+    from scipy import stats as sps
+
+    from paper_2603_07327_amd.gpet import Context, Mlp, pack_params
+
+    n = args.surrogate_events
+    sc = G.hot_rod_scene(n_events=n)
+    ctx = Context(0)
+    ctx.set_scene(sc)
+    ctx.enable_timing(True)
+    # ---- training pairs (seed 7), in slices
+    slice_ev = 20_000_000
+    hits = ctx.alloc_hits(int(3.0 * slice_ev))
+    xs, ys = [], []
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.surrogate_train_events:
+        m = min(slice_ev, args.surrogate_train_events - done)
+        pairs = ctx.alloc_pairs(2 * m)
+        rc, _ = ctx.surrogate_pairs_into(hits, pairs, m, seed=7, first=done)
+        if rc != 0:
+            raise RuntimeError("pair generation: capacity")
+        k = pairs["count"]
+        xs.append(pairs["x"][: 6 * k].view(k, 6).clone())
+        ys.append(pairs["label"][:k].clone())
+        del pairs
+        done += m
+    x = torch.cat(xs)
+    y = torch.cat(ys)
+    del xs, ys
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    sizes = [6, *G.SURROGATE_HIDDEN, 1851]
+    net = Mlp(ctx, sizes, pack_params(G.mlp_init(sizes, seed=1)))
+    t0 = time.perf_counter()
+    losses = net.train(x, y, steps=args.surrogate_steps, batch=8192, lr=1e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_pairs = int(y.numel())
+    ce_marg = None
+    counts = torch.bincount(y.long(), minlength=1851).double().cpu().numpy()
+    p = (counts + 0.5) / (counts.sum() + 0.5 * 1851)
+    ce_marg = float(-(counts * np.log(p)).sum() / counts.sum())
+    del x, y, hits
+    torch.cuda.empty_cache()
+
+    # ---- timed runs: plain and surrogate, each followed by the digitizer
+    hits = ctx.alloc_hits(int(3.2 * n))
+    singles = ctx.alloc_singles(int(2.2 * n))
+    coinc = (ctx._empty(n, torch.int32), ctx._empty(n, torch.int32))
+
+    def run(mode, seed):
+        if mode == "plain":
+            rc, st = ctx.transport_into(hits, n, seed=seed)
+            sst = None
+        else:
+            rc, st, sst = ctx.surrogate_transport_into(net, hits, n, seed=seed)
+        if rc != 0:
+            raise RuntimeError(f"{mode}: hit capacity")
+        rc, nc = ctx.digitize_into(hits, singles, coinc, seed=seed)
+        if rc != 0:
+            raise RuntimeError(f"{mode}: digitizer capacity")
+        return nc, st, sst
+
+    out = {}
+    hist = {}
+    for mode in ("plain", "surrogate"):
+        run(mode, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nc, st, sst = run(mode, 0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = singles.numpy()
+        hist[mode] = np.bincount(s["gid"][s["in_window"] != 0], minlength=ctx.info.n_crystals)
+        out[mode] = {"value": n / dt, "ms": dt * 1e3, "coincidences": nc, "sensitivity": nc / n,
+                     "transport_kernel_ms": ctx.timings()[0]}
+        if sst is not None:
+            out[mode].update({"entries": sst["entries"], "photons_on_network": sst["entries"] / (2.0 * n),
+                              "none_fraction": sst["none"] / max(1, sst["entries"]),
+                              "transport_ms": sst["ms_transport"], "network_ms": sst["ms_network"]})
+            achieved = sst["entries"] * SURROGATE_FLOP_PER_ENTRY / (sst["ms_network"] * 1e-3)
+            out[mode]["network_roofline"] = {"bound": "mfma", "achieved": achieved / 1e12, "peak": 2500.0,
+                                             "unit": "TFLOP/s", "frac": achieved / 2.5e15,
+                                             "flop_per_entry": SURROGATE_FLOP_PER_ENTRY}
+    a, b = hist["plain"], hist["surrogate"]
+    keep = (a + b) >= 10
+    ka, kb = a[keep].astype(float), b[keep].astype(float)
+    na, nb = ka.sum(), kb.sum()
+    chi2 = float((((np.sqrt(nb / na) * ka - np.sqrt(na / nb) * kb) ** 2) / (ka + kb)).sum())
+    dof = int(keep.sum()) - 1
+    net.close()
+    ctx.close()
+    return {"workload": f"hot-rod phantom: design C, water cylinder 25 x 70 mm (0.5 mm voxels), six-sector rods, "
+                        f"{n:.0e} events, transport + digitizer",
+            "plain": out["plain"], "surrogate": out["surrogate"],
+            "speedup_vs_plain": out["surrogate"]["value"] / out["plain"]["value"],
+            "sensitivity_rel_diff": out["surrogate"]["sensitivity"] / out["plain"]["sensitivity"] - 1.0,
+            "singles_chi2": {"chi2": chi2, "dof": dof, "p": float(sps.chi2.sf(chi2, dof))},
+            "training": {"pairs": n_pairs, "events": args.surrogate_train_events, "pair_gen_s": t_pairs,
+                         "steps": args.surrogate_steps, "batch": 8192, "train_s": t_train,
+                         "loss_first": float(losses[0]), "loss_last100": float(np.mean(losses[-100:])),
+                         "marginal_ce": ce_marg}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +330,11 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="event-count scale of the batched design sweep (0 skips it)")
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner")
+    ap.add_argument("--surrogate-events", type=int, default=100_000_000,
+                    help="events of the hot-rod phantom workload timed plain and with the surrogate (0 skips)")
+    ap.add_argument("--surrogate-train-events", type=int, default=100_000_000,
+                    help="events whose detector entries make the training pairs")
+    ap.add_argument("--surrogate-steps", type=int, default=6000, help="Adam steps of batch 8192")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the event-parallel sharding "
@@ -295,6 +416,8 @@ def main():
     del ctxs
     if args.batched_scale > 0:
         line["batched"] = batched_form(args)
+    if args.surrogate_events > 0:
+        line["surrogate"] = surrogate_form(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

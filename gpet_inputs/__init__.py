@@ -354,3 +354,20 @@ def batch_sweep(n_scale=1.0, seed=0, n_lo=1e5, n_hi=1e7):
                                 "label": f"t{t:g}_o{o:g}_g{g:g}_x{x:g}"})
                     i += 1
     return mats, physics(rayleigh=True), out
+
+
+SURROGATE_HIDDEN = (256, 256, 256, 256)
+
+
+def mlp_init(sizes, seed=0):
+    """Initial MLP parameters: He-normal weights (std sqrt(2 / fan_in)) on the
+    hidden layers, std sqrt(1 / fan_in) / 4 on the output layer, zero biases;
+    numpy PCG64 stream of `seed`.  Returns [(W [out, in], b [out]), ...] as
+    float32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    n = len(sizes) - 1
+    for k, (i, j) in enumerate(zip(sizes[:-1], sizes[1:])):
+        std = math.sqrt(2.0 / i) if k < n - 1 else 0.25 * math.sqrt(1.0 / i)
+        out.append((rng.normal(0.0, std, (j, i)).astype(np.float32), np.zeros(j, np.float32)))
+    return out

@@ -337,6 +337,114 @@ gpet_status gpet_batch_digitize(gpet_batch *batch, const gpet_hits *hits, const 
  * (NUL-terminated, truncated to cap bytes; may be NULL). */
 gpet_status gpet_batch_autotune(gpet_batch *batch, uint64_t seed, gpet_hits *hits, char *json, size_t cap);
 
+/* ---------------------------------------------------------------------- */
+/* Surrogate network: a ReLU MLP (widths sizes[0] -> ... -> sizes[n-1]) with  */
+/* BF16 weights and activations on the matrix cores, FP32 accumulation,     */
+/* softmax cross-entropy over sizes[n-1] classes and Adam on FP32 master     */
+/* weights.  Packed parameter layout (host float32): per layer l, W_l        */
+/* [sizes[l+1]][sizes[l]] row-major, then b_l [sizes[l+1]].                  */
+/* ---------------------------------------------------------------------- */
+typedef struct gpet_mlp gpet_mlp;
+
+typedef struct {
+  uint32_t batch;       /* rows per step, drawn uniformly with replacement */
+  uint32_t steps;
+  double lr, beta1, beta2, eps; /* Adam (Kingma and Ba) */
+  uint64_t seed;        /* key of the batch-index stream */
+} gpet_train_params;
+
+/* sizes: n_sizes (2..16) widths, input 1..256, others 1..8192; weights: packed
+ * host initial values (NULL: zeros).  The network keeps a pointer to ctx and
+ * uses its stream. */
+gpet_status gpet_mlp_create(gpet_ctx *ctx, int32_t n_sizes, const int32_t *sizes, const float *weights,
+                            gpet_mlp **out);
+void gpet_mlp_destroy(gpet_mlp *mlp);
+/* Replaces the master weights (host, packed) and clears the Adam state. */
+gpet_status gpet_mlp_set_weights(gpet_mlp *mlp, const float *weights);
+gpet_status gpet_mlp_get_weights(gpet_mlp *mlp, float *weights);
+/* Logits (device, n x classes, FP32) of device inputs x (n x sizes[0], FP32;
+ * rounded to BF16 on entry). */
+gpet_status gpet_mlp_forward(gpet_mlp *mlp, uint32_t n, const float *x, float *logits);
+/* Mean cross-entropy of (x, y) (device; labels in [0, classes)) and its
+ * gradient with respect to the packed parameters (host, float32). */
+gpet_status gpet_mlp_loss_grad(gpet_mlp *mlp, uint32_t n, const float *x, const int32_t *y, double *loss,
+                               float *grad);
+/* `steps` Adam steps on mini-batches of (x, y) (device, n_pairs rows); the
+ * mean loss of every step's batch (before its update) goes to loss_per_step
+ * (host, steps entries; may be NULL).  Batch row r of step t is pair
+ * floor(w n_pairs / 2^32), w = word r % 4 of Philox(seed; t, r / 4, 0, 9),
+ * t counting the network's Adam steps from 1. */
+gpet_status gpet_mlp_train(gpet_mlp *mlp, uint64_t n_pairs, const float *x, const int32_t *y,
+                           const gpet_train_params *params, float *loss_per_step);
+
+/* ---------------------------------------------------------------------- */
+/* Detector-response surrogate.  A photon entering its first panel through  */
+/* the front face, inside the domain below, can be handed to the network   */
+/* instead of being transported through the panel.                          */
+/*                                                                          */
+/* Domain (decided from the entry state only): energy >= e_min_kev; entry   */
+/* depth coordinate within front_tol_mm of the front face; |d_t / d_depth|  */
+/* and |d_a / d_depth| <= max_slope; the straight line's point at mid-depth */
+/* inside a module; every layer's neighbourhood of (2 half_width + 1)^2     */
+/* crystals around its anchor inside that layer's crystal array.  Anchor:   */
+/* the last layer's crystal whose pitch cell holds the mid-depth point; in   */
+/* another layer, the crystal whose cell holds that cell's centre (a centre */
+/* on a cell boundary goes to the upper cell).                               */
+/* Features x[6]: 2 f_t - 1, 2 f_a - 1 (f: position of the mid-depth point  */
+/* in the anchor cell), the two slopes over max_slope, 2 (E - e_min) /      */
+/* (511 - e_min) - 1, and the depth component of the direction.             */
+/* Classes: 0 = no crystal of the panel stay collects e_min_kev or more, or  */
+/* the largest sum lies outside the neighbourhood; else 1 + ((layer W + i) W */
+/* + j) (n_ebins + 1) + bin for the crystal with the largest deposit sum    */
+/* (ties: lower gid), (i, j) its offset + half_width from the anchor,       */
+/* W = 2 half_width + 1, bin = n_ebins when the sum is within               */
+/* photopeak_tol_kev of the entry energy, else floor((sum - e_min) / ebin)  */
+/* clipped to [0, n_ebins - 1].  A class stands for one single: the entry   */
+/* energy (photopeak) or e_min + ebin (bin + u) deposited at the layer's    */
+/* mid-depth in that crystal, at the entry time.                            */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t half_width;  /* 0..7 */
+  int32_t n_ebins;     /* 1..1024 */
+  double e_min_kev, ebin_kev, photopeak_tol_kev, max_slope, front_tol_mm;
+} gpet_surrogate_spec;
+
+/* Training pairs (device SoA): features x[6 per pair], class label, event
+ * id, flags (bit 0: the largest deposit lay outside the neighbourhood; bit 1:
+ * the photon touched more than 8 crystals, only the first 8 were summed;
+ * bit 2: photon B). */
+typedef struct {
+  float *x;
+  int32_t *label;
+  uint32_t *event;
+  uint32_t *flags;
+  uint64_t capacity;
+  uint64_t count; /* out */
+} gpet_pairs;
+
+typedef struct {
+  uint64_t entries;          /* photons handed to the network */
+  uint64_t none;             /* of them, sampled class 0 (no single) */
+  float ms_transport, ms_network;
+} gpet_surrogate_stats;
+
+/* Full transport of events [first_event, first_event + n_events) (hits as
+ * gpet_transport) that also records one pair per photon entering its first
+ * panel inside the domain, labelled from that photon's deposits in the
+ * panel.  Pair order is unspecified; GPET_ERR_CAPACITY if pairs overflow. */
+gpet_status gpet_surrogate_pairs(gpet_ctx *ctx, const gpet_surrogate_spec *spec, uint64_t first_event,
+                                 uint64_t n_events, uint64_t seed, uint32_t instance, gpet_hits *hits,
+                                 gpet_pairs *pairs, gpet_stats *stats);
+/* Transport with the surrogate: in-domain photons end at their first panel
+ * entry and the network samples their single (Philox counter (0, event,
+ * instance, 4 + photon): word 0 the class, word 1 the energy in its bin);
+ * every other photon is transported in full.  The network must map 6
+ * features to the spec's class count for this scanner.  Hits as
+ * gpet_transport (surrogate singles carry process 3 in aux). */
+gpet_status gpet_surrogate_transport(gpet_ctx *ctx, gpet_mlp *mlp, const gpet_surrogate_spec *spec,
+                                     uint64_t first_event, uint64_t n_events, uint64_t seed, uint32_t instance,
+                                     gpet_hits *hits, gpet_stats *stats, gpet_surrogate_stats *sstats);
+
 /* Launch shape of the transport kernel: blocks of 256 lanes per compute unit
  * (0 = as many as fit); the scheduling of lane actions within a wavefront
  * (0: every pending action runs each loop trip, with panel searches held until

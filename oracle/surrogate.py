@@ -115,7 +115,8 @@ def entry_state(spec: Spec, lat: Lattice, xl, dl, e) -> Entry:
     module, and for every layer the neighbourhood around the anchor crystal
     lies inside that layer's crystal array.  The anchor: the crystal of the
     last layer whose pitch cell holds the mid-depth point; for another layer,
-    its crystal whose cell holds the centre of that cell.
+    its crystal whose cell holds the centre of that cell (a centre on a cell
+    boundary goes to the upper cell).
     Features: the mid-depth point's position in the anchor cell (scaled to
     [-1, 1)), the two slopes over max_slope, the energy scaled to [-1, 1] over
     [e_min, 511], and the depth component of the direction."""
@@ -140,8 +141,10 @@ def entry_state(spec: Spec, lat: Lattice, xl, dl, e) -> Entry:
     h = spec.half_width
     anchor = []
     for y in lat.layers:
-        jt = math.floor((ct - y["off_t"]) / y["pitch_t"])
-        ja = math.floor((ca - y["off_a"]) / y["pitch_a"])
+        # a cell centre on a crystal boundary of another layer (offset of half
+        # a pitch) belongs to the upper crystal: nudge by 1e-3 pitch
+        jt = math.floor((ct - y["off_t"]) / y["pitch_t"] + 1e-3)
+        ja = math.floor((ca - y["off_a"]) / y["pitch_a"] + 1e-3)
         if not (h <= jt <= y["n_t"] - 1 - h and h <= ja <= y["n_a"] - 1 - h):
             return Entry(False)
         anchor.append((jt, ja))

@@ -824,6 +824,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   return GPET_OK;
 }
 
+size_t scan_tmp_words(size_t n) { return scan_scratch_words(n); }
+void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st) { exclusive_scan(a, n, tmp, st); }
+
 void free_scratch(DigitizeScratch &scr) {
   if (scr.pinned) (void)hipHostFree(scr.pinned);
   scr.pinned = nullptr;

@@ -371,6 +371,7 @@ void gpet_ctx_destroy(gpet_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->squeue.blob) (void)hipFree(c->squeue.blob);
   for (void *p : {(void *)c->d_mu, (void *)c->d_mu_mass, (void *)c->d_mu_det, (void *)c->d_maj_det, (void *)c->d_maj_ph,
                   (void *)c->d_pose, (void *)c->d_vmat, (void *)c->d_vden, (void *)c->d_rods,
                   (void *)c->d_rod_cum, (void *)c->d_ctrl, (void *)c->d_plain})
@@ -621,15 +622,17 @@ static void set_hits(RunArgs &A, gpet_hits *h) {
 }
 
 // runs a prepared transport launch and reads back the counts
+// device controls: [0] event-chunk counter, [1] hit count, [2..11] stats,
+// [12] pairs / surrogate entries
 static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, int det_slots, const LaunchShape &shape,
-                                 gpet_hits *h, gpet_stats *stats) {
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 24, c->stream);
+                                 gpet_hits *h, gpet_stats *stats, int mode = kModePlain) {
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 26, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
-  if (A.total_chunks) launch_transport(A, det_slots, shape, c->n_cu, c->stream);
+  if (A.total_chunks) launch_transport(A, det_slots, shape, c->n_cu, c->stream, mode);
   if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
   gpet_status s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
-  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 12 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 13 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
   if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "transport: kernel");
   if (s) return s;
   h->count = c->h_ctrl[1];
@@ -827,6 +830,191 @@ gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, u
   if (n) launch_trace(A, c->scene.n_det_slots, c->stream);
   s = hip_check(c, hipGetLastError(), "trace: launch");
   return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "trace");
+}
+
+// ---------------------------------------------------------------------------
+// surrogate
+// ---------------------------------------------------------------------------
+static gpet_status surrogate_spec(gpet_ctx *c, const gpet_surrogate_spec *p, SurSpecD &P, int &n_classes) {
+  if (!p) return fail(c, GPET_ERR_ARG, "surrogate: null spec");
+  if (p->half_width < 0 || p->half_width > 7 || p->n_ebins < 1 || p->n_ebins > 1024 ||
+      !(p->e_min_kev > 0 && p->e_min_kev < 511.0) || !(p->ebin_kev > 0) || !(p->photopeak_tol_kev >= 0) ||
+      !(p->max_slope > 0) || !(p->front_tol_mm > 0))
+    return fail(c, GPET_ERR_ARG, "surrogate: spec out of range");
+  const DevScene &S = c->scene;
+  const int W = 2 * p->half_width + 1;
+  for (int l = 0; l < S.n_layers; ++l)
+    if (S.layer[l].n_t < W || S.layer[l].n_a < W || S.layer[l].n_t > 1023 || S.layer[l].n_a > 1023)
+      return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: a layer is narrower than the neighbourhood (or wider than 1023)");
+  if (S.n_panels > 127 || S.mod_n_t * S.mod_n_a > (1 << 24))
+    return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: more than 127 panels or 2^24 modules");
+  P.half = p->half_width;
+  P.n_ebins = p->n_ebins;
+  P.e_min = (float)p->e_min_kev;
+  P.ebin = (float)p->ebin_kev;
+  P.tol = (float)p->photopeak_tol_kev;
+  P.max_slope = (float)p->max_slope;
+  P.front_tol = (float)p->front_tol_mm;
+  n_classes = 1 + S.n_layers * W * W * (p->n_ebins + 1);
+  return GPET_OK;
+}
+
+gpet_status gpet_surrogate_pairs(gpet_ctx *c, const gpet_surrogate_spec *spec, uint64_t first, uint64_t n,
+                                 uint64_t seed, uint32_t instance, gpet_hits *h, gpet_pairs *pairs,
+                                 gpet_stats *stats) {
+  gpet_status s = ready(c);
+  if (s) return s;
+  SurSpecD P;
+  int n_classes = 0;
+  s = surrogate_spec(c, spec, P, n_classes);
+  if (s) return s;
+  if (!h || !pairs) return fail(c, GPET_ERR_ARG, "surrogate pairs: null output");
+  if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "surrogate pairs: event range");
+  if (!hits_ok(h)) return fail(c, GPET_ERR_ARG, "surrogate pairs: null hit array");
+  if (pairs->capacity && (!pairs->x || !pairs->label || !pairs->flags || !pairs->event))
+    return fail(c, GPET_ERR_ARG, "surrogate pairs: null pair array");
+  (void)hipSetDevice(c->device);
+  RunArgs A;
+  s = run_args(c, first, n, seed, instance, A);
+  if (s) return s;
+  set_hits(A, h);
+  A.sur = P;
+  A.px = pairs->x;
+  A.plabel = pairs->label;
+  A.pflags = pairs->flags;
+  A.pevent = pairs->event;
+  A.pcount = c->d_ctrl + 12;
+  A.pcap = pairs->capacity;
+  s = run_transport(c, A, c->scene.n_det_slots, c->shape, h, stats, kModeRecord);
+  pairs->count = c->h_ctrl[12];
+  if (s) return s;
+  if (pairs->count > pairs->capacity) return fail(c, GPET_ERR_CAPACITY, "surrogate pairs: pair capacity too small");
+  return GPET_OK;
+}
+
+// the entry queue for `cap` entries
+static gpet_status ensure_queue(gpet_ctx *c, size_t cap) {
+  SurQueue &Q = c->squeue;
+  if (Q.cap >= cap) return GPET_OK;
+  if (Q.blob) (void)hipFree(Q.blob);
+  Q = SurQueue{};
+  const size_t tmp = scan_tmp_words(cap);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t bytes = al(cap * 24) + al(cap * 4) * 6 + al(cap * 8) * 2 + al(tmp * 4);
+  if (hipMalloc(&Q.blob, bytes) != hipSuccess) {
+    Q.blob = nullptr;
+    return fail(c, GPET_ERR_HIP, "surrogate: queue allocation failed");
+  }
+  char *p = (char *)Q.blob;
+  auto take = [&](size_t b) {
+    char *r = p;
+    p += al(b);
+    return (void *)r;
+  };
+  Q.x = (float *)take(cap * 24);
+  Q.e = (float *)take(cap * 4);
+  Q.ev = (uint32_t *)take(cap * 4);
+  Q.meta = (uint32_t *)take(cap * 4);
+  Q.cls = (uint32_t *)take(cap * 4);
+  Q.pos = (uint32_t *)take(cap * 4);
+  Q.anchor = (uint32_t *)take(cap * 8);
+  Q.time = (unsigned long long *)take(cap * 8);
+  Q.scan_tmp = (uint32_t *)take(tmp * 4);
+  Q.cap = cap;
+  return GPET_OK;
+}
+
+gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrogate_spec *spec, uint64_t first,
+                                     uint64_t n, uint64_t seed, uint32_t instance, gpet_hits *h, gpet_stats *stats,
+                                     gpet_surrogate_stats *ss) {
+  gpet_status s = ready(c);
+  if (s) return s;
+  SurSpecD P;
+  int n_classes = 0;
+  s = surrogate_spec(c, spec, P, n_classes);
+  if (s) return s;
+  if (!q || q->ctx != c) return fail(c, GPET_ERR_ARG, "surrogate: network missing or made on another context");
+  if (q->size[0] != 6 || q->size[q->n_layers] != n_classes)
+    return fail(c, GPET_ERR_ARG, "surrogate: the network must map 6 features to " + std::to_string(n_classes) +
+                                     " classes for this scanner and spec");
+  if (!h) return fail(c, GPET_ERR_ARG, "surrogate: null hits");
+  if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "surrogate: event range");
+  if (!hits_ok(h)) return fail(c, GPET_ERR_ARG, "surrogate: null hit array");
+  (void)hipSetDevice(c->device);
+  constexpr uint64_t kSlice = 8u << 20; // events per transport launch (queue of 2 per event)
+  s = ensure_queue(c, (size_t)2 * std::min<uint64_t>(std::max<uint64_t>(n, 1), kSlice));
+  if (s) return s;
+  const SurQueue &Q = c->squeue;
+  hipEvent_t ev[4];
+  for (hipEvent_t &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(c, GPET_ERR_HIP, "surrogate: event creation failed");
+  float ms_t = 0.f, ms_n = 0.f;
+  uint64_t entries = 0, none = 0;
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 26, c->stream);
+  for (uint64_t off = 0; off < n && !s; off += kSlice) {
+    const uint64_t len = std::min(kSlice, n - off);
+    RunArgs A;
+    s = run_args(c, first + off, len, seed, instance, A);
+    if (s) break;
+    set_hits(A, h);
+    A.sur = P;
+    A.px = Q.x;
+    A.qev = Q.ev;
+    A.qmeta = Q.meta;
+    A.qanchor = Q.anchor;
+    A.qe = Q.e;
+    A.qtime = Q.time;
+    A.pcount = c->d_ctrl + 12;
+    A.pcap = Q.cap;
+    launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2, c->stream);        // event-chunk counter
+    launch_fill_u32((uint32_t *)(c->d_ctrl + 12), 0u, 2, c->stream); // queue count
+    (void)hipEventRecord(ev[0], c->stream);
+    launch_transport(A, c->scene.n_det_slots, c->shape, c->n_cu, c->stream, kModeSurrogate);
+    (void)hipEventRecord(ev[1], c->stream);
+    s = hip_check(c, hipGetLastError(), "surrogate: transport launch");
+    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + 12, c->d_ctrl + 12, 8, hipMemcpyDeviceToHost, c->stream),
+                          "surrogate: readback");
+    if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "surrogate: transport");
+    if (s) break;
+    const uint64_t nq = c->h_ctrl[12];
+    if (nq > Q.cap) {
+      s = fail(c, GPET_ERR_HIP, "surrogate: entry queue overflow");
+      break;
+    }
+    entries += nq;
+    (void)hipEventRecord(ev[2], c->stream);
+    const int r = surrogate_hits(q, (const DevScene *)c->d_plain, P, Q, (uint32_t)nq, A.k0, A.k1, instance, A,
+                                 c->stream, c->err, &none);
+    (void)hipEventRecord(ev[3], c->stream);
+    if (r != GPET_OK) {
+      s = r;
+      break;
+    }
+    s = hip_check(c, hipStreamSynchronize(c->stream), "surrogate: network");
+    float a = 0.f, b = 0.f;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[2], ev[3]);
+    ms_t += a;
+    ms_n += b;
+  }
+  for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
+  if (s) return s;
+  s = hip_check(c, hipMemcpy(c->h_ctrl, c->d_ctrl, 12 * 8, hipMemcpyDeviceToHost), "surrogate: readback");
+  if (s) return s;
+  h->count = c->h_ctrl[1];
+  if (stats) {
+    uint64_t *o = (uint64_t *)stats;
+    for (int k = 0; k < 10; ++k) o[k] = c->h_ctrl[2 + k];
+  }
+  if (ss) {
+    ss->entries = entries;
+    ss->none = none;
+    ss->ms_transport = ms_t;
+    ss->ms_network = ms_n;
+  }
+  c->last_ms[0] = ms_t;
+  if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "surrogate: hit capacity too small");
+  return GPET_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -11,6 +11,16 @@
 
 namespace gpet {
 
+// Surrogate entry domain and outcome classes on the device (see
+// gpet_surrogate_spec in the C header).
+struct SurSpecD {
+  int half, n_ebins;
+  float e_min, ebin, tol, max_slope, front_tol;
+};
+
+// Transport kernel modes
+enum : int { kModePlain = 0, kModeTrace = 1, kModeRecord = 2, kModeSurrogate = 3 };
+
 // Device outputs and controls of one transport launch over a table of
 // instances (one instance for a plain run).  Work is handed out in chunks of
 // `chunk` consecutive events of one instance; chunk c of the launch belongs to
@@ -38,6 +48,20 @@ struct RunArgs {
   int max_vertices;
   uint32_t search_batch; // lanes of a wave that must wait for a panel search before it runs
   uint32_t schedule;     // 0: all phases each trip; 1: the most-populated phase only
+  // record and surrogate modes: photons entering their first panel inside the
+  // surrogate domain get an entry with features px (6 per entry).  Record:
+  // label and flags once the photon leaves the panel.  Surrogate: an entry
+  // queue (event, meta = photon | panel << 1 | module << 8, two words of
+  // packed per-layer anchors, entry energy, entry time) and the photon ends.
+  SurSpecD sur;
+  float *px;
+  int32_t *plabel;
+  uint32_t *pflags, *pevent;
+  uint32_t *qev, *qmeta, *qanchor;
+  float *qe;
+  unsigned long long *qtime;
+  unsigned long long *pcount; // device: pairs / queue entries produced
+  unsigned long long pcap;
 };
 
 struct LaunchShape {
@@ -49,7 +73,8 @@ size_t transport_lds_bytes(int det_slots);
 
 // kernels (transport.hip); det_slots is the largest detector material slot
 // count of the launch's scenes (it sizes the LDS tables)
-void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st);
+void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st,
+                      int mode = kModePlain);
 void launch_trace(const RunArgs &A, int det_slots, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
 void launch_philox(uint64_t seed, const uint32_t *ctr, uint32_t n, uint32_t *out, hipStream_t st);
@@ -88,6 +113,19 @@ struct DigitizeArgs {
   const gpet_tallies *tallies = nullptr;
   unsigned long long *coinc_per_inst = nullptr; // host, one count per instance (optional)
 };
+// exclusive prefix sum of n u32 in place; tmp holds scan_tmp_words(n) words
+size_t scan_tmp_words(size_t n);
+void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st);
+
+// Surrogate entry queue (library scratch): SoA of `cap` entries
+struct SurQueue {
+  size_t cap = 0;
+  void *blob = nullptr;
+  float *x = nullptr, *e = nullptr;
+  uint32_t *ev = nullptr, *meta = nullptr, *anchor = nullptr, *cls = nullptr, *pos = nullptr, *scan_tmp = nullptr;
+  unsigned long long *time = nullptr;
+};
+
 // returns GPET_OK or an error code; fills counts
 int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::string &err);
 void free_scratch(DigitizeScratch &scr);
@@ -127,6 +165,7 @@ struct gpet_ctx {
   gpet::DevScene scene{};
   gpet::LaunchShape shape{};
   gpet::DigitizeScratch scratch{};
+  gpet::SurQueue squeue{};
   // generations of the material list and phantom; a batch made from this
   // context refuses to run once either changed (its scenes point at them)
   uint64_t mat_gen = 0, phantom_gen = 0;
@@ -157,3 +196,42 @@ struct gpet_batch {
   uint32_t *d_prefix = nullptr;
   gpet::RunArgs base{}; // table pointers and controls; hits and seed set per call
 };
+
+// The surrogate network: a ReLU MLP with FP32 master weights and Adam moments,
+// padded BF16 weight copies for the matrix cores, and a workspace of `cap`
+// rows (activations, logits, gradient buffers).
+struct gpet_mlp {
+  gpet_ctx *ctx = nullptr;
+  int device = 0;
+  std::vector<int> size;  // layer widths, input first
+  std::vector<int> psize; // widths padded to multiples of 64
+  int n_layers = 0;       // weight matrices
+  size_t n_params = 0;
+  std::vector<size_t> w_off, b_off;                  // offsets in the packed parameter vector
+  float *master = nullptr, *m = nullptr, *v = nullptr; // packed fp32 (per layer W [out][in], then b)
+  std::vector<uint16_t *> wb;                        // padded bf16 weights per layer [out_pad][in_pad]
+  std::vector<float *> gw;                           // padded fp32 weight gradients per layer
+  float *gb = nullptr;                               // packed gradients (biases at b_off)
+  float *bp = nullptr;                               // padded fp32 biases, bp_stride per layer
+  int bp_stride = 0;
+  uint64_t adam_t = 0;
+  uint32_t cap = 0;
+  std::vector<uint16_t *> act; // bf16 input of every layer (act[0]: packed network input)
+  float *logits = nullptr;
+  uint16_t *dz[2] = {nullptr, nullptr};
+  int32_t *yb = nullptr;
+  uint32_t *idx = nullptr;
+  double *row_loss = nullptr, *loss_sum = nullptr;
+  uint32_t *flag = nullptr; // bit 0: a label outside the classes
+};
+
+namespace gpet {
+// Network inference on the first nq entries of a surrogate queue: classes
+// sampled from the softmax (Philox key (k0, k1), counter (0, event, inst_rng,
+// 4 + photon)), then one synthetic hit per entry whose class is not 0,
+// appended after *hit_count (device) in queue order.  d_scene: the scene the
+// entries were made in (device).  Adds the class-0 count to *n_none.
+int surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P, const SurQueue &Q, uint32_t nq,
+                   uint32_t k0, uint32_t k1, uint32_t inst_rng, const RunArgs &hits, hipStream_t st, std::string &err,
+                   uint64_t *n_none);
+} // namespace gpet

@@ -1,0 +1,672 @@
+// mlp.hip -- the surrogate network on gfx950 matrix cores: a ReLU MLP with
+// BF16 weights and activations, FP32 accumulation (v_mfma_f32_16x16x32_bf16),
+// softmax cross-entropy, backpropagation and Adam on FP32 master weights.
+//
+// All matrix products go through one LDS-tiled kernel: a 256-lane block
+// computes a 64 x 64 tile of C = A B with 4 waves of 32 x 32 (2 x 2 MFMA tiles
+// of 16 x 16), stepping K by 32.  Operands are staged in LDS K-contiguous, so
+// each lane feeds an MFMA with one 16-byte LDS read per operand; operands that
+// are K-strided in memory (the transposes of the backward pass) are transposed
+// on their way into LDS.  Sizes are padded to multiples of 64; padded weights
+// and biases are zero and padded rows carry zero gradient.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gpet_internal.hpp"
+
+namespace gpet {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 64;
+constexpr int kTk = 32;
+constexpr int kLdsRow = kTk + 8; // bf16 per LDS row (padding against bank conflicts)
+
+// float -> bfloat16 bits, round to nearest even
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_BF16 = 3 };
+
+// C[m][n] = sum_k A(m, k) B(k, n) over a padded problem (M, N multiples of 64,
+// K a multiple of 32).  A(m, k) = a[m lda + k] (AT: a[k lda + m]);
+// B(k, n) = b[n ldb + k] (BT: b[k ldb + n]).  Epilogue per EPI.
+template <bool AT, bool BT, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, int lda, const uint16_t *__restrict__ b,
+                                              int ldb, int K, const float *__restrict__ bias,
+                                              const uint16_t *__restrict__ mask, void *__restrict__ out, int ldc) {
+  __shared__ __attribute__((aligned(16))) uint16_t sa[kTile * kLdsRow];
+  __shared__ __attribute__((aligned(16))) uint16_t sb[kTile * kLdsRow];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < K; k0 += kTk) {
+    // ---- stage A (64 x 32) and B (32 x 64) K-contiguous in LDS
+    if constexpr (!AT) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      *(uint4 *)&sa[r * kLdsRow + c] = *(const uint4 *)&a[(size_t)(m0 + r) * lda + k0 + c];
+    } else {
+      const int kk = tid >> 3, c = (tid & 7) * 8;
+      const uint4 v = *(const uint4 *)&a[(size_t)(k0 + kk) * lda + m0 + c];
+      const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sa[(c + j) * kLdsRow + kk] = e[j];
+    }
+    if constexpr (!BT) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      *(uint4 *)&sb[r * kLdsRow + c] = *(const uint4 *)&b[(size_t)(n0 + r) * ldb + k0 + c];
+    } else {
+      const int kk = tid >> 3, c = (tid & 7) * 8;
+      const uint4 v = *(const uint4 *)&b[(size_t)(k0 + kk) * ldb + n0 + c];
+      const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sb[(c + j) * kLdsRow + kk] = e[j];
+    }
+    __syncthreads();
+    // ---- lane l feeds row/column l % 16 with k = 8 (l / 16) .. + 8
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    bf16x8 fa[2], fb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      fa[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sa[(wm + 16 * i + lr) * kLdsRow + lk]);
+      fb[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sb[(wn + 16 * i + lr) * kLdsRow + lk]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // ---- epilogue: lane l holds column l % 16, rows 4 (l / 16) .. + 4 of each tile
+  const int cn = lane & 15, rb = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + rb + q, n = n0 + wn + 16 * j + cn;
+        float v = acc[i][j][q];
+        const size_t o = (size_t)m * ldc + n;
+        if constexpr (EPI == EPI_BIAS_RELU_BF16) {
+          ((uint16_t *)out)[o] = f2bf(fmaxf(v + bias[n], 0.0f));
+        } else if constexpr (EPI == EPI_BIAS_F32) {
+          ((float *)out)[o] = v + bias[n];
+        } else if constexpr (EPI == EPI_F32) {
+          ((float *)out)[o] = v;
+        } else {
+          ((uint16_t *)out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? v : 0.0f);
+        }
+      }
+}
+
+template <bool AT, bool BT, int EPI>
+static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, int N, int K, const float *bias,
+                 const uint16_t *mask, void *out, int ldc, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), dim3(N / kTile, M / kTile), dim3(256), 0, st, a, lda, b, ldb, K, bias, mask,
+                     out, ldc);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise and reduction kernels
+// ---------------------------------------------------------------------------
+// rows of fp32 inputs [n][n_in] -> bf16 [n_pad][in_pad] (zero padded); with
+// idx, row r takes input row idx[r] (and label y[idx[r]])
+__global__ void k_pack_input(const float *x, const int32_t *y, const uint32_t *idx, uint32_t n, int n_in, int in_pad,
+                             uint32_t n_pad, uint16_t *xb, int32_t *yb) {
+  const uint32_t r = blockIdx.x * blockDim.y + threadIdx.y;
+  if (r >= n_pad) return;
+  const int c = threadIdx.x;
+  const bool live = r < n;
+  const uint32_t src = live ? (idx ? idx[r] : r) : 0u;
+  for (int k = c; k < in_pad; k += blockDim.x)
+    xb[(size_t)r * in_pad + k] = (live && k < n_in) ? f2bf(x[(size_t)src * n_in + k]) : (uint16_t)0;
+  if (yb && c == 0) yb[r] = live ? y[src] : -1;
+}
+
+// one wave per row: loss = logsumexp(z) - z[y]; dz = (softmax(z) - onehot(y)) / n
+// as bf16 (zero in padded columns and rows)
+// (a label outside [0, C) sets *bad and is read as class 0)
+__global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int C, const int32_t *y, uint32_t n,
+                                                    uint32_t n_pad, float inv_n, uint16_t *dz, double *row_loss,
+                                                    uint32_t *bad) {
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n_pad) return;
+  const float *zr = z + (size_t)r * ldz;
+  uint16_t *dr = dz + (size_t)r * ldz;
+  if (r >= n) {
+    for (int c = lane; c < ldz; c += 64) dr[c] = 0;
+    if (lane == 0) row_loss[r] = 0.0;
+    return;
+  }
+  float mx = -INFINITY;
+  for (int c = lane; c < C; c += 64) mx = fmaxf(mx, zr[c]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  float s = 0.f;
+  for (int c = lane; c < C; c += 64) s += __expf(zr[c] - mx);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  const float inv_s = 1.0f / s;
+  int yy = y[r];
+  if (yy < 0 || yy >= C) {
+    if (lane == 0) atomicOr(bad, 1u);
+    yy = 0;
+  }
+  for (int c = lane; c < ldz; c += 64) {
+    const float p = c < C ? __expf(zr[c] - mx) * inv_s : 0.0f;
+    dr[c] = f2bf(((c == yy ? p - 1.0f : p)) * inv_n);
+  }
+  if (lane == 0) row_loss[r] = (double)mx + log((double)s) - (double)zr[yy];
+}
+
+__global__ void __launch_bounds__(1024) k_sum_f64(const double *v, uint32_t n, double *out) {
+  __shared__ double s[1024];
+  double a = 0.0;
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) a += v[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+// db[c] = sum over rows of dz[r][c]
+__global__ void k_col_sum(const uint16_t *dz, int ld, uint32_t rows, int cols, float *db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float a = 0.f;
+  for (uint32_t r = 0; r < rows; ++r) a += bf2f(dz[(size_t)r * ld + c]);
+  db[c] = a;
+}
+
+// Adam on one tensor: master [rows][cols] against gradients with row stride
+// ldg; refreshes the bf16 copy wb [rows][ldb] and/or the fp32 copy fc [cols]
+// (biases, rows = 1)
+__global__ void k_adam(float *w, float *m, float *v, const float *g, int rows, int cols, int ldg, float lr, float b1,
+                       float b2, float eps, float c1, float c2, uint16_t *wb, int ldb, float *fc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int r = i / cols, c = i - r * cols;
+  const float gg = g[(size_t)r * ldg + c];
+  const float mm = b1 * m[i] + (1.0f - b1) * gg;
+  const float vv = b2 * v[i] + (1.0f - b2) * gg * gg;
+  m[i] = mm;
+  v[i] = vv;
+  const float nw = w[i] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+  w[i] = nw;
+  if (wb) wb[(size_t)r * ldb + c] = f2bf(nw);
+  if (fc) fc[i] = nw;
+}
+
+// bf16 copy of a master weight matrix into its padded buffer
+__global__ void k_to_bf16(const float *w, int rows, int cols, uint16_t *wb, int ldb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int r = i / cols, c = i - r * cols;
+  wb[(size_t)r * ldb + c] = f2bf(w[i]);
+}
+
+// training batch indices: uniform with replacement from Philox (key seed,
+// counter (step, r / 4, 0, 9))
+__global__ void k_batch_indices(uint32_t k0, uint32_t k1, uint32_t step, uint32_t n, uint64_t n_pairs, uint32_t *idx) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint4 w = philox(k0, k1, make_uint4(step, r >> 2, 0u, 9u));
+  const uint32_t word = (r & 3) == 0 ? w.x : (r & 3) == 1 ? w.y : (r & 3) == 2 ? w.z : w.w;
+  idx[r] = (uint32_t)(((unsigned long long)word * n_pairs) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// surrogate sampling: one wave per queue entry
+// ---------------------------------------------------------------------------
+// class = first c whose cumulative softmax mass reaches u * total; each lane
+// sums a contiguous run of classes, a wave scan orders the runs, and the lane
+// holding the crossing walks its run in the same order
+__global__ void __launch_bounds__(256) k_sample_classes(const float *z, int ldz, int C, uint32_t n, const uint32_t *ev,
+                                                        const uint32_t *meta, uint32_t k0, uint32_t k1,
+                                                        uint32_t inst_rng, uint32_t *cls, uint32_t *nonzero) {
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const float *zr = z + (size_t)r * ldz;
+  float mx = -INFINITY;
+  for (int c = lane; c < C; c += 64) mx = fmaxf(mx, zr[c]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  const int per = (C + 63) / 64;
+  const int lo = min(lane * per, C), hi = min(lo + per, C);
+  float part = 0.f;
+  for (int c = lo; c < hi; ++c) part += __expf(zr[c] - mx);
+  float incl = part;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const float total = __shfl(incl, 63);
+  const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
+  const float target = to_unit(w.x) * total;
+  const uint64_t crossed = __ballot(incl >= target && hi > lo);
+  int c_out = C - 1;
+  if (crossed) {
+    const int L = __ffsll((unsigned long long)crossed) - 1;
+    int found = C - 1;
+    if (lane == L) {
+      float acc = incl - part;
+      found = hi - 1;
+      for (int c = lo; c < hi; ++c) {
+        acc += __expf(zr[c] - mx);
+        if (acc >= target) {
+          found = c;
+          break;
+        }
+      }
+    }
+    c_out = __shfl(found, L);
+  }
+  if (lane == 0) {
+    cls[r] = (uint32_t)c_out;
+    nonzero[r] = c_out != 0 ? 1u : 0u;
+  }
+}
+
+// one synthetic hit per entry with a class other than 0, at *hit_count + pos
+__global__ void k_emit_hits(uint32_t n, const uint32_t *cls, const uint32_t *pos, const uint32_t *ev,
+                            const uint32_t *meta, const uint32_t *anchor, const float *e_in,
+                            const unsigned long long *time, const DevScene *Sp, SurSpecD P, uint32_t k0, uint32_t k1,
+                            uint32_t inst_rng, RunArgs H) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n || cls[r] == 0) return;
+  const DevScene &S = *Sp;
+  const int c = (int)cls[r] - 1;
+  const int nb = P.n_ebins + 1, W = 2 * P.half + 1;
+  const int b = c % nb, k = c / nb;
+  const int l = k / (W * W), rr = k - l * W * W;
+  const int dt = rr / W, da = rr - dt * W;
+  const uint32_t aw = anchor[2 * r + (l >> 1)] >> (20 * (l & 1));
+  const int it = (int)(aw & 1023u) + dt - P.half, ia = (int)((aw >> 10) & 1023u) + da - P.half;
+  const uint32_t m = meta[r];
+  const int panel = (int)((m >> 1) & 127u), module = (int)(m >> 8);
+  const int gid = panel * S.crystals_per_panel + module * S.crystals_per_module + S.layer[l].base +
+                  ia * S.layer[l].n_t + it;
+  const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (m & 1u)));
+  const float edep = b == P.n_ebins ? e_in[r] : P.e_min + P.ebin * ((float)b + to_unit(w.y));
+  const unsigned long long i = *H.hit_count + pos[r];
+  if (i >= H.capacity) return;
+  H.h_event[i] = ev[r];
+  H.h_gid[i] = (uint32_t)gid;
+  H.h_edep[i] = edep;
+  H.h_depth[i] = 0.5f * (S.layer[l].d0 + S.layer[l].d1);
+  H.h_time[i] = time[r];
+  H.h_aux[i] = (m & 1u) | (3u << 1);
+  if (H.h_inst) H.h_inst[i] = 0u;
+}
+
+__global__ void k_add_u64(unsigned long long *p, unsigned long long v) { *p += v; }
+
+static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+static inline int pad_to(int x, int m) { return (x + m - 1) / m * m; }
+
+} // namespace gpet
+
+using namespace gpet;
+
+namespace {
+
+gpet_status mlp_fail(gpet_mlp *q, gpet_status code, const std::string &msg) {
+  if (q && q->ctx) q->ctx->err = msg;
+  return code;
+}
+
+void free_workspace(gpet_mlp *q) {
+  for (uint16_t *p : q->act)
+    if (p) (void)hipFree(p);
+  q->act.clear();
+  for (void *p : {(void *)q->logits, (void *)q->dz[0], (void *)q->dz[1], (void *)q->yb, (void *)q->idx,
+                  (void *)q->row_loss, (void *)q->loss_sum, (void *)q->flag})
+    if (p) (void)hipFree(p);
+  q->flag = nullptr;
+  q->logits = nullptr;
+  q->dz[0] = q->dz[1] = nullptr;
+  q->yb = nullptr;
+  q->idx = nullptr;
+  q->row_loss = q->loss_sum = nullptr;
+  q->cap = 0;
+}
+
+// workspace for at least n rows (rounded up to a tile)
+gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
+  const uint32_t need = (uint32_t)pad_to((int)std::max<uint32_t>(n, 1), kTile);
+  if (need <= q->cap) return GPET_OK;
+  free_workspace(q);
+  bool ok = true;
+  q->act.assign(q->n_layers, nullptr);
+  int widest = 0;
+  for (int l = 0; l < q->n_layers; ++l) {
+    ok = ok && hipMalloc((void **)&q->act[l], (size_t)need * q->psize[l] * 2) == hipSuccess;
+    widest = std::max(widest, q->psize[l + 1]);
+  }
+  ok = ok && hipMalloc((void **)&q->logits, (size_t)need * q->psize[q->n_layers] * 4) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->dz[0], (size_t)need * widest * 2) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->dz[1], (size_t)need * widest * 2) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->yb, (size_t)need * 4) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->idx, (size_t)need * 4) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->row_loss, (size_t)need * 8) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->loss_sum, 8) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->flag, 8) == hipSuccess;
+  if (!ok) {
+    free_workspace(q);
+    return mlp_fail(q, GPET_ERR_HIP, "mlp: workspace allocation failed");
+  }
+  q->cap = need;
+  return GPET_OK;
+}
+
+// forward pass of the rows packed in act[0]; logits (fp32, padded) at q->logits
+void forward(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
+  for (int l = 0; l < q->n_layers; ++l) {
+    const int K = q->psize[l], N = q->psize[l + 1];
+    const float *bias = q->bp + l * q->bp_stride;
+    if (l + 1 < q->n_layers)
+      gemm<false, false, EPI_BIAS_RELU_BF16>(q->act[l], K, q->wb[l], K, (int)n_pad, N, K, bias, nullptr, q->act[l + 1],
+                                             N, st);
+    else
+      gemm<false, false, EPI_BIAS_F32>(q->act[l], K, q->wb[l], K, (int)n_pad, N, K, bias, nullptr, q->logits, N, st);
+  }
+}
+
+// loss of the rows in act[0] / yb and the gradient of the mean loss into gw / gb
+void backward(gpet_mlp *q, uint32_t n, uint32_t n_pad, hipStream_t st) {
+  const int L = q->n_layers;
+  const int C = q->size[L], Cp = q->psize[L];
+  hipLaunchKernelGGL(k_softmax_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, C, q->yb, n, n_pad,
+                     1.0f / (float)n, q->dz[0], q->row_loss, q->flag);
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(1024), 0, st, q->row_loss, n_pad, q->loss_sum);
+  int cur = 0;
+  for (int l = L - 1; l >= 0; --l) {
+    const int K = q->psize[l], N = q->psize[l + 1];
+    // dW[o][i] = sum_r dz[r][o] act[r][i]: A = dz^T (M = N, K = rows), B(k = r, n = i) = act[r][i]
+    gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, (int)n_pad, nullptr, nullptr, q->gw[l], K, st);
+    hipLaunchKernelGGL(k_col_sum, dim3(cdiv(q->size[l + 1], 256)), dim3(256), 0, st, q->dz[cur], N, n_pad,
+                       q->size[l + 1], q->gb + q->b_off[l]);
+    if (l) {
+      // dh[r][i] = sum_o dz[r][o] W[o][i], masked by the ReLU of layer l's input
+      gemm<false, true, EPI_MASK_BF16>(q->dz[cur], N, q->wb[l], K, (int)n_pad, K, N, nullptr, q->act[l],
+                                       q->dz[cur ^ 1], K, st);
+      cur ^= 1;
+    }
+  }
+}
+
+} // namespace
+
+int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P, const SurQueue &Q, uint32_t nq,
+                         uint32_t k0, uint32_t k1, uint32_t inst_rng, const RunArgs &H, hipStream_t st,
+                         std::string &err, uint64_t *n_none) {
+  if (nq == 0) return GPET_OK;
+  constexpr uint32_t kChunk = 1u << 18;
+  if (ensure_workspace(q, std::min(nq, kChunk)) != GPET_OK) {
+    err = q->ctx->err;
+    return GPET_ERR_HIP;
+  }
+  const int C = q->size[q->n_layers], Cp = q->psize[q->n_layers];
+  for (uint32_t off = 0; off < nq; off += kChunk) {
+    const uint32_t n = std::min(kChunk, nq - off);
+    const uint32_t n_pad = (uint32_t)pad_to((int)n, kTile);
+    hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, Q.x + (size_t)6 * off,
+                       (const int32_t *)nullptr, (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad,
+                       q->act[0], (int32_t *)nullptr);
+    forward(q, n_pad, st);
+    hipLaunchKernelGGL(k_sample_classes, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, C, n, Q.ev + off,
+                       Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
+  }
+  // nonzero flags -> positions; the class-0 count comes from the same scan
+  unsigned long long *cnt = H.hit_count;
+  uint32_t last[2] = {0u, 0u};
+  (void)hipMemcpyAsync(&last[0], Q.pos + nq - 1, 4, hipMemcpyDeviceToHost, st);
+  scan_exclusive_u32(Q.pos, nq, Q.scan_tmp, st);
+  (void)hipMemcpyAsync(&last[1], Q.pos + nq - 1, 4, hipMemcpyDeviceToHost, st);
+  hipLaunchKernelGGL(k_emit_hits, dim3(cdiv(nq, 256)), dim3(256), 0, st, nq, Q.cls, Q.pos, Q.ev, Q.meta, Q.anchor, Q.e,
+                     Q.time, d_scene, P, k0, k1, inst_rng, H);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    err = "surrogate: kernel error";
+    return GPET_ERR_HIP;
+  }
+  const uint64_t kept = (uint64_t)last[1] + last[0];
+  *n_none += nq - kept;
+  // hit count += kept (device-side, after the emit kernel read the old value)
+  hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, cnt, (unsigned long long)kept);
+  return hipGetLastError() == hipSuccess ? GPET_OK : GPET_ERR_HIP;
+}
+
+extern "C" {
+
+gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, const float *weights, gpet_mlp **out) {
+  if (!c || !out || !sizes) return GPET_ERR_ARG;
+  *out = nullptr;
+  if (n_sizes < 2 || n_sizes > 16) {
+    c->err = "mlp: 2..16 layer widths";
+    return GPET_ERR_ARG;
+  }
+  if (sizes[0] < 1 || sizes[0] > 256) {
+    c->err = "mlp: input width in 1..256";
+    return GPET_ERR_ARG;
+  }
+  for (int i = 1; i < n_sizes; ++i)
+    if (sizes[i] < 1 || sizes[i] > 8192) {
+      c->err = "mlp: layer widths in 1..8192";
+      return GPET_ERR_ARG;
+    }
+  gpet_mlp *q = new (std::nothrow) gpet_mlp();
+  if (!q) return GPET_ERR_ARG;
+  q->ctx = c;
+  q->device = c->device;
+  q->size.assign(sizes, sizes + n_sizes);
+  q->n_layers = n_sizes - 1;
+  q->psize.resize(n_sizes);
+  q->psize[0] = pad_to(sizes[0], kTile);
+  for (int i = 1; i < n_sizes; ++i) q->psize[i] = pad_to(sizes[i], kTile);
+  size_t o = 0;
+  for (int l = 0; l < q->n_layers; ++l) {
+    q->w_off.push_back(o);
+    o += (size_t)sizes[l] * sizes[l + 1];
+    q->b_off.push_back(o);
+    o += (size_t)sizes[l + 1];
+  }
+  q->n_params = o;
+  (void)hipSetDevice(c->device);
+  int widest = 0;
+  for (int i = 1; i < n_sizes; ++i) widest = std::max(widest, q->psize[i]);
+  q->bp_stride = widest;
+  bool ok = hipMalloc((void **)&q->master, o * 4) == hipSuccess && hipMalloc((void **)&q->m, o * 4) == hipSuccess &&
+            hipMalloc((void **)&q->v, o * 4) == hipSuccess && hipMalloc((void **)&q->gb, o * 4) == hipSuccess &&
+            hipMalloc((void **)&q->bp, (size_t)q->n_layers * widest * 4) == hipSuccess &&
+            hipMemset(q->bp, 0, (size_t)q->n_layers * widest * 4) == hipSuccess;
+  q->wb.assign(q->n_layers, nullptr);
+  q->gw.assign(q->n_layers, nullptr);
+  for (int l = 0; ok && l < q->n_layers; ++l) {
+    const size_t e = (size_t)q->psize[l] * q->psize[l + 1];
+    ok = hipMalloc((void **)&q->wb[l], e * 2) == hipSuccess && hipMalloc((void **)&q->gw[l], e * 4) == hipSuccess &&
+         hipMemset(q->wb[l], 0, e * 2) == hipSuccess;
+  }
+  if (!ok) {
+    gpet_mlp_destroy(q);
+    c->err = "mlp: device allocation failed";
+    return GPET_ERR_HIP;
+  }
+  *out = q;
+  if (weights) return gpet_mlp_set_weights(q, weights);
+  std::vector<float> zero(o, 0.f);
+  return gpet_mlp_set_weights(q, zero.data());
+}
+
+void gpet_mlp_destroy(gpet_mlp *q) {
+  if (!q) return;
+  (void)hipSetDevice(q->device);
+  (void)hipDeviceSynchronize();
+  free_workspace(q);
+  for (uint16_t *p : q->wb)
+    if (p) (void)hipFree(p);
+  for (float *p : q->gw)
+    if (p) (void)hipFree(p);
+  for (void *p : {(void *)q->master, (void *)q->m, (void *)q->v, (void *)q->gb, (void *)q->bp})
+    if (p) (void)hipFree(p);
+  delete q;
+}
+
+gpet_status gpet_mlp_set_weights(gpet_mlp *q, const float *w) {
+  if (!q || !w) return GPET_ERR_ARG;
+  gpet_ctx *c = q->ctx;
+  (void)hipSetDevice(q->device);
+  for (size_t i = 0; i < q->n_params; ++i)
+    if (!std::isfinite(w[i])) return mlp_fail(q, GPET_ERR_ARG, "mlp: weights must be finite");
+  if (hipMemcpy(q->master, w, q->n_params * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(q->m, 0, q->n_params * 4) != hipSuccess || hipMemset(q->v, 0, q->n_params * 4) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp: upload failed");
+  q->adam_t = 0;
+  for (int l = 0; l < q->n_layers; ++l) {
+    const int rows = q->size[l + 1], cols = q->size[l];
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv((size_t)rows * cols, 256)), dim3(256), 0, c->stream,
+                       q->master + q->w_off[l], rows, cols, q->wb[l], q->psize[l]);
+    (void)hipMemcpyAsync(q->bp + l * q->bp_stride, q->master + q->b_off[l], (size_t)rows * 4,
+                         hipMemcpyDeviceToDevice, c->stream);
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return mlp_fail(q, GPET_ERR_HIP, "mlp: weight conversion");
+  return GPET_OK;
+}
+
+gpet_status gpet_mlp_get_weights(gpet_mlp *q, float *w) {
+  if (!q || !w) return GPET_ERR_ARG;
+  (void)hipSetDevice(q->device);
+  if (hipStreamSynchronize(q->ctx->stream) != hipSuccess ||
+      hipMemcpy(w, q->master, q->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp: download failed");
+  return GPET_OK;
+}
+
+gpet_status gpet_mlp_forward(gpet_mlp *q, uint32_t n, const float *x, float *logits) {
+  if (!q) return GPET_ERR_ARG;
+  if (n && (!x || !logits)) return mlp_fail(q, GPET_ERR_ARG, "mlp forward: null buffers");
+  if (n == 0) return GPET_OK;
+  (void)hipSetDevice(q->device);
+  gpet_status s = ensure_workspace(q, n);
+  if (s) return s;
+  hipStream_t st = q->ctx->stream;
+  const uint32_t n_pad = (uint32_t)pad_to((int)n, kTile);
+  hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, x, (const int32_t *)nullptr,
+                     (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad, q->act[0], (int32_t *)nullptr);
+  forward(q, n_pad, st);
+  const int C = q->size[q->n_layers], Cp = q->psize[q->n_layers];
+  if (hipMemcpy2DAsync(logits, (size_t)C * 4, q->logits, (size_t)Cp * 4, (size_t)C * 4, n, hipMemcpyDeviceToDevice,
+                       st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp forward");
+  return GPET_OK;
+}
+
+gpet_status gpet_mlp_loss_grad(gpet_mlp *q, uint32_t n, const float *x, const int32_t *y, double *loss, float *grad) {
+  if (!q) return GPET_ERR_ARG;
+  if (!n || !x || !y || !loss || !grad) return mlp_fail(q, GPET_ERR_ARG, "mlp loss_grad: arguments");
+  (void)hipSetDevice(q->device);
+  gpet_status s = ensure_workspace(q, n);
+  if (s) return s;
+  hipStream_t st = q->ctx->stream;
+  const uint32_t n_pad = (uint32_t)pad_to((int)n, kTile);
+  launch_fill_u32(q->flag, 0u, 1, st);
+  hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, x, y, (const uint32_t *)nullptr, n,
+                     q->size[0], q->psize[0], n_pad, q->act[0], q->yb);
+  forward(q, n_pad, st);
+  backward(q, n, n_pad, st);
+  double ls = 0.0;
+  uint32_t bad = 0;
+  std::vector<float> gpad;
+  if (hipMemcpyAsync(&ls, q->loss_sum, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&bad, q->flag, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(grad, q->gb, q->n_params * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp loss_grad");
+  if (bad) return mlp_fail(q, GPET_ERR_ARG, "mlp loss_grad: a label lies outside [0, classes)");
+  // weight gradients from their padded buffers (biases were read with gb)
+  for (int l = 0; l < q->n_layers; ++l) {
+    const int rows = q->size[l + 1], cols = q->size[l], ld = q->psize[l];
+    gpad.resize((size_t)q->psize[l + 1] * ld);
+    if (hipMemcpy(gpad.data(), q->gw[l], gpad.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return mlp_fail(q, GPET_ERR_HIP, "mlp loss_grad");
+    for (int r = 0; r < rows; ++r) std::memcpy(grad + q->w_off[l] + (size_t)r * cols, &gpad[(size_t)r * ld], cols * 4);
+  }
+  *loss = ls / (double)n;
+  return GPET_OK;
+}
+
+gpet_status gpet_mlp_train(gpet_mlp *q, uint64_t n_pairs, const float *x, const int32_t *y,
+                           const gpet_train_params *hp, float *loss_per_step) {
+  if (!q) return GPET_ERR_ARG;
+  if (!hp || !x || !y || n_pairs == 0) return mlp_fail(q, GPET_ERR_ARG, "mlp train: arguments");
+  if (hp->batch < 1 || hp->batch > (1u << 20) || !(hp->lr > 0) || !(hp->beta1 >= 0 && hp->beta1 < 1) ||
+      !(hp->beta2 >= 0 && hp->beta2 < 1) || !(hp->eps > 0))
+    return mlp_fail(q, GPET_ERR_ARG, "mlp train: hyperparameters");
+  (void)hipSetDevice(q->device);
+  gpet_status s = ensure_workspace(q, hp->batch);
+  if (s) return s;
+  hipStream_t st = q->ctx->stream;
+  const uint32_t n = hp->batch, n_pad = (uint32_t)pad_to((int)n, kTile);
+  std::vector<double> losses(hp->steps, 0.0);
+  double *d_losses = nullptr;
+  if (hp->steps && hipMalloc((void **)&d_losses, (size_t)hp->steps * 8) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp train: allocation failed");
+  launch_fill_u32(q->flag, 0u, 1, st);
+  for (uint32_t t = 0; t < hp->steps; ++t) {
+    hipLaunchKernelGGL(k_batch_indices, dim3(cdiv(n, 256)), dim3(256), 0, st, (uint32_t)hp->seed,
+                       (uint32_t)(hp->seed >> 32), (uint32_t)(q->adam_t + 1), n, n_pairs, q->idx);
+    hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, x, y, (const uint32_t *)q->idx, n,
+                       q->size[0], q->psize[0], n_pad, q->act[0], q->yb);
+    forward(q, n_pad, st);
+    backward(q, n, n_pad, st);
+    (void)hipMemcpyAsync(d_losses + t, q->loss_sum, 8, hipMemcpyDeviceToDevice, st);
+    ++q->adam_t;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(hp->beta1, (double)q->adam_t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(hp->beta2, (double)q->adam_t)));
+    for (int l = 0; l < q->n_layers; ++l) {
+      const int rows = q->size[l + 1], cols = q->size[l];
+      hipLaunchKernelGGL(k_adam, dim3(cdiv((size_t)rows * cols, 256)), dim3(256), 0, st, q->master + q->w_off[l],
+                         q->m + q->w_off[l], q->v + q->w_off[l], q->gw[l], rows, cols, q->psize[l], (float)hp->lr,
+                         (float)hp->beta1, (float)hp->beta2, (float)hp->eps, c1, c2, q->wb[l], q->psize[l],
+                         (float *)nullptr);
+      hipLaunchKernelGGL(k_adam, dim3(cdiv(rows, 256)), dim3(256), 0, st, q->master + q->b_off[l],
+                         q->m + q->b_off[l], q->v + q->b_off[l], q->gb + q->b_off[l], 1, rows, rows, (float)hp->lr,
+                         (float)hp->beta1, (float)hp->beta2, (float)hp->eps, c1, c2, (uint16_t *)nullptr, 0,
+                         q->bp + l * q->bp_stride);
+    }
+  }
+  bool ok = hipGetLastError() == hipSuccess;
+  if (hp->steps)
+    ok = ok && hipMemcpyAsync(losses.data(), d_losses, (size_t)hp->steps * 8, hipMemcpyDeviceToHost, st) == hipSuccess;
+  uint32_t bad = 0;
+  ok = ok && hipMemcpyAsync(&bad, q->flag, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (d_losses) (void)hipFree(d_losses);
+  if (!ok) return mlp_fail(q, GPET_ERR_HIP, "mlp train: kernel error");
+  if (bad) return mlp_fail(q, GPET_ERR_ARG, "mlp train: a label lies outside [0, classes)");
+  if (loss_per_step)
+    for (uint32_t t = 0; t < hp->steps; ++t) loss_per_step[t] = (float)(losses[t] / (double)n);
+  return GPET_OK;
+}
+
+} // extern "C"

@@ -94,8 +94,54 @@ __device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, u
   wave_sync_lds();
 }
 
-template <bool TRACE>
+// Surrogate domain of a photon entering a panel at local position xl with
+// local direction dl and energy e: front-face entry, lateral slopes within
+// the limit, the mid-depth point of its straight line inside a module, and
+// every layer's neighbourhood around its anchor crystal inside the layer's
+// array.  Anchors: the last layer's crystal whose pitch cell holds the
+// mid-depth point; in another layer, the crystal whose cell holds that cell's
+// centre.  Outputs the 6 features, the module and the anchors (10 bits per
+// index, (i_t, i_a) per layer, two layers per word).
+template <class SC>
+__device__ __forceinline__ bool entry_domain(SC &S, const SurSpecD &P, const Vec &xl, const Vec &dl, float e,
+                                             float f[6], int &module, uint32_t anchor[2]) {
+  if (!(e >= P.e_min) || fabsf(xl.x) > P.front_tol || !(dl.x > 0.0f)) return false;
+  const float st = dl.y / dl.x, sa = dl.z / dl.x;
+  if (fabsf(st) > P.max_slope || fabsf(sa) > P.max_slope) return false;
+  const float s = (0.5f * S.depth - xl.x) / dl.x;
+  const float t = xl.y + s * dl.y, a = xl.z + s * dl.z;
+  const float mtf = floorf((t - S.mod_t0) * S.inv_step_t), maf = floorf((a - S.mod_a0) * S.inv_step_a);
+  if (!(mtf >= 0.0f && mtf < (float)S.mod_n_t && maf >= 0.0f && maf < (float)S.mod_n_a)) return false;
+  const int mt = (int)mtf, ma = (int)maf;
+  const float ut = t - S.mod_t0 - (float)mt * S.mod_step_t, ua = a - S.mod_a0 - (float)ma * S.mod_step_a;
+  if (!(ut >= 0.0f && ut < S.mod_t && ua >= 0.0f && ua < S.mod_a)) return false;
+  const int nl = S.n_layers;
+  const float rt = S.layer[nl - 1].off_t, ra = S.layer[nl - 1].off_a;
+  const float pt = S.layer[nl - 1].pitch_t, pa = S.layer[nl - 1].pitch_a;
+  const float qt = (ut - rt) / pt, qa = (ua - ra) / pa;
+  const float it = floorf(qt), ia = floorf(qa);
+  const float ct = rt + (it + 0.5f) * pt, ca = ra + (ia + 0.5f) * pa;
+  anchor[0] = anchor[1] = 0u;
+  for (int l = 0; l < nl; ++l) {
+    const int jt = (int)floorf((ct - S.layer[l].off_t) / S.layer[l].pitch_t + 1e-3f);
+    const int ja = (int)floorf((ca - S.layer[l].off_a) / S.layer[l].pitch_a + 1e-3f);
+    if (jt < P.half || jt > S.layer[l].n_t - 1 - P.half || ja < P.half || ja > S.layer[l].n_a - 1 - P.half)
+      return false;
+    anchor[l >> 1] |= ((uint32_t)jt | ((uint32_t)ja << 10)) << (20 * (l & 1));
+  }
+  f[0] = 2.0f * (qt - it) - 1.0f;
+  f[1] = 2.0f * (qa - ia) - 1.0f;
+  f[2] = st / P.max_slope;
+  f[3] = sa / P.max_slope;
+  f[4] = 2.0f * (e - P.e_min) / (511.0f - P.e_min) - 1.0f;
+  f[5] = dl.x;
+  module = ma * S.mod_n_t + mt;
+  return true;
+}
+
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
+  constexpr bool TRACE = MODE == kModeTrace, REC = MODE == kModeRecord, SUR = MODE == kModeSurrogate;
   extern __shared__ float4 lds4[];
   const int lane = (int)__lane_id();
   const int wave = (int)(threadIdx.x >> 6);
@@ -132,6 +178,12 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   int q_gid = -1, q_mat = -1, q_trials = 0, q_back = P_PANEL;
   // wave-uniform bookkeeping: the instance the wave works on, its current
   // range of event indices, a claimed next range, and the hit staging count
+  // record mode: the pair being labelled and its per-crystal deposit sums
+  constexpr int kSlots = 8;
+  uint32_t rec_idx = ~0u, rec_anchor[2] = {0u, 0u}, rec_gid[kSlots];
+  float rec_sum[kSlots], rec_e = 0.f;
+  int rec_module = 0, rec_panel = 0, rec_n = 0;
+  bool rec_ovf = false;
   uint32_t inst = 0, inst_rng = A.inst_id[0];
   uint32_t cur_next = 0, cur_end = 0, pend_inst = 0, pend_next = 0, pend_end = 0, staged = 0;
   bool have_pend = false, exhausted = false;
@@ -267,7 +319,10 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     const float4 r = to_unit4(w);
     c_blocks += count(draw && sid != 0u);
 
-    bool hit = false, ended = false;
+    bool hit = false, ended = false, push = false;
+    float sf[6];
+    int s_module = 0;
+    uint32_t s_anchor[2] = {0u, 0u};
     float h_edep = 0.f;
     int h_proc = 0;
     bool stepped = false, real = false, searched = false, entered = false, trial = false, scattered = false,
@@ -362,6 +417,12 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
         d = dir_to_local(P, d);
         phase = P_PANEL;
         if (++steps > kMaxSteps) capped = ended = true; // bounds panel-to-panel hops as well
+        if constexpr (REC || SUR) {
+          if (last < 0 && !capped && entry_domain(S, A.sur, x, d, e, sf, s_module, s_anchor)) {
+            push = true;
+            if constexpr (SUR) ended = true; // the network takes over from here
+          }
+        }
       }
     } else if (phase == P_PANEL) {
       const Lerp lp = lerp_at(e);
@@ -458,6 +519,91 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     c_scatter += count(scattered);
     c_capped += count(capped);
 
+    // ---- record / surrogate: one atomic per wave reserves the new entries
+    if constexpr (REC || SUR) {
+      const uint64_t pm = __ballot(push);
+      if (pm) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(A.pcount, (unsigned long long)__popcll(pm));
+        base = __shfl(base, 0);
+        if (push) {
+          const unsigned long long i = base + (unsigned long long)__popcll(pm & below);
+          const bool fits = i < A.pcap;
+          if (fits) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) A.px[6 * i + k] = sf[k];
+          }
+          if constexpr (REC) {
+            if (fits) A.pevent[i] = ev;
+            rec_idx = fits ? (uint32_t)i : ~0u;
+            rec_anchor[0] = s_anchor[0];
+            rec_anchor[1] = s_anchor[1];
+            rec_module = s_module;
+            rec_panel = panel;
+            rec_e = e;
+            rec_n = 0;
+            rec_ovf = false;
+          } else if (fits) {
+            A.qev[i] = ev;
+            A.qmeta[i] = (uint32_t)ph | ((uint32_t)panel << 1) | ((uint32_t)s_module << 8);
+            A.qanchor[2 * i] = s_anchor[0];
+            A.qanchor[2 * i + 1] = s_anchor[1];
+            A.qe[i] = e;
+            A.qtime[i] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
+          }
+        }
+      }
+    }
+    if constexpr (REC) {
+      if (rec_idx != ~0u) {
+        if (hit) { // per-crystal deposit sums of the photon's stay in its first panel
+          int k = 0;
+          while (k < rec_n && rec_gid[k] != (uint32_t)q_gid) ++k;
+          if (k < rec_n) {
+            rec_sum[k] += h_edep;
+          } else if (rec_n < kSlots) {
+            rec_gid[rec_n] = (uint32_t)q_gid;
+            rec_sum[rec_n] = h_edep;
+            ++rec_n;
+          } else {
+            rec_ovf = true;
+          }
+        }
+        if (ended || phase == P_SEARCH) { // left the panel or stopped: label the pair
+          int best = -1;
+          for (int k = 0; k < rec_n; ++k)
+            if (best < 0 || rec_sum[k] > rec_sum[best] || (rec_sum[k] == rec_sum[best] && rec_gid[k] < rec_gid[best]))
+              best = k;
+          int cls = 0;
+          uint32_t flags = (rec_ovf ? 2u : 0u) | ((uint32_t)ph << 2);
+          if (best >= 0 && rec_sum[best] >= A.sur.e_min) {
+            const int g = (int)rec_gid[best];
+            const int r = g - rec_panel * S.crystals_per_panel;
+            const int m = r >= 0 ? r / S.crystals_per_module : -1;
+            const int r2 = r - m * S.crystals_per_module;
+            int l = S.n_layers - 1;
+            while (l > 0 && r2 < S.layer[l].base) --l;
+            const int idx = r2 - S.layer[l].base;
+            const int ia = idx / S.layer[l].n_t, it = idx - ia * S.layer[l].n_t;
+            const uint32_t aw = rec_anchor[l >> 1] >> (20 * (l & 1));
+            const int at = (int)(aw & 1023u), aa = (int)((aw >> 10) & 1023u);
+            const int h = A.sur.half, W = 2 * h + 1;
+            if (r < 0 || r >= S.crystals_per_panel || m != rec_module || abs(it - at) > h || abs(ia - aa) > h) {
+              flags |= 1u; // the largest deposit lies outside the neighbourhood
+            } else {
+              int b;
+              if (rec_sum[best] >= rec_e - A.sur.tol) b = A.sur.n_ebins;
+              else b = min(max((int)floorf((rec_sum[best] - A.sur.e_min) / A.sur.ebin), 0), A.sur.n_ebins - 1);
+              cls = 1 + ((l * W + (it - at + h)) * W + (ia - aa + h)) * (A.sur.n_ebins + 1) + b;
+            }
+          }
+          A.plabel[rec_idx] = cls;
+          A.pflags[rec_idx] = flags;
+          rec_idx = ~0u;
+        }
+      }
+    }
+
     // ---- stage hits in LDS; write out 64 or more at a time
     const uint64_t hm = __ballot(hit);
     if (hm) {
@@ -494,14 +640,15 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   }
 }
 
-void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st) {
+template <int MODE>
+static void launch_mode(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st) {
   // one resident wave set: as many blocks per CU as the kernel's registers and
   // LDS allow (unless the shape asks for a given number)
   const size_t lds = transport_lds_bytes(det_slots);
   int per_cu = L.blocks_per_cu;
   if (per_cu <= 0) {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transport<false>, kBlock, lds) != hipSuccess || occ < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transport<MODE>, kBlock, lds) != hipSuccess || occ < 1)
       occ = 4;
     per_cu = occ;
   }
@@ -509,12 +656,19 @@ void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int
   uint64_t grid = (uint64_t)n_cu * per_cu;
   if (need < grid) grid = need;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_transport<false>, dim3((unsigned)grid), dim3(kBlock), lds, st, A);
+  hipLaunchKernelGGL(k_transport<MODE>, dim3((unsigned)grid), dim3(kBlock), lds, st, A);
+}
+
+void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st, int mode) {
+  if (mode == kModeRecord) launch_mode<kModeRecord>(A, det_slots, L, n_cu, st);
+  else if (mode == kModeSurrogate) launch_mode<kModeSurrogate>(A, det_slots, L, n_cu, st);
+  else launch_mode<kModePlain>(A, det_slots, L, n_cu, st);
 }
 
 void launch_trace(const RunArgs &A, int det_slots, hipStream_t st) {
   const unsigned grid = (A.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_transport<true>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(det_slots), st, A);
+  hipLaunchKernelGGL(k_transport<kModeTrace>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(det_slots), st,
+                     A);
 }
 
 // ---------------------------------------------------------------------------

@@ -108,6 +108,27 @@ class Tallies(C.Structure):
                 ("energy_spectrum", C.c_void_p), ("doi", C.c_void_p), ("doi_bins", C.c_int32)]
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("batch", C.c_uint32), ("steps", C.c_uint32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+class SurrogateSpec(C.Structure):
+    _fields_ = [("half_width", C.c_int32), ("n_ebins", C.c_int32), ("e_min_kev", C.c_double),
+                ("ebin_kev", C.c_double), ("photopeak_tol_kev", C.c_double), ("max_slope", C.c_double),
+                ("front_tol_mm", C.c_double)]
+
+
+class Pairs(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("label", C.c_void_p), ("event", C.c_void_p), ("flags", C.c_void_p),
+                ("capacity", C.c_uint64), ("count", C.c_uint64)]
+
+
+class SurrogateStats(C.Structure):
+    _fields_ = [("entries", C.c_uint64), ("none", C.c_uint64), ("ms_transport", C.c_float),
+                ("ms_network", C.c_float)]
+
+
 class Instance(C.Structure):
     _fields_ = [("scanner", C.POINTER(Scanner)), ("source", C.POINTER(Source)), ("first_event", C.c_uint64),
                 ("n_events", C.c_uint64), ("instance", C.c_uint32)]
@@ -118,7 +139,10 @@ EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_s
            "gpet_philox", "gpet_tables_get", "gpet_locate", "gpet_ray_locate", "gpet_sample_compton",
            "gpet_sample_rayleigh", "gpet_trace", "gpet_ctx_enable_timing", "gpet_timings",
            "gpet_ctx_set_launch", "gpet_batch_create", "gpet_batch_destroy", "gpet_batch_info",
-           "gpet_batch_set_launch", "gpet_batch_transport", "gpet_batch_digitize", "gpet_batch_autotune")
+           "gpet_batch_set_launch", "gpet_batch_transport", "gpet_batch_digitize", "gpet_batch_autotune",
+           "gpet_mlp_create", "gpet_mlp_destroy", "gpet_mlp_set_weights", "gpet_mlp_get_weights",
+           "gpet_mlp_forward", "gpet_mlp_loss_grad", "gpet_mlp_train", "gpet_surrogate_pairs",
+           "gpet_surrogate_transport")
 
 _lib = None
 
@@ -162,8 +186,20 @@ def load_library(path: str = LIB_PATH):
     L.gpet_batch_transport.argtypes = [vp, C.c_uint64, P(Hits), P(Stats)]
     L.gpet_batch_digitize.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), vp]
     L.gpet_batch_autotune.argtypes = [vp, C.c_uint64, P(Hits), C.c_char_p, C.c_size_t]
+    L.gpet_mlp_create.argtypes = [vp, C.c_int32, vp, vp, P(vp)]
+    L.gpet_mlp_destroy.argtypes = [vp]
+    L.gpet_mlp_destroy.restype = None
+    L.gpet_mlp_set_weights.argtypes = [vp, vp]
+    L.gpet_mlp_get_weights.argtypes = [vp, vp]
+    L.gpet_mlp_forward.argtypes = [vp, C.c_uint32, vp, vp]
+    L.gpet_mlp_loss_grad.argtypes = [vp, C.c_uint32, vp, vp, P(C.c_double), vp]
+    L.gpet_mlp_train.argtypes = [vp, C.c_uint64, vp, vp, P(TrainParams), vp]
+    L.gpet_surrogate_pairs.argtypes = [vp, P(SurrogateSpec), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                                       P(Hits), P(Pairs), P(Stats)]
+    L.gpet_surrogate_transport.argtypes = [vp, vp, P(SurrogateSpec), C.c_uint64, C.c_uint64, C.c_uint64,
+                                           C.c_uint32, P(Hits), P(Stats), P(SurrogateStats)]
     for name in EXPORTS:
-        if name not in ("gpet_ctx_destroy", "gpet_last_error", "gpet_batch_destroy"):
+        if name not in ("gpet_ctx_destroy", "gpet_last_error", "gpet_batch_destroy", "gpet_mlp_destroy"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -298,10 +334,10 @@ class Context:
         self.h = h
         self.info = None
         self.scene = None
-        self._batches = weakref.WeakSet()
+        self._batches = weakref.WeakSet()  # batches and networks made from this context
 
     def close(self):
-        """Destroys the context (and first every batch made from it)."""
+        """Destroys the context (and first every batch and network made from it)."""
         for b in list(getattr(self, "_batches", ())):
             b.close()
         if getattr(self, "h", None):
@@ -520,6 +556,69 @@ class Context:
             out[n] = flts[:, k]
         return out
 
+    # ------------------------------------------------------------- surrogate
+    @staticmethod
+    def spec_struct(spec=None):
+        """SurrogateSpec from a dict or object with the oracle's Spec fields."""
+        d = {"half_width": 2, "n_ebins": 36, "e_min_kev": 224.0, "ebin_kev": 8.0, "photopeak_tol_kev": 1.0,
+             "max_slope": 0.25, "front_tol_mm": 1e-3}
+        if spec is not None:
+            d.update(spec if isinstance(spec, dict) else {k: getattr(spec, k) for k in d})
+        return SurrogateSpec(**d)
+
+    def alloc_pairs(self, capacity):
+        t = self.torch
+        return {"x": self._empty(6 * capacity, t.float32), "label": self._empty(capacity, t.int32),
+                "event": self._empty(capacity, t.int32), "flags": self._empty(capacity, t.int32),
+                "capacity": int(capacity), "count": 0}
+
+    def surrogate_pairs_into(self, hits: HitList, pairs: dict, n_events, seed=0, first=0, instance=0, spec=None):
+        h = hits.struct()
+        h.count = 0
+        pr = Pairs(pairs["x"].data_ptr(), pairs["label"].data_ptr(), pairs["event"].data_ptr(),
+                   pairs["flags"].data_ptr(), pairs["capacity"], 0)
+        st = Stats()
+        rc = self.L.gpet_surrogate_pairs(self.h, C.byref(self.spec_struct(spec)), first, n_events, seed, instance,
+                                         C.byref(h), C.byref(pr), C.byref(st))
+        hits.count = int(h.count)
+        hits.first_event, hits.n_events = first, n_events
+        pairs["count"] = int(pr.count)
+        if rc not in (OK, ERR_CAPACITY):
+            self._check(rc)
+        return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}
+
+    def surrogate_pairs(self, n_events, seed=0, first=0, instance=0, spec=None):
+        """(hits, pairs as numpy dict x/label/event/flags, stats)."""
+        hits = self.alloc_hits(max(1024, int(3.5 * n_events)))
+        pairs = self.alloc_pairs(max(1024, 2 * n_events))
+        rc, st = self.surrogate_pairs_into(hits, pairs, n_events, seed, first, instance, spec)
+        self._check(rc)
+        n = pairs["count"]
+        out = {"x": pairs["x"][: 6 * n].cpu().numpy().reshape(n, 6), "label": pairs["label"][:n].cpu().numpy(),
+               "event": pairs["event"][:n].cpu().numpy().view(np.uint32),
+               "flags": pairs["flags"][:n].cpu().numpy().view(np.uint32)}
+        return hits, out, st
+
+    def surrogate_transport_into(self, mlp, hits: HitList, n_events, seed=0, first=0, instance=0, spec=None):
+        h = hits.struct()
+        h.count = 0
+        st, ss = Stats(), SurrogateStats()
+        rc = self.L.gpet_surrogate_transport(self.h, mlp.h, C.byref(self.spec_struct(spec)), first, n_events, seed,
+                                             instance, C.byref(h), C.byref(st), C.byref(ss))
+        hits.count = int(h.count)
+        hits.first_event, hits.n_events = first, n_events
+        if rc not in (OK, ERR_CAPACITY):
+            self._check(rc)
+        sst = {"entries": int(ss.entries), "none": int(ss.none), "ms_transport": float(ss.ms_transport),
+               "ms_network": float(ss.ms_network)}
+        return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}, sst
+
+    def surrogate_transport(self, mlp, n_events, seed=0, first=0, instance=0, spec=None):
+        hits = self.alloc_hits(max(1024, int(3.5 * n_events)))
+        rc, st, sst = self.surrogate_transport_into(mlp, hits, n_events, seed, first, instance, spec)
+        self._check(rc)
+        return hits, st, sst
+
 
 class Batch:
     """A table of instances (scanner, source, event range, RNG instance id)
@@ -639,3 +738,88 @@ class Batch:
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1)
         return r
+
+
+def pack_params(params) -> np.ndarray:
+    """[(W [out, in], b [out]), ...] -> packed float32 vector (the C ABI layout)."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float32).reshape(-1), np.asarray(b, np.float32)])
+                           for W, b in params]).astype(np.float32)
+
+
+def unpack_params(flat, sizes):
+    out, o = [], 0
+    for i, j in zip(sizes[:-1], sizes[1:]):
+        W = np.asarray(flat[o:o + i * j]).reshape(j, i)
+        o += i * j
+        out.append((W, np.asarray(flat[o:o + j])))
+        o += j
+    return out
+
+
+class Mlp:
+    """The surrogate network on the GPU (BF16 matrix cores, FP32 master weights)."""
+
+    def __init__(self, ctx: Context, sizes, weights=None):
+        self.ctx, self.L = ctx, ctx.L
+        self.sizes = [int(v) for v in sizes]
+        self.n_params = sum(i * j + j for i, j in zip(self.sizes[:-1], self.sizes[1:]))
+        sz = np.array(self.sizes, np.int32)
+        w = None if weights is None else np.ascontiguousarray(weights, np.float32)
+        if w is not None and w.size != self.n_params:
+            raise ValueError("packed weights of the wrong size")
+        h = C.c_void_p()
+        ctx._check(self.L.gpet_mlp_create(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p),
+                                          None if w is None else w.ctypes.data_as(C.c_void_p), C.byref(h)), "mlp")
+        self.h = h
+        ctx._batches.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gpet_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, flat):
+        w = np.ascontiguousarray(flat, np.float32)
+        assert w.size == self.n_params
+        self.ctx._check(self.L.gpet_mlp_set_weights(self.h, w.ctypes.data_as(C.c_void_p)))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(self.n_params, np.float32)
+        self.ctx._check(self.L.gpet_mlp_get_weights(self.h, w.ctypes.data_as(C.c_void_p)))
+        return w
+
+    def _dev(self, a, dtype):
+        t = self.ctx.torch
+        if isinstance(a, t.Tensor):
+            return a.contiguous()
+        return t.from_numpy(np.ascontiguousarray(a, dtype)).to(self.ctx.dev)
+
+    def forward(self, x) -> np.ndarray:
+        xd = self._dev(x, np.float32)
+        n = xd.shape[0]
+        out = self.ctx._empty(n * self.sizes[-1], self.ctx.torch.float32)
+        self.ctx._check(self.L.gpet_mlp_forward(self.h, n, _ptr(xd), _ptr(out)))
+        return out[: n * self.sizes[-1]].cpu().numpy().reshape(n, self.sizes[-1])
+
+    def loss_grad(self, x, y):
+        xd, yd = self._dev(x, np.float32), self._dev(y, np.int32)
+        loss = C.c_double()
+        g = np.empty(self.n_params, np.float32)
+        self.ctx._check(self.L.gpet_mlp_loss_grad(self.h, xd.shape[0], _ptr(xd), _ptr(yd), C.byref(loss),
+                                                  g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+    def train(self, x, y, steps, batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        """Adam steps on device (or host) pairs; returns the per-step batch losses."""
+        xd, yd = self._dev(x, np.float32), self._dev(y, np.int32)
+        hp = TrainParams(batch, steps, lr, beta1, beta2, eps, seed)
+        losses = np.empty(max(steps, 1), np.float32)
+        self.ctx._check(self.L.gpet_mlp_train(self.h, yd.shape[0], _ptr(xd), _ptr(yd), C.byref(hp),
+                                              losses.ctypes.data_as(C.c_void_p)))
+        return losses[:steps]

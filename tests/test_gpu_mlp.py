@@ -1,0 +1,137 @@
+"""The surrogate network's matrix-core kernels through the C ABI against the
+FP64 reference: forward products (matrix-core operand layout), the gradient
+of the mean cross-entropy (every transposed product of the backward pass),
+one Adam step, and training that lowers the loss on a learnable task."""
+import numpy as np
+import pytest
+
+import gpet_inputs as G
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _bf16_params(flat, sizes):
+    return [(S.bf16_round(W), b.astype(np.float64)) for W, b in S.unpack(flat, sizes)]
+
+
+@pytest.mark.parametrize("k,n,rows", [(6, 64, 64), (64, 130, 200), (256, 1851, 1000), (250, 70, 1)])
+def test_single_layer_forward_matches_fp64(ctx, k, n, rows):
+    """logits = bf16(x) bf16(W)^T + b with FP32 accumulation: every element
+    within 1e-5 of the FP64 product of the same BF16 operands (relative to the
+    row's scale); ragged sizes exercise the padding."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    rng = np.random.default_rng(k + n)
+    P = [(rng.normal(0, 1, (n, k)).astype(np.float32), rng.normal(0, 1, n).astype(np.float32))]
+    x = rng.normal(0, 1, (rows, k)).astype(np.float32)
+    m = Mlp(ctx, [k, n], pack_params(P))
+    got = m.forward(x)
+    ref = S.bf16_round(x) @ S.bf16_round(P[0][0]).T + P[0][1].astype(np.float64)
+    scale = np.sqrt((S.bf16_round(x) ** 2).sum(1, keepdims=True) * (S.bf16_round(P[0][0]) ** 2).sum(1)[None, :])
+    assert np.max(np.abs(got - ref) / (scale + 1e-30)) < 1e-5
+    m.close()
+
+
+def test_gradient_matches_fp64_backprop(ctx):
+    """Surrogate-sized network 6 -> 4 x 256 -> 1851 on a fixed batch: loss and
+    every gradient tensor against FP64 backpropagation at the same BF16
+    weights and inputs (relative L2 error <= 2e-2 per tensor)."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    sizes = [6, *G.SURROGATE_HIDDEN, 1851]
+    P = G.mlp_init(sizes, seed=3)
+    rng = np.random.default_rng(4)
+    P = [(W, rng.normal(0, 0.05, len(b)).astype(np.float32)) for W, b in P]
+    flat = pack_params(P)
+    x = rng.uniform(-1, 1, (700, 6)).astype(np.float32)
+    y = rng.integers(0, 1851, 700).astype(np.int32)
+    y[:50] = 0
+    m = Mlp(ctx, sizes, flat)
+    loss, g = m.loss_grad(x, y)
+    ref_loss, ref_g = S.loss_and_grad(_bf16_params(flat, sizes), S.bf16_round(x), y)
+    assert abs(loss - ref_loss) / ref_loss < 1e-2, (loss, ref_loss)
+    G_gpu = S.unpack(g, sizes)
+    for k, ((gw, gb), (rw, rb)) in enumerate(zip(G_gpu, ref_g)):
+        for a, r, name in ((gw, rw, "W"), (gb, rb, "b")):
+            err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+            print(k, name, err)
+            assert err <= 2e-2, (k, name, err)
+    m.close()
+
+
+def _batch_indices(oracle_mod, seed, step, batch, n_pairs):
+    ctr = np.zeros(((batch + 3) // 4, 4), np.uint32)
+    ctr[:, 0] = step
+    ctr[:, 1] = np.arange(len(ctr))
+    ctr[:, 3] = 9
+    w = oracle_mod.philox(seed, ctr).reshape(-1)[:batch].astype(np.uint64)
+    return ((w * np.uint64(n_pairs)) >> np.uint64(32)).astype(np.int64)
+
+
+def test_one_adam_step_matches_fp64(ctx, oracle_mod):
+    """One training step: the batch drawn from the documented index stream,
+    then FP64 loss, gradient and Adam at the same BF16 weights; the step's
+    reported loss and the weight update agree."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    sizes = [6, 64, 64, 40]
+    P = G.mlp_init(sizes, seed=5)
+    flat = pack_params(P)
+    rng = np.random.default_rng(6)
+    n_pairs = 5000
+    x = rng.uniform(-1, 1, (n_pairs, 6)).astype(np.float32)
+    y = rng.integers(0, 40, n_pairs).astype(np.int32)
+    m = Mlp(ctx, sizes, flat)
+    lr = 1e-3
+    losses = m.train(x, y, steps=1, batch=512, lr=lr, seed=77)
+    w1 = m.get_weights().astype(np.float64)
+    idx = _batch_indices(oracle_mod, 77, 1, 512, n_pairs)
+    params = [(W.astype(np.float64), b.astype(np.float64)) for W, b in P]
+    loss, g = S.loss_and_grad(_bf16_params(flat, sizes), S.bf16_round(x[idx]), y[idx])
+    z = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    newp, _, _ = S.adam_step(params, g, z, z, 1, lr)
+    ref = pack_params(newp).astype(np.float64)
+    assert abs(losses[0] - loss) / loss < 1e-2
+    d_gpu, d_ref = w1 - flat, ref - flat
+    close = np.abs(d_gpu - d_ref) <= 0.05 * lr
+    print("agree", close.mean())
+    assert close.mean() > 0.97
+    m.close()
+
+
+def test_training_lowers_the_loss(ctx):
+    """A learnable task (label = argmax of a fixed random linear map of x over
+    16 classes): 300 steps take the loss from about log 16 to below a third of it."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    sizes = [6, 128, 128, 16]
+    rng = np.random.default_rng(8)
+    A = rng.normal(0, 1, (6, 16))
+    x = rng.uniform(-1, 1, (200_000, 6)).astype(np.float32)
+    y = np.argmax(x @ A, axis=1).astype(np.int32)
+    m = Mlp(ctx, sizes, pack_params(G.mlp_init(sizes, seed=9)))
+    losses = m.train(x, y, steps=300, batch=1024, lr=3e-3, seed=1)
+    print(losses[:3], losses[-3:])
+    assert abs(losses[0] - np.log(16)) < 0.5
+    assert losses[-20:].mean() < losses[0] / 3
+    m.close()
+
+
+def test_mlp_rejects_bad_labels(ctx):
+    from paper_2603_07327_amd.gpet import ERR_ARG, GpetError, Mlp
+    m = Mlp(ctx, [6, 64, 10])
+    x = np.zeros((10, 6), np.float32)
+    y = np.full(10, 3, np.int32)
+    y[4] = 10
+    with pytest.raises(GpetError) as e:
+        m.loss_grad(x, y)
+    assert e.value.code == ERR_ARG
+    m.close()

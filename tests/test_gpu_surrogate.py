@@ -1,0 +1,162 @@
+"""The surrogate path through the C ABI against the FP64 reference: recorded
+training pairs (entry domain, features and labels of RNG-matched histories),
+transport with the network (the reference composes the oracle's own
+transport of the other photons with FP64 network samples), and what a
+network trained on the pairs gains over sampling the class marginal."""
+import math
+
+import numpy as np
+import pytest
+
+import gpet_inputs as G
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _to_unit(w):
+    """Uniform in (0, 1) of a 32-bit word: (2 (w >> 9) + 1) 2^-24."""
+    return (2.0 * (np.asarray(w, np.uint64) >> np.uint64(9)).astype(np.float64) + 1.0) * 2.0**-24
+
+
+def _oracle_entries(oracle_mod, sc, n, seed, inst=0):
+    o = oracle_mod.OracleScene(sc)
+    v = o.trace(n, seed=seed, instance=inst)
+    recs = S.photon_entries(S.Spec(), sc, o.poses(), v)
+    return o, {(r["event"], r["photon"]): r for r in recs if r["entered"] and r["entry"].in_domain}
+
+
+@pytest.mark.parametrize("case", ["point", "rods_phantom"])
+def test_pairs_match_oracle(ctx, oracle_mod, case):
+    n = 20_000
+    sc = G.small_animal_scene("C", (3.0, 1.0, 2.0), n_events=n) if case == "point" else G.hot_rod_scene(n_events=n)
+    ctx.set_scene(sc)
+    _, pairs, _ = ctx.surrogate_pairs(n, seed=11)
+    _, ref = _oracle_entries(oracle_mod, sc, n, 11)
+    got = {(int(e), int((f >> 2) & 1)): k for k, (e, f) in enumerate(zip(pairs["event"], pairs["flags"]))}
+    assert len(got) == len(pairs["event"])  # one pair per photon at most
+    common = got.keys() & ref.keys()
+    union = got.keys() | ref.keys()
+    print(case, "gpu", len(got), "oracle", len(ref), "common", len(common))
+    assert len(ref) > 2000
+    assert len(union) - len(common) <= max(3, 0.002 * len(union))
+    same = 0
+    for key in common:
+        k, r = got[key], ref[key]
+        np.testing.assert_allclose(pairs["x"][k], r["entry"].x, atol=2e-3)
+        if pairs["label"][k] == r["label"]:
+            same += 1
+            assert bool(pairs["flags"][k] & 1) == r["truncated"]
+    print(case, "label agreement", same / len(common))
+    assert same >= 0.995 * len(common)
+    # labels are valid classes; class 0 covers truncation
+    assert np.all((pairs["label"] >= 0) & (pairs["label"] < 1851))
+    assert np.all(pairs["label"][(pairs["flags"] & 1) != 0] == 0)
+
+
+def _peaked_mlp_params(seed):
+    sizes = [6, 64, 64, 1851]
+    P = G.mlp_init(sizes, seed=seed)
+    W, b = P[-1]
+    P[-1] = (W * 60.0, b)
+    return sizes, P
+
+
+def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod):
+    """Hits of a surrogate run: photons outside the domain keep their full
+    transport (the oracle's hits for those photons), in-domain photons get the
+    single of the class the FP64 network samples with the same uniforms."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    n, seed = 20_000, 5
+    sc = G.hot_rod_scene(n_events=n)
+    ctx.set_scene(sc)
+    sizes, P = _peaked_mlp_params(3)
+    flat = pack_params(P)
+    m = Mlp(ctx, sizes, flat)
+    hits, st, sst = ctx.surrogate_transport(m, n, seed=seed)
+    g = hits.numpy()
+    o, ref = _oracle_entries(oracle_mod, sc, n, seed)
+    spec, lat = S.Spec(), S.Lattice(sc["scanner"])
+    print("entries gpu", sst["entries"], "oracle", len(ref), "none", sst["none"])
+    assert abs(sst["entries"] - len(ref)) <= max(3, 0.002 * len(ref))
+    # --- synthetic singles
+    keys = sorted(ref)
+    X = np.stack([ref[k]["entry"].x for k in keys])
+    logits, _, _ = S.forward([(S.bf16_round(W), b.astype(np.float64)) for W, b in S.unpack(flat, sizes)],
+                             S.bf16_round(X))
+    ev = np.array([k[0] for k in keys], np.uint32)
+    ph = np.array([k[1] for k in keys], np.uint32)
+    ctr = np.stack([np.zeros_like(ev), ev, np.zeros_like(ev), 4 + ph], 1)
+    w = oracle_mod.philox(seed, ctr)
+    cls = S.sample_class(logits, _to_unit(w[:, 0]))
+    u1 = _to_unit(w[:, 1])
+    wt = oracle_mod.philox(seed, np.stack([np.full_like(ev, 2), ev, np.zeros_like(ev), np.zeros_like(ev)], 1))
+    X64 = (wt[:, 1].astype(np.uint64) << np.uint64(32)) | wt[:, 0].astype(np.uint64)
+    dur = int(sc["source"]["duration_ps"])
+    t_e = np.array([(int(x) * dur) >> 64 for x in X64], np.int64)
+    want = {}
+    for i, k in enumerate(keys):
+        r = ref[k]
+        h = S.class_hit(spec, lat, r["entry"], r["panel"], r["e"], int(cls[i]), float(u1[i]))
+        if h is not None:
+            want[k] = (h[0], h[1], h[2], t_e[i] + math.floor(r["L"] / S.C_MM_PER_PS + 0.5))
+    proc = (g["aux"].view(np.uint32) >> 1) & 3
+    syn = proc == 3
+    have = {(int(e), int(a & 1)): (int(gi), float(ed), float(dp), int(tp)) for e, a, gi, ed, dp, tp in
+            zip(g["event"][syn].view(np.uint32), g["aux"][syn].view(np.uint32), g["gid"][syn], g["edep_kev"][syn],
+                g["depth_mm"][syn], g["time_ps"][syn])}
+    assert len(have) == int(syn.sum())
+    both = have.keys() & want.keys()
+    agree = sum(1 for k in both if have[k][0] == want[k][0] and abs(have[k][1] - want[k][1]) < 1e-3 * want[k][1]
+                and abs(have[k][2] - want[k][2]) < 1e-4 and abs(have[k][3] - want[k][3]) <= 1)
+    print("synthetic gpu", len(have), "oracle", len(want), "agree", agree)
+    assert len(want) > 1000
+    assert agree >= 0.98 * max(len(have), len(want))
+    assert sst["entries"] - sst["none"] == len(have)
+    # --- full-transport hits of the photons outside the domain
+    mc, _ = o.transport(n, seed=seed)
+    dom = set(ref)
+    keep = np.array([(int(e), int(p)) not in dom for e, p in zip(mc["event"], mc["photon"])], bool)
+    n_mc_gpu = int((~syn).sum())
+    print("mc hits gpu", n_mc_gpu, "oracle", int(keep.sum()))
+    assert abs(n_mc_gpu - keep.sum()) <= max(5, 0.003 * keep.sum())
+    m.close()
+
+
+def test_trained_network_beats_the_class_marginal(ctx):
+    """Train 6 -> 4 x 256 -> 1851 on pairs recorded from the hot-rod phantom
+    scene (seed 7) and score held-out pairs (seed 8): the network's
+    cross-entropy lies well below that of the training marginal, the
+    class-blind model the surrogate would be without its inputs."""
+    import torch
+
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    sc = G.hot_rod_scene(n_events=2_000_000)
+    ctx.set_scene(sc)
+    _, tr, _ = ctx.surrogate_pairs(2_000_000, seed=7)
+    _, te, _ = ctx.surrogate_pairs(300_000, seed=8)
+    sizes = [6, *G.SURROGATE_HIDDEN, 1851]
+    m = Mlp(ctx, sizes, pack_params(G.mlp_init(sizes, seed=1)))
+    x = torch.from_numpy(tr["x"]).to(ctx.dev)
+    y = torch.from_numpy(tr["label"]).to(ctx.dev)
+    losses = m.train(x, y, steps=1500, batch=4096, lr=1e-3, seed=3)
+    z = m.forward(te["x"])
+    zmax = z.max(1, keepdims=True)
+    ce_net = float(np.mean(np.log(np.exp(z - zmax).sum(1)) + zmax[:, 0] - z[np.arange(len(z)), te["label"]]))
+    freq = (np.bincount(tr["label"], minlength=1851) + 0.5) / (len(tr["label"]) + 0.5 * 1851)
+    ce_marg = float(np.mean(-np.log(freq[te["label"]])))
+    print("pairs", len(tr["label"]), "train loss", losses[:2], losses[-2:], "held-out CE net", ce_net,
+          "marginal", ce_marg)
+    assert ce_net < ce_marg - 0.5
+    m.close()
