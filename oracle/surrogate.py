@@ -246,16 +246,19 @@ def photon_entries(spec: Spec, sc: dict, poses: np.ndarray, v: np.ndarray):
 # ---------------------------------------------------------------------------
 # MLP in float64
 # ---------------------------------------------------------------------------
-def forward(params, x):
+def forward(params, x, store=None):
     """params: [(W [out, in], b [out]), ...]; ReLU after every layer but the
-    last.  Returns (logits, list of layer inputs, list of pre-activations)."""
+    last.  `store` (optional) rounds every hidden activation as it is stored
+    (the method keeps activations in BF16; arithmetic stays float64).
+    Returns (logits, list of layer inputs, list of pre-activations)."""
+    keep = store or (lambda a: a)
     h = np.asarray(x, np.float64)
     ins, zs = [], []
     for k, (W, b) in enumerate(params):
         ins.append(h)
         z = h @ W.T + b
         zs.append(z)
-        h = np.maximum(z, 0.0) if k < len(params) - 1 else z
+        h = keep(np.maximum(z, 0.0)) if k < len(params) - 1 else z
     return h, ins, zs
 
 
@@ -265,23 +268,26 @@ def softmax(z):
     return e / e.sum(axis=1, keepdims=True)
 
 
-def loss_and_grad(params, x, y):
+def loss_and_grad(params, x, y, store=None):
     """Mean softmax cross-entropy over the batch and its gradient with respect
-    to every weight and bias (backpropagation written out)."""
-    z, ins, zs = forward(params, x)
+    to every weight and bias (backpropagation written out).  `store`
+    (optional) rounds what the method stores between products: hidden
+    activations and the gradients with respect to pre-activations."""
+    keep = store or (lambda a: a)
+    z, ins, zs = forward(params, x, store)
     n = len(y)
     m = z.max(axis=1)
     lse = m + np.log(np.exp(z - m[:, None]).sum(axis=1))
     loss = float(np.mean(lse - z[np.arange(n), y]))
     dz = softmax(z)
     dz[np.arange(n), y] -= 1.0
-    dz /= n
+    dz = keep(dz / n)
     grads = [None] * len(params)
     for k in range(len(params) - 1, -1, -1):
         W, _ = params[k]
         grads[k] = (dz.T @ ins[k], dz.sum(axis=0))
         if k:
-            dz = (dz @ W) * (zs[k - 1] > 0.0)
+            dz = keep((dz @ W) * (ins[k] > 0.0))
     return loss, grads
 
 

@@ -844,8 +844,8 @@ static gpet_status surrogate_spec(gpet_ctx *c, const gpet_surrogate_spec *p, Sur
   const DevScene &S = c->scene;
   const int W = 2 * p->half_width + 1;
   for (int l = 0; l < S.n_layers; ++l)
-    if (S.layer[l].n_t < W || S.layer[l].n_a < W || S.layer[l].n_t > 1023 || S.layer[l].n_a > 1023)
-      return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: a layer is narrower than the neighbourhood (or wider than 1023)");
+    if (S.layer[l].n_t < W || S.layer[l].n_a < W || S.layer[l].n_t > 65535 || S.layer[l].n_a > 65535)
+      return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: a layer is narrower than the neighbourhood (or wider than 65535)");
   if (S.n_panels > 127 || S.mod_n_t * S.mod_n_a > (1 << 24))
     return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: more than 127 panels or 2^24 modules");
   P.half = p->half_width;
@@ -900,7 +900,7 @@ static gpet_status ensure_queue(gpet_ctx *c, size_t cap) {
   Q = SurQueue{};
   const size_t tmp = scan_tmp_words(cap);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t bytes = al(cap * 24) + al(cap * 4) * 6 + al(cap * 8) * 2 + al(tmp * 4);
+  const size_t bytes = al(cap * 24) + al(cap * 4) * 6 + al(cap * 4 * kMaxLayers) + al(cap * 8) + al(tmp * 4);
   if (hipMalloc(&Q.blob, bytes) != hipSuccess) {
     Q.blob = nullptr;
     return fail(c, GPET_ERR_HIP, "surrogate: queue allocation failed");
@@ -917,7 +917,7 @@ static gpet_status ensure_queue(gpet_ctx *c, size_t cap) {
   Q.meta = (uint32_t *)take(cap * 4);
   Q.cls = (uint32_t *)take(cap * 4);
   Q.pos = (uint32_t *)take(cap * 4);
-  Q.anchor = (uint32_t *)take(cap * 8);
+  Q.anchor = (uint32_t *)take(cap * 4 * kMaxLayers);
   Q.time = (unsigned long long *)take(cap * 8);
   Q.scan_tmp = (uint32_t *)take(tmp * 4);
   Q.cap = cap;

@@ -51,8 +51,8 @@ struct RunArgs {
   // record and surrogate modes: photons entering their first panel inside the
   // surrogate domain get an entry with features px (6 per entry).  Record:
   // label and flags once the photon leaves the panel.  Surrogate: an entry
-  // queue (event, meta = photon | panel << 1 | module << 8, two words of
-  // packed per-layer anchors, entry energy, entry time) and the photon ends.
+  // queue (event, meta = photon | panel << 1 | module << 8, one anchor word
+  // per layer i_t | i_a << 16, entry energy, entry time) and the photon ends.
   SurSpecD sur;
   float *px;
   int32_t *plabel;
@@ -204,7 +204,7 @@ struct gpet_mlp {
   gpet_ctx *ctx = nullptr;
   int device = 0;
   std::vector<int> size;  // layer widths, input first
-  std::vector<int> psize; // widths padded to multiples of 64
+  std::vector<int> psize; // padded widths: input to a multiple of 64, the others of 128
   int n_layers = 0;       // weight matrices
   size_t n_params = 0;
   std::vector<size_t> w_off, b_off;                  // offsets in the packed parameter vector
@@ -223,6 +223,7 @@ struct gpet_mlp {
   uint32_t *idx = nullptr;
   double *row_loss = nullptr, *loss_sum = nullptr;
   uint32_t *flag = nullptr; // bit 0: a label outside the classes
+  float *part = nullptr, *part_b = nullptr; // split-K partial weight gradients, partial bias sums
 };
 
 namespace gpet {

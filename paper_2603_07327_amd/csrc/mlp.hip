@@ -7,8 +7,9 @@
 // of 16 x 16), stepping K by 32.  Operands are staged in LDS K-contiguous, so
 // each lane feeds an MFMA with one 16-byte LDS read per operand; operands that
 // are K-strided in memory (the transposes of the backward pass) are transposed
-// on their way into LDS.  Sizes are padded to multiples of 64; padded weights
-// and biases are zero and padded rows carry zero gradient.
+// on their way into LDS.  Rows and layer widths are padded to multiples of
+// 128, the input width to 64; padded weights and biases are zero and padded
+// rows carry zero gradient.
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -21,7 +22,8 @@ namespace gpet {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64;
+constexpr int kTile = 64;     // input width padding
+constexpr int kRowPad = 128;  // padding of rows and layer widths (128 x 128 product tiles)
 constexpr int kTk = 32;
 constexpr int kLdsRow = kTk + 8; // bf16 per LDS row (padding against bank conflicts)
 
@@ -34,72 +36,115 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_BF16 = 3 };
 
-// C[m][n] = sum_k A(m, k) B(k, n) over a padded problem (M, N multiples of 64,
-// K a multiple of 32).  A(m, k) = a[m lda + k] (AT: a[k lda + m]);
-// B(k, n) = b[n ldb + k] (BT: b[k ldb + n]).  Epilogue per EPI.
-template <bool AT, bool BT, int EPI>
+// C[m][n] = sum_k A(m, k) B(k, n) over a padded problem (M a multiple of BM,
+// N of BN, K of 32).  A(m, k) = a[m lda + k] (AT: a[k lda + m]);
+// B(k, n) = b[n ldb + k] (BT: b[k ldb + n]).  Four waves in a 2 x 2 grid,
+// each computing a (BM / 2) x (BN / 2) block of 16 x 16 MFMA tiles; the
+// next K step's operands are loaded into registers while the current one is
+// multiplied.  Epilogue per EPI.
+template <int BM, int BN, bool AT, bool BT, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, int lda, const uint16_t *__restrict__ b,
                                               int ldb, int K, const float *__restrict__ bias,
-                                              const uint16_t *__restrict__ mask, void *__restrict__ out, int ldc) {
-  __shared__ __attribute__((aligned(16))) uint16_t sa[kTile * kLdsRow];
-  __shared__ __attribute__((aligned(16))) uint16_t sb[kTile * kLdsRow];
+                                              const uint16_t *__restrict__ mask, void *__restrict__ out, int ldc,
+                                              size_t split_stride) {
+  // split K: slice z covers [z K, (z + 1) K) and writes its partial product
+  // split_stride elements further on (EPI_F32 only)
+  const int kz = blockIdx.z * K;
+  if constexpr (AT) a += (size_t)kz * lda;
+  else a += kz;
+  if constexpr (BT) b += (size_t)kz * ldb;
+  else b += kz;
+  if constexpr (EPI == EPI_F32) out = (float *)out + blockIdx.z * split_stride;
+  constexpr int TM = BM / 32, TN = BN / 32; // MFMA tiles per wave and axis
+  constexpr int PA = BM / 64, PB = BN / 64; // 16-byte loads per thread and operand
+  __shared__ __attribute__((aligned(16))) uint16_t sa[BM * kLdsRow];
+  __shared__ __attribute__((aligned(16))) uint16_t sb[BN * kLdsRow];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  floatx4 acc[2][2];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  floatx4 acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[PA], rb[PB];
+  // global -> registers for the K step at k0
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+      const int t = tid + 256 * p;
+      if constexpr (!AT) ra[p] = *(const uint4 *)&a[(size_t)(m0 + (t >> 2)) * lda + k0 + (t & 3) * 8];
+      else ra[p] = *(const uint4 *)&a[(size_t)(k0 + t / (BM / 8)) * lda + m0 + (t % (BM / 8)) * 8];
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+      const int t = tid + 256 * p;
+      if constexpr (!BT) rb[p] = *(const uint4 *)&b[(size_t)(n0 + (t >> 2)) * ldb + k0 + (t & 3) * 8];
+      else rb[p] = *(const uint4 *)&b[(size_t)(k0 + t / (BN / 8)) * ldb + n0 + (t % (BN / 8)) * 8];
+    }
+  };
+  // registers -> LDS, K-contiguous rows
+  auto store = [&]() {
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+      const int t = tid + 256 * p;
+      if constexpr (!AT) {
+        *(uint4 *)&sa[(t >> 2) * kLdsRow + (t & 3) * 8] = ra[p];
+      } else {
+        const int kk = t / (BM / 8), c = (t % (BM / 8)) * 8;
+        const uint16_t *e = (const uint16_t *)&ra[p];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sa[(c + j) * kLdsRow + kk] = e[j];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+      const int t = tid + 256 * p;
+      if constexpr (!BT) {
+        *(uint4 *)&sb[(t >> 2) * kLdsRow + (t & 3) * 8] = rb[p];
+      } else {
+        const int kk = t / (BN / 8), c = (t % (BN / 8)) * 8;
+        const uint16_t *e = (const uint16_t *)&rb[p];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sb[(c + j) * kLdsRow + kk] = e[j];
+      }
+    }
+  };
+  load(0);
+  store();
+  __syncthreads();
+  const int lr = lane & 15, lk = (lane >> 4) * 8; // lane l: row/column l % 16, k = 8 (l / 16) .. + 8
   for (int k0 = 0; k0 < K; k0 += kTk) {
-    // ---- stage A (64 x 32) and B (32 x 64) K-contiguous in LDS
-    if constexpr (!AT) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      *(uint4 *)&sa[r * kLdsRow + c] = *(const uint4 *)&a[(size_t)(m0 + r) * lda + k0 + c];
-    } else {
-      const int kk = tid >> 3, c = (tid & 7) * 8;
-      const uint4 v = *(const uint4 *)&a[(size_t)(k0 + kk) * lda + m0 + c];
-      const uint16_t *e = (const uint16_t *)&v;
+    const bool more = k0 + kTk < K;
+    if (more) load(k0 + kTk);
+    bf16x8 fa[TM], fb[TN];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sa[(c + j) * kLdsRow + kk] = e[j];
-    }
-    if constexpr (!BT) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      *(uint4 *)&sb[r * kLdsRow + c] = *(const uint4 *)&b[(size_t)(n0 + r) * ldb + k0 + c];
-    } else {
-      const int kk = tid >> 3, c = (tid & 7) * 8;
-      const uint4 v = *(const uint4 *)&b[(size_t)(k0 + kk) * ldb + n0 + c];
-      const uint16_t *e = (const uint16_t *)&v;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) sb[(c + j) * kLdsRow + kk] = e[j];
-    }
-    __syncthreads();
-    // ---- lane l feeds row/column l % 16 with k = 8 (l / 16) .. + 8
-    const int lr = lane & 15, lk = (lane >> 4) * 8;
-    bf16x8 fa[2], fb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < TM; ++i)
       fa[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sa[(wm + 16 * i + lr) * kLdsRow + lk]);
-      fb[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sb[(wn + 16 * i + lr) * kLdsRow + lk]);
-    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < TN; ++j)
+      fb[j] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sb[(wn + 16 * j + lr) * kLdsRow + lk]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
   }
   // ---- epilogue: lane l holds column l % 16, rows 4 (l / 16) .. + 4 of each tile
-  const int cn = lane & 15, rb = (lane >> 4) * 4;
+  const int cn = lane & 15, rb4 = (lane >> 4) * 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm + 16 * i + rb + q, n = n0 + wn + 16 * j + cn;
-        float v = acc[i][j][q];
+        const int m = m0 + wm + 16 * i + rb4 + q, n = n0 + wn + 16 * j + cn;
+        const float v = acc[i][j][q];
         const size_t o = (size_t)m * ldc + n;
         if constexpr (EPI == EPI_BIAS_RELU_BF16) {
           ((uint16_t *)out)[o] = f2bf(fmaxf(v + bias[n], 0.0f));
@@ -113,12 +158,36 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, in
       }
 }
 
+// 128 x 128 tiles where both sizes allow them (the wide layers), else 64 x 64;
+// `splits` K slices (K / splits a multiple of 32), partial products
+// split_stride elements apart
 template <bool AT, bool BT, int EPI>
 static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, int N, int K, const float *bias,
-                 const uint16_t *mask, void *out, int ldc, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), dim3(N / kTile, M / kTile), dim3(256), 0, st, a, lda, b, ldb, K, bias, mask,
-                     out, ldc);
+                 const uint16_t *mask, void *out, int ldc, hipStream_t st, int splits = 1, size_t split_stride = 0) {
+  const int Ks = K / splits;
+  if (M % 128 == 0 && N % 128 == 0)
+    hipLaunchKernelGGL((k_gemm<128, 128, AT, BT, EPI>), dim3(N / 128, M / 128, splits), dim3(256), 0, st, a, lda, b,
+                       ldb, Ks, bias, mask, out, ldc, split_stride);
+  else
+    hipLaunchKernelGGL((k_gemm<64, 64, AT, BT, EPI>), dim3(N / 64, M / 64, splits), dim3(256), 0, st, a, lda, b, ldb,
+                       Ks, bias, mask, out, ldc, split_stride);
 }
+
+// number of K slices for an M x N product over K rows: enough blocks for
+// the whole chip, each slice at least 128 deep and K / slices a multiple of 32
+static int split_want(int M, int N) {
+  const int tiles = (M % 128 == 0 && N % 128 == 0) ? (M / 128) * (N / 128) : (M / 64) * (N / 64);
+  return (1024 + tiles - 1) / tiles;
+}
+static int split_count(int M, int N, int K) {
+  const int want = split_want(M, N);
+  int best = 1;
+  for (int s = 1; s <= want && s * 128 <= K; ++s)
+    if (K % (32 * s) == 0) best = s;
+  return best;
+}
+// upper bound of split_count over every K <= K_max
+static int split_bound(int M, int N, int K_max) { return std::max(1, std::min(split_want(M, N), K_max / 128)); }
 
 // ---------------------------------------------------------------------------
 // elementwise and reduction kernels
@@ -187,13 +256,25 @@ __global__ void __launch_bounds__(1024) k_sum_f64(const double *v, uint32_t n, d
   if (threadIdx.x == 0) *out = s[0];
 }
 
-// db[c] = sum over rows of dz[r][c]
-__global__ void k_col_sum(const uint16_t *dz, int ld, uint32_t rows, int cols, float *db) {
+// partial column sums: slice blockIdx.y of `slices` sums its rows of dz into
+// part[slice][c]
+__global__ void k_col_sum_part(const uint16_t *dz, int ld, uint32_t rows, int cols, int slices, float *part) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
+  const uint32_t per = (rows + slices - 1) / slices;
+  const uint32_t r0 = blockIdx.y * per, r1 = min(rows, r0 + per);
   float a = 0.f;
-  for (uint32_t r = 0; r < rows; ++r) a += bf2f(dz[(size_t)r * ld + c]);
-  db[c] = a;
+  for (uint32_t r = r0; r < r1; ++r) a += bf2f(dz[(size_t)r * ld + c]);
+  part[(size_t)blockIdx.y * cols + c] = a;
+}
+
+// out[i] = sum over s of part[s n + i] (slices summed in order)
+__global__ void k_reduce_slices(const float *part, int slices, size_t n, float *out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float a = 0.f;
+  for (int s = 0; s < slices; ++s) a += part[(size_t)s * n + i];
+  out[i] = a;
 }
 
 // Adam on one tensor: master [rows][cols] against gradients with row stride
@@ -300,8 +381,8 @@ __global__ void k_emit_hits(uint32_t n, const uint32_t *cls, const uint32_t *pos
   const int b = c % nb, k = c / nb;
   const int l = k / (W * W), rr = k - l * W * W;
   const int dt = rr / W, da = rr - dt * W;
-  const uint32_t aw = anchor[2 * r + (l >> 1)] >> (20 * (l & 1));
-  const int it = (int)(aw & 1023u) + dt - P.half, ia = (int)((aw >> 10) & 1023u) + da - P.half;
+  const uint32_t aw = anchor[(size_t)kMaxLayers * r + l];
+  const int it = (int)(aw & 0xFFFFu) + dt - P.half, ia = (int)(aw >> 16) + da - P.half;
   const uint32_t m = meta[r];
   const int panel = (int)((m >> 1) & 127u), module = (int)(m >> 8);
   const int gid = panel * S.crystals_per_panel + module * S.crystals_per_module + S.layer[l].base +
@@ -340,9 +421,10 @@ void free_workspace(gpet_mlp *q) {
     if (p) (void)hipFree(p);
   q->act.clear();
   for (void *p : {(void *)q->logits, (void *)q->dz[0], (void *)q->dz[1], (void *)q->yb, (void *)q->idx,
-                  (void *)q->row_loss, (void *)q->loss_sum, (void *)q->flag})
+                  (void *)q->row_loss, (void *)q->loss_sum, (void *)q->flag, (void *)q->part, (void *)q->part_b})
     if (p) (void)hipFree(p);
   q->flag = nullptr;
+  q->part = q->part_b = nullptr;
   q->logits = nullptr;
   q->dz[0] = q->dz[1] = nullptr;
   q->yb = nullptr;
@@ -353,7 +435,7 @@ void free_workspace(gpet_mlp *q) {
 
 // workspace for at least n rows (rounded up to a tile)
 gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
-  const uint32_t need = (uint32_t)pad_to((int)std::max<uint32_t>(n, 1), kTile);
+  const uint32_t need = (uint32_t)pad_to((int)std::max<uint32_t>(n, 1), kRowPad);
   if (need <= q->cap) return GPET_OK;
   free_workspace(q);
   bool ok = true;
@@ -371,6 +453,14 @@ gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
   ok = ok && hipMalloc((void **)&q->row_loss, (size_t)need * 8) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->loss_sum, 8) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->flag, 8) == hipSuccess;
+  // split-K partial products of the weight gradients and partial bias sums
+  size_t part = 0;
+  for (int l = 0; l < q->n_layers; ++l) {
+    const int M = q->psize[l + 1], N = q->psize[l];
+    part = std::max(part, (size_t)split_bound(M, N, (int)need) * M * N);
+  }
+  ok = ok && hipMalloc((void **)&q->part, part * 4) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->part_b, (size_t)64 * widest * 4) == hipSuccess;
   if (!ok) {
     free_workspace(q);
     return mlp_fail(q, GPET_ERR_HIP, "mlp: workspace allocation failed");
@@ -402,10 +492,22 @@ void backward(gpet_mlp *q, uint32_t n, uint32_t n_pad, hipStream_t st) {
   int cur = 0;
   for (int l = L - 1; l >= 0; --l) {
     const int K = q->psize[l], N = q->psize[l + 1];
-    // dW[o][i] = sum_r dz[r][o] act[r][i]: A = dz^T (M = N, K = rows), B(k = r, n = i) = act[r][i]
-    gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, (int)n_pad, nullptr, nullptr, q->gw[l], K, st);
-    hipLaunchKernelGGL(k_col_sum, dim3(cdiv(q->size[l + 1], 256)), dim3(256), 0, st, q->dz[cur], N, n_pad,
-                       q->size[l + 1], q->gb + q->b_off[l]);
+    // dW[o][i] = sum_r dz[r][o] act[r][i]: A = dz^T (M = N, K = rows), B(k = r, n = i) = act[r][i];
+    // split over rows into partial products, then summed in slice order
+    const int sp = split_count(N, K, (int)n_pad);
+    const size_t ne = (size_t)N * K;
+    if (sp > 1) {
+      gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, (int)n_pad, nullptr, nullptr, q->part, K, st, sp,
+                                ne);
+      hipLaunchKernelGGL(k_reduce_slices, dim3(cdiv(ne, 256)), dim3(256), 0, st, q->part, sp, ne, q->gw[l]);
+    } else {
+      gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, (int)n_pad, nullptr, nullptr, q->gw[l], K, st);
+    }
+    const int cols = q->size[l + 1], slices = (int)std::min<uint32_t>(64u, std::max<uint32_t>(1u, n_pad / 128));
+    hipLaunchKernelGGL(k_col_sum_part, dim3(cdiv(cols, 256), slices), dim3(256), 0, st, q->dz[cur], N, n_pad, cols,
+                       slices, q->part_b);
+    hipLaunchKernelGGL(k_reduce_slices, dim3(cdiv(cols, 256)), dim3(256), 0, st, q->part_b, slices, (size_t)cols,
+                       q->gb + q->b_off[l]);
     if (l) {
       // dh[r][i] = sum_o dz[r][o] W[o][i], masked by the ReLU of layer l's input
       gemm<false, true, EPI_MASK_BF16>(q->dz[cur], N, q->wb[l], K, (int)n_pad, K, N, nullptr, q->act[l],
@@ -429,7 +531,7 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
   const int C = q->size[q->n_layers], Cp = q->psize[q->n_layers];
   for (uint32_t off = 0; off < nq; off += kChunk) {
     const uint32_t n = std::min(kChunk, nq - off);
-    const uint32_t n_pad = (uint32_t)pad_to((int)n, kTile);
+    const uint32_t n_pad = (uint32_t)pad_to((int)n, kRowPad);
     hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, Q.x + (size_t)6 * off,
                        (const int32_t *)nullptr, (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad,
                        q->act[0], (int32_t *)nullptr);
@@ -482,7 +584,7 @@ gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, 
   q->n_layers = n_sizes - 1;
   q->psize.resize(n_sizes);
   q->psize[0] = pad_to(sizes[0], kTile);
-  for (int i = 1; i < n_sizes; ++i) q->psize[i] = pad_to(sizes[i], kTile);
+  for (int i = 1; i < n_sizes; ++i) q->psize[i] = pad_to(sizes[i], kRowPad);
   size_t o = 0;
   for (int l = 0; l < q->n_layers; ++l) {
     q->w_off.push_back(o);
@@ -569,7 +671,7 @@ gpet_status gpet_mlp_forward(gpet_mlp *q, uint32_t n, const float *x, float *log
   gpet_status s = ensure_workspace(q, n);
   if (s) return s;
   hipStream_t st = q->ctx->stream;
-  const uint32_t n_pad = (uint32_t)pad_to((int)n, kTile);
+  const uint32_t n_pad = (uint32_t)pad_to((int)n, kRowPad);
   hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, x, (const int32_t *)nullptr,
                      (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad, q->act[0], (int32_t *)nullptr);
   forward(q, n_pad, st);
@@ -588,7 +690,7 @@ gpet_status gpet_mlp_loss_grad(gpet_mlp *q, uint32_t n, const float *x, const in
   gpet_status s = ensure_workspace(q, n);
   if (s) return s;
   hipStream_t st = q->ctx->stream;
-  const uint32_t n_pad = (uint32_t)pad_to((int)n, kTile);
+  const uint32_t n_pad = (uint32_t)pad_to((int)n, kRowPad);
   launch_fill_u32(q->flag, 0u, 1, st);
   hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, x, y, (const uint32_t *)nullptr, n,
                      q->size[0], q->psize[0], n_pad, q->act[0], q->yb);
@@ -626,7 +728,7 @@ gpet_status gpet_mlp_train(gpet_mlp *q, uint64_t n_pairs, const float *x, const 
   gpet_status s = ensure_workspace(q, hp->batch);
   if (s) return s;
   hipStream_t st = q->ctx->stream;
-  const uint32_t n = hp->batch, n_pad = (uint32_t)pad_to((int)n, kTile);
+  const uint32_t n = hp->batch, n_pad = (uint32_t)pad_to((int)n, kRowPad);
   std::vector<double> losses(hp->steps, 0.0);
   double *d_losses = nullptr;
   if (hp->steps && hipMalloc((void **)&d_losses, (size_t)hp->steps * 8) != hipSuccess)

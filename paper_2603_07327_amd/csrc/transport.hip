@@ -100,11 +100,11 @@ __device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, u
 // every layer's neighbourhood around its anchor crystal inside the layer's
 // array.  Anchors: the last layer's crystal whose pitch cell holds the
 // mid-depth point; in another layer, the crystal whose cell holds that cell's
-// centre.  Outputs the 6 features, the module and the anchors (10 bits per
-// index, (i_t, i_a) per layer, two layers per word).
+// centre.  Outputs the 6 features, the module and the anchors (one word per
+// layer: i_t | i_a << 16).
 template <class SC>
 __device__ __forceinline__ bool entry_domain(SC &S, const SurSpecD &P, const Vec &xl, const Vec &dl, float e,
-                                             float f[6], int &module, uint32_t anchor[2]) {
+                                             float f[6], int &module, uint32_t anchor[kMaxLayers]) {
   if (!(e >= P.e_min) || fabsf(xl.x) > P.front_tol || !(dl.x > 0.0f)) return false;
   const float st = dl.y / dl.x, sa = dl.z / dl.x;
   if (fabsf(st) > P.max_slope || fabsf(sa) > P.max_slope) return false;
@@ -121,13 +121,12 @@ __device__ __forceinline__ bool entry_domain(SC &S, const SurSpecD &P, const Vec
   const float qt = (ut - rt) / pt, qa = (ua - ra) / pa;
   const float it = floorf(qt), ia = floorf(qa);
   const float ct = rt + (it + 0.5f) * pt, ca = ra + (ia + 0.5f) * pa;
-  anchor[0] = anchor[1] = 0u;
   for (int l = 0; l < nl; ++l) {
     const int jt = (int)floorf((ct - S.layer[l].off_t) / S.layer[l].pitch_t + 1e-3f);
     const int ja = (int)floorf((ca - S.layer[l].off_a) / S.layer[l].pitch_a + 1e-3f);
     if (jt < P.half || jt > S.layer[l].n_t - 1 - P.half || ja < P.half || ja > S.layer[l].n_a - 1 - P.half)
       return false;
-    anchor[l >> 1] |= ((uint32_t)jt | ((uint32_t)ja << 10)) << (20 * (l & 1));
+    anchor[l] = (uint32_t)jt | ((uint32_t)ja << 16);
   }
   f[0] = 2.0f * (qt - it) - 1.0f;
   f[1] = 2.0f * (qa - ia) - 1.0f;
@@ -180,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   // range of event indices, a claimed next range, and the hit staging count
   // record mode: the pair being labelled and its per-crystal deposit sums
   constexpr int kSlots = 8;
-  uint32_t rec_idx = ~0u, rec_anchor[2] = {0u, 0u}, rec_gid[kSlots];
+  uint32_t rec_idx = ~0u, rec_anchor[kMaxLayers] = {0u, 0u, 0u, 0u}, rec_gid[kSlots];
   float rec_sum[kSlots], rec_e = 0.f;
   int rec_module = 0, rec_panel = 0, rec_n = 0;
   bool rec_ovf = false;
@@ -322,7 +321,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     bool hit = false, ended = false, push = false;
     float sf[6];
     int s_module = 0;
-    uint32_t s_anchor[2] = {0u, 0u};
+    uint32_t s_anchor[kMaxLayers] = {0u, 0u, 0u, 0u};
     float h_edep = 0.f;
     int h_proc = 0;
     bool stepped = false, real = false, searched = false, entered = false, trial = false, scattered = false,
@@ -536,8 +535,8 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
           if constexpr (REC) {
             if (fits) A.pevent[i] = ev;
             rec_idx = fits ? (uint32_t)i : ~0u;
-            rec_anchor[0] = s_anchor[0];
-            rec_anchor[1] = s_anchor[1];
+#pragma unroll
+            for (int l = 0; l < kMaxLayers; ++l) rec_anchor[l] = s_anchor[l];
             rec_module = s_module;
             rec_panel = panel;
             rec_e = e;
@@ -546,8 +545,8 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
           } else if (fits) {
             A.qev[i] = ev;
             A.qmeta[i] = (uint32_t)ph | ((uint32_t)panel << 1) | ((uint32_t)s_module << 8);
-            A.qanchor[2 * i] = s_anchor[0];
-            A.qanchor[2 * i + 1] = s_anchor[1];
+#pragma unroll
+            for (int l = 0; l < kMaxLayers; ++l) A.qanchor[kMaxLayers * i + l] = s_anchor[l];
             A.qe[i] = e;
             A.qtime[i] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
           }
@@ -585,8 +584,8 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
             while (l > 0 && r2 < S.layer[l].base) --l;
             const int idx = r2 - S.layer[l].base;
             const int ia = idx / S.layer[l].n_t, it = idx - ia * S.layer[l].n_t;
-            const uint32_t aw = rec_anchor[l >> 1] >> (20 * (l & 1));
-            const int at = (int)(aw & 1023u), aa = (int)((aw >> 10) & 1023u);
+            const uint32_t aw = rec_anchor[l];
+            const int at = (int)(aw & 0xFFFFu), aa = (int)(aw >> 16);
             const int h = A.sur.half, W = 2 * h + 1;
             if (r < 0 || r >= S.crystals_per_panel || m != rec_module || abs(it - at) > h || abs(ia - aa) > h) {
               flags |= 1u; // the largest deposit lies outside the neighbourhood

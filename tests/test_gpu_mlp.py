@@ -44,9 +44,14 @@ def test_single_layer_forward_matches_fp64(ctx, k, n, rows):
 
 
 def test_gradient_matches_fp64_backprop(ctx):
-    """Surrogate-sized network 6 -> 4 x 256 -> 1851 on a fixed batch: loss and
-    every gradient tensor against FP64 backpropagation at the same BF16
-    weights and inputs (relative L2 error <= 2e-2 per tensor)."""
+    """Surrogate-sized network 6 -> 4 x 256 -> 1851 on a fixed batch, against
+    FP64 backpropagation at the same BF16 weights and inputs.  The method
+    stores activations and pre-activation gradients in BF16, so the reference
+    rounds them at the same points (float64 arithmetic otherwise): every
+    gradient tensor within 1e-2 relative L2 of it.  Against pure float64 the
+    GPU stays within 1.2x of the BF16-storage reference's own distance
+    (which grows toward the input layer: about 0.2 % at the output, 5 % at
+    the first layer for this batch)."""
     from paper_2603_07327_amd.gpet import Mlp, pack_params
     sizes = [6, *G.SURROGATE_HIDDEN, 1851]
     P = G.mlp_init(sizes, seed=3)
@@ -58,14 +63,21 @@ def test_gradient_matches_fp64_backprop(ctx):
     y[:50] = 0
     m = Mlp(ctx, sizes, flat)
     loss, g = m.loss_grad(x, y)
-    ref_loss, ref_g = S.loss_and_grad(_bf16_params(flat, sizes), S.bf16_round(x), y)
-    assert abs(loss - ref_loss) / ref_loss < 1e-2, (loss, ref_loss)
+    Pb = _bf16_params(flat, sizes)
+    ref_loss, ref_g = S.loss_and_grad(Pb, S.bf16_round(x), y, store=S.bf16_round)
+    f64_loss, f64_g = S.loss_and_grad(Pb, S.bf16_round(x), y)
+    assert abs(loss - ref_loss) / ref_loss < 1e-3, (loss, ref_loss)
+    assert abs(loss - f64_loss) / f64_loss < 1e-2, (loss, f64_loss)
     G_gpu = S.unpack(g, sizes)
-    for k, ((gw, gb), (rw, rb)) in enumerate(zip(G_gpu, ref_g)):
-        for a, r, name in ((gw, rw, "W"), (gb, rb, "b")):
-            err = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
-            print(k, name, err)
-            assert err <= 2e-2, (k, name, err)
+    for k in range(len(sizes) - 1):
+        for j, name in ((0, "W"), (1, "b")):
+            a, r, f = G_gpu[k][j], ref_g[k][j], f64_g[k][j]
+            err = np.linalg.norm(a - r) / np.linalg.norm(r)
+            e64 = np.linalg.norm(a - f) / np.linalg.norm(f)
+            r64 = np.linalg.norm(r - f) / np.linalg.norm(f)
+            print(k, name, "vs bf16-storage", err, "vs fp64", e64, "storage alone", r64)
+            assert err <= 1e-2, (k, name, err)
+            assert e64 <= 1.2 * r64 + 1e-3, (k, name, e64, r64)
     m.close()
 
 

@@ -51,15 +51,21 @@ def test_pairs_match_oracle(ctx, oracle_mod, case):
     print(case, "gpu", len(got), "oracle", len(ref), "common", len(common))
     assert len(ref) > 2000
     assert len(union) - len(common) <= max(3, 0.002 * len(union))
-    same = 0
+    same = checked = 0
     for key in common:
         k, r = got[key], ref[key]
+        # a mid-depth point within 1e-4 of a cell boundary may fall on either
+        # side in FP32 (feature -1 instead of +1, anchor one crystal over)
+        if np.any(np.abs(np.abs(r["entry"].x[:2]) - 1.0) < 2e-4):
+            continue
+        checked += 1
         np.testing.assert_allclose(pairs["x"][k], r["entry"].x, atol=2e-3)
         if pairs["label"][k] == r["label"]:
             same += 1
             assert bool(pairs["flags"][k] & 1) == r["truncated"]
-    print(case, "label agreement", same / len(common))
-    assert same >= 0.995 * len(common)
+    print(case, "label agreement", same / checked, "checked", checked)
+    assert checked >= 0.99 * len(common)
+    assert same >= 0.995 * checked
     # labels are valid classes; class 0 covers truncation
     assert np.all((pairs["label"] >= 0) & (pairs["label"] < 1851))
     assert np.all(pairs["label"][(pairs["flags"] & 1) != 0] == 0)
