@@ -206,9 +206,37 @@ __global__ void k_pack_input(const float *x, const int32_t *y, const uint32_t *i
   if (yb && c == 0) yb[r] = live ? y[src] : -1;
 }
 
+// Row statistics of a logit row by one wave: running maximum m and sum of
+// exp(z - m) over the first C entries, 4 consecutive entries per lane per
+// 256-entry tile (16-byte loads; ld a multiple of 4), combined across lanes.
+__device__ __forceinline__ void row_max_sum(const float *zr, int C, int lane, float &m, float &s) {
+  m = -INFINITY;
+  s = 0.f;
+  for (int c0 = 4 * lane; c0 < C; c0 += 256) {
+    const float4 v = *(const float4 *)(zr + c0);
+    const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (c0 + j >= C) break;
+      if (e[j] > m) {
+        s *= __expf(m - e[j]);
+        m = e[j];
+      }
+      s += __expf(e[j] - m);
+    }
+  }
+  float M = m;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) M = fmaxf(M, __shfl_xor(M, o));
+  s = m == -INFINITY ? 0.f : s * __expf(m - M);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  m = M;
+}
+
 // one wave per row: loss = logsumexp(z) - z[y]; dz = (softmax(z) - onehot(y)) / n
-// as bf16 (zero in padded columns and rows)
-// (a label outside [0, C) sets *bad and is read as class 0)
+// as bf16 (zero in padded columns and rows); a label outside [0, C) sets *bad
+// and is read as class 0
 __global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int C, const int32_t *y, uint32_t n,
                                                     uint32_t n_pad, float inv_n, uint16_t *dz, double *row_loss,
                                                     uint32_t *bad) {
@@ -222,23 +250,25 @@ __global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int
     if (lane == 0) row_loss[r] = 0.0;
     return;
   }
-  float mx = -INFINITY;
-  for (int c = lane; c < C; c += 64) mx = fmaxf(mx, zr[c]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-  float s = 0.f;
-  for (int c = lane; c < C; c += 64) s += __expf(zr[c] - mx);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  float mx, s;
+  row_max_sum(zr, C, lane, mx, s);
   const float inv_s = 1.0f / s;
   int yy = y[r];
   if (yy < 0 || yy >= C) {
     if (lane == 0) atomicOr(bad, 1u);
     yy = 0;
   }
-  for (int c = lane; c < ldz; c += 64) {
-    const float p = c < C ? __expf(zr[c] - mx) * inv_s : 0.0f;
-    dr[c] = f2bf(((c == yy ? p - 1.0f : p)) * inv_n);
+  for (int c0 = 4 * lane; c0 < ldz; c0 += 256) {
+    const float4 v = *(const float4 *)(zr + c0);
+    const float e[4] = {v.x, v.y, v.z, v.w};
+    uint16_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + j;
+      const float p = c < C ? __expf(e[j] - mx) * inv_s : 0.0f;
+      o[j] = f2bf((c == yy ? p - 1.0f : p) * inv_n);
+    }
+    *(uint2 *)(dr + c0) = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
   }
   if (lane == 0) row_loss[r] = (double)mx + log((double)s) - (double)zr[yy];
 }
@@ -317,9 +347,10 @@ __global__ void k_batch_indices(uint32_t k0, uint32_t k1, uint32_t step, uint32_
 // ---------------------------------------------------------------------------
 // surrogate sampling: one wave per queue entry
 // ---------------------------------------------------------------------------
-// class = first c whose cumulative softmax mass reaches u * total; each lane
-// sums a contiguous run of classes, a wave scan orders the runs, and the lane
-// holding the crossing walks its run in the same order
+// class = first c whose cumulative softmax mass reaches u * total: the row's
+// maximum and total in one pass, then 256-class tiles in class order (4
+// consecutive classes per lane, a wave prefix sum per tile) until the tile
+// that crosses, where the crossing lane walks its 4 classes
 __global__ void __launch_bounds__(256) k_sample_classes(const float *z, int ldz, int C, uint32_t n, const uint32_t *ev,
                                                         const uint32_t *meta, uint32_t k0, uint32_t k1,
                                                         uint32_t inst_rng, uint32_t *cls, uint32_t *nonzero) {
@@ -327,40 +358,45 @@ __global__ void __launch_bounds__(256) k_sample_classes(const float *z, int ldz,
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
   const float *zr = z + (size_t)r * ldz;
-  float mx = -INFINITY;
-  for (int c = lane; c < C; c += 64) mx = fmaxf(mx, zr[c]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-  const int per = (C + 63) / 64;
-  const int lo = min(lane * per, C), hi = min(lo + per, C);
-  float part = 0.f;
-  for (int c = lo; c < hi; ++c) part += __expf(zr[c] - mx);
-  float incl = part;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const float t = __shfl_up(incl, o);
-    if (lane >= o) incl += t;
-  }
-  const float total = __shfl(incl, 63);
+  float mx, total;
+  row_max_sum(zr, C, lane, mx, total);
   const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
   const float target = to_unit(w.x) * total;
-  const uint64_t crossed = __ballot(incl >= target && hi > lo);
   int c_out = C - 1;
-  if (crossed) {
-    const int L = __ffsll((unsigned long long)crossed) - 1;
-    int found = C - 1;
-    if (lane == L) {
-      float acc = incl - part;
-      found = hi - 1;
-      for (int c = lo; c < hi; ++c) {
-        acc += __expf(zr[c] - mx);
-        if (acc >= target) {
-          found = c;
+  float acc = 0.f; // mass of the tiles before this one
+  for (int t0 = 0; t0 < C; t0 += 256) {
+    const int c0 = t0 + 4 * lane;
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c0 < C) {
+      const float4 v = *(const float4 *)(zr + c0);
+      const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p[j] = c0 + j < C ? __expf(e[j] - mx) : 0.f;
+    }
+    const float part = (p[0] + p[1]) + (p[2] + p[3]);
+    float incl = part;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const float tt = __shfl_up(incl, o);
+      if (lane >= o) incl += tt;
+    }
+    const uint64_t crossed = __ballot(acc + incl >= target && c0 < C);
+    if (crossed) {
+      const int L = __ffsll((unsigned long long)crossed) - 1;
+      int found = min(c0 + 3, C - 1);
+      float a = acc + incl - part;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a += p[j];
+        if (a >= target && c0 + j < C) {
+          found = c0 + j;
           break;
         }
       }
+      c_out = __shfl(found, L);
+      break;
     }
-    c_out = __shfl(found, L);
+    acc += __shfl(incl, 63);
   }
   if (lane == 0) {
     cls[r] = (uint32_t)c_out;
