@@ -7,9 +7,9 @@
 // of 16 x 16), stepping K by 32.  Operands are staged in LDS K-contiguous, so
 // each lane feeds an MFMA with one 16-byte LDS read per operand; operands that
 // are K-strided in memory (the transposes of the backward pass) are transposed
-// on their way into LDS.  Rows and layer widths are padded to multiples of
-// 128, the input width to 64; padded weights and biases are zero and padded
-// rows carry zero gradient.
+// on their way into LDS.  Rows are padded to multiples of 256, layer widths
+// to 128 and the input width to 64; padded weights and biases are zero and
+// padded rows carry zero gradient.
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -23,7 +23,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;     // input width padding
-constexpr int kRowPad = 128;  // padding of rows and layer widths (128 x 128 product tiles)
+constexpr int kRowPad = 256;   // padding of rows (256-row product tiles)
+constexpr int kWidthPad = 128; // padding of layer widths (128-column product tiles)
 constexpr int kTk = 32;
 constexpr int kLdsRow = kTk + 8; // bf16 per LDS row (padding against bank conflicts)
 
@@ -158,12 +159,98 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, in
       }
 }
 
+// The forward products (both operands K-contiguous, K <= 256): a 256 x 128
+// block of 8 waves (64 x 64 each) keeps its whole 128-column slab of the
+// weights in LDS for the full K and streams the activations through a
+// double-buffered 256 x 32 LDS stage (one barrier per K step), the next
+// stage's rows loaded into registers while the current one is multiplied.
+constexpr int kNtKmax = 256;
+constexpr int kNtRowB = kNtKmax + 8; // bf16 per weight-slab row in LDS
+constexpr size_t kNtLds = (size_t)(128 * kNtRowB + 2 * 256 * kLdsRow) * sizeof(uint16_t);
+
+template <int EPI>
+__global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a, int lda,
+                                                 const uint16_t *__restrict__ b, int ldb, int K,
+                                                 const float *__restrict__ bias, void *__restrict__ out, int ldc) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_nt[];
+  uint16_t *sbw = lds_nt;                   // 128 x kNtRowB weight slab
+  uint16_t *sac = lds_nt + 128 * kNtRowB;   // 2 x 256 x kLdsRow activation stages
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 256, n0 = blockIdx.x * 128;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int kc = K / 8; // 16-byte chunks per row
+  for (int t = tid; t < 128 * kc; t += 512) {
+    const int r = t / kc, c = (t - r * kc) * 8;
+    *(uint4 *)&sbw[r * kNtRowB + c] = *(const uint4 *)&b[(size_t)(n0 + r) * ldb + c];
+  }
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // thread t moves rows (t >> 2) and (t >> 2) + 128, chunk t & 3, of each activation stage
+  const int ar = tid >> 2, ac = (tid & 3) * 8;
+  const uint16_t *pa = a + (size_t)(m0 + ar) * lda + ac;
+  const size_t half = (size_t)128 * lda;
+  uint4 r0 = *(const uint4 *)pa, r1 = *(const uint4 *)(pa + half);
+  *(uint4 *)&sac[ar * kLdsRow + ac] = r0;
+  *(uint4 *)&sac[(ar + 128) * kLdsRow + ac] = r1;
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  int q = 0;
+  for (int k0 = 0; k0 < K; k0 += kTk) {
+    const bool more = k0 + kTk < K;
+    if (more) {
+      r0 = *(const uint4 *)(pa + k0 + kTk);
+      r1 = *(const uint4 *)(pa + half + k0 + kTk);
+    }
+    const uint16_t *sa = sac + q * 256 * kLdsRow;
+    bf16x8 fa[4], fb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fa[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sa[(wm + 16 * i + fr) * kLdsRow + fk]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      fb[j] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sbw[(wn + 16 * j + fr) * kNtRowB + k0 + fk]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      uint16_t *sn = sac + (q ^ 1) * 256 * kLdsRow;
+      *(uint4 *)&sn[ar * kLdsRow + ac] = r0;
+      *(uint4 *)&sn[(ar + 128) * kLdsRow + ac] = r1;
+    }
+    __syncthreads();
+    q ^= 1;
+  }
+  const int cn = lane & 15, rb4 = (lane >> 4) * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int m = m0 + wm + 16 * i + rb4 + qq, n = n0 + wn + 16 * j + cn;
+        const float v = acc[i][j][qq] + bias[n];
+        const size_t o = (size_t)m * ldc + n;
+        if constexpr (EPI == EPI_BIAS_RELU_BF16) ((uint16_t *)out)[o] = f2bf(fmaxf(v, 0.0f));
+        else ((float *)out)[o] = v;
+      }
+}
+
 // 128 x 128 tiles where both sizes allow them (the wide layers), else 64 x 64;
 // `splits` K slices (K / splits a multiple of 32), partial products
 // split_stride elements apart
 template <bool AT, bool BT, int EPI>
 static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, int N, int K, const float *bias,
                  const uint16_t *mask, void *out, int ldc, hipStream_t st, int splits = 1, size_t split_stride = 0) {
+  if constexpr (!AT && !BT && (EPI == EPI_BIAS_RELU_BF16 || EPI == EPI_BIAS_F32)) {
+    if (M % 256 == 0 && N % 128 == 0 && K % kTk == 0 && K <= kNtKmax) {
+      hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3(N / 128, M / 256), dim3(512), kNtLds, st, a, lda, b, ldb, K, bias, out,
+                         ldc);
+      return;
+    }
+  }
   const int Ks = K / splits;
   if (M % 128 == 0 && N % 128 == 0)
     hipLaunchKernelGGL((k_gemm<128, 128, AT, BT, EPI>), dim3(N / 128, M / 128, splits), dim3(256), 0, st, a, lda, b,
@@ -620,7 +707,7 @@ gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, 
   q->n_layers = n_sizes - 1;
   q->psize.resize(n_sizes);
   q->psize[0] = pad_to(sizes[0], kTile);
-  for (int i = 1; i < n_sizes; ++i) q->psize[i] = pad_to(sizes[i], kRowPad);
+  for (int i = 1; i < n_sizes; ++i) q->psize[i] = pad_to(sizes[i], kWidthPad);
   size_t o = 0;
   for (int l = 0; l < q->n_layers; ++l) {
     q->w_off.push_back(o);
