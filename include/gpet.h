@@ -445,6 +445,21 @@ gpet_status gpet_surrogate_transport(gpet_ctx *ctx, gpet_mlp *mlp, const gpet_su
                                      uint64_t first_event, uint64_t n_events, uint64_t seed, uint32_t instance,
                                      gpet_hits *hits, gpet_stats *stats, gpet_surrogate_stats *sstats);
 
+/* HIP graph of the batched transport step, for callers that replay one batch
+ * step many times from a tight loop: gpet_batch_graph_capture records the
+ * reset of the context's counters and the persistent transport launch for
+ * this seed and these hit buffers (hits->instance required) into a graph
+ * owned by the batch, replacing an earlier one; the launch shape and chunk
+ * size in force are baked in.  gpet_batch_graph_launch enqueues it on the
+ * context's stream and returns without synchronizing; every replay
+ * reproduces gpet_batch_transport's hits.  gpet_batch_read_counts
+ * synchronizes the stream and returns the hit count (GPET_ERR_CAPACITY if it
+ * exceeds the capacity) and stats (may be NULL) of the last transport on
+ * the context, eager or replayed. */
+gpet_status gpet_batch_graph_capture(gpet_batch *batch, uint64_t seed, gpet_hits *hits);
+gpet_status gpet_batch_graph_launch(gpet_batch *batch);
+gpet_status gpet_batch_read_counts(gpet_batch *batch, gpet_hits *hits, gpet_stats *stats);
+
 /* Launch shape of the transport kernel: blocks of 256 lanes per compute unit
  * (0 = as many as fit); the scheduling of lane actions within a wavefront
  * (0: every pending action runs each loop trip, with panel searches held until

@@ -1160,10 +1160,11 @@ gpet_status gpet_batch_create(gpet_ctx *c, int32_t n, const gpet_instance *inst,
 
 void gpet_batch_destroy(gpet_batch *b) {
   if (!b) return;
-  if (b->d_blob) { // the context may be gone already: touch only the device
+  if (b->d_blob || b->graph) { // the context may be gone already: touch only the device
     (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
-    (void)hipFree(b->d_blob);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->d_blob) (void)hipFree(b->d_blob);
   }
   delete b;
 }
@@ -1214,6 +1215,67 @@ gpet_status gpet_batch_transport(gpet_batch *b, uint64_t seed, gpet_hits *h, gpe
   A.schedule = b->shape.schedule;
   set_hits(A, h);
   return run_transport(c, A, b->det_slots, b->shape, h, stats);
+}
+
+gpet_status gpet_batch_graph_capture(gpet_batch *b, uint64_t seed, gpet_hits *h) {
+  gpet_status s = batch_ready(b);
+  if (s) return s;
+  gpet_ctx *c = b->ctx;
+  if (!h) return fail(c, GPET_ERR_ARG, "batch graph: null hits");
+  if (!hits_ok(h) || (h->capacity && !h->instance)) return fail(c, GPET_ERR_ARG, "batch graph: null hit array");
+  RunArgs A = b->base;
+  A.k0 = (uint32_t)seed;
+  A.k1 = (uint32_t)(seed >> 32);
+  A.search_batch = b->shape.search_batch;
+  A.schedule = b->shape.schedule;
+  set_hits(A, h);
+  hipStream_t cs = nullptr;
+  if (hipStreamCreate(&cs) != hipSuccess) return fail(c, GPET_ERR_HIP, "batch graph: stream creation failed");
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 26, cs); // a kernel, not a memset node
+    if (A.total_chunks) launch_transport(A, b->det_slots, b->shape, c->n_cu, cs);
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess && g;
+  }
+  ok = ok && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (!ok) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return fail(c, GPET_ERR_HIP, "batch graph: capture failed");
+  }
+  if (b->graph) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipGraphExecDestroy(b->graph);
+  }
+  b->graph = exec;
+  return GPET_OK;
+}
+
+gpet_status gpet_batch_graph_launch(gpet_batch *b) {
+  gpet_status s = batch_ready(b);
+  if (s) return s;
+  if (!b->graph) return fail(b->ctx, GPET_ERR_STATE, "batch graph: nothing captured");
+  return hip_check(b->ctx, hipGraphLaunch(b->graph, b->ctx->stream), "batch graph: launch");
+}
+
+gpet_status gpet_batch_read_counts(gpet_batch *b, gpet_hits *h, gpet_stats *stats) {
+  gpet_status s = batch_ready(b);
+  if (s) return s;
+  gpet_ctx *c = b->ctx;
+  if (!h) return fail(c, GPET_ERR_ARG, "batch counts: null hits");
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 12 * 8, hipMemcpyDeviceToHost, c->stream), "batch counts");
+  if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "batch counts");
+  if (s) return s;
+  h->count = c->h_ctrl[1];
+  if (stats) {
+    uint64_t *o = (uint64_t *)stats;
+    for (int k = 0; k < 10; ++k) o[k] = c->h_ctrl[2 + k];
+  }
+  if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "batch counts: hit capacity too small");
+  return GPET_OK;
 }
 
 gpet_status gpet_batch_digitize(gpet_batch *b, const gpet_hits *h, const gpet_digitizer *p, gpet_singles *sg,

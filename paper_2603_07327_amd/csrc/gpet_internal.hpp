@@ -194,6 +194,7 @@ struct gpet_batch {
   gpet::LaunchShape shape{};
   char *d_blob = nullptr;
   uint32_t *d_prefix = nullptr;
+  hipGraphExec_t graph = nullptr; // captured transport step (gpet_batch_graph_capture)
   gpet::RunArgs base{}; // table pointers and controls; hits and seed set per call
 };
 

@@ -142,7 +142,8 @@ EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_s
            "gpet_batch_set_launch", "gpet_batch_transport", "gpet_batch_digitize", "gpet_batch_autotune",
            "gpet_mlp_create", "gpet_mlp_destroy", "gpet_mlp_set_weights", "gpet_mlp_get_weights",
            "gpet_mlp_forward", "gpet_mlp_loss_grad", "gpet_mlp_train", "gpet_surrogate_pairs",
-           "gpet_surrogate_transport")
+           "gpet_surrogate_transport", "gpet_batch_graph_capture", "gpet_batch_graph_launch",
+           "gpet_batch_read_counts")
 
 _lib = None
 
@@ -194,6 +195,9 @@ def load_library(path: str = LIB_PATH):
     L.gpet_mlp_forward.argtypes = [vp, C.c_uint32, vp, vp]
     L.gpet_mlp_loss_grad.argtypes = [vp, C.c_uint32, vp, vp, P(C.c_double), vp]
     L.gpet_mlp_train.argtypes = [vp, C.c_uint64, vp, vp, P(TrainParams), vp]
+    L.gpet_batch_graph_capture.argtypes = [vp, C.c_uint64, P(Hits)]
+    L.gpet_batch_graph_launch.argtypes = [vp]
+    L.gpet_batch_read_counts.argtypes = [vp, P(Hits), P(Stats)]
     L.gpet_surrogate_pairs.argtypes = [vp, P(SurrogateSpec), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
                                        P(Hits), P(Pairs), P(Stats)]
     L.gpet_surrogate_transport.argtypes = [vp, vp, P(SurrogateSpec), C.c_uint64, C.c_uint64, C.c_uint64,
@@ -691,6 +695,26 @@ class Batch:
             rc, stats = self.transport_into(hits, seed)
             self.ctx._check(rc)
         return hits, stats
+
+    def graph_capture(self, hits: HitList, seed=0):
+        """Capture the transport step (counter reset + persistent launch) into a HIP graph."""
+        h = hits.struct()
+        h.count = 0
+        self.ctx._check(self.L.gpet_batch_graph_capture(self.h, seed, C.byref(h)))
+
+    def graph_launch(self):
+        """Enqueue the captured step on the context's stream (no synchronization)."""
+        self.ctx._check(self.L.gpet_batch_graph_launch(self.h))
+
+    def read_counts(self, hits: HitList):
+        """Synchronize; (status, stats) of the last transport, hit count into hits."""
+        h = hits.struct()
+        st = Stats()
+        rc = self.L.gpet_batch_read_counts(self.h, C.byref(h), C.byref(st))
+        hits.count = int(h.count)
+        if rc not in (OK, ERR_CAPACITY):
+            self.ctx._check(rc)
+        return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
                       e_hi=650.0, window_ps=3000):
