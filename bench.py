@@ -35,20 +35,28 @@ import gpet_inputs as G  # noqa: E402
 # 4: the weighted instruction counts of straight-line gfx950 builds of each
 # primitive in its division-free form (hardware reciprocal, rsq, sin/cos in
 # revolutions, 64-bit-multiply Philox), minus an empty load/store kernel.
-UNIT_COST = {"philox": 156, "step": 142, "kahn": 38, "rotation": 54, "slab": 88, "source": 18}
+UNIT_COST = {"philox": 156, "step": 142, "kahn": 38, "rotation": 54, "slab": 88, "source": 18,
+             "ring_test": 65, "ring_axial": 26, "ring_prune": 131}
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (no packed FP32)
 EVENT_BLOCKS = 3              # Philox blocks of the event stream per annihilation
 TRANSPORT_SOURCES = ("paper_2603_07327_amd/csrc/transport.hip", "paper_2603_07327_amd/csrc/gpet_device.hpp")
 
 
-def algorithmic_work(stats: dict, n_panels: int) -> float:
+def algorithmic_work(stats: dict, ring: bool = True) -> float:
     """VALU lane-ops the method needs for a transport launch with these counts:
     W = N_blocks c_philox + N_steps c_step + N_trials c_kahn + N_scatter c_rot
-        + N_search n_panels c_slab + N_events c_source."""
+        + W_search + N_events c_source, where for a ring of panels
+    W_search = N_search c_axial + N_tests c_ring_test + N_pruned c_prune
+    (N_tests: panel boxes tested, N_pruned: searches that first narrowed the
+    candidates by azimuth) and otherwise N_tests c_slab."""
+    if ring:
+        w_search = (stats["searches"] * UNIT_COST["ring_axial"] + stats["panel_tests"] * UNIT_COST["ring_test"]
+                    + stats["pruned_searches"] * UNIT_COST["ring_prune"])
+    else:
+        w_search = stats["panel_tests"] * UNIT_COST["slab"]
     return ((stats["blocks"] + EVENT_BLOCKS * stats["events"]) * UNIT_COST["philox"]
             + stats["steps"] * UNIT_COST["step"] + stats["kahn_trials"] * UNIT_COST["kahn"]
-            + stats["scatters"] * UNIT_COST["rotation"] + stats["searches"] * n_panels * UNIT_COST["slab"]
-            + stats["events"] * UNIT_COST["source"])
+            + stats["scatters"] * UNIT_COST["rotation"] + w_search + stats["events"] * UNIT_COST["source"])
 
 
 def transport_source_hash() -> str:
@@ -332,7 +340,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=10_000_000, help="events per design and position")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--search-batch", type=int, default=48)
+    ap.add_argument("--search-batch", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -390,7 +398,7 @@ def main():
                 raise RuntimeError("digitizer capacity too small")
             if record:
                 kernel_ms.append(c.timings()[0])
-                work.append(algorithmic_work(st, 12))
+                work.append(algorithmic_work(st, ring=True))
                 stats_last = st
             out.append((d, hits.count, singles.count, nc))
         return out

@@ -217,7 +217,10 @@ typedef struct {
 typedef struct {
   uint64_t events, panel_entries, steps, real_interactions, kahn_trials, panel_searches,
       rng_blocks, capped, scatters;
-  uint64_t wave_trips; /* loop trips summed over wavefronts (64 lanes each) */
+  uint64_t wave_trips;      /* loop trips summed over wavefronts (64 lanes each) */
+  uint64_t panel_tests;     /* panel boxes tested by the searches */
+  uint64_t pruned_searches; /* searches from inside a repeated ring that tested only the panels
+                               whose azimuth range the ray sweeps */
 } gpet_stats;
 
 /* Transport events [first_event, first_event + n_events) with key `seed`.

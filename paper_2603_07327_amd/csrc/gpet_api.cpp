@@ -190,6 +190,16 @@ gpet_status build_geometry(gpet_ctx *c, const gpet_scanner *g, std::vector<int> 
   S.depth = (float)g->depth_mm;
   S.half_w = (float)(0.5 * g->width_mm);
   S.half_l = (float)(0.5 * g->length_mm);
+  S.ring_reg = (S.ring && g->placement == GPET_PLACE_REPEAT && g->radius_mm > 0.0) ? 1 : 0;
+  if (S.ring_reg) {
+    const double R = g->radius_mm, hw = 0.5 * g->width_mm, D = g->depth_mm;
+    S.ring_R2 = (float)(R * R * (1.0 - 2e-6));
+    S.ring_rmax2 = (float)(((R + D) * (R + D) + hw * hw) * (1.0 + 2e-6));
+    S.ring_n = (float)g->n_panels;
+    S.ring_u0 = (float)(g->phi0_rad * g->n_panels / (2.0 * kPi));
+    // half span, plus twice the azimuth approximation's bound (6.0e-4 turn) and rounding slack
+    S.ring_a = (float)(std::atan(hw / R) * g->n_panels / (2.0 * kPi) + 2.0 * 6.0e-4 * g->n_panels + 1e-3);
+  }
   S.mod_n_t = g->mod_n_t;
   S.mod_n_a = g->mod_n_a;
   S.mod_t0 = (float)(-0.5 * w_mod);
@@ -312,6 +322,12 @@ gpet_status build_source(gpet_ctx *c, const gpet_source *src, DevScene &S, std::
 void set_geometry_fields(DevScene &S, const DevScene &G) {
   S.n_panels = G.n_panels;
   S.ring = G.ring;
+  S.ring_reg = G.ring_reg;
+  S.ring_R2 = G.ring_R2;
+  S.ring_rmax2 = G.ring_rmax2;
+  S.ring_n = G.ring_n;
+  S.ring_u0 = G.ring_u0;
+  S.ring_a = G.ring_a;
   S.depth = G.depth;
   S.half_w = G.half_w;
   S.half_l = G.half_l;
@@ -353,6 +369,7 @@ gpet_status gpet_ctx_create(int device, void *hip_stream, gpet_ctx **out) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
     c->n_cu = cu;
+  static_assert(kCtrlWords <= 16, "control words");
   if (hipMalloc((void **)&c->d_ctrl, 16 * sizeof(unsigned long long)) != hipSuccess) {
     delete c;
     return GPET_ERR_HIP;
@@ -622,24 +639,22 @@ static void set_hits(RunArgs &A, gpet_hits *h) {
 }
 
 // runs a prepared transport launch and reads back the counts
-// device controls: [0] event-chunk counter, [1] hit count, [2..11] stats,
-// [12] pairs / surrogate entries
 static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, int det_slots, const LaunchShape &shape,
                                  gpet_hits *h, gpet_stats *stats, int mode = kModePlain) {
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 26, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
   if (A.total_chunks) launch_transport(A, det_slots, shape, c->n_cu, c->stream, mode);
   if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
   gpet_status s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
-  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 13 * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, kCtrlWords * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
   if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "transport: kernel");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (c->timing) (void)hipEventElapsedTime(&c->last_ms[0], c->ev[0], c->ev[1]);
   if (stats) {
     uint64_t *o = (uint64_t *)stats;
-    for (int k = 0; k < 10; ++k) o[k] = c->h_ctrl[2 + k];
+    for (int k = 0; k < kStatCount; ++k) o[k] = c->h_ctrl[2 + k];
   }
   if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "transport: hit capacity too small");
   return GPET_OK;
@@ -825,7 +840,7 @@ gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, u
   A.vflt = vflt;
   A.vcount = counts;
   A.max_vertices = maxv;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 24, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
   launch_fill_u32((uint32_t *)counts, 0u, 2 * (size_t)n, c->stream);
   if (n) launch_trace(A, c->scene.n_det_slots, c->stream);
   s = hip_check(c, hipGetLastError(), "trace: launch");
@@ -883,10 +898,10 @@ gpet_status gpet_surrogate_pairs(gpet_ctx *c, const gpet_surrogate_spec *spec, u
   A.plabel = pairs->label;
   A.pflags = pairs->flags;
   A.pevent = pairs->event;
-  A.pcount = c->d_ctrl + 12;
+  A.pcount = c->d_ctrl + kCtrlPairs;
   A.pcap = pairs->capacity;
   s = run_transport(c, A, c->scene.n_det_slots, c->shape, h, stats, kModeRecord);
-  pairs->count = c->h_ctrl[12];
+  pairs->count = c->h_ctrl[kCtrlPairs];
   if (s) return s;
   if (pairs->count > pairs->capacity) return fail(c, GPET_ERR_CAPACITY, "surrogate pairs: pair capacity too small");
   return GPET_OK;
@@ -950,7 +965,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     if (hipEventCreate(&e) != hipSuccess) return fail(c, GPET_ERR_HIP, "surrogate: event creation failed");
   float ms_t = 0.f, ms_n = 0.f;
   uint64_t entries = 0, none = 0;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 26, c->stream);
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
   for (uint64_t off = 0; off < n && !s; off += kSlice) {
     const uint64_t len = std::min(kSlice, n - off);
     RunArgs A;
@@ -964,19 +979,19 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     A.qanchor = Q.anchor;
     A.qe = Q.e;
     A.qtime = Q.time;
-    A.pcount = c->d_ctrl + 12;
+    A.pcount = c->d_ctrl + kCtrlPairs;
     A.pcap = Q.cap;
     launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2, c->stream);        // event-chunk counter
-    launch_fill_u32((uint32_t *)(c->d_ctrl + 12), 0u, 2, c->stream); // queue count
+    launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairs), 0u, 2, c->stream); // queue count
     (void)hipEventRecord(ev[0], c->stream);
     launch_transport(A, c->scene.n_det_slots, c->shape, c->n_cu, c->stream, kModeSurrogate);
     (void)hipEventRecord(ev[1], c->stream);
     s = hip_check(c, hipGetLastError(), "surrogate: transport launch");
-    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + 12, c->d_ctrl + 12, 8, hipMemcpyDeviceToHost, c->stream),
+    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairs, c->d_ctrl + kCtrlPairs, 8, hipMemcpyDeviceToHost, c->stream),
                           "surrogate: readback");
     if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "surrogate: transport");
     if (s) break;
-    const uint64_t nq = c->h_ctrl[12];
+    const uint64_t nq = c->h_ctrl[kCtrlPairs];
     if (nq > Q.cap) {
       s = fail(c, GPET_ERR_HIP, "surrogate: entry queue overflow");
       break;
@@ -999,12 +1014,12 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   }
   for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
   if (s) return s;
-  s = hip_check(c, hipMemcpy(c->h_ctrl, c->d_ctrl, 12 * 8, hipMemcpyDeviceToHost), "surrogate: readback");
+  s = hip_check(c, hipMemcpy(c->h_ctrl, c->d_ctrl, kCtrlWords * 8, hipMemcpyDeviceToHost), "surrogate: readback");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (stats) {
     uint64_t *o = (uint64_t *)stats;
-    for (int k = 0; k < 10; ++k) o[k] = c->h_ctrl[2 + k];
+    for (int k = 0; k < kStatCount; ++k) o[k] = c->h_ctrl[2 + k];
   }
   if (ss) {
     ss->entries = entries;
@@ -1235,7 +1250,7 @@ gpet_status gpet_batch_graph_capture(gpet_batch *b, uint64_t seed, gpet_hits *h)
   hipGraphExec_t exec = nullptr;
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 26, cs); // a kernel, not a memset node
+    launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, cs); // a kernel, not a memset node
     if (A.total_chunks) launch_transport(A, b->det_slots, b->shape, c->n_cu, cs);
     ok = hipStreamEndCapture(cs, &g) == hipSuccess && g;
   }
@@ -1266,13 +1281,13 @@ gpet_status gpet_batch_read_counts(gpet_batch *b, gpet_hits *h, gpet_stats *stat
   if (s) return s;
   gpet_ctx *c = b->ctx;
   if (!h) return fail(c, GPET_ERR_ARG, "batch counts: null hits");
-  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 12 * 8, hipMemcpyDeviceToHost, c->stream), "batch counts");
+  s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, kCtrlWords * 8, hipMemcpyDeviceToHost, c->stream), "batch counts");
   if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "batch counts");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (stats) {
     uint64_t *o = (uint64_t *)stats;
-    for (int k = 0; k < 10; ++k) o[k] = c->h_ctrl[2 + k];
+    for (int k = 0; k < kStatCount; ++k) o[k] = c->h_ctrl[2 + k];
   }
   if (h->count > h->capacity) return fail(c, GPET_ERR_CAPACITY, "batch counts: hit capacity too small");
   return GPET_OK;
@@ -1325,7 +1340,7 @@ gpet_status gpet_batch_autotune(gpet_batch *b, uint64_t seed, gpet_hits *h, char
   };
   s = gpet_batch_transport(b, seed, h, nullptr); // warm-up
   const int bpcs[] = {0, 2, 4};
-  const int sbs[] = {32, 40, 48, 56, 64};
+  const int sbs[] = {8, 16, 24, 32, 48};
   const uint32_t chunks[] = {64, 256, 1024, 4096};
   for (uint32_t ch : chunks)
     if (!s) s = run(best.bpc, best.sb, ch);

@@ -52,6 +52,13 @@ struct DevScene {
   // panels
   int n_panels;
   int ring; // all panels have axial axis +z and one common axial offset
+  // repeated ring (evenly spaced panels, front faces at one radius): searches
+  // from inside the front-face radius test only the panels whose azimuth
+  // range the ray sweeps while between that radius and the outer one
+  int ring_reg;
+  float ring_R2, ring_rmax2; // squared front-face radius (shrunk by 2e-6) and outer corner radius
+  float ring_n, ring_u0;     // panels per turn; panel 0's azimuth in panel units
+  float ring_a;              // half azimuth span of a panel in panel units, plus the azimuth error bound
   float depth, half_w, half_l;
   // n_panels x 12: rows of the local axes (depth, t, a) in global coordinates,
   // then the front-face centre projected on them; local = R x - R o
@@ -247,6 +254,90 @@ __device__ __forceinline__ int panel_search_ring(SC &S, Vec x, Vec d, int exclud
   }
   t_in = bt;
   return best;
+}
+
+// Azimuth of (x, y) in turns, (-1/2, 1/2]: octant reduction and the
+// arctangent approximation atan(z) ~ z (pi/4 + 0.273 (1 - z)) on [0, 1]
+// (Rajan et al., IEEE Signal Processing Magazine 2006), whose error stays
+// below 0.0038 rad = 6.0e-4 turn.
+__device__ __forceinline__ float azimuth_turns(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float z = fminf(ax, ay) * rcp(fmaxf(fmaxf(ax, ay), 1e-30f));
+  float t = z * (0.125f + 0.0434494f * (1.0f - z));
+  if (ay > ax) t = 0.25f - t;
+  if (x < 0.0f) t = 0.5f - t;
+  return y < 0.0f ? -t : t;
+}
+
+// The ring search restricted to candidate panels (same tests, same result)
+// for a repeated ring.  Every point of panel k lies within atan(w / 2R) of
+// k's axis in azimuth and at a radius in [R, r_max].  Along the ray the
+// azimuth changes monotonically (the line does not wrap around the axis), so
+// only panels whose azimuth range meets the sweep of the part of the ray that
+// can still lie in that radius band are candidates: from the ray's start (or
+// its first crossing of R when it starts inside R, or of r_max when it starts
+// beyond) to its last exit through r_max.  u is the azimuth in panel units;
+// ring_a includes the azimuth approximation's error.  A sweep of nearly half
+// a turn (a ray passing by the axis) takes the full search.  Ties keep the
+// lower index as in the full search.
+template <class SC>
+__device__ __forceinline__ int panel_search_ring_pruned(SC &S, Vec x, Vec d, int exclude, float &t_in, int &tested) {
+  tested = 0;
+  t_in = INFINITY;
+  const float a = d.x * d.x + d.y * d.y, b = x.x * d.x + x.y * d.y, c0 = x.x * x.x + x.y * x.y;
+  float ta = 0.0f, tb = 0.0f;
+  if (!(a > 1e-20f)) {
+    // parallel to the axis: the radius stays put
+    if (c0 < S.ring_R2 || c0 > S.ring_rmax2) return -1;
+  } else {
+    const float inv_a = rcp(a);
+    const float disc = b * b - a * (c0 - S.ring_rmax2);
+    if (!(disc >= 0.0f)) return -1; // never within r_max
+    const float sq = hw_sqrt(disc);
+    tb = (-b + sq) * inv_a;
+    if (tb < 0.0f) return -1; // only moves away beyond r_max
+    if (c0 < S.ring_R2) ta = (-b + hw_sqrt(fmaxf(b * b - a * (c0 - S.ring_R2), 0.0f))) * inv_a;
+    else ta = fmaxf((-b - sq) * inv_a, 0.0f);
+  }
+  const float z1 = azimuth_turns(x.y + ta * d.y, x.x + ta * d.x);
+  float dz = azimuth_turns(x.y + tb * d.y, x.x + tb * d.x) - z1;
+  dz = dz > 0.5f ? dz - 1.0f : (dz < -0.5f ? dz + 1.0f : dz);
+  if (fabsf(dz) > 0.45f) {
+    tested = S.n_panels;
+    return panel_search_ring(S, x, d, exclude, t_in);
+  }
+  const float u1 = z1 * S.ring_n - S.ring_u0, u2 = u1 + dz * S.ring_n;
+  const int k0 = (int)ceilf(fminf(u1, u2) - S.ring_a), k1 = (int)floorf(fmaxf(u1, u2) + S.ring_a);
+  float tn_a = -INFINITY, tf_a = INFINITY;
+  slab_axis(x.z - ((CFloat *)S.pose)[11], d.z, -S.half_l, S.half_l, tn_a, tf_a);
+  int best = -1;
+  float bt = INFINITY;
+  const int n = S.n_panels;
+  for (int k = k0; k <= k1 && k < k0 + n; ++k) {
+    int p = k % n;
+    if (p < 0) p += n;
+    CFloat *P = (CFloat *)(S.pose + 12 * p);
+    float tn = tn_a, tf = tf_a;
+    slab_axis(x.x * P[0] + x.y * P[1] - P[9], d.x * P[0] + d.y * P[1], 0.0f, S.depth, tn, tf);
+    slab_axis(x.x * P[3] + x.y * P[4] - P[10], d.x * P[3] + d.y * P[4], -S.half_w, S.half_w, tn, tf);
+    const float te = fmaxf(tn, 0.0f);
+    if (tn <= tf && tf > 0.0f && p != exclude && (te < bt || (te == bt && p < best))) {
+      bt = te;
+      best = p;
+    }
+    ++tested;
+  }
+  t_in = bt;
+  return best;
+}
+
+// The transport's panel search: the pruned ring search for a repeated ring,
+// the full ring or general search otherwise; `tested` counts panel boxes.
+template <class SC> __device__ __forceinline__ int search_panels(SC &S, Vec x, Vec d, int exclude, float &t_in,
+                                                                 int &tested) {
+  if (S.ring_reg) return panel_search_ring_pruned(S, x, d, exclude, t_in, tested);
+  tested = S.n_panels;
+  return S.ring ? panel_search_ring(S, x, d, exclude, t_in) : panel_search(S, x, d, exclude, t_in);
 }
 
 template <class SC> __device__ __forceinline__ int find_panel(SC &S, Vec x, Vec d, int exclude, float &t_in) {

@@ -18,6 +18,13 @@ struct SurSpecD {
   float e_min, ebin, tol, max_slope, front_tol;
 };
 
+// Device control words of a context (u64): [0] event-chunk counter (u32),
+// [1] hit count, [2, 2 + kStatCount) work counters in gpet_stats order,
+// [kCtrlPairs] pairs / surrogate entries.
+constexpr int kStatCount = 12;
+constexpr int kCtrlPairs = 2 + kStatCount;
+constexpr int kCtrlWords = kCtrlPairs + 1;
+
 // Transport kernel modes
 enum : int { kModePlain = 0, kModeTrace = 1, kModeRecord = 2, kModeSurrogate = 3 };
 
@@ -40,7 +47,7 @@ struct RunArgs {
   unsigned long long capacity;
   unsigned long long *hit_count; // device
   uint32_t *work;                // device event-fetch counter
-  unsigned long long *stats;     // device, 10 counters (gpet_stats order)
+  unsigned long long *stats;     // device, kStatCount counters (gpet_stats order)
   // trace mode
   int32_t *vint;
   float *vflt;
@@ -66,7 +73,7 @@ struct RunArgs {
 
 struct LaunchShape {
   int blocks_per_cu = 0;      // blocks of 256 lanes per CU; 0 = the occupancy limit
-  uint32_t search_batch = 48; // see RunArgs::search_batch
+  uint32_t search_batch = 16; // see RunArgs::search_batch
   uint32_t schedule = 0;      // see RunArgs::schedule
 };
 size_t transport_lds_bytes(int det_slots);
@@ -156,7 +163,7 @@ struct gpet_ctx {
   // source
   bool have_source = false;
   float *d_rods = nullptr, *d_rod_cum = nullptr;
-  // device controls: [0] work (u32 x2), [1] hit count, [2..11] stats
+  // device control words (see kCtrlWords)
   unsigned long long *d_ctrl = nullptr;
   unsigned long long *h_ctrl = nullptr; // pinned mirror of d_ctrl
   // one-instance launch table of plain runs (scene + chunk table) and its

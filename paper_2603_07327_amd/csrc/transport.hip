@@ -14,7 +14,7 @@
 // plain run, many for a batched sweep): waves claim chunks of consecutive events
 // of one instance with one atomic and switch instance only once drained, so the
 // scene stays wave-uniform (scalar loads).
-// hits are staged per wave in LDS and written out 64 at a time (one atomic and
+// hits are staged per wave in LDS and written out 128 or more at a time (one atomic and
 // coalesced stores per flush).  The detector attenuation rows and majorant are
 // staged in LDS at kernel start.
 #include "gpet_internal.hpp"
@@ -30,8 +30,13 @@ enum : int { V_STEP = 0, V_ENTER_PANEL = 1, V_EXIT = 2, V_ESCAPE = 3, V_DEAD = 4
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kStage = 128;       // staged hits per wave; flushed when 64 or more are pending
-constexpr int kStageBytes = 4 * 6 + 8; // event, gid, aux, instance, edep, depth, time
+// staged hits per wave: flushed once kFlushAt or more are pending, so a trip
+// (at most one hit per lane) always fits.  The one output counter is shared
+// by every wave of the chip, so fewer, larger flushes matter more than the
+// occupancy the staging area costs (4 blocks per CU)
+constexpr int kFlushAt = 128;
+constexpr int kStage = kFlushAt + 64;
+constexpr int kStageBytes = 4 * 5 + 8; // event, gid, aux, edep, depth, time
 
 // LDS bytes of one block for a scene with `slots` detector table rows
 size_t transport_lds_bytes(int slots) {
@@ -67,13 +72,14 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 // per-wave staging area of hits in LDS (structure of arrays)
 struct Stage {
-  uint32_t *ev, *gid, *aux, *inst;
+  uint32_t *ev, *gid, *aux;
   float *edep, *depth;
   unsigned long long *time;
 };
 
-// write `cnt` staged hits of this wave to the global SoA arrays
-__device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, uint32_t cnt, int lane) {
+// write `cnt` staged hits of this wave (all of instance `inst`) to the global SoA arrays
+__device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, uint32_t cnt, int lane,
+                                            uint32_t inst) {
   if (cnt == 0) return;
   unsigned long long base = 0;
   if (lane == 0) base = atomicAdd(A.hit_count, (unsigned long long)cnt);
@@ -88,7 +94,7 @@ __device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, u
       A.h_depth[i] = st.depth[k];
       A.h_time[i] = st.time[k];
       A.h_aux[i] = st.aux[k];
-      if (A.h_inst) A.h_inst[i] = st.inst[k];
+      if (A.h_inst) A.h_inst[i] = inst;
     }
   }
   wave_sync_lds();
@@ -160,8 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   st.ev = (uint32_t *)(st.time + kStage);
   st.gid = st.ev + kStage;
   st.aux = st.gid + kStage;
-  st.inst = st.aux + kStage;
-  st.edep = (float *)(st.inst + kStage);
+  st.edep = (float *)(st.aux + kStage);
   st.depth = st.edep + kStage;
   __syncthreads();
 
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   uint32_t cur_next = 0, cur_end = 0, pend_inst = 0, pend_next = 0, pend_end = 0, staged = 0;
   bool have_pend = false, exhausted = false;
   unsigned long long c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0,
-                     c_blocks = 0, c_capped = 0, c_scatter = 0, c_trips = 0;
+                     c_blocks = 0, c_capped = 0, c_scatter = 0, c_trips = 0, c_tests = 0, c_pruned = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
   auto start_photon = [&](CScene &S, int which) {
@@ -248,6 +253,8 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
         }
       }
       if (have_pend && pend_inst != inst && __ballot(phase != P_FETCH && phase != P_DONE) == 0 && avail == 0) {
+        flush_stage(A, st, staged, lane, inst); // staged hits carry the wave's instance
+        staged = 0;
         inst = pend_inst; // drained: switch the wave to the claimed instance
         inst_rng = A.inst_id[inst];
         sp = (CScene *)(A.scenes + inst);
@@ -319,6 +326,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     c_blocks += count(draw && sid != 0u);
 
     bool hit = false, ended = false, push = false;
+    int n_tested = 0;
     float sf[6];
     int s_module = 0;
     uint32_t s_anchor[kMaxLayers] = {0u, 0u, 0u, 0u};
@@ -401,7 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     } else if (phase == P_SEARCH) {
       searched = true;
       float ti;
-      const int p = find_panel(S, x, d, last, ti);
+      const int p = search_panels(S, x, d, last, ti, n_tested);
       if (p < 0) {
         vertex<TRACE>(A, ev, ph, V_ESCAPE, -1, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
         ended = true;
@@ -513,6 +521,14 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     c_steps += count(stepped);
     c_real += count(real);
     c_search += count(searched);
+    if (__ballot(searched)) {
+      // panel tests summed over the wave (a lane's count, reduced by the wave)
+      int t = n_tested;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+      c_tests += (unsigned long long)t;
+      c_pruned += count(searched && S.ring_reg);
+    }
     c_entries += count(entered);
     c_trials += count(trial);
     c_scatter += count(scattered);
@@ -614,12 +630,11 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
         st.depth[k] = x.x;
         st.time[k] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
         st.aux[k] = (uint32_t)ph | ((uint32_t)h_proc << 1) | (seq << 8);
-        st.inst[k] = inst;
         ++seq;
       }
       staged += (uint32_t)__popcll(hm);
-      if (staged >= 64) {
-        flush_stage(A, st, staged, lane);
+      if (staged >= kFlushAt) {
+        flush_stage(A, st, staged, lane, inst);
         staged = 0;
       }
     }
@@ -628,13 +643,13 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       else phase = P_FETCH;
     }
   }
-  flush_stage(A, st, staged, lane);
+  flush_stage(A, st, staged, lane, inst);
 
-  const unsigned long long cnt[10] = {c_events, c_entries, c_steps, c_real, c_trials, c_search, c_blocks,
-                                      c_capped, c_scatter, c_trips};
+  const unsigned long long cnt[kStatCount] = {c_events, c_entries, c_steps,   c_real,  c_trials, c_search,
+                                              c_blocks, c_capped,  c_scatter, c_trips, c_tests,  c_pruned};
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 10; ++k)
+    for (int k = 0; k < kStatCount; ++k)
       if (cnt[k]) atomicAdd(A.stats + k, cnt[k]);
   }
 }
@@ -725,7 +740,8 @@ __global__ void k_ray_locate(DevScene S, uint32_t n, const float *o, const float
   if (r >= n) return;
   const Vec ro{o[3 * r], o[3 * r + 1], o[3 * r + 2]}, rd{d[3 * r], d[3 * r + 1], d[3 * r + 2]};
   float ti;
-  const int p = find_panel(S, ro, rd, -1, ti);
+  int tested;
+  const int p = search_panels(S, ro, rd, -1, ti, tested); // the transport's search
   t_in[r] = p >= 0 ? ti : -1.0f;
   for (int k = 0; k < ns; ++k) {
     int32_t *q = ids6 + 6 * ((size_t)r * ns + k);

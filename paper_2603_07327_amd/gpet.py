@@ -27,7 +27,7 @@ SRC_POINT, SRC_CYLINDERS, SRC_BEAM = 0, 1, 2
 V_STEP, V_ENTER_PANEL, V_EXIT, V_ESCAPE, V_DEAD, V_ENTER_PHANTOM, V_EMIT = range(7)
 
 STAT_NAMES = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks", "capped",
-              "scatters", "wave_trips")
+              "scatters", "wave_trips", "panel_tests", "pruned_searches")
 
 
 class GpetError(RuntimeError):
@@ -362,7 +362,7 @@ class Context:
     def _empty(self, n, dtype):
         return self.torch.empty(max(int(n), 1), dtype=dtype, device=self.dev)
 
-    def set_launch(self, blocks_per_cu=0, search_batch=48, schedule=0):
+    def set_launch(self, blocks_per_cu=0, search_batch=16, schedule=0):
         self._check(self.L.gpet_ctx_set_launch(self.h, blocks_per_cu, search_batch, schedule))
 
     def enable_timing(self, on=True):
@@ -670,7 +670,7 @@ class Batch:
         except Exception:
             pass
 
-    def set_launch(self, blocks_per_cu=0, search_batch=48, chunk=1024):
+    def set_launch(self, blocks_per_cu=0, search_batch=16, chunk=1024):
         self.ctx._check(self.L.gpet_batch_set_launch(self.h, blocks_per_cu, search_batch, chunk))
 
     def alloc_hits(self, capacity):
