@@ -346,10 +346,13 @@ struct BucketBufs {
   uint32_t *pinned_map;
 };
 
-// Sorts (b.k0, b.v0) into (b.k1, b.v1) by (key, value).  `items[i]` is the
-// number of keys of instance i and `range[i]` the extent of their local value.
-// Returns 0 when sorted, bit 0 when a bucket was too large for LDS, bit 1 when
-// a key fell outside the map (then (k1, v1) are not sorted).
+// Sorts (b.k0, b.v0) into (b.k1, b.v1) by (key, value), leaving (k0, v0)
+// intact.  `items[i]` is the number of keys of instance i and `range[i]` the
+// extent of their local value.  Returns 1 when the map needs more buckets than
+// the scratch holds (nothing launched).  Otherwise the work is enqueued and
+// *bb.pinned_flag receives, once the stream reaches it, 0 when sorted, bit 0
+// when a bucket was too large for LDS, bit 1 when a key fell outside the map
+// (then (k1, v1) are not sorted).
 template <bool AGG>
 static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shift, int local_shift,
                             unsigned long long local_mask, const std::vector<uint64_t> &items,
@@ -382,8 +385,7 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shif
   hipLaunchKernelGGL(k_bucket_scatter<AGG>, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, M, bb.count, b.k1, b.v1);
   hipLaunchKernelGGL(k_bucket_local_sort, dim3((unsigned)nb), dim3(256), 0, st, b.k1, b.v1, bb.count, bb.overflow);
   (void)hipMemcpyAsync(bb.pinned_flag, bb.overflow, 4, hipMemcpyDeviceToHost, st);
-  (void)hipStreamSynchronize(st);
-  return *bb.pinned_flag;
+  return 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -622,7 +624,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
     scr.bytes = need;
   }
-  const size_t pinned_bytes = 64 + 4 * ni + 16 * ni;
+  const size_t pinned_bytes = 64 + 32 * ni;
   if (scr.pinned_bytes < pinned_bytes) {
     if (scr.pinned) (void)hipHostFree(scr.pinned);
     scr.pinned = nullptr;
@@ -659,11 +661,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   uint32_t *d_tab = (uint32_t *)take(ni * 4 * 4); // first, n_events, cpp, rng
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
   // pinned host words: [0, 16) scalar readbacks, [16, 16 + ni) per-instance
-  // counts, then 4 ni words for the instance table / bucket map uploads
+  // counts, 3 ni words of bucket-map uploads, 4 ni words of instance table
   uint32_t *rb = (uint32_t *)scr.pinned;
   uint32_t *rb_count = rb + 16;
   bb.pinned_flag = rb + 12;
   bb.pinned_map = rb + 16 + ni;
+  uint32_t *tab = rb + 16 + 4 * ni;
   auto sync = [&](const char *what) {
     if (hipStreamSynchronize(st) != hipSuccess) {
       err = std::string("digitize: stream error ") + what;
@@ -672,8 +675,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     return true;
   };
 
-  // instance table on the device
-  uint32_t *tab = bb.pinned_map; // staged here before any bucket map is
+  // instance table on the device (its pinned staging is not reused before the call ends)
   for (size_t i = 0; i < ni; ++i) {
     tab[i] = D.first[i];
     tab[ni + i] = D.n_events[i];
@@ -681,7 +683,6 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     tab[3 * ni + i] = D.rng[i];
   }
   (void)hipMemcpyAsync(d_tab, tab, ni * 16, hipMemcpyHostToDevice, st);
-  if (!sync("uploading the instance table")) return GPET_ERR_HIP;
   const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, (uint32_t)ni};
   uint32_t max_events = 1;
   for (size_t i = 0; i < ni; ++i) max_events = std::max(max_events, D.n_events[i]);
@@ -700,17 +701,13 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux, D.h_inst, IT,
                      D.gid_bits, inst_shift, sb.k0, sb.v0, err_flag);
   std::vector<uint64_t> items(ni, n);
-  if (ni > 1) {
+  (void)hipMemcpyAsync(rb + 13, err_flag, 4, hipMemcpyDeviceToHost, st); // checked at the next synchronization
+  if (ni > 1) { // per-instance counts size the bucket map
     launch_fill_u32(d_icount, 0u, ni, st);
     hipLaunchKernelGGL(k_inst_count, dim3(grid_for(n)), dim3(256), 0, st, sb.k0, n, inst_shift, (uint32_t)ni,
                        d_icount);
     (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
-  }
-  (void)hipMemcpyAsync(rb + 13, err_flag, 4, hipMemcpyDeviceToHost, st);
-  if (!sync("building hit keys")) return GPET_ERR_HIP;
-  if (rb[13] & 2u) {
-    err = "digitize: a hit's instance or event id lies outside its declared range";
-    return GPET_ERR_ARG;
+    if (!sync("building hit keys")) return GPET_ERR_HIP;
   }
   std::vector<double> range(ni);
   for (size_t i = 0; i < ni; ++i) {
@@ -718,21 +715,36 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     range[i] = (double)D.n_events[i];
   }
   const unsigned long long ev_mask = (1ull << event_bits) - 1;
+  const int hit_bits = hit_shift + event_bits + inst_bits;
   const unsigned long long *hk = sb.k1;
   const uint32_t *hp = sb.v1;
-  const uint32_t hflag = bucket_sort<true>(sb, bb, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp);
-  if (hflag) { // a bucket overflowed LDS: sort every key bit instead
-    const int bits = hit_shift + event_bits + inst_bits;
-    const bool f1 = radix_sort(sb, n, bits, st);
+  // 2. adder: single index of each run = exclusive scan of run heads
+  auto run_heads = [&]() {
+    hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
+    (void)hipMemcpyAsync(rb + 0, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
+    exclusive_scan(flag, n, sb.scan_tmp, st);
+    (void)hipMemcpyAsync(rb + 1, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
+  };
+  rb[12] = 0u;
+  const bool mapped = bucket_sort<true>(sb, bb, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp) == 0;
+  if (!mapped) { // too many buckets for the scratch: sort every key bit instead
+    const bool f1 = radix_sort(sb, n, hit_bits, st);
     hk = f1 ? sb.k1 : sb.k0;
     hp = f1 ? sb.v1 : sb.v0;
   }
-  // 2. adder: single index of each run = exclusive scan of run heads
-  hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
-  (void)hipMemcpyAsync(rb + 0, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
-  exclusive_scan(flag, n, sb.scan_tmp, st);
-  (void)hipMemcpyAsync(rb + 1, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
+  run_heads();
   if (!sync("after the hit sort")) return GPET_ERR_HIP;
+  if (rb[13] & 2u) {
+    err = "digitize: a hit's instance or event id lies outside its declared range";
+    return GPET_ERR_ARG;
+  }
+  if (mapped && rb[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
+    const bool f1 = radix_sort(sb, n, hit_bits, st);
+    hk = f1 ? sb.k1 : sb.k0;
+    hp = f1 ? sb.v1 : sb.v0;
+    run_heads();
+    if (!sync("after the hit sort")) return GPET_ERR_HIP;
+  }
   const uint64_t ns = (uint64_t)rb[1] + rb[0];
   S->count = ns;
   if (ns > S->capacity) {
@@ -786,23 +798,38 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const unsigned long long *tk = sb.k1;
   const uint32_t *ti = sb.v1;
   const unsigned long long t_mask = time_bits < 64 ? (1ull << time_bits) - 1 : ~0ull;
+  // 5. coincidences: count per cluster, scan, write
+  auto run_coinc = [&]() {
+    hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
+                       D.window_ps, flag);
+    (void)hipMemcpyAsync(rb + 6, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
+    exclusive_scan(flag, nw, sb.scan_tmp, st);
+    (void)hipMemcpyAsync(rb + 7, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
+    hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
+                       D.window_ps, flag, C->first, C->second, C->capacity);
+  };
+  bool tmapped = false;
+  rb[12] = 0u;
   if (nw == 1) {
     tk = sb.k0;
     ti = sb.v0;
-  } else if (bucket_sort<false>(sb, bb, nw, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st, sb.scan_tmp)) {
+  } else if (bucket_sort<false>(sb, bb, nw, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st, sb.scan_tmp) ==
+             0) {
+    tmapped = true;
+  } else {
     const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
     tk = f2 ? sb.k1 : sb.k0;
     ti = f2 ? sb.v1 : sb.v0;
   }
-  // 5. coincidences: count per cluster, scan, write
-  hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
-                     D.window_ps, flag);
-  (void)hipMemcpyAsync(rb + 6, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
-  exclusive_scan(flag, nw, sb.scan_tmp, st);
-  (void)hipMemcpyAsync(rb + 7, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
-  hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
-                     D.window_ps, flag, C->first, C->second, C->capacity);
+  run_coinc();
   if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
+  if (tmapped && rb[12]) { // a bucket overflowed LDS: sort every key bit and redo the pairing
+    const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
+    tk = f2 ? sb.k1 : sb.k0;
+    ti = f2 ? sb.v1 : sb.v0;
+    run_coinc();
+    if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
+  }
   C->count = (uint64_t)rb[7] + rb[6];
   if (C->count > C->capacity) {
     err = "digitize: coincidence capacity too small";
