@@ -1,18 +1,21 @@
 // digitize.hip -- crystal-level digitizer for gfx950.
 //
 // Pipeline (all on the device, stream ordered):
-//   1. hits -> 64-bit keys (event - first) << gid_bits | gid, stable LSD radix
-//      sort (8-bit digits, ranks from wave ballots so equal digits keep their
-//      order);
-//   2. adder: one single per run of equal keys; energy and energy-weighted
-//      depth are summed as exact 2^-32 fixed-point integers, so the result does
-//      not depend on the (atomic) order the hits were appended in;
+//   1. hits -> 64-bit keys (instance, event, crystal, photon, hit index),
+//      grouped by event bucket (counters with one atomic per group of equal
+//      buckets in a wave) and sorted inside each bucket by one wave;
+//   2. adder: one single per run of equal (instance, event, crystal); energy
+//      and energy-weighted depth are summed as exact 2^-32 fixed-point
+//      integers, so the result does not depend on the order of the hits;
 //   3. Gaussian blur from the digitizer Philox stream and the energy window;
-//   4. windowed singles sorted by time (stable, so ties stay in (event, gid)
-//      order), split into clusters at gaps larger than the coincidence window;
-//      inside a cluster, non-retriggering windows are resolved sequentially by
-//      the cluster's first lane; counts are scanned so that the coincidence
-//      list comes out in a fixed order.
+//   4. windowed singles sorted by (instance, time, single index): stable radix
+//      passes over the time bucket, then one wave per bucket; split into
+//      clusters at gaps larger than the coincidence window; inside a cluster,
+//      non-retriggering windows are resolved sequentially by the cluster's
+//      first lane; counts are scanned so that the coincidence list comes out
+//      in a fixed order.
+// A bucket too large for the in-LDS sort sends the step to a plain LSD radix
+// sort over every key bit.
 #include <algorithm>
 #include <cstring>
 
@@ -20,9 +23,6 @@
 
 namespace gpet {
 
-constexpr int kSortBlock = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanBlock * kScanItems;
@@ -86,8 +86,56 @@ static void exclusive_scan(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort of (u64 key, u32 value), 8-bit digits
+// Bucket map: a monotone map of (u64) keys spread evenly over their range
+// (event ids, event times) to buckets of about 128 keys.
 // ---------------------------------------------------------------------------
+// Bucket of a key: instance i = key >> inst_shift owns buckets
+// [base[i], base[i] + count[i]); inside them the bucket grows linearly with the
+// key's local value v = (key >> local_shift) & local_mask (event index or time),
+// so every instance gets buckets in proportion to its item count.  A key whose
+// instance lies outside the map gets bucket nb.
+struct BucketMap {
+  int inst_shift, local_shift;
+  unsigned long long local_mask;
+  const uint32_t *base, *count;
+  const float *scale; // buckets per unit of v
+  uint32_t n_inst, nb;
+};
+
+__device__ __forceinline__ uint32_t bucket_of(const BucketMap &M, unsigned long long key) {
+  const uint32_t i = M.inst_shift < 64 ? (uint32_t)(key >> M.inst_shift) : 0u;
+  if (i >= M.n_inst) return M.nb;
+  const unsigned long long v = (key >> M.local_shift) & M.local_mask;
+  const uint32_t b = min((uint32_t)((float)v * M.scale[i]), M.count[i] - 1u);
+  return M.base[i] + b;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix passes over (u64 key, u32 value) with up to 8-bit digits.
+// A digit is either a byte of the key or a digit of its bucket.  Tiles of 4096
+// items: a histogram pass, a scan of the (digit, tile) counts, then a scatter
+// that ranks the tile in LDS (wave ballots keep equal digits in input order)
+// and writes it out digit by digit, so stores come in runs.
+// ---------------------------------------------------------------------------
+constexpr int kTileBlock = 256;
+constexpr int kTileItems = 16;
+constexpr int kTile = kTileBlock * kTileItems;
+constexpr int kTileWaveItems = kTile / (kTileBlock / 64);
+
+struct KeyDigit {
+  int shift;
+  __device__ __forceinline__ uint32_t operator()(unsigned long long k) const { return (uint32_t)(k >> shift) & 255u; }
+};
+
+struct BucketDigit {
+  BucketMap M;
+  int shift;
+  uint32_t mask;
+  __device__ __forceinline__ uint32_t operator()(unsigned long long k) const {
+    return (bucket_of(M, k) >> shift) & mask;
+  }
+};
+
 // lanes of the wave holding the same digit (among `valid` lanes)
 __device__ __forceinline__ uint64_t digit_peers(uint32_t digit, bool valid) {
   uint64_t m = __ballot(valid);
@@ -100,64 +148,113 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t digit, bool valid) {
   return m;
 }
 
-__global__ void __launch_bounds__(kSortBlock) k_radix_hist(const unsigned long long *keys, size_t n, int shift,
-                                                           uint32_t *hist, uint32_t n_tiles) {
+// exclusive prefix sum of one value per thread over a 256-thread block
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t x, uint32_t *wave_tot) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wave_tot[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int k = 0; k < w; ++k) before += wave_tot[k];
+  return before + inc - x;
+}
+
+template <class Digit>
+__global__ void __launch_bounds__(kTileBlock) k_tile_hist(const unsigned long long *keys, size_t n, Digit dg,
+                                                          uint32_t *hist, uint32_t n_tiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t below = __lanemask_lt();
-  const size_t base = (size_t)blockIdx.x * kSortTile;
-  for (int it = 0; it < kSortItems; ++it) {
-    const size_t i = base + (size_t)it * kSortBlock + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t dg = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
-    const uint64_t peers = digit_peers(dg, valid);
-    if (valid && (peers & below) == 0) atomicAdd(&h[dg], (uint32_t)__popcll(peers));
+  const size_t base = (size_t)blockIdx.x * kTile;
+#pragma unroll 4
+  for (int r = 0; r < kTileItems; ++r) {
+    const size_t i = base + (size_t)r * kTileBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[dg(keys[i])], 1u);
   }
   __syncthreads();
   hist[(size_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(kSortBlock) k_radix_scatter(const unsigned long long *kin, const uint32_t *vin,
-                                                              unsigned long long *kout, uint32_t *vout, size_t n,
-                                                              int shift, const uint32_t *offs, uint32_t n_tiles) {
-  constexpr int kWaves = kSortBlock / 64;
-  __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_cnt[kWaves][256];
-  const int wave = threadIdx.x >> 6;
-  const uint64_t below = __lanemask_lt();
-  s_base[threadIdx.x] = offs[(size_t)threadIdx.x * n_tiles + blockIdx.x];
+// `offs` = exclusive scan of the histogram (digit-major), i.e. where the
+// tile's first item of each digit goes
+template <class Digit>
+__global__ void __launch_bounds__(kTileBlock) k_tile_scatter(const unsigned long long *kin, const uint32_t *vin,
+                                                             unsigned long long *kout, uint32_t *vout, size_t n,
+                                                             Digit dg, const uint32_t *offs, uint32_t n_tiles) {
+  constexpr int kWaves = kTileBlock / 64;
+  __shared__ unsigned long long sk[kTile];
+  __shared__ uint32_t sv[kTile];
+  __shared__ uint8_t sd[kTile];
+  __shared__ uint32_t wcnt[kWaves][256]; // per-wave running counts, then per-wave starts
+  __shared__ uint32_t lstart[256], gstart[256], wave_tot[kWaves];
+  const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) s_cnt[w][threadIdx.x] = 0;
+  for (int k = 0; k < kWaves; ++k) wcnt[k][t] = 0;
+  gstart[t] = offs[(size_t)t * n_tiles + blockIdx.x];
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * kSortTile;
-  for (int it = 0; it < kSortItems; ++it) {
-    const size_t i = base + (size_t)it * kSortBlock + threadIdx.x;
-    const bool valid = i < n;
-    const unsigned long long key = valid ? kin[i] : 0ull;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t dg = (uint32_t)(key >> shift) & 255u;
-    const uint64_t peers = digit_peers(dg, valid);
-    const uint32_t rank = (uint32_t)__popcll(peers & below);
-    if (valid && rank == 0) s_cnt[wave][dg] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    uint32_t pos = 0;
-    if (valid) {
-      pos = s_base[dg] + rank;
-      for (int w = 0; w < wave; ++w) pos += s_cnt[w][dg];
-    }
-    __syncthreads();
-    uint32_t tot = 0;
+  // wave w ranks items [w 1024, w 1024 + 1024) of the tile, 64 per round, in order
+  const size_t base = (size_t)blockIdx.x * kTile + (size_t)w * kTileWaveItems;
+  const uint64_t below = __lanemask_lt();
+  unsigned long long k[kTileItems];
+  uint32_t v[kTileItems], d[kTileItems], rk[kTileItems];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      tot += s_cnt[w][threadIdx.x];
-      s_cnt[w][threadIdx.x] = 0;
+  for (int r = 0; r < kTileItems; ++r) {
+    const size_t i = base + (size_t)r * 64 + lane;
+    const bool valid = i < n;
+    k[r] = valid ? kin[i] : 0ull;
+    v[r] = valid ? vin[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kTileItems; ++r) {
+    const bool valid = base + (size_t)r * 64 + lane < n;
+    d[r] = valid ? dg(k[r]) : 0u;
+    const uint64_t peers = digit_peers(d[r], valid);
+    const uint32_t before = (uint32_t)__popcll(peers & below);
+    const uint32_t run = wcnt[w][d[r]];
+    rk[r] = run + before;
+    // LDS operations of a wave complete in order, so every lane has read the
+    // count before its group's first lane replaces it
+    if (valid && before == 0) wcnt[w][d[r]] = run + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  uint32_t c[kWaves], tot = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    c[q] = wcnt[q][t];
+    tot += c[q];
+  }
+  const uint32_t ls = block_exclusive_256(tot, wave_tot);
+  lstart[t] = ls;
+  uint32_t acc = ls;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    wcnt[q][t] = acc;
+    acc += c[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kTileItems; ++r) {
+    if (base + (size_t)r * 64 + lane < n) {
+      const uint32_t p = wcnt[w][d[r]] + rk[r];
+      sk[p] = k[r];
+      sv[p] = v[r];
+      sd[p] = (uint8_t)d[r];
     }
-    s_base[threadIdx.x] += tot;
-    __syncthreads();
-    if (valid && pos < n) {
-      kout[pos] = key;
-      vout[pos] = val;
+  }
+  __syncthreads();
+  const size_t t0 = (size_t)blockIdx.x * kTile;
+  const uint32_t cnt = (uint32_t)min((size_t)kTile, n - t0);
+  for (uint32_t idx = t; idx < cnt; idx += kTileBlock) {
+    const uint32_t dd = sd[idx];
+    const uint32_t pos = gstart[dd] + (idx - lstart[dd]);
+    if (pos < n) {
+      kout[pos] = sk[idx];
+      vout[pos] = sv[idx];
     }
   }
 }
@@ -169,29 +266,42 @@ struct SortBufs {
   uint32_t *scan_tmp;
 };
 
+static inline uint32_t tile_count(size_t n) { return (uint32_t)((n + kTile - 1) / kTile); }
+
+// one stable pass (ki, vi) -> (ko, vo) by the digit dg
+template <class Digit>
+static void radix_pass(SortBufs &b, const unsigned long long *ki, const uint32_t *vi, unsigned long long *ko,
+                       uint32_t *vo, size_t n, Digit dg, hipStream_t st) {
+  const uint32_t tiles = tile_count(n);
+  hipLaunchKernelGGL(k_tile_hist<Digit>, dim3(tiles), dim3(kTileBlock), 0, st, ki, n, dg, b.hist, tiles);
+  exclusive_scan(b.hist, (size_t)256 * tiles, b.scan_tmp, st);
+  hipLaunchKernelGGL(k_tile_scatter<Digit>, dim3(tiles), dim3(kTileBlock), 0, st, ki, vi, ko, vo, n, dg, b.hist,
+                     tiles);
+}
+
 // sorts (k0, v0) over the low `bits` bits; returns true if the result sits in (k1, v1)
 static bool radix_sort(SortBufs &b, size_t n, int bits, hipStream_t st) {
   if (n <= 1 || bits <= 0) return false;
-  const uint32_t tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
   bool flip = false;
   for (int shift = 0; shift < bits; shift += 8) {
     unsigned long long *ki = flip ? b.k1 : b.k0, *ko = flip ? b.k0 : b.k1;
     uint32_t *vi = flip ? b.v1 : b.v0, *vo = flip ? b.v0 : b.v1;
-    hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kSortBlock), 0, st, ki, n, shift, b.hist, tiles);
-    exclusive_scan(b.hist, (size_t)256 * tiles, b.scan_tmp, st);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortBlock), 0, st, ki, vi, ko, vo, n, shift, b.hist,
-                       tiles);
+    radix_pass(b, ki, vi, ko, vo, n, KeyDigit{shift}, st);
     flip = !flip;
   }
   return flip;
 }
 
 // ---------------------------------------------------------------------------
-// Bucket sort of (u64 key, u32 value) for keys spread evenly over their range
-// (event ids, event times): count per bucket (key >> shift), scan, scatter by
-// bucket, then sort each bucket (about 256 items) in LDS with a bitonic network
-// ordered by (key, value).  The scatter order inside a bucket depends on
-// atomics; the local sort by (key, value) makes the result deterministic.
+// Bucket sort of (u64 key, u32 value) by (key, value): order the items by
+// bucket, then sort each bucket: one wave per bucket with a register bitonic
+// network, the rare larger bucket in LDS.  Two ways to group by bucket:
+//   * clustered keys (hits: an event's hits share a bucket) -- per-bucket
+//     counters with one atomic per group of equal buckets in a wave, scan,
+//     scatter; the order inside a bucket depends on the atomics;
+//   * spread keys (times) -- stable radix passes over the bucket number, no
+//     global atomics, then bucket starts from the sorted buckets.
+// The final sort by (key, value) makes the result deterministic either way.
 // ---------------------------------------------------------------------------
 constexpr int kLocalSort = 1024; // largest bucket sorted in LDS
 
@@ -208,28 +318,7 @@ __device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
   return mine;
 }
 
-// Bucket of a key: instance i = key >> inst_shift owns buckets
-// [base[i], base[i] + count[i]); inside them the bucket grows linearly with the
-// key's local value v = (key >> local_shift) & local_mask (event index or time),
-// so every instance gets buckets in proportion to its item count.
-struct BucketMap {
-  int inst_shift, local_shift;
-  unsigned long long local_mask;
-  const uint32_t *base, *count;
-  const float *scale; // buckets per unit of v
-  uint32_t n_inst, nb;
-};
-
-__device__ __forceinline__ uint32_t bucket_of(const BucketMap &M, unsigned long long key) {
-  const uint32_t i = M.inst_shift < 64 ? (uint32_t)(key >> M.inst_shift) : 0u;
-  if (i >= M.n_inst) return M.nb; // caller treats as out of range
-  const unsigned long long v = (key >> M.local_shift) & M.local_mask;
-  const uint32_t b = min((uint32_t)((float)v * M.scale[i]), M.count[i] - 1u);
-  return M.base[i] + b;
-}
-
 // keys whose bucket falls outside the map are skipped and flagged (bit 1 of *flag)
-template <bool AGG>
 __global__ void k_bucket_count(const unsigned long long *key, size_t n, BucketMap M, uint32_t *count,
                                uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,16 +326,11 @@ __global__ void k_bucket_count(const unsigned long long *key, size_t n, BucketMa
   if (i < n && kb >= M.nb) atomicOr(flag, 2u);
   const bool valid = i < n && kb < M.nb;
   const uint32_t b = valid ? kb : 0u;
-  if constexpr (AGG) {
-    const uint64_t peers = equal_peers(b, valid);
-    if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[b], (uint32_t)__popcll(peers));
-  } else {
-    if (valid) atomicAdd(&count[b], 1u);
-  }
+  const uint64_t peers = equal_peers(b, valid);
+  if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[b], (uint32_t)__popcll(peers));
 }
 
 // cursor holds bucket starts on entry and bucket ends on exit
-template <bool AGG>
 __global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *vin, size_t n, BucketMap M,
                                  uint32_t *cursor, unsigned long long *kout, uint32_t *vout) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,22 +338,31 @@ __global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *
   const uint32_t kb = i < n ? bucket_of(M, k) : 0u;
   const bool valid = i < n && kb < M.nb;
   const uint32_t b = valid ? kb : 0u;
-  uint32_t pos = 0;
-  if constexpr (AGG) {
-    const uint64_t below = __lanemask_lt();
-    const uint64_t peers = equal_peers(b, valid);
-    const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : 0;
-    uint32_t base = 0;
-    if (valid && (peers & below) == 0) base = atomicAdd(&cursor[b], (uint32_t)__popcll(peers));
-    base = __shfl(base, leader);
-    pos = base + (uint32_t)__popcll(peers & below);
-  } else {
-    if (valid) pos = atomicAdd(&cursor[b], 1u);
-  }
+  const uint64_t below = __lanemask_lt();
+  const uint64_t peers = equal_peers(b, valid);
+  const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : 0;
+  uint32_t base = 0;
+  if (valid && (peers & below) == 0) base = atomicAdd(&cursor[b], (uint32_t)__popcll(peers));
+  base = __shfl(base, leader);
+  const uint32_t pos = base + (uint32_t)__popcll(peers & below);
   if (valid && pos < n) {
     kout[pos] = k;
     vout[pos] = vin[i];
   }
+}
+
+// start[b] = first position of bucket b in keys sorted by bucket, b in [0, nb];
+// keys outside the map (bucket nb) sit at the end and are flagged (bit 1)
+__global__ void k_bucket_bounds(const unsigned long long *key, size_t n, BucketMap M, uint32_t *start,
+                                uint32_t *flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t b = min(bucket_of(M, key[i]), M.nb);
+  if (b == M.nb && (i == 0 || min(bucket_of(M, key[i - 1]), M.nb) != M.nb)) atomicOr(flag, 2u);
+  const int64_t prev = i ? (int64_t)min(bucket_of(M, key[i - 1]), M.nb) : -1;
+  for (int64_t q = prev + 1; q <= (int64_t)b; ++q) start[q] = (uint32_t)i;
+  if (i == n - 1)
+    for (uint32_t q = b + 1; q <= M.nb; ++q) start[q] = (uint32_t)n;
 }
 
 // items per instance (instance = key >> shift)
@@ -285,49 +378,147 @@ __device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, un
   return ka < kb || (ka == kb && va < vb);
 }
 
-// one block per bucket; `end` holds bucket ends (the scattered cursor)
-__global__ void __launch_bounds__(256) k_bucket_local_sort(unsigned long long *key, uint32_t *val,
-                                                           const uint32_t *end, uint32_t *overflow) {
-  __shared__ unsigned long long sk[kLocalSort];
-  __shared__ uint32_t sv[kLocalSort];
-  const uint32_t b = blockIdx.x;
-  const uint32_t lo = b ? end[b - 1] : 0u, hi = end[b];
-  const uint32_t size = hi - lo;
-  if (size <= 1) return;
-  if (size > (uint32_t)kLocalSort) {
-    if (threadIdx.x == 0) atomicOr(overflow, 1u);
-    return;
-  }
-  uint32_t P = 2;
-  while (P < size) P <<= 1;
-  for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
-    sk[t] = t < size ? key[lo + t] : ~0ull;
-    sv[t] = t < size ? val[lo + t] : ~0u;
-  }
-  __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
-        const uint32_t u = t ^ j;
-        if (u > t) {
-          const bool up = (t & k) == 0;
-          const bool swap = up ? pair_less(sk[u], sv[u], sk[t], sv[t]) : pair_less(sk[t], sv[t], sk[u], sv[u]);
-          if (swap) {
-            const unsigned long long tk = sk[t];
-            sk[t] = sk[u];
-            sk[u] = tk;
-            const uint32_t tv = sv[t];
-            sv[t] = sv[u];
-            sv[u] = tv;
+// Bitonic sort of P = 64 E (key, value) pairs held E per lane, ascending by
+// (key, value).  Element l E + r sits in register r of lane l, so partners
+// closer than E stay in the lane and the others are one lane shuffle away.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(unsigned long long (&k)[E], uint32_t (&v)[E]) {
+  const int lane = __lane_id();
+  constexpr int P = 64 * E;
+#pragma unroll
+  for (int kk = 2; kk <= P; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int u = r ^ j;
+          if (u > r) {
+            const bool asc = ((lane * E + r) & kk) == 0;
+            if (asc ? pair_less(k[u], v[u], k[r], v[r]) : pair_less(k[r], v[r], k[u], v[u])) {
+              const unsigned long long tk = k[r];
+              k[r] = k[u];
+              k[u] = tk;
+              const uint32_t tv = v[r];
+              v[r] = v[u];
+              v[u] = tv;
+            }
+          }
+        }
+      } else {
+        const int lx = j / E; // partner lane distance
+        const bool lower = (lane & lx) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool asc = ((lane * E + r) & kk) == 0;
+          const unsigned long long pk = __shfl_xor(k[r], lx);
+          const uint32_t pv = __shfl_xor(v[r], lx);
+          const bool p_less = pair_less(pk, pv, k[r], v[r]);
+          // the lower element of an ascending pair keeps the smaller one
+          if (lower == asc ? p_less : !p_less) {
+            k[r] = pk;
+            v[r] = pv;
           }
         }
       }
-      __syncthreads();
     }
   }
-  for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) {
-    key[lo + t] = sk[t];
-    val[lo + t] = sv[t];
+}
+
+// sorts key/val[lo, lo + size) in place with one wave, size <= 64 E
+template <int E>
+__device__ __forceinline__ void wave_sort_range(unsigned long long *key, uint32_t *val, uint32_t lo,
+                                                uint32_t size) {
+  const uint32_t lane = __lane_id();
+  unsigned long long k[E];
+  uint32_t v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t t = lane * E + r;
+    k[r] = t < size ? key[lo + t] : ~0ull;
+    v[r] = t < size ? val[lo + t] : ~0u;
+  }
+  wave_bitonic<E>(k, v);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t t = lane * E + r;
+    if (t < size) {
+      key[lo + t] = k[r];
+      val[lo + t] = v[r];
+    }
+  }
+}
+
+constexpr int kWaveSort = 256; // largest bucket sorted by one wave
+
+// one wave per bucket; bucket b spans [start[b], start[b + 1]).  Buckets too
+// large for a wave are listed in big[] (count in *n_big) for the block sort.
+__global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *key, uint32_t *val,
+                                                          const uint32_t *start, uint32_t nb, uint32_t *big,
+                                                          uint32_t *n_big) {
+  const uint32_t b = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  const uint32_t lo = start[b], hi = start[b + 1];
+  const uint32_t size = hi - lo;
+  if (size <= 1) return;
+  if (size <= 64) {
+    wave_sort_range<1>(key, val, lo, size);
+  } else if (size <= 128) {
+    wave_sort_range<2>(key, val, lo, size);
+  } else if (size <= (uint32_t)kWaveSort) {
+    wave_sort_range<4>(key, val, lo, size);
+  } else if (__lane_id() == 0) {
+    big[atomicAdd(n_big, 1u)] = b;
+  }
+}
+
+// one block per listed bucket (grid-stride over the list), bitonic network in LDS
+__global__ void __launch_bounds__(256) k_bucket_block_sort(unsigned long long *key, uint32_t *val,
+                                                           const uint32_t *start, const uint32_t *big,
+                                                           const uint32_t *n_big, uint32_t *overflow) {
+  __shared__ unsigned long long sk[kLocalSort];
+  __shared__ uint32_t sv[kLocalSort];
+  const uint32_t listed = *n_big;
+  for (uint32_t it = blockIdx.x; it < listed; it += gridDim.x) {
+    const uint32_t b = big[it];
+    const uint32_t lo = start[b], hi = start[b + 1];
+    const uint32_t size = hi - lo;
+    if (size > (uint32_t)kLocalSort) {
+      if (threadIdx.x == 0) atomicOr(overflow, 1u);
+      continue;
+    }
+    uint32_t P = 2;
+    while (P < size) P <<= 1;
+    for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
+      sk[t] = t < size ? key[lo + t] : ~0ull;
+      sv[t] = t < size ? val[lo + t] : ~0u;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
+          const uint32_t u = t ^ j;
+          if (u > t) {
+            const bool up = (t & k) == 0;
+            const bool swap = up ? pair_less(sk[u], sv[u], sk[t], sv[t]) : pair_less(sk[t], sv[t], sk[u], sv[u]);
+            if (swap) {
+              const unsigned long long tk = sk[t];
+              sk[t] = sk[u];
+              sk[u] = tk;
+              const uint32_t tv = sv[t];
+              sv[t] = sv[u];
+              sv[u] = tv;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) {
+      key[lo + t] = sk[t];
+      val[lo + t] = sv[t];
+    }
+    __syncthreads();
   }
 }
 
@@ -338,31 +529,36 @@ static int log2_ceil(uint64_t x) {
 }
 
 struct BucketBufs {
-  uint32_t *count;       // bucket counters (>= max_buckets words)
+  uint32_t *count;       // nb + 1 bucket starts (>= max_buckets + 1 words)
   size_t max_buckets;
-  uint32_t *overflow;    // device flag
+  uint32_t *overflow;    // device words: [0] overflow flag, [1] listed big buckets
+  uint32_t *big;         // big-bucket list (>= max_buckets words)
   uint32_t *map;         // per-instance bucket map (3 words per instance)
   uint32_t *pinned_flag; // host mirrors
   uint32_t *pinned_map;
 };
 
-// Sorts (b.k0, b.v0) into (b.k1, b.v1) by (key, value), leaving (k0, v0)
-// intact.  `items[i]` is the number of keys of instance i and `range[i]` the
-// extent of their local value.  Returns 1 when the map needs more buckets than
-// the scratch holds (nothing launched).  Otherwise the work is enqueued and
-// *bb.pinned_flag receives, once the stream reaches it, 0 when sorted, bit 0
-// when a bucket was too large for LDS, bit 1 when a key fell outside the map
-// (then (k1, v1) are not sorted).
-template <bool AGG>
+// Sorts the items (b.k0, b.v0) by (key, value) into (out_k, out_v), which is
+// (b.k1, b.v1) or, after an even number of radix passes, (b.k0, b.v0).
+// CLUSTERED picks the grouping by bucket counters, which leaves (k0, v0)
+// intact; the radix passes over the bucket number use both pairs.  `items[i]`
+// is the number of keys of instance i and `range[i]` the extent of their local
+// value.  Returns 1 when the map needs more buckets than the scratch holds
+// (nothing launched).  Otherwise the work is enqueued and *bb.pinned_flag
+// receives, once the stream reaches it, 0 when sorted, bit 0 when a bucket was
+// too large for LDS, bit 1 when a key fell outside the map (then the output is
+// not sorted).
+template <bool CLUSTERED>
 static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shift, int local_shift,
                             unsigned long long local_mask, const std::vector<uint64_t> &items,
-                            const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp) {
+                            const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp,
+                            const unsigned long long *&out_k, const uint32_t *&out_v) {
   const size_t ni = items.size();
   std::vector<uint32_t> base(ni), cnt(ni);
   std::vector<float> scale(ni);
   size_t nb = 0;
   for (size_t i = 0; i < ni; ++i) {
-    const uint64_t c = std::max<uint64_t>(1, (items[i] + 255) / 256);
+    const uint64_t c = std::max<uint64_t>(1, (items[i] + 127) / 128);
     base[i] = (uint32_t)nb;
     cnt[i] = (uint32_t)c;
     scale[i] = (float)((double)c / std::max(range[i], 1.0));
@@ -377,13 +573,37 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shif
   std::memcpy(bb.pinned_map + 2 * ni, scale.data(), ni * 4);
   (void)hipMemcpyAsync(bb.map, bb.pinned_map, 3 * ni * 4, hipMemcpyHostToDevice, st);
   BucketMap M{inst_shift, local_shift, local_mask, d_base, d_cnt, d_scale, (uint32_t)ni, (uint32_t)nb};
-  launch_fill_u32(bb.count, 0u, nb, st);
-  launch_fill_u32(bb.overflow, 0u, 1, st);
+  launch_fill_u32(bb.overflow, 0u, 2, st);
   const unsigned g = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_bucket_count<AGG>, dim3(g), dim3(256), 0, st, b.k0, n, M, bb.count, bb.overflow);
-  exclusive_scan(bb.count, nb, scan_tmp, st);
-  hipLaunchKernelGGL(k_bucket_scatter<AGG>, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, M, bb.count, b.k1, b.v1);
-  hipLaunchKernelGGL(k_bucket_local_sort, dim3((unsigned)nb), dim3(256), 0, st, b.k1, b.v1, bb.count, bb.overflow);
+  unsigned long long *ko = b.k1;
+  uint32_t *vo = b.v1;
+  if constexpr (CLUSTERED) {
+    // count[0] = 0 and count[1 + b] counts bucket b: after the scan and the
+    // scatter, count[b] is the start of bucket b and count[b + 1] its end
+    launch_fill_u32(bb.count, 0u, nb + 1, st);
+    hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, b.k0, n, M, bb.count + 1, bb.overflow);
+    exclusive_scan(bb.count + 1, nb, scan_tmp, st);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, M, bb.count + 1, b.k1, b.v1);
+  } else {
+    // stable passes over the bucket number, low digit first, (k0, v0) -> (k1, v1) -> ...
+    const int bits = std::max(1, log2_ceil(nb + 1));
+    const int passes = (bits + 7) / 8;
+    const int width = (bits + passes - 1) / passes;
+    for (int p = 0; p < passes; ++p) {
+      const bool odd = (p & 1) != 0;
+      radix_pass(b, odd ? b.k1 : b.k0, odd ? b.v1 : b.v0, odd ? b.k0 : b.k1, odd ? b.v0 : b.v1, n,
+                 BucketDigit{M, p * width, (1u << width) - 1u}, st);
+    }
+    ko = (passes & 1) ? b.k1 : b.k0;
+    vo = (passes & 1) ? b.v1 : b.v0;
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, st, ko, n, M, bb.count, bb.overflow);
+  }
+  hipLaunchKernelGGL(k_bucket_wave_sort, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, ko, vo, bb.count,
+                     (uint32_t)nb, bb.big, bb.overflow + 1);
+  hipLaunchKernelGGL(k_bucket_block_sort, dim3(256), dim3(256), 0, st, ko, vo, bb.count, bb.big, bb.overflow + 1,
+                     bb.overflow);
+  out_k = ko;
+  out_v = vo;
   (void)hipMemcpyAsync(bb.pinned_flag, bb.overflow, 4, hipMemcpyDeviceToHost, st);
   return 0u;
 }
@@ -609,11 +829,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
 
   // scratch: 2 key + 2 value arrays, flags, positions, single instances, radix
   // histogram, scan temp, bucket counters and maps, instance table
-  const size_t tiles = (n + kSortTile - 1) / kSortTile;
+  const size_t tiles = tile_count(n);
   const size_t max_buckets = n / 128 + 1024 + 2 * ni;
   const size_t scan_words = scan_scratch_words(std::max<size_t>(std::max<size_t>(256 * tiles, n), max_buckets));
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
-                      align_up(scan_words * 4) + align_up(max_buckets * 4) + align_up(ni * 4) * 8 + 1024;
+                      align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) * 2 + align_up(ni * 4) * 8 + 1024;
   if (scr.bytes < need) {
     if (scr.buf) (void)hipFree(scr.buf);
     scr.buf = nullptr;
@@ -654,8 +874,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   unsigned long long *tmax_dev = (unsigned long long *)take(8);
   uint32_t *err_flag = (uint32_t *)take(8);
   BucketBufs bb;
-  bb.count = (uint32_t *)take(max_buckets * 4);
+  bb.count = (uint32_t *)take((max_buckets + 1) * 4);
   bb.max_buckets = max_buckets;
+  bb.big = (uint32_t *)take(max_buckets * 4);
   bb.overflow = (uint32_t *)take(8);
   bb.map = (uint32_t *)take(ni * 4 * 3);
   uint32_t *d_tab = (uint32_t *)take(ni * 4 * 4); // first, n_events, cpp, rng
@@ -718,6 +939,8 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const int hit_bits = hit_shift + event_bits + inst_bits;
   const unsigned long long *hk = sb.k1;
   const uint32_t *hp = sb.v1;
+  const unsigned long long *bk = nullptr;
+  const uint32_t *bv = nullptr;
   // 2. adder: single index of each run = exclusive scan of run heads
   auto run_heads = [&]() {
     hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
@@ -726,8 +949,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     (void)hipMemcpyAsync(rb + 1, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
   };
   rb[12] = 0u;
-  const bool mapped = bucket_sort<true>(sb, bb, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp) == 0;
-  if (!mapped) { // too many buckets for the scratch: sort every key bit instead
+  const bool mapped =
+      bucket_sort<true>(sb, bb, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp, bk, bv) == 0;
+  if (mapped) {
+    hk = bk;
+    hp = bv;
+  } else { // too many buckets for the scratch: sort every key bit instead
     const bool f1 = radix_sort(sb, n, hit_bits, st);
     hk = f1 ? sb.k1 : sb.k0;
     hp = f1 ? sb.v1 : sb.v0;
@@ -813,9 +1040,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   if (nw == 1) {
     tk = sb.k0;
     ti = sb.v0;
-  } else if (bucket_sort<false>(sb, bb, nw, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st, sb.scan_tmp) ==
-             0) {
+  } else if (bucket_sort<false>(sb, bb, nw, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st, sb.scan_tmp,
+                                bk, bv) == 0) {
     tmapped = true;
+    tk = bk;
+    ti = bv;
   } else {
     const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
     tk = f2 ? sb.k1 : sb.k0;
@@ -823,7 +1052,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   }
   run_coinc();
   if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
-  if (tmapped && rb[12]) { // a bucket overflowed LDS: sort every key bit and redo the pairing
+  if (tmapped && rb[12]) { // a bucket overflowed LDS: rebuild the keys, sort every bit, redo the pairing
+    hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->in_window, wpos,
+                       (const unsigned long long *)S->time_ps, s_inst, ni > 1 ? time_bits : 64, sb.k0, sb.v0);
     const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
     tk = f2 ? sb.k1 : sb.k0;
     ti = f2 ? sb.v1 : sb.v0;

@@ -207,10 +207,12 @@ def _oracle_hits(oracle_mod, ev, gid, edep, time_ps):
     return h
 
 
-@pytest.mark.parametrize("case", ["same_time", "one_event", "random"])
+@pytest.mark.parametrize("case", ["same_time", "one_event", "mid_bucket", "random"])
 def test_digitizer_crafted_against_oracle(ctx, oracle_mod, case):
     """Inputs that push the bucket sort into its fallback (a bucket larger than
-    LDS holds) and a plain random case; singles and coincidences element-wise."""
+    LDS holds), buckets too large for one wave but within LDS (an event with
+    700 hits, 1500 hits at one time stamp) and a plain random case; singles
+    and coincidences element-wise."""
     sc = G.small_animal_scene("C", n_events=10)
     o = _both(ctx, oracle_mod, sc)
     rng = np.random.default_rng(3)
@@ -226,6 +228,12 @@ def test_digitizer_crafted_against_oracle(ctx, oracle_mod, case):
         ev = np.full(n, 5)
         gid = rng.permutation(nc)[:n]
         t = 10**9 + rng.integers(0, 20000, n)
+    elif case == "mid_bucket":
+        n = 20_000
+        ev = np.sort(np.concatenate([rng.integers(0, 20_000, n - 700), np.full(700, 1234)]))
+        gid = rng.integers(0, nc, n)
+        t = rng.integers(0, 20_000 * 2000, n)
+        t[rng.permutation(n)[:1500]] = 7 * 10**6
     else:
         n = 50_000
         ev = np.sort(rng.integers(0, 40_000, n))
