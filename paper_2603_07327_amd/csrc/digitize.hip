@@ -24,44 +24,88 @@
 namespace gpet {
 
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 4;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
+// exclusive prefix sum of one value per thread over a 256-thread block
+// (wave_tot: 4 words of LDS; ends with the block synchronized once)
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t x, uint32_t *wave_tot) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wave_tot[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int k = 0; k < w; ++k) before += wave_tot[k];
+  return before + inc - x;
+}
+
 // ---------------------------------------------------------------------------
-// exclusive scan of u32 (in place); block totals scanned recursively
+// exclusive scan of u32 in place: tile sums, their scan (recursively), then
+// each tile scanned with its offset.  The grand total can go straight to a
+// (pinned host) word, so no copy is needed to read it back.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kScanBlock) k_scan_tiles(uint32_t *a, size_t n, uint32_t *tile_sums) {
-  __shared__ uint32_t s[kScanBlock];
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const uint32_t *a, size_t n, uint32_t *tile_sums) {
+  __shared__ uint32_t ws[kScanBlock / 64];
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const size_t i = base + (size_t)r * kScanBlock + threadIdx.x;
+    if (i < n) s += a[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (__lane_id() == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// thread t scans the 16 consecutive items [t 16, t 16 + 16) of its tile
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t *a, size_t n, const uint32_t *tile_offs,
+                                                           uint32_t *total) {
+  __shared__ uint32_t ws[kScanBlock / 64];
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems], run = 0;
+  uint32_t v[kScanItems];
+  const bool full = base + kScanItems <= n && (((uintptr_t)a) & 15u) == 0;
+  if (full) {
+    const uint4 *q = (const uint4 *)(a + base);
+#pragma unroll
+    for (int k = 0; k < kScanItems / 4; ++k) {
+      const uint4 u = q[k];
+      v[4 * k] = u.x;
+      v[4 * k + 1] = u.y;
+      v[4 * k + 2] = u.z;
+      v[4 * k + 3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = base + k < n ? a[base + k] : 0u;
+  }
+  uint32_t run = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? a[base + k] : 0u;
     const uint32_t t = v[k];
     v[k] = run;
     run += t;
   }
-  s[threadIdx.x] = run;
-  __syncthreads();
-  for (int o = 1; o < kScanBlock; o <<= 1) {
-    const uint32_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-    __syncthreads();
-    s[threadIdx.x] += t;
-    __syncthreads();
+  const uint32_t off = block_exclusive_256(run, ws) + (tile_offs ? tile_offs[blockIdx.x] : 0u);
+  if (full) {
+    uint4 *q = (uint4 *)(a + base);
+#pragma unroll
+    for (int k = 0; k < kScanItems / 4; ++k)
+      q[k] = make_uint4(v[4 * k] + off, v[4 * k + 1] + off, v[4 * k + 2] + off, v[4 * k + 3] + off);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < n) a[base + k] = v[k] + off;
   }
-  const uint32_t excl = s[threadIdx.x] - run;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) a[base + k] = v[k] + excl;
-  if (threadIdx.x == kScanBlock - 1 && tile_sums) tile_sums[blockIdx.x] = s[kScanBlock - 1];
-}
-
-__global__ void k_scan_add(uint32_t *a, size_t n, const uint32_t *tile_offs) {
-  const size_t i = (size_t)blockIdx.x * kScanTile + threadIdx.x;
-  const uint32_t off = tile_offs[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (i + (size_t)k * kScanBlock < n) a[i + (size_t)k * kScanBlock] += off;
+  // the thread holding the last item knows the grand total
+  if (total && base < n && base + kScanItems >= n) *total = off + run;
 }
 
 static size_t scan_scratch_words(size_t n) {
@@ -73,21 +117,23 @@ static size_t scan_scratch_words(size_t n) {
   return w + 1;
 }
 
-static void exclusive_scan(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st) {
+// `total` (may be null) receives the sum
+static void exclusive_scan(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st, uint32_t *total = nullptr) {
   if (n == 0) return;
   const size_t tiles = (n + kScanTile - 1) / kScanTile;
   if (tiles == 1) {
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, st, a, n, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanBlock), 0, st, a, n, (const uint32_t *)nullptr, total);
     return;
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, tmp);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, (const uint32_t *)a, n, tmp);
   exclusive_scan(tmp, tiles, tmp + tiles, st);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, tmp);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, (const uint32_t *)tmp,
+                     total);
 }
 
 // ---------------------------------------------------------------------------
 // Bucket map: a monotone map of (u64) keys spread evenly over their range
-// (event ids, event times) to buckets of about 128 keys.
+// (event ids, event times) to buckets of a few dozen keys.
 // ---------------------------------------------------------------------------
 // Bucket of a key: instance i = key >> inst_shift owns buckets
 // [base[i], base[i] + count[i]); inside them the bucket grows linearly with the
@@ -146,22 +192,6 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t digit, bool valid) {
     m &= bit ? v : ~v;
   }
   return m;
-}
-
-// exclusive prefix sum of one value per thread over a 256-thread block
-__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t x, uint32_t *wave_tot) {
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  uint32_t inc = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == 63) wave_tot[w] = inc;
-  __syncthreads();
-  uint32_t before = 0;
-  for (int k = 0; k < w; ++k) before += wave_tot[k];
-  return before + inc - x;
 }
 
 template <class Digit>
@@ -294,8 +324,8 @@ static bool radix_sort(SortBufs &b, size_t n, int bits, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Bucket sort of (u64 key, u32 value) by (key, value): order the items by
-// bucket, then sort each bucket: one wave per bucket with a register bitonic
-// network, the rare larger bucket in LDS.  Two ways to group by bucket:
+// bucket, then sort each bucket: a wave per few buckets with a register
+// bitonic network, the rare larger bucket in LDS.  Two ways to group by bucket:
 //   * clustered keys (hits: an event's hits share a bucket) -- per-bucket
 //     counters with one atomic per group of equal buckets in a wave, scan,
 //     scatter; the order inside a bucket depends on the atomics;
@@ -304,6 +334,7 @@ static bool radix_sort(SortBufs &b, size_t n, int bits, hipStream_t st) {
 // The final sort by (key, value) makes the result deterministic either way.
 // ---------------------------------------------------------------------------
 constexpr int kLocalSort = 1024; // largest bucket sorted in LDS
+constexpr int kBucketMean = 48;  // target items per bucket: most fit one per lane
 
 // lanes of the wave whose value equals this lane's (one ballot per distinct value)
 __device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
@@ -318,12 +349,12 @@ __device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
   return mine;
 }
 
-// keys whose bucket falls outside the map are skipped and flagged (bit 1 of *flag)
+// keys whose bucket falls outside the map are skipped and flagged (*flag = 2)
 __global__ void k_bucket_count(const unsigned long long *key, size_t n, BucketMap M, uint32_t *count,
                                uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t kb = i < n ? bucket_of(M, key[i]) : 0u;
-  if (i < n && kb >= M.nb) atomicOr(flag, 2u);
+  if (i < n && kb >= M.nb) *flag = 2u;
   const bool valid = i < n && kb < M.nb;
   const uint32_t b = valid ? kb : 0u;
   const uint64_t peers = equal_peers(b, valid);
@@ -352,13 +383,13 @@ __global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *
 }
 
 // start[b] = first position of bucket b in keys sorted by bucket, b in [0, nb];
-// keys outside the map (bucket nb) sit at the end and are flagged (bit 1)
+// keys outside the map (bucket nb) sit at the end and are flagged (*flag = 2)
 __global__ void k_bucket_bounds(const unsigned long long *key, size_t n, BucketMap M, uint32_t *start,
                                 uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t b = min(bucket_of(M, key[i]), M.nb);
-  if (b == M.nb && (i == 0 || min(bucket_of(M, key[i - 1]), M.nb) != M.nb)) atomicOr(flag, 2u);
+  if (b == M.nb && (i == 0 || min(bucket_of(M, key[i - 1]), M.nb) != M.nb)) *flag = 2u;
   const int64_t prev = i ? (int64_t)min(bucket_of(M, key[i - 1]), M.nb) : -1;
   for (int64_t q = prev + 1; q <= (int64_t)b; ++q) start[q] = (uint32_t)i;
   if (i == n - 1)
@@ -378,11 +409,46 @@ __device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, un
   return ka < kb || (ka == kb && va < vb);
 }
 
-// Bitonic sort of P = 64 E (key, value) pairs held E per lane, ascending by
-// (key, value).  Element l E + r sits in register r of lane l, so partners
-// closer than E stay in the lane and the others are one lane shuffle away.
+// Value of lane (lane ^ lx) for lx in {1, 2, 4, 8, 16, 32} without the LDS
+// crossbar: DPP quad permutes (1, 2), row shifts (4), a row rotation (8) and
+// the gfx950 half-row / half-wave swaps (16, 32).  lx must fold to a constant.
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lx) {
+  const uint32_t lane = __lane_id();
+  switch (lx) {
+  case 1:
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false); // quad_perm [1,0,3,2]
+  case 2:
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false); // quad_perm [2,3,0,1]
+  case 4: {
+    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, false); // lane + 4
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false); // lane - 4
+    return (lane & 4u) ? dn : up;
+  }
+  case 8:
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false); // row_ror:8
+  case 16: {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (lane & 16u) ? r[0] : r[1];
+  }
+  case 32: {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane & 32u) ? r[0] : r[1];
+  }
+  default:
+    return (uint32_t)__shfl_xor((int)x, lx);
+  }
+}
+
+__device__ __forceinline__ unsigned long long lane_xor_u64(unsigned long long x, int lx) {
+  const uint32_t lo = lane_xor((uint32_t)x, lx), hi = lane_xor((uint32_t)(x >> 32), lx);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Bitonic sort of P = 64 E packed u64 items held E per lane, ascending.
+// Element l E + r sits in register r of lane l, so partners closer than E stay
+// in the lane and the others are one lane exchange away.
 template <int E>
-__device__ __forceinline__ void wave_bitonic(unsigned long long (&k)[E], uint32_t (&v)[E]) {
+__device__ __forceinline__ void wave_bitonic_u64(unsigned long long (&p)[E]) {
   const int lane = __lane_id();
   constexpr int P = 64 * E;
 #pragma unroll
@@ -395,14 +461,9 @@ __device__ __forceinline__ void wave_bitonic(unsigned long long (&k)[E], uint32_
           const int u = r ^ j;
           if (u > r) {
             const bool asc = ((lane * E + r) & kk) == 0;
-            if (asc ? pair_less(k[u], v[u], k[r], v[r]) : pair_less(k[r], v[r], k[u], v[u])) {
-              const unsigned long long tk = k[r];
-              k[r] = k[u];
-              k[u] = tk;
-              const uint32_t tv = v[r];
-              v[r] = v[u];
-              v[u] = tv;
-            }
+            const unsigned long long lo = p[r] < p[u] ? p[r] : p[u], hi = p[r] < p[u] ? p[u] : p[r];
+            p[r] = asc ? lo : hi;
+            p[u] = asc ? hi : lo;
           }
         }
       } else {
@@ -411,64 +472,118 @@ __device__ __forceinline__ void wave_bitonic(unsigned long long (&k)[E], uint32_
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           const bool asc = ((lane * E + r) & kk) == 0;
-          const unsigned long long pk = __shfl_xor(k[r], lx);
-          const uint32_t pv = __shfl_xor(v[r], lx);
-          const bool p_less = pair_less(pk, pv, k[r], v[r]);
+          const unsigned long long q = lane_xor_u64(p[r], lx);
+          const bool q_less = q < p[r];
           // the lower element of an ascending pair keeps the smaller one
-          if (lower == asc ? p_less : !p_less) {
-            k[r] = pk;
-            v[r] = pv;
-          }
+          if (lower == asc ? q_less : !q_less) p[r] = q;
         }
       }
     }
   }
 }
 
-// sorts key/val[lo, lo + size) in place with one wave, size <= 64 E
+// Sorts the first 64 E (key, value) items of k/v (lane-major, `size` >= 1
+// real items, the rest ~0) with one wave.  Each key is taken relative to the
+// first item's key b: u = key - b + 2^(63 - vbits), and u << vbits | value is
+// one u64 whose order is the (key, value) order when every value is below
+// 2^vbits and every u fits 64 - vbits bits short of all ones.  Returns false,
+// leaving k/v as they were, when some key lies too far from b.
 template <int E>
-__device__ __forceinline__ void wave_sort_range(unsigned long long *key, uint32_t *val, uint32_t lo,
-                                                uint32_t size) {
+__device__ __forceinline__ bool wave_sort_packed(unsigned long long (&k)[2], uint32_t (&v)[2], uint32_t size,
+                                                 int vbits) {
   const uint32_t lane = __lane_id();
-  unsigned long long k[E];
-  uint32_t v[E];
+  const unsigned long long b =
+      ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(k[0] >> 32)) << 32) |
+      (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)k[0]);
+  const long long bias = 1ll << (63 - vbits);
+  bool far = false;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const uint32_t t = lane * E + r;
-    k[r] = t < size ? key[lo + t] : ~0ull;
-    v[r] = t < size ? val[lo + t] : ~0u;
+    const long long d = (long long)(k[r] - b);
+    if (lane * E + r < size && (d < -bias || d > bias - 2)) far = true;
   }
-  wave_bitonic<E>(k, v);
+  if (__ballot(far)) return false;
+  unsigned long long p[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r)
+    p[r] = lane * E + r < size ? ((k[r] - b + (unsigned long long)bias) << vbits) | v[r] : ~0ull;
+  wave_bitonic_u64<E>(p);
+  const unsigned long long vmask = (1ull << vbits) - 1ull;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const uint32_t t = lane * E + r;
-    if (t < size) {
-      key[lo + t] = k[r];
-      val[lo + t] = v[r];
-    }
+    k[r] = (p[r] >> vbits) + b - (unsigned long long)bias;
+    v[r] = (uint32_t)(p[r] & vmask);
+  }
+  return true;
+}
+
+constexpr int kWaveSort = 128;   // largest bucket sorted by one wave
+constexpr int kWaveBuckets = 4;  // consecutive buckets per wave
+
+// a bucket of up to 64 items goes one per lane, up to 128 two per lane
+__device__ __forceinline__ void wave_load_bucket(const unsigned long long *key, const uint32_t *val, uint32_t lo,
+                                                 uint32_t size, unsigned long long (&k)[2], uint32_t (&v)[2]) {
+  const uint32_t lane = __lane_id();
+  const uint32_t e = size <= 64 ? 1u : 2u;
+  const uint32_t n_ld = size <= (uint32_t)kWaveSort ? size : 0u;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const uint32_t t = lane * e + r;
+    const bool ld = r < (int)e && t < n_ld;
+    k[r] = ld ? key[lo + t] : ~0ull;
+    v[r] = ld ? val[lo + t] : ~0u;
   }
 }
 
-constexpr int kWaveSort = 256; // largest bucket sorted by one wave
-
-// one wave per bucket; bucket b spans [start[b], start[b + 1]).  Buckets too
-// large for a wave are listed in big[] (count in *n_big) for the block sort.
+// kWaveBuckets consecutive buckets per wave, the next one loading while the
+// current one sorts; bucket b spans [start[b], start[b + 1]).  Buckets a wave
+// cannot take (over 128 items, keys spanning 2^32 or more) are listed in big[]
+// (count in *n_big) for the block sort.  Values are below 2^vbits (1..32).
 __global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *key, uint32_t *val,
-                                                          const uint32_t *start, uint32_t nb, uint32_t *big,
-                                                          uint32_t *n_big) {
-  const uint32_t b = blockIdx.x * 4u + (threadIdx.x >> 6);
-  if (b >= nb) return;
-  const uint32_t lo = start[b], hi = start[b + 1];
-  const uint32_t size = hi - lo;
-  if (size <= 1) return;
-  if (size <= 64) {
-    wave_sort_range<1>(key, val, lo, size);
-  } else if (size <= 128) {
-    wave_sort_range<2>(key, val, lo, size);
-  } else if (size <= (uint32_t)kWaveSort) {
-    wave_sort_range<4>(key, val, lo, size);
-  } else if (__lane_id() == 0) {
-    big[atomicAdd(n_big, 1u)] = b;
+                                                          const uint32_t *start, uint32_t nb, int vbits,
+                                                          uint32_t *big, uint32_t *n_big) {
+  const uint32_t b0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * kWaveBuckets;
+  if (b0 >= nb) return;
+  const uint32_t lane = __lane_id();
+  const uint32_t nq = min((uint32_t)kWaveBuckets, nb - b0);
+  uint32_t lo = start[b0], hi = start[b0 + 1];
+  unsigned long long k[2];
+  uint32_t v[2];
+  wave_load_bucket(key, val, lo, hi - lo, k, v);
+#pragma unroll 1
+  for (uint32_t q = 0; q < nq; ++q) {
+    uint32_t nhi = hi;
+    unsigned long long kn[2] = {~0ull, ~0ull};
+    uint32_t vn[2] = {~0u, ~0u};
+    if (q + 1 < nq) {
+      nhi = start[b0 + q + 2];
+      wave_load_bucket(key, val, hi, nhi - hi, kn, vn);
+    }
+    const uint32_t size = hi - lo;
+    bool listed = size > (uint32_t)kWaveSort;
+    if (size > 1 && !listed) {
+      const uint32_t e = size <= 64 ? 1u : 2u;
+      if (e == 1 ? wave_sort_packed<1>(k, v, size, vbits) : wave_sort_packed<2>(k, v, size, vbits)) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const uint32_t t = lane * e + r;
+          if (r < (int)e && t < size) {
+            key[lo + t] = k[r];
+            val[lo + t] = v[r];
+          }
+        }
+      } else {
+        listed = true;
+      }
+    }
+    if (listed && lane == 0) big[atomicAdd(n_big, 1u)] = b0 + q;
+    lo = hi;
+    hi = nhi;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      k[r] = kn[r];
+      v[r] = vn[r];
+    }
   }
 }
 
@@ -484,7 +599,7 @@ __global__ void __launch_bounds__(256) k_bucket_block_sort(unsigned long long *k
     const uint32_t lo = start[b], hi = start[b + 1];
     const uint32_t size = hi - lo;
     if (size > (uint32_t)kLocalSort) {
-      if (threadIdx.x == 0) atomicOr(overflow, 1u);
+      if (threadIdx.x == 0) *overflow = 1u;
       continue;
     }
     uint32_t P = 2;
@@ -531,25 +646,27 @@ static int log2_ceil(uint64_t x) {
 struct BucketBufs {
   uint32_t *count;       // nb + 1 bucket starts (>= max_buckets + 1 words)
   size_t max_buckets;
-  uint32_t *overflow;    // device words: [0] overflow flag, [1] listed big buckets
+  uint32_t *n_big;       // device word: listed big buckets
   uint32_t *big;         // big-bucket list (>= max_buckets words)
   uint32_t *map;         // per-instance bucket map (3 words per instance)
-  uint32_t *pinned_flag; // host mirrors
+  uint32_t *pinned_flag; // pinned host word the kernels set when the bucket sort fails
   uint32_t *pinned_map;
 };
 
-// Sorts the items (b.k0, b.v0) by (key, value) into (out_k, out_v), which is
+// Sorts the items (b.k0, b.v0), whose values are below value_bound (at most
+// 2^32), by (key, value) into (out_k, out_v), which is
 // (b.k1, b.v1) or, after an even number of radix passes, (b.k0, b.v0).
 // CLUSTERED picks the grouping by bucket counters, which leaves (k0, v0)
 // intact; the radix passes over the bucket number use both pairs.  `items[i]`
 // is the number of keys of instance i and `range[i]` the extent of their local
 // value.  Returns 1 when the map needs more buckets than the scratch holds
-// (nothing launched).  Otherwise the work is enqueued and *bb.pinned_flag
-// receives, once the stream reaches it, 0 when sorted, bit 0 when a bucket was
-// too large for LDS, bit 1 when a key fell outside the map (then the output is
-// not sorted).
+// (nothing launched).  Otherwise the work is enqueued; the caller zeroes
+// *bb.pinned_flag beforehand and finds it nonzero after the stream has run the
+// work when a bucket was too large for LDS (1) or a key fell outside the map
+// (2): then the output is not sorted.  The kernels store to the pinned word
+// directly, so no copy is needed to read it.
 template <bool CLUSTERED>
-static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shift, int local_shift,
+static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t value_bound, int inst_shift, int local_shift,
                             unsigned long long local_mask, const std::vector<uint64_t> &items,
                             const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp,
                             const unsigned long long *&out_k, const uint32_t *&out_v) {
@@ -558,7 +675,7 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shif
   std::vector<float> scale(ni);
   size_t nb = 0;
   for (size_t i = 0; i < ni; ++i) {
-    const uint64_t c = std::max<uint64_t>(1, (items[i] + 127) / 128);
+    const uint64_t c = std::max<uint64_t>(1, (items[i] + kBucketMean - 1) / kBucketMean);
     base[i] = (uint32_t)nb;
     cnt[i] = (uint32_t)c;
     scale[i] = (float)((double)c / std::max(range[i], 1.0));
@@ -573,7 +690,7 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shif
   std::memcpy(bb.pinned_map + 2 * ni, scale.data(), ni * 4);
   (void)hipMemcpyAsync(bb.map, bb.pinned_map, 3 * ni * 4, hipMemcpyHostToDevice, st);
   BucketMap M{inst_shift, local_shift, local_mask, d_base, d_cnt, d_scale, (uint32_t)ni, (uint32_t)nb};
-  launch_fill_u32(bb.overflow, 0u, 2, st);
+  launch_fill_u32(bb.n_big, 0u, 1, st);
   const unsigned g = (unsigned)((n + 255) / 256);
   unsigned long long *ko = b.k1;
   uint32_t *vo = b.v1;
@@ -581,7 +698,7 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shif
     // count[0] = 0 and count[1 + b] counts bucket b: after the scan and the
     // scatter, count[b] is the start of bucket b and count[b + 1] its end
     launch_fill_u32(bb.count, 0u, nb + 1, st);
-    hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, b.k0, n, M, bb.count + 1, bb.overflow);
+    hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, b.k0, n, M, bb.count + 1, bb.pinned_flag);
     exclusive_scan(bb.count + 1, nb, scan_tmp, st);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, M, bb.count + 1, b.k1, b.v1);
   } else {
@@ -596,15 +713,15 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, int inst_shif
     }
     ko = (passes & 1) ? b.k1 : b.k0;
     vo = (passes & 1) ? b.v1 : b.v0;
-    hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, st, ko, n, M, bb.count, bb.overflow);
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, st, ko, n, M, bb.count, bb.pinned_flag);
   }
-  hipLaunchKernelGGL(k_bucket_wave_sort, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, ko, vo, bb.count,
-                     (uint32_t)nb, bb.big, bb.overflow + 1);
-  hipLaunchKernelGGL(k_bucket_block_sort, dim3(256), dim3(256), 0, st, ko, vo, bb.count, bb.big, bb.overflow + 1,
-                     bb.overflow);
+  const size_t sort_waves = (nb + kWaveBuckets - 1) / kWaveBuckets;
+  hipLaunchKernelGGL(k_bucket_wave_sort, dim3((unsigned)((sort_waves + 3) / 4)), dim3(256), 0, st, ko, vo, bb.count,
+                     (uint32_t)nb, std::max(1, log2_ceil(value_bound)), bb.big, bb.n_big);
+  hipLaunchKernelGGL(k_bucket_block_sort, dim3(256), dim3(256), 0, st, ko, vo, bb.count, bb.big, bb.n_big,
+                     bb.pinned_flag);
   out_k = ko;
   out_v = vo;
-  (void)hipMemcpyAsync(bb.pinned_flag, bb.overflow, 4, hipMemcpyDeviceToHost, st);
   return 0u;
 }
 
@@ -619,7 +736,7 @@ struct InstTab {
 
 // key = instance | (event - first) | gid | photon | index of the hit within its
 // photon (7 bits, saturated): unique per hit, so the sorted order is fixed.
-// Hits outside their instance's event range are flagged (bit 1 of *flag).
+// Hits outside their instance's event range are flagged (*flag = 2).
 __global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux,
                            const uint32_t *hinst, InstTab T, int gid_bits, int inst_shift, unsigned long long *key,
                            uint32_t *val, uint32_t *flag) {
@@ -630,7 +747,7 @@ __global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, co
   const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
   uint32_t e = 0;
   if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in]) {
-    atomicOr(flag, 2u);
+    *flag = 2u;
   } else {
     e = ev[i] - T.first[in];
   }
@@ -830,7 +947,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   // scratch: 2 key + 2 value arrays, flags, positions, single instances, radix
   // histogram, scan temp, bucket counters and maps, instance table
   const size_t tiles = tile_count(n);
-  const size_t max_buckets = n / 128 + 1024 + 2 * ni;
+  const size_t max_buckets = n / kBucketMean + 1024 + 2 * ni;
   const size_t scan_words = scan_scratch_words(std::max<size_t>(std::max<size_t>(256 * tiles, n), max_buckets));
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
                       align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) * 2 + align_up(ni * 4) * 8 + 1024;
@@ -871,18 +988,17 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   uint32_t *s_inst = (uint32_t *)take(n * 4);
   sb.hist = (uint32_t *)take(256 * tiles * 4);
   sb.scan_tmp = (uint32_t *)take(scan_words * 4);
-  unsigned long long *tmax_dev = (unsigned long long *)take(8);
-  uint32_t *err_flag = (uint32_t *)take(8);
   BucketBufs bb;
   bb.count = (uint32_t *)take((max_buckets + 1) * 4);
   bb.max_buckets = max_buckets;
   bb.big = (uint32_t *)take(max_buckets * 4);
-  bb.overflow = (uint32_t *)take(8);
+  bb.n_big = (uint32_t *)take(8);
   bb.map = (uint32_t *)take(ni * 4 * 3);
   uint32_t *d_tab = (uint32_t *)take(ni * 4 * 4); // first, n_events, cpp, rng
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
-  // pinned host words: [0, 16) scalar readbacks, [16, 16 + ni) per-instance
-  // counts, 3 ni words of bucket-map uploads, 4 ni words of instance table
+  // pinned host words: [0, 16) scalars that kernels write directly (scan
+  // totals, maximum time, failure flags), [16, 16 + ni) per-instance counts,
+  // 3 ni words of bucket-map uploads, 4 ni words of instance table
   uint32_t *rb = (uint32_t *)scr.pinned;
   uint32_t *rb_count = rb + 16;
   bb.pinned_flag = rb + 12;
@@ -918,11 +1034,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   }
 
   // 1. sort hits by (instance, event, gid, photon, index)
-  launch_fill_u32(err_flag, 0u, 1, st);
+  uint32_t *err_flag = rb + 13; // checked at the next synchronization
+  *err_flag = 0u;
   hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux, D.h_inst, IT,
                      D.gid_bits, inst_shift, sb.k0, sb.v0, err_flag);
   std::vector<uint64_t> items(ni, n);
-  (void)hipMemcpyAsync(rb + 13, err_flag, 4, hipMemcpyDeviceToHost, st); // checked at the next synchronization
   if (ni > 1) { // per-instance counts size the bucket map
     launch_fill_u32(d_icount, 0u, ni, st);
     hipLaunchKernelGGL(k_inst_count, dim3(grid_for(n)), dim3(256), 0, st, sb.k0, n, inst_shift, (uint32_t)ni,
@@ -944,13 +1060,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   // 2. adder: single index of each run = exclusive scan of run heads
   auto run_heads = [&]() {
     hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
-    (void)hipMemcpyAsync(rb + 0, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
-    exclusive_scan(flag, n, sb.scan_tmp, st);
-    (void)hipMemcpyAsync(rb + 1, flag + n - 1, 4, hipMemcpyDeviceToHost, st);
+    exclusive_scan(flag, n, sb.scan_tmp, st, rb + 1);
   };
   rb[12] = 0u;
   const bool mapped =
-      bucket_sort<true>(sb, bb, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp, bk, bv) == 0;
+      bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp, bk, bv) == 0;
   if (mapped) {
     hk = bk;
     hp = bv;
@@ -972,7 +1086,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     run_heads();
     if (!sync("after the hit sort")) return GPET_ERR_HIP;
   }
-  const uint64_t ns = (uint64_t)rb[1] + rb[0];
+  const uint64_t ns = rb[1];
   S->count = ns;
   if (ns > S->capacity) {
     err = "digitize: singles capacity too small";
@@ -988,13 +1102,10 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                      T ? T->singles_per_crystal : nullptr, T ? T->energy_spectrum : nullptr,
                      (const unsigned long long *)S->time_ps, sb.k1);
   hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
-                     (size_t)grid_for(ns), tmax_dev);
-  (void)hipMemcpyAsync(rb + 2, wpos + ns - 1, 4, hipMemcpyDeviceToHost, st);
-  exclusive_scan(wpos, ns, sb.scan_tmp, st);
-  (void)hipMemcpyAsync(rb + 3, wpos + ns - 1, 4, hipMemcpyDeviceToHost, st);
-  (void)hipMemcpyAsync(rb + 4, tmax_dev, 8, hipMemcpyDeviceToHost, st);
+                     (size_t)grid_for(ns), (unsigned long long *)(rb + 4));
+  exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
   if (!sync("after the energy window")) return GPET_ERR_HIP;
-  const size_t nw = (size_t)rb[3] + rb[2];
+  const size_t nw = rb[3];
   const unsigned long long tmax = (unsigned long long)rb[4] | ((unsigned long long)rb[5] << 32);
   // time bits leave room for the window, so keys of two instances differ by more than it
   int time_bits = 0;
@@ -1029,9 +1140,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   auto run_coinc = [&]() {
     hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
                        D.window_ps, flag);
-    (void)hipMemcpyAsync(rb + 6, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
-    exclusive_scan(flag, nw, sb.scan_tmp, st);
-    (void)hipMemcpyAsync(rb + 7, flag + nw - 1, 4, hipMemcpyDeviceToHost, st);
+    exclusive_scan(flag, nw, sb.scan_tmp, st, rb + 7);
     hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
                        D.window_ps, flag, C->first, C->second, C->capacity);
   };
@@ -1040,8 +1149,8 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   if (nw == 1) {
     tk = sb.k0;
     ti = sb.v0;
-  } else if (bucket_sort<false>(sb, bb, nw, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st, sb.scan_tmp,
-                                bk, bv) == 0) {
+  } else if (bucket_sort<false>(sb, bb, nw, ns, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st,
+                                sb.scan_tmp, bk, bv) == 0) {
     tmapped = true;
     tk = bk;
     ti = bv;
@@ -1061,7 +1170,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     run_coinc();
     if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
   }
-  C->count = (uint64_t)rb[7] + rb[6];
+  C->count = rb[7];
   if (C->count > C->capacity) {
     err = "digitize: coincidence capacity too small";
     return GPET_ERR_CAPACITY;
@@ -1083,7 +1192,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
 }
 
 size_t scan_tmp_words(size_t n) { return scan_scratch_words(n); }
-void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st) { exclusive_scan(a, n, tmp, st); }
+void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st, uint32_t *total) {
+  exclusive_scan(a, n, tmp, st, total);
+}
 
 void free_scratch(DigitizeScratch &scr) {
   if (scr.pinned) (void)hipHostFree(scr.pinned);

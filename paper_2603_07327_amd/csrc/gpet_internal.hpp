@@ -120,9 +120,10 @@ struct DigitizeArgs {
   const gpet_tallies *tallies = nullptr;
   unsigned long long *coinc_per_inst = nullptr; // host, one count per instance (optional)
 };
-// exclusive prefix sum of n u32 in place; tmp holds scan_tmp_words(n) words
+// exclusive prefix sum of n u32 in place; tmp holds scan_tmp_words(n) words;
+// `total` (may be null, may be pinned host memory) receives the sum
 size_t scan_tmp_words(size_t n);
-void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st);
+void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st, uint32_t *total = nullptr);
 
 // Surrogate entry queue (library scratch): SoA of `cap` entries
 struct SurQueue {

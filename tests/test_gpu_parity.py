@@ -207,12 +207,13 @@ def _oracle_hits(oracle_mod, ev, gid, edep, time_ps):
     return h
 
 
-@pytest.mark.parametrize("case", ["same_time", "one_event", "mid_bucket", "random"])
+@pytest.mark.parametrize("case", ["same_time", "one_event", "mid_bucket", "late_times", "random"])
 def test_digitizer_crafted_against_oracle(ctx, oracle_mod, case):
     """Inputs that push the bucket sort into its fallback (a bucket larger than
     LDS holds), buckets too large for one wave but within LDS (an event with
-    700 hits, 1500 hits at one time stamp) and a plain random case; singles
-    and coincidences element-wise."""
+    700 hits, 1500 hits at one time stamp), a bucket whose time stamps span
+    too much for the packed wave sort (30 hits far beyond the acquisition
+    end) and a plain random case; singles and coincidences element-wise."""
     sc = G.small_animal_scene("C", n_events=10)
     o = _both(ctx, oracle_mod, sc)
     rng = np.random.default_rng(3)
@@ -234,6 +235,12 @@ def test_digitizer_crafted_against_oracle(ctx, oracle_mod, case):
         gid = rng.integers(0, nc, n)
         t = rng.integers(0, 20_000 * 2000, n)
         t[rng.permutation(n)[:1500]] = 7 * 10**6
+    elif case == "late_times":
+        n = 20_000
+        ev = np.sort(rng.integers(0, 20_000, n))
+        gid = rng.integers(0, nc, n)
+        t = rng.integers(0, int(sc["source"]["duration_ps"]), n)
+        t[rng.permutation(n)[:30]] = 2**60 + rng.integers(0, 10**6, 30)
     else:
         n = 50_000
         ev = np.sort(rng.integers(0, 40_000, n))
