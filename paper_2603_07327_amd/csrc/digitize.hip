@@ -736,7 +736,8 @@ struct InstTab {
 
 // key = instance | (event - first) | gid | photon | index of the hit within its
 // photon (7 bits, saturated): unique per hit, so the sorted order is fixed.
-// Hits outside their instance's event range are flagged (*flag = 2).
+// Hits outside their instance's event range or with a crystal id of more than
+// gid_bits bits are flagged (*flag = 2).
 __global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux,
                            const uint32_t *hinst, InstTab T, int gid_bits, int inst_shift, unsigned long long *key,
                            uint32_t *val, uint32_t *flag) {
@@ -746,13 +747,14 @@ __global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, co
   const uint32_t a = aux[i];
   const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
   uint32_t e = 0;
-  if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in]) {
+  const uint32_t g = gid[i];
+  if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in] || (gid_bits < 32 && (g >> gid_bits) != 0)) {
     *flag = 2u;
   } else {
     e = ev[i] - T.first[in];
   }
   const unsigned long long inst_bits = inst_shift < 64 ? (unsigned long long)(in < T.n_inst ? in : 0u) << inst_shift : 0ull;
-  key[i] = inst_bits | ((((unsigned long long)e << gid_bits) | gid[i]) << 8) | low;
+  key[i] = inst_bits | ((((unsigned long long)e << gid_bits) | (g & ((1ull << gid_bits) - 1))) << 8) | low;
   val[i] = (uint32_t)i;
 }
 
@@ -763,14 +765,18 @@ __global__ void k_heads(size_t n, const unsigned long long *key, uint32_t *flag)
   flag[i] = (i == 0 || (key[i] >> 8) != (key[i - 1] >> 8)) ? 1u : 0u;
 }
 
+// One single per run of equal (instance, event, crystal) in key order; the
+// event and crystal come out of the key.  e/d/t are the hits' energy, depth
+// and time, indexed by perm.
 __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t *perm, const uint32_t *seg,
-                        const uint32_t *ev, const uint32_t *gid, const float *edep, const float *depth,
-                        const unsigned long long *time, int inst_shift, uint32_t *s_ev, uint32_t *s_gid,
+                        const float *edep, const float *depth, const unsigned long long *time, InstTab T,
+                        int gid_bits, unsigned long long ev_mask, int inst_shift, uint32_t *s_ev, uint32_t *s_gid,
                         float *s_edep, float *s_depth, unsigned long long *s_time, uint32_t *s_inst_int,
                         uint32_t *s_inst_out, uint64_t cap) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const unsigned long long run = key[i] >> 8;
+  const unsigned long long k = key[i];
+  const unsigned long long run = k >> 8;
   if (i > 0 && (key[i - 1] >> 8) == run) return;
   unsigned long long se = 0, sd = 0, tm = ~0ull;
   size_t j = i;
@@ -784,11 +790,10 @@ __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t 
   } while (j < n && (key[j] >> 8) == run);
   const uint32_t s = seg[i];
   if (s >= cap) return;
-  const uint32_t h = perm[i];
   const double E = (double)se * 0x1p-32;
-  const uint32_t in = inst_shift < 64 ? (uint32_t)(key[i] >> inst_shift) : 0u;
-  s_ev[s] = ev[h];
-  s_gid[s] = gid[h];
+  const uint32_t in = inst_shift < 64 ? (uint32_t)(k >> inst_shift) : 0u;
+  s_ev[s] = T.first[in] + (uint32_t)((run >> gid_bits) & ev_mask);
+  s_gid[s] = (uint32_t)(run & ((1ull << gid_bits) - 1));
   s_edep[s] = (float)E;
   s_depth[s] = se ? (float)((double)sd / (double)se) : 0.0f;
   s_time[s] = tm;
@@ -942,7 +947,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
                        T->hits_per_crystal, T->doi, T->doi_bins, D.panel_depth);
   if (D.coinc_per_inst) std::fill(D.coinc_per_inst, D.coinc_per_inst + ni, 0ull);
-  if (n == 0) return hipStreamSynchronize(st) == hipSuccess ? GPET_OK : GPET_ERR_HIP;
+  if (n == 0) return wait_stream(st) == hipSuccess ? GPET_OK : GPET_ERR_HIP;
 
   // scratch: 2 key + 2 value arrays, flags, positions, single instances, radix
   // histogram, scan temp, bucket counters and maps, instance table
@@ -952,14 +957,17 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
                       align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) * 2 + align_up(ni * 4) * 8 + 1024;
   if (scr.bytes < need) {
+    // a quarter of headroom: hit counts drift from call to call, and a
+    // free + allocate pair costs about as much as the whole digitizer
     if (scr.buf) (void)hipFree(scr.buf);
     scr.buf = nullptr;
     scr.bytes = 0;
-    if (hipMalloc(&scr.buf, need) != hipSuccess) {
+    const size_t grow = need + need / 4;
+    if (hipMalloc(&scr.buf, grow) != hipSuccess) {
       err = "digitize: device scratch allocation failed";
       return GPET_ERR_HIP;
     }
-    scr.bytes = need;
+    scr.bytes = grow;
   }
   const size_t pinned_bytes = 64 + 32 * ni;
   if (scr.pinned_bytes < pinned_bytes) {
@@ -1005,7 +1013,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   bb.pinned_map = rb + 16 + ni;
   uint32_t *tab = rb + 16 + 4 * ni;
   auto sync = [&](const char *what) {
-    if (hipStreamSynchronize(st) != hipSuccess) {
+    if (wait_stream(st) != hipSuccess) {
       err = std::string("digitize: stream error ") + what;
       return false;
     }
@@ -1063,8 +1071,8 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     exclusive_scan(flag, n, sb.scan_tmp, st, rb + 1);
   };
   rb[12] = 0u;
-  const bool mapped =
-      bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st, sb.scan_tmp, bk, bv) == 0;
+  const bool mapped = bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st,
+                                        sb.scan_tmp, bk, bv) == 0;
   if (mapped) {
     hk = bk;
     hp = bv;
@@ -1076,7 +1084,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   run_heads();
   if (!sync("after the hit sort")) return GPET_ERR_HIP;
   if (rb[13] & 2u) {
-    err = "digitize: a hit's instance or event id lies outside its declared range";
+    err = "digitize: a hit's instance, event or crystal id lies outside its declared range";
     return GPET_ERR_ARG;
   }
   if (mapped && rb[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
@@ -1092,8 +1100,8 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     err = "digitize: singles capacity too small";
     return GPET_ERR_CAPACITY;
   }
-  hipLaunchKernelGGL(k_adder, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_event, D.h_gid, D.h_edep,
-                     D.h_depth, D.h_time, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
+  hipLaunchKernelGGL(k_adder, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth, D.h_time, IT,
+                     D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
                      (unsigned long long *)S->time_ps, s_inst, S->instance, S->capacity);
   // 3. blur + window; per-block maxima of the windowed time stamps go to the
   //    (now free) second key array, then one block reduces them
@@ -1189,6 +1197,14 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
   }
   return GPET_OK;
+}
+
+hipError_t wait_stream(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+    __builtin_ia32_pause();
+  }
 }
 
 size_t scan_tmp_words(size_t n) { return scan_scratch_words(n); }

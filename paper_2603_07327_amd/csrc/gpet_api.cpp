@@ -648,7 +648,7 @@ static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, int det_slots, c
   gpet_status s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
   s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, kCtrlWords * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
-  if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "transport: kernel");
+  if (!s) s = hip_check(c, wait_stream(c->stream), "transport: kernel");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (c->timing) (void)hipEventElapsedTime(&c->last_ms[0], c->ev[0], c->ev[1]);
@@ -989,7 +989,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     s = hip_check(c, hipGetLastError(), "surrogate: transport launch");
     if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairs, c->d_ctrl + kCtrlPairs, 8, hipMemcpyDeviceToHost, c->stream),
                           "surrogate: readback");
-    if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "surrogate: transport");
+    if (!s) s = hip_check(c, wait_stream(c->stream), "surrogate: transport");
     if (s) break;
     const uint64_t nq = c->h_ctrl[kCtrlPairs];
     if (nq > Q.cap) {
@@ -1005,7 +1005,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
       s = r;
       break;
     }
-    s = hip_check(c, hipStreamSynchronize(c->stream), "surrogate: network");
+    s = hip_check(c, wait_stream(c->stream), "surrogate: network");
     float a = 0.f, b = 0.f;
     (void)hipEventElapsedTime(&a, ev[0], ev[1]);
     (void)hipEventElapsedTime(&b, ev[2], ev[3]);
@@ -1282,7 +1282,7 @@ gpet_status gpet_batch_read_counts(gpet_batch *b, gpet_hits *h, gpet_stats *stat
   gpet_ctx *c = b->ctx;
   if (!h) return fail(c, GPET_ERR_ARG, "batch counts: null hits");
   s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, kCtrlWords * 8, hipMemcpyDeviceToHost, c->stream), "batch counts");
-  if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "batch counts");
+  if (!s) s = hip_check(c, wait_stream(c->stream), "batch counts");
   if (s) return s;
   h->count = c->h_ctrl[1];
   if (stats) {

@@ -120,6 +120,11 @@ struct DigitizeArgs {
   const gpet_tallies *tallies = nullptr;
   unsigned long long *coinc_per_inst = nullptr; // host, one count per instance (optional)
 };
+// Waits for the stream by polling it: the host thread stays awake, so the
+// work it queues after a long kernel starts without a blocking wait's
+// wake-up delay.  Returns what the stream reports (hipSuccess when idle).
+hipError_t wait_stream(hipStream_t st);
+
 // exclusive prefix sum of n u32 in place; tmp holds scan_tmp_words(n) words;
 // `total` (may be null, may be pinned host memory) receives the sum
 size_t scan_tmp_words(size_t n);

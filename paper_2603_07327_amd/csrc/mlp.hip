@@ -670,7 +670,7 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
   (void)hipMemcpyAsync(&last[1], Q.pos + nq - 1, 4, hipMemcpyDeviceToHost, st);
   hipLaunchKernelGGL(k_emit_hits, dim3(cdiv(nq, 256)), dim3(256), 0, st, nq, Q.cls, Q.pos, Q.ev, Q.meta, Q.anchor, Q.e,
                      Q.time, d_scene, P, k0, k1, inst_rng, H);
-  if (hipStreamSynchronize(st) != hipSuccess) {
+  if (wait_stream(st) != hipSuccess) {
     err = "surrogate: kernel error";
     return GPET_ERR_HIP;
   }

@@ -271,6 +271,10 @@ def test_digitizer_rejects_events_outside_range(ctx, oracle_mod):
     h = _hitlist(ctx, [3, 500], [1, 2], np.array([511, 511], np.float32), [0, 10], first=0, n_events=100)
     with pytest.raises(GpetError):
         ctx.digitize(h, seed=1)
+    # a crystal id wider than the key's crystal field
+    h = _hitlist(ctx, [3, 5], [1, 1 << 20], np.array([511, 511], np.float32), [0, 10], first=0, n_events=100)
+    with pytest.raises(GpetError):
+        ctx.digitize(h, seed=1)
 
 
 @pytest.mark.parametrize("case", ["ring8", "C"])
