@@ -38,14 +38,18 @@ import gpet_inputs as G  # noqa: E402
 UNIT_COST = {"philox": 156, "step": 142, "kahn": 38, "rotation": 54, "slab": 88, "source": 18,
              "ring_test": 65, "ring_axial": 26, "ring_prune": 131}
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (no packed FP32)
-EVENT_BLOCKS = 3              # Philox blocks of the event stream per annihilation
+# Philox blocks of the event stream per annihilation: direction and time for
+# point and beam sources, plus the emission point for rod sources
+EVENT_BLOCKS = {"point": 2, "beam": 2, "rods": 3}
 TRANSPORT_SOURCES = ("paper_2603_07327_amd/csrc/transport.hip", "paper_2603_07327_amd/csrc/gpet_device.hpp")
 
 
-def algorithmic_work(stats: dict, ring: bool = True) -> float:
+def algorithmic_work(stats: dict, ring: bool = True, source: str = "point") -> float:
     """VALU lane-ops the method needs for a transport launch with these counts:
-    W = N_blocks c_philox + N_steps c_step + N_trials c_kahn + N_scatter c_rot
-        + W_search + N_events c_source, where for a ring of panels
+    W = (N_blocks + b_event N_events) c_philox + N_steps c_step + N_trials c_kahn
+        + N_scatter c_rot + W_search + N_events c_source, where N_blocks counts
+    the photon streams' blocks and b_event the event stream's blocks per
+    annihilation (EVENT_BLOCKS of the source kind), and for a ring of panels
     W_search = N_search c_axial + N_tests c_ring_test + N_pruned c_prune
     (N_tests: panel boxes tested, N_pruned: searches that first narrowed the
     candidates by azimuth) and otherwise N_tests c_slab."""
@@ -54,7 +58,7 @@ def algorithmic_work(stats: dict, ring: bool = True) -> float:
                     + stats["pruned_searches"] * UNIT_COST["ring_prune"])
     else:
         w_search = stats["panel_tests"] * UNIT_COST["slab"]
-    return ((stats["blocks"] + EVENT_BLOCKS * stats["events"]) * UNIT_COST["philox"]
+    return ((stats["blocks"] + EVENT_BLOCKS[source] * stats["events"]) * UNIT_COST["philox"]
             + stats["steps"] * UNIT_COST["step"] + stats["kahn_trials"] * UNIT_COST["kahn"]
             + stats["scatters"] * UNIT_COST["rotation"] + w_search + stats["events"] * UNIT_COST["source"])
 
@@ -398,7 +402,7 @@ def main():
                 raise RuntimeError("digitizer capacity too small")
             if record:
                 kernel_ms.append(c.timings()[0])
-                work.append(algorithmic_work(st, ring=True))
+                work.append(algorithmic_work(st, ring=True, source="point"))
                 stats_last = st
             out.append((d, hits.count, singles.count, nc))
         return out

@@ -396,14 +396,43 @@ __global__ void k_bucket_bounds(const unsigned long long *key, size_t n, BucketM
     for (uint32_t q = b + 1; q <= M.nb; ++q) start[q] = (uint32_t)n;
 }
 
-// items per instance (instance = key >> shift)
-__global__ void k_inst_count(const unsigned long long *key, size_t n, int shift, uint32_t n_inst, uint32_t *count) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t v = i < n ? (shift < 64 ? (uint32_t)(key[i] >> shift) : 0u) : 0u;
-  const bool valid = i < n && v < n_inst;
-  const uint64_t peers = equal_peers(v, valid);
-  if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[v], (uint32_t)__popcll(peers));
+// Items per instance: a block counts kInstItems items in an LDS histogram
+// (for up to kInstLds instances) and adds its nonzero bins to the global
+// counts; with more instances every item adds to the global count directly.
+constexpr int kInstLds = 4096;
+constexpr int kInstItems = 16;
+
+template <class Inst>
+__device__ __forceinline__ void inst_histogram(size_t n, uint32_t n_inst, uint32_t *count, Inst inst_of) {
+  __shared__ uint32_t h[kInstLds];
+  const bool lds = n_inst <= (uint32_t)kInstLds;
+  if (lds)
+    for (uint32_t b = threadIdx.x; b < n_inst; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * blockDim.x * kInstItems;
+  for (int r = 0; r < kInstItems; ++r) {
+    const size_t i = base + (size_t)r * blockDim.x + threadIdx.x;
+    if (i >= n) break;
+    const uint32_t v = inst_of(i);
+    if (v < n_inst) {
+      if (lds) atomicAdd(&h[v], 1u);
+      else atomicAdd(&count[v], 1u);
+    }
+  }
+  __syncthreads();
+  if (lds)
+    for (uint32_t b = threadIdx.x; b < n_inst; b += blockDim.x)
+      if (h[b]) atomicAdd(&count[b], h[b]);
 }
+
+// items per instance (instance = key >> shift)
+__global__ void __launch_bounds__(256) k_inst_count(const unsigned long long *key, size_t n, int shift,
+                                                    uint32_t n_inst, uint32_t *count) {
+  inst_histogram(n, n_inst, count,
+                 [&](size_t i) { return shift < 64 ? (uint32_t)(key[i] >> shift) : 0u; });
+}
+
+static inline unsigned inst_grid(size_t n) { return (unsigned)((n + 256 * kInstItems - 1) / (256 * kInstItems)); }
 
 __device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, unsigned long long kb, uint32_t vb) {
   return ka < kb || (ka == kb && va < vb);
@@ -910,13 +939,9 @@ __global__ void k_coinc_write(size_t n, const unsigned long long *t, const uint3
 }
 
 // coincidences per instance (instance of the first single)
-__global__ void k_coinc_inst(size_t n, const uint32_t *first, const uint32_t *s_inst, uint32_t n_inst,
-                             uint32_t *count) {
-  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t v = k < n ? s_inst[first[k]] : 0u;
-  const bool valid = k < n && v < n_inst;
-  const uint64_t peers = equal_peers(v, valid);
-  if (valid && (peers & __lanemask_lt()) == 0) atomicAdd(&count[v], (uint32_t)__popcll(peers));
+__global__ void __launch_bounds__(256) k_coinc_inst(size_t n, const uint32_t *first, const uint32_t *s_inst,
+                                                    uint32_t n_inst, uint32_t *count) {
+  inst_histogram(n, n_inst, count, [&](size_t k) { return s_inst[first[k]]; });
 }
 
 __global__ void k_hit_tallies(size_t n, const uint32_t *gid, const float *depth, uint32_t *hpc, uint32_t *doi,
@@ -1049,7 +1074,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   std::vector<uint64_t> items(ni, n);
   if (ni > 1) { // per-instance counts size the bucket map
     launch_fill_u32(d_icount, 0u, ni, st);
-    hipLaunchKernelGGL(k_inst_count, dim3(grid_for(n)), dim3(256), 0, st, sb.k0, n, inst_shift, (uint32_t)ni,
+    hipLaunchKernelGGL(k_inst_count, dim3(inst_grid(n)), dim3(256), 0, st, sb.k0, n, inst_shift, (uint32_t)ni,
                        d_icount);
     (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
     if (!sync("building hit keys")) return GPET_ERR_HIP;
@@ -1132,7 +1157,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   std::vector<uint64_t> witems(ni, nw);
   if (ni > 1) {
     launch_fill_u32(d_icount, 0u, ni, st);
-    hipLaunchKernelGGL(k_inst_count, dim3(grid_for(nw)), dim3(256), 0, st, sb.k0, nw, time_bits, (uint32_t)ni,
+    hipLaunchKernelGGL(k_inst_count, dim3(inst_grid(nw)), dim3(256), 0, st, sb.k0, nw, time_bits, (uint32_t)ni,
                        d_icount);
     (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
     if (!sync("counting windowed singles")) return GPET_ERR_HIP;
@@ -1189,7 +1214,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     } else {
       launch_fill_u32(d_icount, 0u, ni, st);
       if (C->count)
-        hipLaunchKernelGGL(k_coinc_inst, dim3(grid_for(C->count)), dim3(256), 0, st, (size_t)C->count, C->first,
+        hipLaunchKernelGGL(k_coinc_inst, dim3(inst_grid(C->count)), dim3(256), 0, st, (size_t)C->count, C->first,
                            s_inst, (uint32_t)ni, d_icount);
       (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
       if (!sync("counting coincidences per instance")) return GPET_ERR_HIP;

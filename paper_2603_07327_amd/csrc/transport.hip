@@ -63,8 +63,6 @@ __device__ __forceinline__ void vertex(const RunArgs &A, uint32_t ev, int ph, in
   }
 }
 
-__device__ __forceinline__ unsigned long long count(bool b) { return (unsigned long long)__popcll(__ballot(b)); }
-
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -191,8 +189,10 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   uint32_t inst = 0, inst_rng = A.inst_id[0];
   uint32_t cur_next = 0, cur_end = 0, pend_inst = 0, pend_next = 0, pend_end = 0, staged = 0;
   bool have_pend = false, exhausted = false;
-  unsigned long long c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0,
-                     c_blocks = 0, c_capped = 0, c_scatter = 0, c_trips = 0, c_tests = 0, c_pruned = 0;
+  // work counters: per-lane counts (summed over the wave at the end), trips per wave
+  uint32_t c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0, c_blocks = 0,
+           c_capped = 0, c_scatter = 0, c_tests = 0, c_pruned = 0;
+  unsigned long long c_trips = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
   auto start_photon = [&](CScene &S, int which) {
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       ++n;
     }
     const float4 r = to_unit4(w);
-    c_blocks += count(draw && sid != 0u);
+    c_blocks += (draw && sid != 0u) ? 1u : 0u;
 
     bool hit = false, ended = false, push = false;
     int n_tested = 0;
@@ -517,22 +517,16 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     }
 
     // ---- work counters (scalar)
-    c_events += count(emitted);
-    c_steps += count(stepped);
-    c_real += count(real);
-    c_search += count(searched);
-    if (__ballot(searched)) {
-      // panel tests summed over the wave (a lane's count, reduced by the wave)
-      int t = n_tested;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-      c_tests += (unsigned long long)t;
-      c_pruned += count(searched && S.ring_reg);
-    }
-    c_entries += count(entered);
-    c_trials += count(trial);
-    c_scatter += count(scattered);
-    c_capped += count(capped);
+    c_events += emitted ? 1u : 0u;
+    c_steps += stepped ? 1u : 0u;
+    c_real += real ? 1u : 0u;
+    c_search += searched ? 1u : 0u;
+    c_tests += (uint32_t)n_tested;
+    c_pruned += (searched && S.ring_reg) ? 1u : 0u;
+    c_entries += entered ? 1u : 0u;
+    c_trials += trial ? 1u : 0u;
+    c_scatter += scattered ? 1u : 0u;
+    c_capped += capped ? 1u : 0u;
 
     // ---- record / surrogate: one atomic per wave reserves the new entries
     if constexpr (REC || SUR) {
@@ -645,8 +639,17 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   }
   flush_stage(A, st, staged, lane, inst);
 
-  const unsigned long long cnt[kStatCount] = {c_events, c_entries, c_steps,   c_real,  c_trials, c_search,
-                                              c_blocks, c_capped,  c_scatter, c_trips, c_tests,  c_pruned};
+  uint32_t lc[kStatCount] = {c_events, c_entries, c_steps,   c_real, c_trials, c_search,
+                             c_blocks, c_capped,  c_scatter, 0u,     c_tests,  c_pruned};
+  unsigned long long cnt[kStatCount];
+#pragma unroll
+  for (int k = 0; k < kStatCount; ++k) {
+    unsigned long long t = lc[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    cnt[k] = t;
+  }
+  cnt[9] = c_trips;
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < kStatCount; ++k)
