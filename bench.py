@@ -63,6 +63,21 @@ def algorithmic_work(stats: dict, ring: bool = True, source: str = "point") -> f
             + stats["scatters"] * UNIT_COST["rotation"] + w_search + stats["events"] * UNIT_COST["source"])
 
 
+# Bytes each digitizer stage moves per item, as built: hit keys 24, hit sort
+# 60 (count, scatter, wave sort), run heads and their scan 24, adder 32 per
+# hit (key, index, segment, energy / depth / time) and 28 per single written;
+# blur 36, window scan 12, time keys 20 per single; time keys written 12, time
+# sort 96 (two radix passes, bucket starts, wave sort) and pairing 40 per
+# windowed single; 8 per coincidence written.
+DIGI_BYTES = {"hit": 24 + 60 + 24 + 32, "single": 28 + 36 + 12 + 20, "windowed": 12 + 96 + 40, "coinc": 8}
+HBM_PEAK = 8.0e12
+
+
+def digitizer_bytes(hits: int, singles: int, windowed: int, coinc: int) -> float:
+    return (hits * DIGI_BYTES["hit"] + singles * DIGI_BYTES["single"] + windowed * DIGI_BYTES["windowed"]
+            + coinc * DIGI_BYTES["coinc"])
+
+
 def transport_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -100,9 +115,20 @@ def cpu_baseline(target_s: float = 12.0):
     h, _ = s.transport(n, seed=1)
     s.digitize(h, seed=1)
     dt = time.perf_counter() - t0
+    # one host thread on a proportionally smaller sample (events are independent)
+    n1 = max(10_000, int(n * 0.3 / max(threads, 1)))
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        h, _ = s.transport(n1, seed=1)
+        s.digitize(h, seed=1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
     return {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"design C, source at the centre, events [0, {n}) seed 1, transport + digitizer, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "single_core": {"value": n1 / dt1, "events": n1, "seconds": dt1}}
 
 
 def batched_form(args):
@@ -387,6 +413,7 @@ def main():
         ctxs.append((d, c, hits, singles, coinc))
 
     kernel_ms, work, stats_last = [], [], None
+    digi_ms, digi_bytes = [], []
 
     def step(i, record):
         nonlocal stats_last
@@ -401,9 +428,13 @@ def main():
             if rc != 0:
                 raise RuntimeError("digitizer capacity too small")
             if record:
-                kernel_ms.append(c.timings()[0])
+                tm = c.timings()
+                kernel_ms.append(tm[0])
                 work.append(algorithmic_work(st, ring=True, source="point"))
                 stats_last = st
+                digi_ms.append(tm[1])
+                windowed = int(singles.in_window[: singles.count].sum().item())
+                digi_bytes.append(digitizer_bytes(hits.count, singles.count, windowed, nc))
             out.append((d, hits.count, singles.count, nc))
         return out
 
@@ -438,6 +469,11 @@ def main():
                      "traffic": measured_traffic(n), "kernel_ms": avg_ms,
                      "work_per_launch": float(np.mean(work)), "transport_source": transport_source_hash()},
         "last_step": res, "stats_last": stats_last,
+        "digitizer_roofline": {"bound": "hbm", "achieved": float(np.mean(digi_bytes)) / (float(np.mean(digi_ms)) * 1e-3)
+                               / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                               "frac": float(np.mean(digi_bytes)) / (float(np.mean(digi_ms)) * 1e-3) / HBM_PEAK,
+                               "bytes_per_design": float(np.mean(digi_bytes)), "ms_per_design": float(np.mean(digi_ms)),
+                               "bytes_per_item": DIGI_BYTES},
     }
     for _, c, *_ in ctxs:
         c.close()

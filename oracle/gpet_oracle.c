@@ -758,6 +758,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Host threads the next calls use (n >= 1); results do not depend on it. */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Transport events [first, first+n).  Writes at most cap hits in event order;
  * returns the number of hits produced (which may exceed cap). */
 int64_t or_transport(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed,
@@ -820,9 +829,13 @@ static int cmp_single_time(const void *a, const void *b) {
   return 0;
 }
 
-/* Digitizer at crystal readout level:
+/* Digitizer:
  *  adder   - hits of one event in one crystal sum into a single; its time is the
  *            earliest hit time, its depth the energy-weighted mean;
+ *  readout - at module (panel) level the crystal singles of one event in one
+ *            module (panel) merge into one single: energies summed, the
+ *            earliest time, the crystal and depth of the largest deposit (the
+ *            lower crystal id on a tie) -- the readout levels of Sec. 2.1;
  *  blur    - Gaussian with FWHM(E) = fwhm_511 * sqrt(511 E) (16 % at 511 keV,
  *            Sec. 2.3), normal deviate by Box-Muller from the digitizer stream;
  *  window  - e_lo <= E <= e_hi on the blurred energy;
@@ -835,7 +848,6 @@ static int cmp_single_time(const void *a, const void *b) {
 int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits, const or_digitizer *dg,
                     or_single *singles, int64_t cap_s, uint32_t *coinc, int64_t cap_c,
                     int64_t *n_coinc) {
-  (void)s;
   const or_hit **ord = (const or_hit **)malloc((size_t)(n_hits ? n_hits : 1) * sizeof(*ord));
   for (int64_t i = 0; i < n_hits; i++) ord[i] = &hits[i];
   qsort(ord, (size_t)n_hits, sizeof(*ord), cmp_hit);
@@ -860,6 +872,27 @@ int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits, const
     i = j;
   }
   free(ord);
+  if (dg->readout == 1 || dg->readout == 2) {
+    const uint32_t G = (uint32_t)(dg->readout == 1 ? s->crystals_per_module : s->crystals_per_panel);
+    int64_t m = 0;
+    for (int64_t i = 0; i < ns;) {
+      int64_t j = i, best = i;
+      double e = 0;
+      uint64_t tm = UINT64_MAX;
+      while (j < ns && sg[j].event == sg[i].event && sg[j].gid / G == sg[i].gid / G) {
+        e += sg[j].edep;
+        if (sg[j].time_ps < tm) tm = sg[j].time_ps;
+        if (sg[j].edep > sg[best].edep) best = j;
+        j++;
+      }
+      or_single q = sg[best]; /* best >= i >= m: read before the slot is reused */
+      q.edep = e;
+      q.time_ps = tm;
+      sg[m++] = q;
+      i = j;
+    }
+    ns = m;
+  }
   for (int64_t i = 0; i < ns; i++) {
     or_single *q = &sg[i];
     rng_t r;

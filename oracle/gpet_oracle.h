@@ -123,6 +123,7 @@ typedef struct {
   uint64_t seed;
   uint32_t instance;
   int32_t doi_bins;
+  int32_t readout;     /* single readout level: 0 crystal, 1 module, 2 panel */
 } or_digitizer;
 
 typedef struct {
@@ -150,4 +151,5 @@ int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits,
                     const or_digitizer *dg, or_single *singles, int64_t cap_s,
                     uint32_t *coinc, int64_t cap_c, int64_t *n_coinc);
 int or_num_threads(void);
+void or_set_threads(int n);
 #endif

@@ -94,7 +94,7 @@ class Vertex(C.Structure):
 class Digitizer(C.Structure):
     _fields_ = [("fwhm_511", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double),
                 ("window_ps", C.c_uint64), ("seed", C.c_uint64), ("instance", C.c_uint32),
-                ("doi_bins", C.c_int32)]
+                ("doi_bins", C.c_int32), ("readout", C.c_int32)]
 
 
 class Single(C.Structure):
@@ -137,6 +137,8 @@ def lib():
         L.or_digitize.argtypes = [P(Scene), P(Hit), C.c_int64, P(Digitizer), P(Single), C.c_int64,
                                   P(C.c_uint32), C.c_int64, P(C.c_int64)]
         L.or_num_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -310,9 +312,11 @@ class OracleScene:
         return np.frombuffer(buf, dtype=np.dtype(Vertex), count=n).copy()
 
     def digitize(self, hits, seed=0, fwhm_511=0.16, e_lo=350.0, e_hi=650.0, window_ps=3000,
-                 instance=0):
+                 instance=0, readout=0):
+        """Adder, readout (0 crystal, 1 module, 2 panel), blur, window and
+        coincidence sorter; returns (singles, coincidence index pairs)."""
         hits = np.ascontiguousarray(hits)
-        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, 200)
+        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, 200, readout)
         n = len(hits)
         sg = (Single * max(1, n))()
         cc = np.empty((max(1, n), 2), np.uint32)
@@ -326,3 +330,8 @@ class OracleScene:
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the following calls (results do not depend on it)."""
+    lib().or_set_threads(int(n))

@@ -125,3 +125,58 @@ def test_window_applies_before_sorting(oracle_mod):
     h["edep"] = [511.0, 100.0, 511.0]
     _, coinc = s.digitize(h, fwhm_511=0.0)
     assert len(coinc) == 1
+
+
+# ---------------------------------------------------------------------------
+# single readout levels (Sec. 2.1): crystal, module, panel
+# ---------------------------------------------------------------------------
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _golden_readout():
+    hits, want = [], {"module": [], "panel": []}
+    for line in open(f"{GOLDEN}/readout_example.txt"):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        row = (int(f[1]), int(f[2]), float(f[3]), float(f[4]), int(f[5]))
+        (hits if f[0] == "hit" else want[f[0]]).append(row)
+    return hits, want
+
+
+@pytest.mark.parametrize("level,code", [("module", 1), ("panel", 2)])
+def test_readout_worked_example(oracle_mod, level, code):
+    """Module and panel singles of a small hand-worked example: sums, earliest
+    times, the crystal and depth of the largest deposit, ties to the lower id."""
+    s = _scene(oracle_mod)
+    rows, want = _golden_readout()
+    h = _hits(oracle_mod, len(rows))
+    for k, (ev, gid, e, dep, t) in enumerate(rows):
+        h[k]["event"], h[k]["gid"], h[k]["edep"], h[k]["depth"], h[k]["time_ps"] = ev, gid, e, dep, t
+    singles, _ = s.digitize(h, fwhm_511=0.0, e_lo=-1e9, e_hi=1e9, readout=code)
+    got = [(int(q["event"]), int(q["gid"]), float(q["edep"]), float(q["depth"]), int(q["time_ps"]))
+           for q in singles]
+    assert len(got) == len(want[level])
+    for g, w in zip(got, want[level]):
+        assert g[:2] == w[:2] and g[4] == w[4], (g, w)
+        assert abs(g[2] - w[2]) < 1e-9 and abs(g[3] - w[3]) < 1e-9, (g, w)
+
+
+def test_readout_levels_conserve_energy_and_nest(oracle_mod):
+    """On transported hits: every level holds the same energy per event, the
+    module level has one single per (event, module) the crystal level touches
+    and the panel level one per (event, panel), and at the panel level no two
+    singles of an event share a panel."""
+    s = oracle_mod.OracleScene(G.small_animal_scene("C", n_events=30000))
+    hits, _ = s.transport(30000, seed=4)
+    levels = [s.digitize(hits, seed=4, fwhm_511=0.0, e_lo=-1e9, e_hi=1e9, readout=r)[0] for r in (0, 1, 2)]
+    cpm, cpp = s.s.crystals_per_module, s.s.crystals_per_panel
+    per_event = [np.bincount(q["event"], weights=q["edep"], minlength=30000) for q in levels]
+    np.testing.assert_allclose(per_event[1], per_event[0], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(per_event[2], per_event[0], rtol=1e-12, atol=1e-9)
+    c = levels[0]
+    assert len(levels[1]) == len({(int(e), int(g) // cpm) for e, g in zip(c["event"], c["gid"])})
+    assert len(levels[2]) == len({(int(e), int(g) // cpp) for e, g in zip(c["event"], c["gid"])})
+    assert len(levels[2]) < len(levels[1]) < len(c)
+    p = levels[2]
+    assert len({(int(e), int(g) // cpp) for e, g in zip(p["event"], p["gid"])}) == len(p)
