@@ -835,7 +835,8 @@ static int cmp_single_time(const void *a, const void *b) {
  *  readout - at module (panel) level the crystal singles of one event in one
  *            module (panel) merge into one single: energies summed, the
  *            earliest time, the crystal and depth of the largest deposit (the
- *            lower crystal id on a tie) -- the readout levels of Sec. 2.1;
+ *            lower crystal id on a tie, energies compared in single
+ *            precision) -- the readout levels of Sec. 2.1;
  *  blur    - Gaussian with FWHM(E) = fwhm_511 * sqrt(511 E) (16 % at 511 keV,
  *            Sec. 2.3), normal deviate by Box-Muller from the digitizer stream;
  *  window  - e_lo <= E <= e_hi on the blurred energy;
@@ -882,7 +883,9 @@ int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits, const
       while (j < ns && sg[j].event == sg[i].event && sg[j].gid / G == sg[i].gid / G) {
         e += sg[j].edep;
         if (sg[j].time_ps < tm) tm = sg[j].time_ps;
-        if (sg[j].edep > sg[best].edep) best = j;
+        /* the winner is an argmax decided in floating point: taken in single
+         * precision, the precision the crystal energies are kept in on the GPU */
+        if ((float)sg[j].edep > (float)sg[best].edep) best = j;
         j++;
       }
       or_single q = sg[best]; /* best >= i >= m: read before the slot is reused */
