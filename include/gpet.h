@@ -230,9 +230,13 @@ gpet_status gpet_transport(gpet_ctx *ctx, uint64_t first_event, uint64_t n_event
                            uint32_t instance, gpet_hits *hits, gpet_stats *stats);
 
 /* ---------------------------------------------------------------------- */
-/* Digitizer at crystal readout level                                       */
+/* Digitizer                                                                 */
 /*  adder:  hits of one event in one crystal form a single: energy = sum of  */
 /*          deposits, time = earliest hit time, depth = energy-weighted mean;*/
+/*  readout (Sec. 2.1 readout levels): at module (panel) level the crystal   */
+/*          singles of one event in one module (panel) merge into one single:*/
+/*          energies summed, earliest time, crystal id and depth of the      */
+/*          largest deposit (the lower id on a tie);                         */
 /*  blur:   E + N(0,1) * fwhm_511 * sqrt(511 E) / 2.3548 (16 % at 511 keV);   */
 /*  window: e_lo <= blurred E <= e_hi;                                       */
 /*  sorter: windowed singles in (time, event, gid) order; a window of        */
@@ -247,9 +251,22 @@ typedef struct {
   uint64_t seed;      /* key of the blur stream */
   uint32_t instance;
   uint64_t first_event, n_events; /* event range the hits came from */
+  uint32_t readout;   /* GPET_READOUT_CRYSTAL, _MODULE or _PANEL */
+  /* Energy-window sweep (Sec. 2.3 evaluates 150/250/350/450-700 keV): for
+   * each of n_sweep extra windows [sweep_lo_kev[w], sweep_hi_kev[w]] the
+   * coincidences of the same blurred singles are counted (not listed) into
+   * sweep_coincidences[w * n_instances + i] (host memory; n_instances is 1
+   * for gpet_digitize).  The arrays are read and written during the call and
+   * may be NULL when n_sweep is 0.  The listed outputs keep the main window. */
+  uint32_t n_sweep;
+  const double *sweep_lo_kev, *sweep_hi_kev;
+  uint64_t *sweep_coincidences;
 } gpet_digitizer;
 
-/* Singles in (instance, event, gid) order. */
+enum { GPET_READOUT_CRYSTAL = 0, GPET_READOUT_MODULE = 1, GPET_READOUT_PANEL = 2 };
+
+/* Singles in (instance, event, gid) order; at module or panel readout gid is
+ * the crystal of the largest deposit and edep the readout unit's sum. */
 typedef struct {
   uint32_t *event, *gid;
   float *edep_kev;    /* summed deposit */
@@ -260,6 +277,7 @@ typedef struct {
   uint32_t *instance; /* optional (may be NULL): instance index of the single */
   uint64_t capacity;
   uint64_t count;     /* out */
+  uint64_t windowed;  /* out: singles inside the (main) energy window */
 } gpet_singles;
 
 /* Coincidences as index pairs into the singles arrays, earlier single first,

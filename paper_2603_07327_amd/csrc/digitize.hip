@@ -402,8 +402,9 @@ __global__ void k_bucket_bounds(const unsigned long long *key, size_t n, BucketM
 constexpr int kInstLds = 4096;
 constexpr int kInstItems = 16;
 
-template <class Inst>
-__device__ __forceinline__ void inst_histogram(size_t n, uint32_t n_inst, uint32_t *count, Inst inst_of) {
+template <class Inst, class Weight>
+__device__ __forceinline__ void inst_histogram(size_t n, uint32_t n_inst, uint32_t *count, Inst inst_of,
+                                               Weight weight_of) {
   __shared__ uint32_t h[kInstLds];
   const bool lds = n_inst <= (uint32_t)kInstLds;
   if (lds)
@@ -413,10 +414,12 @@ __device__ __forceinline__ void inst_histogram(size_t n, uint32_t n_inst, uint32
   for (int r = 0; r < kInstItems; ++r) {
     const size_t i = base + (size_t)r * blockDim.x + threadIdx.x;
     if (i >= n) break;
+    const uint32_t wgt = weight_of(i);
+    if (wgt == 0u) continue;
     const uint32_t v = inst_of(i);
     if (v < n_inst) {
-      if (lds) atomicAdd(&h[v], 1u);
-      else atomicAdd(&count[v], 1u);
+      if (lds) atomicAdd(&h[v], wgt);
+      else atomicAdd(&count[v], wgt);
     }
   }
   __syncthreads();
@@ -428,8 +431,9 @@ __device__ __forceinline__ void inst_histogram(size_t n, uint32_t n_inst, uint32
 // items per instance (instance = key >> shift)
 __global__ void __launch_bounds__(256) k_inst_count(const unsigned long long *key, size_t n, int shift,
                                                     uint32_t n_inst, uint32_t *count) {
-  inst_histogram(n, n_inst, count,
-                 [&](size_t i) { return shift < 64 ? (uint32_t)(key[i] >> shift) : 0u; });
+  inst_histogram(
+      n, n_inst, count, [&](size_t i) { return shift < 64 ? (uint32_t)(key[i] >> shift) : 0u; },
+      [](size_t) { return 1u; });
 }
 
 static inline unsigned inst_grid(size_t n) { return (unsigned)((n + 256 * kInstItems - 1) / (256 * kInstItems)); }
@@ -838,7 +842,7 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, co
                                               unsigned long long *block_max) {
   __shared__ unsigned long long s_max[4];
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long tm = 0; // largest time stamp among windowed singles
+  unsigned long long tm = 0; // largest time stamp of all singles (every window's keys fit its width)
   if (i < n) {
     // normal deviate by Box-Muller from the digitizer stream of (gid, event, instance)
     const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], T.rng[s_inst[i]], 3u));
@@ -853,7 +857,7 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, co
     wflag[i] = in;
     if (spp && in) atomicAdd(&spp[s_gid[i]], 1u);
     if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
-    if (in) tm = s_time[i];
+    tm = s_time[i];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -883,6 +887,75 @@ __global__ void __launch_bounds__(1024) k_max_u64(const unsigned long long *v, s
 }
 
 // windowed singles: key = instance | time, value = single index
+// ---------------------------------------------------------------------------
+// readout levels: crystal singles (in instance, event, gid order) of one
+// event in one readout unit (gid / unit[instance] crystals) form a run
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool same_unit(size_t i, size_t j, const uint32_t *ev, const uint32_t *gid,
+                                          const uint32_t *inst, const uint32_t *unit) {
+  const uint32_t a = inst[i];
+  return a == inst[j] && ev[i] == ev[j] && gid[i] / unit[a] == gid[j] / unit[a];
+}
+
+__global__ void k_readout_heads(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *inst,
+                                const uint32_t *unit, uint32_t *flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (i == 0 || !same_unit(i, i - 1, ev, gid, inst, unit)) ? 1u : 0u;
+}
+
+// one readout single per run: energies summed, earliest time, crystal and depth
+// of the largest deposit (the first, i.e. lowest gid, on a tie); written at
+// the run's scanned index into the o_* arrays
+__global__ void k_readout_merge(size_t n, const uint32_t *seg, const uint32_t *ev, const uint32_t *gid,
+                                const uint32_t *inst, const uint32_t *unit, const float *edep, const float *depth,
+                                const unsigned long long *time, uint32_t *o_ev, uint32_t *o_gid, float *o_edep,
+                                float *o_depth, unsigned long long *o_time, uint32_t *o_inst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (i > 0 && same_unit(i, i - 1, ev, gid, inst, unit))) return;
+  double e = 0.0;
+  unsigned long long tm = ~0ull;
+  size_t best = i, j = i;
+  do {
+    e += (double)edep[j];
+    tm = time[j] < tm ? time[j] : tm;
+    if (edep[j] > edep[best]) best = j;
+    ++j;
+  } while (j < n && same_unit(j, i, ev, gid, inst, unit));
+  const uint32_t g = seg[i];
+  o_ev[g] = ev[best];
+  o_gid[g] = gid[best];
+  o_edep[g] = (float)e;
+  o_depth[g] = depth[best];
+  o_time[g] = tm;
+  o_inst[g] = inst[best];
+}
+
+__global__ void k_readout_copy(size_t n, const uint32_t *a_ev, const uint32_t *a_gid, const float *a_edep,
+                               const float *a_depth, const unsigned long long *a_time, const uint32_t *a_inst,
+                               uint32_t *ev, uint32_t *gid, float *edep, float *depth, unsigned long long *time,
+                               uint32_t *inst, uint32_t *inst_out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ev[i] = a_ev[i];
+  gid[i] = a_gid[i];
+  edep[i] = a_edep[i];
+  depth[i] = a_depth[i];
+  time[i] = a_time[i];
+  inst[i] = a_inst[i];
+  if (inst_out) inst_out[i] = a_inst[i];
+}
+
+// energy window of a sweep on the blurred energies: flag and a copy to scan
+__global__ void k_window_flags(size_t n, const float *energy, float e_lo, float e_hi, uint32_t *flag,
+                               uint32_t *pos) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t in = (energy[i] >= e_lo && energy[i] <= e_hi) ? 1u : 0u;
+  flag[i] = in;
+  pos[i] = in;
+}
+
 __global__ void k_time_keys(size_t n, const uint32_t *win, const uint32_t *pos, const unsigned long long *s_time,
                             const uint32_t *s_inst, int time_bits, unsigned long long *key, uint32_t *val) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -941,7 +1014,17 @@ __global__ void k_coinc_write(size_t n, const unsigned long long *t, const uint3
 // coincidences per instance (instance of the first single)
 __global__ void __launch_bounds__(256) k_coinc_inst(size_t n, const uint32_t *first, const uint32_t *s_inst,
                                                     uint32_t n_inst, uint32_t *count) {
-  inst_histogram(n, n_inst, count, [&](size_t k) { return s_inst[first[k]]; });
+  inst_histogram(n, n_inst, count, [&](size_t k) { return s_inst[first[k]]; }, [](size_t) { return 1u; });
+}
+
+// coincidences per instance from the per-cluster counts of time-sorted keys
+// (instance = key >> shift)
+__global__ void __launch_bounds__(256) k_coinc_inst_counts(size_t n, const uint32_t *cnt,
+                                                           const unsigned long long *key, int shift,
+                                                           uint32_t n_inst, uint32_t *count) {
+  inst_histogram(
+      n, n_inst, count, [&](size_t k) { return shift < 64 ? (uint32_t)(key[k] >> shift) : 0u; },
+      [&](size_t k) { return cnt[k]; });
 }
 
 __global__ void k_hit_tallies(size_t n, const uint32_t *gid, const float *depth, uint32_t *hpc, uint32_t *doi,
@@ -967,7 +1050,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   gpet_coincidences *C = D.coinc;
   const gpet_tallies *T = D.tallies;
   S->count = 0;
+  S->windowed = 0;
   C->count = 0;
+  if (D.sweep_out) std::fill(D.sweep_out, D.sweep_out + D.sweep_lo.size() * ni, (uint64_t)0);
   if (T && (T->hits_per_crystal || T->doi) && n)
     hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
                        T->hits_per_crystal, T->doi, T->doi_bins, D.panel_depth);
@@ -980,7 +1065,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const size_t max_buckets = n / kBucketMean + 1024 + 2 * ni;
   const size_t scan_words = scan_scratch_words(std::max<size_t>(std::max<size_t>(256 * tiles, n), max_buckets));
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
-                      align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) * 2 + align_up(ni * 4) * 8 + 1024;
+                      align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) * 2 + align_up(ni * 4) * 10 + 1024;
   if (scr.bytes < need) {
     // a quarter of headroom: hit counts drift from call to call, and a
     // free + allocate pair costs about as much as the whole digitizer
@@ -994,7 +1079,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
     scr.bytes = grow;
   }
-  const size_t pinned_bytes = 64 + 32 * ni;
+  const size_t pinned_bytes = 64 + 36 * ni;
   if (scr.pinned_bytes < pinned_bytes) {
     if (scr.pinned) (void)hipHostFree(scr.pinned);
     scr.pinned = nullptr;
@@ -1027,11 +1112,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   bb.big = (uint32_t *)take(max_buckets * 4);
   bb.n_big = (uint32_t *)take(8);
   bb.map = (uint32_t *)take(ni * 4 * 3);
-  uint32_t *d_tab = (uint32_t *)take(ni * 4 * 4); // first, n_events, cpp, rng
+  uint32_t *d_tab = (uint32_t *)take(ni * 4 * 5); // first, n_events, cpp, rng, readout unit
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
   // pinned host words: [0, 16) scalars that kernels write directly (scan
   // totals, maximum time, failure flags), [16, 16 + ni) per-instance counts,
-  // 3 ni words of bucket-map uploads, 4 ni words of instance table
+  // 3 ni words of bucket-map uploads, 5 ni words of instance table
   uint32_t *rb = (uint32_t *)scr.pinned;
   uint32_t *rb_count = rb + 16;
   bb.pinned_flag = rb + 12;
@@ -1051,8 +1136,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     tab[ni + i] = D.n_events[i];
     tab[2 * ni + i] = D.cpp[i];
     tab[3 * ni + i] = D.rng[i];
+    // crystals per readout unit (a crystal is its own unit at crystal level)
+    tab[4 * ni + i] = D.readout == GPET_READOUT_MODULE ? std::max(1u, D.cpm[i])
+                      : D.readout == GPET_READOUT_PANEL ? std::max(1u, D.cpp[i])
+                                                        : 1u;
   }
-  (void)hipMemcpyAsync(d_tab, tab, ni * 16, hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(d_tab, tab, ni * 20, hipMemcpyHostToDevice, st);
   const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, (uint32_t)ni};
   uint32_t max_events = 1;
   for (size_t i = 0; i < ni; ++i) max_events = std::max(max_events, D.n_events[i]);
@@ -1119,17 +1208,38 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     run_heads();
     if (!sync("after the hit sort")) return GPET_ERR_HIP;
   }
-  const uint64_t ns = rb[1];
+  uint64_t ns = rb[1];
   S->count = ns;
-  if (ns > S->capacity) {
-    err = "digitize: singles capacity too small";
+  S->windowed = 0;
+  if (ns > S->capacity) { // the crystal singles pass through the output arrays
+    err = "digitize: singles capacity too small (it must hold the crystal-level singles)";
     return GPET_ERR_CAPACITY;
   }
   hipLaunchKernelGGL(k_adder, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth, D.h_time, IT,
                      D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
                      (unsigned long long *)S->time_ps, s_inst, S->instance, S->capacity);
-  // 3. blur + window; per-block maxima of the windowed time stamps go to the
-  //    (now free) second key array, then one block reduces them
+  // 2b. module / panel readout: runs of (instance, event, unit) merge into the
+  //     free sort buffers, then back into the output arrays
+  if (D.readout != GPET_READOUT_CRYSTAL) {
+    const uint32_t *unit = d_tab + 4 * ni;
+    uint32_t *o_ev = sb.v0, *o_gid = sb.v1, *o_inst = wpos;
+    float *o_edep = (float *)sb.k1, *o_depth = (float *)sb.k1 + n;
+    unsigned long long *o_time = sb.k0;
+    hipLaunchKernelGGL(k_readout_heads, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst,
+                       unit, flag);
+    exclusive_scan(flag, ns, sb.scan_tmp, st, rb + 1);
+    hipLaunchKernelGGL(k_readout_merge, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, flag, S->event, S->gid,
+                       s_inst, unit, S->edep_kev, S->depth_mm, (const unsigned long long *)S->time_ps, o_ev, o_gid,
+                       o_edep, o_depth, o_time, o_inst);
+    if (!sync("in the readout")) return GPET_ERR_HIP;
+    ns = rb[1];
+    S->count = ns;
+    hipLaunchKernelGGL(k_readout_copy, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, o_ev, o_gid, o_edep,
+                       o_depth, o_time, o_inst, S->event, S->gid, S->edep_kev, S->depth_mm,
+                       (unsigned long long *)S->time_ps, s_inst, S->instance);
+  }
+  // 3. blur + window; per-block maxima of the time stamps go to the (now
+  //    free) second key array, then one block reduces them
   hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
                      S->edep_kev, S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
                      T ? T->singles_per_crystal : nullptr, T ? T->energy_spectrum : nullptr,
@@ -1139,87 +1249,124 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
   if (!sync("after the energy window")) return GPET_ERR_HIP;
   const size_t nw = rb[3];
+  S->windowed = nw;
   const unsigned long long tmax = (unsigned long long)rb[4] | ((unsigned long long)rb[5] << 32);
   // time bits leave room for the window, so keys of two instances differ by more than it
   int time_bits = 0;
   while (time_bits < 63 && ((tmax + D.window_ps + 1) >> time_bits) != 0) ++time_bits;
-  if (nw == 0) {
-    if (D.coinc_per_inst) std::fill(D.coinc_per_inst, D.coinc_per_inst + ni, 0ull);
-    return GPET_OK;
-  }
+  const size_t n_sweep = D.sweep_lo.size();
+  if (D.coinc_per_inst) std::fill(D.coinc_per_inst, D.coinc_per_inst + ni, 0ull);
+  if (D.sweep_out) std::fill(D.sweep_out, D.sweep_out + n_sweep * ni, (uint64_t)0);
+  if (nw == 0 && n_sweep == 0) return GPET_OK;
   if (time_bits + inst_bits > 64) {
     err = "digitize: instance and time stamp do not fit a 64-bit sort key";
     return GPET_ERR_ARG;
   }
-  // 4. windowed singles in (instance, time) order (ties keep (event, gid) order)
-  hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->in_window, wpos,
-                     (const unsigned long long *)S->time_ps, s_inst, ni > 1 ? time_bits : 64, sb.k0, sb.v0);
-  std::vector<uint64_t> witems(ni, nw);
-  if (ni > 1) {
-    launch_fill_u32(d_icount, 0u, ni, st);
-    hipLaunchKernelGGL(k_inst_count, dim3(inst_grid(nw)), dim3(256), 0, st, sb.k0, nw, time_bits, (uint32_t)ni,
-                       d_icount);
-    (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
-    if (!sync("counting windowed singles")) return GPET_ERR_HIP;
-    for (size_t i = 0; i < ni; ++i) witems[i] = rb_count[i];
-  }
   std::vector<double> trange(ni, (double)tmax + 1.0);
   for (size_t i = 0; i < ni; ++i)
     if (D.duration.size() == ni && D.duration[i]) trange[i] = (double)D.duration[i] + 1048576.0;
-  const unsigned long long *tk = sb.k1;
-  const uint32_t *ti = sb.v1;
+  const int tb = ni > 1 ? time_bits : 64;
   const unsigned long long t_mask = time_bits < 64 ? (1ull << time_bits) - 1 : ~0ull;
-  // 5. coincidences: count per cluster, scan, write
-  auto run_coinc = [&]() {
-    hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
-                       D.window_ps, flag);
-    exclusive_scan(flag, nw, sb.scan_tmp, st, rb + 7);
-    hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nw)), dim3(256), 0, st, nw, tk, ti, S->gid, s_inst, IT.cpp,
-                       D.window_ps, flag, C->first, C->second, C->capacity);
-  };
-  bool tmapped = false;
-  rb[12] = 0u;
-  if (nw == 1) {
-    tk = sb.k0;
-    ti = sb.v0;
-  } else if (bucket_sort<false>(sb, bb, nw, ns, ni > 1 ? time_bits : 64, 0, t_mask, witems, trange, st,
-                                sb.scan_tmp, bk, bv) == 0) {
-    tmapped = true;
-    tk = bk;
-    ti = bv;
-  } else {
-    const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
-    tk = f2 ? sb.k1 : sb.k0;
-    ti = f2 ? sb.v1 : sb.v0;
-  }
-  run_coinc();
-  if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
-  if (tmapped && rb[12]) { // a bucket overflowed LDS: rebuild the keys, sort every bit, redo the pairing
-    hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->in_window, wpos,
-                       (const unsigned long long *)S->time_ps, s_inst, ni > 1 ? time_bits : 64, sb.k0, sb.v0);
-    const bool f2 = radix_sort(sb, nw, time_bits + inst_bits, st);
-    tk = f2 ? sb.k1 : sb.k0;
-    ti = f2 ? sb.v1 : sb.v0;
-    run_coinc();
-    if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
-  }
-  C->count = rb[7];
-  if (C->count > C->capacity) {
-    err = "digitize: coincidence capacity too small";
-    return GPET_ERR_CAPACITY;
-  }
-  if (D.coinc_per_inst) {
-    if (ni == 1) {
-      D.coinc_per_inst[0] = C->count;
-    } else {
+
+  // 4-5. The singles flagged in `win` (exclusive scan of the flags in wpos,
+  // nwin of them) in (instance, time, index) order, split into clusters and
+  // paired.  list: write the coincidence list (count in rb[7]); otherwise
+  // count the coincidences per instance into rb_count.  make_flags() rebuilds
+  // win and wpos if the pairing overwrote them (flag doubles as both).
+  auto pair_window = [&](const uint32_t *win, size_t nwin, bool list, auto &&make_flags) -> int {
+    hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, win, wpos,
+                       (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
+    std::vector<uint64_t> witems(ni, nwin);
+    if (ni > 1) {
       launch_fill_u32(d_icount, 0u, ni, st);
-      if (C->count)
-        hipLaunchKernelGGL(k_coinc_inst, dim3(inst_grid(C->count)), dim3(256), 0, st, (size_t)C->count, C->first,
-                           s_inst, (uint32_t)ni, d_icount);
+      hipLaunchKernelGGL(k_inst_count, dim3(inst_grid(nwin)), dim3(256), 0, st, sb.k0, nwin, time_bits,
+                         (uint32_t)ni, d_icount);
       (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
-      if (!sync("counting coincidences per instance")) return GPET_ERR_HIP;
-      for (size_t i = 0; i < ni; ++i) D.coinc_per_inst[i] = rb_count[i];
+      if (!sync("counting windowed singles")) return GPET_ERR_HIP;
+      for (size_t i = 0; i < ni; ++i) witems[i] = rb_count[i];
     }
+    const unsigned long long *tk = sb.k1;
+    const uint32_t *ti = sb.v1;
+    auto count_pairs = [&]() {
+      hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nwin)), dim3(256), 0, st, nwin, tk, ti, S->gid, s_inst, IT.cpp,
+                         D.window_ps, flag);
+      if (list) {
+        exclusive_scan(flag, nwin, sb.scan_tmp, st, rb + 7);
+        hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nwin)), dim3(256), 0, st, nwin, tk, ti, S->gid, s_inst,
+                           IT.cpp, D.window_ps, flag, C->first, C->second, C->capacity);
+      } else {
+        launch_fill_u32(d_icount, 0u, ni, st);
+        hipLaunchKernelGGL(k_coinc_inst_counts, dim3(inst_grid(nwin)), dim3(256), 0, st, nwin, flag, tk, tb,
+                           (uint32_t)ni, d_icount);
+        (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+      }
+    };
+    bool mapped_t = false;
+    rb[12] = 0u;
+    if (nwin == 1) {
+      tk = sb.k0;
+      ti = sb.v0;
+    } else if (bucket_sort<false>(sb, bb, nwin, ns, tb, 0, t_mask, witems, trange, st, sb.scan_tmp, bk, bv) == 0) {
+      mapped_t = true;
+      tk = bk;
+      ti = bv;
+    } else {
+      const bool f2 = radix_sort(sb, nwin, time_bits + inst_bits, st);
+      tk = f2 ? sb.k1 : sb.k0;
+      ti = f2 ? sb.v1 : sb.v0;
+    }
+    count_pairs();
+    if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
+    if (mapped_t && rb[12]) { // a bucket overflowed LDS: rebuild the keys, sort every bit, redo the pairing
+      make_flags();
+      hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, win, wpos,
+                         (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
+      const bool f2 = radix_sort(sb, nwin, time_bits + inst_bits, st);
+      tk = f2 ? sb.k1 : sb.k0;
+      ti = f2 ? sb.v1 : sb.v0;
+      count_pairs();
+      if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
+    }
+    return GPET_OK;
+  };
+
+  // the main window: the coincidence list
+  if (nw > 0) {
+    const int r = pair_window(S->in_window, nw, true, [] {});
+    if (r != GPET_OK) return r;
+    C->count = rb[7];
+    if (C->count > C->capacity) {
+      err = "digitize: coincidence capacity too small";
+      return GPET_ERR_CAPACITY;
+    }
+    if (D.coinc_per_inst) {
+      if (ni == 1) {
+        D.coinc_per_inst[0] = C->count;
+      } else {
+        launch_fill_u32(d_icount, 0u, ni, st);
+        if (C->count)
+          hipLaunchKernelGGL(k_coinc_inst, dim3(inst_grid(C->count)), dim3(256), 0, st, (size_t)C->count,
+                             C->first, s_inst, (uint32_t)ni, d_icount);
+        (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+        if (!sync("counting coincidences per instance")) return GPET_ERR_HIP;
+        for (size_t i = 0; i < ni; ++i) D.coinc_per_inst[i] = rb_count[i];
+      }
+    }
+  }
+  // the sweep windows on the same blurred energies: counts only
+  for (size_t w = 0; w < n_sweep; ++w) {
+    auto make_flags = [&]() {
+      hipLaunchKernelGGL(k_window_flags, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->energy_kev,
+                         D.sweep_lo[w], D.sweep_hi[w], flag, wpos);
+      exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
+    };
+    make_flags();
+    if (!sync("in the window sweep")) return GPET_ERR_HIP;
+    const size_t nsw = rb[3];
+    if (nsw == 0) continue;
+    const int r = pair_window(flag, nsw, false, make_flags);
+    if (r != GPET_OK) return r;
+    for (size_t i = 0; i < ni; ++i) D.sweep_out[w * ni + i] = rb_count[i];
   }
   return GPET_OK;
 }

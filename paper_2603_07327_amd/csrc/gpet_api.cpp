@@ -701,6 +701,18 @@ static gpet_status digitizer_params(gpet_ctx *c, const gpet_hits *h, const gpet_
   D.window_ps = p->window_ps;
   D.k0 = (uint32_t)p->seed;
   D.k1 = (uint32_t)(p->seed >> 32);
+  if (p->readout > GPET_READOUT_PANEL) return fail(c, GPET_ERR_ARG, "digitize: unknown readout level");
+  D.readout = p->readout;
+  if (p->n_sweep) {
+    if (!p->sweep_lo_kev || !p->sweep_hi_kev || !p->sweep_coincidences)
+      return fail(c, GPET_ERR_ARG, "digitize: null sweep array");
+    for (uint32_t w = 0; w < p->n_sweep; ++w) {
+      if (!(p->sweep_lo_kev[w] <= p->sweep_hi_kev[w])) return fail(c, GPET_ERR_ARG, "digitize: sweep window");
+      D.sweep_lo.push_back((float)p->sweep_lo_kev[w]);
+      D.sweep_hi.push_back((float)p->sweep_hi_kev[w]);
+    }
+    D.sweep_out = p->sweep_coincidences;
+  }
   D.singles = sg;
   D.coinc = cc;
   return GPET_OK;
@@ -732,6 +744,7 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
   D.first = {(uint32_t)p->first_event};
   D.n_events = {(uint32_t)p->n_events};
   D.cpp = {(uint32_t)c->info.crystals_per_panel};
+  D.cpm = {(uint32_t)c->info.crystals_per_module};
   D.rng = {p->instance};
   D.duration = {c->have_source ? (unsigned long long)c->scene.duration_ps : 0ull};
   D.gid_bits = bits_for((uint64_t)c->info.n_crystals - 1);
@@ -1091,6 +1104,7 @@ gpet_status gpet_batch_create(gpet_ctx *c, int32_t n, const gpet_instance *inst,
     b->count.push_back((uint32_t)inst[i].n_events);
     b->id.push_back(inst[i].instance);
     b->cpp.push_back((uint32_t)G[i].info.crystals_per_panel);
+    b->cpm.push_back((uint32_t)G[i].info.crystals_per_module);
     b->duration.push_back(inst[i].source->duration_ps);
     b->gid_bits = std::max(b->gid_bits, bits_for((uint64_t)G[i].info.n_crystals - 1));
     b->total_events += inst[i].n_events;
@@ -1308,6 +1322,7 @@ gpet_status gpet_batch_digitize(gpet_batch *b, const gpet_hits *h, const gpet_di
   for (uint32_t i = 0; i < b->n; ++i)
     if (D.n_events[i] == 0) D.n_events[i] = 1; // empty instance: no hit can name it
   D.cpp = b->cpp;
+  D.cpm = b->cpm;
   D.rng = b->id;
   D.duration = b->duration;
   D.gid_bits = b->gid_bits;

@@ -108,6 +108,11 @@ struct DigitizeArgs {
   const float *h_edep = nullptr, *h_depth = nullptr;
   const unsigned long long *h_time = nullptr;
   std::vector<uint32_t> first, n_events, cpp, rng; // per instance: range, crystals per panel, RNG id
+  std::vector<uint32_t> cpm;                        // per instance: crystals per module
+  uint32_t readout = 0;                             // GPET_READOUT_*
+  // energy-window sweep: windows and host counts (window-major, one per instance)
+  std::vector<float> sweep_lo, sweep_hi;
+  uint64_t *sweep_out = nullptr;
   std::vector<unsigned long long> duration;        // per instance acquisition length in ps (0: unknown)
   int gid_bits = 1;
   float fwhm_511 = 0.f, e_lo = 0.f, e_hi = 0.f;
@@ -197,7 +202,7 @@ struct gpet_batch {
   int device = 0;
   uint32_t n = 0;
   std::vector<gpet_geometry_info> info;
-  std::vector<uint32_t> first, count, id, cpp;
+  std::vector<uint32_t> first, count, id, cpp, cpm;
   std::vector<unsigned long long> duration;
   uint64_t mat_gen = 0, phantom_gen = 0;
   int det_slots = 0;

@@ -90,13 +90,38 @@ class Stats(C.Structure):
 class Digitizer(C.Structure):
     _fields_ = [("fwhm_511", C.c_double), ("e_lo_kev", C.c_double), ("e_hi_kev", C.c_double),
                 ("window_ps", C.c_uint64), ("seed", C.c_uint64), ("instance", C.c_uint32),
-                ("first_event", C.c_uint64), ("n_events", C.c_uint64)]
+                ("first_event", C.c_uint64), ("n_events", C.c_uint64), ("readout", C.c_uint32),
+                ("n_sweep", C.c_uint32), ("sweep_lo_kev", C.c_void_p), ("sweep_hi_kev", C.c_void_p),
+                ("sweep_coincidences", C.c_void_p)]
+
+
+READOUT = {"crystal": 0, "module": 1, "panel": 2}
+
+
+def _readout_code(readout) -> int:
+    return READOUT[readout] if isinstance(readout, str) else int(readout)
+
+
+def _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events, readout, sweep):
+    """The parameter struct plus the host arrays its sweep pointers refer to
+    (kept alive by the caller for the duration of the call)."""
+    dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events, _readout_code(readout))
+    keep = None
+    if sweep:
+        lo = np.ascontiguousarray([w[0] for w in sweep], np.float64)
+        hi = np.ascontiguousarray([w[1] for w in sweep], np.float64)
+        keep = (lo, hi)
+        dg.n_sweep = len(sweep)
+        dg.sweep_lo_kev = lo.ctypes.data
+        dg.sweep_hi_kev = hi.ctypes.data
+    return dg, keep
 
 
 class Singles(C.Structure):
     _fields_ = [("event", C.c_void_p), ("gid", C.c_void_p), ("edep_kev", C.c_void_p), ("energy_kev", C.c_void_p),
                 ("depth_mm", C.c_void_p), ("time_ps", C.c_void_p), ("in_window", C.c_void_p),
-                ("instance", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_uint64)]
+                ("instance", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_uint64),
+                ("windowed", C.c_uint64)]
 
 
 class Coincidences(C.Structure):
@@ -255,6 +280,7 @@ class SingleList:
     in_window: "torch.Tensor"
     count: int
     instance: "torch.Tensor | None" = None
+    windowed: int = 0  # singles inside the main energy window
 
     def numpy(self):
         n = self.count
@@ -457,9 +483,16 @@ class Context:
                           self._empty(capacity, t.int32) if instance else None)
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
-                      e_hi=650.0, window_ps=3000, instance=0, tallies=None):
+                      e_hi=650.0, window_ps=3000, instance=0, tallies=None, readout="crystal", sweep=None):
+        """Digitize into preallocated outputs; returns (status, coincidences) or,
+        with sweep = [(e_lo, e_hi), ...], (status, coincidences, counts of the
+        sweep windows).  readout: "crystal", "module" or "panel"."""
         h = hits.struct()
-        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, hits.first_event, max(1, hits.n_events))
+        dg, keep = _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, hits.first_event,
+                              max(1, hits.n_events), readout, sweep)
+        counts = np.zeros(len(sweep) if sweep else 0, np.uint64)
+        if sweep:
+            dg.sweep_coincidences = counts.ctypes.data
         s = singles.struct()
         cc = Coincidences(coinc[0].data_ptr(), coinc[1].data_ptr(), coinc[0].numel(), 0)
         tl = None
@@ -469,9 +502,13 @@ class Context:
                          int(tallies["doi"].numel()) if tallies.get("doi") is not None else 0)
         rc = self.L.gpet_digitize(self.h, C.byref(h), C.byref(dg), C.byref(s), C.byref(cc),
                                   C.byref(tl) if tl is not None else None)
+        del keep
         singles.count = int(s.count)
+        singles.windowed = int(s.windowed)
         if rc not in (OK, ERR_CAPACITY):
             self._check(rc)
+        if sweep is not None:
+            return rc, int(cc.count), counts.astype(np.int64)
         return rc, int(cc.count)
 
     def alloc_tallies(self, doi_bins=200):
@@ -482,12 +519,16 @@ class Context:
                 "doi": z(doi_bins)}
 
     def digitize(self, hits: HitList, seed=0, tallies=None, **kw):
+        """(singles, (first, second)) and, with sweep=..., the sweep counts."""
         t = self.torch
         cap = max(1024, hits.count)
         singles = self.alloc_singles(cap)
         coinc = (self._empty(cap // 2 + 16, t.int32), self._empty(cap // 2 + 16, t.int32))
-        rc, nc = self.digitize_into(hits, singles, coinc, seed=seed, tallies=tallies, **kw)
-        self._check(rc)
+        out = self.digitize_into(hits, singles, coinc, seed=seed, tallies=tallies, **kw)
+        self._check(out[0])
+        nc = out[1]
+        if len(out) == 3:
+            return singles, (coinc[0][:nc], coinc[1][:nc]), out[2]
         return singles, (coinc[0][:nc], coinc[1][:nc])
 
     # ------------------------------------------------------------ check surface
@@ -717,18 +758,26 @@ class Batch:
         return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
-                      e_hi=650.0, window_ps=3000):
-        """Returns (status, coincidence count, coincidences per instance)."""
+                      e_hi=650.0, window_ps=3000, readout="crystal", sweep=None):
+        """Returns (status, coincidence count, coincidences per instance) and,
+        with sweep = [(e_lo, e_hi), ...], the sweep counts [window][instance]."""
         h = hits.struct()
-        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, 0, 0, 1)
+        dg, keep = _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, 0, 0, 1, readout, sweep)
+        counts = np.zeros((len(sweep) if sweep else 0, self.n), np.uint64)
+        if sweep:
+            dg.sweep_coincidences = counts.ctypes.data
         s = singles.struct()
         cc = Coincidences(coinc[0].data_ptr(), coinc[1].data_ptr(), coinc[0].numel(), 0)
         per = np.zeros(self.n, np.uint64)
         rc = self.L.gpet_batch_digitize(self.h, C.byref(h), C.byref(dg), C.byref(s), C.byref(cc),
                                         per.ctypes.data_as(C.c_void_p))
+        del keep
         singles.count = int(s.count)
+        singles.windowed = int(s.windowed)
         if rc not in (OK, ERR_CAPACITY):
             self.ctx._check(rc)
+        if sweep is not None:
+            return rc, int(cc.count), per.astype(np.int64), counts.astype(np.int64)
         return rc, int(cc.count), per.astype(np.int64)
 
     def digitize(self, hits: HitList, seed=0, **kw):
@@ -736,9 +785,12 @@ class Batch:
         cap = max(1024, hits.count)
         singles = self.ctx.alloc_singles(cap, instance=True)
         coinc = (self.ctx._empty(cap // 2 + 16, t.int32), self.ctx._empty(cap // 2 + 16, t.int32))
-        rc, nc, per = self.digitize_into(hits, singles, coinc, seed=seed, **kw)
-        self.ctx._check(rc)
-        return singles, (coinc[0][:nc], coinc[1][:nc]), per
+        out = self.digitize_into(hits, singles, coinc, seed=seed, **kw)
+        self.ctx._check(out[0])
+        nc = out[1]
+        if len(out) == 4:
+            return singles, (coinc[0][:nc], coinc[1][:nc]), out[2], out[3]
+        return singles, (coinc[0][:nc], coinc[1][:nc]), out[2]
 
     def autotune(self, hits: HitList, seed=0, cache_path=None, key=None):
         """Launch shape and chunk size for this batch: read from the JSON cache

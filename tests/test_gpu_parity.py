@@ -428,3 +428,80 @@ def test_edge_cases(ctx, oracle_mod):
     assert st["events"] == 4097
     ev = h.numpy()["event"]
     assert ev.min() >= 3 and ev.max() < 3 + 4097
+
+
+# ---------------------------------------------------------------------------
+# single readout levels (Sec. 2.1) and the energy-window sweep (Sec. 2.3)
+# ---------------------------------------------------------------------------
+def _readout_compare(s, so, ca, cb, co, edge_tol=1e-2):
+    assert len(s["event"]) == len(so)
+    assert np.array_equal(s["event"].view(np.uint32), so["event"])
+    assert np.array_equal(s["gid"].view(np.uint32), so["gid"])
+    assert np.array_equal(s["time_ps"].view(np.uint64), so["time_ps"])
+    np.testing.assert_allclose(s["edep_kev"], so["edep"], rtol=2e-6, atol=1e-4)
+    np.testing.assert_allclose(s["depth_mm"], so["depth"], rtol=1e-5, atol=1e-5)
+    edge = (np.abs(so["energy"] - 350) < edge_tol) | (np.abs(so["energy"] - 650) < edge_tol)
+    assert np.array_equal(s["in_window"][~edge] != 0, so["in_window"][~edge] != 0)
+    got = sorted(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
+    ref = sorted(map(tuple, co.tolist()))
+    if not edge.any():
+        assert got == ref
+    else:
+        assert len(set(got) ^ set(ref)) <= 4 * int(edge.sum())
+
+
+@pytest.mark.parametrize("level", ["module", "panel"])
+def test_readout_on_transported_hits(ctx, oracle_mod, level):
+    """Module and panel readout of the same (GPU-produced) hits against the
+    oracle: merged singles and coincidences element by element."""
+    n = 200_000
+    sc = G.small_animal_scene("C", n_events=n)
+    o = _both(ctx, oracle_mod, sc)
+    hits, _ = ctx.transport(n, seed=5)
+    sg, (ca, cb) = ctx.digitize(hits, seed=6, readout=level)
+    so, co = o.digitize(_hits_as_oracle(oracle_mod, hits.numpy()), seed=6, readout={"module": 1, "panel": 2}[level])
+    s = sg.numpy()
+    print(level, "singles", len(so), "coincidences", len(co))
+    _readout_compare(s, so, ca, cb, co)
+    assert sg.windowed == int((s["in_window"] != 0).sum())
+
+
+@pytest.mark.parametrize("level", ["module", "panel"])
+def test_readout_crafted_against_oracle(ctx, oracle_mod, level):
+    """Dense crafted hits (many crystals of one unit per event, ties of equal
+    energy) through both readouts."""
+    sc = G.small_animal_scene("C", n_events=10)
+    o = _both(ctx, oracle_mod, sc)
+    rng = np.random.default_rng(12)
+    n = 30_000
+    ev = np.sort(rng.integers(0, 8000, n))
+    unit = o.s.crystals_per_module if level == "module" else o.s.crystals_per_panel
+    gid = (rng.integers(0, 12 * 4420 // unit, n) * unit + rng.integers(0, 8, n)).astype(np.int64)
+    edep = rng.choice([100.0, 150.0, 200.0, 250.0, 300.0], n).astype(np.float32)  # ties on purpose
+    t = rng.integers(0, 8000 * 3000, n)
+    sg, (ca, cb) = ctx.digitize(_hitlist(ctx, ev, gid, edep, t, 0, 8000), seed=4, readout=level)
+    so, co = o.digitize(_oracle_hits(oracle_mod, ev, gid, edep, t), seed=4,
+                        readout={"module": 1, "panel": 2}[level])
+    _readout_compare(sg.numpy(), so, ca, cb, co)
+
+
+def test_window_sweep_counts(ctx, oracle_mod):
+    """The four windows of the sensitivity study counted in one call equal
+    four separate calls (same blurred energies) and the oracle's counts.  A
+    wider window need not give more coincidences: the extra singles also turn
+    pairs into discarded multiples."""
+    n = 300_000
+    sc = G.small_animal_scene("C", n_events=n)
+    o = _both(ctx, oracle_mod, sc)
+    hits, _ = ctx.transport(n, seed=8)
+    sweep = [(150.0, 700.0), (250.0, 700.0), (350.0, 700.0), (450.0, 700.0)]
+    _, (ca, _), counts = ctx.digitize(hits, seed=9, sweep=sweep)
+    assert len(ca) > 0
+    h = _hits_as_oracle(oracle_mod, hits.numpy())
+    for (lo, hi), c in zip(sweep, counts):
+        _, (a, _) = ctx.digitize(hits, seed=9, e_lo=lo, e_hi=hi)
+        assert int(c) == len(a), (lo, hi)
+        so, co = o.digitize(h, seed=9, e_lo=lo, e_hi=hi)
+        edge = int(((np.abs(so["energy"] - lo) < 1e-2) | (np.abs(so["energy"] - hi) < 1e-2)).sum())
+        print(lo, hi, "gpu", int(c), "oracle", len(co), "edge singles", edge)
+        assert abs(int(c) - len(co)) <= 4 * edge
