@@ -131,6 +131,75 @@ def cpu_baseline(target_s: float = 12.0):
             "single_core": {"value": n1 / dt1, "events": n1, "seconds": dt1}}
 
 
+SWEEP_WINDOWS = [(150.0, 700.0), (250.0, 700.0), (350.0, 700.0), (450.0, 700.0)]
+
+
+def window_sweep(ctxs, n, seed, pos):
+    """The sensitivity study of the last step's hits (one source position):
+    coincidences / events in the four energy windows at crystal, module and
+    panel readout for each design, the symmetric difference
+    200 (S_A - S_C) / (S_A + S_C) between the one-layer design A and the offset
+    two-layer design C, and the digitizer time of a pass that lists the
+    350-650 keV coincidences and counts the four windows."""
+    import torch
+    sens, ms = {}, {}
+    for d, c, hits, singles, coinc in ctxs:
+        sens[d] = {}
+        for level in ("crystal", "module", "panel"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, _, cnt = c.digitize_into(hits, singles, coinc, seed=seed, readout=level, sweep=SWEEP_WINDOWS)
+            torch.cuda.synchronize()
+            ms.setdefault(level, []).append((time.perf_counter() - t0) * 1e3)
+            if rc != 0:
+                raise RuntimeError("window sweep: capacity")
+            sens[d][level] = [int(x) / n for x in cnt]
+    dsym = {level: [200.0 * (a - b) / (a + b) if a + b > 0 else 0.0
+                    for a, b in zip(sens["A"][level], sens["C"][level])] for level in sens["A"]}
+    return {"windows_kev": SWEEP_WINDOWS, "source_position_mm": list(pos), "events_per_design": n,
+            "sensitivity": sens, "dsym_A_vs_C_percent": dsym,
+            "ms_per_design": {k: float(np.mean(v)) for k, v in ms.items()}}
+
+
+def config1_form():
+    """The small ring (8 panels of 8 x 8 crystals, point source at the
+    centre): transport + digitizer events/s at 1e5 events (launch-bound,
+    median of 5) and 1e8 events, and the oracle's rate on a bounded sample."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2603_07327_amd.gpet import Context
+    out = {"workload": "8 panels at 40 mm, 8x8 LYSO 1.5 mm crystals, point source at the centre"}
+    for n, reps in ((100_000, 5), (100_000_000, 1)):
+        sc = G.ring8_scene(n_events=n)
+        c = Context(0)
+        c.set_scene(sc)
+        hits = c.alloc_hits(max(4096, int(0.5 * n)))
+        singles = c.alloc_singles(max(4096, int(0.5 * n)))
+        coinc = (c._empty(max(4096, n // 10), torch.int32), c._empty(max(4096, n // 10), torch.int32))
+        times = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, _ = c.transport_into(hits, n, seed=r)
+            rc2, nc = c.digitize_into(hits, singles, coinc, seed=r)
+            torch.cuda.synchronize()
+            if rc or rc2:
+                raise RuntimeError("config 1: capacity")
+            if r:
+                times.append(time.perf_counter() - t0)
+        out[f"events_{n}"] = {"value": n / float(np.median(times)), "unit": "events/s",
+                              "ms": float(np.median(times)) * 1e3, "coincidences": nc}
+        c.close()
+    s = O.OracleScene(G.ring8_scene(n_events=1_000_000))
+    t0 = time.perf_counter()
+    h, _ = s.transport(1_000_000, seed=1)
+    s.digitize(h, seed=1)
+    dt = time.perf_counter() - t0
+    out["oracle"] = {"value": 1_000_000 / dt, "unit": "events/s", "cores": O.num_threads(), "events": 1_000_000}
+    return out
+
+
 def batched_form(args):
     """The batched design sweep (36 designs x 4 source offsets, log-uniform event
     counts): one persistent transport launch over all instances plus one
@@ -378,6 +447,8 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="event-count scale of the batched design sweep (0 skips it)")
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner")
+    ap.add_argument("--no-config1", dest="config1", action="store_false",
+                    help="skip the small-ring rates at 1e5 and 1e8 events")
     ap.add_argument("--surrogate-events", type=int, default=100_000_000,
                     help="events of the hot-rod phantom workload timed plain and with the surrogate (0 skips)")
     ap.add_argument("--surrogate-train-events", type=int, default=100_000_000,
@@ -433,8 +504,7 @@ def main():
                 work.append(algorithmic_work(st, ring=True, source="point"))
                 stats_last = st
                 digi_ms.append(tm[1])
-                windowed = int(singles.in_window[: singles.count].sum().item())
-                digi_bytes.append(digitizer_bytes(hits.count, singles.count, windowed, nc))
+                digi_bytes.append(digitizer_bytes(hits.count, singles.count, singles.windowed, nc))
             out.append((d, hits.count, singles.count, nc))
         return out
 
@@ -475,9 +545,13 @@ def main():
                                "bytes_per_design": float(np.mean(digi_bytes)), "ms_per_design": float(np.mean(digi_ms)),
                                "bytes_per_item": DIGI_BYTES},
     }
+    line["window_sweep"] = window_sweep(ctxs, n, 1000 + args.warmup + args.steps - 1,
+                                        G.SWEEP_POSITIONS[(args.warmup + args.steps - 1) % len(G.SWEEP_POSITIONS)])
     for _, c, *_ in ctxs:
         c.close()
     del ctxs
+    if args.config1:
+        line["config1"] = config1_form()
     if args.batched_scale > 0:
         line["batched"] = batched_form(args)
     if args.surrogate_events > 0:
