@@ -161,6 +161,55 @@ def window_sweep(ctxs, n, seed, pos):
             "ms_per_design": {k: float(np.mean(v)) for k, v in ms.items()}}
 
 
+# the paper's Table 1 (Derenzo rods, 10 runs): hit and coincidence events
+PAPER_TABLE1 = {"1CL": (2671908, 378152), "1CL-split": (2673328, 378866), "2CL": (2620170, 363893)}
+
+
+def paper_scanners_form(n: int = 10_000_000):
+    """The paper's three validation scanners (H2RSPET-1CL, -1CL-split, -2CL)
+    with the Derenzo rods in a water cube: transport + digitizer events/s
+    (median of 3 after one warm-up) and hits and coincidences of each, with
+    their ratios to 1CL next to those of the paper's Table 1 (context only:
+    the attenuation tables here are synthetic)."""
+    import torch
+
+    from paper_2603_07327_amd.gpet import Context
+    out = {"workload": f"H2RSPET 1CL / 1CL-split / 2CL (10 panels at 85 mm, 6 modules of 51x51), Derenzo rods "
+                       f"(116 rods, 0.3-1.0 mm) in a 40.25 mm water cube, {n:.0e} events"}
+    res = {}
+    for kind in ("1CL", "1CL-split", "2CL"):
+        c = Context(0)
+        c.set_scene(G.derenzo_scene(kind, n))
+        c.enable_timing(True)
+        hits = c.alloc_hits(int(3.0 * n))
+        singles = c.alloc_singles(int(2.5 * n))
+        coinc = (c._empty(n, torch.int32), c._empty(n, torch.int32))
+        times, kms = [], []
+        for r in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = c.transport_into(hits, n, seed=0)
+            rc2, nc = c.digitize_into(hits, singles, coinc, seed=0)
+            torch.cuda.synchronize()
+            if rc or rc2:
+                raise RuntimeError("paper scanners: capacity")
+            if r:
+                times.append(time.perf_counter() - t0)
+                kms.append(c.timings()[0])
+        res[kind] = {"value": n / float(np.median(times)), "unit": "events/s", "ms": float(np.median(times)) * 1e3,
+                     "transport_kernel_ms": float(np.median(kms)), "hits": hits.count, "singles": singles.count,
+                     "coincidences": nc}
+        c.close()
+    for kind in res:
+        res[kind]["hits_ratio_to_1CL"] = res[kind]["hits"] / res["1CL"]["hits"]
+        res[kind]["coincidences_ratio_to_1CL"] = res[kind]["coincidences"] / res["1CL"]["coincidences"]
+        ph, pc = PAPER_TABLE1[kind]
+        res[kind]["paper_hits_ratio_to_1CL"] = ph / PAPER_TABLE1["1CL"][0]
+        res[kind]["paper_coincidences_ratio_to_1CL"] = pc / PAPER_TABLE1["1CL"][1]
+    out.update(res)
+    return out
+
+
 def config1_form():
     """The small ring (8 panels of 8 x 8 crystals, point source at the
     centre): transport + digitizer events/s at 1e5 events (launch-bound,
@@ -449,6 +498,8 @@ def main():
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner")
     ap.add_argument("--no-config1", dest="config1", action="store_false",
                     help="skip the small-ring rates at 1e5 and 1e8 events")
+    ap.add_argument("--no-paper-scanners", dest="paper_scanners", action="store_false",
+                    help="skip the H2RSPET / Derenzo workload")
     ap.add_argument("--surrogate-events", type=int, default=100_000_000,
                     help="events of the hot-rod phantom workload timed plain and with the surrogate (0 skips)")
     ap.add_argument("--surrogate-train-events", type=int, default=100_000_000,
@@ -552,6 +603,8 @@ def main():
     del ctxs
     if args.config1:
         line["config1"] = config1_form()
+    if args.paper_scanners:
+        line["paper_scanners"] = paper_scanners_form()
     if args.batched_scale > 0:
         line["batched"] = batched_form(args)
     if args.surrogate_events > 0:

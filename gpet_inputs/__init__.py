@@ -155,6 +155,26 @@ def hot_rod_layout(diameters=(0.8, 1.0, 1.25, 1.5, 1.75, 2.0), r_max=11.5, lengt
     return np.asarray(rods, np.float64)
 
 
+def derenzo_layout(diameters=(0.3, 0.4, 0.5, 0.625, 0.75, 1.0), rows=(3, 4, 5, 6, 7, 8),
+                   length=20.0) -> np.ndarray:
+    """Derenzo rods of the paper's visibility study (Sec. 2.3): six sectors of
+    rods of one diameter each, 2d centre-to-centre, 20 mm long; sector k holds
+    rows[k] rows (1 + 2 + ... rods: 6, 10, 15, 21, 28, 36).  Placement follows
+    hot_rod_layout (sector bisectors at 60k + 30 degrees, first row at d + 1 mm).
+    Returns rows of (cx, cy, radius, z0, z1)."""
+    rods = []
+    for k, (d, n_rows) in enumerate(zip(diameters, rows)):
+        ang = math.radians(60.0 * k + 30.0)
+        ux, uy = math.cos(ang), math.sin(ang)
+        vx, vy = -uy, ux
+        for j in range(n_rows):
+            h = (d + 1.0) + j * 2.0 * d * math.sqrt(3.0) / 2.0
+            for i in range(j + 1):
+                off = (i - j / 2.0) * 2.0 * d
+                rods.append((h * ux + off * vx, h * uy + off * vy, d / 2.0, -length / 2.0, length / 2.0))
+    return np.asarray(rods, np.float64)
+
+
 def rod_source(rods: np.ndarray, n_events: int) -> dict:
     vol = float(np.sum(math.pi * rods[:, 2] ** 2 * (rods[:, 4] - rods[:, 3])))
     return {"kind": SRC_CYLINDERS, "pos": (0.0, 0.0, 0.0), "dir": (0.0, 0.0, 1.0),
@@ -180,6 +200,14 @@ def water_cylinder_phantom(diameter=25.0, length=70.0, voxel=0.5, mat_water=2, m
     den = np.ascontiguousarray(np.broadcast_to(den2, (nz, ny, nx)))
     return {"shape": (nx, ny, nz), "voxel": (voxel, voxel, voxel), "origin": (ox, oy, oz),
             "mat": mat, "dens": den}
+
+
+def water_box_phantom(side=40.25, voxel=0.5, mat_water=2, water_density=1.0) -> dict:
+    """Voxelized water cube centred at the origin (the Derenzo phantom's body)."""
+    n = int(round(side / voxel))
+    o = -n * voxel / 2.0
+    return {"shape": (n, n, n), "voxel": (voxel, voxel, voxel), "origin": (o, o, o),
+            "mat": np.full((n, n, n), mat_water, np.uint8), "dens": np.full((n, n, n), water_density, np.float32)}
 
 
 def slab_phantom(mats, thicknesses, densities, cross=20.0, voxel=0.5) -> dict:
@@ -257,6 +285,35 @@ def small_animal_scanner(design: str, thick=10.0, gap=None, offset=None, black=F
         lays = [layer(0.0, 2 * thick, 1, 1, 24.0, 24.0, 24.0, 24.0)]
     depth = max(l["depth0"] + l["thick"] for l in lays)
     return scanner(12, 65.0, depth, 1, 4, 24.0, 24.0, 0.0, 2.0, lays)
+
+
+H2RSPET = ("1CL", "1CL-split", "2CL")
+
+
+def h2rspet_scanner(kind: str) -> dict:
+    """The paper's validation scanners (Sec. 2.2): 10 panels at 85 mm, each
+    1.0 x 5.1 x 34.1 cm (radial x tangential x axial) holding 6 modules along
+    the axis, 51 x 51 crystals of 0.92 mm at 1.0 mm pitch, 7 mm between
+    modules; 1CL: one 10 mm layer; 1CL-split: two aligned 5 mm layers;
+    2CL: an inner 50 x 50 layer offset by half a pitch (R-offset) over an outer
+    51 x 51 layer, 5 mm each."""
+    if kind == "1CL":
+        lays = [layer(0.0, 10.0, 51, 51, 0.92, 0.92, 1.0, 1.0)]
+    elif kind == "1CL-split":
+        lays = [layer(0.0, 5.0, 51, 51, 0.92, 0.92, 1.0, 1.0), layer(5.0, 5.0, 51, 51, 0.92, 0.92, 1.0, 1.0)]
+    elif kind == "2CL":
+        lays = [layer(0.0, 5.0, 50, 50, 0.92, 0.92, 1.0, 1.0, 0.5, 0.5),
+                layer(5.0, 5.0, 51, 51, 0.92, 0.92, 1.0, 1.0)]
+    else:
+        raise KeyError(kind)
+    return scanner(10, 85.0, 10.0, 1, 6, 51.0, 51.0, 0.0, 7.0, lays)
+
+
+def derenzo_scene(kind: str = "2CL", n_events: int = 1_000_000, with_phantom: bool = True) -> dict:
+    """An H2RSPET scanner with the Derenzo rods in a water cube."""
+    mats = [material("lyso", density=7.4), material("air"), material("water")]
+    ph = water_box_phantom() if with_phantom else None
+    return scene(mats, physics(rayleigh=True), h2rspet_scanner(kind), rod_source(derenzo_layout(), n_events), ph)
 
 
 # Source positions of the sensitivity sweep: radial 0..50 mm (5 mm steps) along

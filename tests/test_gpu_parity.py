@@ -80,9 +80,9 @@ def test_rayleigh_sampler_matched(ctx, oracle_mod):
 # ---------------------------------------------------------------------------
 # geometry
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("design", ["A", "B", "C"])
+@pytest.mark.parametrize("design", ["A", "B", "C", "H2-2CL"])
 def test_locate_bit_exact_off_boundaries(ctx, oracle_mod, design):
-    sc = G.small_animal_scene(design, n_events=10)
+    sc = G.derenzo_scene("2CL", 10) if design == "H2-2CL" else G.small_animal_scene(design, n_events=10)
     o = _both(ctx, oracle_mod, sc)
     P = o.poses()
     rng = np.random.default_rng(7)
@@ -126,10 +126,12 @@ def test_fixed_rays_bit_exact(ctx, oracle_mod, case):
 # ---------------------------------------------------------------------------
 # transport
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom", "tilted"])
+@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom", "tilted", "derenzo_2CL"])
 def test_matched_histories(ctx, oracle_mod, case):
     if case == "ring8":
         sc, n = G.ring8_scene(n_events=5000), 5000
+    elif case == "derenzo_2CL":
+        sc, n = G.derenzo_scene("2CL", 3000), 3000
     elif case == "tilted":
         sc, n = G.tilted_ring_scene(n_events=5000), 5000
     elif case == "C":
@@ -277,11 +279,12 @@ def test_digitizer_rejects_events_outside_range(ctx, oracle_mod):
         ctx.digitize(h, seed=1)
 
 
-@pytest.mark.parametrize("case", ["ring8", "C"])
+@pytest.mark.parametrize("case", ["ring8", "C", "derenzo_2CL"])
 def test_tallies_matched_seed(ctx, oracle_mod, case):
     """Same seed and event ids: sensitivity within 0.5 % relative."""
-    n = 1_000_000 if case == "ring8" else 300_000
-    sc = G.ring8_scene(n_events=n) if case == "ring8" else G.small_animal_scene("C", n_events=n)
+    n = {"ring8": 1_000_000, "C": 300_000, "derenzo_2CL": 300_000}[case]
+    sc = {"ring8": lambda: G.ring8_scene(n_events=n), "C": lambda: G.small_animal_scene("C", n_events=n),
+          "derenzo_2CL": lambda: G.derenzo_scene("2CL", n)}[case]()
     o = _both(ctx, oracle_mod, sc)
     hits, st = ctx.transport(n, seed=0)
     _, (ca, _) = ctx.digitize(hits, seed=0)
