@@ -25,7 +25,8 @@ import numpy as np
 # ---------------------------------------------------------------------------
 # Materials (composition only).  Atomic masses in g/mol.
 # ---------------------------------------------------------------------------
-_A = {1: 1.008, 7: 14.007, 8: 15.999, 14: 28.086, 18: 39.948, 39: 88.906, 71: 174.967}
+_A = {1: 1.008, 7: 14.007, 8: 15.999, 14: 28.086, 18: 39.948, 32: 72.630, 39: 88.906, 71: 174.967,
+      83: 208.980}
 
 PROC_PE, PROC_COMPTON, PROC_RAYLEIGH = 1, 2, 4
 PROC_ALL = PROC_PE | PROC_COMPTON | PROC_RAYLEIGH
@@ -46,6 +47,9 @@ def material(name: str, density: float | None = None, mask: int = PROC_ALL) -> d
     elif name == "water":
         zs, a, w = _by_atoms({1: 2.0, 8: 1.0})
         rho = 1.0
+    elif name == "bgo":  # Bi4 Ge3 O12
+        zs, a, w = _by_atoms({83: 4.0, 32: 3.0, 8: 12.0})
+        rho = 7.13
     elif name == "air":  # dry air by mass: N, O, Ar
         zs = [7, 8, 18]
         a = [_A[z] for z in zs]
@@ -285,6 +289,38 @@ def small_animal_scanner(design: str, thick=10.0, gap=None, offset=None, black=F
         lays = [layer(0.0, 2 * thick, 1, 1, 24.0, 24.0, 24.0, 24.0)]
     depth = max(l["depth0"] + l["thick"] for l in lays)
     return scanner(12, 65.0, depth, 1, 4, 24.0, 24.0, 0.0, 2.0, lays)
+
+
+STACKS = ("stack3", "stack4")
+
+
+def stack_scanner(kind: str) -> dict:
+    """Deeper stacks on the small-animal panel (12 panels at 65 mm, 1 x 4
+    modules of 24 mm, 1 mm pitch, 0.92 mm crystals), for the 3- and 4-layer
+    architectures the paper points to (Discussion).
+    stack3: 22x22 (6 mm, centred), 0.2 mm gap, 23x23 (7 mm, half-pitch
+    offset), 24x24 (7 mm);
+    stack4: four 5 mm layers alternating BGO (material 2) and LYSO: 24x24,
+    23x24 shifted half a pitch along t, 24x23 shifted along a, 23x23 shifted
+    along both."""
+    if kind == "stack3":
+        lays = [layer(0.0, 6.0, 22, 22, 0.92, 0.92, 1.0, 1.0, 1.0, 1.0),
+                layer(6.2, 7.0, 23, 23, 0.92, 0.92, 1.0, 1.0, 0.5, 0.5),
+                layer(13.2, 7.0, 24, 24, 0.92, 0.92, 1.0, 1.0)]
+    elif kind == "stack4":
+        lays = [layer(0.0, 5.0, 24, 24, 0.92, 0.92, 1.0, 1.0, mat_crystal=2),
+                layer(5.0, 5.0, 23, 24, 0.92, 0.92, 1.0, 1.0, 0.5, 0.0),
+                layer(10.0, 5.0, 24, 23, 0.92, 0.92, 1.0, 1.0, 0.0, 0.5, mat_crystal=2),
+                layer(15.0, 5.0, 23, 23, 0.92, 0.92, 1.0, 1.0, 0.5, 0.5)]
+    else:
+        raise KeyError(kind)
+    depth = max(l["depth0"] + l["thick"] for l in lays)
+    return scanner(12, 65.0, depth, 1, 4, 24.0, 24.0, 0.0, 2.0, lays)
+
+
+def stack_scene(kind: str, pos=(0.0, 0.0, 0.0), n_events: int = 1_000_000) -> dict:
+    mats = [material("lyso"), material("air"), material("bgo")]
+    return scene(mats, physics(rayleigh=True), stack_scanner(kind), point_source(pos, n_events))
 
 
 H2RSPET = ("1CL", "1CL-split", "2CL")

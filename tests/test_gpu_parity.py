@@ -80,9 +80,14 @@ def test_rayleigh_sampler_matched(ctx, oracle_mod):
 # ---------------------------------------------------------------------------
 # geometry
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("design", ["A", "B", "C", "H2-2CL"])
+@pytest.mark.parametrize("design", ["A", "B", "C", "H2-2CL", "stack3", "stack4"])
 def test_locate_bit_exact_off_boundaries(ctx, oracle_mod, design):
-    sc = G.derenzo_scene("2CL", 10) if design == "H2-2CL" else G.small_animal_scene(design, n_events=10)
+    if design == "H2-2CL":
+        sc = G.derenzo_scene("2CL", 10)
+    elif design.startswith("stack"):
+        sc = G.stack_scene(design, n_events=10)
+    else:
+        sc = G.small_animal_scene(design, n_events=10)
     o = _both(ctx, oracle_mod, sc)
     P = o.poses()
     rng = np.random.default_rng(7)
@@ -126,10 +131,12 @@ def test_fixed_rays_bit_exact(ctx, oracle_mod, case):
 # ---------------------------------------------------------------------------
 # transport
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom", "tilted", "derenzo_2CL"])
+@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom", "tilted", "derenzo_2CL", "stack4"])
 def test_matched_histories(ctx, oracle_mod, case):
     if case == "ring8":
         sc, n = G.ring8_scene(n_events=5000), 5000
+    elif case == "stack4":
+        sc, n = G.stack_scene("stack4", (3.0, 1.0, 2.0), 5000), 5000
     elif case == "derenzo_2CL":
         sc, n = G.derenzo_scene("2CL", 3000), 3000
     elif case == "tilted":
@@ -279,12 +286,13 @@ def test_digitizer_rejects_events_outside_range(ctx, oracle_mod):
         ctx.digitize(h, seed=1)
 
 
-@pytest.mark.parametrize("case", ["ring8", "C", "derenzo_2CL"])
+@pytest.mark.parametrize("case", ["ring8", "C", "derenzo_2CL", "stack3", "stack4"])
 def test_tallies_matched_seed(ctx, oracle_mod, case):
     """Same seed and event ids: sensitivity within 0.5 % relative."""
-    n = {"ring8": 1_000_000, "C": 300_000, "derenzo_2CL": 300_000}[case]
+    n = {"ring8": 1_000_000, "C": 300_000, "derenzo_2CL": 300_000, "stack3": 300_000, "stack4": 300_000}[case]
     sc = {"ring8": lambda: G.ring8_scene(n_events=n), "C": lambda: G.small_animal_scene("C", n_events=n),
-          "derenzo_2CL": lambda: G.derenzo_scene("2CL", n)}[case]()
+          "derenzo_2CL": lambda: G.derenzo_scene("2CL", n), "stack3": lambda: G.stack_scene("stack3", n_events=n),
+          "stack4": lambda: G.stack_scene("stack4", n_events=n)}[case]()
     o = _both(ctx, oracle_mod, sc)
     hits, st = ctx.transport(n, seed=0)
     _, (ca, _) = ctx.digitize(hits, seed=0)

@@ -62,9 +62,9 @@ def test_repetition_mode_poses(oracle_mod):
     np.testing.assert_allclose(steps, 2 * math.pi / n, rtol=1e-12)       # equal rotation step
 
 
-@pytest.mark.parametrize("design", ["A", "B", "C", "B0"])
+@pytest.mark.parametrize("design", ["A", "B", "C", "B0", "stack3", "stack4"])
 def test_locate_matches_brute_force(oracle_mod, design):
-    sc = G.small_animal_scene(design, n_events=10)
+    sc = G.stack_scene(design, n_events=10) if design.startswith("stack") else G.small_animal_scene(design, n_events=10)
     s = oracle_mod.OracleScene(sc)
     scan = sc["scanner"]
     lo, hi, meta, per_panel = _boxes(scan)
@@ -79,6 +79,7 @@ def test_locate_matches_brute_force(oracle_mod, design):
     glob = P[panel, 0:3] + loc[:, 0:1] * P[panel, 3:6] + loc[:, 1:2] * P[panel, 6:9] \
         + loc[:, 2:3] * P[panel, 9:12]
     ids, bd = s.locate(glob)
+    crystal_mats = {ly["mat_crystal"] for ly in scan["layers"]}
     ok = bd > 1e-9
     assert ok.mean() > 0.99
     inside_panel = ((loc[:, 0] >= 0) & (loc[:, 0] < scan["depth"]) &
@@ -93,12 +94,12 @@ def test_locate_matches_brute_force(oracle_mod, design):
             continue
         assert ids[i, 0] == panel[i]
         if len(k) == 0:
-            assert ids[i, 4] == -1 and ids[i, 5] != 0
+            assert ids[i, 4] == -1 and ids[i, 5] not in crystal_mats
         else:
             module, layer, cid, lid = meta[k[0]]
             assert (ids[i, 1], ids[i, 2], ids[i, 3]) == (module, layer, cid)
             assert ids[i, 4] == panel[i] * per_panel + lid
-            assert ids[i, 5] == 0
+            assert ids[i, 5] == scan["layers"][layer]["mat_crystal"]
 
 
 def test_crystal_volume_deficit(oracle_mod):
