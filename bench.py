@@ -41,7 +41,8 @@ VALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (no pac
 # Philox blocks of the event stream per annihilation: direction and time for
 # point and beam sources, plus the emission point for rod sources
 EVENT_BLOCKS = {"point": 2, "beam": 2, "rods": 3}
-TRANSPORT_SOURCES = ("paper_2603_07327_amd/csrc/transport.hip", "paper_2603_07327_amd/csrc/gpet_device.hpp")
+TRANSPORT_SOURCES = ("paper_2603_07327_amd/csrc/transport.hip", "paper_2603_07327_amd/csrc/gpet_device.hpp",
+                     "paper_2603_07327_amd/csrc/transport_common.hpp")
 
 
 def algorithmic_work(stats: dict, ring: bool = True, source: str = "point") -> float:

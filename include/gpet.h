@@ -485,8 +485,10 @@ gpet_status gpet_batch_read_counts(gpet_batch *batch, gpet_hits *hits, gpet_stat
  * (0 = as many as fit); the scheduling of lane actions within a wavefront
  * (0: every pending action runs each loop trip, with panel searches held until
  * `search_batch` lanes (1..64) need one; 1: only the action held by the most
- * lanes runs).  Results do not depend on the shape (every random number is
- * keyed by event id). */
+ * lanes runs; 2: plain transport only -- each wavefront keeps a pool of 128
+ * photons in LDS and every loop trip gathers up to 64 photons waiting for the
+ * same action onto its lanes; other calls run as schedule 0).  Results do not
+ * depend on the shape (every random number is keyed by event id). */
 gpet_status gpet_ctx_set_launch(gpet_ctx *ctx, int32_t blocks_per_cu, int32_t search_batch, int32_t schedule);
 
 /* Kernel timing: when enabled, HIP events bracket the transport kernel and

@@ -20,6 +20,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse multiply-adds only inside one expression, so the same source
+    # arithmetic rounds the same way in every kernel that contains it
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -639,11 +639,11 @@ static void set_hits(RunArgs &A, gpet_hits *h) {
 }
 
 // runs a prepared transport launch and reads back the counts
-static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, int det_slots, const LaunchShape &shape,
+static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, const LaunchShape &shape,
                                  gpet_hits *h, gpet_stats *stats, int mode = kModePlain) {
   launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
-  if (A.total_chunks) launch_transport(A, det_slots, shape, c->n_cu, c->stream, mode);
+  if (A.total_chunks) launch_transport(A, shape, c->n_cu, c->stream, mode);
   if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
   gpet_status s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
@@ -676,7 +676,7 @@ gpet_status gpet_transport(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t see
   s = run_args(c, first, n, seed, instance, A);
   if (s) return s;
   set_hits(A, h);
-  return run_transport(c, A, c->scene.n_det_slots, c->shape, h, stats);
+  return run_transport(c, A, c->shape, h, stats);
 }
 
 // shared validation of digitizer parameters
@@ -756,8 +756,8 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
 gpet_status gpet_ctx_set_launch(gpet_ctx *c, int32_t blocks_per_cu, int32_t search_batch, int32_t schedule) {
   if (!c) return GPET_ERR_ARG;
   if (blocks_per_cu < 0 || blocks_per_cu > 64 || search_batch < 1 || search_batch > 64 || schedule < 0 ||
-      schedule > 1)
-    return fail(c, GPET_ERR_ARG, "launch: blocks_per_cu in 0..64, search_batch in 1..64, schedule 0 or 1");
+      schedule > 2)
+    return fail(c, GPET_ERR_ARG, "launch: blocks_per_cu in 0..64, search_batch in 1..64, schedule 0, 1 or 2");
   c->shape.blocks_per_cu = blocks_per_cu;
   c->shape.search_batch = (uint32_t)search_batch;
   c->shape.schedule = (uint32_t)schedule;
@@ -855,7 +855,7 @@ gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, u
   A.max_vertices = maxv;
   launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
   launch_fill_u32((uint32_t *)counts, 0u, 2 * (size_t)n, c->stream);
-  if (n) launch_trace(A, c->scene.n_det_slots, c->stream);
+  if (n) launch_trace(A, c->stream);
   s = hip_check(c, hipGetLastError(), "trace: launch");
   return s ? s : hip_check(c, hipStreamSynchronize(c->stream), "trace");
 }
@@ -913,7 +913,7 @@ gpet_status gpet_surrogate_pairs(gpet_ctx *c, const gpet_surrogate_spec *spec, u
   A.pevent = pairs->event;
   A.pcount = c->d_ctrl + kCtrlPairs;
   A.pcap = pairs->capacity;
-  s = run_transport(c, A, c->scene.n_det_slots, c->shape, h, stats, kModeRecord);
+  s = run_transport(c, A, c->shape, h, stats, kModeRecord);
   pairs->count = c->h_ctrl[kCtrlPairs];
   if (s) return s;
   if (pairs->count > pairs->capacity) return fail(c, GPET_ERR_CAPACITY, "surrogate pairs: pair capacity too small");
@@ -997,7 +997,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2, c->stream);        // event-chunk counter
     launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairs), 0u, 2, c->stream); // queue count
     (void)hipEventRecord(ev[0], c->stream);
-    launch_transport(A, c->scene.n_det_slots, c->shape, c->n_cu, c->stream, kModeSurrogate);
+    launch_transport(A, c->shape, c->n_cu, c->stream, kModeSurrogate);
     (void)hipEventRecord(ev[1], c->stream);
     s = hip_check(c, hipGetLastError(), "surrogate: transport launch");
     if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairs, c->d_ctrl + kCtrlPairs, 8, hipMemcpyDeviceToHost, c->stream),
@@ -1243,7 +1243,7 @@ gpet_status gpet_batch_transport(gpet_batch *b, uint64_t seed, gpet_hits *h, gpe
   A.search_batch = b->shape.search_batch;
   A.schedule = b->shape.schedule;
   set_hits(A, h);
-  return run_transport(c, A, b->det_slots, b->shape, h, stats);
+  return run_transport(c, A, b->shape, h, stats);
 }
 
 gpet_status gpet_batch_graph_capture(gpet_batch *b, uint64_t seed, gpet_hits *h) {
@@ -1265,7 +1265,7 @@ gpet_status gpet_batch_graph_capture(gpet_batch *b, uint64_t seed, gpet_hits *h)
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
     launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, cs); // a kernel, not a memset node
-    if (A.total_chunks) launch_transport(A, b->det_slots, b->shape, c->n_cu, cs);
+    if (A.total_chunks) launch_transport(A, b->shape, c->n_cu, cs);
     ok = hipStreamEndCapture(cs, &g) == hipSuccess && g;
   }
   ok = ok && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;

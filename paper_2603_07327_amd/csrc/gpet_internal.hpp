@@ -54,7 +54,8 @@ struct RunArgs {
   int32_t *vcount;
   int max_vertices;
   uint32_t search_batch; // lanes of a wave that must wait for a panel search before it runs
-  uint32_t schedule;     // 0: all phases each trip; 1: the most-populated phase only
+  uint32_t schedule;     // 0: all phases each trip; 1: the most-populated phase only;
+                         // 2: plain runs use the per-wave photon pools (k_transport_pool)
   // record and surrogate modes: photons entering their first panel inside the
   // surrogate domain get an entry with features px (6 per entry).  Record:
   // label and flags once the photon leaves the panel.  Surrogate: an entry
@@ -76,13 +77,14 @@ struct LaunchShape {
   uint32_t search_batch = 16; // see RunArgs::search_batch
   uint32_t schedule = 0;      // see RunArgs::schedule
 };
-size_t transport_lds_bytes(int det_slots);
+size_t transport_lds_bytes();
 
-// kernels (transport.hip); det_slots is the largest detector material slot
-// count of the launch's scenes (it sizes the LDS tables)
-void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st,
+// kernels (transport.hip)
+void launch_transport(const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st,
                       int mode = kModePlain);
-void launch_trace(const RunArgs &A, int det_slots, hipStream_t st);
+// plain runs with per-wave photon pools (LaunchShape::schedule 2)
+void launch_transport_pool(const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st);
+void launch_trace(const RunArgs &A, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
 void launch_philox(uint64_t seed, const uint32_t *ctr, uint32_t n, uint32_t *out, hipStream_t st);
 void launch_locate(const DevScene &S, uint32_t n, const float *xyz, int32_t *ids6, hipStream_t st);

@@ -17,32 +17,12 @@
 // hits are staged per wave in LDS and written out 128 or more at a time (one atomic and
 // coalesced stores per flush).  The detector attenuation rows and majorant are
 // staged in LDS at kernel start.
-#include "gpet_internal.hpp"
+#include "transport_common.hpp"
 
 namespace gpet {
 
-enum : int {
-  P_FETCH = 0, P_EMIT_DIR = 1, P_EMIT_POS = 2, P_EMIT_TIME = 3, P_PHANTOM = 4, P_SEARCH = 5,
-  P_PANEL = 6, P_KAHN = 7, P_RAYLEIGH = 8, P_DONE = 9
-};
-enum : int { V_STEP = 0, V_ENTER_PANEL = 1, V_EXIT = 2, V_ESCAPE = 3, V_DEAD = 4, V_ENTER_PHANTOM = 5,
-             V_EMIT = 6 };
-
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-// staged hits per wave: flushed once kFlushAt or more are pending, so a trip
-// (at most one hit per lane) always fits.  The one output counter is shared
-// by every wave of the chip, so fewer, larger flushes matter more than the
-// occupancy the staging area costs (4 blocks per CU)
-constexpr int kFlushAt = 128;
-constexpr int kStage = kFlushAt + 64;
-constexpr int kStageBytes = 4 * 5 + 8; // event, gid, aux, edep, depth, time
-
-// LDS bytes of one block for a scene with `slots` detector table rows
-size_t transport_lds_bytes(int slots) {
-  return (size_t)slots * kTabStride * sizeof(float4) + kTabStride * sizeof(float) +
-         (size_t)kWaves * kStage * kStageBytes;
-}
+// LDS bytes of one block: the per-wave hit staging areas
+size_t transport_lds_bytes() { return (size_t)kWaves * kStage * kStageBytes; }
 
 template <bool TRACE>
 __device__ __forceinline__ void vertex(const RunArgs &A, uint32_t ev, int ph, int kind, int region,
@@ -61,41 +41,6 @@ __device__ __forceinline__ void vertex(const RunArgs &A, uint32_t ev, int ph, in
     }
     A.vcount[p] = c + 1;
   }
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// per-wave staging area of hits in LDS (structure of arrays)
-struct Stage {
-  uint32_t *ev, *gid, *aux;
-  float *edep, *depth;
-  unsigned long long *time;
-};
-
-// write `cnt` staged hits of this wave (all of instance `inst`) to the global SoA arrays
-__device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, uint32_t cnt, int lane,
-                                            uint32_t inst) {
-  if (cnt == 0) return;
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(A.hit_count, (unsigned long long)cnt);
-  base = __shfl(base, 0);
-  wave_sync_lds();
-  for (uint32_t k = (uint32_t)lane; k < cnt; k += 64) {
-    const unsigned long long i = base + k;
-    if (i < A.capacity) {
-      A.h_event[i] = st.ev[k];
-      A.h_gid[i] = st.gid[k];
-      A.h_edep[i] = st.edep[k];
-      A.h_depth[i] = st.depth[k];
-      A.h_time[i] = st.time[k];
-      A.h_aux[i] = st.aux[k];
-      if (A.h_inst) A.h_inst[i] = inst;
-    }
-  }
-  wave_sync_lds();
 }
 
 // Surrogate domain of a photon entering a panel at local position xl with
@@ -150,15 +95,13 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   const int wave = (int)(threadIdx.x >> 6);
   const uint64_t below = __lanemask_lt();
 
-  // ---- the instances share their materials: stage instance 0's detector
-  //      attenuation rows and majorant in LDS
+  // ---- the instances share their materials: instance 0's detector
+  //      attenuation rows and majorant (a few KB per material, read through
+  //      the vector caches, which leaves LDS to the hit staging)
   CScene *sp = (CScene *)A.scenes;
-  const int n_slots = sp->n_det_slots;
-  float4 *s_mu = lds4;
-  float *s_maj = (float *)(lds4 + (size_t)n_slots * kTabStride);
-  for (int i = threadIdx.x; i < n_slots * kTabStride; i += kBlock) s_mu[i] = sp->mu_det[i];
-  for (int i = threadIdx.x; i < kTabStride; i += kBlock) s_maj[i] = sp->maj_det[i];
-  char *stage_base = (char *)(s_maj + kTabStride) + (size_t)wave * kStage * kStageBytes;
+  const float4 *s_mu = sp->mu_det;
+  const float *s_maj = sp->maj_det;
+  char *stage_base = (char *)lds4 + (size_t)wave * kStage * kStageBytes;
   Stage st;
   st.time = (unsigned long long *)stage_base;
   st.ev = (uint32_t *)(st.time + kStage);
@@ -658,10 +601,10 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
 }
 
 template <int MODE>
-static void launch_mode(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st) {
+static void launch_mode(const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st) {
   // one resident wave set: as many blocks per CU as the kernel's registers and
   // LDS allow (unless the shape asks for a given number)
-  const size_t lds = transport_lds_bytes(det_slots);
+  const size_t lds = transport_lds_bytes();
   int per_cu = L.blocks_per_cu;
   if (per_cu <= 0) {
     int occ = 0;
@@ -676,15 +619,19 @@ static void launch_mode(const RunArgs &A, int det_slots, const LaunchShape &L, i
   hipLaunchKernelGGL(k_transport<MODE>, dim3((unsigned)grid), dim3(kBlock), lds, st, A);
 }
 
-void launch_transport(const RunArgs &A, int det_slots, const LaunchShape &L, int n_cu, hipStream_t st, int mode) {
-  if (mode == kModeRecord) launch_mode<kModeRecord>(A, det_slots, L, n_cu, st);
-  else if (mode == kModeSurrogate) launch_mode<kModeSurrogate>(A, det_slots, L, n_cu, st);
-  else launch_mode<kModePlain>(A, det_slots, L, n_cu, st);
+void launch_transport(const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st, int mode) {
+  if (mode == kModePlain && L.schedule == 2) {
+    launch_transport_pool(A, L, n_cu, st);
+    return;
+  }
+  if (mode == kModeRecord) launch_mode<kModeRecord>(A, L, n_cu, st);
+  else if (mode == kModeSurrogate) launch_mode<kModeSurrogate>(A, L, n_cu, st);
+  else launch_mode<kModePlain>(A, L, n_cu, st);
 }
 
-void launch_trace(const RunArgs &A, int det_slots, hipStream_t st) {
+void launch_trace(const RunArgs &A, hipStream_t st) {
   const unsigned grid = (A.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_transport<kModeTrace>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(det_slots), st,
+  hipLaunchKernelGGL(k_transport<kModeTrace>, dim3(grid ? grid : 1), dim3(kBlock), transport_lds_bytes(), st,
                      A);
 }
 

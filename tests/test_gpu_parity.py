@@ -386,8 +386,9 @@ def test_determinism_and_chunking(ctx, oracle_mod):
 
 
 def test_launch_shape_does_not_change_results(ctx, oracle_mod):
-    """Every random number is keyed by event id, so block count, search batching
-    and the lane scheduler leave the hit set (and its digitized output) unchanged."""
+    """Every random number is keyed by event id, so block count, search batching,
+    the lane scheduler and the per-wave photon pools leave the hit set (and its
+    digitized output) unchanged."""
     n = 60_000
     ctx.set_scene(G.hot_rod_scene(n_events=n))
 
@@ -396,7 +397,7 @@ def test_launch_shape_does_not_change_results(ctx, oracle_mod):
         key = np.lexsort((g["aux"], g["gid"], g["event"]))
         return {k: v[key] for k, v in g.items()}
     ref = None
-    for shape in [(0, 32, 0), (2, 1, 0), (3, 64, 0), (0, 32, 1), (1, 16, 1)]:
+    for shape in [(0, 32, 0), (2, 1, 0), (3, 64, 0), (0, 32, 1), (1, 16, 1), (0, 16, 2), (1, 16, 2)]:
         ctx.set_launch(*shape)
         h, st = ctx.transport(n, seed=21)
         s, c = ctx.digitize(h, seed=21)
