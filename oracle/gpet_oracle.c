@@ -30,6 +30,7 @@
 #define R_E 2.8179403262e-13   /* classical electron radius, cm */
 #define N_AV 6.02214076e23     /* Avogadro, 1/mol */
 #define C_MM_PER_PS 0.299792458
+#define FWHM_PER_SIGMA 2.354820045030949 /* 2 sqrt(2 ln 2) */
 #define MAX_STEPS (1 << 20)
 
 /* ------------------------------------------------------------------------ */
@@ -718,7 +719,13 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
 
 /* Event: the annihilation point and an isotropic direction from the event
  * stream; photon A leaves along +d, photon B along -d, both at 511 keV
- * (no positron range, annihilation at the emission site, Sec. 2.3). */
+ * (Sec. 2.3: no positron range, annihilation at the emission site).
+ * Optional physics the paper leaves out (Sec. 2.3, Sec. 4):
+ *  acollinearity   - photon B leaves at polar angle theta from -d, theta the
+ *                    length of a 2-D normal vector with the given FWHM per
+ *                    component, azimuth uniform (words 2, 3 of block 2);
+ *  positron range  - the annihilation point is the emission point plus a 3-D
+ *                    normal offset with the given FWHM per axis (block 3). */
 static void event(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uint32_t inst) {
   rng_t r;
   rng_init(&r, seed, ev, inst, 0);
@@ -745,6 +752,20 @@ static void event(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uint
     x[2] = rd[3] + u1[1] * (rd[4] - rd[3]);
   }
   double dm[3] = {-d[0], -d[1], -d[2]};
+  if (s->src.acol_fwhm_deg > 0) {
+    double sig = s->src.acol_fwhm_deg * (PI / 180.0) / FWHM_PER_SIGMA;
+    double th = sig * sqrt(-2.0 * log(u01(w[2])));
+    rotate(dm, cos(th), 2.0 * PI * u01(w[3]));
+  }
+  if (s->src.prange_fwhm_mm > 0) {
+    uint32_t b[4];
+    rng_raw(&r, 3, b);
+    double sig = s->src.prange_fwhm_mm / FWHM_PER_SIGMA;
+    double a = sqrt(-2.0 * log(u01(b[0]))), c = sqrt(-2.0 * log(u01(b[2])));
+    x[0] += sig * a * cos(2.0 * PI * u01(b[1]));
+    x[1] += sig * a * sin(2.0 * PI * u01(b[1]));
+    x[2] += sig * c * cos(2.0 * PI * u01(b[3]));
+  }
   k->cnt[0]++;
   photon(s, k, seed, ev, inst, 0, x, d, t_e);
   photon(s, k, seed, ev, inst, 1, x, dm, t_e);
@@ -829,6 +850,15 @@ static int cmp_single_time(const void *a, const void *b) {
   return 0;
 }
 
+/* dead-time order: unit, then (time, event, crystal) */
+static uint32_t g_dead_unit = 1;
+static int cmp_single_unit_time(const void *a, const void *b) {
+  const or_single *x = &g_sorted_base[*(const int64_t *)a], *y = &g_sorted_base[*(const int64_t *)b];
+  const uint32_t ux = x->gid / g_dead_unit, uy = y->gid / g_dead_unit;
+  if (ux != uy) return ux < uy ? -1 : 1;
+  return cmp_single_time(a, b);
+}
+
 /* Digitizer:
  *  adder   - hits of one event in one crystal sum into a single; its time is the
  *            earliest hit time, its depth the energy-weighted mean;
@@ -839,6 +869,17 @@ static int cmp_single_time(const void *a, const void *b) {
  *            precision) -- the readout levels of Sec. 2.1;
  *  blur    - Gaussian with FWHM(E) = fwhm_511 * sqrt(511 E) (16 % at 511 keV,
  *            Sec. 2.3), normal deviate by Box-Muller from the digitizer stream;
+ *  time    - (timing resolution, optional) the time moves by a normal
+ *            deviate of the given FWHM rounded to the nearest ps (ties to
+ *            even), not below 0: words 2, 3 of the blur block;
+ *  depth   - (DOI resolution, optional) the depth moves by a normal deviate
+ *            of the given FWHM: block 0 of digitizer stream 6;
+ *  dead    - (optional) each unit of the dead-time level sees its blurred
+ *            singles in (time, event, crystal) order; paralyzable: a single
+ *            is lost when the previous one of its unit came less than dead_ps
+ *            earlier; non-paralyzable: when the last single kept came less
+ *            than dead_ps earlier.  Lost singles stay in the list (lost = 1)
+ *            but pass no window;
  *  window  - e_lo <= E <= e_hi on the blurred energy;
  *  sorter  - windowed singles in time order; a non-retriggering window of
  *            width window_ps (3 ns, Sec. 2.3) opens at the earliest unused
@@ -904,14 +945,45 @@ int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits, const
     rng_raw(&r, q->gid, w);
     double u0 = u01(w[0]), u1 = u01(w[1]);
     double nrm = sqrt(-2.0 * log(u0)) * cos(2.0 * PI * u1);
-    double sig = dg->fwhm_511 * sqrt(511.0 * q->edep) / 2.354820045030949;
+    double sig = dg->fwhm_511 * sqrt(511.0 * q->edep) / FWHM_PER_SIGMA;
     q->energy = q->edep + sig * nrm;
     q->in_window = q->energy >= dg->e_lo && q->energy <= dg->e_hi;
+    q->lost = 0;
+    if (dg->time_fwhm_ps > 0) {
+      double z = sqrt(-2.0 * log(u01(w[2]))) * cos(2.0 * PI * u01(w[3]));
+      double tb = (double)q->time_ps + nearbyint(dg->time_fwhm_ps / FWHM_PER_SIGMA * z);
+      q->time_ps = tb > 0 ? (uint64_t)tb : 0;
+    }
+    if (dg->doi_fwhm_mm > 0) {
+      rng_t r6;
+      rng_init(&r6, dg->seed, q->event, dg->instance, 6);
+      uint32_t v[4];
+      rng_raw(&r6, q->gid, v);
+      double z = sqrt(-2.0 * log(u01(v[0]))) * cos(2.0 * PI * u01(v[1]));
+      q->depth += dg->doi_fwhm_mm / FWHM_PER_SIGMA * z;
+    }
+  }
+  if (dg->dead_mode == 1 || dg->dead_mode == 2) {
+    const uint32_t G = (uint32_t)(dg->dead_level == 1 ? s->crystals_per_module
+                                  : dg->dead_level == 2 ? s->crystals_per_panel : 1);
+    int64_t *ord = (int64_t *)malloc((size_t)(ns ? ns : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < ns; i++) ord[i] = i;
+    g_sorted_base = sg;
+    g_dead_unit = G;
+    qsort(ord, (size_t)ns, sizeof(int64_t), cmp_single_unit_time);
+    uint64_t ref = 0; /* previous single (paralyzable) or last kept one */
+    for (int64_t k = 0; k < ns; k++) {
+      or_single *q = &sg[ord[k]];
+      const int first = k == 0 || sg[ord[k - 1]].gid / G != q->gid / G;
+      if (!first && q->time_ps - ref < dg->dead_ps) q->lost = 1;
+      if (dg->dead_mode == 1 || !q->lost) ref = q->time_ps;
+    }
+    free(ord);
   }
   int64_t nw = 0;
   int64_t *idx = (int64_t *)malloc((size_t)(ns ? ns : 1) * sizeof(int64_t));
   for (int64_t i = 0; i < ns; i++)
-    if (sg[i].in_window) idx[nw++] = i;
+    if (sg[i].in_window && !sg[i].lost) idx[nw++] = i;
   g_sorted_base = sg;
   qsort(idx, (size_t)nw, sizeof(int64_t), cmp_single_time);
   int64_t nc = 0;

@@ -17,7 +17,12 @@
  *   or_locate            brute-force enumeration of crystal boxes
  *   or_transport         narrow-beam exp(-mu L), black-ring solid angle,
  *                        collinearity, energy conservation, split-layer invariance
- *   or_digitize          brute-force adder / O(n^2) coincidence reference
+ *   or_digitize          brute-force adder / O(n^2) coincidence reference;
+ *                        time and depth blur against the normal law, dead
+ *                        time against brute force and the Poisson throughput
+ *                        of both dead-time models
+ *   source extensions    acollinearity and positron range against the normal
+ *                        law of each transverse / spatial component
  */
 #ifndef GPET_ORACLE_H
 #define GPET_ORACLE_H
@@ -80,6 +85,8 @@ typedef struct {
   int32_t n_rods;
   const double *rods; /* n_rods x (cx, cy, radius, z0, z1) */
   uint64_t duration_ps;
+  double acol_fwhm_deg;  /* photon-pair acollinearity (0: back to back) */
+  double prange_fwhm_mm; /* positron range, FWHM of each axis (0: annihilation at the emission site) */
 } or_source;
 
 typedef struct {
@@ -124,13 +131,19 @@ typedef struct {
   uint32_t instance;
   int32_t doi_bins;
   int32_t readout;     /* single readout level: 0 crystal, 1 module, 2 panel */
+  double time_fwhm_ps; /* timing resolution (0: none) */
+  double doi_fwhm_mm;  /* depth-of-interaction resolution (0: none) */
+  uint64_t dead_ps;    /* dead time of a unit */
+  int32_t dead_mode;   /* 0 none, 1 paralyzable, 2 non-paralyzable */
+  int32_t dead_level;  /* dead-time unit: 0 crystal, 1 module, 2 panel */
 } or_digitizer;
 
 typedef struct {
   uint32_t event, gid;
   double edep, energy, depth;
   uint64_t time_ps;
-  int32_t in_window;
+  int32_t in_window; /* blurred energy inside [e_lo, e_hi] */
+  int32_t lost;      /* dropped by the dead time of its unit */
 } or_single;
 
 void or_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, int64_t n);

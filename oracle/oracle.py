@@ -64,7 +64,8 @@ class Phantom(C.Structure):
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos", C.c_double * 3), ("dir", C.c_double * 3),
-                ("n_rods", C.c_int32), ("rods", C.POINTER(C.c_double)), ("duration_ps", C.c_uint64)]
+                ("n_rods", C.c_int32), ("rods", C.POINTER(C.c_double)), ("duration_ps", C.c_uint64),
+                ("acol_fwhm_deg", C.c_double), ("prange_fwhm_mm", C.c_double)]
 
 
 class Scene(C.Structure):
@@ -94,13 +95,15 @@ class Vertex(C.Structure):
 class Digitizer(C.Structure):
     _fields_ = [("fwhm_511", C.c_double), ("e_lo", C.c_double), ("e_hi", C.c_double),
                 ("window_ps", C.c_uint64), ("seed", C.c_uint64), ("instance", C.c_uint32),
-                ("doi_bins", C.c_int32), ("readout", C.c_int32)]
+                ("doi_bins", C.c_int32), ("readout", C.c_int32), ("time_fwhm_ps", C.c_double),
+                ("doi_fwhm_mm", C.c_double), ("dead_ps", C.c_uint64), ("dead_mode", C.c_int32),
+                ("dead_level", C.c_int32)]
 
 
 class Single(C.Structure):
     _fields_ = [("event", C.c_uint32), ("gid", C.c_uint32), ("edep", C.c_double),
                 ("energy", C.c_double), ("depth", C.c_double), ("time_ps", C.c_uint64),
-                ("in_window", C.c_int32)]
+                ("in_window", C.c_int32), ("lost", C.c_int32)]
 
 
 V_STEP, V_ENTER_PANEL, V_EXIT, V_ESCAPE, V_DEAD, V_ENTER_PHANTOM, V_EMIT = range(7)
@@ -234,6 +237,8 @@ class OracleScene:
             s.src.n_rods = len(rods)
             s.src.rods = _ptr(rods, C.c_double)
         s.src.duration_ps = int(src["duration_ps"])
+        s.src.acol_fwhm_deg = float(src.get("acolinearity_fwhm_deg", 0.0))
+        s.src.prange_fwhm_mm = float(src.get("positron_range_fwhm_mm", 0.0))
         rc = lib().or_prepare(C.byref(s))
         if rc != 0:
             raise ValueError(f"oracle scene rejected ({rc})")
@@ -312,11 +317,15 @@ class OracleScene:
         return np.frombuffer(buf, dtype=np.dtype(Vertex), count=n).copy()
 
     def digitize(self, hits, seed=0, fwhm_511=0.16, e_lo=350.0, e_hi=650.0, window_ps=3000,
-                 instance=0, readout=0):
-        """Adder, readout (0 crystal, 1 module, 2 panel), blur, window and
-        coincidence sorter; returns (singles, coincidence index pairs)."""
+                 instance=0, readout=0, time_fwhm_ps=0.0, doi_fwhm_mm=0.0, dead_ps=0, dead_mode=0,
+                 dead_level=1):
+        """Adder, readout (0 crystal, 1 module, 2 panel), energy / time / depth
+        blur, dead time (mode 0 none, 1 paralyzable, 2 non-paralyzable; level
+        as readout), window and coincidence sorter; returns (singles,
+        coincidence index pairs)."""
         hits = np.ascontiguousarray(hits)
-        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, 200, readout)
+        dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, 200, readout, time_fwhm_ps,
+                       doi_fwhm_mm, int(dead_ps), dead_mode, dead_level)
         n = len(hits)
         sg = (Single * max(1, n))()
         cc = np.empty((max(1, n), 2), np.uint32)
