@@ -176,6 +176,14 @@ gpet_status gpet_phantom_set(gpet_ctx *ctx, const gpet_phantom *phantom);
 /* (no positron range) sending photon A along +d and photon B along -d at     */
 /* 511 keV, d isotropic (BEAM: d fixed).  Event times are uniform on          */
 /* [0, duration_ps) (a fixed number of decays of a constant activity).       */
+/* Optional physics the paper leaves out (0 = off, the paper's setting):     */
+/*  acolinearity_fwhm_deg  photon B leaves at polar angle theta from -d,      */
+/*                         theta the length of a 2-D normal vector of this   */
+/*                         FWHM per component (0.5 deg in water), azimuth     */
+/*                         uniform;                                           */
+/*  positron_range_fwhm_mm the annihilation point is the emission point plus */
+/*                         a 3-D normal offset of this FWHM per axis (Sec. 4 */
+/*                         quotes 0.102 mm for 18F).                          */
 /* ---------------------------------------------------------------------- */
 #define GPET_SRC_POINT 0
 #define GPET_SRC_CYLINDERS 1 /* rods (cx, cy, radius, z0, z1), uniform activity density */
@@ -188,6 +196,8 @@ typedef struct {
   int32_t n_rods;     /* CYLINDERS: 1..GPET_MAX_RODS */
   const double *rods; /* host, n_rods x 5 */
   uint64_t duration_ps;
+  double acolinearity_fwhm_deg;  /* 0 .. 10 */
+  double positron_range_fwhm_mm; /* 0 .. 10 */
 } gpet_source;
 
 gpet_status gpet_source_set(gpet_ctx *ctx, const gpet_source *source);
@@ -238,6 +248,14 @@ gpet_status gpet_transport(gpet_ctx *ctx, uint64_t first_event, uint64_t n_event
 /*          energies summed, earliest time, crystal id and depth of the      */
 /*          largest deposit (the lower id on a tie);                         */
 /*  blur:   E + N(0,1) * fwhm_511 * sqrt(511 E) / 2.3548 (16 % at 511 keV);   */
+/*          optional time blur (timing resolution): t + rint(N(0,1) *        */
+/*          time_fwhm_ps / 2.3548), not below 0; optional depth blur (DOI    */
+/*          resolution): depth + N(0,1) * doi_fwhm_mm / 2.3548;              */
+/*  dead:   optional dead time per crystal, module or panel (dead_time_level)*/
+/*          over the blurred singles in (time, event, gid) order: a single is*/
+/*          lost when the previous single of its unit (paralyzable) or the   */
+/*          last one kept (non-paralyzable) came less than dead_time_ps      */
+/*          earlier; lost singles stay listed and enter no window;           */
 /*  window: e_lo <= blurred E <= e_hi;                                       */
 /*  sorter: windowed singles in (time, event, gid) order; a window of        */
 /*          window_ps (inclusive) opens at the earliest unused single and    */
@@ -261,9 +279,18 @@ typedef struct {
   uint32_t n_sweep;
   const double *sweep_lo_kev, *sweep_hi_kev;
   uint64_t *sweep_coincidences;
+  /* Detector response the paper leaves to analytic models (Sec. 4); 0 = off.
+   * Time deviate: words 2, 3 of the energy-blur Philox block; depth deviate:
+   * Philox counter (gid, event, instance, 6). */
+  double time_fwhm_ps;       /* 0 .. 1e6 */
+  double doi_fwhm_mm;        /* 0 .. 100 */
+  uint64_t dead_time_ps;
+  uint32_t dead_time_mode;   /* GPET_DEAD_NONE, _PARALYZABLE, _NONPARALYZABLE */
+  uint32_t dead_time_level;  /* GPET_READOUT_CRYSTAL, _MODULE or _PANEL */
 } gpet_digitizer;
 
 enum { GPET_READOUT_CRYSTAL = 0, GPET_READOUT_MODULE = 1, GPET_READOUT_PANEL = 2 };
+enum { GPET_DEAD_NONE = 0, GPET_DEAD_PARALYZABLE = 1, GPET_DEAD_NONPARALYZABLE = 2 };
 
 /* Singles in (instance, event, gid) order; at module or panel readout gid is
  * the crystal of the largest deposit and edep the readout unit's sum. */
@@ -273,11 +300,13 @@ typedef struct {
   float *energy_kev;  /* blurred */
   float *depth_mm;
   uint64_t *time_ps;
-  uint32_t *in_window;
+  uint32_t *in_window; /* bit 0: blurred energy inside the main window; bit 1:
+                          lost to dead time.  A single enters the coincidence
+                          sorter when in_window == 1 */
   uint32_t *instance; /* optional (may be NULL): instance index of the single */
   uint64_t capacity;
   uint64_t count;     /* out */
-  uint64_t windowed;  /* out: singles inside the (main) energy window */
+  uint64_t windowed;  /* out: singles inside the (main) energy window and not lost */
 } gpet_singles;
 
 /* Coincidences as index pairs into the singles arrays, earlier single first,

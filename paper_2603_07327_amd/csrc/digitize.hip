@@ -838,14 +838,16 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, co
                                               const uint32_t *s_inst, InstTab T, const float *s_edep,
                                               float *s_energy, uint32_t *s_win, uint32_t *wflag, uint32_t k0,
                                               uint32_t k1, float fwhm, float e_lo, float e_hi, uint32_t *spp,
-                                              uint32_t *spec, const unsigned long long *s_time,
-                                              unsigned long long *block_max) {
+                                              uint32_t *spec, unsigned long long *s_time, float time_sigma,
+                                              float *s_depth, float doi_sigma, unsigned long long *block_max) {
   __shared__ unsigned long long s_max[4];
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long tm = 0; // largest time stamp of all singles (every window's keys fit its width)
   if (i < n) {
-    // normal deviate by Box-Muller from the digitizer stream of (gid, event, instance)
-    const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], T.rng[s_inst[i]], 3u));
+    // normal deviates by Box-Muller from the digitizer stream of (gid, event,
+    // instance): words 0, 1 for the energy, 2, 3 for the time
+    const uint32_t rng = T.rng[s_inst[i]];
+    const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], rng, 3u));
     const float u0 = to_unit(w.x), u1 = to_unit(w.y);
     const float g = sqrtf(-2.0f * logf(u0)) * cos_rev(u1);
     const float E = s_edep[i];
@@ -858,6 +860,16 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, co
     if (spp && in) atomicAdd(&spp[s_gid[i]], 1u);
     if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
     tm = s_time[i];
+    if (time_sigma > 0.0f) { // timing resolution: rounded to the ps, not below 0
+      const float gt = sqrtf(-2.0f * logf(to_unit(w.z))) * cos_rev(to_unit(w.w));
+      const long long tb = (long long)tm + (long long)rintf(time_sigma * gt);
+      tm = tb > 0 ? (unsigned long long)tb : 0ull;
+      s_time[i] = tm;
+    }
+    if (doi_sigma > 0.0f) { // DOI resolution: stream 6 of (gid, event, instance)
+      const uint4 v = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], rng, 6u));
+      s_depth[i] += doi_sigma * (sqrtf(-2.0f * logf(to_unit(v.x))) * cos_rev(to_unit(v.y)));
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -947,11 +959,11 @@ __global__ void k_readout_copy(size_t n, const uint32_t *a_ev, const uint32_t *a
 }
 
 // energy window of a sweep on the blurred energies: flag and a copy to scan
-__global__ void k_window_flags(size_t n, const float *energy, float e_lo, float e_hi, uint32_t *flag,
-                               uint32_t *pos) {
+__global__ void k_window_flags(size_t n, const float *energy, const uint32_t *s_win, float e_lo, float e_hi,
+                               uint32_t *flag, uint32_t *pos) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t in = (energy[i] >= e_lo && energy[i] <= e_hi) ? 1u : 0u;
+  const uint32_t in = (energy[i] >= e_lo && energy[i] <= e_hi && !(s_win[i] & 2u)) ? 1u : 0u;
   flag[i] = in;
   pos[i] = in;
 }
@@ -959,7 +971,7 @@ __global__ void k_window_flags(size_t n, const float *energy, float e_lo, float 
 __global__ void k_time_keys(size_t n, const uint32_t *win, const uint32_t *pos, const unsigned long long *s_time,
                             const uint32_t *s_inst, int time_bits, unsigned long long *key, uint32_t *val) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !win[i] || pos[i] >= n) return;
+  if (i >= n || win[i] != 1u || pos[i] >= n) return; // in the window and not lost
   key[pos[i]] = time_bits < 64 ? ((unsigned long long)s_inst[i] << time_bits) | s_time[i] : s_time[i];
   val[pos[i]] = (uint32_t)i;
 }
@@ -1039,6 +1051,104 @@ __global__ void k_hit_tallies(size_t n, const uint32_t *gid, const float *depth,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dead time: the blurred singles in (instance, unit, time, index) order -- a
+// stable radix sort by time, then a stable one by (instance, unit) -- and
+// each unit's run scanned for losses.
+// ---------------------------------------------------------------------------
+__global__ void k_dead_time_keys(size_t n, const unsigned long long *s_time, unsigned long long *key,
+                                 uint32_t *val) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = s_time[i];
+  val[i] = (uint32_t)i;
+}
+
+// key of the single at sorted position p: (instance, unit); vin may alias vout
+__global__ void k_dead_unit_keys(size_t n, const uint32_t *vin, const uint32_t *s_gid, const uint32_t *s_inst,
+                                 const uint32_t *unit_size, int unit_bits, unsigned long long *kout,
+                                 uint32_t *vout) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t i = vin[p];
+  const uint32_t in = s_inst ? s_inst[i] : 0u;
+  kout[p] = ((unsigned long long)in << unit_bits) | (s_gid[i] / unit_size[in]);
+  vout[p] = i;
+}
+
+// paralyzable: lost when the previous single of the unit came less than tau earlier
+__global__ void k_dead_paralyzable(size_t n, const unsigned long long *key, const uint32_t *val,
+                                   const unsigned long long *s_time, unsigned long long tau, uint32_t *lost) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t i = val[p];
+  uint32_t l = 0u;
+  if (p > 0 && key[p] == key[p - 1]) l = s_time[i] - s_time[val[p - 1]] < tau ? 1u : 0u;
+  lost[i] = l;
+}
+
+__global__ void k_dead_heads(size_t n, const unsigned long long *key, uint32_t *head) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  head[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
+}
+
+// start of each unit's run (pos: exclusive scan of the head flags)
+__global__ void k_dead_starts(size_t n, const unsigned long long *key, const uint32_t *pos, uint32_t *start) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  if (p == 0 || key[p] != key[p - 1]) start[pos[p]] = (uint32_t)p;
+}
+
+// non-paralyzable: one wave per unit walks its run 64 singles at a time; the
+// chain of kept singles is resolved in scalar registers (a single is kept
+// when it comes tau or more after the last kept one)
+__global__ void __launch_bounds__(256) k_dead_nonparalyzable(uint32_t n_runs, const uint32_t *start, size_t n,
+                                                             const uint32_t *val,
+                                                             const unsigned long long *s_time,
+                                                             unsigned long long tau, uint32_t *lost) {
+  const uint32_t run = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (run >= n_runs) return; // whole waves leave together
+  const int lane = (int)__lane_id();
+  const size_t b = start[run], e = run + 1 < n_runs ? start[run + 1] : n;
+  unsigned long long last = 0;
+  bool have = false;
+  for (size_t base = b; base < e; base += 64) {
+    const size_t p = base + (size_t)lane;
+    const bool ok = p < e;
+    const uint32_t i = ok ? val[p] : 0u;
+    const unsigned long long t = ok ? s_time[i] : 0ull;
+    const int cnt = e - base < 64 ? (int)(e - base) : 64;
+    const uint32_t t_lo = (uint32_t)t, t_hi = (uint32_t)(t >> 32);
+    uint64_t keep = 0;
+    for (int l = 0; l < cnt; ++l) {
+      const unsigned long long tl = ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)t_hi, l) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)t_lo, l);
+      if (!have || tl - last >= tau) {
+        keep |= 1ull << l;
+        last = tl;
+        have = true;
+      }
+    }
+    if (ok) lost[i] = ((keep >> lane) & 1ull) ? 0u : 1u;
+  }
+}
+
+// lost singles leave the window (bit 1 of in_window); the in-window tallies
+// and the spectrum count what survives
+__global__ void k_dead_apply(size_t n, const uint32_t *lost, uint32_t *s_win, uint32_t *wflag, const uint32_t *s_gid,
+                             const float *s_energy, uint32_t *spp, uint32_t *spec) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t l = lost[i], in = s_win[i] & 1u;
+  s_win[i] = in | (l << 1);
+  wflag[i] = (in && !l) ? 1u : 0u;
+  if (l) return;
+  if (spp && in) atomicAdd(&spp[s_gid[i]], 1u);
+  const float Eb = s_energy[i];
+  if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
+}
+
 static inline unsigned grid_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1079,7 +1189,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
     scr.bytes = grow;
   }
-  const size_t pinned_bytes = 64 + 36 * ni;
+  const size_t pinned_bytes = 64 + 40 * ni;
   if (scr.pinned_bytes < pinned_bytes) {
     if (scr.pinned) (void)hipHostFree(scr.pinned);
     scr.pinned = nullptr;
@@ -1112,11 +1222,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   bb.big = (uint32_t *)take(max_buckets * 4);
   bb.n_big = (uint32_t *)take(8);
   bb.map = (uint32_t *)take(ni * 4 * 3);
-  uint32_t *d_tab = (uint32_t *)take(ni * 4 * 5); // first, n_events, cpp, rng, readout unit
+  uint32_t *d_tab = (uint32_t *)take(ni * 4 * 6); // first, n_events, cpp, rng, readout unit, dead-time unit
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
   // pinned host words: [0, 16) scalars that kernels write directly (scan
   // totals, maximum time, failure flags), [16, 16 + ni) per-instance counts,
-  // 3 ni words of bucket-map uploads, 5 ni words of instance table
+  // 3 ni words of bucket-map uploads, 6 ni words of instance table
   uint32_t *rb = (uint32_t *)scr.pinned;
   uint32_t *rb_count = rb + 16;
   bb.pinned_flag = rb + 12;
@@ -1140,8 +1250,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     tab[4 * ni + i] = D.readout == GPET_READOUT_MODULE ? std::max(1u, D.cpm[i])
                       : D.readout == GPET_READOUT_PANEL ? std::max(1u, D.cpp[i])
                                                         : 1u;
+    tab[5 * ni + i] = D.dead_level == GPET_READOUT_MODULE ? std::max(1u, D.cpm[i])
+                      : D.dead_level == GPET_READOUT_PANEL ? std::max(1u, D.cpp[i])
+                                                           : 1u;
   }
-  (void)hipMemcpyAsync(d_tab, tab, ni * 20, hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(d_tab, tab, ni * 24, hipMemcpyHostToDevice, st);
   const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, (uint32_t)ni};
   uint32_t max_events = 1;
   for (size_t i = 0; i < ni; ++i) max_events = std::max(max_events, D.n_events[i]);
@@ -1239,13 +1352,49 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                        (unsigned long long *)S->time_ps, s_inst, S->instance);
   }
   // 3. blur + window; per-block maxima of the time stamps go to the (now
-  //    free) second key array, then one block reduces them
+  //    free) second key array, then one block reduces them.  With dead time
+  //    the tallies wait until the losses are known.
+  const bool dead = D.dead_mode != GPET_DEAD_NONE && ns > 0;
+  unsigned long long *s_time = (unsigned long long *)S->time_ps;
   hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
                      S->edep_kev, S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
-                     T ? T->singles_per_crystal : nullptr, T ? T->energy_spectrum : nullptr,
-                     (const unsigned long long *)S->time_ps, sb.k1);
+                     (T && !dead) ? T->singles_per_crystal : nullptr, (T && !dead) ? T->energy_spectrum : nullptr,
+                     s_time, D.time_sigma, S->depth_mm, D.doi_sigma, sb.k1);
   hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
                      (size_t)grid_for(ns), (unsigned long long *)(rb + 4));
+  if (dead) {
+    // 3b. dead time per unit (free here: the key/value pairs, flag, wpos)
+    if (!sync("after the blur")) return GPET_ERR_HIP;
+    const unsigned long long tm = (unsigned long long)rb[4] | ((unsigned long long)rb[5] << 32);
+    int tbits = 1;
+    while (tbits < 64 && (tm >> tbits) != 0) ++tbits;
+    hipLaunchKernelGGL(k_dead_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns,
+                       (const unsigned long long *)s_time, sb.k0, sb.v0);
+    const bool f1 = radix_sort(sb, ns, tbits, st);
+    const int unit_bits = D.gid_bits;
+    hipLaunchKernelGGL(k_dead_unit_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, f1 ? sb.v1 : sb.v0,
+                       S->gid, ni > 1 ? s_inst : nullptr, d_tab + 5 * ni, unit_bits, sb.k0, sb.v0);
+    const bool f2 = radix_sort(sb, ns, unit_bits + inst_bits, st);
+    const unsigned long long *uk = f2 ? sb.k1 : sb.k0;
+    const uint32_t *uv = f2 ? sb.v1 : sb.v0;
+    uint32_t *lost = flag;
+    if (D.dead_mode == GPET_DEAD_PARALYZABLE) {
+      hipLaunchKernelGGL(k_dead_paralyzable, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uk, uv,
+                         (const unsigned long long *)s_time, D.dead_ps, lost);
+    } else {
+      uint32_t *start = f2 ? sb.v0 : sb.v1; // the free value array
+      hipLaunchKernelGGL(k_dead_heads, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uk, wpos);
+      exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 6);
+      hipLaunchKernelGGL(k_dead_starts, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uk, wpos, start);
+      if (!sync("in the dead time")) return GPET_ERR_HIP;
+      const uint32_t n_runs = rb[6];
+      hipLaunchKernelGGL(k_dead_nonparalyzable, dim3((n_runs + 3) / 4), dim3(256), 0, st, n_runs, start,
+                         (size_t)ns, uv, (const unsigned long long *)s_time, D.dead_ps, lost);
+    }
+    hipLaunchKernelGGL(k_dead_apply, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, lost, S->in_window, wpos,
+                       S->gid, S->energy_kev, T ? T->singles_per_crystal : nullptr,
+                       T ? T->energy_spectrum : nullptr);
+  }
   exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
   if (!sync("after the energy window")) return GPET_ERR_HIP;
   const size_t nw = rb[3];
@@ -1357,7 +1506,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   for (size_t w = 0; w < n_sweep; ++w) {
     auto make_flags = [&]() {
       hipLaunchKernelGGL(k_window_flags, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->energy_kev,
-                         D.sweep_lo[w], D.sweep_hi[w], flag, wpos);
+                         S->in_window, D.sweep_lo[w], D.sweep_hi[w], flag, wpos);
       exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
     };
     make_flags();

@@ -314,6 +314,13 @@ gpet_status build_source(gpet_ctx *c, const gpet_source *src, DevScene &S, std::
   S.bdy = (float)src->dir[1];
   S.bdz = (float)src->dir[2];
   S.duration_ps = src->duration_ps;
+  if (!(src->acolinearity_fwhm_deg >= 0.0 && src->acolinearity_fwhm_deg <= 10.0))
+    return fail(c, GPET_ERR_ARG, who + "acollinearity FWHM must lie in [0, 10] degrees");
+  if (!(src->positron_range_fwhm_mm >= 0.0 && src->positron_range_fwhm_mm <= 10.0))
+    return fail(c, GPET_ERR_ARG, who + "positron range FWHM must lie in [0, 10] mm");
+  const double fwhm_per_sigma = 2.354820045030949; // 2 sqrt(2 ln 2)
+  S.acol_sigma = (float)(src->acolinearity_fwhm_deg * (3.14159265358979323846 / 180.0) / fwhm_per_sigma);
+  S.prange_sigma = (float)(src->positron_range_fwhm_mm / fwhm_per_sigma);
   return GPET_OK;
 }
 
@@ -713,6 +720,18 @@ static gpet_status digitizer_params(gpet_ctx *c, const gpet_hits *h, const gpet_
     }
     D.sweep_out = p->sweep_coincidences;
   }
+  if (!(p->time_fwhm_ps >= 0.0 && p->time_fwhm_ps <= 1e6))
+    return fail(c, GPET_ERR_ARG, "digitize: timing resolution must lie in [0, 1e6] ps");
+  if (!(p->doi_fwhm_mm >= 0.0 && p->doi_fwhm_mm <= 100.0))
+    return fail(c, GPET_ERR_ARG, "digitize: DOI resolution must lie in [0, 100] mm");
+  if (p->dead_time_mode > GPET_DEAD_NONPARALYZABLE) return fail(c, GPET_ERR_ARG, "digitize: unknown dead-time mode");
+  if (p->dead_time_level > GPET_READOUT_PANEL) return fail(c, GPET_ERR_ARG, "digitize: unknown dead-time level");
+  const double fwhm_per_sigma = 2.354820045030949; // 2 sqrt(2 ln 2)
+  D.time_sigma = (float)(p->time_fwhm_ps / fwhm_per_sigma);
+  D.doi_sigma = (float)(p->doi_fwhm_mm / fwhm_per_sigma);
+  D.dead_mode = p->dead_time_ps ? p->dead_time_mode : (uint32_t)GPET_DEAD_NONE;
+  D.dead_level = p->dead_time_level;
+  D.dead_ps = p->dead_time_ps;
   D.singles = sg;
   D.coinc = cc;
   return GPET_OK;

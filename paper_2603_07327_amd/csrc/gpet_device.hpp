@@ -97,6 +97,8 @@ struct DevScene {
   const float *rod_cum; // cumulative rod weights
   float rod_total;
   unsigned long long duration_ps;
+  float acol_sigma;   // acollinearity: sigma of each transverse angle component (rad), 0 = off
+  float prange_sigma; // positron range: sigma of each offset component (mm), 0 = off
 };
 
 // ---------------------------------------------------------------------------
@@ -438,10 +440,9 @@ __device__ __forceinline__ float thomson(float u) {
   return cbrtf(q + s) + cbrtf(q - s);
 }
 
-// Direction update for polar cosine c and azimuth 2*pi*u_phi about the old
-// direction (the reference axis for phi is fixed by the old direction).
-__device__ __forceinline__ void rotate(Vec &d, float c, float u_phi) {
-  const float st = hw_sqrt(fmaxf(0.0f, 1.0f - c * c));
+// Direction update for polar cosine c (sine st) and azimuth 2*pi*u_phi about
+// the old direction (the reference axis for phi is fixed by the old direction).
+__device__ __forceinline__ void rotate_cs(Vec &d, float c, float st, float u_phi) {
   const float sp = sin_rev(u_phi), cp = cos_rev(u_phi);
   const float s2 = d.x * d.x + d.y * d.y;
   Vec n;
@@ -455,6 +456,9 @@ __device__ __forceinline__ void rotate(Vec &d, float c, float u_phi) {
   }
   const float inn = rsq(n.x * n.x + n.y * n.y + n.z * n.z);
   d = Vec{n.x * inn, n.y * inn, n.z * inn};
+}
+__device__ __forceinline__ void rotate(Vec &d, float c, float u_phi) {
+  rotate_cs(d, c, hw_sqrt(fmaxf(0.0f, 1.0f - c * c)), u_phi);
 }
 
 // process of a real collision: 1 photoelectric, 2 Compton, 3 Rayleigh

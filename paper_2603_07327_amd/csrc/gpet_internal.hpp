@@ -121,6 +121,11 @@ struct DigitizeArgs {
   unsigned long long window_ps = 0;
   uint32_t k0 = 0, k1 = 0;
   float panel_depth = 0.f;
+  // detector response options: time and depth blur sigmas (ps, mm; 0 = off),
+  // dead time (GPET_DEAD_*, unit level GPET_READOUT_*, length in ps)
+  float time_sigma = 0.f, doi_sigma = 0.f;
+  uint32_t dead_mode = 0, dead_level = 0;
+  unsigned long long dead_ps = 0;
   // outputs
   gpet_singles *singles = nullptr;
   gpet_coincidences *coinc = nullptr;

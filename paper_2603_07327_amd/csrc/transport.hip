@@ -290,8 +290,11 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       if (S.src_kind == 2) sdir = Vec{S.bdx, S.bdy, S.bdz};
       if (S.src_kind == 1) {
         phase = P_EMIT_POS;
+      } else if (S.prange_sigma > 0.0f) {
+        phase = P_EMIT_RANGE; // block 1 is not needed
+        n = 3;
       } else {
-        phase = P_EMIT_TIME; // block 1 is not needed
+        phase = P_EMIT_TIME; // blocks 1 and 3 are not needed
         n = 2;
       }
     } else if (phase == P_EMIT_POS) {
@@ -302,12 +305,25 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       const float *rd = S.rods + 5 * i;
       const float rr = rd[2] * hw_sqrt(q_u1);
       src = Vec{rd[0] + rr * cos_rev(r.x), rd[1] + rr * sin_rev(r.x), rd[3] + r.y * (rd[4] - rd[3])};
+      if (S.prange_sigma > 0.0f) {
+        phase = P_EMIT_RANGE;
+        n = 3;
+      } else {
+        phase = P_EMIT_TIME;
+      }
+    } else if (phase == P_EMIT_RANGE) {
+      // block 3: the annihilation point
+      src = positron_offset(S, src, r);
       phase = P_EMIT_TIME;
+      n = 2;
     } else if (phase == P_EMIT_TIME) {
-      // block 2: event time uniform on [0, T) from the raw 64-bit word
+      // block 2: event time uniform on [0, T) from the raw 64-bit word; photon
+      // A starts along sdir, photon B will start along -sdir
       t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
       emitted = true;
+      const Vec bdir = photon_b_dir(S, sdir, r.z, r.w);
       start_photon(S, 0);
+      sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
     } else if (phase == P_PHANTOM) {
       const Lerp lp = lerp_at(e);
       const float mb = lerp1(S.maj_ph, lp);

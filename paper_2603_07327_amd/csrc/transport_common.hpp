@@ -5,10 +5,39 @@
 
 namespace gpet {
 
+// emission runs event-stream blocks 0 (direction), 1 (rod point), 3 (positron
+// range) and 2 (time, acollinearity), each phase drawing one block
 enum : int {
-  P_FETCH = 0, P_EMIT_DIR = 1, P_EMIT_POS = 2, P_EMIT_TIME = 3, P_PHANTOM = 4, P_SEARCH = 5,
-  P_PANEL = 6, P_KAHN = 7, P_RAYLEIGH = 8, P_DONE = 9
+  P_FETCH = 0, P_EMIT_DIR = 1, P_EMIT_POS = 2, P_EMIT_RANGE = 3, P_EMIT_TIME = 4, P_PHANTOM = 5,
+  P_SEARCH = 6, P_PANEL = 7, P_KAHN = 8, P_RAYLEIGH = 9, P_DONE = 10
 };
+
+// photon B's direction: -d, turned by the acollinearity angle when it is on
+// (theta from words 2, 3 of event block 2 as the length of a 2-D normal
+// vector, azimuth uniform)
+template <class SC> __device__ __forceinline__ Vec photon_b_dir(SC &S, Vec d, float u_len, float u_phi) {
+  Vec b{-d.x, -d.y, -d.z};
+  if (S.acol_sigma > 0.0f) {
+    // theta stays below 6 sigma (sigma <= 10 deg / 2.355): the Taylor series
+    // of sin and cos to theta^9 and theta^10 are exact to float rounding there
+    const float th = S.acol_sigma * hw_sqrt(2.0f * neg_ln(u_len)), t2 = th * th;
+    const float sn =
+        th * (1.0f + t2 * (-1.0f / 6.0f + t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f + t2 * (1.0f / 362880.0f)))));
+    const float cs =
+        1.0f + t2 * (-0.5f + t2 * (1.0f / 24.0f + t2 * (-1.0f / 720.0f + t2 * (1.0f / 40320.0f +
+                                                                                  t2 * (-1.0f / 3628800.0f)))));
+    rotate_cs(b, cs, sn, u_phi);
+  }
+  return b;
+}
+
+// positron range: the emission point plus a normal offset per axis (event
+// block 3, two Box-Muller pairs)
+template <class SC> __device__ __forceinline__ Vec positron_offset(SC &S, Vec x, float4 r) {
+  const float a = S.prange_sigma * hw_sqrt(2.0f * neg_ln(r.x));
+  const float b = S.prange_sigma * hw_sqrt(2.0f * neg_ln(r.z));
+  return Vec{x.x + a * cos_rev(r.y), x.y + a * sin_rev(r.y), x.z + b * cos_rev(r.w)};
+}
 enum : int { V_STEP = 0, V_ENTER_PANEL = 1, V_EXIT = 2, V_ESCAPE = 3, V_DEAD = 4, V_ENTER_PHANTOM = 5,
              V_EMIT = 6 };
 

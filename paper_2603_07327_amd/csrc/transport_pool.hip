@@ -246,8 +246,11 @@ __global__ void __launch_bounds__(kBlock) k_transport_pool(RunArgs A) {
       if (S.src_kind == 2) d = Vec{S.bdx, S.bdy, S.bdz};
       if (S.src_kind == 1) {
         phase = P_EMIT_POS;
+      } else if (S.prange_sigma > 0.0f) {
+        phase = P_EMIT_RANGE; // block 1 is not needed
+        n = 3;
       } else {
-        phase = P_EMIT_TIME; // block 1 is not needed
+        phase = P_EMIT_TIME; // blocks 1 and 3 are not needed
         n = 2;
       }
     } else if (best == P_EMIT_POS) {
@@ -258,16 +261,26 @@ __global__ void __launch_bounds__(kBlock) k_transport_pool(RunArgs A) {
       const float *rd = S.rods + 5 * i;
       const float rr = rd[2] * hw_sqrt(L);
       x = Vec{rd[0] + rr * cos_rev(r.x), rd[1] + rr * sin_rev(r.x), rd[3] + r.y * (rd[4] - rd[3])};
+      if (S.prange_sigma > 0.0f) {
+        phase = P_EMIT_RANGE;
+        n = 3;
+      } else {
+        phase = P_EMIT_TIME;
+      }
+    } else if (best == P_EMIT_RANGE) {
+      // block 3: the annihilation point
+      x = positron_offset(S, x, r);
       phase = P_EMIT_TIME;
+      n = 2;
     } else if (best == P_EMIT_TIME) {
       // block 2: event time uniform on [0, T) from the raw 64-bit word; both
       // photons start (A here along +d, B in the pair's other slot along -d)
       t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
       emitted = true;
-      const Vec src = x, sdir = d;
+      const Vec src = x, sdir = d, bdir = photon_b_dir(S, d, r.z, r.w);
 #pragma unroll
       for (int which = 0; which < 2; ++which) {
-        Vec xs = src, ds = which ? Vec{-sdir.x, -sdir.y, -sdir.z} : sdir;
+        Vec xs = src, ds = which ? bdir : sdir;
         float Ls = 0.0f;
         int p0 = P_SEARCH;
         if (S.has_phantom) {

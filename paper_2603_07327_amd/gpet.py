@@ -74,7 +74,8 @@ class Phantom(C.Structure):
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos_mm", C.c_double * 3), ("dir", C.c_double * 3),
-                ("n_rods", C.c_int32), ("rods", C.POINTER(C.c_double)), ("duration_ps", C.c_uint64)]
+                ("n_rods", C.c_int32), ("rods", C.POINTER(C.c_double)), ("duration_ps", C.c_uint64),
+                ("acolinearity_fwhm_deg", C.c_double), ("positron_range_fwhm_mm", C.c_double)]
 
 
 class Hits(C.Structure):
@@ -92,20 +93,32 @@ class Digitizer(C.Structure):
                 ("window_ps", C.c_uint64), ("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("first_event", C.c_uint64), ("n_events", C.c_uint64), ("readout", C.c_uint32),
                 ("n_sweep", C.c_uint32), ("sweep_lo_kev", C.c_void_p), ("sweep_hi_kev", C.c_void_p),
-                ("sweep_coincidences", C.c_void_p)]
+                ("sweep_coincidences", C.c_void_p), ("time_fwhm_ps", C.c_double), ("doi_fwhm_mm", C.c_double),
+                ("dead_time_ps", C.c_uint64), ("dead_time_mode", C.c_uint32), ("dead_time_level", C.c_uint32)]
 
 
 READOUT = {"crystal": 0, "module": 1, "panel": 2}
+DEAD_TIME = {"none": 0, "paralyzable": 1, "nonparalyzable": 2}
 
 
 def _readout_code(readout) -> int:
     return READOUT[readout] if isinstance(readout, str) else int(readout)
 
 
-def _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events, readout, sweep):
+def _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events, readout, sweep, response=None):
     """The parameter struct plus the host arrays its sweep pointers refer to
-    (kept alive by the caller for the duration of the call)."""
+    (kept alive by the caller for the duration of the call).  response: dict of
+    the optional detector response -- time_fwhm_ps, doi_fwhm_mm, dead_time_ps,
+    dead_time_mode ("paralyzable" / "nonparalyzable"), dead_time_level
+    ("crystal" / "module" / "panel")."""
     dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events, _readout_code(readout))
+    r = response or {}
+    dg.time_fwhm_ps = float(r.get("time_fwhm_ps", 0.0))
+    dg.doi_fwhm_mm = float(r.get("doi_fwhm_mm", 0.0))
+    dg.dead_time_ps = int(r.get("dead_time_ps", 0))
+    mode = r.get("dead_time_mode", "none")
+    dg.dead_time_mode = DEAD_TIME[mode] if isinstance(mode, str) else int(mode)
+    dg.dead_time_level = _readout_code(r.get("dead_time_level", "module"))
     keep = None
     if sweep:
         lo = np.ascontiguousarray([w[0] for w in sweep], np.float64)
@@ -345,6 +358,8 @@ def pack_source(src: dict):
         s.n_rods = len(keep)
         s.rods = keep.ctypes.data_as(C.POINTER(C.c_double))
     s.duration_ps = int(src["duration_ps"])
+    s.acolinearity_fwhm_deg = float(src.get("acolinearity_fwhm_deg", 0.0))
+    s.positron_range_fwhm_mm = float(src.get("positron_range_fwhm_mm", 0.0))
     return s, keep
 
 
@@ -483,13 +498,15 @@ class Context:
                           self._empty(capacity, t.int32) if instance else None)
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
-                      e_hi=650.0, window_ps=3000, instance=0, tallies=None, readout="crystal", sweep=None):
+                      e_hi=650.0, window_ps=3000, instance=0, tallies=None, readout="crystal", sweep=None,
+                      response=None):
         """Digitize into preallocated outputs; returns (status, coincidences) or,
         with sweep = [(e_lo, e_hi), ...], (status, coincidences, counts of the
-        sweep windows).  readout: "crystal", "module" or "panel"."""
+        sweep windows).  readout: "crystal", "module" or "panel"; response: the
+        optional time / DOI blur and dead time (see _digitizer)."""
         h = hits.struct()
         dg, keep = _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, hits.first_event,
-                              max(1, hits.n_events), readout, sweep)
+                              max(1, hits.n_events), readout, sweep, response)
         counts = np.zeros(len(sweep) if sweep else 0, np.uint64)
         if sweep:
             dg.sweep_coincidences = counts.ctypes.data
@@ -758,11 +775,11 @@ class Batch:
         return rc, {n: int(getattr(st, n)) for n in STAT_NAMES}
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
-                      e_hi=650.0, window_ps=3000, readout="crystal", sweep=None):
+                      e_hi=650.0, window_ps=3000, readout="crystal", sweep=None, response=None):
         """Returns (status, coincidence count, coincidences per instance) and,
         with sweep = [(e_lo, e_hi), ...], the sweep counts [window][instance]."""
         h = hits.struct()
-        dg, keep = _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, 0, 0, 1, readout, sweep)
+        dg, keep = _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, 0, 0, 1, readout, sweep, response)
         counts = np.zeros((len(sweep) if sweep else 0, self.n), np.uint64)
         if sweep:
             dg.sweep_coincidences = counts.ctypes.data

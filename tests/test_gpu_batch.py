@@ -224,9 +224,15 @@ def test_batch_graph_replays_match_eager(ctxs):
     b.close()
 
 
-def test_batch_readout_and_sweep_match_plain(ctxs):
-    """Module readout and a three-window sweep in one batched pass: every
-    instance's singles and counts equal its plain run's."""
+RESPONSE = {"time_fwhm_ps": 500.0, "doi_fwhm_mm": 2.0, "dead_time_ps": 100_000_000,
+            "dead_time_mode": "nonparalyzable", "dead_time_level": "module"}
+
+
+@pytest.mark.parametrize("response", [None, RESPONSE], ids=["plain", "response"])
+def test_batch_readout_and_sweep_match_plain(ctxs, response):
+    """Module readout and a three-window sweep in one batched pass (and with
+    time / DOI blur and a 100 us dead time per module): every instance's
+    singles and counts equal its plain run's."""
     from paper_2603_07327_amd.gpet import Batch
     cb, cp = ctxs
     inst = _instances()
@@ -237,13 +243,16 @@ def test_batch_readout_and_sweep_match_plain(ctxs):
     seed = 31
     sweep = [(150.0, 700.0), (350.0, 700.0), (450.0, 700.0)]
     hits, _ = b.transport(seed=seed)
-    sg, (ca, _), per, counts = b.digitize(hits, seed=seed + 1, readout="module", sweep=sweep)
+    sg, (ca, _), per, counts = b.digitize(hits, seed=seed + 1, readout="module", sweep=sweep, response=response)
     s = sg.numpy()
     assert counts.shape == (len(sweep), len(inst))
+    if response:
+        assert np.count_nonzero(s["in_window"].view(np.uint32) & 2) > 0
     for i, d in enumerate(inst):
         cp.set_scene(d["scene"])
         ph, _ = cp.transport(d["n_events"], seed=seed, first=d["first_event"], instance=d["instance"])
-        ps, (qa, _), pc = cp.digitize(ph, seed=seed + 1, instance=d["instance"], readout="module", sweep=sweep)
+        ps, (qa, _), pc = cp.digitize(ph, seed=seed + 1, instance=d["instance"], readout="module", sweep=sweep,
+                                      response=response)
         rs = ps.numpy()
         sel = s["instance"] == i
         for k in rs:

@@ -1,0 +1,219 @@
+"""GPU parity of the optional physics against the FP64 oracle: acollinearity
+and positron range in the transport (RNG-matched histories, and the photon
+pool schedule against the lane kernel), timing / DOI resolution and dead
+time in the digitizer (the same hits through both, crafted cases exactly).
+
+Bars: discrete history steps identical and positions / energies within
+1e-5 relative (as for the plain transport); blurred times within 1 ps (the
+rounding of a float and a double deviate can differ by one near a half);
+depths within 1e-4 mm; lost flags and coincidences identical except where a
+time within 1 ps of a dead-time or window edge decides them.
+"""
+import numpy as np
+import pytest
+
+import gpet_inputs as G
+from tests.gpu_util import compare_histories
+
+pytestmark = pytest.mark.gpu
+
+EXT = {"acolinearity_fwhm_deg": 0.5, "positron_range_fwhm_mm": 0.5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _with_source(sc, **kw):
+    sc = dict(sc)
+    sc["source"] = dict(sc["source"])
+    sc["source"].update(kw)
+    return sc
+
+
+@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom"])
+def test_matched_histories_with_source_physics(ctx, oracle_mod, case):
+    if case == "ring8":
+        sc, n = G.ring8_scene(n_events=5000), 5000
+    elif case == "C":
+        sc, n = G.small_animal_scene("C", (2.0, -1.0, 3.0), n_events=5000), 5000
+    else:
+        sc, n = G.hot_rod_scene(n_events=3000), 3000
+    sc = _with_source(sc, acolinearity_fwhm_deg=3.0, positron_range_fwhm_mm=2.0)
+    ctx.set_scene(sc)
+    o = oracle_mod.OracleScene(sc)
+    vo = o.trace(n, seed=3)
+    vg = ctx.trace(n, seed=3)
+    n_ph, n_div, wp, we, fails = compare_histories(vg, vo, o.poses())
+    print(f"{case}: {n_ph} photons, {n_div} diverged, worst pos {wp:.2e}, worst E {we:.2e}")
+    assert not fails, fails[:5]
+    assert n_div <= 0.01 * n_ph
+    # the emission vertices carry the effects: B not opposite A, both at one point off the source
+    em = vg[vg["kind"] == 6]
+    a, b = em[em["photon"] == 0], em[em["photon"] == 1]
+    a = a[np.argsort(a["event"])]
+    b = b[np.argsort(b["event"])]
+    da = np.stack([a["dx"], a["dy"], a["dz"]], 1)
+    db = np.stack([b["dx"], b["dy"], b["dz"]], 1)
+    dev = np.degrees(np.arccos(np.clip(-np.sum(da * db, 1), -1, 1)))
+    assert 0.5 < np.median(dev) < 5.0
+    assert np.array_equal(np.stack([a["x"], a["y"], a["z"]], 1), np.stack([b["x"], b["y"], b["z"]], 1))
+
+
+def test_pool_schedule_with_source_physics(ctx):
+    """The photon-pool kernel draws the same emission blocks as the lane kernel."""
+    n = 40_000
+    ctx.set_scene(_with_source(G.hot_rod_scene(n_events=n), **EXT))
+
+    def canon(h):
+        g = h.numpy()
+        key = np.lexsort((g["aux"], g["gid"], g["event"]))
+        return {k: v[key] for k, v in g.items()}
+    out = []
+    for shape in [(0, 16, 0), (0, 16, 2)]:
+        ctx.set_launch(*shape)
+        h, st = ctx.transport(n, seed=8)
+        out.append((canon(h), st["steps"]))
+    ctx.set_launch(0, 32, 0)
+    for k in out[0][0]:
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert out[0][1] == out[1][1]
+
+
+def test_source_physics_rejects_bad_values(ctx):
+    from paper_2603_07327_amd.gpet import GpetError
+    sc = G.ring8_scene(n_events=100)
+    for kw in ({"acolinearity_fwhm_deg": -1.0}, {"acolinearity_fwhm_deg": 11.0},
+               {"positron_range_fwhm_mm": float("nan")}, {"positron_range_fwhm_mm": 20.0}):
+        with pytest.raises(GpetError):
+            ctx.set_scene(_with_source(sc, **kw))
+
+
+def _hits_as_oracle(oracle_mod, g):
+    h = np.zeros(len(g["event"]), dtype=np.dtype(oracle_mod.Hit))
+    h["event"] = g["event"].view(np.uint32)
+    h["gid"] = g["gid"].view(np.uint32)
+    h["edep"] = g["edep_kev"]
+    h["depth"] = g["depth_mm"]
+    h["time_ps"] = g["time_ps"].view(np.uint64)
+    h["photon"] = g["aux"].view(np.uint32) & 1
+    h["seq"] = g["aux"].view(np.uint32) >> 8
+    return h
+
+
+LEVELS = {"crystal": 0, "module": 1, "panel": 2}
+MODES = {"paralyzable": 1, "nonparalyzable": 2}
+
+
+@pytest.mark.parametrize("mode,level,readout", [("paralyzable", "module", "crystal"),
+                                                ("nonparalyzable", "module", "crystal"),
+                                                ("nonparalyzable", "crystal", "crystal"),
+                                                ("nonparalyzable", "panel", "module"),
+                                                ("paralyzable", "panel", "panel")])
+def test_response_on_identical_hits(ctx, oracle_mod, mode, level, readout):
+    """Time and DOI blur plus dead time on the same transported hits; the
+    acquisition is compressed to 0.2 ms so that units are busy."""
+    n = 200_000
+    sc = _with_source(G.small_animal_scene("C", n_events=n), duration_ps=200_000_000)
+    ctx.set_scene(sc)
+    o = oracle_mod.OracleScene(sc)
+    hits, _ = ctx.transport(n, seed=5)
+    # a few per cent to a third of the singles lost: units see about 3, 80
+    # and 300 singles per 200 us at crystal, module and panel level
+    tau = {"crystal": 5_000_000, "module": 30_000, "panel": 5_000}[level]
+    resp = {"time_fwhm_ps": 400.0, "doi_fwhm_mm": 2.0, "dead_time_ps": tau, "dead_time_mode": mode,
+            "dead_time_level": level}
+    sg, (ca, cb) = ctx.digitize(hits, seed=6, readout=readout, response=resp)
+    so, co = o.digitize(_hits_as_oracle(oracle_mod, hits.numpy()), seed=6, readout=LEVELS[readout],
+                        time_fwhm_ps=400.0, doi_fwhm_mm=2.0, dead_ps=tau, dead_mode=MODES[mode],
+                        dead_level=LEVELS[level])
+    s = sg.numpy()
+    assert len(s["event"]) == len(so)
+    assert np.array_equal(s["event"].view(np.uint32), so["event"])
+    assert np.array_equal(s["gid"].view(np.uint32), so["gid"])
+    dt = s["time_ps"].view(np.int64) - so["time_ps"].astype(np.int64)
+    assert np.all(np.abs(dt) <= 1), np.abs(dt).max()
+    n_dt = int(np.count_nonzero(dt))
+    assert n_dt <= 1e-3 * len(so) + 5
+    np.testing.assert_allclose(s["depth_mm"], so["depth"], rtol=0, atol=1e-4)
+    np.testing.assert_allclose(s["energy_kev"], so["energy"], rtol=1e-5, atol=1e-3)
+    lost_g = (s["in_window"].view(np.uint32) >> 1) & 1
+    edge = (np.abs(so["energy"] - 350) < 1e-2) | (np.abs(so["energy"] - 650) < 1e-2)
+    # a dead-time decision moves only where a blurred time differs: each such
+    # single can flip its own state and the chain after it in its unit
+    n_lost_diff = int(np.count_nonzero(lost_g != so["lost"]))
+    print(f"{mode}/{level}/{readout}: singles {len(so)}, lost {int(so['lost'].sum())}, "
+          f"times off by 1 ps {n_dt}, lost flags differing {n_lost_diff}, coinc {len(co)}")
+    assert so["lost"].sum() > 0.02 * len(so)
+    assert n_lost_diff <= 20 * n_dt
+    win_g = s["in_window"].view(np.uint32) == 1
+    win_o = (so["in_window"] != 0) & (so["lost"] == 0)
+    same = (lost_g == so["lost"]) & ~edge
+    assert np.array_equal(win_g[same], win_o[same])
+    assert s["in_window"].view(np.uint32).sum() > 0
+    got = set(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
+    ref = set(map(tuple, co.tolist()))
+    assert len(got ^ ref) <= 4 * (int(edge.sum()) + n_lost_diff + n_dt)
+    assert len(ref) > 500
+
+
+def test_response_off_changes_nothing(ctx):
+    n = 50_000
+    ctx.set_scene(G.small_animal_scene("C", n_events=n))
+    hits, _ = ctx.transport(n, seed=9)
+    s0, c0 = ctx.digitize(hits, seed=3)
+    s1, c1 = ctx.digitize(hits, seed=3, response={"time_fwhm_ps": 0.0, "doi_fwhm_mm": 0.0, "dead_time_ps": 0,
+                                                  "dead_time_mode": "paralyzable"})
+    a, b = s0.numpy(), s1.numpy()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(c0[0].cpu().numpy(), c1[0].cpu().numpy())
+
+
+def _hitlist(ctx, ev, gid, edep, time_ps, first, n_events):
+    import torch
+    from paper_2603_07327_amd.gpet import HitList
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(ctx.dev)  # noqa: E731
+    n = len(ev)
+    return HitList(t(np.asarray(ev, np.uint32).view(np.int32), np.int32),
+                   t(np.asarray(gid, np.uint32).view(np.int32), np.int32), t(edep, np.float32),
+                   t(np.zeros(n), np.float32), t(np.asarray(time_ps, np.int64), np.int64),
+                   t(np.zeros(n, np.int32), np.int32), n, first, n_events)
+
+
+@pytest.mark.parametrize("tau,mode,lost,n_coinc", [(15000, "paralyzable", [0, 0, 0, 0, 1, 1], 2),
+                                                   (20000, "paralyzable", [0, 0, 0, 0, 1, 1], 2),
+                                                   (20000, "nonparalyzable", [0, 0, 0, 0, 1, 1], 2),
+                                                   (25000, "paralyzable", [0, 0, 1, 1, 1, 1], 1),
+                                                   (25000, "nonparalyzable", [0, 0, 1, 1, 0, 0], 2)])
+def test_dead_time_crafted(ctx, oracle_mod, tau, mode, lost, n_coinc):
+    """Three events with one pair each in panels 0 and 6 at 0, 20 and 30 ns,
+    panel-level dead time: the same losses as the oracle's worked cases (a gap
+    of exactly the dead time is not dead)."""
+    sc = G.small_animal_scene("C", n_events=10)
+    ctx.set_scene(sc)
+    cpp = ctx.info.crystals_per_panel
+    ev = [0, 0, 1, 1, 2, 2]
+    gid = [5, 6 * cpp + 5, 900, 6 * cpp + 900, 7, 6 * cpp + 7]
+    t = [0, 0, 20000, 20000, 30000, 30000]
+    h = _hitlist(ctx, ev, gid, np.full(6, 511.0), t, 0, 3)
+    resp = {"dead_time_ps": tau, "dead_time_mode": mode, "dead_time_level": "panel"}
+    sg, (ca, cb) = ctx.digitize(h, seed=1, fwhm_511=0.0, response=resp)
+    s = sg.numpy()
+    assert ((s["in_window"].view(np.uint32) >> 1) & 1).tolist() == lost
+    assert sg.windowed == 6 - sum(lost)
+    assert len(ca) == n_coinc
+    h2 = np.zeros(6, dtype=np.dtype(oracle_mod.Hit))
+    h2["event"], h2["gid"], h2["edep"], h2["time_ps"] = ev, gid, 511.0, t
+    so, co = oracle_mod.OracleScene(sc).digitize(h2, seed=1, fwhm_511=0.0, dead_ps=tau, dead_mode=MODES[mode],
+                                                 dead_level=2)
+    assert so["lost"].tolist() == lost and len(co) == n_coinc
+    got = sorted(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
+    assert got == sorted(map(tuple, co.tolist()))
