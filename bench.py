@@ -250,6 +250,65 @@ def config1_form():
     return out
 
 
+# the optional physics at published values: 0.5 deg acollinearity (photon
+# pairs in water), the 0.102 mm positron range the paper quotes for 18F
+# (Sec. 4), with a 300 ps timing and 2 mm DOI resolution and a 1 us
+# non-paralyzable dead time per crystal (the singles are crystal singles: at
+# module level the second crystal single of a photon that scatters inside a
+# module would fall in its dead time)
+EXT_SOURCE = {"acolinearity_fwhm_deg": 0.5, "positron_range_fwhm_mm": 0.102}
+EXT_RESPONSE = {"time_fwhm_ps": 300.0, "doi_fwhm_mm": 2.0, "dead_time_ps": 1_000_000,
+                "dead_time_mode": "nonparalyzable", "dead_time_level": "crystal"}
+
+
+def extensions_form(n: int = 10_000_000):
+    """Design C, source at the centre: transport + digitizer with every
+    optional effect on against the paper's setting (all off), median of 3
+    after one warm-up each; kernel times from the library's HIP events."""
+    import torch
+
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    c.enable_timing(True)
+    hits = c.alloc_hits(int(3.2 * n))
+    singles = c.alloc_singles(int(2.2 * n))
+    coinc = (c._empty(n, torch.int32), c._empty(n, torch.int32))
+    out = {"workload": f"design C, point source at the centre, {n:.0e} events",
+           "source": EXT_SOURCE, "response": EXT_RESPONSE}
+    for form in ("off", "on"):
+        src = G.point_source((0.0, 0.0, 0.0), n)
+        if form == "on":
+            src.update(EXT_SOURCE)
+        sc = G.small_animal_scene("C", (0.0, 0.0, 0.0), n_events=n)
+        sc["source"] = src
+        c.set_scene(sc)
+        resp = EXT_RESPONSE if form == "on" else None
+        wall, tk, dg = [], [], []
+        for r in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, _ = c.transport_into(hits, n, seed=r)
+            rc2, nc = c.digitize_into(hits, singles, coinc, seed=r, response=resp)
+            torch.cuda.synchronize()
+            if rc or rc2:
+                raise RuntimeError("extensions: capacity")
+            if r:
+                wall.append(time.perf_counter() - t0)
+                tm = c.timings()
+                tk.append(tm[0])
+                dg.append(tm[1])
+        lost = 0
+        if form == "on":
+            lost = int(((singles.in_window[:singles.count] & 2) != 0).sum())
+        out[form] = {"value": n / float(np.median(wall)), "unit": "events/s",
+                     "transport_kernel_ms": float(np.median(tk)), "digitizer_ms": float(np.median(dg)),
+                     "hits": hits.count, "singles": singles.count, "lost_to_dead_time": lost,
+                     "coincidences": nc}
+    out["slowdown"] = out["off"]["value"] / out["on"]["value"]
+    c.close()
+    return out
+
+
 def batched_form(args):
     """The batched design sweep (36 designs x 4 source offsets, log-uniform event
     counts): one persistent transport launch over all instances plus one
@@ -497,6 +556,8 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="event-count scale of the batched design sweep (0 skips it)")
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner")
+    ap.add_argument("--no-extensions", dest="extensions", action="store_false",
+                    help="skip the optional-physics form (acollinearity, positron range, resolutions, dead time)")
     ap.add_argument("--no-config1", dest="config1", action="store_false",
                     help="skip the small-ring rates at 1e5 and 1e8 events")
     ap.add_argument("--no-paper-scanners", dest="paper_scanners", action="store_false",
@@ -602,6 +663,8 @@ def main():
     for _, c, *_ in ctxs:
         c.close()
     del ctxs
+    if args.extensions:
+        line["extensions"] = extensions_form(n)
     if args.config1:
         line["config1"] = config1_form()
     if args.paper_scanners:

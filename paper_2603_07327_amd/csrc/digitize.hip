@@ -1100,37 +1100,79 @@ __global__ void k_dead_starts(size_t n, const unsigned long long *key, const uin
   if (p == 0 || key[p] != key[p - 1]) start[pos[p]] = (uint32_t)p;
 }
 
-// non-paralyzable: one wave per unit walks its run 64 singles at a time; the
-// chain of kept singles is resolved in scalar registers (a single is kept
-// when it comes tau or more after the last kept one)
+// times in unit order, so the scan below reads them contiguously
+__global__ void k_dead_gather(size_t n, const uint32_t *val, const unsigned long long *s_time,
+                              unsigned long long *t_sorted) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  t_sorted[p] = s_time[val[p]];
+}
+
+// non-paralyzable: one wave per unit walks its run 1024 singles at a time,
+// lane c taking the chunk of kDeadChunk consecutive singles c.  A chunk's
+// kept set follows from the state entering it (whether a single was kept
+// before, and the time of the last one): each lane runs the rule over its
+// chunk from a guessed entry, takes the exit of the lane before as its next
+// entry, and runs again until no entry changes.  Lane c is exact after c + 1
+// rounds; as chains from different entries merge within a few singles, two
+// or three rounds settle most windows.
+constexpr int kDeadChunk = 16;
 __global__ void __launch_bounds__(256) k_dead_nonparalyzable(uint32_t n_runs, const uint32_t *start, size_t n,
                                                              const uint32_t *val,
-                                                             const unsigned long long *s_time,
+                                                             const unsigned long long *t_sorted,
                                                              unsigned long long tau, uint32_t *lost) {
   const uint32_t run = blockIdx.x * 4u + (threadIdx.x >> 6);
   if (run >= n_runs) return; // whole waves leave together
   const int lane = (int)__lane_id();
   const size_t b = start[run], e = run + 1 < n_runs ? start[run + 1] : n;
-  unsigned long long last = 0;
-  bool have = false;
-  for (size_t base = b; base < e; base += 64) {
-    const size_t p = base + (size_t)lane;
-    const bool ok = p < e;
-    const uint32_t i = ok ? val[p] : 0u;
-    const unsigned long long t = ok ? s_time[i] : 0ull;
-    const int cnt = e - base < 64 ? (int)(e - base) : 64;
-    const uint32_t t_lo = (uint32_t)t, t_hi = (uint32_t)(t >> 32);
-    uint64_t keep = 0;
-    for (int l = 0; l < cnt; ++l) {
-      const unsigned long long tl = ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)t_hi, l) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)t_lo, l);
-      if (!have || tl - last >= tau) {
-        keep |= 1ull << l;
-        last = tl;
-        have = true;
+  bool have_prev = false; // state entering the window (wave-uniform)
+  unsigned long long last_prev = 0;
+  for (size_t base = b; base < e; base += (size_t)64 * kDeadChunk) {
+    const size_t c0 = base + (size_t)lane * kDeadChunk;
+    const int nk = c0 >= e ? 0 : (e - c0 < (size_t)kDeadChunk ? (int)(e - c0) : kDeadChunk);
+    unsigned long long t[kDeadChunk];
+#pragma unroll
+    for (int k = 0; k < kDeadChunk; ++k) t[k] = k < nk ? t_sorted[c0 + k] : 0ull;
+    bool in_have = lane == 0 ? have_prev : false;
+    unsigned long long in_last = lane == 0 ? last_prev : 0ull;
+    uint32_t mask = 0;
+    bool out_have = false;
+    unsigned long long out_last = 0;
+    for (int round = 0; round <= 64; ++round) {
+      bool h = in_have;
+      unsigned long long L = in_last;
+      uint32_t m = 0;
+#pragma unroll
+      for (int k = 0; k < kDeadChunk; ++k) {
+        if (k < nk && (!h || t[k] - L >= tau)) {
+          m |= 1u << k;
+          L = t[k];
+          h = true;
+        }
       }
+      mask = m;
+      out_have = h;
+      out_last = L;
+      // the entry of lane c is the exit of lane c - 1
+      bool nh = __shfl_up((int)h, 1) != 0;
+      unsigned long long nl = ((unsigned long long)(uint32_t)__shfl_up((int)(uint32_t)(L >> 32), 1) << 32) |
+                              (uint32_t)__shfl_up((int)(uint32_t)L, 1);
+      if (lane == 0) {
+        nh = have_prev;
+        nl = last_prev;
+      }
+      const bool changed = nh != in_have || (nh && nl != in_last);
+      in_have = nh;
+      in_last = nl;
+      if (__ballot(changed) == 0) break;
     }
-    if (ok) lost[i] = ((keep >> lane) & 1ull) ? 0u : 1u;
+#pragma unroll
+    for (int k = 0; k < kDeadChunk; ++k)
+      if (k < nk) lost[val[c0 + k]] = ((mask >> k) & 1u) ? 0u : 1u;
+    // empty chunks pass their entry through, so the last lane holds the window's exit
+    have_prev = __builtin_amdgcn_readlane((int)out_have, 63) != 0;
+    last_prev = ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(out_last >> 32), 63) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)out_last, 63);
   }
 }
 
@@ -1382,14 +1424,17 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       hipLaunchKernelGGL(k_dead_paralyzable, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uk, uv,
                          (const unsigned long long *)s_time, D.dead_ps, lost);
     } else {
-      uint32_t *start = f2 ? sb.v0 : sb.v1; // the free value array
+      uint32_t *start = f2 ? sb.v0 : sb.v1;               // the free value array
+      unsigned long long *t_sorted = f2 ? sb.k0 : sb.k1;  // and the free key array
       hipLaunchKernelGGL(k_dead_heads, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uk, wpos);
       exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 6);
       hipLaunchKernelGGL(k_dead_starts, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uk, wpos, start);
+      hipLaunchKernelGGL(k_dead_gather, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uv,
+                         (const unsigned long long *)s_time, t_sorted);
       if (!sync("in the dead time")) return GPET_ERR_HIP;
       const uint32_t n_runs = rb[6];
       hipLaunchKernelGGL(k_dead_nonparalyzable, dim3((n_runs + 3) / 4), dim3(256), 0, st, n_runs, start,
-                         (size_t)ns, uv, (const unsigned long long *)s_time, D.dead_ps, lost);
+                         (size_t)ns, uv, (const unsigned long long *)t_sorted, D.dead_ps, lost);
     }
     hipLaunchKernelGGL(k_dead_apply, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, lost, S->in_window, wpos,
                        S->gid, S->energy_kev, T ? T->singles_per_crystal : nullptr,
