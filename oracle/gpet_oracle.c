@@ -842,15 +842,16 @@ static int cmp_hit(const void *a, const void *b) {
 }
 
 static const or_single *g_sorted_base;
+/* time order; equal times keep the list order, which is (event, crystal)
+ * order as the adder left it */
 static int cmp_single_time(const void *a, const void *b) {
-  const or_single *x = &g_sorted_base[*(const int64_t *)a], *y = &g_sorted_base[*(const int64_t *)b];
+  const int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
+  const or_single *x = &g_sorted_base[ia], *y = &g_sorted_base[ib];
   if (x->time_ps != y->time_ps) return x->time_ps < y->time_ps ? -1 : 1;
-  if (x->event != y->event) return x->event < y->event ? -1 : 1;
-  if (x->gid != y->gid) return x->gid < y->gid ? -1 : 1;
-  return 0;
+  return ia < ib ? -1 : ia > ib;
 }
 
-/* dead-time order: unit, then (time, event, crystal) */
+/* dead-time order: unit, then (time, list position) */
 static uint32_t g_dead_unit = 1;
 static int cmp_single_unit_time(const void *a, const void *b) {
   const or_single *x = &g_sorted_base[*(const int64_t *)a], *y = &g_sorted_base[*(const int64_t *)b];
@@ -874,8 +875,14 @@ static int cmp_single_unit_time(const void *a, const void *b) {
  *            even), not below 0: words 2, 3 of the blur block;
  *  depth   - (DOI resolution, optional) the depth moves by a normal deviate
  *            of the given FWHM: block 0 of digitizer stream 6;
+ *  light   - (light sharing, optional) with probability ls_prob the
+ *            crystal is read as one of its edge neighbours in the same layer
+ *            and module (those that exist, in the order t-1, t+1, a-1, a+1),
+ *            chosen uniformly; block 0 of digitizer stream 8, decided in
+ *            integers: word 0 < floor(ls_prob 2^32), neighbour (word 1 * n) >> 32.
+ *            The list keeps its order;
  *  dead    - (optional) each unit of the dead-time level sees its blurred
- *            singles in (time, event, crystal) order; paralyzable: a single
+ *            singles in (time, list position) order; paralyzable: a single
  *            is lost when the previous one of its unit came less than dead_ps
  *            earlier; non-paralyzable: when the last single kept came less
  *            than dead_ps earlier.  Lost singles stay in the list (lost = 1)
@@ -961,6 +968,33 @@ int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits, const
       rng_raw(&r6, q->gid, v);
       double z = sqrt(-2.0 * log(u01(v[0]))) * cos(2.0 * PI * u01(v[1]));
       q->depth += dg->doi_fwhm_mm / FWHM_PER_SIGMA * z;
+    }
+  }
+  if (dg->ls_prob > 0) {
+    const uint64_t thr = dg->ls_prob >= 1.0 ? (1ull << 32) : (uint64_t)floor(dg->ls_prob * 4294967296.0);
+    const uint32_t cpm = (uint32_t)s->crystals_per_module;
+    for (int64_t i = 0; i < ns; i++) {
+      or_single *q = &sg[i];
+      rng_t r8;
+      rng_init(&r8, dg->seed, q->event, dg->instance, 8);
+      uint32_t v[4];
+      rng_raw(&r8, q->gid, v);
+      if ((uint64_t)v[0] >= thr) continue;
+      /* the crystal's place in its module: layer by its first id, then (t, a) */
+      const uint32_t local = q->gid % cpm;
+      int l = 0;
+      for (int k = 1; k < s->scan.n_layers; k++)
+        if (local >= (uint32_t)s->layer_base[k]) l = k;
+      const uint32_t nt = (uint32_t)s->scan.layer[l].n_t, na = (uint32_t)s->scan.layer[l].n_a;
+      const uint32_t it = (local - (uint32_t)s->layer_base[l]) % nt;
+      const uint32_t ia = (local - (uint32_t)s->layer_base[l]) / nt;
+      uint32_t nb[4];
+      int n = 0;
+      if (it > 0) nb[n++] = q->gid - 1;
+      if (it + 1 < nt) nb[n++] = q->gid + 1;
+      if (ia > 0) nb[n++] = q->gid - nt;
+      if (ia + 1 < na) nb[n++] = q->gid + nt;
+      if (n) q->gid = nb[((uint64_t)v[1] * (uint64_t)n) >> 32];
     }
   }
   if (dg->dead_mode == 1 || dg->dead_mode == 2) {

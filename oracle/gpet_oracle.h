@@ -18,7 +18,8 @@
  *   or_transport         narrow-beam exp(-mu L), black-ring solid angle,
  *                        collinearity, energy conservation, split-layer invariance
  *   or_digitize          brute-force adder / O(n^2) coincidence reference;
- *                        time and depth blur against the normal law, dead
+ *                        time and depth blur against the normal law, light
+ *                        sharing against the neighbour set and its law, dead
  *                        time against brute force and the Poisson throughput
  *                        of both dead-time models
  *   source extensions    acollinearity and positron range against the normal
@@ -136,6 +137,7 @@ typedef struct {
   uint64_t dead_ps;    /* dead time of a unit */
   int32_t dead_mode;   /* 0 none, 1 paralyzable, 2 non-paralyzable */
   int32_t dead_level;  /* dead-time unit: 0 crystal, 1 module, 2 panel */
+  double ls_prob;      /* light sharing: probability of reading a neighbour crystal */
 } or_digitizer;
 
 typedef struct {

@@ -97,7 +97,7 @@ class Digitizer(C.Structure):
                 ("window_ps", C.c_uint64), ("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("doi_bins", C.c_int32), ("readout", C.c_int32), ("time_fwhm_ps", C.c_double),
                 ("doi_fwhm_mm", C.c_double), ("dead_ps", C.c_uint64), ("dead_mode", C.c_int32),
-                ("dead_level", C.c_int32)]
+                ("dead_level", C.c_int32), ("ls_prob", C.c_double)]
 
 
 class Single(C.Structure):
@@ -318,14 +318,15 @@ class OracleScene:
 
     def digitize(self, hits, seed=0, fwhm_511=0.16, e_lo=350.0, e_hi=650.0, window_ps=3000,
                  instance=0, readout=0, time_fwhm_ps=0.0, doi_fwhm_mm=0.0, dead_ps=0, dead_mode=0,
-                 dead_level=1):
+                 dead_level=1, light_sharing=0.0):
         """Adder, readout (0 crystal, 1 module, 2 panel), energy / time / depth
-        blur, dead time (mode 0 none, 1 paralyzable, 2 non-paralyzable; level
-        as readout), window and coincidence sorter; returns (singles,
+        blur, light sharing (probability of reading a neighbour crystal),
+        dead time (mode 0 none, 1 paralyzable, 2 non-paralyzable; level as
+        readout), window and coincidence sorter; returns (singles,
         coincidence index pairs)."""
         hits = np.ascontiguousarray(hits)
         dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, 200, readout, time_fwhm_ps,
-                       doi_fwhm_mm, int(dead_ps), dead_mode, dead_level)
+                       doi_fwhm_mm, int(dead_ps), dead_mode, dead_level, light_sharing)
         n = len(hits)
         sg = (Single * max(1, n))()
         cc = np.empty((max(1, n), 2), np.uint32)

@@ -8,6 +8,9 @@ Sec. 4: analytic blurring of the detector response).
   the FWHM given per axis, and both photons start at the same point;
 * timing and DOI resolution: time and depth move by a normal deviate of the
   given FWHM (time rounded to the ps);
+* light sharing: a moved crystal is an edge neighbour in its layer and
+  module, each existing neighbour equally likely, moved with the given
+  probability;
 * dead time: a brute-force definition on small random inputs, and the
   throughput of a Poisson stream, exp(-rate tau) for the paralyzable and
   1 / (1 + rate tau) for the non-paralyzable model.
@@ -265,3 +268,52 @@ def test_dead_singles_pass_no_window(oracle_mod):
     sg, cc = s.digitize(h, seed=1, fwhm_511=0.0, window_ps=3000, dead_ps=25000, dead_mode=2, dead_level=2)
     assert sg["lost"].tolist() == [0, 0, 1, 1, 0, 0]
     assert len(cc) == 2
+
+
+def _place(scene, gid):
+    """(module id, layer, i_t, i_a) of crystal ids, from the id layout."""
+    S = scene.s
+    cpm = S.crystals_per_module
+    local = gid % cpm
+    bases = [S.layer_base[k] for k in range(S.scan.n_layers)]
+    layer = np.searchsorted(bases, local, side="right") - 1
+    nt = np.array([S.scan.layer[k].n_t for k in range(S.scan.n_layers)])[layer]
+    i = local - np.array(bases)[layer]
+    return gid // cpm, layer, i % nt, i // nt
+
+
+@pytest.mark.parametrize("design", ["A", "C"])
+def test_light_sharing_moves_to_a_neighbour(oracle_mod, design):
+    s = oracle_mod.OracleScene(G.small_animal_scene(design, n_events=10))
+    n = 30000
+    rng = np.random.default_rng(11)
+    h = np.zeros(n, dtype=np.dtype(oracle_mod.Hit))
+    h["event"] = np.arange(n)
+    h["gid"] = rng.integers(0, s.n_crystals, n)
+    h["edep"] = 511.0
+    h["time_ps"] = 10**9 + np.arange(n, dtype=np.uint64) * 10**7
+    s0, _ = s.digitize(h, seed=2)
+    s1, _ = s.digitize(h, seed=2, light_sharing=1.0)
+    assert np.array_equal(s0["energy"], s1["energy"])  # the blur draws follow the true crystal
+    g0, g1 = s0["gid"].astype(np.int64), s1["gid"].astype(np.int64)
+    m0, l0, t0, a0 = _place(s, g0)
+    m1, l1, t1, a1 = _place(s, g1)
+    assert np.array_equal(m0, m1) and np.array_equal(l0, l1)
+    assert np.all(np.abs(t1 - t0) + np.abs(a1 - a0) == 1)
+    # each existing neighbour equally likely: crystals with 4 neighbours
+    S = s.s
+    nt = np.array([S.scan.layer[k].n_t for k in range(S.scan.n_layers)])[l0]
+    na = np.array([S.scan.layer[k].n_a for k in range(S.scan.n_layers)])[l0]
+    inner = (t0 > 0) & (t0 < nt - 1) & (a0 > 0) & (a0 < na - 1)
+    code = (t1 - t0 + 1) + 3 * (a1 - a0 + 1)  # 3 (t-1), 5 (t+1), 1 (a-1), 7 (a+1)
+    counts = np.array([np.sum(code[inner] == c) for c in (3, 5, 1, 7)])
+    assert stats.chisquare(counts).pvalue > 1e-3
+    # corners have exactly their two neighbours
+    corner = (t0 == 0) & (a0 == 0)
+    assert set(np.unique(code[corner]).tolist()) <= {5, 7} and corner.sum() > 0
+    # partial probability: the moved fraction is binomial
+    s3, _ = s.digitize(h, seed=2, light_sharing=0.3)
+    moved = np.mean(s3["gid"] != s0["gid"])
+    assert abs(moved - 0.3) < 4 * np.sqrt(0.3 * 0.7 / n)
+    s4, _ = s.digitize(h, seed=2, light_sharing=0.0)
+    assert np.array_equal(s4["gid"], s0["gid"])
