@@ -252,13 +252,13 @@ def config1_form():
 
 # the optional physics at published values: 0.5 deg acollinearity (photon
 # pairs in water), the 0.102 mm positron range the paper quotes for 18F
-# (Sec. 4), with a 300 ps timing and 2 mm DOI resolution and a 1 us
-# non-paralyzable dead time per crystal (the singles are crystal singles: at
+# (Sec. 4), with a 300 ps timing and 2 mm DOI resolution, 10 % light sharing
+# and a 1 us non-paralyzable dead time per crystal (the singles are crystal singles: at
 # module level the second crystal single of a photon that scatters inside a
 # module would fall in its dead time)
 EXT_SOURCE = {"acolinearity_fwhm_deg": 0.5, "positron_range_fwhm_mm": 0.102}
 EXT_RESPONSE = {"time_fwhm_ps": 300.0, "doi_fwhm_mm": 2.0, "dead_time_ps": 1_000_000,
-                "dead_time_mode": "nonparalyzable", "dead_time_level": "crystal"}
+                "dead_time_mode": "nonparalyzable", "dead_time_level": "crystal", "light_sharing": 0.1}
 
 
 def extensions_form(n: int = 10_000_000):

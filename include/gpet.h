@@ -251,13 +251,15 @@ gpet_status gpet_transport(gpet_ctx *ctx, uint64_t first_event, uint64_t n_event
 /*          optional time blur (timing resolution): t + rint(N(0,1) *        */
 /*          time_fwhm_ps / 2.3548), not below 0; optional depth blur (DOI    */
 /*          resolution): depth + N(0,1) * doi_fwhm_mm / 2.3548;              */
+/*  light:  optional light sharing: the crystal read as a neighbour        */
+/*          (light_sharing, below);                                          */
 /*  dead:   optional dead time per crystal, module or panel (dead_time_level)*/
-/*          over the blurred singles in (time, event, gid) order: a single is*/
+/*          over the blurred singles in (time, list position) order: one is  */
 /*          lost when the previous single of its unit (paralyzable) or the   */
 /*          last one kept (non-paralyzable) came less than dead_time_ps      */
 /*          earlier; lost singles stay listed and enter no window;           */
 /*  window: e_lo <= blurred E <= e_hi;                                       */
-/*  sorter: windowed singles in (time, event, gid) order; a window of        */
+/*  sorter: windowed singles in (time, list position) order; a window of    */
 /*          window_ps (inclusive) opens at the earliest unused single and    */
 /*          does not retrigger; exactly two singles in different panels make */
 /*          a coincidence, any other content is discarded.                   */
@@ -287,6 +289,12 @@ typedef struct {
   uint64_t dead_time_ps;
   uint32_t dead_time_mode;   /* GPET_DEAD_NONE, _PARALYZABLE, _NONPARALYZABLE */
   uint32_t dead_time_level;  /* GPET_READOUT_CRYSTAL, _MODULE or _PANEL */
+  /* Light sharing (Sec. 4, analytic): probability 0..1 that a single's crystal
+   * is read as one of its existing edge neighbours in the same layer and
+   * module (order t-1, t+1, a-1, a+1), chosen uniformly; Philox counter (gid,
+   * event, instance, 8): word 0 < floor(p 2^32) moves it, neighbour
+   * (word 1 * count) >> 32.  Applied after the blur; the list keeps its order. */
+  double light_sharing;
 } gpet_digitizer;
 
 enum { GPET_READOUT_CRYSTAL = 0, GPET_READOUT_MODULE = 1, GPET_READOUT_PANEL = 2 };

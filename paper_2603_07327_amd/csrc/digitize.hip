@@ -834,20 +834,48 @@ __global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t 
   if (s_inst_out) s_inst_out[s] = in;
 }
 
-__global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, const uint32_t *s_gid,
+// light sharing: the crystal read instead of `gid` (one of its existing edge
+// neighbours in the same layer and module, in the order t-1, t+1, a-1, a+1,
+// picked by the high half of pick * count); geo holds per instance the
+// crystals per module and the layer words, row-major over instances
+__device__ __forceinline__ uint32_t shared_crystal(uint32_t gid, const uint32_t *geo, uint32_t ni, uint32_t in,
+                                                   uint32_t pick) {
+  const uint32_t cpm = geo[in];
+  const uint32_t *lw = geo + ni; // [word][instance]
+  const uint32_t local = gid % cpm;
+  const int nl = (int)lw[in];
+  int l = 0;
+  for (int k = 1; k < nl; ++k)
+    if (local >= lw[(1 + k) * ni + in]) l = k;
+  const uint32_t base = lw[(1 + l) * ni + in];
+  const uint32_t nt = lw[(1 + kMaxLayers + l) * ni + in], na = lw[(1 + 2 * kMaxLayers + l) * ni + in];
+  const uint32_t it = (local - base) % nt, ia = (local - base) / nt;
+  uint32_t nb[4];
+  uint32_t cnt = 0;
+  if (it > 0) nb[cnt++] = gid - 1;
+  if (it + 1 < nt) nb[cnt++] = gid + 1;
+  if (ia > 0) nb[cnt++] = gid - nt;
+  if (ia + 1 < na) nb[cnt++] = gid + nt;
+  return cnt ? nb[((unsigned long long)pick * cnt) >> 32] : gid;
+}
+
+__global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, uint32_t *s_gid,
                                               const uint32_t *s_inst, InstTab T, const float *s_edep,
                                               float *s_energy, uint32_t *s_win, uint32_t *wflag, uint32_t k0,
                                               uint32_t k1, float fwhm, float e_lo, float e_hi, uint32_t *spp,
                                               uint32_t *spec, unsigned long long *s_time, float time_sigma,
-                                              float *s_depth, float doi_sigma, unsigned long long *block_max) {
+                                              float *s_depth, float doi_sigma, unsigned long long ls_thresh,
+                                              const uint32_t *geo, unsigned long long *block_max) {
   __shared__ unsigned long long s_max[4];
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long tm = 0; // largest time stamp of all singles (every window's keys fit its width)
   if (i < n) {
     // normal deviates by Box-Muller from the digitizer stream of (gid, event,
     // instance): words 0, 1 for the energy, 2, 3 for the time
-    const uint32_t rng = T.rng[s_inst[i]];
-    const uint4 w = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], rng, 3u));
+    const uint32_t in_i = s_inst[i], rng = T.rng[in_i];
+    const uint32_t w_gid = s_gid[i]; // the counters take the crystal that was hit
+    uint32_t gid = w_gid;
+    const uint4 w = philox(k0, k1, make_uint4(gid, s_ev[i], rng, 3u));
     const float u0 = to_unit(w.x), u1 = to_unit(w.y);
     const float g = sqrtf(-2.0f * logf(u0)) * cos_rev(u1);
     const float E = s_edep[i];
@@ -857,7 +885,14 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, co
     s_energy[i] = Eb;
     s_win[i] = in;
     wflag[i] = in;
-    if (spp && in) atomicAdd(&spp[s_gid[i]], 1u);
+    if (ls_thresh) { // light sharing: stream 8 of (gid, event, instance)
+      const uint4 v = philox(k0, k1, make_uint4(gid, s_ev[i], rng, 8u));
+      if ((unsigned long long)v.x < ls_thresh) {
+        gid = shared_crystal(gid, geo, T.n_inst, in_i, v.y);
+        s_gid[i] = gid;
+      }
+    }
+    if (spp && in) atomicAdd(&spp[gid], 1u);
     if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
     tm = s_time[i];
     if (time_sigma > 0.0f) { // timing resolution: rounded to the ps, not below 0
@@ -867,7 +902,7 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, co
       s_time[i] = tm;
     }
     if (doi_sigma > 0.0f) { // DOI resolution: stream 6 of (gid, event, instance)
-      const uint4 v = philox(k0, k1, make_uint4(s_gid[i], s_ev[i], rng, 6u));
+      const uint4 v = philox(k0, k1, make_uint4(w_gid, s_ev[i], rng, 6u));
       s_depth[i] += doi_sigma * (sqrtf(-2.0f * logf(to_unit(v.x))) * cos_rev(to_unit(v.y)));
     }
   }
@@ -1192,6 +1227,9 @@ __global__ void k_dead_apply(size_t n, const uint32_t *lost, uint32_t *s_win, ui
 }
 
 static inline unsigned grid_for(size_t n) { return (unsigned)((n + 255) / 256); }
+// rows of the per-instance table: first event, event count, crystals per
+// panel, RNG id, readout unit, dead-time unit, crystals per module, layer words
+constexpr int kTabRows = 7 + kLayerWords;
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1231,7 +1269,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
     scr.bytes = grow;
   }
-  const size_t pinned_bytes = 64 + 40 * ni;
+  const size_t pinned_bytes = 64 + 4 * (4 + kTabRows) * ni;
   if (scr.pinned_bytes < pinned_bytes) {
     if (scr.pinned) (void)hipHostFree(scr.pinned);
     scr.pinned = nullptr;
@@ -1264,11 +1302,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   bb.big = (uint32_t *)take(max_buckets * 4);
   bb.n_big = (uint32_t *)take(8);
   bb.map = (uint32_t *)take(ni * 4 * 3);
-  uint32_t *d_tab = (uint32_t *)take(ni * 4 * 6); // first, n_events, cpp, rng, readout unit, dead-time unit
+  // first, n_events, cpp, rng, readout unit, dead-time unit, crystals per module, layer words
+  uint32_t *d_tab = (uint32_t *)take(ni * 4 * kTabRows);
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
   // pinned host words: [0, 16) scalars that kernels write directly (scan
   // totals, maximum time, failure flags), [16, 16 + ni) per-instance counts,
-  // 3 ni words of bucket-map uploads, 6 ni words of instance table
+  // 3 ni words of bucket-map uploads, kTabRows ni words of instance table
   uint32_t *rb = (uint32_t *)scr.pinned;
   uint32_t *rb_count = rb + 16;
   bb.pinned_flag = rb + 12;
@@ -1295,8 +1334,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     tab[5 * ni + i] = D.dead_level == GPET_READOUT_MODULE ? std::max(1u, D.cpm[i])
                       : D.dead_level == GPET_READOUT_PANEL ? std::max(1u, D.cpp[i])
                                                            : 1u;
+    tab[6 * ni + i] = std::max(1u, D.cpm[i]);
+    const bool have_layers = D.layers.size() >= (i + 1) * kLayerWords;
+    for (int k = 0; k < kLayerWords; ++k) // without a layout: one layer of 1 x 1 (no neighbours)
+      tab[(7 + k) * ni + i] = have_layers ? D.layers[i * kLayerWords + k] : (k == 0 || k > kMaxLayers ? 1u : 0u);
   }
-  (void)hipMemcpyAsync(d_tab, tab, ni * 24, hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(d_tab, tab, ni * 4 * kTabRows, hipMemcpyHostToDevice, st);
   const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, (uint32_t)ni};
   uint32_t max_events = 1;
   for (size_t i = 0; i < ni; ++i) max_events = std::max(max_events, D.n_events[i]);
@@ -1401,7 +1444,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
                      S->edep_kev, S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
                      (T && !dead) ? T->singles_per_crystal : nullptr, (T && !dead) ? T->energy_spectrum : nullptr,
-                     s_time, D.time_sigma, S->depth_mm, D.doi_sigma, sb.k1);
+                     s_time, D.time_sigma, S->depth_mm, D.doi_sigma, D.ls_thresh, d_tab + 6 * ni, sb.k1);
   hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
                      (size_t)grid_for(ns), (unsigned long long *)(rb + 4));
   if (dead) {

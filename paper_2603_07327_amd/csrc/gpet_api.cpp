@@ -732,6 +732,9 @@ static gpet_status digitizer_params(gpet_ctx *c, const gpet_hits *h, const gpet_
   D.dead_mode = p->dead_time_ps ? p->dead_time_mode : (uint32_t)GPET_DEAD_NONE;
   D.dead_level = p->dead_time_level;
   D.dead_ps = p->dead_time_ps;
+  if (!(p->light_sharing >= 0.0 && p->light_sharing <= 1.0))
+    return fail(c, GPET_ERR_ARG, "digitize: light-sharing probability must lie in [0, 1]");
+  D.ls_thresh = p->light_sharing >= 1.0 ? (1ull << 32) : (unsigned long long)std::floor(p->light_sharing * 4294967296.0);
   D.singles = sg;
   D.coinc = cc;
   return GPET_OK;
@@ -764,6 +767,7 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
   D.n_events = {(uint32_t)p->n_events};
   D.cpp = {(uint32_t)c->info.crystals_per_panel};
   D.cpm = {(uint32_t)c->info.crystals_per_module};
+  layer_words(c->scene, D.layers);
   D.rng = {p->instance};
   D.duration = {c->have_source ? (unsigned long long)c->scene.duration_ps : 0ull};
   D.gid_bits = bits_for((uint64_t)c->info.n_crystals - 1);
@@ -1124,6 +1128,7 @@ gpet_status gpet_batch_create(gpet_ctx *c, int32_t n, const gpet_instance *inst,
     b->id.push_back(inst[i].instance);
     b->cpp.push_back((uint32_t)G[i].info.crystals_per_panel);
     b->cpm.push_back((uint32_t)G[i].info.crystals_per_module);
+    layer_words(S[i], b->layers);
     b->duration.push_back(inst[i].source->duration_ps);
     b->gid_bits = std::max(b->gid_bits, bits_for((uint64_t)G[i].info.n_crystals - 1));
     b->total_events += inst[i].n_events;
@@ -1342,6 +1347,7 @@ gpet_status gpet_batch_digitize(gpet_batch *b, const gpet_hits *h, const gpet_di
     if (D.n_events[i] == 0) D.n_events[i] = 1; // empty instance: no hit can name it
   D.cpp = b->cpp;
   D.cpm = b->cpm;
+  D.layers = b->layers;
   D.rng = b->id;
   D.duration = b->duration;
   D.gid_bits = b->gid_bits;

@@ -104,6 +104,15 @@ struct DigitizeScratch {
 // One digitizer pass over the hits of one or more instances.  Instance i owns
 // the event ids [first[i], first[i] + n_events[i]); its hits carry i in h_inst
 // (h_inst may be null when there is one instance).
+constexpr int kLayerWords = 1 + 3 * kMaxLayers;
+// layer words of a scene: count, first ids, n_t, n_a
+inline void layer_words(const DevScene &S, std::vector<uint32_t> &out) {
+  out.push_back((uint32_t)S.n_layers);
+  for (int k = 0; k < kMaxLayers; ++k) out.push_back(k < S.n_layers ? (uint32_t)S.layer[k].base : 0u);
+  for (int k = 0; k < kMaxLayers; ++k) out.push_back(k < S.n_layers ? (uint32_t)S.layer[k].n_t : 1u);
+  for (int k = 0; k < kMaxLayers; ++k) out.push_back(k < S.n_layers ? (uint32_t)S.layer[k].n_a : 1u);
+}
+
 struct DigitizeArgs {
   uint64_t n_hits = 0;
   const uint32_t *h_event = nullptr, *h_gid = nullptr, *h_aux = nullptr, *h_inst = nullptr;
@@ -126,6 +135,11 @@ struct DigitizeArgs {
   float time_sigma = 0.f, doi_sigma = 0.f;
   uint32_t dead_mode = 0, dead_level = 0;
   unsigned long long dead_ps = 0;
+  // light sharing: Philox word 0 below this moves the crystal (0 = off, 2^32 = always)
+  unsigned long long ls_thresh = 0;
+  // per instance kLayerWords words: layer count, then first crystal id, n_t and
+  // n_a of up to kMaxLayers layers (the crystal id layout inside a module)
+  std::vector<uint32_t> layers;
   // outputs
   gpet_singles *singles = nullptr;
   gpet_coincidences *coinc = nullptr;
@@ -210,6 +224,7 @@ struct gpet_batch {
   uint32_t n = 0;
   std::vector<gpet_geometry_info> info;
   std::vector<uint32_t> first, count, id, cpp, cpm;
+  std::vector<uint32_t> layers; // kLayerWords per instance (see DigitizeArgs)
   std::vector<unsigned long long> duration;
   uint64_t mat_gen = 0, phantom_gen = 0;
   int det_slots = 0;

@@ -94,7 +94,8 @@ class Digitizer(C.Structure):
                 ("first_event", C.c_uint64), ("n_events", C.c_uint64), ("readout", C.c_uint32),
                 ("n_sweep", C.c_uint32), ("sweep_lo_kev", C.c_void_p), ("sweep_hi_kev", C.c_void_p),
                 ("sweep_coincidences", C.c_void_p), ("time_fwhm_ps", C.c_double), ("doi_fwhm_mm", C.c_double),
-                ("dead_time_ps", C.c_uint64), ("dead_time_mode", C.c_uint32), ("dead_time_level", C.c_uint32)]
+                ("dead_time_ps", C.c_uint64), ("dead_time_mode", C.c_uint32), ("dead_time_level", C.c_uint32),
+                ("light_sharing", C.c_double)]
 
 
 READOUT = {"crystal": 0, "module": 1, "panel": 2}
@@ -110,7 +111,8 @@ def _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events,
     (kept alive by the caller for the duration of the call).  response: dict of
     the optional detector response -- time_fwhm_ps, doi_fwhm_mm, dead_time_ps,
     dead_time_mode ("paralyzable" / "nonparalyzable"), dead_time_level
-    ("crystal" / "module" / "panel")."""
+    ("crystal" / "module" / "panel"), light_sharing (probability of reading
+    a neighbour crystal)."""
     dg = Digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events, _readout_code(readout))
     r = response or {}
     dg.time_fwhm_ps = float(r.get("time_fwhm_ps", 0.0))
@@ -119,6 +121,7 @@ def _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, first, n_events,
     mode = r.get("dead_time_mode", "none")
     dg.dead_time_mode = DEAD_TIME[mode] if isinstance(mode, str) else int(mode)
     dg.dead_time_level = _readout_code(r.get("dead_time_level", "module"))
+    dg.light_sharing = float(r.get("light_sharing", 0.0))
     keep = None
     if sweep:
         lo = np.ascontiguousarray([w[0] for w in sweep], np.float64)

@@ -225,7 +225,7 @@ def test_batch_graph_replays_match_eager(ctxs):
 
 
 RESPONSE = {"time_fwhm_ps": 500.0, "doi_fwhm_mm": 2.0, "dead_time_ps": 100_000_000,
-            "dead_time_mode": "nonparalyzable", "dead_time_level": "module"}
+            "dead_time_mode": "nonparalyzable", "dead_time_level": "module", "light_sharing": 0.3}
 
 
 @pytest.mark.parametrize("response", [None, RESPONSE], ids=["plain", "response"])

@@ -129,11 +129,11 @@ def test_response_on_identical_hits(ctx, oracle_mod, mode, level, readout):
     # and 300 singles per 200 us at crystal, module and panel level
     tau = {"crystal": 5_000_000, "module": 30_000, "panel": 5_000}[level]
     resp = {"time_fwhm_ps": 400.0, "doi_fwhm_mm": 2.0, "dead_time_ps": tau, "dead_time_mode": mode,
-            "dead_time_level": level}
+            "dead_time_level": level, "light_sharing": 0.25}
     sg, (ca, cb) = ctx.digitize(hits, seed=6, readout=readout, response=resp)
     so, co = o.digitize(_hits_as_oracle(oracle_mod, hits.numpy()), seed=6, readout=LEVELS[readout],
                         time_fwhm_ps=400.0, doi_fwhm_mm=2.0, dead_ps=tau, dead_mode=MODES[mode],
-                        dead_level=LEVELS[level])
+                        dead_level=LEVELS[level], light_sharing=0.25)
     s = sg.numpy()
     assert len(s["event"]) == len(so)
     assert np.array_equal(s["event"].view(np.uint32), so["event"])
@@ -162,6 +162,32 @@ def test_response_on_identical_hits(ctx, oracle_mod, mode, level, readout):
     ref = set(map(tuple, co.tolist()))
     assert len(got ^ ref) <= 4 * (int(edge.sum()) + n_lost_diff + n_dt)
     assert len(ref) > 500
+
+
+@pytest.mark.parametrize("kind", ["stack4", "2CL"])
+def test_light_sharing_matches_oracle(ctx, oracle_mod, kind):
+    """Light sharing on every single of a 4-layer stack and of the paper's
+    two-layer scanner (layer decode of the crystal id, edge neighbours):
+    crystal ids bit-exact, as both sides decide in integers."""
+    n = 100_000
+    sc = G.stack_scene("stack4", (2.0, 1.0, 0.0), n) if kind == "stack4" else G.derenzo_scene("2CL", n)
+    ctx.set_scene(sc)
+    o = oracle_mod.OracleScene(sc)
+    hits, _ = ctx.transport(n, seed=12)
+    for p in (1.0, 0.4):
+        sg, (ca, cb) = ctx.digitize(hits, seed=13, response={"light_sharing": p})
+        so, co = o.digitize(_hits_as_oracle(oracle_mod, hits.numpy()), seed=13, light_sharing=p)
+        s = sg.numpy()
+        assert np.array_equal(s["event"].view(np.uint32), so["event"])
+        assert np.array_equal(s["gid"].view(np.uint32), so["gid"]), (kind, p)
+        edge = (np.abs(so["energy"] - 350) < 1e-2) | (np.abs(so["energy"] - 650) < 1e-2)
+        got = set(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
+        ref = set(map(tuple, co.tolist()))
+        assert len(got ^ ref) <= 4 * int(edge.sum())
+    s0, _ = ctx.digitize(hits, seed=13)
+    moved = np.mean(s0.numpy()["gid"] != s["gid"])
+    print(f"{kind}: {len(so)} singles, moved {moved:.3f} at p = 0.4")
+    assert abs(moved - 0.4) < 0.02
 
 
 def test_response_off_changes_nothing(ctx):
