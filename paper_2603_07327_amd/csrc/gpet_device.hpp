@@ -355,34 +355,56 @@ typedef __attribute__((address_space(4))) const DevScene CScene; // constant-add
 // Hierarchical locate in panel p at local (depth, t, a): module grid, then
 // the layer selected by depth, then that layer's crystal array.
 template <class SC> __device__ __forceinline__ Loc locate(SC &S, int p, Vec l) {
-  Loc r{S.fill, S.fill_slot, -1, -1, -1, -1};
   const float mt = floorf((l.y - S.mod_t0) * S.inv_step_t);
   const float ma = floorf((l.z - S.mod_a0) * S.inv_step_a);
   const float ut = l.y - S.mod_t0 - mt * S.mod_step_t;
   const float ua = l.z - S.mod_a0 - ma * S.mod_step_a;
-  if (mt < 0.0f || mt >= (float)S.mod_n_t || ma < 0.0f || ma >= (float)S.mod_n_a || ut >= S.mod_t ||
-      ua >= S.mod_a)
-    return r;
-  r.module = (int)ma * S.mod_n_t + (int)mt;
-  int L = -1;
+  const bool in_mod = !(mt < 0.0f || mt >= (float)S.mod_n_t || ma < 0.0f || ma >= (float)S.mod_n_a ||
+                        ut >= S.mod_t || ua >= S.mod_a);
+  // the layer holding the depth; its fields picked lane by lane from the
+  // (wave-uniform) layer table, the lowest matching layer winning
+  int L = -1, nt = 1, na = 1, mat_c = 0, slot_c = 0, mat_i = 0, slot_i = 0, base = 0;
+  float off_t = 0.0f, off_a = 0.0f, ipt = 0.0f, ipa = 0.0f, pt = 0.0f, pa = 0.0f, lo_t = 0.0f, hi_t = 0.0f,
+        lo_a = 0.0f, hi_a = 0.0f;
 #pragma unroll
-  for (int k = kMaxLayers - 1; k >= 0; --k)
-    if (k < S.n_layers && l.x >= S.layer[k].d0 && l.x < S.layer[k].d1) L = k;
-  if (L < 0) return r;
-  auto &y = S.layer[L];
-  r.layer = L;
-  r.mat = y.mat_interval;
-  r.slot = y.slot_interval;
-  const float it = floorf((ut - y.off_t) * y.inv_pitch_t);
-  const float ia = floorf((ua - y.off_a) * y.inv_pitch_a);
-  const float ct = ut - y.off_t - it * y.pitch_t;
-  const float ca = ua - y.off_a - ia * y.pitch_a;
-  if (it < 0.0f || it >= (float)y.n_t || ia < 0.0f || ia >= (float)y.n_a) return r;
-  if (ct < y.lo_t || ct >= y.hi_t || ca < y.lo_a || ca >= y.hi_a) return r;
-  r.mat = y.mat_crystal;
-  r.slot = y.slot_crystal;
-  r.crystal = (int)ia * y.n_t + (int)it;
-  r.gid = p * S.crystals_per_panel + r.module * S.crystals_per_module + y.base + r.crystal;
+  for (int k = kMaxLayers - 1; k >= 0; --k) {
+    if (k < S.n_layers) {
+      const auto &y = S.layer[k];
+      const bool m = l.x >= y.d0 && l.x < y.d1;
+      L = m ? k : L;
+      nt = m ? y.n_t : nt;
+      na = m ? y.n_a : na;
+      mat_c = m ? y.mat_crystal : mat_c;
+      slot_c = m ? y.slot_crystal : slot_c;
+      mat_i = m ? y.mat_interval : mat_i;
+      slot_i = m ? y.slot_interval : slot_i;
+      base = m ? y.base : base;
+      off_t = m ? y.off_t : off_t;
+      off_a = m ? y.off_a : off_a;
+      ipt = m ? y.inv_pitch_t : ipt;
+      ipa = m ? y.inv_pitch_a : ipa;
+      pt = m ? y.pitch_t : pt;
+      pa = m ? y.pitch_a : pa;
+      lo_t = m ? y.lo_t : lo_t;
+      hi_t = m ? y.hi_t : hi_t;
+      lo_a = m ? y.lo_a : lo_a;
+      hi_a = m ? y.hi_a : hi_a;
+    }
+  }
+  const float it = floorf((ut - off_t) * ipt);
+  const float ia = floorf((ua - off_a) * ipa);
+  const float ct = ut - off_t - it * pt;
+  const float ca = ua - off_a - ia * pa;
+  const bool has_layer = in_mod && L >= 0;
+  const bool crystal = has_layer && !(it < 0.0f || it >= (float)nt || ia < 0.0f || ia >= (float)na) &&
+                       !(ct < lo_t || ct >= hi_t || ca < lo_a || ca >= hi_a);
+  Loc r;
+  r.module = in_mod ? (int)ma * S.mod_n_t + (int)mt : -1;
+  r.layer = has_layer ? L : -1;
+  r.mat = crystal ? mat_c : has_layer ? mat_i : S.fill;
+  r.slot = crystal ? slot_c : has_layer ? slot_i : S.fill_slot;
+  r.crystal = crystal ? (int)ia * nt + (int)it : -1;
+  r.gid = crystal ? p * S.crystals_per_panel + r.module * S.crystals_per_module + base + r.crystal : -1;
   return r;
 }
 

@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   auto start_photon = [&](CScene &S, int which) {
     ph = which;
     x = src;
-    d = which ? Vec{-sdir.x, -sdir.y, -sdir.z} : sdir;
+    if (which) d = Vec{-sdir.x, -sdir.y, -sdir.z}; // photon A's direction is already in d
     e = 511.0f;
     L = 0.0f;
     seq = 0;
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     const float4 r = to_unit4(w);
     c_blocks += (draw && sid != 0u) ? 1u : 0u;
 
-    bool hit = false, ended = false, push = false;
+    bool hit = false, ended = false, push = false, start_a = false;
     int n_tested = 0;
     float sf[6];
     int s_module = 0;
@@ -322,8 +322,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
       emitted = true;
       const Vec bdir = photon_b_dir(S, sdir, r.z, r.w);
-      start_photon(S, 0);
+      d = sdir;
       sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
+      start_a = true; // photon A starts with the trip's other photon starts
     } else if (phase == P_PHANTOM) {
       const Lerp lp = lerp_at(e);
       const float mb = lerp1(S.maj_ph, lp);
@@ -591,10 +592,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
         staged = 0;
       }
     }
-    if (ended) {
-      if (ph == 0) start_photon(S, 1);
-      else phase = P_FETCH;
-    }
+    // ---- photon starts: A after the emission, B once A has ended
+    if (start_a || (ended && ph == 0)) start_photon(S, start_a ? 0 : 1);
+    else if (ended) phase = P_FETCH;
   }
   flush_stage(A, st, staged, lane, inst);
 
