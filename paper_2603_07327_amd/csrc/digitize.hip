@@ -1254,8 +1254,10 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const size_t tiles = tile_count(n);
   const size_t max_buckets = n / kBucketMean + 1024 + 2 * ni;
   const size_t scan_words = scan_scratch_words(std::max<size_t>(std::max<size_t>(256 * tiles, n), max_buckets));
+  // (each term one take() below, in the same order)
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
-                      align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) * 2 + align_up(ni * 4) * 10 + 1024;
+                      align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) + align_up(max_buckets * 4) +
+                      align_up(8) + align_up(ni * 4 * 3) + align_up(ni * 4 * kTabRows) + align_up(ni * 4);
   if (scr.bytes < need) {
     // a quarter of headroom: hit counts drift from call to call, and a
     // free + allocate pair costs about as much as the whole digitizer
@@ -1305,6 +1307,10 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   // first, n_events, cpp, rng, readout unit, dead-time unit, crystals per module, layer words
   uint32_t *d_tab = (uint32_t *)take(ni * 4 * kTabRows);
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
+  if ((size_t)(p - (char *)scr.buf) > scr.bytes) {
+    err = "digitize: scratch accounting does not cover its allocations";
+    return GPET_ERR_HIP;
+  }
   // pinned host words: [0, 16) scalars that kernels write directly (scan
   // totals, maximum time, failure flags), [16, 16 + ni) per-instance counts,
   // 3 ni words of bucket-map uploads, kTabRows ni words of instance table
