@@ -80,10 +80,15 @@ def digitizer_bytes(hits: int, singles: int, windowed: int, coinc: int) -> float
 
 
 def transport_source_hash() -> str:
+    """Hash of the transport kernel's sources without their // comments and
+    blank lines, so that a change of comments keeps the counters valid."""
     import hashlib
     h = hashlib.sha256()
     for f in TRANSPORT_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        for line in open(os.path.join(ROOT, f), encoding="utf-8"):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -249,8 +249,8 @@ gpet_status build_geometry(gpet_ctx *c, const gpet_scanner *g, std::vector<int> 
   return GPET_OK;
 }
 
-// Detector tables: one attenuation row per slot (staged in LDS by the
-// transport kernel) and the node-wise maximum of the attenuation over the
+// Detector tables: one attenuation row per slot (read by the transport
+// kernels) and the node-wise maximum of the attenuation over the
 // materials marked in `used` (the detector majorant).
 void detector_tables(const gpet_ctx *c, const std::vector<int> &slot_mat, const std::vector<bool> &used,
                      std::vector<float4> &rows, std::vector<float> &maj) {

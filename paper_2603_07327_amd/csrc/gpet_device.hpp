@@ -39,7 +39,7 @@ struct LayerD {
   float lo_t, hi_t, lo_a, hi_a; // crystal extent inside its pitch cell
   int n_t, n_a;
   int mat_crystal, mat_interval;
-  int slot_crystal, slot_interval; // rows of the detector table staged in LDS
+  int slot_crystal, slot_interval; // rows of the detector attenuation table
   int base;                        // first crystal id of the layer inside a module
   int pad_;
 };
@@ -75,7 +75,7 @@ struct DevScene {
   int crystals_per_module, crystals_per_panel;
   // attenuation (1/mm): per material rows of kTabStride float4 (PE, Compton, Rayleigh, total)
   const float4 *mu;      // at the nominal density
-  const float4 *mu_det;  // the detector's materials, one row per slot (staged in LDS)
+  const float4 *mu_det;  // the detector's materials, one row per slot
   int n_det_slots;
   const float4 *mu_mass; // per g/cm^3
   const float *maj_det;  // detector majorant

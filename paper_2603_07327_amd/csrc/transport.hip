@@ -14,9 +14,9 @@
 // plain run, many for a batched sweep): waves claim chunks of consecutive events
 // of one instance with one atomic and switch instance only once drained, so the
 // scene stays wave-uniform (scalar loads).
-// hits are staged per wave in LDS and written out 128 or more at a time (one atomic and
-// coalesced stores per flush).  The detector attenuation rows and majorant are
-// staged in LDS at kernel start.
+// Hits are staged per wave in LDS and written out kFlushAt or more at a time
+// (one atomic and coalesced stores per flush).  The detector attenuation rows
+// and majorant (a few KB) are read through the vector caches.
 #include "transport_common.hpp"
 
 namespace gpet {
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       }
     }
 
-    // ---- stage hits in LDS; write out 64 or more at a time
+    // ---- stage hits in LDS; write out kFlushAt or more at a time
     const uint64_t hm = __ballot(hit);
     if (hm) {
       if (hit) {

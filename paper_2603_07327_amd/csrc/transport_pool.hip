@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_transport_pool(RunArgs A) {
     c_scatter += scattered ? 1u : 0u;
     c_capped += capped ? 1u : 0u;
 
-    // ---- stage hits in LDS; write out 128 or more at a time
+    // ---- stage hits in LDS; write out kFlushAt or more at a time
     const uint64_t hm = __ballot(hit);
     if (hm) {
       if (hit) {
