@@ -265,6 +265,7 @@ struct gpet_mlp {
   double *row_loss = nullptr, *loss_sum = nullptr;
   uint32_t *flag = nullptr; // bit 0: a label outside the classes
   float *part = nullptr, *part_b = nullptr; // split-K partial weight gradients, partial bias sums
+  void *tstats = nullptr; // float2 (max, sum of exponentials) per row and 128-class tile of the logits
 };
 
 namespace gpet {

@@ -35,7 +35,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_BF16 = 3 };
+enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_BF16 = 3, EPI_BIAS_F32_STATS = 4 };
 
 // C[m][n] = sum_k A(m, k) B(k, n) over a padded problem (M a multiple of BM,
 // N of BN, K of 32).  A(m, k) = a[m lda + k] (AT: a[k lda + m]);
@@ -168,10 +168,14 @@ constexpr int kNtKmax = 256;
 constexpr int kNtRowB = kNtKmax + 8; // bf16 per weight-slab row in LDS
 constexpr size_t kNtLds = (size_t)(128 * kNtRowB + 2 * 256 * kLdsRow) * sizeof(uint16_t);
 
+// EPI_BIAS_F32_STATS also writes, per row and 128-column block, the maximum
+// of the logits of the columns below n_valid and the sum of their exponentials
+// relative to it: stats[row * gridDim.x + block column] = (max, sum).
 template <int EPI>
 __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a, int lda,
                                                  const uint16_t *__restrict__ b, int ldb, int K,
-                                                 const float *__restrict__ bias, void *__restrict__ out, int ldc) {
+                                                 const float *__restrict__ bias, void *__restrict__ out, int ldc,
+                                                 float2 *__restrict__ stats, int n_valid) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds_nt[];
   uint16_t *sbw = lds_nt;                   // 128 x kNtRowB weight slab
   uint16_t *sac = lds_nt + 128 * kNtRowB;   // 2 x 256 x kLdsRow activation stages
@@ -224,18 +228,68 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
     q ^= 1;
   }
   const int cn = lane & 15, rb4 = (lane >> 4) * 4;
+  if constexpr (EPI == EPI_BIAS_F32_STATS) {
+    // a row's 64 columns of this wave sit in the 16 lanes of its lane group
+    // (4 each): max and exponential sum over them, then the two waves of a
+    // row block (wn = 0, 64) merge through LDS (free after the last K step)
+    float *sred = (float *)lds_nt;
+    float rm[16], rs[16];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        const int m = m0 + wm + 16 * i + rb4 + qq, n = n0 + wn + 16 * j + cn;
-        const float v = acc[i][j][qq] + bias[n];
-        const size_t o = (size_t)m * ldc + n;
-        if constexpr (EPI == EPI_BIAS_RELU_BF16) ((uint16_t *)out)[o] = f2bf(fmaxf(v, 0.0f));
-        else ((float *)out)[o] = v;
+        const int m = m0 + wm + 16 * i + rb4 + qq;
+        float v[4], vm = -INFINITY;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = n0 + wn + 16 * j + cn;
+          const float x = acc[i][j][qq] + bias[n];
+          ((float *)out)[(size_t)m * ldc + n] = x;
+          v[j] = n < n_valid ? x : -INFINITY;
+          vm = fmaxf(vm, v[j]);
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) vm = fmaxf(vm, __shfl_xor(vm, o));
+        float sum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sum += v[j] > -INFINITY ? __expf(v[j] - vm) : 0.0f;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o);
+        rm[4 * i + qq] = vm;
+        rs[4 * i + qq] = sum;
+        if (wn == 64 && cn == 0) {
+          const int rl = wm + 16 * i + rb4 + qq;
+          sred[2 * rl] = vm;
+          sred[2 * rl + 1] = sum;
+        }
       }
+    __syncthreads();
+    if (wn == 0 && cn == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int rl = wm + 16 * i + rb4 + qq;
+          const float m1 = rm[4 * i + qq], s1 = rs[4 * i + qq], m2 = sred[2 * rl], s2 = sred[2 * rl + 1];
+          const float M = fmaxf(m1, m2);
+          const float S = (m1 > -INFINITY ? s1 * __expf(m1 - M) : 0.0f) + (m2 > -INFINITY ? s2 * __expf(m2 - M) : 0.0f);
+          stats[(size_t)(m0 + rl) * gridDim.x + blockIdx.x] = make_float2(M, S);
+        }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int m = m0 + wm + 16 * i + rb4 + qq, n = n0 + wn + 16 * j + cn;
+          const float v = acc[i][j][qq] + bias[n];
+          const size_t o = (size_t)m * ldc + n;
+          if constexpr (EPI == EPI_BIAS_RELU_BF16) ((uint16_t *)out)[o] = f2bf(fmaxf(v, 0.0f));
+          else ((float *)out)[o] = v;
+        }
+  }
 }
 
 // 128 x 128 tiles where both sizes allow them (the wide layers), else 64 x 64;
@@ -247,7 +301,7 @@ static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, 
   if constexpr (!AT && !BT && (EPI == EPI_BIAS_RELU_BF16 || EPI == EPI_BIAS_F32)) {
     if (M % 256 == 0 && N % 128 == 0 && K % kTk == 0 && K <= kNtKmax) {
       hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3(N / 128, M / 256), dim3(512), kNtLds, st, a, lda, b, ldb, K, bias, out,
-                         ldc);
+                         ldc, (float2 *)nullptr, 0);
       return;
     }
   }
@@ -491,6 +545,61 @@ __global__ void __launch_bounds__(256) k_sample_classes(const float *z, int ldz,
   }
 }
 
+// The same draw from the per-tile statistics of the last product: the row's
+// maximum and total from its (max, sum) pairs (one per 128-class tile, at
+// most 64), the tile whose cumulative mass reaches u * total, then the class
+// inside that tile from its 128 logits (two per lane) -- 1 KB read per row
+// instead of the whole row twice.  Sums run in another order than in
+// k_sample_classes, so a draw within rounding of a class boundary may land
+// on the neighbouring class.
+__global__ void __launch_bounds__(256) k_sample_tiles(const float2 *stats, int n_tiles, const float *z, int ldz, int C,
+                                                      uint32_t n, const uint32_t *ev, const uint32_t *meta,
+                                                      uint32_t k0, uint32_t k1, uint32_t inst_rng, uint32_t *cls,
+                                                      uint32_t *nonzero) {
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const float2 t = lane < n_tiles ? stats[(size_t)r * n_tiles + lane] : make_float2(-INFINITY, 0.0f);
+  float mx = t.x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  const float w = t.x > -INFINITY ? t.y * __expf(t.x - mx) : 0.0f;
+  float incl = w;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float tt = __shfl_up(incl, o);
+    if (lane >= o) incl += tt;
+  }
+  const float total = __shfl(incl, 63);
+  const uint4 wr = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
+  const float target = to_unit(wr.x) * total;
+  const uint64_t crossed = __ballot(incl >= target && lane < n_tiles);
+  const int T = crossed ? __ffsll((unsigned long long)crossed) - 1 : n_tiles - 1;
+  const float before = __shfl(incl - w, T);
+  const float *zr = z + (size_t)r * ldz;
+  const int c0 = T * 128 + 2 * lane;
+  const float p0 = c0 < C ? __expf(zr[c0] - mx) : 0.0f;
+  const float p1 = c0 + 1 < C ? __expf(zr[c0 + 1] - mx) : 0.0f;
+  const float part = p0 + p1;
+  float in2 = part;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float tt = __shfl_up(in2, o);
+    if (lane >= o) in2 += tt;
+  }
+  const uint64_t cr2 = __ballot(before + in2 >= target && c0 < C);
+  int c_out = min(T * 128 + 127, C - 1); // rounding left the target beyond the tile
+  if (cr2) {
+    const int L = __ffsll((unsigned long long)cr2) - 1;
+    const int mine = (before + in2 - part + p0 >= target || c0 + 1 >= C) ? c0 : c0 + 1;
+    c_out = __shfl(mine, L);
+  }
+  if (lane == 0) {
+    cls[r] = (uint32_t)c_out;
+    nonzero[r] = c_out != 0 ? 1u : 0u;
+  }
+}
+
 // one synthetic hit per entry with a class other than 0, at *hit_count + pos
 __global__ void k_emit_hits(uint32_t n, const uint32_t *cls, const uint32_t *pos, const uint32_t *ev,
                             const uint32_t *meta, const uint32_t *anchor, const float *e_in,
@@ -544,9 +653,11 @@ void free_workspace(gpet_mlp *q) {
     if (p) (void)hipFree(p);
   q->act.clear();
   for (void *p : {(void *)q->logits, (void *)q->dz[0], (void *)q->dz[1], (void *)q->yb, (void *)q->idx,
-                  (void *)q->row_loss, (void *)q->loss_sum, (void *)q->flag, (void *)q->part, (void *)q->part_b})
+                  (void *)q->row_loss, (void *)q->loss_sum, (void *)q->flag, (void *)q->part, (void *)q->part_b,
+                  (void *)q->tstats})
     if (p) (void)hipFree(p);
   q->flag = nullptr;
+  q->tstats = nullptr;
   q->part = q->part_b = nullptr;
   q->logits = nullptr;
   q->dz[0] = q->dz[1] = nullptr;
@@ -569,6 +680,7 @@ gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
     widest = std::max(widest, q->psize[l + 1]);
   }
   ok = ok && hipMalloc((void **)&q->logits, (size_t)need * q->psize[q->n_layers] * 4) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->tstats, (size_t)need * (q->psize[q->n_layers] / 128) * sizeof(float2)) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->dz[0], (size_t)need * widest * 2) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->dz[1], (size_t)need * widest * 2) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->yb, (size_t)need * 4) == hipSuccess;
@@ -603,6 +715,22 @@ void forward(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
     else
       gemm<false, false, EPI_BIAS_F32>(q->act[l], K, q->wb[l], K, (int)n_pad, N, K, bias, nullptr, q->logits, N, st);
   }
+}
+
+// forward pass for sampling: the last product also leaves per-tile row
+// statistics in q->tstats (the forward product kernel always applies: rows
+// padded to 256, widths to 128, K <= 256 for the hidden layers)
+void forward_sample(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
+  const int L = q->n_layers;
+  for (int l = 0; l + 1 < L; ++l) {
+    const int K = q->psize[l], N = q->psize[l + 1];
+    gemm<false, false, EPI_BIAS_RELU_BF16>(q->act[l], K, q->wb[l], K, (int)n_pad, N, K, q->bp + l * q->bp_stride,
+                                           nullptr, q->act[l + 1], N, st);
+  }
+  const int K = q->psize[L - 1], N = q->psize[L];
+  hipLaunchKernelGGL(k_gemm_nt<EPI_BIAS_F32_STATS>, dim3(N / 128, n_pad / 256), dim3(512), kNtLds, st, q->act[L - 1],
+                     K, q->wb[L - 1], K, K, q->bp + (L - 1) * q->bp_stride, (void *)q->logits, N, (float2 *)q->tstats,
+                     q->size[L]);
 }
 
 // loss of the rows in act[0] / yb and the gradient of the mean loss into gw / gb
@@ -652,15 +780,25 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
     return GPET_ERR_HIP;
   }
   const int C = q->size[q->n_layers], Cp = q->psize[q->n_layers];
+  // the tile statistics need the forward product kernel for the last layer
+  // (input width <= 256) and at most 64 tiles of 128 classes
+  const int Kl = q->psize[q->n_layers - 1];
+  const bool tiles = Kl <= kNtKmax && Kl % kTk == 0 && Cp / 128 <= 64;
   for (uint32_t off = 0; off < nq; off += kChunk) {
     const uint32_t n = std::min(kChunk, nq - off);
     const uint32_t n_pad = (uint32_t)pad_to((int)n, kRowPad);
     hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, Q.x + (size_t)6 * off,
                        (const int32_t *)nullptr, (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad,
                        q->act[0], (int32_t *)nullptr);
-    forward(q, n_pad, st);
-    hipLaunchKernelGGL(k_sample_classes, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, C, n, Q.ev + off,
-                       Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
+    if (tiles) {
+      forward_sample(q, n_pad, st);
+      hipLaunchKernelGGL(k_sample_tiles, dim3(cdiv(n, 4)), dim3(256), 0, st, (const float2 *)q->tstats, Cp / 128,
+                         q->logits, Cp, C, n, Q.ev + off, Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
+    } else {
+      forward(q, n_pad, st);
+      hipLaunchKernelGGL(k_sample_classes, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, C, n, Q.ev + off,
+                         Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
+    }
   }
   // nonzero flags -> positions; the class-0 count comes from the same scan
   unsigned long long *cnt = H.hit_count;
