@@ -1,0 +1,134 @@
+"""Parity at the benchmark's full size and launch configuration: design C,
+1e7 events per launch, source off centre, default launch shape (blocks per
+CU from the occupancy, search batch 16, lane schedule 0).
+
+The oracle cannot run 1e7 events in a test, but every random number is keyed
+by the event id, so it re-simulates sampled blocks of event ids one by one
+and their hits must match the GPU's hits of the same ids (RNG-matched: equal
+up to rare FP32-versus-FP64 branch flips).  The digitizer's adder and blur
+act per (event, crystal), so the singles of the sampled events are checked
+against the oracle's digitizer run on the GPU's own hits of those events;
+the coincidences, which couple events through time, are checked through
+properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import gpet_inputs as G
+
+pytestmark = pytest.mark.gpu
+
+N = 10_000_000
+POS = G.SWEEP_POSITIONS[3]
+
+
+@pytest.fixture(scope="module")
+def run():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    sc = G.small_animal_scene("C", POS, n_events=N)
+    c.set_scene(sc)
+    c.set_launch(0, 16, 0)
+    hits, st = c.transport(N, seed=1001)
+    singles, coinc = c.digitize(hits, seed=1001)
+    out = {"scene": sc, "ctx": c, "stats": st, "hits": hits.numpy(), "singles": singles.numpy(),
+           "coinc": (coinc[0].cpu().numpy(), coinc[1].cpu().numpy()), "n_crystals": c.info.n_crystals,
+           "cpp": c.info.crystals_per_panel}
+    yield out
+    c.close()
+
+
+def _blocks(rng, n_blocks=20, size=100):
+    starts = np.sort(rng.choice(N // size, n_blocks, replace=False)) * size
+    return [(int(s), size) for s in starts] + [(0, size), (N - size, size)]
+
+
+def test_sampled_events_match_oracle(run, oracle_mod):
+    o = oracle_mod.OracleScene(run["scene"])
+    g = run["hits"]
+    ev = g["event"].view(np.uint32)
+    order = np.argsort(ev, kind="stable")
+    evs = ev[order]
+    rng = np.random.default_rng(5)
+    n_ev = n_diff = n_hits = 0
+    for first, size in _blocks(rng):
+        rh, _ = o.transport(size, seed=1001, first=first)
+        lo, hi = np.searchsorted(evs, [first, first + size])
+        gh = {k: v[order[lo:hi]] for k, v in g.items()}
+        for e in range(first, first + size):
+            a = rh[rh["event"] == e]
+            b_sel = gh["event"].view(np.uint32) == e
+            gid_g = np.sort(gh["gid"][b_sel].view(np.uint32))
+            gid_o = np.sort(a["gid"])
+            n_ev += 1
+            n_hits += len(a)
+            if len(gid_g) != len(gid_o) or not np.array_equal(gid_g, gid_o):
+                n_diff += 1
+                continue
+            if len(a):
+                eg = np.sort(gh["edep_kev"][b_sel].astype(np.float64))
+                np.testing.assert_allclose(eg, np.sort(a["edep"]), rtol=2e-4, atol=2e-3)
+                tg = np.sort(gh["time_ps"][b_sel].view(np.uint64).astype(np.int64))
+                assert np.all(np.abs(tg - np.sort(a["time_ps"].astype(np.int64))) <= 1)
+    print(f"{n_ev} sampled events, {n_hits} oracle hits, {n_diff} events differing")
+    assert n_hits > 1000
+    assert n_diff <= max(3, 0.01 * n_ev)
+
+
+def test_sampled_singles_match_oracle_digitizer(run, oracle_mod):
+    o = oracle_mod.OracleScene(run["scene"])
+    g, s = run["hits"], run["singles"]
+    ev_h = g["event"].view(np.uint32)
+    ev_s = s["event"].view(np.uint32)
+    rng = np.random.default_rng(6)
+    pick = np.sort(rng.choice(N, 3000, replace=False)).astype(np.uint32)
+    hs = np.isin(ev_h, pick)
+    h = np.zeros(int(hs.sum()), dtype=np.dtype(oracle_mod.Hit))
+    h["event"] = ev_h[hs]
+    h["gid"] = g["gid"][hs].view(np.uint32)
+    h["edep"] = g["edep_kev"][hs]
+    h["depth"] = g["depth_mm"][hs]
+    h["time_ps"] = g["time_ps"][hs].view(np.uint64)
+    h["photon"] = g["aux"][hs].view(np.uint32) & 1
+    h["seq"] = g["aux"][hs].view(np.uint32) >> 8
+    so, _ = o.digitize(h, seed=1001)
+    ss = np.isin(ev_s, pick)
+    assert np.array_equal(ev_s[ss], so["event"])
+    assert np.array_equal(s["gid"][ss].view(np.uint32), so["gid"])
+    assert np.array_equal(s["time_ps"][ss].view(np.uint64), so["time_ps"])
+    np.testing.assert_allclose(s["edep_kev"][ss], so["edep"], rtol=1e-6, atol=1e-5)
+    np.testing.assert_allclose(s["energy_kev"][ss], so["energy"], rtol=1e-5, atol=1e-3)
+    edge = (np.abs(so["energy"] - 350) < 1e-2) | (np.abs(so["energy"] - 650) < 1e-2)
+    assert np.array_equal((s["in_window"][ss] != 0)[~edge], (so["in_window"] != 0)[~edge])
+    print(f"{len(so)} singles of {len(pick)} sampled events")
+    assert len(so) > 1000
+
+
+def test_full_size_properties(run):
+    g, s = run["hits"], run["singles"]
+    a, b = run["coinc"]
+    st = run["stats"]
+    assert st["events"] == N and st["capped"] == 0
+    gid = g["gid"].view(np.uint32)
+    assert gid.max() < run["n_crystals"]
+    assert np.all((g["edep_kev"] > 0) & (g["edep_kev"] <= 511.001))
+    # singles: (event, gid) strictly increasing, energies summed per crystal
+    ev = s["event"].view(np.uint32).astype(np.int64)
+    sg = s["gid"].view(np.uint32).astype(np.int64)
+    key = ev * (1 << 20) + sg
+    assert np.all(np.diff(key) > 0)
+    assert abs(float(s["edep_kev"].astype(np.float64).sum()) - float(g["edep_kev"].astype(np.float64).sum())) \
+        <= 1e-5 * float(g["edep_kev"].astype(np.float64).sum())
+    # coincidences: both singles in the window, within 3 ns, in different panels, in time order
+    win = s["in_window"].view(np.uint32)
+    t = s["time_ps"].view(np.uint64).astype(np.int64)
+    assert np.all(win[a] == 1) and np.all(win[b] == 1)
+    dt = t[b] - t[a]
+    assert np.all((dt >= 0) & (dt <= 3000))
+    assert np.all(sg[a] // run["cpp"] != sg[b] // run["cpp"])
+    assert np.all(np.diff(t[a]) >= 0)
+    assert len(a) > 100_000
+    print(f"{len(g['event'])} hits, {len(ev)} singles, {int(win.sum())} in window, {len(a)} coincidences")
