@@ -260,3 +260,49 @@ def test_batch_readout_and_sweep_match_plain(ctxs, response):
         assert per[i] == len(qa), i
         assert np.array_equal(counts[:, i], pc), (i, counts[:, i], pc)
     b.close()
+
+
+def test_batch_full_size_sampled_events(ctxs, oracle_mod):
+    """The benchmark's batched sweep at full size (144 instances, 3.7e8
+    events in one persistent launch): sampled blocks of event ids of sampled
+    instances, selected on the device, match the oracle's re-simulation of
+    the same ids with the instance's scanner, source and random-number id."""
+    import torch
+    from paper_2603_07327_amd.gpet import Batch
+    cb, _ = ctxs
+    mats, phys, inst = G.batch_sweep(n_scale=1.0, seed=0)
+    total = sum(d["n_events"] for d in inst)
+    cb.set_materials(mats, phys)
+    cb.set_phantom(None)
+    b = Batch(cb, inst)
+    hits, st = b.transport(seed=0, capacity=int(1.2 * total))
+    assert st["events"] == total and st["capped"] == 0
+    v = hits.view()
+    rng = np.random.default_rng(8)
+    n_ev = n_diff = n_hits = 0
+    for i in sorted(rng.choice(len(inst), 8, replace=False).tolist()):
+        d = inst[i]
+        o = oracle_mod.OracleScene(G.scene(mats, phys, d["scanner"], d["source"]))
+        size = min(100, d["n_events"])
+        for first in sorted({0, int(rng.integers(0, d["n_events"] - size + 1))}):
+            sel = (v.instance == i) & (v.event >= first) & (v.event < first + size)
+            idx = torch.nonzero(sel).flatten()
+            g_ev = v.event[idx].cpu().numpy().view(np.uint32)
+            g_gid = v.gid[idx].cpu().numpy().view(np.uint32)
+            g_e = v.edep_kev[idx].cpu().numpy()
+            rh, _ = o.transport(size, seed=0, first=first, instance=d["instance"])
+            for e in range(first, first + size):
+                a = rh[rh["event"] == e]
+                m = g_ev == e
+                n_ev += 1
+                n_hits += len(a)
+                if not np.array_equal(np.sort(g_gid[m]), np.sort(a["gid"])):
+                    n_diff += 1
+                    continue
+                if len(a):
+                    np.testing.assert_allclose(np.sort(g_e[m].astype(np.float64)), np.sort(a["edep"]),
+                                               rtol=2e-4, atol=2e-3)
+    print(f"{total} events in one launch; {n_ev} sampled events, {n_hits} oracle hits, {n_diff} differing")
+    assert n_hits > 100
+    assert n_diff <= max(3, 0.01 * n_ev)
+    b.close()
