@@ -505,6 +505,7 @@ typedef struct {
   or_vertex *v; /* trace mode */
   int64_t nv, vcap;
   int64_t cnt[8]; /* events, panel entries, steps, real, trials, searches, blocks, capped */
+  int analog;     /* analog tracking instead of Woodcock (a check of the latter) */
 } sink_t;
 
 static void push_hit(sink_t *k, const or_hit *h) {
@@ -578,6 +579,70 @@ static void phantom_voxel(const or_phantom *ph, const double x[3], int64_t *vox)
   *vox = ((int64_t)iz * ph->ny + (int64_t)iy) * ph->nx + (int64_t)ix;
 }
 
+/* ---- analog tracking: the photon flies to the next plane where the
+ * material may change, spending the sampled optical depth segment by segment
+ * (the textbook method that Woodcock tracking must agree with in law) ---- */
+#define ANALOG_NUDGE 1e-9 /* mm past a plane, so the next lookup sees the next cell */
+
+static double ahead(double c, double dc, double pos) {
+  if (dc > 0.0 && pos > c) return (pos - c) / dc;
+  if (dc < 0.0 && pos < c) return (pos - c) / dc;
+  return INFINITY;
+}
+
+/* distance from a phantom point to the next voxel face along d */
+static double next_voxel_plane(const or_phantom *P, const double x[3], const double d[3]) {
+  const double o[3] = {P->ox, P->oy, P->oz}, h[3] = {P->dx, P->dy, P->dz};
+  double b = INFINITY;
+  for (int i = 0; i < 3; i++) {
+    if (d[i] == 0.0) continue;
+    double idx = floor((x[i] - o[i]) / h[i]);
+    double lo = o[i] + idx * h[i], hi = lo + h[i];
+    b = dmin(b, d[i] > 0.0 ? ahead(x[i], d[i], hi) : ahead(x[i], d[i], lo > x[i] - 1e-12 ? lo - h[i] : lo));
+  }
+  return b;
+}
+
+/* distance from a panel-local point to the next plane where the material
+ * may change: panel faces, layer faces, module edges and the crystal edges of
+ * every layer (a superset of the material boundaries) */
+static double next_material_plane(const or_scanner *sc, const double l[3], const double d[3]) {
+  double b = dmin(ahead(l[0], d[0], 0.0), ahead(l[0], d[0], sc->depth));
+  for (int k = 0; k < sc->n_layers; k++) {
+    b = dmin(b, ahead(l[0], d[0], sc->layer[k].depth0));
+    b = dmin(b, ahead(l[0], d[0], sc->layer[k].depth0 + sc->layer[k].thick));
+  }
+  for (int ax = 1; ax <= 2; ax++) {
+    const double c = l[ax], dc = d[ax];
+    if (dc == 0.0) continue;
+    const double half = ax == 1 ? 0.5 * sc->width : 0.5 * sc->length;
+    b = dmin(b, dmin(ahead(c, dc, -half), ahead(c, dc, half)));
+    const int n_mod = ax == 1 ? sc->mod_n_t : sc->mod_n_a;
+    const double msz = ax == 1 ? sc->mod_t : sc->mod_a, gap = ax == 1 ? sc->gap_t : sc->gap_a;
+    const double step = msz + gap, m0 = -0.5 * (n_mod * msz + (n_mod - 1) * gap);
+    const int km = (int)floor((c - m0) / step);
+    for (int kk = km - 1; kk <= km + 1; kk++) {
+      if (kk < 0 || kk >= n_mod) continue;
+      const double ms = m0 + kk * step;
+      b = dmin(b, dmin(ahead(c, dc, ms), ahead(c, dc, ms + msz)));
+      for (int L = 0; L < sc->n_layers; L++) {
+        const or_layer *ly = &sc->layer[L];
+        const double off = ax == 1 ? ly->off_t : ly->off_a, pitch = ax == 1 ? ly->pitch_t : ly->pitch_a;
+        const double cr = ax == 1 ? ly->cryst_t : ly->cryst_a;
+        const int n = ax == 1 ? ly->n_t : ly->n_a;
+        const double lo = 0.5 * (pitch - cr), hi = 0.5 * (pitch + cr);
+        const int j = (int)floor((c - ms - off) / pitch);
+        for (int jj = j - 1; jj <= j + 1; jj++) {
+          if (jj < 0 || jj >= n) continue;
+          const double base = ms + off + jj * pitch;
+          b = dmin(b, dmin(ahead(c, dc, base + lo), ahead(c, dc, base + hi)));
+        }
+      }
+    }
+  }
+  return b;
+}
+
 /* Transport one photon: phantom phase, then panel search / in-panel phase. */
 static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uint32_t inst, int ph,
                    const double x0[3], const double d0[3], uint64_t t_e) {
@@ -607,7 +672,54 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
         vtx(k, ev, ph, OR_V_ENTER_PHANTOM, 0, -1, -1, -1, 0, 0, 0, (int)r.n, x, e, 0, d);
       }
     }
-    while (in) {
+    if (in && k->analog) { /* inside the box from its surface */
+      for (int i = 0; i < 3; i++) x[i] += ANALOG_NUDGE * d[i];
+      L += ANALOG_NUDGE;
+    }
+    while (in && k->analog) {
+      double u[4];
+      rng_next(&r, u);
+      k->cnt[6]++;
+      double tau = -log(u[0]), mu3[3], mu = 0;
+      int m = -1, real = 0;
+      for (;;) {
+        phantom_voxel(P, x, &vox);
+        if (vox < 0) break;
+        m = P->mat[vox];
+        mu_at(s, m, (double)P->dens[vox], e, mu3);
+        mu = mu3[0] + mu3[1] + mu3[2];
+        double sb = next_voxel_plane(P, x, d);
+        if (tau < mu * sb) {
+          double sdist = tau / mu;
+          for (int i = 0; i < 3; i++) x[i] += sdist * d[i];
+          L += sdist;
+          real = 1;
+          break;
+        }
+        tau -= mu * sb;
+        for (int i = 0; i < 3; i++) x[i] += (sb + ANALOG_NUDGE) * d[i];
+        L += sb + ANALOG_NUDGE;
+      }
+      if (!real) {
+        vtx(k, ev, ph, OR_V_EXIT, 0, -1, -1, -1, 0, 0, 0, (int)r.n, x, e, 0, d);
+        break;
+      }
+      k->cnt[2]++;
+      k->cnt[3]++;
+      if (++steps > MAX_STEPS) { k->cnt[7]++; return; }
+      int proc = pick_process(mu3, mu, u[2]);
+      double edep;
+      int tr;
+      int alive = interact(s, &r, proc, &e, d, 2.0 * PI * u[3], &edep, &tr);
+      k->cnt[4] += tr;
+      k->cnt[6] += tr + (proc == 3);
+      vtx(k, ev, ph, OR_V_STEP, 0, -1, -1, m, 1, proc, tr, (int)r.n, x, e, edep, d);
+      if (!alive) {
+        vtx(k, ev, ph, OR_V_DEAD, 0, -1, -1, m, 0, proc, 0, (int)r.n, x, 0, 0, d);
+        return;
+      }
+    }
+    while (in && !k->analog) {
       double u[4];
       rng_next(&r, u);
       k->cnt[6]++;
@@ -665,6 +777,68 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
     double xl[3], dl[3];
     to_local(P, x, xl);
     dir_to_local(P, d, dl);
+    if (k->analog) {
+      for (int i = 0; i < 3; i++) xl[i] += ANALOG_NUDGE * dl[i];
+      L += ANALOG_NUDGE;
+    }
+    for (; k->analog;) {
+      double u[4];
+      rng_next(&r, u);
+      k->cnt[6]++;
+      double tau = -log(u[0]), mu3[3], mu = 0;
+      int real = 0;
+      loc_t lc = {0, -1, -1, -1, -1};
+      for (;;) {
+        if (!inside_panel(sc, xl)) break;
+        lc = locate_local(s, p, xl, NULL);
+        mu_at(s, lc.mat, s->mat[lc.mat].density, e, mu3);
+        mu = mu3[0] + mu3[1] + mu3[2];
+        double sb = next_material_plane(sc, xl, dl);
+        if (tau < mu * sb) {
+          double sdist = tau / mu;
+          for (int i = 0; i < 3; i++) xl[i] += sdist * dl[i];
+          L += sdist;
+          real = 1;
+          break;
+        }
+        tau -= mu * sb;
+        for (int i = 0; i < 3; i++) xl[i] += (sb + ANALOG_NUDGE) * dl[i];
+        L += sb + ANALOG_NUDGE;
+      }
+      if (!real) { /* left the panel */
+        to_global(P, xl, x);
+        dir_to_global(P, dl, d);
+        vtx(k, ev, ph, OR_V_EXIT, 1, p, -1, -1, 0, 0, 0, (int)r.n, xl, e, 0, dl);
+        last = p;
+        break;
+      }
+      k->cnt[2]++;
+      k->cnt[3]++;
+      if (++steps > MAX_STEPS) { k->cnt[7]++; return; }
+      lc = locate_local(s, p, xl, NULL);
+      int proc = pick_process(mu3, mu, u[2]);
+      double edep;
+      int tr;
+      int alive = interact(s, &r, proc, &e, dl, 2.0 * PI * u[3], &edep, &tr);
+      k->cnt[4] += tr;
+      k->cnt[6] += tr + (proc == 3);
+      vtx(k, ev, ph, OR_V_STEP, 1, p, lc.gid, lc.mat, 1, proc, tr, (int)r.n, xl, e, edep, dl);
+      if (lc.gid >= 0 && proc != 3) {
+        or_hit h;
+        h.event = ev; h.photon = (uint32_t)ph; h.gid = (uint32_t)lc.gid; h.panel = (uint32_t)p;
+        h.module = (uint32_t)lc.module; h.layer = (uint32_t)lc.layer; h.crystal = (uint32_t)lc.crystal;
+        h.process = (uint32_t)proc; h.seq = seq++;
+        h.edep = edep; h.tof_ps = L / C_MM_PER_PS;
+        h.depth = xl[0]; h.t = xl[1]; h.a = xl[2];
+        h.time_ps = t_e + (uint64_t)floor(h.tof_ps + 0.5);
+        push_hit(k, &h);
+      }
+      if (!alive) {
+        vtx(k, ev, ph, OR_V_DEAD, 1, p, lc.gid, lc.mat, 0, proc, 0, (int)r.n, xl, 0, 0, dl);
+        return;
+      }
+    }
+    if (k->analog) continue;
     for (;;) {
       double u[4];
       rng_next(&r, u);
@@ -790,10 +964,11 @@ void or_set_threads(int n) {
 
 /* Transport events [first, first+n).  Writes at most cap hits in event order;
  * returns the number of hits produced (which may exceed cap). */
-int64_t or_transport(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed,
-                     uint32_t instance, or_hit *hits, int64_t cap, int64_t *counters) {
+static int64_t transport_mode(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                              or_hit *hits, int64_t cap, int64_t *counters, int analog) {
   int nt = or_num_threads();
   sink_t *sk = (sink_t *)calloc((size_t)nt, sizeof(sink_t));
+  for (int t = 0; t < nt; t++) sk[t].analog = analog;
 #pragma omp parallel num_threads(nt)
   {
 #ifdef _OPENMP
@@ -818,15 +993,36 @@ int64_t or_transport(const or_scene *s, uint64_t first, uint64_t n, uint64_t see
   return tot;
 }
 
-int64_t or_trace(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
-                 or_vertex *v, int64_t cap) {
+int64_t or_transport(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                     or_hit *hits, int64_t cap, int64_t *counters) {
+  return transport_mode(s, first, n, seed, instance, hits, cap, counters, 0);
+}
+
+int64_t or_transport_analog(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                            or_hit *hits, int64_t cap, int64_t *counters) {
+  return transport_mode(s, first, n, seed, instance, hits, cap, counters, 1);
+}
+
+static int64_t trace_mode(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                          or_vertex *v, int64_t cap, int analog) {
   sink_t k;
   memset(&k, 0, sizeof(k));
   k.v = v;
   k.vcap = cap;
+  k.analog = analog;
   for (uint64_t e = first; e < first + n; e++) event(s, &k, seed, (uint32_t)e, instance);
   free(k.hits);
   return k.nv;
+}
+
+int64_t or_trace(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                 or_vertex *v, int64_t cap) {
+  return trace_mode(s, first, n, seed, instance, v, cap, 0);
+}
+
+int64_t or_trace_analog(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                        or_vertex *v, int64_t cap) {
+  return trace_mode(s, first, n, seed, instance, v, cap, 1);
 }
 
 /* ------------------------------------------------------------------------ */

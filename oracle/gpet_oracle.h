@@ -16,7 +16,8 @@
  *   or_sample_rayleigh   KS against the Thomson CDF
  *   or_locate            brute-force enumeration of crystal boxes
  *   or_transport         narrow-beam exp(-mu L), black-ring solid angle,
- *                        collinearity, energy conservation, split-layer invariance
+ *                        collinearity, energy conservation, split-layer invariance,
+ *                        tallies equal in law to analog tracking
  *   or_digitize          brute-force adder / O(n^2) coincidence reference;
  *                        time and depth blur against the normal law, light
  *                        sharing against the neighbour set and its law, dead
@@ -160,8 +161,14 @@ void or_ray_locate(const or_scene *s, int64_t n_rays, const double *o, const dou
                    int32_t n_samp, double step, double *t_in, int32_t *ids6, double *bdist);
 int64_t or_transport(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed,
                      uint32_t instance, or_hit *hits, int64_t cap, int64_t *counters);
+/* the same with analog tracking (flights from material boundary to boundary)
+ * instead of Woodcock tracking: a check of the latter, equal in law */
+int64_t or_transport_analog(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed,
+                            uint32_t instance, or_hit *hits, int64_t cap, int64_t *counters);
 int64_t or_trace(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
                  or_vertex *v, int64_t cap);
+int64_t or_trace_analog(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed, uint32_t instance,
+                        or_vertex *v, int64_t cap);
 int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits,
                     const or_digitizer *dg, or_single *singles, int64_t cap_s,
                     uint32_t *coinc, int64_t cap_c, int64_t *n_coinc);

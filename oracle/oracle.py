@@ -130,9 +130,15 @@ def lib():
         L.or_locate.argtypes = [P(Scene), C.c_int64, P(C.c_double), P(C.c_int32), P(C.c_double)]
         L.or_ray_locate.argtypes = [P(Scene), C.c_int64, P(C.c_double), P(C.c_double), C.c_int32,
                                     C.c_double, P(C.c_double), P(C.c_int32), P(C.c_double)]
+        L.or_transport_analog.restype = C.c_int64
+        L.or_transport_analog.argtypes = [P(Scene), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                                          P(Hit), C.c_int64, P(C.c_int64)]
         L.or_transport.restype = C.c_int64
         L.or_transport.argtypes = [P(Scene), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
                                    P(Hit), C.c_int64, P(C.c_int64)]
+        L.or_trace_analog.restype = C.c_int64
+        L.or_trace_analog.argtypes = [P(Scene), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, P(Vertex),
+                                      C.c_int64]
         L.or_trace.restype = C.c_int64
         L.or_trace.argtypes = [P(Scene), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, P(Vertex),
                                C.c_int64]
@@ -291,14 +297,15 @@ class OracleScene:
         return t_in, ids, bd
 
     # -- transport
-    def transport(self, n_events, seed=0, first=0, instance=0):
-        """Returns (hits structured array, counters dict)."""
+    def transport(self, n_events, seed=0, first=0, instance=0, analog=False):
+        """Returns (hits structured array, counters dict); analog=True tracks
+        from material boundary to boundary instead of Woodcock tracking."""
         cnt = np.zeros(8, np.int64)
         cap = max(16, int(3 * n_events))
+        fn = lib().or_transport_analog if analog else lib().or_transport
         while True:
             buf = (Hit * cap)()
-            n = lib().or_transport(C.byref(self.s), first, n_events, seed, instance, buf, cap,
-                                   _ptr(cnt, C.c_int64))
+            n = fn(C.byref(self.s), first, n_events, seed, instance, buf, cap, _ptr(cnt, C.c_int64))
             if n <= cap:
                 break
             cap = int(n)
@@ -308,12 +315,13 @@ class OracleScene:
                  "capped")
         return arr, dict(zip(names, cnt.tolist()))
 
-    def trace(self, n_events, seed=0, first=0, instance=0, cap=None):
+    def trace(self, n_events, seed=0, first=0, instance=0, cap=None, analog=False):
         cap = cap or max(64, 200 * n_events)
         buf = (Vertex * cap)()
-        n = lib().or_trace(C.byref(self.s), first, n_events, seed, instance, buf, cap)
+        fn = lib().or_trace_analog if analog else lib().or_trace
+        n = fn(C.byref(self.s), first, n_events, seed, instance, buf, cap)
         if n > cap:
-            return self.trace(n_events, seed, first, instance, int(n))
+            return self.trace(n_events, seed, first, instance, int(n), analog)
         return np.frombuffer(buf, dtype=np.dtype(Vertex), count=n).copy()
 
     def digitize(self, hits, seed=0, fwhm_511=0.16, e_lo=350.0, e_hi=650.0, window_ps=3000,

@@ -74,10 +74,11 @@ def _photon_a_collided(v, region):
     return np.unique(a["event"])
 
 
-def test_narrow_beam_crystal_transmission(oracle_mod):
+@pytest.mark.parametrize("analog", [False, True], ids=["woodcock", "analog"])
+def test_narrow_beam_crystal_transmission(oracle_mod, analog):
     n = 200_000
     s = oracle_mod.OracleScene(_beam_scene())
-    v = s.trace(n)
+    v = s.trace(n, analog=analog)
     coll = _photon_a_collided(v, 1)
     p = math.exp(-s.mu(0, 511.0).sum() * 10.0)
     assert p == pytest.approx(0.45262, abs=5e-5)  # 0.7927 /cm over 10 mm
@@ -91,21 +92,23 @@ def test_narrow_beam_crystal_transmission(oracle_mod):
     assert abs(_z((f["process"] == 1).sum(), len(f), frac)) < 4
 
 
-def test_narrow_beam_phantom_slabs(oracle_mod):
+@pytest.mark.parametrize("analog", [False, True], ids=["woodcock", "analog"])
+def test_narrow_beam_phantom_slabs(oracle_mod, analog):
     """20 mm water then 5 mm LYSO at 3 g/cm^3: uncollided fraction
     exp(-(mu_w 20 + mu_L 5)); the LYSO slab sets the majorant, so water voxels
-    take the virtual-collision branch most of the time."""
+    take the virtual-collision branch most of the time (Woodcock); analog
+    flights cross the voxel faces instead."""
     ph = G.slab_phantom([2, 0], [20.0, 5.0], [1.0, 3.0])
     s = oracle_mod.OracleScene(_beam_scene(ph, beam_pos=(-1.0, 0.1, 0.1)))
     n = 200_000
-    v = s.trace(n)
+    v = s.trace(n, analog=analog)
     coll = _photon_a_collided(v, 0)
     mu_w = s.mu(2, 511.0).sum()                # water at 1.0 g/cm^3
     mu_l = s.mu(0, 511.0).sum() / 7.1 * 3.0    # LYSO scaled to 3 g/cm^3
     p = math.exp(-(mu_w * 20.0 + mu_l * 5.0))
     assert abs(_z(n - len(coll), n, p)) < 4
     virt = v[(v["kind"] == V_STEP) & (v["region"] == 0) & (v["accept"] == 0)]
-    assert len(virt) > 0
+    assert (len(virt) == 0) if analog else (len(virt) > 0)
 
 
 @pytest.mark.parametrize("case", ["ring8", "ring12"])
