@@ -376,8 +376,8 @@ gpet_status gpet_ctx_create(int device, void *hip_stream, gpet_ctx **out) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
     c->n_cu = cu;
-  static_assert(kCtrlWords <= 16, "control words");
-  if (hipMalloc((void **)&c->d_ctrl, 16 * sizeof(unsigned long long)) != hipSuccess) {
+  static_assert(kCtrlWords <= 16 && kCtrlWorkWord >= 16 && kCtrlWorkWord < kCtrlAlloc, "control words");
+  if (hipMalloc((void **)&c->d_ctrl, kCtrlAlloc * sizeof(unsigned long long)) != hipSuccess) {
     delete c;
     return GPET_ERR_HIP;
   }
@@ -626,7 +626,7 @@ static gpet_status run_args(gpet_ctx *c, uint64_t first, uint64_t n, uint64_t se
   A.n = (uint32_t)n;
   A.k0 = (uint32_t)seed;
   A.k1 = (uint32_t)(seed >> 32);
-  A.work = (uint32_t *)(c->d_ctrl + 0);
+  A.work = (uint32_t *)(c->d_ctrl + kCtrlWorkWord);
   A.hit_count = c->d_ctrl + 1;
   A.stats = c->d_ctrl + 2;
   A.search_batch = c->shape.search_batch;
@@ -645,10 +645,16 @@ static void set_hits(RunArgs &A, gpet_hits *h) {
   A.capacity = h->capacity;
 }
 
+// zeroes the control words (counts, work counters) and the event-claim counter
+static void reset_ctrl(gpet_ctx *c, hipStream_t st) {
+  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, st);
+  launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlWorkWord), 0u, 2, st);
+}
+
 // runs a prepared transport launch and reads back the counts
 static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, const LaunchShape &shape,
                                  gpet_hits *h, gpet_stats *stats, int mode = kModePlain) {
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
+  reset_ctrl(c, c->stream);
   if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
   if (A.total_chunks) launch_transport(A, shape, c->n_cu, c->stream, mode);
   if (c->timing) (void)hipEventRecord(c->ev[1], c->stream);
@@ -876,7 +882,7 @@ gpet_status gpet_trace(gpet_ctx *c, uint64_t first, uint32_t n, uint64_t seed, u
   A.vflt = vflt;
   A.vcount = counts;
   A.max_vertices = maxv;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
+  reset_ctrl(c, c->stream);
   launch_fill_u32((uint32_t *)counts, 0u, 2 * (size_t)n, c->stream);
   if (n) launch_trace(A, c->stream);
   s = hip_check(c, hipGetLastError(), "trace: launch");
@@ -1001,7 +1007,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     if (hipEventCreate(&e) != hipSuccess) return fail(c, GPET_ERR_HIP, "surrogate: event creation failed");
   float ms_t = 0.f, ms_n = 0.f;
   uint64_t entries = 0, none = 0;
-  launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, c->stream);
+  reset_ctrl(c, c->stream);
   for (uint64_t off = 0; off < n && !s; off += kSlice) {
     const uint64_t len = std::min(kSlice, n - off);
     RunArgs A;
@@ -1017,7 +1023,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     A.qtime = Q.time;
     A.pcount = c->d_ctrl + kCtrlPairs;
     A.pcap = Q.cap;
-    launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2, c->stream);        // event-chunk counter
+    launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlWorkWord), 0u, 2, c->stream); // event-chunk counter
     launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairs), 0u, 2, c->stream); // queue count
     (void)hipEventRecord(ev[0], c->stream);
     launch_transport(A, c->shape, c->n_cu, c->stream, kModeSurrogate);
@@ -1197,7 +1203,7 @@ gpet_status gpet_batch_create(gpet_ctx *c, int32_t n, const gpet_instance *inst,
   A.inst_count = dtab + 2 * n + 1;
   A.inst_id = dtab + 3 * n + 1;
   A.n_inst = (uint32_t)n;
-  A.work = (uint32_t *)(c->d_ctrl + 0);
+  A.work = (uint32_t *)(c->d_ctrl + kCtrlWorkWord);
   A.hit_count = c->d_ctrl + 1;
   A.stats = c->d_ctrl + 2;
   b->mat_gen = c->mat_gen;
@@ -1288,7 +1294,7 @@ gpet_status gpet_batch_graph_capture(gpet_batch *b, uint64_t seed, gpet_hits *h)
   hipGraphExec_t exec = nullptr;
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, cs); // a kernel, not a memset node
+    reset_ctrl(c, cs); // kernels, not memset nodes
     if (A.total_chunks) launch_transport(A, b->shape, c->n_cu, cs);
     ok = hipStreamEndCapture(cs, &g) == hipSuccess && g;
   }

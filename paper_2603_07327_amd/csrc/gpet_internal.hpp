@@ -18,12 +18,16 @@ struct SurSpecD {
   float e_min, ebin, tol, max_slope, front_tol;
 };
 
-// Device control words of a context (u64): [0] event-chunk counter (u32),
-// [1] hit count, [2, 2 + kStatCount) work counters in gpet_stats order,
+// Device control words of a context (u64): [0] spare, [1] hit count, [2, 2 + kStatCount) work counters in gpet_stats order,
 // [kCtrlPairs] pairs / surrogate entries.
 constexpr int kStatCount = 12;
 constexpr int kCtrlPairs = 2 + kStatCount;
 constexpr int kCtrlWords = kCtrlPairs + 1;
+// the event-claim counter of the transport sits on a cache line of its own,
+// apart from the hit counter: both take one atomic per wave now and then from
+// every CU, and sharing a line serialises them (about 5 % of a launch)
+constexpr int kCtrlWorkWord = 32;
+constexpr int kCtrlAlloc = 64; // u64 words of the control buffer
 
 // Transport kernel modes
 enum : int { kModePlain = 0, kModeTrace = 1, kModeRecord = 2, kModeSurrogate = 3 };
