@@ -609,10 +609,19 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     cnt[k] = t;
   }
   cnt[9] = c_trips;
+  // the block's four waves add up their counters in LDS: one atomic per
+  // counter and block instead of per wave (they share the hit counter's line)
+  __shared__ unsigned long long s_cnt[kWaves][kStatCount];
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < kStatCount; ++k)
-      if (cnt[k]) atomicAdd(A.stats + k, cnt[k]);
+    for (int k = 0; k < kStatCount; ++k) s_cnt[wave][k] = cnt[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatCount) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += s_cnt[w][threadIdx.x];
+    if (t) atomicAdd(A.stats + threadIdx.x, t);
   }
 }
 
