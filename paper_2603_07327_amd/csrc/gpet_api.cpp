@@ -376,12 +376,13 @@ gpet_status gpet_ctx_create(int device, void *hip_stream, gpet_ctx **out) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
     c->n_cu = cu;
-  static_assert(kCtrlWords <= 16 && kCtrlWorkWord >= 16 && kCtrlWorkWord < kCtrlAlloc, "control words");
+  static_assert(kCtrlWords <= 16 && kCtrlWorkWord >= 16 && kCtrlPairWord >= kCtrlWorkWord + 16 &&
+                    kCtrlPairWord < kCtrlAlloc, "control words");
   if (hipMalloc((void **)&c->d_ctrl, kCtrlAlloc * sizeof(unsigned long long)) != hipSuccess) {
     delete c;
     return GPET_ERR_HIP;
   }
-  if (hipHostMalloc((void **)&c->h_ctrl, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc((void **)&c->h_ctrl, kCtrlAlloc * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void **)&c->d_plain, kSceneBytes + 256) != hipSuccess ||
       hipHostMalloc((void **)&c->h_plain, kSceneBytes + 256, hipHostMallocDefault) != hipSuccess) {
     gpet_ctx_destroy(c);
@@ -645,10 +646,12 @@ static void set_hits(RunArgs &A, gpet_hits *h) {
   A.capacity = h->capacity;
 }
 
-// zeroes the control words (counts, work counters) and the event-claim counter
+// zeroes the control words (counts, work counters), the event-claim counter
+// and the pair / entry counter
 static void reset_ctrl(gpet_ctx *c, hipStream_t st) {
   launch_fill_u32((uint32_t *)c->d_ctrl, 0u, 2 * kCtrlWords, st);
   launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlWorkWord), 0u, 2, st);
+  launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairWord), 0u, 2, st);
 }
 
 // runs a prepared transport launch and reads back the counts
@@ -661,6 +664,9 @@ static gpet_status run_transport(gpet_ctx *c, const RunArgs &A, const LaunchShap
   gpet_status s = hip_check(c, hipGetLastError(), "transport: launch");
   if (s) return s;
   s = hip_check(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, kCtrlWords * 8, hipMemcpyDeviceToHost, c->stream), "transport: readback");
+  if (!s && mode == kModeRecord)
+    s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairWord, c->d_ctrl + kCtrlPairWord, 8, hipMemcpyDeviceToHost,
+                                    c->stream), "transport: readback");
   if (!s) s = hip_check(c, wait_stream(c->stream), "transport: kernel");
   if (s) return s;
   h->count = c->h_ctrl[1];
@@ -940,10 +946,10 @@ gpet_status gpet_surrogate_pairs(gpet_ctx *c, const gpet_surrogate_spec *spec, u
   A.plabel = pairs->label;
   A.pflags = pairs->flags;
   A.pevent = pairs->event;
-  A.pcount = c->d_ctrl + kCtrlPairs;
+  A.pcount = c->d_ctrl + kCtrlPairWord;
   A.pcap = pairs->capacity;
   s = run_transport(c, A, c->shape, h, stats, kModeRecord);
-  pairs->count = c->h_ctrl[kCtrlPairs];
+  pairs->count = c->h_ctrl[kCtrlPairWord];
   if (s) return s;
   if (pairs->count > pairs->capacity) return fail(c, GPET_ERR_CAPACITY, "surrogate pairs: pair capacity too small");
   return GPET_OK;
@@ -1021,19 +1027,19 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     A.qanchor = Q.anchor;
     A.qe = Q.e;
     A.qtime = Q.time;
-    A.pcount = c->d_ctrl + kCtrlPairs;
+    A.pcount = c->d_ctrl + kCtrlPairWord;
     A.pcap = Q.cap;
     launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlWorkWord), 0u, 2, c->stream); // event-chunk counter
-    launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairs), 0u, 2, c->stream); // queue count
+    launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairWord), 0u, 2, c->stream); // queue count
     (void)hipEventRecord(ev[0], c->stream);
     launch_transport(A, c->shape, c->n_cu, c->stream, kModeSurrogate);
     (void)hipEventRecord(ev[1], c->stream);
     s = hip_check(c, hipGetLastError(), "surrogate: transport launch");
-    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairs, c->d_ctrl + kCtrlPairs, 8, hipMemcpyDeviceToHost, c->stream),
+    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairWord, c->d_ctrl + kCtrlPairWord, 8, hipMemcpyDeviceToHost, c->stream),
                           "surrogate: readback");
     if (!s) s = hip_check(c, wait_stream(c->stream), "surrogate: transport");
     if (s) break;
-    const uint64_t nq = c->h_ctrl[kCtrlPairs];
+    const uint64_t nq = c->h_ctrl[kCtrlPairWord];
     if (nq > Q.cap) {
       s = fail(c, GPET_ERR_HIP, "surrogate: entry queue overflow");
       break;

@@ -19,7 +19,7 @@ struct SurSpecD {
 };
 
 // Device control words of a context (u64): [0] spare, [1] hit count, [2, 2 + kStatCount) work counters in gpet_stats order,
-// [kCtrlPairs] pairs / surrogate entries.
+// [kCtrlPairs] spare (pairs and surrogate entries are counted at kCtrlPairWord).
 constexpr int kStatCount = 12;
 constexpr int kCtrlPairs = 2 + kStatCount;
 constexpr int kCtrlWords = kCtrlPairs + 1;
@@ -27,6 +27,9 @@ constexpr int kCtrlWords = kCtrlPairs + 1;
 // apart from the hit counter: both take one atomic per wave now and then from
 // every CU, and sharing a line serialises them (about 5 % of a launch)
 constexpr int kCtrlWorkWord = 32;
+// the pair / surrogate-entry counter likewise (one atomic per wave and trip
+// that records or queues an entry)
+constexpr int kCtrlPairWord = 48;
 constexpr int kCtrlAlloc = 64; // u64 words of the control buffer
 
 // Transport kernel modes
