@@ -10,9 +10,10 @@
 // Every action that needs random numbers takes one Philox block, drawn at a
 // single call site at the top of the trip, so the costliest primitive runs
 // once per trip with all its lanes together instead of once per divergent
-// branch.  The one exception: the emission of a point or beam source draws its
-// time block inside the direction step, so photon A starts one trip earlier
-// (a trip of every event saved costs less than the second call site).  The launch covers a table of instances (scanner + source; one for a
+// branch.  The one exception: without a positron range the emission draws its
+// time block inside the direction step (point and beam sources) or the rod
+// point step (rod sources), so photon A starts one trip earlier (a trip of
+// every event saved costs less than the second call site).  The launch covers a table of instances (scanner + source; one for a
 // plain run, many for a batched sweep): waves claim chunks of consecutive events
 // of one instance with one atomic and switch instance only once drained, so the
 // scene stays wave-uniform (scalar loads).
@@ -319,7 +320,15 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
         phase = P_EMIT_RANGE;
         n = 3;
       } else {
-        phase = P_EMIT_TIME;
+        // block 2 (time, acollinearity) now, so photon A starts in this trip
+        const uint4 w2 = philox(A.k0, A.k1, make_uint4(2u, ev, inst_rng, 0u));
+        const float4 r2 = to_unit4(w2);
+        t_event = __umul64hi(((unsigned long long)w2.y << 32) | w2.x, S.duration_ps);
+        emitted = true;
+        const Vec bdir = photon_b_dir(S, sdir, r2.z, r2.w);
+        d = sdir;
+        sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
+        start_a = true;
       }
     } else if (phase == P_EMIT_RANGE) {
       // block 3: the annihilation point
