@@ -10,10 +10,10 @@
 // Every action that needs random numbers takes one Philox block, drawn at a
 // single call site at the top of the trip, so the costliest primitive runs
 // once per trip with all its lanes together instead of once per divergent
-// branch.  The one exception: without a positron range the emission draws its
-// time block inside the direction step (point and beam sources) or the rod
-// point step (rod sources), so photon A starts one trip earlier (a trip of
-// every event saved costs less than the second call site).  The launch covers a table of instances (scanner + source; one for a
+// branch.  The one exception: the emission draws its positron-range and time
+// blocks inside its last step (the direction step of point and beam sources,
+// the rod-point step of rod sources), so photon A starts one or two trips
+// earlier (a trip of every event saved costs less than the extra call sites).  The launch covers a table of instances (scanner + source; one for a
 // plain run, many for a batched sweep): waves claim chunks of consecutive events
 // of one instance with one atomic and switch instance only once drained, so the
 // scene stays wave-uniform (scalar loads).
@@ -169,6 +169,22 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     }
   };
 
+  // the end of an emission: the positron-range block (3) when asked for, then
+  // the time block (2) with the acollinearity, drawn here rather than in trips
+  // of their own; photon A starts at the trip's start site
+  bool start_a = false;
+  auto emit_finish = [&](CScene &S) {
+    if (S.prange_sigma > 0.0f)
+      src = positron_offset(S, src, to_unit4(philox(A.k0, A.k1, make_uint4(3u, ev, inst_rng, 0u))));
+    const uint4 w2 = philox(A.k0, A.k1, make_uint4(2u, ev, inst_rng, 0u));
+    const float4 r2 = to_unit4(w2);
+    t_event = __umul64hi(((unsigned long long)w2.y << 32) | w2.x, S.duration_ps);
+    const Vec bdir = photon_b_dir(S, sdir, r2.z, r2.w);
+    d = sdir;
+    sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
+    start_a = true;
+  };
+
   for (;;) {
     // ---- lanes without an event take the next ids: first from the current
     //      range, then from a claimed range of the same instance; a range of
@@ -271,7 +287,8 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     const float4 r = to_unit4(w);
     c_blocks += (draw && sid != 0u) ? 1u : 0u;
 
-    bool hit = false, ended = false, push = false, start_a = false;
+    bool hit = false, ended = false, push = false;
+    start_a = false;
     int n_tested = 0;
     float sf[6];
     int s_module = 0;
@@ -293,20 +310,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       if (S.src_kind == 2) sdir = Vec{S.bdx, S.bdy, S.bdz};
       if (S.src_kind == 1) {
         phase = P_EMIT_POS;
-      } else if (S.prange_sigma > 0.0f) {
-        phase = P_EMIT_RANGE; // block 1 is not needed
-        n = 3;
-      } else {
-        // blocks 1 and 3 are not needed: block 2 (time, acollinearity) now,
-        // so photon A starts in this trip
-        const uint4 w2 = philox(A.k0, A.k1, make_uint4(2u, ev, inst_rng, 0u));
-        const float4 r2 = to_unit4(w2);
-        t_event = __umul64hi(((unsigned long long)w2.y << 32) | w2.x, S.duration_ps);
+      } else { // block 1 is not needed
+        emit_finish(S);
         emitted = true;
-        const Vec bdir = photon_b_dir(S, sdir, r2.z, r2.w);
-        d = sdir;
-        sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
-        start_a = true;
       }
     } else if (phase == P_EMIT_POS) {
       // block 1: point in the chosen rod (rod ~ volume, uniform in its disk and length)
@@ -316,34 +322,8 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       const float *rd = S.rods + 5 * i;
       const float rr = rd[2] * hw_sqrt(q_u1);
       src = Vec{rd[0] + rr * cos_rev(r.x), rd[1] + rr * sin_rev(r.x), rd[3] + r.y * (rd[4] - rd[3])};
-      if (S.prange_sigma > 0.0f) {
-        phase = P_EMIT_RANGE;
-        n = 3;
-      } else {
-        // block 2 (time, acollinearity) now, so photon A starts in this trip
-        const uint4 w2 = philox(A.k0, A.k1, make_uint4(2u, ev, inst_rng, 0u));
-        const float4 r2 = to_unit4(w2);
-        t_event = __umul64hi(((unsigned long long)w2.y << 32) | w2.x, S.duration_ps);
-        emitted = true;
-        const Vec bdir = photon_b_dir(S, sdir, r2.z, r2.w);
-        d = sdir;
-        sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
-        start_a = true;
-      }
-    } else if (phase == P_EMIT_RANGE) {
-      // block 3: the annihilation point
-      src = positron_offset(S, src, r);
-      phase = P_EMIT_TIME;
-      n = 2;
-    } else if (phase == P_EMIT_TIME) {
-      // block 2: event time uniform on [0, T) from the raw 64-bit word; photon
-      // A starts along sdir, photon B will start along -sdir
-      t_event = __umul64hi(((unsigned long long)w.y << 32) | w.x, S.duration_ps);
+      emit_finish(S);
       emitted = true;
-      const Vec bdir = photon_b_dir(S, sdir, r.z, r.w);
-      d = sdir;
-      sdir = Vec{-bdir.x, -bdir.y, -bdir.z};
-      start_a = true; // photon A starts with the trip's other photon starts
     } else if (phase == P_PHANTOM) {
       const Lerp lp = lerp_at(e);
       const float mb = lerp1(S.maj_ph, lp);

@@ -6,9 +6,10 @@
 namespace gpet {
 
 // emission runs event-stream blocks 0 (direction), 1 (rod point), 3 (positron
-// range) and 2 (time, acollinearity), each phase drawing one block; without a
-// positron range the lane kernel draws block 2 inside P_EMIT_DIR (point and
-// beam sources) or P_EMIT_POS (rod sources)
+// range) and 2 (time, acollinearity), each phase drawing one block in the
+// photon-pool kernel; the lane kernel draws blocks 3 and 2 inside P_EMIT_DIR
+// (point and beam sources) or P_EMIT_POS (rod sources) and never enters
+// P_EMIT_RANGE or P_EMIT_TIME
 enum : int {
   P_FETCH = 0, P_EMIT_DIR = 1, P_EMIT_POS = 2, P_EMIT_RANGE = 3, P_EMIT_TIME = 4, P_PHANTOM = 5,
   P_SEARCH = 6, P_PANEL = 7, P_KAHN = 8, P_RAYLEIGH = 9, P_DONE = 10
