@@ -593,7 +593,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the event-parallel sharding "
-                                   "across GPUs is described in DESIGN.md but not built"}))
+                                   "across GPUs (each GPU a disjoint event range, windowed singles "
+                                   "exchanged by time bucket before the coincidence sort) is not built"}))
         sys.exit(2)
 
     import torch
