@@ -9,7 +9,9 @@ up to rare FP32-versus-FP64 branch flips).  The digitizer's adder and blur
 act per (event, crystal), so the singles of the sampled events are checked
 against the oracle's digitizer run on the GPU's own hits of those events;
 the coincidences, which couple events through time, are checked through
-properties that hold at any size.
+properties that hold at any size.  The hot-rod workload (rod source in the
+voxelized water cylinder, design C) gets the same sampled-event check at 1e7
+events, so phantom tracking is covered at its full launch size too.
 """
 import numpy as np
 import pytest
@@ -46,16 +48,16 @@ def _blocks(rng, n_blocks=20, size=100):
     return [(int(s), size) for s in starts] + [(0, size), (N - size, size)]
 
 
-def test_sampled_events_match_oracle(run, oracle_mod):
-    o = oracle_mod.OracleScene(run["scene"])
-    g = run["hits"]
+def _compare_sampled(scene, g, oracle_mod, seed, rng, n_blocks=20):
+    """Re-simulate sampled blocks of event ids in the oracle and compare each
+    event's hits (crystal ids exactly; energies and times to FP32 rounding)."""
+    o = oracle_mod.OracleScene(scene)
     ev = g["event"].view(np.uint32)
     order = np.argsort(ev, kind="stable")
     evs = ev[order]
-    rng = np.random.default_rng(5)
     n_ev = n_diff = n_hits = 0
-    for first, size in _blocks(rng):
-        rh, _ = o.transport(size, seed=1001, first=first)
+    for first, size in _blocks(rng, n_blocks):
+        rh, _ = o.transport(size, seed=seed, first=first)
         lo, hi = np.searchsorted(evs, [first, first + size])
         gh = {k: v[order[lo:hi]] for k, v in g.items()}
         for e in range(first, first + size):
@@ -73,8 +75,40 @@ def test_sampled_events_match_oracle(run, oracle_mod):
                 np.testing.assert_allclose(eg, np.sort(a["edep"]), rtol=2e-4, atol=2e-3)
                 tg = np.sort(gh["time_ps"][b_sel].view(np.uint64).astype(np.int64))
                 assert np.all(np.abs(tg - np.sort(a["time_ps"].astype(np.int64))) <= 1)
+    return n_ev, n_diff, n_hits
+
+
+def test_sampled_events_match_oracle(run, oracle_mod):
+    n_ev, n_diff, n_hits = _compare_sampled(run["scene"], run["hits"], oracle_mod, 1001, np.random.default_rng(5))
     print(f"{n_ev} sampled events, {n_hits} oracle hits, {n_diff} events differing")
     assert n_hits > 1000
+    assert n_diff <= max(3, 0.01 * n_ev)
+
+
+@pytest.fixture(scope="module")
+def rods_run():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    c = Context(0)
+    sc = G.hot_rod_scene(n_events=N)
+    c.set_scene(sc)
+    c.set_launch(0, 16, 0)
+    hits, st = c.transport(N, seed=1002)
+    out = {"scene": sc, "stats": st, "hits": hits.numpy(), "n_crystals": c.info.n_crystals}
+    yield out
+    c.close()
+
+
+def test_hot_rods_sampled_events_match_oracle(rods_run, oracle_mod):
+    st, g = rods_run["stats"], rods_run["hits"]
+    assert st["events"] == N and st["capped"] == 0
+    assert g["gid"].view(np.uint32).max() < rods_run["n_crystals"]
+    n_ev, n_diff, n_hits = _compare_sampled(rods_run["scene"], g, oracle_mod, 1002, np.random.default_rng(7),
+                                            n_blocks=10)
+    print(f"hot rods: {len(g['event'])} hits; {n_ev} sampled events, {n_hits} oracle hits, {n_diff} differing")
+    assert n_hits > 200
     assert n_diff <= max(3, 0.01 * n_ev)
 
 
