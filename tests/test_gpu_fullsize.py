@@ -11,7 +11,8 @@ against the oracle's digitizer run on the GPU's own hits of those events;
 the coincidences, which couple events through time, are checked through
 properties that hold at any size.  The hot-rod workload (rod source in the
 voxelized water cylinder, design C) gets the same sampled-event check at 1e7
-events, so phantom tracking is covered at its full launch size too.
+events, so phantom tracking is covered at its full launch size too, and so
+does the source with acollinearity and positron range on.
 """
 import numpy as np
 import pytest
@@ -166,3 +167,29 @@ def test_full_size_properties(run):
     assert np.all(np.diff(t[a]) >= 0)
     assert len(a) > 100_000
     print(f"{len(g['event'])} hits, {len(ev)} singles, {int(win.sum())} in window, {len(a)} coincidences")
+
+
+def test_source_physics_sampled_events_match_oracle(oracle_mod):
+    """The benchmark's optional-physics form at full size: design C, source at
+    the centre with 0.5 deg acollinearity and a 0.102 mm positron range."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_07327_amd.gpet import Context
+    sc = G.small_animal_scene("C", (0.0, 0.0, 0.0), n_events=N)
+    src = G.point_source((0.0, 0.0, 0.0), N)
+    src.update({"acolinearity_fwhm_deg": 0.5, "positron_range_fwhm_mm": 0.102})
+    sc["source"] = src
+    c = Context(0)
+    try:
+        c.set_scene(sc)
+        c.set_launch(0, 16, 0)
+        hits, st = c.transport(N, seed=1003)
+        g = hits.numpy()
+    finally:
+        c.close()
+    assert st["events"] == N and st["capped"] == 0
+    n_ev, n_diff, n_hits = _compare_sampled(sc, g, oracle_mod, 1003, np.random.default_rng(8), n_blocks=10)
+    print(f"source physics: {len(g['event'])} hits; {n_ev} sampled events, {n_hits} oracle hits, {n_diff} differing")
+    assert n_hits > 200
+    assert n_diff <= max(3, 0.01 * n_ev)
