@@ -37,7 +37,7 @@ def run():
     c.set_launch(0, 16, 0)
     hits, st = c.transport(N, seed=1001)
     singles, coinc = c.digitize(hits, seed=1001)
-    out = {"scene": sc, "ctx": c, "stats": st, "hits": hits.numpy(), "singles": singles.numpy(),
+    out = {"scene": sc, "ctx": c, "stats": st, "hits_t": hits, "hits": hits.numpy(), "singles": singles.numpy(),
            "coinc": (coinc[0].cpu().numpy(), coinc[1].cpu().numpy()), "n_crystals": c.info.n_crystals,
            "cpp": c.info.crystals_per_panel}
     yield out
@@ -193,3 +193,40 @@ def test_source_physics_sampled_events_match_oracle(oracle_mod):
     print(f"source physics: {len(g['event'])} hits; {n_ev} sampled events, {n_hits} oracle hits, {n_diff} differing")
     assert n_hits > 200
     assert n_diff <= max(3, 0.01 * n_ev)
+
+
+def test_sampled_singles_with_response_match_oracle(run, oracle_mod):
+    """Time and DOI blur and light sharing (dead time off, as it couples events)
+    on the full hit list; the singles of 3000 sampled events against the oracle
+    digitizer run on the GPU's hits of those events with the same response."""
+    resp = {"time_fwhm_ps": 300.0, "doi_fwhm_mm": 2.0, "light_sharing": 0.1}
+    sg, _ = run["ctx"].digitize(run["hits_t"], seed=1004, response=resp)
+    s = sg.numpy()
+    g = run["hits"]
+    ev_h = g["event"].view(np.uint32)
+    pick = np.sort(np.random.default_rng(9).choice(N, 3000, replace=False)).astype(np.uint32)
+    hs = np.isin(ev_h, pick)
+    h = np.zeros(int(hs.sum()), dtype=np.dtype(oracle_mod.Hit))
+    h["event"] = ev_h[hs]
+    h["gid"] = g["gid"][hs].view(np.uint32)
+    h["edep"] = g["edep_kev"][hs]
+    h["depth"] = g["depth_mm"][hs]
+    h["time_ps"] = g["time_ps"][hs].view(np.uint64)
+    h["photon"] = g["aux"][hs].view(np.uint32) & 1
+    h["seq"] = g["aux"][hs].view(np.uint32) >> 8
+    o = oracle_mod.OracleScene(run["scene"])
+    so, _ = o.digitize(h, seed=1004, time_fwhm_ps=300.0, doi_fwhm_mm=2.0, light_sharing=0.1)
+    so0, _ = o.digitize(h, seed=1004)
+    ss = np.isin(s["event"].view(np.uint32), pick)
+    assert np.array_equal(s["event"][ss].view(np.uint32), so["event"])
+    assert np.array_equal(s["gid"][ss].view(np.uint32), so["gid"])
+    dt = s["time_ps"][ss].view(np.int64) - so["time_ps"].astype(np.int64)
+    assert np.all(np.abs(dt) <= 1) and np.count_nonzero(dt) <= 1e-3 * len(so) + 5
+    np.testing.assert_allclose(s["depth_mm"][ss], so["depth"], rtol=0, atol=1e-4)
+    np.testing.assert_allclose(s["energy_kev"][ss], so["energy"], rtol=1e-5, atol=1e-3)
+    edge = (np.abs(so["energy"] - 350) < 1e-2) | (np.abs(so["energy"] - 650) < 1e-2)
+    assert np.array_equal((s["in_window"][ss].view(np.uint32) == 1)[~edge], (so["in_window"] != 0)[~edge])
+    assert len(so0) == len(so)
+    moved = int(np.count_nonzero(so0["gid"] != so["gid"]))
+    print(f"{len(so)} singles of {len(pick)} sampled events with the response on, {moved} read by a neighbour")
+    assert len(so) > 1000 and moved > 0.03 * len(so)
