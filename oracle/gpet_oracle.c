@@ -891,6 +891,12 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
   }
 }
 
+/* Event time (Sec. 2.3: a fixed number of decays of a constant activity, so
+ * the times are uniform over the acquisition [0, T)): the 64-bit word X of
+ * the event stream read as a fraction X / 2^64 of T, floor(X T / 2^64),
+ * taken exactly as the high half of the 128-bit product. */
+uint64_t or_event_time(uint64_t X, uint64_t T) { return (uint64_t)(((unsigned __int128)X * T) >> 64); }
+
 /* Event: the annihilation point and an isotropic direction from the event
  * stream; photon A leaves along +d, photon B along -d, both at 511 keV
  * (Sec. 2.3: no positron range, annihilation at the emission site).
@@ -908,8 +914,7 @@ static void event(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uint
   rng_next(&r, u1);
   uint32_t w[4];
   rng_raw(&r, 2, w);
-  uint64_t X = ((uint64_t)w[1] << 32) | w[0];
-  uint64_t t_e = (uint64_t)(((unsigned __int128)X * s->src.duration_ps) >> 64);
+  uint64_t t_e = or_event_time(((uint64_t)w[1] << 32) | w[0], s->src.duration_ps);
   double ct = 2.0 * u0[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * PI * u0[1];
   double d[3] = {st * cos(ph), st * sin(ph), ct};
   double x[3] = {s->src.pos[0], s->src.pos[1], s->src.pos[2]};
@@ -1062,8 +1067,7 @@ static int cmp_single_unit_time(const void *a, const void *b) {
  *  readout - at module (panel) level the crystal singles of one event in one
  *            module (panel) merge into one single: energies summed, the
  *            earliest time, the crystal and depth of the largest deposit (the
- *            lower crystal id on a tie, energies compared in single
- *            precision) -- the readout levels of Sec. 2.1;
+ *            lower crystal id on a tie) -- the readout levels of Sec. 2.1;
  *  blur    - Gaussian with FWHM(E) = fwhm_511 * sqrt(511 E) (16 % at 511 keV,
  *            Sec. 2.3), normal deviate by Box-Muller from the digitizer stream;
  *  time    - (timing resolution, optional) the time moves by a normal
@@ -1127,9 +1131,8 @@ int64_t or_digitize(const or_scene *s, const or_hit *hits, int64_t n_hits, const
       while (j < ns && sg[j].event == sg[i].event && sg[j].gid / G == sg[i].gid / G) {
         e += sg[j].edep;
         if (sg[j].time_ps < tm) tm = sg[j].time_ps;
-        /* the winner is an argmax decided in floating point: taken in single
-         * precision, the precision the crystal energies are kept in on the GPU */
-        if ((float)sg[j].edep > (float)sg[best].edep) best = j;
+        /* the crystal with the largest deposit (the first, i.e. lowest id, on a tie) */
+        if (sg[j].edep > sg[best].edep) best = j;
         j++;
       }
       or_single q = sg[best]; /* best >= i >= m: read before the slot is reused */

@@ -151,6 +151,7 @@ typedef struct {
 
 void or_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, int64_t n);
 double or_sigma_kn(double e_kev); /* barn per electron */
+uint64_t or_event_time(uint64_t X, uint64_t T); /* floor(X T / 2^64) */
 int or_prepare(or_scene *s);
 void or_mu(const or_scene *s, int m, double e, double mu3[3]); /* 1/mm at nominal density */
 int64_t or_sample_compton(double e_kev, int64_t n, uint64_t seed, double *cos_t, double *e_out,

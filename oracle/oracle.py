@@ -121,6 +121,8 @@ def lib():
         L.or_philox.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32), P(C.c_uint32), C.c_int64]
         L.or_sigma_kn.restype = C.c_double
         L.or_sigma_kn.argtypes = [C.c_double]
+        L.or_event_time.restype = C.c_uint64
+        L.or_event_time.argtypes = [C.c_uint64, C.c_uint64]
         L.or_prepare.argtypes = [P(Scene)]
         L.or_mu.argtypes = [P(Scene), C.c_int, C.c_double, P(C.c_double)]
         L.or_sample_compton.restype = C.c_int64
@@ -167,6 +169,11 @@ def philox(seed: int, ctr: np.ndarray) -> np.ndarray:
 
 def sigma_kn(e_kev: float) -> float:
     return lib().or_sigma_kn(e_kev)
+
+
+def event_time(x: int, duration_ps: int) -> int:
+    """Event time of the 64-bit event-stream word x on an acquisition of duration_ps."""
+    return int(lib().or_event_time(x, duration_ps))
 
 
 def sample_compton(e_kev, n, seed=0):
