@@ -352,6 +352,43 @@ class OracleScene:
         singles = np.frombuffer(sg, dtype=np.dtype(Single), count=ns).copy()
         return singles, cc[: nc.value].copy()
 
+    def tallies(self, hits, singles, doi_bins=200):
+        """Scanner tallies of this scene's detector (see :func:`tallies`)."""
+        return tallies(hits, singles, self.n_crystals, float(self.s.scan.depth), doi_bins)
+
+
+def tallies(hits, singles, n_crystals, panel_depth, doi_bins=200):
+    """The scanner tallies the paper reads its results from (Sec. 2.3
+    sensitivity and energy windows; Sec. 3.1, Fig. 3: depth-of-interaction
+    histograms of the hits), written out one item at a time:
+
+    * ``hits_per_crystal[g]``: hits recorded in crystal g;
+    * ``singles_per_crystal[g]``: singles of crystal g inside the energy
+      window and not lost to dead time;
+    * ``energy_spectrum[k]``: live singles whose blurred energy E lies in
+      [k, k + 1) keV, k = 0..699 (energies outside [0, 700) are not counted);
+    * ``doi[b]``: hits whose depth below the panel's front face lies in
+      [b, b + 1) * panel_depth / doi_bins; depths outside the panel go to the
+      first or last bin.
+    """
+    hpc = np.zeros(n_crystals, np.int64)
+    spc = np.zeros(n_crystals, np.int64)
+    spec = np.zeros(700, np.int64)
+    doi = np.zeros(doi_bins, np.int64)
+    for g, d in zip(hits["gid"].tolist(), hits["depth"].tolist()):
+        hpc[g] += 1
+        b = int(np.floor(d / panel_depth * doi_bins))
+        doi[min(max(b, 0), doi_bins - 1)] += 1
+    for g, e, w, lost in zip(singles["gid"].tolist(), singles["energy"].tolist(),
+                             singles["in_window"].tolist(), singles["lost"].tolist()):
+        if lost:
+            continue
+        if w:
+            spc[g] += 1
+        if 0.0 <= e < 700.0:
+            spec[int(np.floor(e))] += 1
+    return {"hits_per_crystal": hpc, "singles_per_crystal": spc, "energy_spectrum": spec, "doi": doi}
+
 
 def num_threads() -> int:
     return lib().or_num_threads()

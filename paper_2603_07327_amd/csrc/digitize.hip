@@ -764,13 +764,14 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
 // Per-instance constants of the digitizer (device arrays of n_inst entries).
 struct InstTab {
   const uint32_t *first, *n_events, *cpp, *rng;
+  const uint32_t *ncr; // crystals of the instance's scanner
   uint32_t n_inst;
 };
 
 // key = instance | (event - first) | gid | photon | index of the hit within its
 // photon (7 bits, saturated): unique per hit, so the sorted order is fixed.
-// Hits outside their instance's event range or with a crystal id of more than
-// gid_bits bits are flagged (*flag = 2).
+// Hits outside their instance's event range or with a crystal id outside the
+// instance's scanner are flagged (*flag = 2).
 __global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux,
                            const uint32_t *hinst, InstTab T, int gid_bits, int inst_shift, unsigned long long *key,
                            uint32_t *val, uint32_t *flag) {
@@ -781,7 +782,8 @@ __global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, co
   const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
   uint32_t e = 0;
   const uint32_t g = gid[i];
-  if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in] || (gid_bits < 32 && (g >> gid_bits) != 0)) {
+  if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in] || g >= T.ncr[in] ||
+      (gid_bits < 32 && (g >> gid_bits) != 0)) {
     *flag = 2u;
   } else {
     e = ev[i] - T.first[in];
@@ -865,7 +867,7 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, ui
                                               uint32_t k1, float fwhm, float e_lo, float e_hi, uint32_t *spp,
                                               uint32_t *spec, unsigned long long *s_time, float time_sigma,
                                               float *s_depth, float doi_sigma, unsigned long long ls_thresh,
-                                              const uint32_t *geo, unsigned long long *block_max) {
+                                              const uint32_t *geo, unsigned long long *block_max, uint32_t n_spp) {
   __shared__ unsigned long long s_max[4];
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long tm = 0; // largest time stamp of all singles (every window's keys fit its width)
@@ -892,7 +894,7 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, ui
         s_gid[i] = gid;
       }
     }
-    if (spp && in) atomicAdd(&spp[gid], 1u);
+    if (spp && in && gid < n_spp) atomicAdd(&spp[gid], 1u);
     if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
     tm = s_time[i];
     if (time_sigma > 0.0f) { // timing resolution: rounded to the ps, not below 0
@@ -1074,11 +1076,14 @@ __global__ void __launch_bounds__(256) k_coinc_inst_counts(size_t n, const uint3
       [&](size_t k) { return cnt[k]; });
 }
 
-__global__ void k_hit_tallies(size_t n, const uint32_t *gid, const float *depth, uint32_t *hpc, uint32_t *doi,
-                              int doi_bins, float panel_depth) {
+// runs after the hit keys have validated every crystal id; the bound on the
+// per-crystal histogram is kept anyway, so no id can write past it
+__global__ void k_hit_tallies(size_t n, const uint32_t *gid, const float *depth, uint32_t *hpc, uint32_t n_cr,
+                              uint32_t *doi, int doi_bins, float panel_depth) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (hpc) atomicAdd(&hpc[gid[i]], 1u);
+  const uint32_t g = gid[i];
+  if (hpc && g < n_cr) atomicAdd(&hpc[g], 1u);
   if (doi) {
     int b = (int)floorf(depth[i] / panel_depth * (float)doi_bins);
     b = b < 0 ? 0 : (b >= doi_bins ? doi_bins - 1 : b);
@@ -1214,22 +1219,23 @@ __global__ void __launch_bounds__(256) k_dead_nonparalyzable(uint32_t n_runs, co
 // lost singles leave the window (bit 1 of in_window); the in-window tallies
 // and the spectrum count what survives
 __global__ void k_dead_apply(size_t n, const uint32_t *lost, uint32_t *s_win, uint32_t *wflag, const uint32_t *s_gid,
-                             const float *s_energy, uint32_t *spp, uint32_t *spec) {
+                             const float *s_energy, uint32_t *spp, uint32_t n_spp, uint32_t *spec) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t l = lost[i], in = s_win[i] & 1u;
   s_win[i] = in | (l << 1);
   wflag[i] = (in && !l) ? 1u : 0u;
   if (l) return;
-  if (spp && in) atomicAdd(&spp[s_gid[i]], 1u);
+  if (spp && in && s_gid[i] < n_spp) atomicAdd(&spp[s_gid[i]], 1u);
   const float Eb = s_energy[i];
   if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
 }
 
 static inline unsigned grid_for(size_t n) { return (unsigned)((n + 255) / 256); }
 // rows of the per-instance table: first event, event count, crystals per
-// panel, RNG id, readout unit, dead-time unit, crystals per module, layer words
-constexpr int kTabRows = 7 + kLayerWords;
+// panel, RNG id, readout unit, dead-time unit, crystals per module, layer
+// words, crystals of the scanner
+constexpr int kTabRows = 8 + kLayerWords;
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1243,9 +1249,6 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   S->windowed = 0;
   C->count = 0;
   if (D.sweep_out) std::fill(D.sweep_out, D.sweep_out + D.sweep_lo.size() * ni, (uint64_t)0);
-  if (T && (T->hits_per_crystal || T->doi) && n)
-    hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
-                       T->hits_per_crystal, T->doi, T->doi_bins, D.panel_depth);
   if (D.coinc_per_inst) std::fill(D.coinc_per_inst, D.coinc_per_inst + ni, 0ull);
   if (n == 0) return wait_stream(st) == hipSuccess ? GPET_OK : GPET_ERR_HIP;
 
@@ -1344,9 +1347,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     const bool have_layers = D.layers.size() >= (i + 1) * kLayerWords;
     for (int k = 0; k < kLayerWords; ++k) // without a layout: one layer of 1 x 1 (no neighbours)
       tab[(7 + k) * ni + i] = have_layers ? D.layers[i * kLayerWords + k] : (k == 0 || k > kMaxLayers ? 1u : 0u);
+    tab[(7 + kLayerWords) * ni + i] = D.ncr[i];
   }
   (void)hipMemcpyAsync(d_tab, tab, ni * 4 * kTabRows, hipMemcpyHostToDevice, st);
-  const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, (uint32_t)ni};
+  const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, d_tab + (7 + kLayerWords) * ni, (uint32_t)ni};
+  // per-crystal tallies are kept for one scanner (the plain entry point)
+  const uint32_t n_tally = D.ncr[0];
   uint32_t max_events = 1;
   for (size_t i = 0; i < ni; ++i) max_events = std::max(max_events, D.n_events[i]);
   int event_bits = 1;
@@ -1405,6 +1411,10 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     err = "digitize: a hit's instance, event or crystal id lies outside its declared range";
     return GPET_ERR_ARG;
   }
+  // hit tallies once every id is known to be in range
+  if (T && (T->hits_per_crystal || T->doi))
+    hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
+                       T->hits_per_crystal, n_tally, T->doi, T->doi_bins, D.panel_depth);
   if (mapped && rb[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
     const bool f1 = radix_sort(sb, n, hit_bits, st);
     hk = f1 ? sb.k1 : sb.k0;
@@ -1450,7 +1460,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
                      S->edep_kev, S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
                      (T && !dead) ? T->singles_per_crystal : nullptr, (T && !dead) ? T->energy_spectrum : nullptr,
-                     s_time, D.time_sigma, S->depth_mm, D.doi_sigma, D.ls_thresh, d_tab + 6 * ni, sb.k1);
+                     s_time, D.time_sigma, S->depth_mm, D.doi_sigma, D.ls_thresh, d_tab + 6 * ni, sb.k1, n_tally);
   hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
                      (size_t)grid_for(ns), (unsigned long long *)(rb + 4));
   if (dead) {
@@ -1486,7 +1496,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                          (size_t)ns, uv, (const unsigned long long *)t_sorted, D.dead_ps, lost);
     }
     hipLaunchKernelGGL(k_dead_apply, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, lost, S->in_window, wpos,
-                       S->gid, S->energy_kev, T ? T->singles_per_crystal : nullptr,
+                       S->gid, S->energy_kev, T ? T->singles_per_crystal : nullptr, n_tally,
                        T ? T->energy_spectrum : nullptr);
   }
   exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);

@@ -779,6 +779,7 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
   D.n_events = {(uint32_t)p->n_events};
   D.cpp = {(uint32_t)c->info.crystals_per_panel};
   D.cpm = {(uint32_t)c->info.crystals_per_module};
+  D.ncr = {(uint32_t)c->info.n_crystals};
   layer_words(c->scene, D.layers);
   D.rng = {p->instance};
   D.duration = {c->have_source ? (unsigned long long)c->scene.duration_ps : 0ull};
@@ -1140,6 +1141,7 @@ gpet_status gpet_batch_create(gpet_ctx *c, int32_t n, const gpet_instance *inst,
     b->id.push_back(inst[i].instance);
     b->cpp.push_back((uint32_t)G[i].info.crystals_per_panel);
     b->cpm.push_back((uint32_t)G[i].info.crystals_per_module);
+    b->ncr.push_back((uint32_t)G[i].info.n_crystals);
     layer_words(S[i], b->layers);
     b->duration.push_back(inst[i].source->duration_ps);
     b->gid_bits = std::max(b->gid_bits, bits_for((uint64_t)G[i].info.n_crystals - 1));
@@ -1359,6 +1361,7 @@ gpet_status gpet_batch_digitize(gpet_batch *b, const gpet_hits *h, const gpet_di
     if (D.n_events[i] == 0) D.n_events[i] = 1; // empty instance: no hit can name it
   D.cpp = b->cpp;
   D.cpm = b->cpm;
+  D.ncr = b->ncr;
   D.layers = b->layers;
   D.rng = b->id;
   D.duration = b->duration;

@@ -127,6 +127,7 @@ struct DigitizeArgs {
   const unsigned long long *h_time = nullptr;
   std::vector<uint32_t> first, n_events, cpp, rng; // per instance: range, crystals per panel, RNG id
   std::vector<uint32_t> cpm;                        // per instance: crystals per module
+  std::vector<uint32_t> ncr;                        // per instance: crystals of the scanner
   uint32_t readout = 0;                             // GPET_READOUT_*
   // energy-window sweep: windows and host counts (window-major, one per instance)
   std::vector<float> sweep_lo, sweep_hi;
@@ -230,7 +231,7 @@ struct gpet_batch {
   int device = 0;
   uint32_t n = 0;
   std::vector<gpet_geometry_info> info;
-  std::vector<uint32_t> first, count, id, cpp, cpm;
+  std::vector<uint32_t> first, count, id, cpp, cpm, ncr;
   std::vector<uint32_t> layers; // kLayerWords per instance (see DigitizeArgs)
   std::vector<unsigned long long> duration;
   uint64_t mat_gen = 0, phantom_gen = 0;

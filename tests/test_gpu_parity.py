@@ -131,7 +131,7 @@ def test_fixed_rays_bit_exact(ctx, oracle_mod, case):
 # ---------------------------------------------------------------------------
 # transport
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["ring8", "C", "rods_phantom", "tilted", "derenzo_2CL", "stack4"])
+@pytest.mark.parametrize("case", ["ring8", "A", "B", "C", "rods_phantom", "tilted", "derenzo_2CL", "stack4"])
 def test_matched_histories(ctx, oracle_mod, case):
     if case == "ring8":
         sc, n = G.ring8_scene(n_events=5000), 5000
@@ -141,8 +141,8 @@ def test_matched_histories(ctx, oracle_mod, case):
         sc, n = G.derenzo_scene("2CL", 3000), 3000
     elif case == "tilted":
         sc, n = G.tilted_ring_scene(n_events=5000), 5000
-    elif case == "C":
-        sc, n = G.small_animal_scene("C", n_events=5000), 5000
+    elif case in ("A", "B", "C"):
+        sc, n = G.small_animal_scene(case, pos=(15.0, 0.0, 10.0), n_events=5000), 5000
     else:
         sc, n = G.hot_rod_scene(n_events=3000), 3000
     o = _both(ctx, oracle_mod, sc)
@@ -286,11 +286,13 @@ def test_digitizer_rejects_events_outside_range(ctx, oracle_mod):
         ctx.digitize(h, seed=1)
 
 
-@pytest.mark.parametrize("case", ["ring8", "C", "derenzo_2CL", "stack3", "stack4"])
+@pytest.mark.parametrize("case", ["ring8", "A", "B", "C", "derenzo_2CL", "stack3", "stack4"])
 def test_tallies_matched_seed(ctx, oracle_mod, case):
     """Same seed and event ids: sensitivity within 0.5 % relative."""
-    n = {"ring8": 1_000_000, "C": 300_000, "derenzo_2CL": 300_000, "stack3": 300_000, "stack4": 300_000}[case]
-    sc = {"ring8": lambda: G.ring8_scene(n_events=n), "C": lambda: G.small_animal_scene("C", n_events=n),
+    n = {"ring8": 1_000_000, "A": 300_000, "B": 300_000, "C": 300_000, "derenzo_2CL": 300_000,
+         "stack3": 300_000, "stack4": 300_000}[case]
+    sc = {"ring8": lambda: G.ring8_scene(n_events=n), "A": lambda: G.small_animal_scene("A", n_events=n),
+          "B": lambda: G.small_animal_scene("B", n_events=n), "C": lambda: G.small_animal_scene("C", n_events=n),
           "derenzo_2CL": lambda: G.derenzo_scene("2CL", n), "stack3": lambda: G.stack_scene("stack3", n_events=n),
           "stack4": lambda: G.stack_scene("stack4", n_events=n)}[case]()
     o = _both(ctx, oracle_mod, sc)

@@ -180,3 +180,42 @@ def test_readout_levels_conserve_energy_and_nest(oracle_mod):
     assert len(levels[2]) < len(levels[1]) < len(c)
     p = levels[2]
     assert len({(int(e), int(g) // cpp) for e, g in zip(p["event"], p["gid"])}) == len(p)
+
+
+def test_tallies_worked_example(oracle_mod):
+    """Hand-counted tallies (Sec. 2.3 windows, Sec. 3.1 DOI histograms): five
+    hits in three crystals of a 20 mm panel read into 4 depth bins of 5 mm,
+    four singles of which one lies outside the window and one is dead."""
+    h = _hits(oracle_mod, 5)
+    h["gid"] = [3, 3, 7, 0, 7]
+    h["depth"] = [0.0, 4.999, 5.0, 19.999, 25.0]  # bins 0, 0, 1, 3, past the back face -> 3
+    s = np.zeros(4, dtype=np.dtype(oracle_mod.Single))
+    s["gid"] = [3, 7, 0, 7]
+    s["energy"] = [511.2, 340.0, 699.999, -3.0]
+    s["in_window"] = [1, 0, 1, 1]
+    s["lost"] = [0, 0, 1, 0]
+    t = oracle_mod.tallies(h, s, n_crystals=8, panel_depth=20.0, doi_bins=4)
+    assert t["hits_per_crystal"].tolist() == [1, 0, 0, 2, 0, 0, 0, 2]
+    assert t["doi"].tolist() == [2, 1, 0, 2]
+    assert t["singles_per_crystal"].tolist() == [0, 0, 0, 1, 0, 0, 0, 1]
+    spec = np.zeros(700, np.int64)
+    spec[511] += 1
+    spec[340] += 1
+    assert np.array_equal(t["energy_spectrum"], spec)
+
+
+def test_tallies_conserve_counts(oracle_mod):
+    """On a transported run: every hit is in one crystal bin and one depth bin;
+    in-window singles and the spectrum count what the single list holds."""
+    s = oracle_mod.OracleScene(G.small_animal_scene("C", n_events=20000))
+    hits, _ = s.transport(20000, seed=4)
+    singles, _ = s.digitize(hits, seed=4)
+    t = s.tallies(hits, singles, doi_bins=200)
+    assert t["hits_per_crystal"].sum() == len(hits) == t["doi"].sum()
+    assert t["singles_per_crystal"].sum() == int(np.sum(singles["in_window"] != 0))
+    inside = (singles["energy"] >= 0) & (singles["energy"] < 700)
+    assert t["energy_spectrum"].sum() == int(inside.sum())
+    # hits per crystal equal the per-crystal sum over the singles' crystals' hits
+    assert np.array_equal(np.nonzero(t["hits_per_crystal"])[0], np.unique(singles["gid"]))
+    # two 10 mm layers in a 20 mm panel: the DOI histogram has hits on both sides of the layer face
+    assert t["doi"][:100].sum() > 0 and t["doi"][100:].sum() > 0
