@@ -271,9 +271,8 @@ def softmax(z):
 def loss_and_grad(params, x, y, store=None):
     """Mean softmax cross-entropy over the batch and its gradient with respect
     to every weight and bias (backpropagation written out).  `store`
-    (optional) rounds what the method stores between products: hidden
-    activations and the gradients with respect to pre-activations."""
-    keep = store or (lambda a: a)
+    (optional) rounds the hidden activations as the forward pass stores them
+    (the method's BF16 activations); the backward pass is exact float64."""
     z, ins, zs = forward(params, x, store)
     n = len(y)
     m = z.max(axis=1)
@@ -281,13 +280,13 @@ def loss_and_grad(params, x, y, store=None):
     loss = float(np.mean(lse - z[np.arange(n), y]))
     dz = softmax(z)
     dz[np.arange(n), y] -= 1.0
-    dz = keep(dz / n)
+    dz = dz / n
     grads = [None] * len(params)
     for k in range(len(params) - 1, -1, -1):
         W, _ = params[k]
         grads[k] = (dz.T @ ins[k], dz.sum(axis=0))
         if k:
-            dz = keep((dz @ W) * (ins[k] > 0.0))
+            dz = (dz @ W) * (ins[k] > 0.0)
     return loss, grads
 
 

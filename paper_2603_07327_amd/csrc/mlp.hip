@@ -35,7 +35,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_BF16 = 3, EPI_BIAS_F32_STATS = 4 };
+enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_HILO = 3, EPI_BIAS_F32_STATS = 4 };
 
 // C[m][n] = sum_k A(m, k) B(k, n) over a padded problem (M a multiple of BM,
 // N of BN, K of 32).  A(m, k) = a[m lda + k] (AT: a[k lda + m]);
@@ -43,18 +43,21 @@ enum : int { EPI_BIAS_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_F32 = 2, EPI_MASK_BF1
 // each computing a (BM / 2) x (BN / 2) block of 16 x 16 MFMA tiles; the
 // next K step's operands are loaded into registers while the current one is
 // multiplied.  Epilogue per EPI.
+//
+// Two-term operands (k_half > 0): the backward pass keeps each gradient as
+// hi + lo, two BF16 planes a_lo elements apart (hi = bf16(g), lo =
+// bf16(g - hi)), so its products keep FP32-like precision on the BF16
+// matrix cores.  Then K = 2 k_half: steps k >= k_half read the lo plane at
+// k - k_half and B again at k - k_half, so C = (hi + lo) B in one pass.
 template <int BM, int BN, bool AT, bool BT, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, int lda, const uint16_t *__restrict__ b,
                                               int ldb, int K, const float *__restrict__ bias,
                                               const uint16_t *__restrict__ mask, void *__restrict__ out, int ldc,
-                                              size_t split_stride) {
+                                              size_t split_stride, size_t a_lo, int k_half) {
   // split K: slice z covers [z K, (z + 1) K) and writes its partial product
-  // split_stride elements further on (EPI_F32 only)
+  // split_stride elements further on (EPI_F32); EPI_MASK_HILO writes the lo
+  // plane of its result split_stride elements after the hi plane
   const int kz = blockIdx.z * K;
-  if constexpr (AT) a += (size_t)kz * lda;
-  else a += kz;
-  if constexpr (BT) b += (size_t)kz * ldb;
-  else b += kz;
   if constexpr (EPI == EPI_F32) out = (float *)out + blockIdx.z * split_stride;
   constexpr int TM = BM / 32, TN = BN / 32; // MFMA tiles per wave and axis
   constexpr int PA = BM / 64, PB = BN / 64; // 16-byte loads per thread and operand
@@ -70,19 +73,23 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, in
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   uint4 ra[PA], rb[PB];
-  // global -> registers for the K step at k0
+  // global -> registers for the K step at k0 of this slice
   auto load = [&](int k0) {
+    const int kg = kz + k0;
+    const bool lo = k_half > 0 && kg >= k_half; // a step never straddles k_half (a multiple of 32)
+    const int kk = lo ? kg - k_half : kg;
+    const uint16_t *ap = lo ? a + a_lo : a;
 #pragma unroll
     for (int p = 0; p < PA; ++p) {
       const int t = tid + 256 * p;
-      if constexpr (!AT) ra[p] = *(const uint4 *)&a[(size_t)(m0 + (t >> 2)) * lda + k0 + (t & 3) * 8];
-      else ra[p] = *(const uint4 *)&a[(size_t)(k0 + t / (BM / 8)) * lda + m0 + (t % (BM / 8)) * 8];
+      if constexpr (!AT) ra[p] = *(const uint4 *)&ap[(size_t)(m0 + (t >> 2)) * lda + kk + (t & 3) * 8];
+      else ra[p] = *(const uint4 *)&ap[(size_t)(kk + t / (BM / 8)) * lda + m0 + (t % (BM / 8)) * 8];
     }
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
       const int t = tid + 256 * p;
-      if constexpr (!BT) rb[p] = *(const uint4 *)&b[(size_t)(n0 + (t >> 2)) * ldb + k0 + (t & 3) * 8];
-      else rb[p] = *(const uint4 *)&b[(size_t)(k0 + t / (BN / 8)) * ldb + n0 + (t % (BN / 8)) * 8];
+      if constexpr (!BT) rb[p] = *(const uint4 *)&b[(size_t)(n0 + (t >> 2)) * ldb + kk + (t & 3) * 8];
+      else rb[p] = *(const uint4 *)&b[(size_t)(kk + t / (BN / 8)) * ldb + n0 + (t % (BN / 8)) * 8];
     }
   };
   // registers -> LDS, K-contiguous rows
@@ -153,8 +160,11 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, in
           ((float *)out)[o] = v + bias[n];
         } else if constexpr (EPI == EPI_F32) {
           ((float *)out)[o] = v;
-        } else {
-          ((uint16_t *)out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? v : 0.0f);
+        } else { // masked by the ReLU of the layer input, kept as hi + lo
+          const float g = bf2f(mask[o]) > 0.0f ? v : 0.0f;
+          const uint16_t hi = f2bf(g);
+          ((uint16_t *)out)[o] = hi;
+          ((uint16_t *)out)[o + split_stride] = f2bf(g - bf2f(hi));
         }
       }
 }
@@ -297,7 +307,8 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
 // split_stride elements apart
 template <bool AT, bool BT, int EPI>
 static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, int N, int K, const float *bias,
-                 const uint16_t *mask, void *out, int ldc, hipStream_t st, int splits = 1, size_t split_stride = 0) {
+                 const uint16_t *mask, void *out, int ldc, hipStream_t st, int splits = 1, size_t split_stride = 0,
+                 size_t a_lo = 0, int k_half = 0) {
   if constexpr (!AT && !BT && (EPI == EPI_BIAS_RELU_BF16 || EPI == EPI_BIAS_F32)) {
     if (M % 256 == 0 && N % 128 == 0 && K % kTk == 0 && K <= kNtKmax) {
       hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3(N / 128, M / 256), dim3(512), kNtLds, st, a, lda, b, ldb, K, bias, out,
@@ -308,10 +319,10 @@ static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, 
   const int Ks = K / splits;
   if (M % 128 == 0 && N % 128 == 0)
     hipLaunchKernelGGL((k_gemm<128, 128, AT, BT, EPI>), dim3(N / 128, M / 128, splits), dim3(256), 0, st, a, lda, b,
-                       ldb, Ks, bias, mask, out, ldc, split_stride);
+                       ldb, Ks, bias, mask, out, ldc, split_stride, a_lo, k_half);
   else
     hipLaunchKernelGGL((k_gemm<64, 64, AT, BT, EPI>), dim3(N / 64, M / 64, splits), dim3(256), 0, st, a, lda, b, ldb,
-                       Ks, bias, mask, out, ldc, split_stride);
+                       Ks, bias, mask, out, ldc, split_stride, a_lo, k_half);
 }
 
 // number of K slices for an M x N product over K rows: enough blocks for
@@ -376,18 +387,19 @@ __device__ __forceinline__ void row_max_sum(const float *zr, int C, int lane, fl
 }
 
 // one wave per row: loss = logsumexp(z) - z[y]; dz = (softmax(z) - onehot(y)) / n
-// as bf16 (zero in padded columns and rows); a label outside [0, C) sets *bad
-// and is read as class 0
+// as hi + lo bf16 planes, the lo plane dz_lo elements after the hi plane (zero
+// in padded columns and rows); a label outside [0, C) sets *bad and is read
+// as class 0
 __global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int C, const int32_t *y, uint32_t n,
-                                                    uint32_t n_pad, float inv_n, uint16_t *dz, double *row_loss,
-                                                    uint32_t *bad) {
+                                                    uint32_t n_pad, float inv_n, uint16_t *dz, size_t dz_lo,
+                                                    double *row_loss, uint32_t *bad) {
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= n_pad) return;
   const float *zr = z + (size_t)r * ldz;
   uint16_t *dr = dz + (size_t)r * ldz;
   if (r >= n) {
-    for (int c = lane; c < ldz; c += 64) dr[c] = 0;
+    for (int c = lane; c < ldz; c += 64) dr[c] = dr[c + dz_lo] = 0;
     if (lane == 0) row_loss[r] = 0.0;
     return;
   }
@@ -402,14 +414,18 @@ __global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int
   for (int c0 = 4 * lane; c0 < ldz; c0 += 256) {
     const float4 v = *(const float4 *)(zr + c0);
     const float e[4] = {v.x, v.y, v.z, v.w};
-    uint16_t o[4];
+    uint16_t o[4], ol[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = c0 + j;
       const float p = c < C ? __expf(e[j] - mx) * inv_s : 0.0f;
-      o[j] = f2bf((c == yy ? p - 1.0f : p) * inv_n);
+      const float g = (c == yy ? p - 1.0f : p) * inv_n;
+      o[j] = f2bf(g);
+      ol[j] = f2bf(g - bf2f(o[j]));
     }
     *(uint2 *)(dr + c0) = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+    *(uint2 *)(dr + dz_lo + c0) =
+        make_uint2((uint32_t)ol[0] | ((uint32_t)ol[1] << 16), (uint32_t)ol[2] | ((uint32_t)ol[3] << 16));
   }
   if (lane == 0) row_loss[r] = (double)mx + log((double)s) - (double)zr[yy];
 }
@@ -427,15 +443,16 @@ __global__ void __launch_bounds__(1024) k_sum_f64(const double *v, uint32_t n, d
   if (threadIdx.x == 0) *out = s[0];
 }
 
-// partial column sums: slice blockIdx.y of `slices` sums its rows of dz into
-// part[slice][c]
-__global__ void k_col_sum_part(const uint16_t *dz, int ld, uint32_t rows, int cols, int slices, float *part) {
+// partial column sums: slice blockIdx.y of `slices` sums its rows of dz
+// (hi + lo planes, dz_lo elements apart) into part[slice][c]
+__global__ void k_col_sum_part(const uint16_t *dz, size_t dz_lo, int ld, uint32_t rows, int cols, int slices,
+                               float *part) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   const uint32_t per = (rows + slices - 1) / slices;
   const uint32_t r0 = blockIdx.y * per, r1 = min(rows, r0 + per);
   float a = 0.f;
-  for (uint32_t r = r0; r < r1; ++r) a += bf2f(dz[(size_t)r * ld + c]);
+  for (uint32_t r = r0; r < r1; ++r) a += bf2f(dz[(size_t)r * ld + c]) + bf2f(dz[(size_t)r * ld + c + dz_lo]);
   part[(size_t)blockIdx.y * cols + c] = a;
 }
 
@@ -681,8 +698,9 @@ gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
   }
   ok = ok && hipMalloc((void **)&q->logits, (size_t)need * q->psize[q->n_layers] * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->tstats, (size_t)need * (q->psize[q->n_layers] / 128) * sizeof(float2)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&q->dz[0], (size_t)need * widest * 2) == hipSuccess;
-  ok = ok && hipMalloc((void **)&q->dz[1], (size_t)need * widest * 2) == hipSuccess;
+  // gradients as hi + lo bf16 planes
+  ok = ok && hipMalloc((void **)&q->dz[0], (size_t)need * widest * 4) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->dz[1], (size_t)need * widest * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->yb, (size_t)need * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->idx, (size_t)need * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->row_loss, (size_t)need * 8) == hipSuccess;
@@ -692,7 +710,7 @@ gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
   size_t part = 0;
   for (int l = 0; l < q->n_layers; ++l) {
     const int M = q->psize[l + 1], N = q->psize[l];
-    part = std::max(part, (size_t)split_bound(M, N, (int)need) * M * N);
+    part = std::max(part, (size_t)split_bound(M, N, 2 * (int)need) * M * N);
   }
   ok = ok && hipMalloc((void **)&q->part, part * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->part_b, (size_t)64 * widest * 4) == hipSuccess;
@@ -733,36 +751,45 @@ void forward_sample(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
                      q->size[L]);
 }
 
-// loss of the rows in act[0] / yb and the gradient of the mean loss into gw / gb
+// loss of the rows in act[0] / yb and the gradient of the mean loss into gw / gb.
+// Each gradient with respect to a pre-activation is kept as hi + lo BF16
+// planes (the lo plane n_pad x N elements after the hi plane), and every
+// product with it runs over both planes, so the backward pass rounds like
+// FP32 storage while the matrix cores take BF16 operands.
 void backward(gpet_mlp *q, uint32_t n, uint32_t n_pad, hipStream_t st) {
   const int L = q->n_layers;
   const int C = q->size[L], Cp = q->psize[L];
   hipLaunchKernelGGL(k_softmax_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, C, q->yb, n, n_pad,
-                     1.0f / (float)n, q->dz[0], q->row_loss, q->flag);
+                     1.0f / (float)n, q->dz[0], (size_t)n_pad * Cp, q->row_loss, q->flag);
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(1024), 0, st, q->row_loss, n_pad, q->loss_sum);
   int cur = 0;
   for (int l = L - 1; l >= 0; --l) {
     const int K = q->psize[l], N = q->psize[l + 1];
-    // dW[o][i] = sum_r dz[r][o] act[r][i]: A = dz^T (M = N, K = rows), B(k = r, n = i) = act[r][i];
-    // split over rows into partial products, then summed in slice order
-    const int sp = split_count(N, K, (int)n_pad);
+    const size_t lo = (size_t)n_pad * N; // the lo plane of dz
+    // dW[o][i] = sum_r dz[r][o] act[r][i]: A = dz^T (M = N, K = rows, twice:
+    // hi then lo), B(k = r, n = i) = act[r][i]; split over rows into partial
+    // products, then summed in slice order
+    const int K2 = 2 * (int)n_pad;
+    const int sp = split_count(N, K, K2);
     const size_t ne = (size_t)N * K;
     if (sp > 1) {
-      gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, (int)n_pad, nullptr, nullptr, q->part, K, st, sp,
-                                ne);
+      gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, K2, nullptr, nullptr, q->part, K, st, sp, ne, lo,
+                                (int)n_pad);
       hipLaunchKernelGGL(k_reduce_slices, dim3(cdiv(ne, 256)), dim3(256), 0, st, q->part, sp, ne, q->gw[l]);
     } else {
-      gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, (int)n_pad, nullptr, nullptr, q->gw[l], K, st);
+      gemm<true, true, EPI_F32>(q->dz[cur], N, q->act[l], K, N, K, K2, nullptr, nullptr, q->gw[l], K, st, 1, 0, lo,
+                                (int)n_pad);
     }
     const int cols = q->size[l + 1], slices = (int)std::min<uint32_t>(64u, std::max<uint32_t>(1u, n_pad / 128));
-    hipLaunchKernelGGL(k_col_sum_part, dim3(cdiv(cols, 256), slices), dim3(256), 0, st, q->dz[cur], N, n_pad, cols,
-                       slices, q->part_b);
+    hipLaunchKernelGGL(k_col_sum_part, dim3(cdiv(cols, 256), slices), dim3(256), 0, st, q->dz[cur], lo, N, n_pad,
+                       cols, slices, q->part_b);
     hipLaunchKernelGGL(k_reduce_slices, dim3(cdiv(cols, 256)), dim3(256), 0, st, q->part_b, slices, (size_t)cols,
                        q->gb + q->b_off[l]);
     if (l) {
-      // dh[r][i] = sum_o dz[r][o] W[o][i], masked by the ReLU of layer l's input
-      gemm<false, true, EPI_MASK_BF16>(q->dz[cur], N, q->wb[l], K, (int)n_pad, K, N, nullptr, q->act[l],
-                                       q->dz[cur ^ 1], K, st);
+      // dh[r][i] = sum_o dz[r][o] W[o][i] over both planes of dz (K = 2N),
+      // masked by the ReLU of layer l's input and split into the next hi + lo
+      gemm<false, true, EPI_MASK_HILO>(q->dz[cur], N, q->wb[l], K, (int)n_pad, K, 2 * N, nullptr, q->act[l],
+                                       q->dz[cur ^ 1], K, st, 1, (size_t)n_pad * K, lo, N);
       cur ^= 1;
     }
   }

@@ -447,14 +447,39 @@ def test_edge_cases(ctx, oracle_mod):
 # ---------------------------------------------------------------------------
 # single readout levels (Sec. 2.1) and the energy-window sweep (Sec. 2.3)
 # ---------------------------------------------------------------------------
-def _readout_compare(s, so, ca, cb, co, edge_tol=1e-2):
+def _readout_near_ties(s, so, so_crystal, unit):
+    """Merged singles whose crystal differs between the GPU and the oracle.
+    The readout names the crystal with the largest deposit of the unit; the
+    oracle compares FP64 sums, the GPU FP32 sums, so a different crystal is
+    accepted only where its FP64 sum lies within FP32 rounding (1e-6
+    relative) of the largest one.  Returns the mask of such singles; fails on
+    any other difference."""
+    diff = s["gid"].view(np.uint32) != so["gid"]
+    if not diff.any():
+        return diff
+    by_unit = {}
+    for ev, g, e in zip(so_crystal["event"].tolist(), so_crystal["gid"].tolist(), so_crystal["edep"].tolist()):
+        by_unit.setdefault((ev, g // unit), []).append((e, g))
+    for i in np.nonzero(diff)[0]:
+        ev, g_ref, g_got = int(so["event"][i]), int(so["gid"][i]), int(s["gid"].view(np.uint32)[i])
+        cands = by_unit[(ev, g_ref // unit)]
+        e_max = max(e for e, _ in cands)
+        near = {g for e, g in cands if e_max - e <= 1e-6 * e_max}
+        assert g_ref in near and g_got in near and len(near) >= 2, (i, ev, g_ref, g_got, cands)
+    return diff
+
+
+def _readout_compare(s, so, ca, cb, co, edge_tol=1e-2, so_crystal=None, unit=1):
     assert len(s["event"]) == len(so)
     assert np.array_equal(s["event"].view(np.uint32), so["event"])
-    assert np.array_equal(s["gid"].view(np.uint32), so["gid"])
+    flip = (_readout_near_ties(s, so, so_crystal, unit) if so_crystal is not None
+            else np.zeros(len(so), bool))
+    assert np.array_equal(s["gid"].view(np.uint32)[~flip], so["gid"][~flip])
     assert np.array_equal(s["time_ps"].view(np.uint64), so["time_ps"])
     np.testing.assert_allclose(s["edep_kev"], so["edep"], rtol=2e-6, atol=1e-4)
-    np.testing.assert_allclose(s["depth_mm"], so["depth"], rtol=1e-5, atol=1e-5)
-    edge = (np.abs(so["energy"] - 350) < edge_tol) | (np.abs(so["energy"] - 650) < edge_tol)
+    # a flipped crystal carries its own depth and blur draw
+    np.testing.assert_allclose(s["depth_mm"][~flip], so["depth"][~flip], rtol=1e-5, atol=1e-5)
+    edge = (np.abs(so["energy"] - 350) < edge_tol) | (np.abs(so["energy"] - 650) < edge_tol) | flip
     assert np.array_equal(s["in_window"][~edge] != 0, so["in_window"][~edge] != 0)
     got = sorted(zip(ca.cpu().numpy().tolist(), cb.cpu().numpy().tolist()))
     ref = sorted(map(tuple, co.tolist()))
@@ -462,6 +487,7 @@ def _readout_compare(s, so, ca, cb, co, edge_tol=1e-2):
         assert got == ref
     else:
         assert len(set(got) ^ set(ref)) <= 4 * int(edge.sum())
+    return int(flip.sum())
 
 
 @pytest.mark.parametrize("level", ["module", "panel"])
@@ -473,10 +499,13 @@ def test_readout_on_transported_hits(ctx, oracle_mod, level):
     o = _both(ctx, oracle_mod, sc)
     hits, _ = ctx.transport(n, seed=5)
     sg, (ca, cb) = ctx.digitize(hits, seed=6, readout=level)
-    so, co = o.digitize(_hits_as_oracle(oracle_mod, hits.numpy()), seed=6, readout={"module": 1, "panel": 2}[level])
+    h = _hits_as_oracle(oracle_mod, hits.numpy())
+    so, co = o.digitize(h, seed=6, readout={"module": 1, "panel": 2}[level])
+    so_crystal, _ = o.digitize(h, seed=6, readout=0)
+    unit = o.s.crystals_per_module if level == "module" else o.s.crystals_per_panel
     s = sg.numpy()
-    print(level, "singles", len(so), "coincidences", len(co))
-    _readout_compare(s, so, ca, cb, co)
+    flips = _readout_compare(s, so, ca, cb, co, so_crystal=so_crystal, unit=unit)
+    print(level, "singles", len(so), "coincidences", len(co), "near-tie crystal flips", flips)
     assert sg.windowed == int((s["in_window"] != 0).sum())
 
 
@@ -494,9 +523,10 @@ def test_readout_crafted_against_oracle(ctx, oracle_mod, level):
     edep = rng.choice([100.0, 150.0, 200.0, 250.0, 300.0], n).astype(np.float32)  # ties on purpose
     t = rng.integers(0, 8000 * 3000, n)
     sg, (ca, cb) = ctx.digitize(_hitlist(ctx, ev, gid, edep, t, 0, 8000), seed=4, readout=level)
-    so, co = o.digitize(_oracle_hits(oracle_mod, ev, gid, edep, t), seed=4,
-                        readout={"module": 1, "panel": 2}[level])
-    _readout_compare(sg.numpy(), so, ca, cb, co)
+    h = _oracle_hits(oracle_mod, ev, gid, edep, t)
+    so, co = o.digitize(h, seed=4, readout={"module": 1, "panel": 2}[level])
+    so_crystal, _ = o.digitize(h, seed=4, readout=0)
+    _readout_compare(sg.numpy(), so, ca, cb, co, so_crystal=so_crystal, unit=unit)
 
 
 def test_window_sweep_counts(ctx, oracle_mod):
