@@ -338,6 +338,25 @@ gpet_status gpet_digitize(gpet_ctx *ctx, const gpet_hits *hits, const gpet_digit
                           gpet_singles *singles, gpet_coincidences *coincidences,
                           gpet_tallies *tallies /* NULL: none */);
 
+/* gpet_digitize for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, arguments, outputs and errors, but the call allocates no device or
+ * pinned host memory.  Its sort buffers, counters and readback words live in
+ * a static device array of GPET_DIGITIZE_NOALLOC_SCRATCH_BYTES (128 MiB) per
+ * GPU, which the library looks up when a context is created on that GPU and
+ * which stays held until the process ends.  A call whose hits need more than
+ * that (about 36.5 bytes per hit plus small tables: some 3.6 million hits)
+ * returns GPET_ERR_ARG with the sizes in gpet_last_error and changes no
+ * output.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (two contexts or streams at once) race and must be
+ * serialized by the caller; each call initializes what it reads, so no state
+ * carries over from the previous call.  Counts come back through pageable
+ * copies at the call's synchronization points. */
+#define GPET_DIGITIZE_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+gpet_status gpet_digitize_noalloc(gpet_ctx *ctx, const gpet_hits *hits, const gpet_digitizer *params,
+                                  gpet_singles *singles, gpet_coincidences *coincidences,
+                                  gpet_tallies *tallies /* NULL: none */);
+
 /* ---------------------------------------------------------------------- */
 /* Batched runs: one persistent transport launch over a table of instances  */
 /* (a design sweep: each instance has its own scanner and source and its    */

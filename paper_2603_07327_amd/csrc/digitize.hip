@@ -18,6 +18,7 @@
 // sort over every key bit.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "gpet_internal.hpp"
 
@@ -1261,29 +1262,47 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const size_t need = align_up(n * 8) * 2 + align_up(n * 4) * 5 + align_up(256 * tiles * 4) +
                       align_up(scan_words * 4) + align_up((max_buckets + 1) * 4) + align_up(max_buckets * 4) +
                       align_up(8) + align_up(ni * 4 * 3) + align_up(ni * 4 * kTabRows) + align_up(ni * 4);
-  if (scr.bytes < need) {
-    // a quarter of headroom: hit counts drift from call to call, and a
-    // free + allocate pair costs about as much as the whole digitizer
-    if (scr.buf) (void)hipFree(scr.buf);
-    scr.buf = nullptr;
-    scr.bytes = 0;
-    const size_t grow = need + need / 4;
-    if (hipMalloc(&scr.buf, grow) != hipSuccess) {
-      err = "digitize: device scratch allocation failed";
-      return GPET_ERR_HIP;
+  // readback words: [0, 16) scalars that kernels write (scan totals, maximum
+  // time, failure flags), [16, 16 + ni) per-instance counts, then the staging
+  // of uploads: 3 ni words of bucket map, kTabRows ni words of instance table
+  const size_t rb_words = 16 + (4 + kTabRows) * ni;
+  if (scr.fixed) {
+    // fixed scratch: nothing is allocated; the readback words sit behind the
+    // sort buffers in device memory and are copied to a host array at each
+    // synchronization
+    if (ni != 1 || rb_words > kFixedHostWords) {
+      err = "digitize: the fixed scratch serves one instance";
+      return GPET_ERR_ARG;
     }
-    scr.bytes = grow;
-  }
-  const size_t pinned_bytes = 64 + 4 * (4 + kTabRows) * ni;
-  if (scr.pinned_bytes < pinned_bytes) {
-    if (scr.pinned) (void)hipHostFree(scr.pinned);
-    scr.pinned = nullptr;
-    scr.pinned_bytes = 0;
-    if (hipHostMalloc((void **)&scr.pinned, pinned_bytes, hipHostMallocDefault) != hipSuccess) {
-      err = "digitize: pinned readback allocation failed";
-      return GPET_ERR_HIP;
+    if (need + align_up(rb_words * 4) > scr.bytes) {
+      err = "digitize: " + std::to_string(n) + " hits need " + std::to_string(need + align_up(rb_words * 4)) +
+            " bytes of scratch, more than the " + std::to_string(scr.bytes) + " bytes of the fixed scratch";
+      return GPET_ERR_ARG;
     }
-    scr.pinned_bytes = pinned_bytes;
+  } else {
+    if (scr.bytes < need) {
+      // a quarter of headroom: hit counts drift from call to call, and a
+      // free + allocate pair costs about as much as the whole digitizer
+      if (scr.buf) (void)hipFree(scr.buf);
+      scr.buf = nullptr;
+      scr.bytes = 0;
+      const size_t grow = need + need / 4;
+      if (hipMalloc(&scr.buf, grow) != hipSuccess) {
+        err = "digitize: device scratch allocation failed";
+        return GPET_ERR_HIP;
+      }
+      scr.bytes = grow;
+    }
+    if (scr.pinned_bytes < rb_words * 4) {
+      if (scr.pinned) (void)hipHostFree(scr.pinned);
+      scr.pinned = nullptr;
+      scr.pinned_bytes = 0;
+      if (hipHostMalloc((void **)&scr.pinned, rb_words * 4, hipHostMallocDefault) != hipSuccess) {
+        err = "digitize: pinned readback allocation failed";
+        return GPET_ERR_HIP;
+      }
+      scr.pinned_bytes = rb_words * 4;
+    }
   }
   char *p = (char *)scr.buf;
   auto take = [&](size_t bytes) {
@@ -1310,21 +1329,29 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   // first, n_events, cpp, rng, readout unit, dead-time unit, crystals per module, layer words
   uint32_t *d_tab = (uint32_t *)take(ni * 4 * kTabRows);
   uint32_t *d_icount = (uint32_t *)take(ni * 4);
+  // rb: the words kernels write (pinned host memory, or device memory behind
+  // the fixed scratch); rbh: where the host reads them after a synchronization
+  // and stages its uploads (the same pinned words, or a host array)
+  uint32_t host_words[kFixedHostWords];
+  uint32_t *rb = scr.fixed ? (uint32_t *)take(rb_words * 4) : (uint32_t *)scr.pinned;
+  uint32_t *rbh = scr.fixed ? host_words : rb;
   if ((size_t)(p - (char *)scr.buf) > scr.bytes) {
     err = "digitize: scratch accounting does not cover its allocations";
     return GPET_ERR_HIP;
   }
-  // pinned host words: [0, 16) scalars that kernels write directly (scan
-  // totals, maximum time, failure flags), [16, 16 + ni) per-instance counts,
-  // 3 ni words of bucket-map uploads, kTabRows ni words of instance table
-  uint32_t *rb = (uint32_t *)scr.pinned;
-  uint32_t *rb_count = rb + 16;
+  uint32_t *rb_count = rb + 16;         // device-visible per-instance counts
+  const uint32_t *rbh_count = rbh + 16; // their host view
   bb.pinned_flag = rb + 12;
-  bb.pinned_map = rb + 16 + ni;
-  uint32_t *tab = rb + 16 + 4 * ni;
+  bb.pinned_map = rbh + 16 + ni;
+  uint32_t *tab = rbh + 16 + 4 * ni;
+  launch_fill_u32(rb + 12, 0u, 2, st); // bucket overflow and id-range flags
   auto sync = [&](const char *what) {
     if (wait_stream(st) != hipSuccess) {
       err = std::string("digitize: stream error ") + what;
+      return false;
+    }
+    if (rbh != rb && hipMemcpy(rbh, rb, (16 + ni) * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+      err = std::string("digitize: readback failed ") + what;
       return false;
     }
     return true;
@@ -1367,7 +1394,6 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
 
   // 1. sort hits by (instance, event, gid, photon, index)
   uint32_t *err_flag = rb + 13; // checked at the next synchronization
-  *err_flag = 0u;
   hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux, D.h_inst, IT,
                      D.gid_bits, inst_shift, sb.k0, sb.v0, err_flag);
   std::vector<uint64_t> items(ni, n);
@@ -1375,12 +1401,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     launch_fill_u32(d_icount, 0u, ni, st);
     hipLaunchKernelGGL(k_inst_count, dim3(inst_grid(n)), dim3(256), 0, st, sb.k0, n, inst_shift, (uint32_t)ni,
                        d_icount);
-    (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDefault, st);
     if (!sync("building hit keys")) return GPET_ERR_HIP;
   }
   std::vector<double> range(ni);
   for (size_t i = 0; i < ni; ++i) {
-    if (ni > 1) items[i] = rb_count[i];
+    if (ni > 1) items[i] = rbh_count[i];
     range[i] = (double)D.n_events[i];
   }
   const unsigned long long ev_mask = (1ull << event_bits) - 1;
@@ -1394,7 +1420,6 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
     exclusive_scan(flag, n, sb.scan_tmp, st, rb + 1);
   };
-  rb[12] = 0u;
   const bool mapped = bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st,
                                         sb.scan_tmp, bk, bv) == 0;
   if (mapped) {
@@ -1407,7 +1432,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   }
   run_heads();
   if (!sync("after the hit sort")) return GPET_ERR_HIP;
-  if (rb[13] & 2u) {
+  if (rbh[13] & 2u) {
     err = "digitize: a hit's instance, event or crystal id lies outside its declared range";
     return GPET_ERR_ARG;
   }
@@ -1415,14 +1440,14 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   if (T && (T->hits_per_crystal || T->doi))
     hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
                        T->hits_per_crystal, n_tally, T->doi, T->doi_bins, D.panel_depth);
-  if (mapped && rb[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
+  if (mapped && rbh[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
     const bool f1 = radix_sort(sb, n, hit_bits, st);
     hk = f1 ? sb.k1 : sb.k0;
     hp = f1 ? sb.v1 : sb.v0;
     run_heads();
     if (!sync("after the hit sort")) return GPET_ERR_HIP;
   }
-  uint64_t ns = rb[1];
+  uint64_t ns = rbh[1];
   S->count = ns;
   S->windowed = 0;
   if (ns > S->capacity) { // the crystal singles pass through the output arrays
@@ -1446,7 +1471,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                        s_inst, unit, S->edep_kev, S->depth_mm, (const unsigned long long *)S->time_ps, o_ev, o_gid,
                        o_edep, o_depth, o_time, o_inst);
     if (!sync("in the readout")) return GPET_ERR_HIP;
-    ns = rb[1];
+    ns = rbh[1];
     S->count = ns;
     hipLaunchKernelGGL(k_readout_copy, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, o_ev, o_gid, o_edep,
                        o_depth, o_time, o_inst, S->event, S->gid, S->edep_kev, S->depth_mm,
@@ -1466,7 +1491,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   if (dead) {
     // 3b. dead time per unit (free here: the key/value pairs, flag, wpos)
     if (!sync("after the blur")) return GPET_ERR_HIP;
-    const unsigned long long tm = (unsigned long long)rb[4] | ((unsigned long long)rb[5] << 32);
+    const unsigned long long tm = (unsigned long long)rbh[4] | ((unsigned long long)rbh[5] << 32);
     int tbits = 1;
     while (tbits < 64 && (tm >> tbits) != 0) ++tbits;
     hipLaunchKernelGGL(k_dead_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns,
@@ -1491,7 +1516,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       hipLaunchKernelGGL(k_dead_gather, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, uv,
                          (const unsigned long long *)s_time, t_sorted);
       if (!sync("in the dead time")) return GPET_ERR_HIP;
-      const uint32_t n_runs = rb[6];
+      const uint32_t n_runs = rbh[6];
       hipLaunchKernelGGL(k_dead_nonparalyzable, dim3((n_runs + 3) / 4), dim3(256), 0, st, n_runs, start,
                          (size_t)ns, uv, (const unsigned long long *)t_sorted, D.dead_ps, lost);
     }
@@ -1501,9 +1526,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   }
   exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
   if (!sync("after the energy window")) return GPET_ERR_HIP;
-  const size_t nw = rb[3];
+  const size_t nw = rbh[3];
   S->windowed = nw;
-  const unsigned long long tmax = (unsigned long long)rb[4] | ((unsigned long long)rb[5] << 32);
+  const unsigned long long tmax = (unsigned long long)rbh[4] | ((unsigned long long)rbh[5] << 32);
   // time bits leave room for the window, so keys of two instances differ by more than it
   int time_bits = 0;
   while (time_bits < 63 && ((tmax + D.window_ps + 1) >> time_bits) != 0) ++time_bits;
@@ -1534,9 +1559,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       launch_fill_u32(d_icount, 0u, ni, st);
       hipLaunchKernelGGL(k_inst_count, dim3(inst_grid(nwin)), dim3(256), 0, st, sb.k0, nwin, time_bits,
                          (uint32_t)ni, d_icount);
-      (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+      (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDefault, st);
       if (!sync("counting windowed singles")) return GPET_ERR_HIP;
-      for (size_t i = 0; i < ni; ++i) witems[i] = rb_count[i];
+      for (size_t i = 0; i < ni; ++i) witems[i] = rbh_count[i];
     }
     const unsigned long long *tk = sb.k1;
     const uint32_t *ti = sb.v1;
@@ -1551,11 +1576,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
         launch_fill_u32(d_icount, 0u, ni, st);
         hipLaunchKernelGGL(k_coinc_inst_counts, dim3(inst_grid(nwin)), dim3(256), 0, st, nwin, flag, tk, tb,
                            (uint32_t)ni, d_icount);
-        (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDefault, st);
       }
     };
     bool mapped_t = false;
-    rb[12] = 0u;
+    launch_fill_u32(rb + 12, 0u, 1, st);
     if (nwin == 1) {
       tk = sb.k0;
       ti = sb.v0;
@@ -1570,7 +1595,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     }
     count_pairs();
     if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
-    if (mapped_t && rb[12]) { // a bucket overflowed LDS: rebuild the keys, sort every bit, redo the pairing
+    if (mapped_t && rbh[12]) { // a bucket overflowed LDS: rebuild the keys, sort every bit, redo the pairing
       make_flags();
       hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, win, wpos,
                          (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
@@ -1587,7 +1612,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   if (nw > 0) {
     const int r = pair_window(S->in_window, nw, true, [] {});
     if (r != GPET_OK) return r;
-    C->count = rb[7];
+    C->count = rbh[7];
     if (C->count > C->capacity) {
       err = "digitize: coincidence capacity too small";
       return GPET_ERR_CAPACITY;
@@ -1600,9 +1625,9 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
         if (C->count)
           hipLaunchKernelGGL(k_coinc_inst, dim3(inst_grid(C->count)), dim3(256), 0, st, (size_t)C->count,
                              C->first, s_inst, (uint32_t)ni, d_icount);
-        (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDefault, st);
         if (!sync("counting coincidences per instance")) return GPET_ERR_HIP;
-        for (size_t i = 0; i < ni; ++i) D.coinc_per_inst[i] = rb_count[i];
+        for (size_t i = 0; i < ni; ++i) D.coinc_per_inst[i] = rbh_count[i];
       }
     }
   }
@@ -1615,11 +1640,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     };
     make_flags();
     if (!sync("in the window sweep")) return GPET_ERR_HIP;
-    const size_t nsw = rb[3];
+    const size_t nsw = rbh[3];
     if (nsw == 0) continue;
     const int r = pair_window(flag, nsw, false, make_flags);
     if (r != GPET_OK) return r;
-    for (size_t i = 0; i < ni; ++i) D.sweep_out[w * ni + i] = rb_count[i];
+    for (size_t i = 0; i < ni; ++i) D.sweep_out[w * ni + i] = rbh_count[i];
   }
   return GPET_OK;
 }
@@ -1635,6 +1660,33 @@ hipError_t wait_stream(hipStream_t st) {
 size_t scan_tmp_words(size_t n) { return scan_scratch_words(n); }
 void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st, uint32_t *total) {
   exclusive_scan(a, n, tmp, st, total);
+}
+
+// The scratch of gpet_digitize_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address); it passes the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+void *fixed_scratch(int device, std::string &err) {
+  static std::mutex mu;
+  static std::vector<void *> addr; // per device
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) {
+    err = "fixed scratch: bad device";
+    return nullptr;
+  }
+  if ((size_t)device >= addr.size()) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("fixed scratch: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    addr[device] = ptr;
+  }
+  return addr[device];
 }
 
 void free_scratch(DigitizeScratch &scr) {

@@ -388,6 +388,12 @@ gpet_status gpet_ctx_create(int device, void *hip_stream, gpet_ctx **out) {
     gpet_ctx_destroy(c);
     return GPET_ERR_HIP;
   }
+  // the static digitizer scratch of this device (with the device current)
+  c->fixed_scratch = fixed_scratch(device, c->err);
+  if (!c->fixed_scratch) {
+    gpet_ctx_destroy(c);
+    return GPET_ERR_HIP;
+  }
   *out = c;
   return GPET_OK;
 }
@@ -752,9 +758,9 @@ static gpet_status digitizer_params(gpet_ctx *c, const gpet_hits *h, const gpet_
   return GPET_OK;
 }
 
-static gpet_status timed_digitize(gpet_ctx *c, DigitizeArgs &D) {
+static gpet_status timed_digitize(gpet_ctx *c, DigitizeArgs &D, DigitizeScratch *scr = nullptr) {
   if (c->timing) (void)hipEventRecord(c->ev[2], c->stream);
-  const int r = run_digitize(D, c->scratch, c->stream, c->err);
+  const int r = run_digitize(D, scr ? *scr : c->scratch, c->stream, c->err);
   if (r != GPET_OK) return r;
   if (c->timing) {
     (void)hipEventRecord(c->ev[3], c->stream);
@@ -764,17 +770,16 @@ static gpet_status timed_digitize(gpet_ctx *c, DigitizeArgs &D) {
   return hip_check(c, hipGetLastError(), "digitize: launch");
 }
 
-gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer *p, gpet_singles *sg,
-                          gpet_coincidences *cc, gpet_tallies *t) {
+// arguments of a plain (one-scanner) digitizer call
+static gpet_status plain_digitizer_args(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer *p, gpet_singles *sg,
+                                        gpet_coincidences *cc, gpet_tallies *t, DigitizeArgs &D) {
   if (!c) return GPET_ERR_ARG;
   if (!c->have_geometry) return fail(c, GPET_ERR_STATE, "digitize: no geometry");
-  DigitizeArgs D;
   gpet_status s = digitizer_params(c, h, p, sg, cc, D);
   if (s) return s;
   if (p->n_events == 0 || p->n_events > 0xffffffffull || p->first_event + p->n_events > 0x100000000ull)
     return fail(c, GPET_ERR_ARG, "digitize: event range");
   if (t && t->doi && t->doi_bins < 1) return fail(c, GPET_ERR_ARG, "digitize: doi_bins");
-  (void)hipSetDevice(c->device);
   D.first = {(uint32_t)p->first_event};
   D.n_events = {(uint32_t)p->n_events};
   D.cpp = {(uint32_t)c->info.crystals_per_panel};
@@ -786,7 +791,30 @@ gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer 
   D.gid_bits = bits_for((uint64_t)c->info.n_crystals - 1);
   D.panel_depth = c->scene.depth;
   D.tallies = t;
+  return GPET_OK;
+}
+
+gpet_status gpet_digitize(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer *p, gpet_singles *sg,
+                          gpet_coincidences *cc, gpet_tallies *t) {
+  DigitizeArgs D;
+  const gpet_status s = plain_digitizer_args(c, h, p, sg, cc, t, D);
+  if (s) return s;
+  (void)hipSetDevice(c->device);
   return timed_digitize(c, D);
+}
+
+gpet_status gpet_digitize_noalloc(gpet_ctx *c, const gpet_hits *h, const gpet_digitizer *p, gpet_singles *sg,
+                                  gpet_coincidences *cc, gpet_tallies *t) {
+  DigitizeArgs D;
+  const gpet_status s = plain_digitizer_args(c, h, p, sg, cc, t, D);
+  if (s) return s;
+  if (!c->fixed_scratch) return fail(c, GPET_ERR_STATE, "digitize_noalloc: no fixed scratch on this device");
+  (void)hipSetDevice(c->device);
+  DigitizeScratch fixed;
+  fixed.buf = c->fixed_scratch;
+  fixed.bytes = kFixedScratchBytes;
+  fixed.fixed = true;
+  return timed_digitize(c, D, &fixed);
 }
 
 gpet_status gpet_ctx_set_launch(gpet_ctx *c, int32_t blocks_per_cu, int32_t search_batch, int32_t schedule) {

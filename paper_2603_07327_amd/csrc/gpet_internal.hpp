@@ -107,7 +107,17 @@ struct DigitizeScratch {
   size_t bytes = 0;
   void *pinned = nullptr; // pinned host words for count readbacks and table uploads
   size_t pinned_bytes = 0;
+  // a fixed buffer (the library's static device scratch): never grown or
+  // freed, no pinned words; calls that need more than `bytes` are refused
+  bool fixed = false;
 };
+// host words a call on the fixed scratch stages its readbacks and uploads in
+constexpr size_t kFixedHostWords = 64;
+// size of the static device scratch of gpet_digitize_noalloc
+constexpr size_t kFixedScratchBytes = GPET_DIGITIZE_NOALLOC_SCRATCH_BYTES;
+// Device address of the static digitizer scratch on `device` (which must be
+// the current device); looked up once per device and kept.  Null on failure.
+void *fixed_scratch(int device, std::string &err);
 // One digitizer pass over the hits of one or more instances.  Instance i owns
 // the event ids [first[i], first[i] + n_events[i]); its hits carry i in h_inst
 // (h_inst may be null when there is one instance).
@@ -212,6 +222,7 @@ struct gpet_ctx {
   gpet::DevScene scene{};
   gpet::LaunchShape shape{};
   gpet::DigitizeScratch scratch{};
+  void *fixed_scratch = nullptr; // this device's static digitizer scratch (not owned)
   gpet::SurQueue squeue{};
   // generations of the material list and phantom; a batch made from this
   // context refuses to run once either changed (its scenes point at them)

@@ -184,7 +184,7 @@ EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_s
            "gpet_mlp_create", "gpet_mlp_destroy", "gpet_mlp_set_weights", "gpet_mlp_get_weights",
            "gpet_mlp_forward", "gpet_mlp_loss_grad", "gpet_mlp_train", "gpet_surrogate_pairs",
            "gpet_surrogate_transport", "gpet_batch_graph_capture", "gpet_batch_graph_launch",
-           "gpet_batch_read_counts")
+           "gpet_batch_read_counts", "gpet_digitize_noalloc")
 
 _lib = None
 
@@ -210,6 +210,7 @@ def load_library(path: str = LIB_PATH):
     L.gpet_source_set.argtypes = [vp, P(Source)]
     L.gpet_transport.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, P(Hits), P(Stats)]
     L.gpet_digitize.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), P(Tallies)]
+    L.gpet_digitize_noalloc.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), P(Tallies)]
     L.gpet_philox.argtypes = [vp, C.c_uint64, vp, C.c_uint32, vp]
     L.gpet_tables_get.argtypes = [vp, vp, vp]
     L.gpet_locate.argtypes = [vp, C.c_uint32, vp, vp]
@@ -502,11 +503,13 @@ class Context:
 
     def digitize_into(self, hits: HitList, singles: SingleList, coinc, seed=0, fwhm_511=0.16, e_lo=350.0,
                       e_hi=650.0, window_ps=3000, instance=0, tallies=None, readout="crystal", sweep=None,
-                      response=None):
+                      response=None, noalloc=False):
         """Digitize into preallocated outputs; returns (status, coincidences) or,
         with sweep = [(e_lo, e_hi), ...], (status, coincidences, counts of the
         sweep windows).  readout: "crystal", "module" or "panel"; response: the
-        optional time / DOI blur and dead time (see _digitizer)."""
+        optional time / DOI blur and dead time (see _digitizer); noalloc: call
+        gpet_digitize_noalloc (the library's static scratch) instead of
+        gpet_digitize."""
         h = hits.struct()
         dg, keep = _digitizer(fwhm_511, e_lo, e_hi, window_ps, seed, instance, hits.first_event,
                               max(1, hits.n_events), readout, sweep, response)
@@ -520,8 +523,8 @@ class Context:
             tl = Tallies(*(tallies[k].data_ptr() if tallies.get(k) is not None else None for k in
                            ("hits_per_crystal", "singles_per_crystal", "energy_spectrum", "doi")),
                          int(tallies["doi"].numel()) if tallies.get("doi") is not None else 0)
-        rc = self.L.gpet_digitize(self.h, C.byref(h), C.byref(dg), C.byref(s), C.byref(cc),
-                                  C.byref(tl) if tl is not None else None)
+        fn = self.L.gpet_digitize_noalloc if noalloc else self.L.gpet_digitize
+        rc = fn(self.h, C.byref(h), C.byref(dg), C.byref(s), C.byref(cc), C.byref(tl) if tl is not None else None)
         del keep
         singles.count = int(s.count)
         singles.windowed = int(s.windowed)
@@ -537,6 +540,11 @@ class Context:
         z = lambda k: t.zeros(k, dtype=t.int32, device=self.dev)  # noqa: E731
         return {"hits_per_crystal": z(n), "singles_per_crystal": z(n), "energy_spectrum": z(700),
                 "doi": z(doi_bins)}
+
+    def digitize_noalloc(self, hits: HitList, seed=0, tallies=None, **kw):
+        """digitize() through gpet_digitize_noalloc (the outputs are still
+        allocated here, by torch; the library allocates nothing)."""
+        return self.digitize(hits, seed=seed, tallies=tallies, noalloc=True, **kw)
 
     def digitize(self, hits: HitList, seed=0, tallies=None, **kw):
         """(singles, (first, second)) and, with sweep=..., the sweep counts."""
