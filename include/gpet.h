@@ -435,6 +435,19 @@ typedef struct {
  * uses its stream. */
 gpet_status gpet_mlp_create(gpet_ctx *ctx, int32_t n_sizes, const int32_t *sizes, const float *weights,
                             gpet_mlp **out);
+/* The same network with a factored output (the surrogate's form): of the
+ * last layer's sizes[n_sizes - 1] outputs, the first n_first (2..64) are an
+ * energy head (class 0 = no single) and the other n2 = sizes[n_sizes - 1] -
+ * n_first are positions; the position given energy class e > 0 follows
+ * softmax(positions + T[e - 1]) with a learned FP32 offset table T of
+ * (n_first - 1) x n2, packed after the layers (row-major).  Labels are
+ * joint: 0 for e = 0, else 1 + k (n_first - 1) + (e - 1) for position k
+ * (the layout of the surrogate's classes with n_first = n_ebins + 2).  The
+ * loss is -log P(e) - [e > 0] log P(k | e); gpet_mlp_forward returns the raw
+ * last-layer outputs (T not added).  A design choice of this library; the
+ * paper names learned surrogates only as a route to speed (Sec. 4). */
+gpet_status gpet_mlp_create_factored(gpet_ctx *ctx, int32_t n_sizes, const int32_t *sizes, int32_t n_first,
+                                     const float *weights, gpet_mlp **out);
 void gpet_mlp_destroy(gpet_mlp *mlp);
 /* Replaces the master weights (host, packed) and clears the Adam state. */
 gpet_status gpet_mlp_set_weights(gpet_mlp *mlp, const float *weights);
@@ -514,10 +527,13 @@ gpet_status gpet_surrogate_pairs(gpet_ctx *ctx, const gpet_surrogate_spec *spec,
                                  gpet_pairs *pairs, gpet_stats *stats);
 /* Transport with the surrogate: in-domain photons end at their first panel
  * entry and the network samples their single (Philox counter (0, event,
- * instance, 4 + photon): word 0 the class, word 1 the energy in its bin);
- * every other photon is transported in full.  The network must map 6
- * features to the spec's class count for this scanner.  Hits as
- * gpet_transport (surrogate singles carry process 3 in aux). */
+ * instance, 4 + photon): word 0 the class -- for a factored network the
+ * energy class --, word 1 the energy in its bin, word 2 the position of a
+ * factored network); every other photon is transported in full.  The
+ * network must map 6 features to the spec's class count for this scanner
+ * (factored: n_ebins + 2 energy classes and n_layers (2 half_width + 1)^2
+ * positions).  Hits as gpet_transport (surrogate singles carry process 3 in
+ * aux). */
 gpet_status gpet_surrogate_transport(gpet_ctx *ctx, gpet_mlp *mlp, const gpet_surrogate_spec *spec,
                                      uint64_t first_event, uint64_t n_events, uint64_t seed, uint32_t instance,
                                      gpet_hits *hits, gpet_stats *stats, gpet_surrogate_stats *sstats);

@@ -316,6 +316,84 @@ def sample_class(logits, u):
     return np.minimum((cdf < u[:, None]).sum(axis=1), p.shape[1] - 1)
 
 
+# ---------------------------------------------------------------------------
+# factored output: an energy head, then the position given the energy
+# ---------------------------------------------------------------------------
+# The outcome class (position k in the neighbourhood, energy index b, or
+# none) is drawn in two steps: the energy class e (0 = none, 1 + b
+# otherwise) from a softmax over the first n_first logits, then, for e > 0,
+# the position from a softmax over the remaining logits plus a learned row
+# T[e - 1] of per-energy position offsets.  The joint label keeps the layout
+# of outcome_class: 0, or 1 + k (n_first - 1) + (e - 1).
+def factored_split(y, n_first):
+    """Joint labels -> (energy class e, position k; k = 0 where e = 0)."""
+    y = np.asarray(y, np.int64)
+    c = np.maximum(y - 1, 0)
+    e = np.where(y > 0, 1 + c % (n_first - 1), 0)
+    k = np.where(y > 0, c // (n_first - 1), 0)
+    return e, k
+
+
+def factored_join(e, k, n_first):
+    e = np.asarray(e, np.int64)
+    return np.where(e > 0, 1 + np.asarray(k, np.int64) * (n_first - 1) + (e - 1), 0)
+
+
+def factored_log_prob(z, T, y, n_first):
+    """log P(y | x) per row from output logits z and the offset table T."""
+    e, k = factored_split(y, n_first)
+    z1, z2 = z[:, :n_first], z[:, n_first:]
+    m1 = z1.max(axis=1)
+    lp = z1[np.arange(len(e)), e] - (m1 + np.log(np.exp(z1 - m1[:, None]).sum(axis=1)))
+    pos = e > 0
+    if pos.any():
+        z2p = z2[pos] + T[e[pos] - 1]
+        m2 = z2p.max(axis=1)
+        lp[pos] += z2p[np.arange(pos.sum()), k[pos]] - (m2 + np.log(np.exp(z2p - m2[:, None]).sum(axis=1)))
+    return lp
+
+
+def factored_loss_and_grad(params, T, x, y, n_first, store=None):
+    """Mean of -log P(y | x) under the factored output, and its gradient with
+    respect to every weight and bias and to T (backpropagation written out;
+    `store` rounds hidden activations as in loss_and_grad)."""
+    z, ins, zs = forward(params, x, store)
+    n = len(y)
+    e, k = factored_split(y, n_first)
+    loss = float(-np.mean(factored_log_prob(z, T, y, n_first)))
+    dz = np.zeros_like(z)
+    dz[:, :n_first] = softmax(z[:, :n_first])
+    dz[np.arange(n), e] -= 1.0
+    pos = np.flatnonzero(e > 0)
+    gT = np.zeros_like(T)
+    if len(pos):
+        p2 = softmax(z[pos, n_first:] + T[e[pos] - 1])
+        p2[np.arange(len(pos)), k[pos]] -= 1.0
+        dz[pos, n_first:] = p2
+        np.add.at(gT, e[pos] - 1, p2 / n)
+    dz = dz / n
+    grads = [None] * len(params)
+    for j in range(len(params) - 1, -1, -1):
+        W, _ = params[j]
+        grads[j] = (dz.T @ ins[j], dz.sum(axis=0))
+        if j:
+            dz = (dz @ W) * (ins[j] > 0.0)
+    return loss, grads, gT
+
+
+def factored_sample(z, T, n_first, u_energy_class, u_position):
+    """Joint class per row: e = first energy class whose cumulative softmax
+    mass reaches u_energy_class; for e > 0, the first position whose
+    cumulative mass under softmax(z2 + T[e - 1]) reaches u_position."""
+    z = np.atleast_2d(z)
+    e = sample_class(z[:, :n_first], u_energy_class)
+    k = np.zeros_like(e)
+    pos = np.flatnonzero(e > 0)
+    if len(pos):
+        k[pos] = sample_class(z[pos, n_first:] + T[e[pos] - 1], np.atleast_1d(u_position)[pos])
+    return factored_join(e, k, n_first)
+
+
 def unpack(flat, sizes):
     """Packed float32 weights (per layer: W [out, in] row-major, then b [out])
     -> list of float64 (W, b)."""
@@ -327,6 +405,15 @@ def unpack(flat, sizes):
         o += j
         params.append((W, b))
     return params
+
+
+def unpack_factored(flat, sizes, n_first):
+    """Packed weights of a factored network: the layers as in unpack, then the
+    offset table T [n_first - 1][sizes[-1] - n_first] row-major."""
+    n_layers = sum(i * j + j for i, j in zip(sizes[:-1], sizes[1:]))
+    n2 = sizes[-1] - n_first
+    T = np.asarray(flat[n_layers:n_layers + (n_first - 1) * n2], np.float64).reshape(n_first - 1, n2)
+    return unpack(flat[:n_layers], sizes), T
 
 
 def bf16_round(a):

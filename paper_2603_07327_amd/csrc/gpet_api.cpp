@@ -1026,9 +1026,16 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   s = surrogate_spec(c, spec, P, n_classes);
   if (s) return s;
   if (!q || q->ctx != c) return fail(c, GPET_ERR_ARG, "surrogate: network missing or made on another context");
-  if (q->size[0] != 6 || q->size[q->n_layers] != n_classes)
+  if (q->n_first) {
+    const int W = 2 * spec->half_width + 1;
+    if (q->size[0] != 6 || q->n_first != spec->n_ebins + 2 || q->n_second != c->scene.n_layers * W * W)
+      return fail(c, GPET_ERR_ARG, "surrogate: a factored network must map 6 features to " +
+                                       std::to_string(spec->n_ebins + 2) + " energy classes and " +
+                                       std::to_string(c->scene.n_layers * W * W) + " positions");
+  } else if (q->size[0] != 6 || q->size[q->n_layers] != n_classes) {
     return fail(c, GPET_ERR_ARG, "surrogate: the network must map 6 features to " + std::to_string(n_classes) +
                                      " classes for this scanner and spec");
+  }
   if (!h) return fail(c, GPET_ERR_ARG, "surrogate: null hits");
   if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "surrogate: event range");
   if (!hits_ok(h)) return fail(c, GPET_ERR_ARG, "surrogate: null hit array");

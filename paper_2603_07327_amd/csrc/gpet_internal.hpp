@@ -268,6 +268,11 @@ struct gpet_mlp {
   int n_layers = 0;       // weight matrices
   size_t n_params = 0;
   std::vector<size_t> w_off, b_off;                  // offsets in the packed parameter vector
+  // factored output: the first n_first outputs are the energy head, the other
+  // n_second the positions, with an fp32 offset table [n_first - 1][n_second]
+  // at tab_off in the packed parameters (n_first = 0: one joint softmax)
+  int n_first = 0, n_second = 0;
+  size_t tab_off = 0;
   float *master = nullptr, *m = nullptr, *v = nullptr; // packed fp32 (per layer W [out][in], then b)
   std::vector<uint16_t *> wb;                        // padded bf16 weights per layer [out_pad][in_pad]
   std::vector<float *> gw;                           // padded fp32 weight gradients per layer
@@ -282,6 +287,7 @@ struct gpet_mlp {
   int32_t *yb = nullptr;
   uint32_t *idx = nullptr;
   double *row_loss = nullptr, *loss_sum = nullptr;
+  int32_t *erow = nullptr;  // energy class of each row (factored output)
   uint32_t *flag = nullptr; // bit 0: a label outside the classes
   float *part = nullptr, *part_b = nullptr; // split-K partial weight gradients, partial bias sums
   void *tstats = nullptr; // float2 (max, sum of exponentials) per row and 128-class tile of the logits

@@ -27,6 +27,7 @@ constexpr int kRowPad = 256;   // padding of rows (256-row product tiles)
 constexpr int kWidthPad = 128; // padding of layer widths (128-column product tiles)
 constexpr int kTk = 32;
 constexpr int kLdsRow = kTk + 8; // bf16 per LDS row (padding against bank conflicts)
+constexpr int kTableSlices = 16; // row slices of the offset-table gradient
 
 // float -> bfloat16 bits, round to nearest even
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -430,6 +431,175 @@ __global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int
   if (lane == 0) row_loss[r] = (double)mx + log((double)s) - (double)zr[yy];
 }
 
+// Factored output (energy head, then the position given the energy): the
+// first n1 logits are the energy classes (0 = none), the next n2 the
+// positions, shifted by the row T[e - 1] of the offset table for energy class
+// e.  A joint label y is 0 (e = 0) or 1 + k (n1 - 1) + (e - 1).
+__device__ __forceinline__ void factored_label(int y, int n1, int &e, int &k) {
+  e = y > 0 ? 1 + (y - 1) % (n1 - 1) : 0;
+  k = y > 0 ? (y - 1) / (n1 - 1) : 0;
+}
+
+// wave-wide maximum and sum of exp(v - max) of z2[c] + t[c], c < n2 (strided by lane)
+__device__ __forceinline__ void offset_row_max_sum(const float *z2, const float *t, int n2, int lane, float &m,
+                                                   float &s) {
+  m = -INFINITY;
+  for (int c = lane; c < n2; c += 64) m = fmaxf(m, z2[c] + t[c]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  s = 0.f;
+  for (int c = lane; c < n2; c += 64) s += __expf(z2[c] + t[c] - m);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+}
+
+// one wave per row: loss = -log P(e) - [e > 0] log P(k | e) and its gradient
+// with respect to the logits, as hi + lo bf16 planes (zero in padded columns
+// and rows); erow[r] = e (0 for padded rows); a label outside the classes sets
+// *bad and is read as 0.  n1 <= 64.
+__global__ void __launch_bounds__(256) k_factored_ce(const float *z, int ldz, int n1, int n2, const float *T,
+                                                     const int32_t *y, uint32_t n, uint32_t n_pad, float inv_n,
+                                                     uint16_t *dz, size_t dz_lo, double *row_loss, int32_t *erow,
+                                                     uint32_t *bad) {
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n_pad) return;
+  const float *zr = z + (size_t)r * ldz;
+  uint16_t *dr = dz + (size_t)r * ldz;
+  if (r >= n) {
+    for (int c = lane; c < ldz; c += 64) dr[c] = dr[c + dz_lo] = 0;
+    if (lane == 0) {
+      row_loss[r] = 0.0;
+      erow[r] = 0;
+    }
+    return;
+  }
+  int yy = y[r];
+  if (yy < 0 || yy > n2 * (n1 - 1)) {
+    if (lane == 0) atomicOr(bad, 1u);
+    yy = 0;
+  }
+  int e, k;
+  factored_label(yy, n1, e, k);
+  // energy head: one class per lane
+  const float v1 = lane < n1 ? zr[lane] : -INFINITY;
+  float m1 = v1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m1 = fmaxf(m1, __shfl_xor(m1, o));
+  float s1 = lane < n1 ? __expf(v1 - m1) : 0.f;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s1 += __shfl_xor(s1, o);
+  // position head given e
+  const float *z2 = zr + n1;
+  const float *t = T + (size_t)(e > 0 ? e - 1 : 0) * n2;
+  float m2 = 0.f, s2 = 1.f;
+  if (e > 0) offset_row_max_sum(z2, t, n2, lane, m2, s2);
+  const float inv_s1 = 1.0f / s1, inv_s2 = 1.0f / s2;
+  for (int c = lane; c < ldz; c += 64) {
+    float g = 0.f;
+    if (c < n1) {
+      g = (__expf(zr[c] - m1) * inv_s1 - (c == e ? 1.0f : 0.0f)) * inv_n;
+    } else if (e > 0 && c < n1 + n2) {
+      const int j = c - n1;
+      g = (__expf(z2[j] + t[j] - m2) * inv_s2 - (j == k ? 1.0f : 0.0f)) * inv_n;
+    }
+    const uint16_t hi = f2bf(g);
+    dr[c] = hi;
+    dr[c + dz_lo] = f2bf(g - bf2f(hi));
+  }
+  if (lane == 0) {
+    double l = (double)m1 + log((double)s1) - (double)zr[e];
+    if (e > 0) l += (double)m2 + log((double)s2) - ((double)z2[k] + (double)t[k]);
+    row_loss[r] = l;
+    erow[r] = e;
+  }
+}
+
+// partial offset-table gradients: slice blockIdx.z of `slices` sums, over its
+// rows r with energy class e = blockIdx.y + 1, the position-head gradient
+// (hi + lo) into part[slice][(e - 1) n2 + j]
+__global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int n1, int n2, const int32_t *erow,
+                                  uint32_t rows, int slices, float *part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (int)blockIdx.y + 1;
+  if (j >= n2) return;
+  const uint32_t per = (rows + slices - 1) / slices;
+  const uint32_t r0 = blockIdx.z * per, r1 = min(rows, r0 + per);
+  float a = 0.f;
+  for (uint32_t r = r0; r < r1; ++r)
+    if (erow[r] == e) {
+      const size_t o = (size_t)r * ldz + n1 + j;
+      a += bf2f(dz[o]) + bf2f(dz[o + dz_lo]);
+    }
+  part[(size_t)blockIdx.z * (n1 - 1) * n2 + (size_t)(e - 1) * n2 + j] = a;
+}
+
+// Factored sampling, one wave per queue entry: the energy class e = first
+// class whose cumulative softmax mass reaches u0 * total (u0: word 0 of
+// Philox (0, event, inst_rng, 4 + photon)); for e > 0 the position k = first
+// position whose cumulative mass under softmax(z2 + T[e - 1]) reaches u2 *
+// total (word 2), walked 64 positions at a time.  cls = the joint label.
+__global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, const float *T,
+                                                         uint32_t n, const uint32_t *ev, const uint32_t *meta,
+                                                         uint32_t k0, uint32_t k1, uint32_t inst_rng, uint32_t *cls,
+                                                         uint32_t *nonzero) {
+  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const float *zr = z + (size_t)r * ldz;
+  const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
+  // energy class
+  const float v1 = lane < n1 ? zr[lane] : -INFINITY;
+  float m1 = v1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m1 = fmaxf(m1, __shfl_xor(m1, o));
+  const float p1 = lane < n1 ? __expf(v1 - m1) : 0.f;
+  float incl = p1;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float tt = __shfl_up(incl, o);
+    if (lane >= o) incl += tt;
+  }
+  const float target1 = to_unit(w.x) * __shfl(incl, 63);
+  const uint64_t c1 = __ballot(incl >= target1 && lane < n1);
+  const int e = c1 ? __ffsll((unsigned long long)c1) - 1 : n1 - 1;
+  if (e == 0) {
+    if (lane == 0) {
+      cls[r] = 0u;
+      nonzero[r] = 0u;
+    }
+    return;
+  }
+  // position given e
+  const float *z2 = zr + n1;
+  const float *t = T + (size_t)(e - 1) * n2;
+  float m2, s2;
+  offset_row_max_sum(z2, t, n2, lane, m2, s2);
+  const float target2 = to_unit(w.z) * s2;
+  int k = n2 - 1; // rounding left the target beyond the last position
+  float acc = 0.f;
+  for (int c0 = 0; c0 < n2; c0 += 64) {
+    const int c = c0 + lane;
+    const float p = c < n2 ? __expf(z2[c] + t[c] - m2) : 0.f;
+    float in2 = p;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const float tt = __shfl_up(in2, o);
+      if (lane >= o) in2 += tt;
+    }
+    const uint64_t cr = __ballot(acc + in2 >= target2 && c < n2);
+    if (cr) {
+      k = c0 + __ffsll((unsigned long long)cr) - 1;
+      break;
+    }
+    acc += __shfl(in2, 63);
+  }
+  if (lane == 0) {
+    cls[r] = 1u + (uint32_t)k * (uint32_t)(n1 - 1) + (uint32_t)(e - 1);
+    nonzero[r] = 1u;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_sum_f64(const double *v, uint32_t n, double *out) {
   __shared__ double s[1024];
   double a = 0.0;
@@ -671,7 +841,7 @@ void free_workspace(gpet_mlp *q) {
   q->act.clear();
   for (void *p : {(void *)q->logits, (void *)q->dz[0], (void *)q->dz[1], (void *)q->yb, (void *)q->idx,
                   (void *)q->row_loss, (void *)q->loss_sum, (void *)q->flag, (void *)q->part, (void *)q->part_b,
-                  (void *)q->tstats})
+                  (void *)q->tstats, (void *)q->erow})
     if (p) (void)hipFree(p);
   q->flag = nullptr;
   q->tstats = nullptr;
@@ -681,6 +851,7 @@ void free_workspace(gpet_mlp *q) {
   q->yb = nullptr;
   q->idx = nullptr;
   q->row_loss = q->loss_sum = nullptr;
+  q->erow = nullptr;
   q->cap = 0;
 }
 
@@ -704,6 +875,7 @@ gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
   ok = ok && hipMalloc((void **)&q->yb, (size_t)need * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->idx, (size_t)need * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->row_loss, (size_t)need * 8) == hipSuccess;
+  ok = ok && hipMalloc((void **)&q->erow, (size_t)need * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->loss_sum, 8) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->flag, 8) == hipSuccess;
   // split-K partial products of the weight gradients and partial bias sums
@@ -712,6 +884,7 @@ gpet_status ensure_workspace(gpet_mlp *q, uint32_t n) {
     const int M = q->psize[l + 1], N = q->psize[l];
     part = std::max(part, (size_t)split_bound(M, N, 2 * (int)need) * M * N);
   }
+  if (q->n_first) part = std::max(part, (size_t)kTableSlices * (q->n_first - 1) * q->n_second);
   ok = ok && hipMalloc((void **)&q->part, part * 4) == hipSuccess;
   ok = ok && hipMalloc((void **)&q->part_b, (size_t)64 * widest * 4) == hipSuccess;
   if (!ok) {
@@ -759,8 +932,20 @@ void forward_sample(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
 void backward(gpet_mlp *q, uint32_t n, uint32_t n_pad, hipStream_t st) {
   const int L = q->n_layers;
   const int C = q->size[L], Cp = q->psize[L];
-  hipLaunchKernelGGL(k_softmax_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, C, q->yb, n, n_pad,
-                     1.0f / (float)n, q->dz[0], (size_t)n_pad * Cp, q->row_loss, q->flag);
+  if (q->n_first) {
+    const int n1 = q->n_first, n2 = q->n_second;
+    const float *T = q->master + q->tab_off;
+    hipLaunchKernelGGL(k_factored_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, n1, n2, T, q->yb, n,
+                       n_pad, 1.0f / (float)n, q->dz[0], (size_t)n_pad * Cp, q->row_loss, q->erow, q->flag);
+    const size_t nt = (size_t)(n1 - 1) * n2;
+    hipLaunchKernelGGL(k_table_grad_part, dim3(cdiv(n2, 256), n1 - 1, kTableSlices), dim3(256), 0, st, q->dz[0],
+                       (size_t)n_pad * Cp, Cp, n1, n2, q->erow, n_pad, kTableSlices, q->part);
+    hipLaunchKernelGGL(k_reduce_slices, dim3(cdiv(nt, 256)), dim3(256), 0, st, q->part, kTableSlices, nt,
+                       q->gb + q->tab_off);
+  } else {
+    hipLaunchKernelGGL(k_softmax_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, C, q->yb, n, n_pad,
+                       1.0f / (float)n, q->dz[0], (size_t)n_pad * Cp, q->row_loss, q->flag);
+  }
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(1024), 0, st, q->row_loss, n_pad, q->loss_sum);
   int cur = 0;
   for (int l = L - 1; l >= 0; --l) {
@@ -817,7 +1002,12 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
     hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, Q.x + (size_t)6 * off,
                        (const int32_t *)nullptr, (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad,
                        q->act[0], (int32_t *)nullptr);
-    if (tiles) {
+    if (q->n_first) {
+      forward(q, n_pad, st);
+      hipLaunchKernelGGL(k_sample_factored, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first,
+                         q->n_second, (const float *)(q->master + q->tab_off), n, Q.ev + off, Q.meta + off, k0, k1,
+                         inst_rng, Q.cls + off, Q.pos + off);
+    } else if (tiles) {
       forward_sample(q, n_pad, st);
       hipLaunchKernelGGL(k_sample_tiles, dim3(cdiv(n, 4)), dim3(256), 0, st, (const float2 *)q->tstats, Cp / 128,
                          q->logits, Cp, C, n, Q.ev + off, Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
@@ -848,7 +1038,8 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
 
 extern "C" {
 
-gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, const float *weights, gpet_mlp **out) {
+static gpet_status mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, int32_t n_first,
+                              const float *weights, gpet_mlp **out) {
   if (!c || !out || !sizes) return GPET_ERR_ARG;
   *out = nullptr;
   if (n_sizes < 2 || n_sizes > 16) {
@@ -864,6 +1055,10 @@ gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, 
       c->err = "mlp: layer widths in 1..8192";
       return GPET_ERR_ARG;
     }
+  if (n_first && (n_first < 2 || n_first > 64 || n_first >= sizes[n_sizes - 1])) {
+    c->err = "mlp: the energy head takes 2..64 of the output classes and leaves at least one position";
+    return GPET_ERR_ARG;
+  }
   gpet_mlp *q = new (std::nothrow) gpet_mlp();
   if (!q) return GPET_ERR_ARG;
   q->ctx = c;
@@ -880,6 +1075,10 @@ gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, 
     q->b_off.push_back(o);
     o += (size_t)sizes[l + 1];
   }
+  q->n_first = n_first;
+  q->n_second = n_first ? sizes[n_sizes - 1] - n_first : 0;
+  q->tab_off = o; // the offset table of a factored output follows the layers
+  if (n_first) o += (size_t)(n_first - 1) * q->n_second;
   q->n_params = o;
   (void)hipSetDevice(c->device);
   int widest = 0;
@@ -905,6 +1104,19 @@ gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, 
   if (weights) return gpet_mlp_set_weights(q, weights);
   std::vector<float> zero(o, 0.f);
   return gpet_mlp_set_weights(q, zero.data());
+}
+
+gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, const float *weights, gpet_mlp **out) {
+  return mlp_create(c, n_sizes, sizes, 0, weights, out);
+}
+
+gpet_status gpet_mlp_create_factored(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, int32_t n_first,
+                                     const float *weights, gpet_mlp **out) {
+  if (n_first < 2) {
+    if (c) c->err = "mlp: the energy head needs at least 2 classes";
+    return GPET_ERR_ARG;
+  }
+  return mlp_create(c, n_sizes, sizes, n_first, weights, out);
 }
 
 void gpet_mlp_destroy(gpet_mlp *q) {
@@ -1043,6 +1255,13 @@ gpet_status gpet_mlp_train(gpet_mlp *q, uint64_t n_pairs, const float *x, const 
                          q->m + q->b_off[l], q->v + q->b_off[l], q->gb + q->b_off[l], 1, rows, rows, (float)hp->lr,
                          (float)hp->beta1, (float)hp->beta2, (float)hp->eps, c1, c2, (uint16_t *)nullptr, 0,
                          q->bp + l * q->bp_stride);
+    }
+    if (q->n_first) { // the offset table: fp32 master only (the kernels read it there)
+      const int rows = q->n_first - 1, cols = q->n_second;
+      hipLaunchKernelGGL(k_adam, dim3(cdiv((size_t)rows * cols, 256)), dim3(256), 0, st, q->master + q->tab_off,
+                         q->m + q->tab_off, q->v + q->tab_off, q->gb + q->tab_off, rows, cols, cols, (float)hp->lr,
+                         (float)hp->beta1, (float)hp->beta2, (float)hp->eps, c1, c2, (uint16_t *)nullptr, 0,
+                         (float *)nullptr);
     }
   }
   bool ok = hipGetLastError() == hipSuccess;

@@ -184,7 +184,7 @@ EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_s
            "gpet_mlp_create", "gpet_mlp_destroy", "gpet_mlp_set_weights", "gpet_mlp_get_weights",
            "gpet_mlp_forward", "gpet_mlp_loss_grad", "gpet_mlp_train", "gpet_surrogate_pairs",
            "gpet_surrogate_transport", "gpet_batch_graph_capture", "gpet_batch_graph_launch",
-           "gpet_batch_read_counts", "gpet_digitize_noalloc")
+           "gpet_batch_read_counts", "gpet_digitize_noalloc", "gpet_mlp_create_factored")
 
 _lib = None
 
@@ -230,6 +230,7 @@ def load_library(path: str = LIB_PATH):
     L.gpet_batch_digitize.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), vp]
     L.gpet_batch_autotune.argtypes = [vp, C.c_uint64, P(Hits), C.c_char_p, C.c_size_t]
     L.gpet_mlp_create.argtypes = [vp, C.c_int32, vp, vp, P(vp)]
+    L.gpet_mlp_create_factored.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, P(vp)]
     L.gpet_mlp_destroy.argtypes = [vp]
     L.gpet_mlp_destroy.restype = None
     L.gpet_mlp_set_weights.argtypes = [vp, vp]
@@ -861,19 +862,29 @@ def unpack_params(flat, sizes):
 
 
 class Mlp:
-    """The surrogate network on the GPU (BF16 matrix cores, FP32 master weights)."""
+    """The surrogate network on the GPU (BF16 matrix cores, FP32 master weights).
+    n_first > 0: factored output (energy head of n_first classes, positions
+    with an offset table; gpet_mlp_create_factored)."""
 
-    def __init__(self, ctx: Context, sizes, weights=None):
+    def __init__(self, ctx: Context, sizes, weights=None, n_first=0):
         self.ctx, self.L = ctx, ctx.L
         self.sizes = [int(v) for v in sizes]
+        self.n_first = int(n_first)
         self.n_params = sum(i * j + j for i, j in zip(self.sizes[:-1], self.sizes[1:]))
+        if self.n_first:
+            self.n_params += (self.n_first - 1) * (self.sizes[-1] - self.n_first)
         sz = np.array(self.sizes, np.int32)
         w = None if weights is None else np.ascontiguousarray(weights, np.float32)
         if w is not None and w.size != self.n_params:
             raise ValueError("packed weights of the wrong size")
         h = C.c_void_p()
-        ctx._check(self.L.gpet_mlp_create(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p),
-                                          None if w is None else w.ctypes.data_as(C.c_void_p), C.byref(h)), "mlp")
+        wp = None if w is None else w.ctypes.data_as(C.c_void_p)
+        if self.n_first:
+            rc = self.L.gpet_mlp_create_factored(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p), self.n_first, wp,
+                                                 C.byref(h))
+        else:
+            rc = self.L.gpet_mlp_create(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p), wp, C.byref(h))
+        ctx._check(rc, "mlp")
         self.h = h
         ctx._batches.add(self)
 

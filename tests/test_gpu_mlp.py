@@ -78,6 +78,58 @@ def test_gradient_matches_fp64_backprop(ctx):
     m.close()
 
 
+def test_factored_gradient_matches_fp64_backprop(ctx):
+    """The factored output (energy head of 20 classes, 338 positions, offset
+    table) on a surrogate-sized trunk: loss within 1e-3 and every gradient
+    tensor, the table's included, within 2e-2 relative L2 of FP64
+    backpropagation at the same BF16 weights and stored activations."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    n1, n2 = 20, 338
+    sizes = [6, *G.SURROGATE_HIDDEN, n1 + n2]
+    P = G.mlp_init(sizes, seed=13)
+    rng = np.random.default_rng(14)
+    P = [(W * (3.0 if k == len(sizes) - 2 else 1.0), rng.normal(0, 0.05, len(b)).astype(np.float32))
+         for k, (W, b) in enumerate(P)]
+    T = rng.normal(0, 0.5, (n1 - 1, n2)).astype(np.float32)
+    flat = np.concatenate([pack_params(P), T.ravel()])
+    x = rng.uniform(-1, 1, (900, 6)).astype(np.float32)
+    e = rng.integers(0, n1, 900)
+    e[:100] = 0
+    y = S.factored_join(e, rng.integers(0, n2, 900), n1).astype(np.int32)
+    m = Mlp(ctx, sizes, flat, n_first=n1)
+    loss, g = m.loss_grad(x, y)
+    Pb = _bf16_params(flat[:len(pack_params(P))], sizes)
+    ref_loss, ref_g, ref_gT = S.factored_loss_and_grad(Pb, T.astype(np.float64), S.bf16_round(x), y, n1,
+                                                       store=S.bf16_round)
+    assert abs(loss - ref_loss) / ref_loss < 1e-3, (loss, ref_loss)
+    n_layer = len(pack_params(P))
+    G_gpu = S.unpack(g[:n_layer], sizes)
+    gT = g[n_layer:].reshape(n1 - 1, n2)
+    for k in range(len(sizes) - 1):
+        for j, name in ((0, "W"), (1, "b")):
+            a, r = G_gpu[k][j], ref_g[k][j]
+            err = np.linalg.norm(a - r) / np.linalg.norm(r)
+            print(k, name, "relative L2 vs fp64 backprop", err)
+            assert err <= 2e-2, (k, name, err)
+    err = np.linalg.norm(gT - ref_gT) / np.linalg.norm(ref_gT)
+    print("table relative L2 vs fp64 backprop", err)
+    assert err <= 2e-2
+    m.close()
+
+
+def test_factored_rejects_bad_labels(ctx):
+    from paper_2603_07327_amd.gpet import ERR_ARG, GpetError, Mlp
+    n1, n2 = 4, 9
+    m = Mlp(ctx, [6, 64, n1 + n2], n_first=n1)
+    x = np.zeros((10, 6), np.float32)
+    y = np.full(10, 3, np.int32)
+    y[4] = 1 + n2 * (n1 - 1)  # one past the last joint label
+    with pytest.raises(GpetError) as e:
+        m.loss_grad(x, y)
+    assert e.value.code == ERR_ARG
+    m.close()
+
+
 def _batch_indices(oracle_mod, seed, step, batch, n_pairs):
     ctr = np.zeros(((batch + 3) // 4, 4), np.uint32)
     ctr[:, 0] = step

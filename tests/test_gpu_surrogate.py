@@ -71,25 +71,38 @@ def test_pairs_match_oracle(ctx, oracle_mod, case):
     assert np.all(pairs["label"][(pairs["flags"] & 1) != 0] == 0)
 
 
-def _peaked_mlp_params(seed):
-    sizes = [6, 64, 64, 1851]
+def _peaked_mlp_params(seed, out=1851):
+    sizes = [6, 64, 64, out]
     P = G.mlp_init(sizes, seed=seed)
     W, b = P[-1]
     P[-1] = (W * 60.0, b)
     return sizes, P
 
 
-def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod):
+# the default spec (5 x 5 neighbourhood, 36 bins + photopeak): a factored
+# network has 38 energy classes and 2 x 25 positions
+N1, N2 = 38, 50
+
+
+@pytest.mark.parametrize("head", ["joint", "factored"])
+def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod, head):
     """Hits of a surrogate run: photons outside the domain keep their full
     transport (the oracle's hits for those photons), in-domain photons get the
-    single of the class the FP64 network samples with the same uniforms."""
+    single of the class the FP64 network samples with the same uniforms
+    (joint softmax, or energy class then position for a factored network)."""
     from paper_2603_07327_amd.gpet import Mlp, pack_params
     n, seed = 20_000, 5
     sc = G.hot_rod_scene(n_events=n)
     ctx.set_scene(sc)
-    sizes, P = _peaked_mlp_params(3)
-    flat = pack_params(P)
-    m = Mlp(ctx, sizes, flat)
+    if head == "joint":
+        sizes, P = _peaked_mlp_params(3)
+        flat = pack_params(P)
+        m = Mlp(ctx, sizes, flat)
+    else:
+        sizes, P = _peaked_mlp_params(3, N1 + N2)
+        T = np.random.default_rng(4).normal(0.0, 2.0, (N1 - 1, N2)).astype(np.float32)
+        flat = np.concatenate([pack_params(P), T.ravel()])
+        m = Mlp(ctx, sizes, flat, n_first=N1)
     hits, st, sst = ctx.surrogate_transport(m, n, seed=seed)
     g = hits.numpy()
     o, ref = _oracle_entries(oracle_mod, sc, n, seed)
@@ -99,13 +112,17 @@ def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod):
     # --- synthetic singles
     keys = sorted(ref)
     X = np.stack([ref[k]["entry"].x for k in keys])
-    logits, _, _ = S.forward([(S.bf16_round(W), b.astype(np.float64)) for W, b in S.unpack(flat, sizes)],
-                             S.bf16_round(X))
+    n_layer_params = len(pack_params(P))
+    logits, _, _ = S.forward([(S.bf16_round(W), b.astype(np.float64))
+                              for W, b in S.unpack(flat[:n_layer_params], sizes)], S.bf16_round(X))
     ev = np.array([k[0] for k in keys], np.uint32)
     ph = np.array([k[1] for k in keys], np.uint32)
     ctr = np.stack([np.zeros_like(ev), ev, np.zeros_like(ev), 4 + ph], 1)
     w = oracle_mod.philox(seed, ctr)
-    cls = S.sample_class(logits, _to_unit(w[:, 0]))
+    if head == "joint":
+        cls = S.sample_class(logits, _to_unit(w[:, 0]))
+    else:
+        cls = S.factored_sample(logits, T.astype(np.float64), N1, _to_unit(w[:, 0]), _to_unit(w[:, 2]))
     u1 = _to_unit(w[:, 1])
     wt = oracle_mod.philox(seed, np.stack([np.full_like(ev, 2), ev, np.zeros_like(ev), np.zeros_like(ev)], 1))
     X64 = (wt[:, 1].astype(np.uint64) << np.uint64(32)) | wt[:, 0].astype(np.uint64)
@@ -126,7 +143,7 @@ def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod):
     both = have.keys() & want.keys()
     agree = sum(1 for k in both if have[k][0] == want[k][0] and abs(have[k][1] - want[k][1]) < 1e-3 * want[k][1]
                 and abs(have[k][2] - want[k][2]) < 1e-4 and abs(have[k][3] - want[k][3]) <= 1)
-    print("synthetic gpu", len(have), "oracle", len(want), "agree", agree)
+    print(head, "synthetic gpu", len(have), "oracle", len(want), "agree", agree)
     assert len(want) > 1000
     assert agree >= 0.98 * max(len(have), len(want))
     assert sst["entries"] - sst["none"] == len(have)
@@ -169,5 +186,37 @@ def test_trained_network_beats_the_class_marginal(ctx):
     ce_marg = float(np.mean(-np.log(freq[te["label"]])))
     print("pairs", len(tr["label"]), "train loss", losses[:2], losses[-2:], "held-out CE net", ce_net,
           "marginal", ce_marg)
+    assert ce_net < ce_marg - 0.4
+    m.close()
+
+
+def test_trained_factored_network_beats_the_class_marginal(ctx):
+    """The factored form of the same comparison: energy head of 38 classes
+    and 50 positions with the offset table, trained on the hot-rod pairs
+    (seed 7), scored on held-out pairs (seed 8) with -log P(e) - log P(k | e)
+    from the FP64 reference's formula applied to the GPU's logits and table."""
+    import torch
+
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    sc = G.hot_rod_scene(n_events=2_000_000)
+    ctx.set_scene(sc)
+    _, tr, _ = ctx.surrogate_pairs(2_000_000, seed=7)
+    _, te, _ = ctx.surrogate_pairs(300_000, seed=8)
+    order = np.lexsort(((tr["flags"] >> 2) & 1, tr["event"]))
+    tr = {k: v[order] for k, v in tr.items()}
+    sizes = [6, *G.SURROGATE_HIDDEN, N1 + N2]
+    init = np.concatenate([pack_params(G.mlp_init(sizes, seed=1)), np.zeros((N1 - 1) * N2, np.float32)])
+    m = Mlp(ctx, sizes, init, n_first=N1)
+    x = torch.from_numpy(tr["x"]).to(ctx.dev)
+    y = torch.from_numpy(tr["label"]).to(ctx.dev)
+    losses = m.train(x, y, steps=1500, batch=4096, lr=1e-3, seed=3)
+    z = m.forward(te["x"]).astype(np.float64)
+    T = m.get_weights()[-(N1 - 1) * N2:].astype(np.float64).reshape(N1 - 1, N2)
+    ce_net = float(-np.mean(S.factored_log_prob(z, T, te["label"], N1)))
+    freq = (np.bincount(tr["label"], minlength=1851) + 0.5) / (len(tr["label"]) + 0.5 * 1851)
+    ce_marg = float(np.mean(-np.log(freq[te["label"]])))
+    print("pairs", len(tr["label"]), "train loss", losses[:2], losses[-2:], "held-out CE net", ce_net,
+          "marginal", ce_marg)
+    assert abs(float(np.mean(losses[-50:])) - ce_net) < 0.3
     assert ce_net < ce_marg - 0.4
     m.close()

@@ -79,6 +79,92 @@ def test_cross_entropy_closed_forms():
     assert loss < 1e-20
 
 
+def _factored_case(seed=11):
+    sizes = [6, 7, 5, 4 + 9]  # energy head of 4 classes (none + 3), 9 positions
+    P = _params(sizes, seed)
+    rng = np.random.default_rng(seed + 1)
+    T = rng.normal(0, 0.7, (3, 9))
+    x = rng.normal(size=(13, 6))
+    y = S.factored_join(rng.integers(0, 4, 13), rng.integers(0, 9, 13), 4)
+    y[:2] = 0
+    return sizes, P, T, x, y
+
+
+def test_factored_gradient_matches_central_differences():
+    """The energy-then-position output (Sec. 4's learned stand-in, this
+    build's factored head): gradients of every weight, bias and table
+    entry against central differences of the loss."""
+    sizes, P, T, x, y = _factored_case()
+    _, g, gT = S.factored_loss_and_grad(P, T, x, y, 4)
+    h = 1e-6
+    worst = 0.0
+    arrays = [(W, g[k][0]) for k, (W, _) in enumerate(P)] + [(b, g[k][1]) for k, (_, b) in enumerate(P)] + [(T, gT)]
+    for arr, garr in arrays:
+        it = np.nditer(arr, flags=["multi_index"])
+        for _ in it:
+            idx = it.multi_index
+            old = arr[idx]
+            arr[idx] = old + h
+            lp, _, _ = S.factored_loss_and_grad(P, T, x, y, 4)
+            arr[idx] = old - h
+            lm, _, _ = S.factored_loss_and_grad(P, T, x, y, 4)
+            arr[idx] = old
+            fd = (lp - lm) / (2 * h)
+            worst = max(worst, abs(fd - garr[idx]) / max(1e-3, abs(fd)))
+    assert worst < 1e-6, worst
+
+
+def test_factored_closed_forms_and_normalization():
+    """Zero weights: loss = log n_first + (share of labels with a single) log
+    n_positions, the energy-head bias gradient is 1/n_first minus the label
+    frequencies, the table gradient of energy e is the mean over its rows of
+    1/n_positions minus the one-hot position.  For any weights the joint
+    probabilities over all 1 + n_positions (n_first - 1) labels sum to 1."""
+    sizes = [6, 5, 4 + 9]
+    P = [(np.zeros((j, i)), np.zeros(j)) for i, j in zip(sizes[:-1], sizes[1:])]
+    T = np.zeros((3, 9))
+    x = np.random.default_rng(0).normal(size=(8, 6))
+    e = np.array([0, 1, 2, 3, 0, 1, 1, 3])
+    k = np.array([0, 4, 8, 0, 0, 4, 5, 2])
+    y = S.factored_join(e, k, 4)
+    assert np.array_equal(np.stack(S.factored_split(y, 4)), np.stack([e, np.where(e > 0, k, 0)]))
+    loss, g, gT = S.factored_loss_and_grad(P, T, x, y, 4)
+    assert abs(loss - (math.log(4) + 6 / 8 * math.log(9))) < 1e-14
+    np.testing.assert_allclose(g[-1][1][:4], 0.25 - np.bincount(e, minlength=4) / 8.0, atol=1e-15)
+    for ei in (1, 2, 3):
+        rows = e == ei
+        want = (rows.sum() / 9.0 - np.bincount(k[rows], minlength=9)) / 8.0
+        np.testing.assert_allclose(gT[ei - 1], want, atol=1e-15)
+    # joint label layout of outcome_class: 1 + position (n_ebins + 1) + bin, e = bin + 1
+    assert S.factored_join(np.array([3]), np.array([5]), 4)[0] == 1 + 5 * 3 + 2
+    sizes, P, T, x, _ = _factored_case(3)
+    z, _, _ = S.forward(P, x)
+    labels = np.arange(1 + 9 * 3)
+    tot = sum(np.exp(S.factored_log_prob(z, T, np.full(len(x), lab), 4)) for lab in labels)
+    np.testing.assert_allclose(tot, 1.0, rtol=1e-13)
+
+
+def test_factored_sampling_follows_its_probabilities():
+    """Stratified uniforms (u = (i + 1/2) / N on each axis, all pairs) give
+    every joint label with its probability to within 2 / N."""
+    sizes, P, T, x, _ = _factored_case(5)
+    z, _, _ = S.forward(P, x[:1])
+    N = 400
+    u = (np.arange(N) + 0.5) / N
+    ue, up = np.meshgrid(u, u, indexing="ij")
+    zz = np.repeat(z, N * N, axis=0)
+    lab = S.factored_sample(zz, T, 4, ue.ravel(), up.ravel())
+    freq = np.bincount(lab, minlength=28) / (N * N)
+    prob = np.exp([S.factored_log_prob(z, T, np.array([c]), 4)[0] for c in range(28)])
+    assert np.max(np.abs(freq - prob)) < 2.0 / N
+    # hand-computed: energy probabilities from the first head alone
+    z1 = np.log(np.array([[0.5, 0.25, 0.125, 0.125]]))
+    zfull = np.concatenate([z1, np.zeros((1, 9))], axis=1)
+    assert S.factored_sample(zfull, np.zeros((3, 9)), 4, np.array([0.49]), np.array([0.5]))[0] == 0
+    # e = 2 (u in (0.75, 0.875]), uniform positions: u_position = 0.35 -> position 3
+    assert S.factored_sample(zfull, np.zeros((3, 9)), 4, np.array([0.8]), np.array([0.35]))[0] == 1 + 3 * 3 + 1
+
+
 def test_adam_first_step_is_signed_learning_rate():
     P = _params([3, 4], 3)
     g = [(np.array([[1e-3, -2.0, 0.5]] * 4), np.array([3.0, -1e-5, 0.25, -7.0]))]
