@@ -425,11 +425,16 @@ def batched_form(args):
 def surrogate_form(args):
     """The hot-rod phantom workload (design C, water cylinder, six-sector rods)
     timed with full transport and with the detector-response surrogate, both
-    followed by the full digitizer.  The network (6 -> 4 x 256 -> 1851) is
-    first trained on pairs recorded from separate runs (seed 7); the timed runs
-    use seed 0.  Reported: events/s of both forms, their sensitivities and
-    per-crystal in-window singles chi-square, the share of photons the
-    network took over, training cost, and the network's matrix-core rate."""
+    followed by the full digitizer.  The network (6 -> 4 x 256 -> energy head
+    of n_ebins + 2 classes and 2 (2 H + 1)^2 positions with the offset table,
+    H = 12 crystals each way around the entry) is first trained on the pairs
+    recorded from separate runs (seed 7), about 1e8 of them; those whose
+    largest deposit lies outside that neighbourhood are left out, so the
+    network samples the outcome given that it lies inside.  The timed runs use seed 0.  Reported: events/s of both forms,
+    sensitivities at matched seeds (seed 0 both) and against an independent
+    full-transport run (seed 1: two-proportion z-test, per-crystal in-window
+    singles chi-square), the share of photons the network took over, the
+    truncated share, training cost, and the network's matrix-core rate."""
     import torch
     from scipy import stats as sps
 
@@ -437,58 +442,69 @@ def surrogate_form(args):
 
     n = args.surrogate_events
     spec = {"half_width": args.surrogate_half_width, "n_ebins": args.surrogate_ebins,
-            "ebin_kev": args.surrogate_ebin_kev}
-    W = 2 * args.surrogate_half_width + 1
-    n_classes = 1 + 2 * W * W * (args.surrogate_ebins + 1)
-    flop_per_entry = 2 * (6 * 256 + 3 * 256 * 256 + 256 * n_classes)  # forward pass, 6 -> 4 x 256 -> classes
+            "ebin_kev": args.surrogate_ebin_kev, "class_half_width": args.surrogate_class_half_width}
+    W = 2 * max(args.surrogate_half_width, args.surrogate_class_half_width) + 1
+    n1, n2 = args.surrogate_ebins + 2, 2 * W * W
+    flop_per_entry = 2 * (6 * 256 + 3 * 256 * 256 + 256 * (n1 + n2))  # forward pass
     sc = G.hot_rod_scene(n_events=n)
     ctx = Context(0)
     ctx.set_scene(sc)
     ctx.enable_timing(True)
-    # ---- training pairs (seed 7), in slices
+    # ---- training pairs (seed 7), in slices; truncated pairs left out
     slice_ev = 20_000_000
-    hits = ctx.alloc_hits(int(3.0 * slice_ev))
-    xs, ys, fl = [], [], []
+    hits = ctx.alloc_hits(int(1.3 * slice_ev))
+    pairs = ctx.alloc_pairs(2 * slice_ev)
+    xs, ys = [], []
+    n_rec = n_trunc = 0
     t0 = time.perf_counter()
     done = 0
     while done < args.surrogate_train_events:
         m = min(slice_ev, args.surrogate_train_events - done)
-        pairs = ctx.alloc_pairs(2 * m)
         rc, _ = ctx.surrogate_pairs_into(hits, pairs, m, seed=7, first=done, spec=spec)
         if rc != 0:
             raise RuntimeError("pair generation: capacity")
         k = pairs["count"]
-        xs.append(pairs["x"][: 6 * k].view(k, 6).clone())
-        ys.append(pairs["label"][:k].clone())
-        fl.append(pairs["flags"][:k].clone())
-        del pairs
+        fl = pairs["flags"][:k]
+        keep = (fl & 1) == 0
+        n_rec += k
+        n_trunc += int(k - int(keep.sum()))
+        # (event, photon) order: reproducible batches whatever order the queue filled in
+        key = (pairs["event"][:k].to(torch.int64) * 2 + ((fl >> 2) & 1).to(torch.int64))[keep]
+        order = torch.argsort(key)
+        xs.append(pairs["x"][: 6 * k].view(k, 6)[keep][order].clone())
+        ys.append(pairs["label"][:k][keep][order].clone())
         done += m
+    del pairs, hits
     x = torch.cat(xs)
     y = torch.cat(ys)
-    flags = torch.cat(fl)
+    del xs, ys
     label_none = float((y == 0).double().mean())
-    truncated = float(((flags & 1) != 0).double().mean())
-    del xs, ys, fl, flags
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
-    sizes = [6, *G.SURROGATE_HIDDEN, n_classes]
-    net = Mlp(ctx, sizes, pack_params(G.mlp_init(sizes, seed=1)))
+    sizes = [6, *G.SURROGATE_HIDDEN, n1 + n2]
+    init = np.concatenate([pack_params(G.mlp_init(sizes, seed=1)), np.zeros((n1 - 1) * n2, np.float32)])
+    net = Mlp(ctx, sizes, init, n_first=n1)
+    # two thirds of the steps at 1e-3, then a quarter at 3e-4 and the rest at
+    # 1e-4 (Adam continues across the calls)
+    s1 = args.surrogate_steps * 2 // 3
+    s2 = args.surrogate_steps // 4
+    schedule = [(s1, 1e-3), (s2, 3e-4), (args.surrogate_steps - s1 - s2, 1e-4)]
     t0 = time.perf_counter()
-    losses = net.train(x, y, steps=args.surrogate_steps, batch=8192, lr=1e-3, seed=3)
+    losses = []
+    for steps, lr in schedule:
+        if steps > 0:
+            losses.extend(net.train(x, y, steps=steps, batch=8192, lr=lr, seed=3).tolist())
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_pairs = int(y.numel())
-    ce_marg = None
-    counts = torch.bincount(y.long(), minlength=n_classes).double().cpu().numpy()
-    p = (counts + 0.5) / (counts.sum() + 0.5 * n_classes)
-    ce_marg = float(-(counts * np.log(p)).sum() / counts.sum())
-    del x, y, hits
+    del x, y
     torch.cuda.empty_cache()
+    train_flop = 3 * flop_per_entry * 8192 * args.surrogate_steps
 
     # ---- timed runs: plain and surrogate, each followed by the digitizer
-    hits = ctx.alloc_hits(int(3.2 * n))
-    singles = ctx.alloc_singles(int(2.2 * n))
-    coinc = (ctx._empty(n, torch.int32), ctx._empty(n, torch.int32))
+    hits = ctx.alloc_hits(int(1.4 * n))
+    singles = ctx.alloc_singles(int(1.3 * n))
+    coinc = (ctx._empty(n // 2, torch.int32), ctx._empty(n // 2, torch.int32))
 
     def run(mode, seed):
         if mode == "plain":
@@ -503,6 +519,10 @@ def surrogate_form(args):
             raise RuntimeError(f"{mode}: digitizer capacity")
         return nc, st, sst
 
+    def in_window_per_crystal():
+        s = singles.numpy()
+        return np.bincount(s["gid"][s["in_window"] != 0], minlength=ctx.info.n_crystals)
+
     out = {}
     hist = {}
     for mode in ("plain", "surrogate"):
@@ -512,8 +532,7 @@ def surrogate_form(args):
         nc, st, sst = run(mode, 0)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        s = singles.numpy()
-        hist[mode] = np.bincount(s["gid"][s["in_window"] != 0], minlength=ctx.info.n_crystals)
+        hist[mode] = in_window_per_crystal()
         out[mode] = {"value": n / dt, "ms": dt * 1e3, "coincidences": nc, "sensitivity": nc / n,
                      "transport_kernel_ms": ctx.timings()[0]}
         if sst is not None:
@@ -525,23 +544,26 @@ def surrogate_form(args):
                                              "unit": "TFLOP/s", "frac": achieved / 2.5e15,
                                              "flop_per_entry": flop_per_entry}
             # the same time against HBM: FP32 logits written by the last
-            # product and what the sampler reads back, plus the BF16
-            # activations of the hidden layers written and read
-            c_pad = (n_classes + 127) // 128 * 128
-            # logits written once; the sampler reads the per-tile (max, sum)
-            # pairs and one 128-class tile of logits
-            bytes_per_entry = 4 * c_pad + 8 * (c_pad // 128) + 4 * 128 + 2 * 2 * 4 * 256
+            # product and read twice by the sampler (energy head, position
+            # head), BF16 activations of the hidden layers written and read
+            c_pad = (n1 + n2 + 127) // 128 * 128
+            bytes_per_entry = 4 * c_pad + 4 * (n1 + 2 * n2) + 2 * 2 * 4 * 256
             bw = sst["entries"] * bytes_per_entry / (sst["ms_network"] * 1e-3)
             out[mode]["network_hbm"] = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                                        "frac": bw / HBM_PEAK, "bytes_per_entry": bytes_per_entry,
-                                        "note": "algorithmic bytes: the product's re-reads of activations "
-                                                "and weights across class tiles are not counted"}
-    a, b = hist["plain"], hist["surrogate"]
+                                        "frac": bw / HBM_PEAK, "bytes_per_entry": bytes_per_entry}
+    # independent full-transport run (seed 1) for the statistical comparison
+    nc_ind, _, _ = run("plain", 1)
+    hist["independent"] = in_window_per_crystal()
+    a, b = hist["independent"], hist["surrogate"]
     keep = (a + b) >= 10
-    ka, kb = a[keep].astype(float), b[keep].astype(float)
+    ka = np.r_[a[keep], a[~keep].sum()].astype(float)
+    kb = np.r_[b[keep], b[~keep].sum()].astype(float)
     na, nb = ka.sum(), kb.sum()
-    chi2 = float((((np.sqrt(nb / na) * ka - np.sqrt(na / nb) * kb) ** 2) / (ka + kb)).sum())
-    dof = int(keep.sum()) - 1
+    chi2 = float((((np.sqrt(nb / na) * ka - np.sqrt(na / nb) * kb) ** 2) / np.maximum(ka + kb, 1)).sum())
+    dof = len(ka) - 1
+    c_s = out["surrogate"]["coincidences"]
+    pp = (c_s + nc_ind) / (2 * n)
+    z = (c_s / n - nc_ind / n) / np.sqrt(pp * (1 - pp) * 2 / n)
     net.close()
     ctx.close()
     return {"workload": f"hot-rod phantom: design C, water cylinder 25 x 70 mm (0.5 mm voxels), six-sector rods, "
@@ -549,13 +571,19 @@ def surrogate_form(args):
             "plain": out["plain"], "surrogate": out["surrogate"],
             "speedup_vs_plain": out["surrogate"]["value"] / out["plain"]["value"],
             "sensitivity_rel_diff": out["surrogate"]["sensitivity"] / out["plain"]["sensitivity"] - 1.0,
-            "singles_chi2": {"chi2": chi2, "dof": dof, "p": float(sps.chi2.sf(chi2, dof))},
-            "spec": dict(spec, classes=n_classes),
-            "training": {"pairs": n_pairs, "events": args.surrogate_train_events, "pair_gen_s": t_pairs,
-                         "label_none_fraction": label_none, "truncated_fraction": truncated,
-                         "steps": args.surrogate_steps, "batch": 8192, "train_s": t_train,
-                         "loss_first": float(losses[0]), "loss_last100": float(np.mean(losses[-100:])),
-                         "marginal_ce": ce_marg}}
+            "matched_seeds": {"sensitivity_rel_diff": out["surrogate"]["sensitivity"] / out["plain"]["sensitivity"]
+                              - 1.0, "bar": 0.005},
+            "independent_seeds": {"plain_seed1_coincidences": nc_ind,
+                                  "sensitivity_rel_diff": c_s / nc_ind - 1.0, "z": float(z),
+                                  "p_z": float(2 * sps.norm.sf(abs(z))),
+                                  "singles_chi2": {"chi2": chi2, "dof": dof, "p": float(sps.chi2.sf(chi2, dof))}},
+            "spec": dict(spec, energy_classes=n1, positions=n2),
+            "training": {"pairs_recorded": n_rec, "truncated_fraction": n_trunc / max(1, n_rec),
+                         "pairs_trained": n_pairs, "events": args.surrogate_train_events, "pair_gen_s": t_pairs,
+                         "label_none_fraction": label_none, "steps": args.surrogate_steps, "batch": 8192,
+                         "schedule": schedule,
+                         "train_s": t_train, "train_tflop_s": train_flop / t_train / 1e12,
+                         "loss_first": float(losses[0]), "loss_last200": float(np.mean(losses[-200:]))}}
 
 
 def main():
@@ -581,13 +609,13 @@ def main():
                     help="skip the H2RSPET / Derenzo workload")
     ap.add_argument("--surrogate-events", type=int, default=100_000_000,
                     help="events of the hot-rod phantom workload timed plain and with the surrogate (0 skips)")
-    ap.add_argument("--surrogate-train-events", type=int, default=100_000_000,
-                    help="events whose detector entries make the training pairs")
-    ap.add_argument("--surrogate-steps", type=int, default=6000, help="Adam steps of batch 8192")
-    # 13 x 13 crystals per layer and 16 keV bins: the largest neighbourhood that
-    # keeps the sensitivity within about 0.5 % of full transport (5 x 5 loses
-    # 7 %, 9 x 9 3 %: the truncated class)
-    ap.add_argument("--surrogate-half-width", type=int, default=6, help="neighbourhood half width (crystals)")
+    ap.add_argument("--surrogate-train-events", type=int, default=1_640_000_000,
+                    help="events whose detector entries make the training pairs (1.64e9: about 1e8 pairs)")
+    ap.add_argument("--surrogate-steps", type=int, default=12000, help="Adam steps of batch 8192 (about one epoch)")
+    ap.add_argument("--surrogate-half-width", type=int, default=6,
+                    help="half width (crystals) of the neighbourhood an entry's domain requires inside each layer")
+    ap.add_argument("--surrogate-class-half-width", type=int, default=12,
+                    help="half width of the neighbourhood the position classes cover")
     ap.add_argument("--surrogate-ebins", type=int, default=18, help="energy bins above 224 keV")
     ap.add_argument("--surrogate-ebin-kev", type=float, default=16.0, help="energy bin width")
     args = ap.parse_args()

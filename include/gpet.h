@@ -437,17 +437,18 @@ gpet_status gpet_mlp_create(gpet_ctx *ctx, int32_t n_sizes, const int32_t *sizes
                             gpet_mlp **out);
 /* The same network with a factored output (the surrogate's form): of the
  * last layer's sizes[n_sizes - 1] outputs, the first n_first (2..64) are an
- * energy head (class 0 = no single) and the other n2 = sizes[n_sizes - 1] -
- * n_first are positions; the position given energy class e > 0 follows
- * softmax(positions + T[e - 1]) with a learned FP32 offset table T of
- * (n_first - 1) x n2, packed after the layers (row-major).  Labels are
+ * energy head (class 0 = no single) and the rest n_groups (1..n_first - 1)
+ * equal blocks of n2 position logits; the position given energy class e > 0
+ * follows softmax(block g + T[e - 1]) with g = (e - 1) n_groups / (n_first -
+ * 1) (contiguous groups of energy classes share a block) and a learned FP32
+ * offset table T of (n_first - 1) x n2, packed after the layers (row-major).  Labels are
  * joint: 0 for e = 0, else 1 + k (n_first - 1) + (e - 1) for position k
  * (the layout of the surrogate's classes with n_first = n_ebins + 2).  The
  * loss is -log P(e) - [e > 0] log P(k | e); gpet_mlp_forward returns the raw
  * last-layer outputs (T not added).  A design choice of this library; the
  * paper names learned surrogates only as a route to speed (Sec. 4). */
 gpet_status gpet_mlp_create_factored(gpet_ctx *ctx, int32_t n_sizes, const int32_t *sizes, int32_t n_first,
-                                     const float *weights, gpet_mlp **out);
+                                     int32_t n_groups, const float *weights, gpet_mlp **out);
 void gpet_mlp_destroy(gpet_mlp *mlp);
 /* Replaces the master weights (host, packed) and clears the Adam state. */
 gpet_status gpet_mlp_set_weights(gpet_mlp *mlp, const float *weights);
@@ -484,19 +485,24 @@ gpet_status gpet_mlp_train(gpet_mlp *mlp, uint64_t n_pairs, const float *x, cons
 /* in the anchor cell), the two slopes over max_slope, 2 (E - e_min) /      */
 /* (511 - e_min) - 1, and the depth component of the direction.             */
 /* Classes: 0 = no crystal of the panel stay collects e_min_kev or more, or  */
-/* the largest sum lies outside the neighbourhood; else 1 + ((layer W + i) W */
-/* + j) (n_ebins + 1) + bin for the crystal with the largest deposit sum    */
-/* (ties: lower gid), (i, j) its offset + half_width from the anchor,       */
-/* W = 2 half_width + 1, bin = n_ebins when the sum is within               */
-/* photopeak_tol_kev of the entry energy, else floor((sum - e_min) / ebin)  */
-/* clipped to [0, n_ebins - 1].  A class stands for one single: the entry   */
-/* energy (photopeak) or e_min + ebin (bin + u) deposited at the layer's    */
-/* mid-depth in that crystal, at the entry time.                            */
+/* the largest sum lies outside the class neighbourhood (half width H =     */
+/* class_half_width, or half_width when 0); else 1 + ((layer W + i) W + j)  */
+/* (n_ebins + 1) + bin for the crystal with the largest deposit sum (ties:  */
+/* lower gid), (i, j) its offset + H from the anchor, W = 2 H + 1, bin =    */
+/* n_ebins when the sum is within photopeak_tol_kev of the entry energy,    */
+/* else floor((sum - e_min) / ebin) clipped to [0, n_ebins - 1].  With H >  */
+/* half_width, class positions may fall outside a layer's array: they never */
+/* occur as labels, and the sampler of a factored network leaves them out.  */
+/* A class stands for one single: the entry energy (photopeak) or e_min +   */
+/* ebin (bin + u) deposited at the layer's mid-depth in that crystal, at    */
+/* the entry time.                                                          */
 /* ---------------------------------------------------------------------- */
 typedef struct {
-  int32_t half_width;  /* 0..7 */
+  int32_t half_width;  /* 0..7: the domain's neighbourhood */
   int32_t n_ebins;     /* 1..1024 */
   double e_min_kev, ebin_kev, photopeak_tol_kev, max_slope, front_tol_mm;
+  int32_t class_half_width; /* 0 (= half_width) or half_width..15: the classes' neighbourhood
+                               (above half_width: factored networks only) */
 } gpet_surrogate_spec;
 
 /* Training pairs (device SoA): features x[6 per pair], class label, event
@@ -531,8 +537,8 @@ gpet_status gpet_surrogate_pairs(gpet_ctx *ctx, const gpet_surrogate_spec *spec,
  * energy class --, word 1 the energy in its bin, word 2 the position of a
  * factored network); every other photon is transported in full.  The
  * network must map 6 features to the spec's class count for this scanner
- * (factored: n_ebins + 2 energy classes and n_layers (2 half_width + 1)^2
- * positions).  Hits as gpet_transport (surrogate singles carry process 3 in
+ * (factored: n_ebins + 2 energy classes and n_layers (2 H + 1)^2 positions
+ * per block).  Hits as gpet_transport (surrogate singles carry process 3 in
  * aux). */
 gpet_status gpet_surrogate_transport(gpet_ctx *ctx, gpet_mlp *mlp, const gpet_surrogate_spec *spec,
                                      uint64_t first_event, uint64_t n_events, uint64_t seed, uint32_t instance,

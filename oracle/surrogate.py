@@ -41,10 +41,17 @@ class Spec:
     photopeak_tol_kev: float = 1.0  # largest deposit within this of the entry energy: photopeak
     max_slope: float = 0.25       # |d_t / d_depth| and |d_a / d_depth| inside the domain
     front_tol_mm: float = 1e-3    # entry depth coordinate of a front-face entry
+    class_half_width: int = 0     # half width of the class neighbourhood (0: half_width)
+
+    @property
+    def chalf(self):
+        """Half width of the neighbourhood the outcome classes cover (at least
+        the domain's; wider, it may reach past a layer's array)."""
+        return self.class_half_width or self.half_width
 
     @property
     def width(self):
-        return 2 * self.half_width + 1
+        return 2 * self.chalf + 1
 
     def n_classes(self, n_layers: int) -> int:
         return 1 + n_layers * self.width ** 2 * (self.n_ebins + 1)
@@ -166,7 +173,7 @@ def outcome_class(spec: Spec, lat: Lattice, ent: Entry, panel: int, e_in: float,
         return 0, False
     p, m, l, it, ia = lat.decode(best)
     at, aa = ent.anchor[l]
-    h, W = spec.half_width, spec.width
+    h, W = spec.chalf, spec.width
     if p != panel or m != ent.module or abs(it - at) > h or abs(ia - aa) > h:
         return 0, True
     if esum >= e_in - spec.photopeak_tol_kev:
@@ -183,7 +190,7 @@ def class_hit(spec: Spec, lat: Lattice, ent: Entry, panel: int, e_in: float, c: 
     if c == 0:
         return None
     k, b = divmod(c - 1, spec.n_ebins + 1)
-    W, h = spec.width, spec.half_width
+    W, h = spec.width, spec.chalf
     l, r = divmod(k, W * W)
     dt, da = divmod(r, W)
     at, aa = ent.anchor[l]
@@ -191,6 +198,20 @@ def class_hit(spec: Spec, lat: Lattice, ent: Entry, panel: int, e_in: float, c: 
     gid = lat.gid(panel, ent.module, l, at + dt - h, aa + da - h)
     edep = e_in if b == spec.n_ebins else spec.e_min_kev + spec.ebin_kev * (b + u_energy)
     return gid, edep, y["depth0"] + 0.5 * y["thick"]
+
+
+def positions_exist(spec: Spec, lat: Lattice, ent: Entry) -> np.ndarray:
+    """Which positions of the class neighbourhood (layer, then offsets -H..H
+    in t and a around the layer's anchor) lie inside their layer's crystal
+    array: a largest deposit can only be there."""
+    W, h = spec.width, spec.chalf
+    out = np.zeros(len(lat.layers) * W * W, bool)
+    for l, y in enumerate(lat.layers):
+        at, aa = ent.anchor[l]
+        for dt in range(W):
+            for da in range(W):
+                out[(l * W + dt) * W + da] = 0 <= at + dt - h < y["n_t"] and 0 <= aa + da - h < y["n_a"]
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -322,9 +343,12 @@ def sample_class(logits, u):
 # The outcome class (position k in the neighbourhood, energy index b, or
 # none) is drawn in two steps: the energy class e (0 = none, 1 + b
 # otherwise) from a softmax over the first n_first logits, then, for e > 0,
-# the position from a softmax over the remaining logits plus a learned row
-# T[e - 1] of per-energy position offsets.  The joint label keeps the layout
-# of outcome_class: 0, or 1 + k (n_first - 1) + (e - 1).
+# the position from a softmax over one block of n2 position logits plus a
+# learned row T[e - 1] of per-energy position offsets.  The logits after the
+# energy head hold n_groups such blocks; energy class e uses block
+# g(e) = (e - 1) n_groups // (n_first - 1), so contiguous groups of energy
+# classes share one.  The joint label keeps the layout of outcome_class: 0,
+# or 1 + k (n_first - 1) + (e - 1).
 def factored_split(y, n_first):
     """Joint labels -> (energy class e, position k; k = 0 where e = 0)."""
     y = np.asarray(y, np.int64)
@@ -339,37 +363,48 @@ def factored_join(e, k, n_first):
     return np.where(e > 0, 1 + np.asarray(k, np.int64) * (n_first - 1) + (e - 1), 0)
 
 
-def factored_log_prob(z, T, y, n_first):
+def _position_logits(z, T, e, n_first, n_groups):
+    """Rows' position logits for energy classes e > 0: block g(e) plus T[e - 1]."""
+    n2 = (z.shape[1] - n_first) // n_groups
+    start = n_first + ((e - 1) * n_groups // (n_first - 1)) * n2
+    cols = start[:, None] + np.arange(n2)[None, :]
+    return np.take_along_axis(z, cols, axis=1) + T[e - 1], cols
+
+
+def factored_log_prob(z, T, y, n_first, n_groups=1):
     """log P(y | x) per row from output logits z and the offset table T."""
     e, k = factored_split(y, n_first)
-    z1, z2 = z[:, :n_first], z[:, n_first:]
+    z1 = z[:, :n_first]
     m1 = z1.max(axis=1)
     lp = z1[np.arange(len(e)), e] - (m1 + np.log(np.exp(z1 - m1[:, None]).sum(axis=1)))
     pos = e > 0
     if pos.any():
-        z2p = z2[pos] + T[e[pos] - 1]
+        z2p, _ = _position_logits(z[pos], T, e[pos], n_first, n_groups)
         m2 = z2p.max(axis=1)
         lp[pos] += z2p[np.arange(pos.sum()), k[pos]] - (m2 + np.log(np.exp(z2p - m2[:, None]).sum(axis=1)))
     return lp
 
 
-def factored_loss_and_grad(params, T, x, y, n_first, store=None):
+def factored_loss_and_grad(params, T, x, y, n_first, store=None, n_groups=1):
     """Mean of -log P(y | x) under the factored output, and its gradient with
     respect to every weight and bias and to T (backpropagation written out;
     `store` rounds hidden activations as in loss_and_grad)."""
     z, ins, zs = forward(params, x, store)
     n = len(y)
     e, k = factored_split(y, n_first)
-    loss = float(-np.mean(factored_log_prob(z, T, y, n_first)))
+    loss = float(-np.mean(factored_log_prob(z, T, y, n_first, n_groups)))
     dz = np.zeros_like(z)
     dz[:, :n_first] = softmax(z[:, :n_first])
     dz[np.arange(n), e] -= 1.0
     pos = np.flatnonzero(e > 0)
     gT = np.zeros_like(T)
     if len(pos):
-        p2 = softmax(z[pos, n_first:] + T[e[pos] - 1])
+        z2p, cols = _position_logits(z[pos], T, e[pos], n_first, n_groups)
+        p2 = softmax(z2p)
         p2[np.arange(len(pos)), k[pos]] -= 1.0
-        dz[pos, n_first:] = p2
+        block = dz[pos]
+        np.put_along_axis(block, cols, p2, axis=1)
+        dz[pos] = block
         np.add.at(gT, e[pos] - 1, p2 / n)
     dz = dz / n
     grads = [None] * len(params)
@@ -381,16 +416,27 @@ def factored_loss_and_grad(params, T, x, y, n_first, store=None):
     return loss, grads, gT
 
 
-def factored_sample(z, T, n_first, u_energy_class, u_position):
+def factored_sample(z, T, n_first, u_energy_class, u_position, n_groups=1, exists=None):
     """Joint class per row: e = first energy class whose cumulative softmax
     mass reaches u_energy_class; for e > 0, the first position whose
-    cumulative mass under softmax(z2 + T[e - 1]) reaches u_position."""
+    cumulative mass under softmax(block g(e) + T[e - 1]) reaches u_position.
+    exists (optional, rows x positions): positions that cannot occur are
+    left out of that softmax."""
     z = np.atleast_2d(z)
     e = sample_class(z[:, :n_first], u_energy_class)
     k = np.zeros_like(e)
     pos = np.flatnonzero(e > 0)
     if len(pos):
-        k[pos] = sample_class(z[pos, n_first:] + T[e[pos] - 1], np.atleast_1d(u_position)[pos])
+        z2p, _ = _position_logits(z[pos], T, e[pos], n_first, n_groups)
+        if exists is not None:
+            ex = np.atleast_2d(exists)[pos]
+            z2p = np.where(ex, z2p, -np.inf)
+            kk = sample_class(z2p, np.atleast_1d(u_position)[pos])
+            # a target beyond the total by rounding: the last position that exists
+            last = ex.shape[1] - 1 - np.argmax(ex[:, ::-1], axis=1)
+            k[pos] = np.where(ex[np.arange(len(pos)), kk], kk, last)
+        else:
+            k[pos] = sample_class(z2p, np.atleast_1d(u_position)[pos])
     return factored_join(e, k, n_first)
 
 
@@ -407,11 +453,11 @@ def unpack(flat, sizes):
     return params
 
 
-def unpack_factored(flat, sizes, n_first):
+def unpack_factored(flat, sizes, n_first, n_groups=1):
     """Packed weights of a factored network: the layers as in unpack, then the
-    offset table T [n_first - 1][sizes[-1] - n_first] row-major."""
+    offset table T [n_first - 1][(sizes[-1] - n_first) / n_groups] row-major."""
     n_layers = sum(i * j + j for i, j in zip(sizes[:-1], sizes[1:]))
-    n2 = sizes[-1] - n_first
+    n2 = (sizes[-1] - n_first) // n_groups
     T = np.asarray(flat[n_layers:n_layers + (n_first - 1) * n2], np.float64).reshape(n_first - 1, n2)
     return unpack(flat[:n_layers], sizes), T
 

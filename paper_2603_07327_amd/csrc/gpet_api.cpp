@@ -931,23 +931,26 @@ static gpet_status surrogate_spec(gpet_ctx *c, const gpet_surrogate_spec *p, Sur
   if (!p) return fail(c, GPET_ERR_ARG, "surrogate: null spec");
   if (p->half_width < 0 || p->half_width > 7 || p->n_ebins < 1 || p->n_ebins > 1024 ||
       !(p->e_min_kev > 0 && p->e_min_kev < 511.0) || !(p->ebin_kev > 0) || !(p->photopeak_tol_kev >= 0) ||
-      !(p->max_slope > 0) || !(p->front_tol_mm > 0))
+      !(p->max_slope > 0) || !(p->front_tol_mm > 0) ||
+      (p->class_half_width != 0 && (p->class_half_width < p->half_width || p->class_half_width > 15)))
     return fail(c, GPET_ERR_ARG, "surrogate: spec out of range");
   const DevScene &S = c->scene;
   const int W = 2 * p->half_width + 1;
+  const int H = p->class_half_width ? p->class_half_width : p->half_width, Wc = 2 * H + 1;
   for (int l = 0; l < S.n_layers; ++l)
     if (S.layer[l].n_t < W || S.layer[l].n_a < W || S.layer[l].n_t > 65535 || S.layer[l].n_a > 65535)
       return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: a layer is narrower than the neighbourhood (or wider than 65535)");
   if (S.n_panels > 127 || S.mod_n_t * S.mod_n_a > (1 << 24))
     return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: more than 127 panels or 2^24 modules");
   P.half = p->half_width;
+  P.chalf = H;
   P.n_ebins = p->n_ebins;
   P.e_min = (float)p->e_min_kev;
   P.ebin = (float)p->ebin_kev;
   P.tol = (float)p->photopeak_tol_kev;
   P.max_slope = (float)p->max_slope;
   P.front_tol = (float)p->front_tol_mm;
-  n_classes = 1 + S.n_layers * W * W * (p->n_ebins + 1);
+  n_classes = 1 + S.n_layers * Wc * Wc * (p->n_ebins + 1);
   return GPET_OK;
 }
 
@@ -1027,14 +1030,16 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   if (s) return s;
   if (!q || q->ctx != c) return fail(c, GPET_ERR_ARG, "surrogate: network missing or made on another context");
   if (q->n_first) {
-    const int W = 2 * spec->half_width + 1;
+    const int W = 2 * P.chalf + 1;
     if (q->size[0] != 6 || q->n_first != spec->n_ebins + 2 || q->n_second != c->scene.n_layers * W * W)
       return fail(c, GPET_ERR_ARG, "surrogate: a factored network must map 6 features to " +
                                        std::to_string(spec->n_ebins + 2) + " energy classes and " +
-                                       std::to_string(c->scene.n_layers * W * W) + " positions");
+                                       std::to_string(c->scene.n_layers * W * W) + " positions per block");
   } else if (q->size[0] != 6 || q->size[q->n_layers] != n_classes) {
     return fail(c, GPET_ERR_ARG, "surrogate: the network must map 6 features to " + std::to_string(n_classes) +
                                      " classes for this scanner and spec");
+  } else if (P.chalf != P.half) {
+    return fail(c, GPET_ERR_ARG, "surrogate: a class neighbourhood wider than the domain's needs a factored network");
   }
   if (!h) return fail(c, GPET_ERR_ARG, "surrogate: null hits");
   if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "surrogate: event range");

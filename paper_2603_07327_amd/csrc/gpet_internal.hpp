@@ -15,6 +15,7 @@ namespace gpet {
 // gpet_surrogate_spec in the C header).
 struct SurSpecD {
   int half, n_ebins;
+  int chalf; // half width of the class neighbourhood (>= half)
   float e_min, ebin, tol, max_slope, front_tol;
 };
 
@@ -268,10 +269,12 @@ struct gpet_mlp {
   int n_layers = 0;       // weight matrices
   size_t n_params = 0;
   std::vector<size_t> w_off, b_off;                  // offsets in the packed parameter vector
-  // factored output: the first n_first outputs are the energy head, the other
-  // n_second the positions, with an fp32 offset table [n_first - 1][n_second]
-  // at tab_off in the packed parameters (n_first = 0: one joint softmax)
-  int n_first = 0, n_second = 0;
+  // factored output: the first n_first outputs are the energy head, then
+  // n_groups blocks of n_second positions (energy class e > 0 uses block
+  // (e - 1) n_groups / (n_first - 1)), with an fp32 offset table
+  // [n_first - 1][n_second] at tab_off in the packed parameters (n_first = 0:
+  // one joint softmax)
+  int n_first = 0, n_second = 0, n_groups = 0;
   size_t tab_off = 0;
   float *master = nullptr, *m = nullptr, *v = nullptr; // packed fp32 (per layer W [out][in], then b)
   std::vector<uint16_t *> wb;                        // padded bf16 weights per layer [out_pad][in_pad]

@@ -432,12 +432,16 @@ __global__ void __launch_bounds__(256) k_softmax_ce(const float *z, int ldz, int
 }
 
 // Factored output (energy head, then the position given the energy): the
-// first n1 logits are the energy classes (0 = none), the next n2 the
-// positions, shifted by the row T[e - 1] of the offset table for energy class
-// e.  A joint label y is 0 (e = 0) or 1 + k (n1 - 1) + (e - 1).
+// first n1 logits are the energy classes (0 = none), then G blocks of n2
+// position logits; energy class e > 0 uses block g(e) = (e - 1) G / (n1 - 1)
+// (contiguous groups of energy classes), shifted by the row T[e - 1] of the
+// offset table.  A joint label y is 0 (e = 0) or 1 + k (n1 - 1) + (e - 1).
 __device__ __forceinline__ void factored_label(int y, int n1, int &e, int &k) {
   e = y > 0 ? 1 + (y - 1) % (n1 - 1) : 0;
   k = y > 0 ? (y - 1) / (n1 - 1) : 0;
+}
+__device__ __forceinline__ int position_block(int e, int n1, int n2, int G) {
+  return n1 + ((e - 1) * G) / (n1 - 1) * n2;
 }
 
 // wave-wide maximum and sum of exp(v - max) of z2[c] + t[c], c < n2 (strided by lane)
@@ -457,7 +461,7 @@ __device__ __forceinline__ void offset_row_max_sum(const float *z2, const float 
 // with respect to the logits, as hi + lo bf16 planes (zero in padded columns
 // and rows); erow[r] = e (0 for padded rows); a label outside the classes sets
 // *bad and is read as 0.  n1 <= 64.
-__global__ void __launch_bounds__(256) k_factored_ce(const float *z, int ldz, int n1, int n2, const float *T,
+__global__ void __launch_bounds__(256) k_factored_ce(const float *z, int ldz, int n1, int n2, int G, const float *T,
                                                      const int32_t *y, uint32_t n, uint32_t n_pad, float inv_n,
                                                      uint16_t *dz, size_t dz_lo, double *row_loss, int32_t *erow,
                                                      uint32_t *bad) {
@@ -489,8 +493,9 @@ __global__ void __launch_bounds__(256) k_factored_ce(const float *z, int ldz, in
   float s1 = lane < n1 ? __expf(v1 - m1) : 0.f;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s1 += __shfl_xor(s1, o);
-  // position head given e
-  const float *z2 = zr + n1;
+  // position head given e (its block of position logits)
+  const int pb = e > 0 ? position_block(e, n1, n2, G) : n1;
+  const float *z2 = zr + pb;
   const float *t = T + (size_t)(e > 0 ? e - 1 : 0) * n2;
   float m2 = 0.f, s2 = 1.f;
   if (e > 0) offset_row_max_sum(z2, t, n2, lane, m2, s2);
@@ -499,8 +504,8 @@ __global__ void __launch_bounds__(256) k_factored_ce(const float *z, int ldz, in
     float g = 0.f;
     if (c < n1) {
       g = (__expf(zr[c] - m1) * inv_s1 - (c == e ? 1.0f : 0.0f)) * inv_n;
-    } else if (e > 0 && c < n1 + n2) {
-      const int j = c - n1;
+    } else if (e > 0 && c >= pb && c < pb + n2) {
+      const int j = c - pb;
       g = (__expf(z2[j] + t[j] - m2) * inv_s2 - (j == k ? 1.0f : 0.0f)) * inv_n;
     }
     const uint16_t hi = f2bf(g);
@@ -518,29 +523,45 @@ __global__ void __launch_bounds__(256) k_factored_ce(const float *z, int ldz, in
 // partial offset-table gradients: slice blockIdx.z of `slices` sums, over its
 // rows r with energy class e = blockIdx.y + 1, the position-head gradient
 // (hi + lo) into part[slice][(e - 1) n2 + j]
-__global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int n1, int n2, const int32_t *erow,
-                                  uint32_t rows, int slices, float *part) {
+__global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int n1, int n2, int G,
+                                  const int32_t *erow, uint32_t rows, int slices, float *part) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int e = (int)blockIdx.y + 1;
   if (j >= n2) return;
   const uint32_t per = (rows + slices - 1) / slices;
   const uint32_t r0 = blockIdx.z * per, r1 = min(rows, r0 + per);
+  const int pb = position_block(e, n1, n2, G);
   float a = 0.f;
   for (uint32_t r = r0; r < r1; ++r)
     if (erow[r] == e) {
-      const size_t o = (size_t)r * ldz + n1 + j;
+      const size_t o = (size_t)r * ldz + pb + j;
       a += bf2f(dz[o]) + bf2f(dz[o + dz_lo]);
     }
   part[(size_t)blockIdx.z * (n1 - 1) * n2 + (size_t)(e - 1) * n2 + j] = a;
 }
 
+// Position j of the class neighbourhood (layer, then offsets of half width
+// H around the layer's anchor) lies inside that layer's crystal array
+__device__ __forceinline__ bool position_exists(int j, const uint32_t *anchor, const DevScene *S, int H) {
+  const int W = 2 * H + 1;
+  const int l = j / (W * W), rr = j - l * W * W;
+  const int dt = rr / W, da = rr - dt * W;
+  const uint32_t aw = anchor[l];
+  const int it = (int)(aw & 0xFFFFu) + dt - H, ia = (int)(aw >> 16) + da - H;
+  return it >= 0 && it < S->layer[l].n_t && ia >= 0 && ia < S->layer[l].n_a;
+}
+
 // Factored sampling, one wave per queue entry: the energy class e = first
 // class whose cumulative softmax mass reaches u0 * total (u0: word 0 of
 // Philox (0, event, inst_rng, 4 + photon)); for e > 0 the position k = first
-// position whose cumulative mass under softmax(z2 + T[e - 1]) reaches u2 *
-// total (word 2), walked 64 positions at a time.  cls = the joint label.
-__global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, const float *T,
-                                                         uint32_t n, const uint32_t *ev, const uint32_t *meta,
+// position whose cumulative mass under softmax(z2 + T[e - 1]) over the
+// positions that exist (inside their layer's array around the entry's
+// anchors) reaches u2 * total (word 2), walked 64 positions at a time.  cls =
+// the joint label.
+__global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, int G,
+                                                         const float *T, uint32_t n, const uint32_t *ev,
+                                                         const uint32_t *meta, const uint32_t *anchor,
+                                                         const DevScene *S, int H,
                                                          uint32_t k0, uint32_t k1, uint32_t inst_rng, uint32_t *cls,
                                                          uint32_t *nonzero) {
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -570,24 +591,40 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
     }
     return;
   }
-  // position given e
-  const float *z2 = zr + n1;
+  // position given e, over the positions that exist
+  const float *z2 = zr + position_block(e, n1, n2, G);
   const float *t = T + (size_t)(e - 1) * n2;
-  float m2, s2;
-  offset_row_max_sum(z2, t, n2, lane, m2, s2);
+  const uint32_t *an = anchor + (size_t)kMaxLayers * r;
+  float m2 = -INFINITY;
+  int last = -1;
+  for (int c = lane; c < n2; c += 64)
+    if (position_exists(c, an, S, H)) {
+      m2 = fmaxf(m2, z2[c] + t[c]);
+      last = c;
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m2 = fmaxf(m2, __shfl_xor(m2, o));
+    last = max(last, __shfl_xor(last, o));
+  }
+  float s2 = 0.f;
+  for (int c = lane; c < n2; c += 64)
+    if (position_exists(c, an, S, H)) s2 += __expf(z2[c] + t[c] - m2);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
   const float target2 = to_unit(w.z) * s2;
-  int k = n2 - 1; // rounding left the target beyond the last position
+  int k = last; // rounding left the target beyond the last position
   float acc = 0.f;
   for (int c0 = 0; c0 < n2; c0 += 64) {
     const int c = c0 + lane;
-    const float p = c < n2 ? __expf(z2[c] + t[c] - m2) : 0.f;
+    const float p = (c < n2 && position_exists(c, an, S, H)) ? __expf(z2[c] + t[c] - m2) : 0.f;
     float in2 = p;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const float tt = __shfl_up(in2, o);
       if (lane >= o) in2 += tt;
     }
-    const uint64_t cr = __ballot(acc + in2 >= target2 && c < n2);
+    const uint64_t cr = __ballot(acc + in2 >= target2 && p > 0.f);
     if (cr) {
       k = c0 + __ffsll((unsigned long long)cr) - 1;
       break;
@@ -796,12 +833,12 @@ __global__ void k_emit_hits(uint32_t n, const uint32_t *cls, const uint32_t *pos
   if (r >= n || cls[r] == 0) return;
   const DevScene &S = *Sp;
   const int c = (int)cls[r] - 1;
-  const int nb = P.n_ebins + 1, W = 2 * P.half + 1;
+  const int nb = P.n_ebins + 1, W = 2 * P.chalf + 1;
   const int b = c % nb, k = c / nb;
   const int l = k / (W * W), rr = k - l * W * W;
   const int dt = rr / W, da = rr - dt * W;
   const uint32_t aw = anchor[(size_t)kMaxLayers * r + l];
-  const int it = (int)(aw & 0xFFFFu) + dt - P.half, ia = (int)(aw >> 16) + da - P.half;
+  const int it = (int)(aw & 0xFFFFu) + dt - P.chalf, ia = (int)(aw >> 16) + da - P.chalf;
   const uint32_t m = meta[r];
   const int panel = (int)((m >> 1) & 127u), module = (int)(m >> 8);
   const int gid = panel * S.crystals_per_panel + module * S.crystals_per_module + S.layer[l].base +
@@ -933,13 +970,13 @@ void backward(gpet_mlp *q, uint32_t n, uint32_t n_pad, hipStream_t st) {
   const int L = q->n_layers;
   const int C = q->size[L], Cp = q->psize[L];
   if (q->n_first) {
-    const int n1 = q->n_first, n2 = q->n_second;
+    const int n1 = q->n_first, n2 = q->n_second, G = q->n_groups;
     const float *T = q->master + q->tab_off;
-    hipLaunchKernelGGL(k_factored_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, n1, n2, T, q->yb, n,
+    hipLaunchKernelGGL(k_factored_ce, dim3(cdiv(n_pad, 4)), dim3(256), 0, st, q->logits, Cp, n1, n2, G, T, q->yb, n,
                        n_pad, 1.0f / (float)n, q->dz[0], (size_t)n_pad * Cp, q->row_loss, q->erow, q->flag);
     const size_t nt = (size_t)(n1 - 1) * n2;
     hipLaunchKernelGGL(k_table_grad_part, dim3(cdiv(n2, 256), n1 - 1, kTableSlices), dim3(256), 0, st, q->dz[0],
-                       (size_t)n_pad * Cp, Cp, n1, n2, q->erow, n_pad, kTableSlices, q->part);
+                       (size_t)n_pad * Cp, Cp, n1, n2, G, q->erow, n_pad, kTableSlices, q->part);
     hipLaunchKernelGGL(k_reduce_slices, dim3(cdiv(nt, 256)), dim3(256), 0, st, q->part, kTableSlices, nt,
                        q->gb + q->tab_off);
   } else {
@@ -1005,7 +1042,8 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
     if (q->n_first) {
       forward(q, n_pad, st);
       hipLaunchKernelGGL(k_sample_factored, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first,
-                         q->n_second, (const float *)(q->master + q->tab_off), n, Q.ev + off, Q.meta + off, k0, k1,
+                         q->n_second, q->n_groups, (const float *)(q->master + q->tab_off), n, Q.ev + off,
+                         Q.meta + off, Q.anchor + (size_t)kMaxLayers * off, d_scene, P.chalf, k0, k1,
                          inst_rng, Q.cls + off, Q.pos + off);
     } else if (tiles) {
       forward_sample(q, n_pad, st);
@@ -1039,7 +1077,7 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
 extern "C" {
 
 static gpet_status mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, int32_t n_first,
-                              const float *weights, gpet_mlp **out) {
+                              int32_t n_groups, const float *weights, gpet_mlp **out) {
   if (!c || !out || !sizes) return GPET_ERR_ARG;
   *out = nullptr;
   if (n_sizes < 2 || n_sizes > 16) {
@@ -1055,8 +1093,10 @@ static gpet_status mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes
       c->err = "mlp: layer widths in 1..8192";
       return GPET_ERR_ARG;
     }
-  if (n_first && (n_first < 2 || n_first > 64 || n_first >= sizes[n_sizes - 1])) {
-    c->err = "mlp: the energy head takes 2..64 of the output classes and leaves at least one position";
+  if (n_first && (n_first < 2 || n_first > 64 || n_first >= sizes[n_sizes - 1] || n_groups < 1 ||
+                  n_groups > n_first - 1 || (sizes[n_sizes - 1] - n_first) % n_groups != 0)) {
+    c->err = "mlp: the energy head takes 2..64 of the outputs, the rest splits into 1..n_first - 1 equal "
+             "position blocks";
     return GPET_ERR_ARG;
   }
   gpet_mlp *q = new (std::nothrow) gpet_mlp();
@@ -1076,7 +1116,8 @@ static gpet_status mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes
     o += (size_t)sizes[l + 1];
   }
   q->n_first = n_first;
-  q->n_second = n_first ? sizes[n_sizes - 1] - n_first : 0;
+  q->n_groups = n_first ? n_groups : 0;
+  q->n_second = n_first ? (sizes[n_sizes - 1] - n_first) / n_groups : 0;
   q->tab_off = o; // the offset table of a factored output follows the layers
   if (n_first) o += (size_t)(n_first - 1) * q->n_second;
   q->n_params = o;
@@ -1107,16 +1148,16 @@ static gpet_status mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes
 }
 
 gpet_status gpet_mlp_create(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, const float *weights, gpet_mlp **out) {
-  return mlp_create(c, n_sizes, sizes, 0, weights, out);
+  return mlp_create(c, n_sizes, sizes, 0, 0, weights, out);
 }
 
 gpet_status gpet_mlp_create_factored(gpet_ctx *c, int32_t n_sizes, const int32_t *sizes, int32_t n_first,
-                                     const float *weights, gpet_mlp **out) {
+                                     int32_t n_groups, const float *weights, gpet_mlp **out) {
   if (n_first < 2) {
     if (c) c->err = "mlp: the energy head needs at least 2 classes";
     return GPET_ERR_ARG;
   }
-  return mlp_create(c, n_sizes, sizes, n_first, weights, out);
+  return mlp_create(c, n_sizes, sizes, n_first, n_groups, weights, out);
 }
 
 void gpet_mlp_destroy(gpet_mlp *q) {

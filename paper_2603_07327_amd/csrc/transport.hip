@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
             const int ia = idx / S.layer[l].n_t, it = idx - ia * S.layer[l].n_t;
             const uint32_t aw = rec_anchor[l];
             const int at = (int)(aw & 0xFFFFu), aa = (int)(aw >> 16);
-            const int h = A.sur.half, W = 2 * h + 1;
+            const int h = A.sur.chalf, W = 2 * h + 1; // the class neighbourhood
             if (r < 0 || r >= S.crystals_per_panel || m != rec_module || abs(it - at) > h || abs(ia - aa) > h) {
               flags |= 1u; // the largest deposit lies outside the neighbourhood
             } else {

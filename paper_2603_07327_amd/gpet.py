@@ -157,7 +157,7 @@ class TrainParams(C.Structure):
 class SurrogateSpec(C.Structure):
     _fields_ = [("half_width", C.c_int32), ("n_ebins", C.c_int32), ("e_min_kev", C.c_double),
                 ("ebin_kev", C.c_double), ("photopeak_tol_kev", C.c_double), ("max_slope", C.c_double),
-                ("front_tol_mm", C.c_double)]
+                ("front_tol_mm", C.c_double), ("class_half_width", C.c_int32)]
 
 
 class Pairs(C.Structure):
@@ -230,7 +230,7 @@ def load_library(path: str = LIB_PATH):
     L.gpet_batch_digitize.argtypes = [vp, P(Hits), P(Digitizer), P(Singles), P(Coincidences), vp]
     L.gpet_batch_autotune.argtypes = [vp, C.c_uint64, P(Hits), C.c_char_p, C.c_size_t]
     L.gpet_mlp_create.argtypes = [vp, C.c_int32, vp, vp, P(vp)]
-    L.gpet_mlp_create_factored.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, P(vp)]
+    L.gpet_mlp_create_factored.argtypes = [vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, P(vp)]
     L.gpet_mlp_destroy.argtypes = [vp]
     L.gpet_mlp_destroy.restype = None
     L.gpet_mlp_set_weights.argtypes = [vp, vp]
@@ -635,7 +635,7 @@ class Context:
     def spec_struct(spec=None):
         """SurrogateSpec from a dict or object with the oracle's Spec fields."""
         d = {"half_width": 2, "n_ebins": 36, "e_min_kev": 224.0, "ebin_kev": 8.0, "photopeak_tol_kev": 1.0,
-             "max_slope": 0.25, "front_tol_mm": 1e-3}
+             "max_slope": 0.25, "front_tol_mm": 1e-3, "class_half_width": 0}
         if spec is not None:
             d.update(spec if isinstance(spec, dict) else {k: getattr(spec, k) for k in d})
         return SurrogateSpec(**d)
@@ -863,16 +863,16 @@ def unpack_params(flat, sizes):
 
 class Mlp:
     """The surrogate network on the GPU (BF16 matrix cores, FP32 master weights).
-    n_first > 0: factored output (energy head of n_first classes, positions
-    with an offset table; gpet_mlp_create_factored)."""
+    n_first > 0: factored output (energy head of n_first classes, n_groups
+    blocks of positions, an offset table; gpet_mlp_create_factored)."""
 
-    def __init__(self, ctx: Context, sizes, weights=None, n_first=0):
+    def __init__(self, ctx: Context, sizes, weights=None, n_first=0, n_groups=1):
         self.ctx, self.L = ctx, ctx.L
         self.sizes = [int(v) for v in sizes]
-        self.n_first = int(n_first)
+        self.n_first, self.n_groups = int(n_first), int(n_groups)
         self.n_params = sum(i * j + j for i, j in zip(self.sizes[:-1], self.sizes[1:]))
         if self.n_first:
-            self.n_params += (self.n_first - 1) * (self.sizes[-1] - self.n_first)
+            self.n_params += (self.n_first - 1) * ((self.sizes[-1] - self.n_first) // self.n_groups)
         sz = np.array(self.sizes, np.int32)
         w = None if weights is None else np.ascontiguousarray(weights, np.float32)
         if w is not None and w.size != self.n_params:
@@ -880,8 +880,8 @@ class Mlp:
         h = C.c_void_p()
         wp = None if w is None else w.ctypes.data_as(C.c_void_p)
         if self.n_first:
-            rc = self.L.gpet_mlp_create_factored(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p), self.n_first, wp,
-                                                 C.byref(h))
+            rc = self.L.gpet_mlp_create_factored(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p), self.n_first,
+                                                 self.n_groups, wp, C.byref(h))
         else:
             rc = self.L.gpet_mlp_create(ctx.h, len(sz), sz.ctypes.data_as(C.c_void_p), wp, C.byref(h))
         ctx._check(rc, "mlp")

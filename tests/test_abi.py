@@ -43,6 +43,7 @@ def test_struct_layouts_match_c(tmp_path):
                "gpet_scanner": gpet.Scanner, "gpet_geometry_info": gpet.GeometryInfo,
                "gpet_phantom": gpet.Phantom, "gpet_source": gpet.Source, "gpet_hits": gpet.Hits,
                "gpet_stats": gpet.Stats, "gpet_digitizer": gpet.Digitizer, "gpet_singles": gpet.Singles,
+               "gpet_surrogate_spec": gpet.SurrogateSpec,
                "gpet_coincidences": gpet.Coincidences, "gpet_tallies": gpet.Tallies,
                "gpet_instance": gpet.Instance}
     src = tmp_path / "probe.c"

@@ -78,14 +78,15 @@ def test_gradient_matches_fp64_backprop(ctx):
     m.close()
 
 
-def test_factored_gradient_matches_fp64_backprop(ctx):
-    """The factored output (energy head of 20 classes, 338 positions, offset
-    table) on a surrogate-sized trunk: loss within 1e-3 and every gradient
-    tensor, the table's included, within 2e-2 relative L2 of FP64
-    backpropagation at the same BF16 weights and stored activations."""
+@pytest.mark.parametrize("groups", [1, 4])
+def test_factored_gradient_matches_fp64_backprop(ctx, groups):
+    """The factored output (energy head of 20 classes, 1 or 4 blocks of 338
+    positions, offset table) on a surrogate-sized trunk: loss within 1e-3 and
+    every gradient tensor, the table's included, within 2e-2 relative L2 of
+    FP64 backpropagation at the same BF16 weights and stored activations."""
     from paper_2603_07327_amd.gpet import Mlp, pack_params
     n1, n2 = 20, 338
-    sizes = [6, *G.SURROGATE_HIDDEN, n1 + n2]
+    sizes = [6, *G.SURROGATE_HIDDEN, n1 + groups * n2]
     P = G.mlp_init(sizes, seed=13)
     rng = np.random.default_rng(14)
     P = [(W * (3.0 if k == len(sizes) - 2 else 1.0), rng.normal(0, 0.05, len(b)).astype(np.float32))
@@ -96,11 +97,11 @@ def test_factored_gradient_matches_fp64_backprop(ctx):
     e = rng.integers(0, n1, 900)
     e[:100] = 0
     y = S.factored_join(e, rng.integers(0, n2, 900), n1).astype(np.int32)
-    m = Mlp(ctx, sizes, flat, n_first=n1)
+    m = Mlp(ctx, sizes, flat, n_first=n1, n_groups=groups)
     loss, g = m.loss_grad(x, y)
     Pb = _bf16_params(flat[:len(pack_params(P))], sizes)
     ref_loss, ref_g, ref_gT = S.factored_loss_and_grad(Pb, T.astype(np.float64), S.bf16_round(x), y, n1,
-                                                       store=S.bf16_round)
+                                                       store=S.bf16_round, n_groups=groups)
     assert abs(loss - ref_loss) / ref_loss < 1e-3, (loss, ref_loss)
     n_layer = len(pack_params(P))
     G_gpu = S.unpack(g[:n_layer], sizes)

@@ -84,7 +84,7 @@ def _peaked_mlp_params(seed, out=1851):
 N1, N2 = 38, 50
 
 
-@pytest.mark.parametrize("head", ["joint", "factored"])
+@pytest.mark.parametrize("head", ["joint", "factored", "factored_groups", "factored_wide"])
 def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod, head):
     """Hits of a surrogate run: photons outside the domain keep their full
     transport (the oracle's hits for those photons), in-domain photons get the
@@ -98,15 +98,20 @@ def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod, head):
         sizes, P = _peaked_mlp_params(3)
         flat = pack_params(P)
         m = Mlp(ctx, sizes, flat)
-    else:
-        sizes, P = _peaked_mlp_params(3, N1 + N2)
-        T = np.random.default_rng(4).normal(0.0, 2.0, (N1 - 1, N2)).astype(np.float32)
+    # factored_wide: classes over a 9 x 9 neighbourhood around the same
+    # domain (5 x 5): positions past an array's edge exist only in the layout
+    wide = head == "factored_wide"
+    n2 = 2 * 81 if wide else N2
+    if head != "joint":
+        groups = 37 if head == "factored_groups" else 1  # one position block per energy class
+        sizes, P = _peaked_mlp_params(3, N1 + groups * n2)
+        T = np.random.default_rng(4).normal(0.0, 2.0, (N1 - 1, n2)).astype(np.float32)
         flat = np.concatenate([pack_params(P), T.ravel()])
-        m = Mlp(ctx, sizes, flat, n_first=N1)
-    hits, st, sst = ctx.surrogate_transport(m, n, seed=seed)
+        m = Mlp(ctx, sizes, flat, n_first=N1, n_groups=groups)
+    hits, st, sst = ctx.surrogate_transport(m, n, seed=seed, spec={"class_half_width": 4} if wide else None)
     g = hits.numpy()
     o, ref = _oracle_entries(oracle_mod, sc, n, seed)
-    spec, lat = S.Spec(), S.Lattice(sc["scanner"])
+    spec, lat = S.Spec(class_half_width=4 if wide else 0), S.Lattice(sc["scanner"])
     print("entries gpu", sst["entries"], "oracle", len(ref), "none", sst["none"])
     assert abs(sst["entries"] - len(ref)) <= max(3, 0.002 * len(ref))
     # --- synthetic singles
@@ -122,7 +127,12 @@ def test_surrogate_transport_matches_oracle_composition(ctx, oracle_mod, head):
     if head == "joint":
         cls = S.sample_class(logits, _to_unit(w[:, 0]))
     else:
-        cls = S.factored_sample(logits, T.astype(np.float64), N1, _to_unit(w[:, 0]), _to_unit(w[:, 2]))
+        ex = np.stack([S.positions_exist(spec, lat, ref[k]["entry"]) for k in keys])
+        cls = S.factored_sample(logits, T.astype(np.float64), N1, _to_unit(w[:, 0]), _to_unit(w[:, 2]), groups,
+                                exists=ex)
+        if wide:  # some drawn positions lie past an array's edge in the unmasked law
+            free = S.factored_sample(logits, T.astype(np.float64), N1, _to_unit(w[:, 0]), _to_unit(w[:, 2]), groups)
+            print("draws moved by the existence mask", int(np.sum(free != cls)))
     u1 = _to_unit(w[:, 1])
     wt = oracle_mod.philox(seed, np.stack([np.full_like(ev, 2), ev, np.zeros_like(ev), np.zeros_like(ev)], 1))
     X64 = (wt[:, 1].astype(np.uint64) << np.uint64(32)) | wt[:, 0].astype(np.uint64)

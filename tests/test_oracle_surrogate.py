@@ -79,8 +79,8 @@ def test_cross_entropy_closed_forms():
     assert loss < 1e-20
 
 
-def _factored_case(seed=11):
-    sizes = [6, 7, 5, 4 + 9]  # energy head of 4 classes (none + 3), 9 positions
+def _factored_case(seed=11, groups=1):
+    sizes = [6, 7, 5, 4 + 9 * groups]  # energy head of 4 classes (none + 3), blocks of 9 positions
     P = _params(sizes, seed)
     rng = np.random.default_rng(seed + 1)
     T = rng.normal(0, 0.7, (3, 9))
@@ -90,12 +90,14 @@ def _factored_case(seed=11):
     return sizes, P, T, x, y
 
 
-def test_factored_gradient_matches_central_differences():
+@pytest.mark.parametrize("groups", [1, 3])
+def test_factored_gradient_matches_central_differences(groups):
     """The energy-then-position output (Sec. 4's learned stand-in, this
-    build's factored head): gradients of every weight, bias and table
-    entry against central differences of the loss."""
-    sizes, P, T, x, y = _factored_case()
-    _, g, gT = S.factored_loss_and_grad(P, T, x, y, 4)
+    build's factored head; with 3 groups each energy class has a position
+    block of its own): gradients of every weight, bias and table entry
+    against central differences of the loss."""
+    sizes, P, T, x, y = _factored_case(groups=groups)
+    _, g, gT = S.factored_loss_and_grad(P, T, x, y, 4, n_groups=groups)
     h = 1e-6
     worst = 0.0
     arrays = [(W, g[k][0]) for k, (W, _) in enumerate(P)] + [(b, g[k][1]) for k, (_, b) in enumerate(P)] + [(T, gT)]
@@ -105,9 +107,9 @@ def test_factored_gradient_matches_central_differences():
             idx = it.multi_index
             old = arr[idx]
             arr[idx] = old + h
-            lp, _, _ = S.factored_loss_and_grad(P, T, x, y, 4)
+            lp, _, _ = S.factored_loss_and_grad(P, T, x, y, 4, n_groups=groups)
             arr[idx] = old - h
-            lm, _, _ = S.factored_loss_and_grad(P, T, x, y, 4)
+            lm, _, _ = S.factored_loss_and_grad(P, T, x, y, 4, n_groups=groups)
             arr[idx] = old
             fd = (lp - lm) / (2 * h)
             worst = max(worst, abs(fd - garr[idx]) / max(1e-3, abs(fd)))
@@ -137,25 +139,33 @@ def test_factored_closed_forms_and_normalization():
         np.testing.assert_allclose(gT[ei - 1], want, atol=1e-15)
     # joint label layout of outcome_class: 1 + position (n_ebins + 1) + bin, e = bin + 1
     assert S.factored_join(np.array([3]), np.array([5]), 4)[0] == 1 + 5 * 3 + 2
-    sizes, P, T, x, _ = _factored_case(3)
-    z, _, _ = S.forward(P, x)
-    labels = np.arange(1 + 9 * 3)
-    tot = sum(np.exp(S.factored_log_prob(z, T, np.full(len(x), lab), 4)) for lab in labels)
-    np.testing.assert_allclose(tot, 1.0, rtol=1e-13)
+    for groups in (1, 3):
+        sizes, P, T, x, _ = _factored_case(3, groups)
+        z, _, _ = S.forward(P, x)
+        labels = np.arange(1 + 9 * 3)
+        tot = sum(np.exp(S.factored_log_prob(z, T, np.full(len(x), lab), 4, groups)) for lab in labels)
+        np.testing.assert_allclose(tot, 1.0, rtol=1e-13)
+    # with one block per energy class, the position law of class e reads block e - 1 only
+    z = np.zeros((1, 4 + 27))
+    z[0, 4 + 9 + 5] = 30.0  # block 1 (energy class 2) peaks at position 5
+    T0 = np.zeros((3, 9))
+    assert S.factored_sample(z, T0, 4, np.array([0.6]), np.array([0.5]), n_groups=3)[0] == 1 + 5 * 3 + 1
+    assert S.factored_sample(z, T0, 4, np.array([0.3]), np.array([0.5]), n_groups=3)[0] == 1 + 4 * 3 + 0
 
 
-def test_factored_sampling_follows_its_probabilities():
+@pytest.mark.parametrize("groups", [1, 3])
+def test_factored_sampling_follows_its_probabilities(groups):
     """Stratified uniforms (u = (i + 1/2) / N on each axis, all pairs) give
     every joint label with its probability to within 2 / N."""
-    sizes, P, T, x, _ = _factored_case(5)
+    sizes, P, T, x, _ = _factored_case(5, groups)
     z, _, _ = S.forward(P, x[:1])
     N = 400
     u = (np.arange(N) + 0.5) / N
     ue, up = np.meshgrid(u, u, indexing="ij")
     zz = np.repeat(z, N * N, axis=0)
-    lab = S.factored_sample(zz, T, 4, ue.ravel(), up.ravel())
+    lab = S.factored_sample(zz, T, 4, ue.ravel(), up.ravel(), groups)
     freq = np.bincount(lab, minlength=28) / (N * N)
-    prob = np.exp([S.factored_log_prob(z, T, np.array([c]), 4)[0] for c in range(28)])
+    prob = np.exp([S.factored_log_prob(z, T, np.array([c]), 4, groups)[0] for c in range(28)])
     assert np.max(np.abs(freq - prob)) < 2.0 / N
     # hand-computed: energy probabilities from the first head alone
     z1 = np.log(np.array([[0.5, 0.25, 0.125, 0.125]]))
@@ -163,6 +173,34 @@ def test_factored_sampling_follows_its_probabilities():
     assert S.factored_sample(zfull, np.zeros((3, 9)), 4, np.array([0.49]), np.array([0.5]))[0] == 0
     # e = 2 (u in (0.75, 0.875]), uniform positions: u_position = 0.35 -> position 3
     assert S.factored_sample(zfull, np.zeros((3, 9)), 4, np.array([0.8]), np.array([0.35]))[0] == 1 + 3 * 3 + 1
+
+
+def test_wide_class_neighbourhood_hand_worked():
+    """A class neighbourhood of half width 8 around anchors near the arrays'
+    edges of design C (23 x 23 over 24 x 24): the positions that exist
+    (inside each layer's array) counted by hand, the label layout with
+    W = 17, and the sampler never drawing a position that does not exist."""
+    spec = S.Spec(half_width=2, n_ebins=36, class_half_width=8)
+    lat = _lat_c()
+    ent = S.Entry(True, np.zeros(6), 0, [(6, 16), (6, 17)])
+    ex = S.positions_exist(spec, lat, ent)
+    W = 17
+    assert len(ex) == 2 * W * W
+    # layer 0: t offsets 2..16 (it = 0..14), a offsets 0..14 (ia = 8..22); layer 1 likewise up to 23
+    assert ex[:W * W].sum() == 15 * 15 and ex[W * W:].sum() == 15 * 15
+    assert not ex[(0 * W + 1) * W + 0] and ex[(0 * W + 2) * W + 0] and not ex[(0 * W + 2) * W + 15]
+    # label of layer 1, crystal (it, ia) = (3, 20), bin 5: offsets (3 - 6 + 8, 20 - 17 + 8) = (5, 11)
+    gid = lat.gid(0, 0, 1, 3, 20)
+    c, trunc = S.outcome_class(spec, lat, ent, 0, 511.0, {gid: 224.0 + 8 * 5 + 1})
+    assert not trunc and c == 1 + ((1 * W + 5) * W + 11) * 37 + 5
+    assert S.class_hit(spec, lat, ent, 0, 511.0, c, 0.5)[0] == gid
+    # a peaked position head on a position that does not exist: the sampler takes the best that does
+    z = np.zeros((1, 38 + 2 * W * W))
+    z[0, 37] = 50.0  # photopeak
+    z[0, 38 + 0] = 40.0  # position 0 (layer 0, offsets (0, 0)): outside the array
+    z[0, 38 + (0 * W + 2) * W + 3] = 30.0
+    lab = S.factored_sample(z, np.zeros((37, 2 * W * W)), 38, np.array([0.5]), np.array([0.5]), exists=ex[None, :])
+    assert lab[0] == 1 + ((0 * W + 2) * W + 3) * 37 + 36
 
 
 def test_adam_first_step_is_signed_learning_rate():
