@@ -1031,6 +1031,8 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   if (!q || q->ctx != c) return fail(c, GPET_ERR_ARG, "surrogate: network missing or made on another context");
   if (q->n_first) {
     const int W = 2 * P.chalf + 1;
+    if (q->n_second > 2048)
+      return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: at most 2048 positions per block (layers x (2 H + 1)^2)");
     if (q->size[0] != 6 || q->n_first != spec->n_ebins + 2 || q->n_second != c->scene.n_layers * W * W)
       return fail(c, GPET_ERR_ARG, "surrogate: a factored network must map 6 features to " +
                                        std::to_string(spec->n_ebins + 2) + " energy classes and " +
@@ -1045,7 +1047,7 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "surrogate: event range");
   if (!hits_ok(h)) return fail(c, GPET_ERR_ARG, "surrogate: null hit array");
   (void)hipSetDevice(c->device);
-  constexpr uint64_t kSlice = 8u << 20; // events per transport launch (queue of 2 per event)
+  constexpr uint64_t kSlice = 32u << 20; // events per transport launch (queue of 2 per event, 72 B each)
   s = ensure_queue(c, (size_t)2 * std::min<uint64_t>(std::max<uint64_t>(n, 1), kSlice));
   if (s) return s;
   const SurQueue &Q = c->squeue;

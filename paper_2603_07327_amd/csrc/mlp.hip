@@ -540,36 +540,29 @@ __global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int
   part[(size_t)blockIdx.z * (n1 - 1) * n2 + (size_t)(e - 1) * n2 + j] = a;
 }
 
-// Position j of the class neighbourhood (layer, then offsets of half width
-// H around the layer's anchor) lies inside that layer's crystal array
-__device__ __forceinline__ bool position_exists(int j, const uint32_t *anchor, const DevScene *S, int H) {
-  const int W = 2 * H + 1;
-  const int l = j / (W * W), rr = j - l * W * W;
-  const int dt = rr / W, da = rr - dt * W;
-  const uint32_t aw = anchor[l];
-  const int it = (int)(aw & 0xFFFFu) + dt - H, ia = (int)(aw >> 16) + da - H;
-  return it >= 0 && it < S->layer[l].n_t && ia >= 0 && ia < S->layer[l].n_a;
-}
-
 // Factored sampling, one wave per queue entry: the energy class e = first
 // class whose cumulative softmax mass reaches u0 * total (u0: word 0 of
 // Philox (0, event, inst_rng, 4 + photon)); for e > 0 the position k = first
 // position whose cumulative mass under softmax(z2 + T[e - 1]) over the
 // positions that exist (inside their layer's array around the entry's
-// anchors) reaches u2 * total (word 2), walked 64 positions at a time.  cls =
-// the joint label.
+// anchors) reaches u2 * total (word 2).  cls = the joint label.
+//
+// One pass over the position logits (n2 <= 64 B): lane l holds positions
+// [l B, (l + 1) B) in registers (masked where they do not exist), so the
+// wave's prefix sum of the lane sums runs in position order, and the lane
+// whose prefix crosses the target walks its own B values.
+template <int B>
 __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, int G,
                                                          const float *T, uint32_t n, const uint32_t *ev,
                                                          const uint32_t *meta, const uint32_t *anchor,
-                                                         const DevScene *S, int H,
-                                                         uint32_t k0, uint32_t k1, uint32_t inst_rng, uint32_t *cls,
-                                                         uint32_t *nonzero) {
+                                                         const DevScene *S, int H, uint32_t k0, uint32_t k1,
+                                                         uint32_t inst_rng, uint32_t *cls, uint32_t *nonzero) {
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
   const float *zr = z + (size_t)r * ldz;
   const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
-  // energy class
+  // energy class: one class per lane
   const float v1 = lane < n1 ? zr[lane] : -INFINITY;
   float m1 = v1;
 #pragma unroll
@@ -591,46 +584,87 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
     }
     return;
   }
-  // position given e, over the positions that exist
+  // layer sizes and this entry's anchors (at most kMaxLayers), selected by value
+  const int nl = S->n_layers;
+  int nt[kMaxLayers], na[kMaxLayers], at[kMaxLayers], aa[kMaxLayers];
+#pragma unroll
+  for (int q = 0; q < kMaxLayers; ++q) {
+    const bool on = q < nl;
+    nt[q] = on ? S->layer[q].n_t : 0;
+    na[q] = on ? S->layer[q].n_a : 0;
+    const uint32_t aw = on ? anchor[(size_t)kMaxLayers * r + q] : 0u;
+    at[q] = (int)(aw & 0xFFFFu) - H;
+    aa[q] = (int)(aw >> 16) - H;
+  }
   const float *z2 = zr + position_block(e, n1, n2, G);
   const float *t = T + (size_t)(e - 1) * n2;
-  const uint32_t *an = anchor + (size_t)kMaxLayers * r;
-  float m2 = -INFINITY;
-  int last = -1;
-  for (int c = lane; c < n2; c += 64)
-    if (position_exists(c, an, S, H)) {
-      m2 = fmaxf(m2, z2[c] + t[c]);
-      last = c;
-    }
+  const int W = 2 * H + 1, WW = W * W;
+  const int j0 = lane * B;
+  int l = j0 / WW, rr = j0 - l * WW;
+  int dt = rr / W, da = rr - dt * W;
+  float v[B];
+  float m = -INFINITY;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    m2 = fmaxf(m2, __shfl_xor(m2, o));
-    last = max(last, __shfl_xor(last, o));
+  for (int i = 0; i < B; ++i) {
+    const int j = j0 + i;
+    int ntl = nt[0], nal = na[0], atl = at[0], aal = aa[0];
+#pragma unroll
+    for (int q = 1; q < kMaxLayers; ++q)
+      if (l == q) {
+        ntl = nt[q];
+        nal = na[q];
+        atl = at[q];
+        aal = aa[q];
+      }
+    const int it = atl + dt, ia = aal + da;
+    const bool ok = j < n2 && it >= 0 && it < ntl && ia >= 0 && ia < nal;
+    v[i] = ok ? z2[j] + t[j] : -INFINITY;
+    m = fmaxf(m, v[i]);
+    if (++da == W) {
+      da = 0;
+      if (++dt == W) {
+        dt = 0;
+        ++l;
+      }
+    }
   }
-  float s2 = 0.f;
-  for (int c = lane; c < n2; c += 64)
-    if (position_exists(c, an, S, H)) s2 += __expf(z2[c] + t[c] - m2);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-  const float target2 = to_unit(w.z) * s2;
-  int k = last; // rounding left the target beyond the last position
-  float acc = 0.f;
-  for (int c0 = 0; c0 < n2; c0 += 64) {
-    const int c = c0 + lane;
-    const float p = (c < n2 && position_exists(c, an, S, H)) ? __expf(z2[c] + t[c] - m2) : 0.f;
-    float in2 = p;
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  float sl = 0.f;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const float tt = __shfl_up(in2, o);
-      if (lane >= o) in2 += tt;
-    }
-    const uint64_t cr = __ballot(acc + in2 >= target2 && p > 0.f);
-    if (cr) {
-      k = c0 + __ffsll((unsigned long long)cr) - 1;
-      break;
-    }
-    acc += __shfl(in2, 63);
+  for (int i = 0; i < B; ++i) {
+    v[i] = v[i] > -INFINITY ? __expf(v[i] - m) : 0.f;
+    sl += v[i];
   }
+  float in2 = sl;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float tt = __shfl_up(in2, o);
+    if (lane >= o) in2 += tt;
+  }
+  const float target2 = to_unit(w.z) * __shfl(in2, 63);
+  const uint64_t cr = __ballot(in2 >= target2 && sl > 0.f);
+  const uint64_t has = __ballot(sl > 0.f);
+  // rounding left the target beyond the total: the last lane holding mass
+  const int L = cr ? __ffsll((unsigned long long)cr) - 1 : 63 - __clzll((long long)has);
+  int k = -1;
+  if (lane == L) { // the first position whose cumulative mass reaches the target (else, by rounding, the last)
+    float a = in2 - sl;
+    int last = -1;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      a += v[i];
+      if (v[i] > 0.f) {
+        last = j0 + i;
+        if (a >= target2) {
+          k = j0 + i;
+          break;
+        }
+      }
+    }
+    if (k < 0) k = last;
+  }
+  k = __shfl(k, L);
   if (lane == 0) {
     cls[r] = 1u + (uint32_t)k * (uint32_t)(n1 - 1) + (uint32_t)(e - 1);
     nonzero[r] = 1u;
@@ -1041,10 +1075,22 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
                        q->act[0], (int32_t *)nullptr);
     if (q->n_first) {
       forward(q, n_pad, st);
-      hipLaunchKernelGGL(k_sample_factored, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first,
-                         q->n_second, q->n_groups, (const float *)(q->master + q->tab_off), n, Q.ev + off,
-                         Q.meta + off, Q.anchor + (size_t)kMaxLayers * off, d_scene, P.chalf, k0, k1,
-                         inst_rng, Q.cls + off, Q.pos + off);
+      const float *T = q->master + q->tab_off;
+      const uint32_t *an = Q.anchor + (size_t)kMaxLayers * off;
+      const int n2 = q->n_second;
+      // the positions in registers: 64 lanes x B, B the smallest of 8, 20, 32 that holds them
+      if (n2 <= 64 * 8)
+        hipLaunchKernelGGL(k_sample_factored<8>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
+                           q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
+                           Q.cls + off, Q.pos + off);
+      else if (n2 <= 64 * 20)
+        hipLaunchKernelGGL(k_sample_factored<20>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
+                           q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
+                           Q.cls + off, Q.pos + off);
+      else // at most 64 x 32 positions (checked by the caller)
+        hipLaunchKernelGGL(k_sample_factored<32>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
+                           q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
+                           Q.cls + off, Q.pos + off);
     } else if (tiles) {
       forward_sample(q, n_pad, st);
       hipLaunchKernelGGL(k_sample_tiles, dim3(cdiv(n, 4)), dim3(256), 0, st, (const float2 *)q->tstats, Cp / 128,
