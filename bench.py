@@ -64,6 +64,22 @@ def algorithmic_work(stats: dict, ring: bool = True, source: str = "point") -> f
             + stats["scatters"] * UNIT_COST["rotation"] + w_search + stats["events"] * UNIT_COST["source"])
 
 
+# The same work in the survey's form, W = N_blk c_philox + N_step c_step +
+# N_trial c_kahn + N_int c_rot + N_search n_panels c_slab + N_events c_src,
+# with the survey's order-of-magnitude unit costs (c_src is not estimated
+# there: the measured 18 is used) and the oracle's own counts; the full panel
+# search is charged (every panel's slab test), not the pruned one the kernel
+# runs.
+SURVEY_UNIT_COST = {"philox": 140, "step": 65, "kahn": 25, "rotation": 35, "slab": 25, "source": 18}
+
+
+def survey_form_work(counts: dict, n_panels: int, source: str = "point", cost=None) -> float:
+    c = cost or SURVEY_UNIT_COST
+    return ((counts["blocks"] + EVENT_BLOCKS[source] * counts["events"]) * c["philox"]
+            + counts["steps"] * c["step"] + counts["kahn_trials"] * c["kahn"] + counts["scatters"] * c["rotation"]
+            + counts["searches"] * n_panels * c["slab"] + counts["events"] * c["source"])
+
+
 # Bytes each digitizer stage moves per item, as built: hit keys 24, hit sort
 # 60 (count, scatter, wave sort), run heads and their scan 24, adder 32 per
 # hit (key, index, segment, energy / depth / time) and 28 per single written;
@@ -104,37 +120,80 @@ def measured_traffic(events_per_launch: int):
     return d["bytes_per_event"] * events_per_launch
 
 
+def survey_form_roofline(probe: dict, oracle_counts: dict, n: int) -> dict:
+    """The transport fraction of the VALU peak three ways, for one launch of
+    design C with the source at the centre (1e7 events): the headline work
+    model (the kernel's own counts, pruned ring search), the survey's formula
+    with its estimated unit costs and the oracle's counts (every panel's slab
+    test charged per search), and the survey's formula with the measured unit
+    costs and the oracle's counts."""
+    sec = probe["kernel_ms"] * 1e-3
+    oc = {k: v * n for k, v in oracle_counts.items()}
+    w_head = algorithmic_work(probe["stats"], ring=True, source="point")
+    w_survey = survey_form_work(oc, 12, "point")
+    measured = dict(SURVEY_UNIT_COST, philox=UNIT_COST["philox"], step=UNIT_COST["step"], kahn=UNIT_COST["kahn"],
+                    rotation=UNIT_COST["rotation"], slab=UNIT_COST["slab"], source=UNIT_COST["source"])
+    w_survey_measured = survey_form_work(oc, 12, "point", measured)
+    return {"workload": "design C, source at the centre, 1e7 events (one transport launch)", "kernel_ms": probe["kernel_ms"],
+            "peak": VALU_PEAK / 1e12, "unit": "TVALU-op/s",
+            "headline_model": {"work_per_launch": w_head, "frac": w_head / sec / VALU_PEAK,
+                               "counts": "kernel counters", "search": "pruned ring tests"},
+            "survey_form_survey_costs": {"work_per_launch": w_survey, "frac": w_survey / sec / VALU_PEAK,
+                                         "unit_costs": SURVEY_UNIT_COST, "counts": "oracle (per event x 1e7)",
+                                         "search": "12 slab tests per search"},
+            "survey_form_measured_costs": {"work_per_launch": w_survey_measured,
+                                           "frac": w_survey_measured / sec / VALU_PEAK, "unit_costs": measured,
+                                           "counts": "oracle (per event x 1e7)", "search": "12 slab tests per search"},
+            "oracle_counts_per_event": oracle_counts,
+            "kernel_counts_per_event": {k: v / n for k, v in probe["stats"].items()}}
+
+
 def cpu_baseline(target_s: float = 12.0):
-    """Oracle events/s (transport + digitizer) on a bounded sample of design C."""
+    """Oracle events/s (transport + digitizer) on a bounded sample of design C:
+    calls of up to 2e7 events (the oracle keeps every hit of a call in host
+    memory) until at least target_s seconds have run; then one host thread
+    on a smaller sample for at least 2 s.  Also returns the oracle's work
+    counters per event."""
     from oracle import oracle as O
     O.build(force=False)
     threads = O.num_threads()
-    sc = G.small_animal_scene("C", (0.0, 0.0, 0.0), n_events=10_000_000)
+    sc = G.small_animal_scene("C", (0.0, 0.0, 0.0), n_events=200_000_000)
     s = O.OracleScene(sc)
     n0 = 100_000
     t0 = time.perf_counter()
     h, _ = s.transport(n0, seed=1)
     s.digitize(h, seed=1)
     dt0 = time.perf_counter() - t0
-    n = int(min(20_000_000, max(n0, n0 * target_s / max(dt0, 1e-3))))
-    t0 = time.perf_counter()
-    h, _ = s.transport(n, seed=1)
-    s.digitize(h, seed=1)
-    dt = time.perf_counter() - t0
-    # one host thread on a proportionally smaller sample (events are independent)
-    n1 = max(10_000, int(n * 0.3 / max(threads, 1)))
+    per_call = int(min(20_000_000, max(n0, n0 * target_s / 3 / max(dt0, 1e-3))))
+    done, dt, counts = 0, 0.0, {}
+    while dt < target_s:
+        t0 = time.perf_counter()
+        h, c = s.transport(per_call, seed=1, first=done)
+        s.digitize(h, seed=1)
+        dt += time.perf_counter() - t0
+        done += per_call
+        for k, v in c.items():
+            counts[k] = counts.get(k, 0) + v
+        del h
+    # one host thread (events are independent): a trial sizes a sample of
+    # about 2.5 s
     O.set_threads(1)
     try:
+        t0 = time.perf_counter()
+        h, _ = s.transport(50_000, seed=1)
+        s.digitize(h, seed=1)
+        n1 = max(50_000, int(50_000 * 2.5 / max(time.perf_counter() - t0, 1e-3)))
         t0 = time.perf_counter()
         h, _ = s.transport(n1, seed=1)
         s.digitize(h, seed=1)
         dt1 = time.perf_counter() - t0
     finally:
         O.set_threads(threads)
-    return {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"design C, source at the centre, events [0, {n}) seed 1, transport + digitizer, "
-                      f"{dt:.1f} s",
-            "single_core": {"value": n1 / dt1, "events": n1, "seconds": dt1}}
+    return {"value": done / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"design C, source at the centre, events [0, {done}) seed 1 in calls of {per_call}, "
+                      f"transport + digitizer, {dt:.1f} s",
+            "single_core": {"value": n1 / dt1, "events": n1, "seconds": dt1},
+            "counts_per_event": {k: v / done for k, v in counts.items()}}
 
 
 SWEEP_WINDOWS = [(150.0, 700.0), (250.0, 700.0), (350.0, 700.0), (450.0, 700.0)]
@@ -362,6 +421,28 @@ def batched_form(args):
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t0) / args.steps
     last_seed = 1 + args.steps
+    # the same step with the transport replayed from its captured HIP graph
+    # (counter reset + persistent launch, seed fixed at capture), then the
+    # digitizer pass (not capturable: it sizes its sort from counts it reads back)
+    b.graph_capture(hits, seed=last_seed)
+
+    def graph_step():
+        b.graph_launch()
+        rc, st = b.read_counts(hits)
+        if rc != 0:
+            raise RuntimeError("batched hit capacity too small")
+        rc, nc, per = b.digitize_into(hits, singles, coinc, seed=last_seed)
+        if rc != 0:
+            raise RuntimeError("batched digitizer capacity too small")
+        return per, st
+
+    per_g, _ = graph_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        per_g, st_g = graph_step()
+    torch.cuda.synchronize()
+    dt_g = (time.perf_counter() - t0) / args.steps
     b.close()
     del hits, singles, coinc
     ctx.close()
@@ -407,12 +488,21 @@ def batched_form(args):
         c.close()
     sens_b = np.array([per_b[i] for i in range(len(inst))], np.float64)
     sens_p = np.array([per_p[d["instance"]] for d in inst], np.float64)
+    sens_g = np.array([per_g[i] for i in range(len(inst))], np.float64)
     rel = np.abs(sens_b - sens_p) / np.maximum(sens_p, 1.0)
+    w_b = algorithmic_work(st_b, ring=True, source="point")
+    k_ms = float(np.mean(kms))
     return {"workload": "batched design sweep: 36 designs (layer thickness 6/8/10/12 mm x offset 0/0.25/0.5 "
                         "pitch x gap 0/0.2/0.5 mm) x 4 radial source offsets = 144 instances, event counts "
                         "log-uniform in [1e5, 1e7], one persistent transport launch + one digitizer pass",
             "instances": len(inst), "events": total, "value": total / dt_b, "unit": "events/s",
-            "ms_per_step": dt_b * 1e3, "transport_kernel_ms": float(np.mean(kms)),
+            "ms_per_step": dt_b * 1e3, "transport_kernel_ms": k_ms,
+            "roofline": {"bound": "alu", "kernel": "k_transport (batched)", "achieved": w_b / (k_ms * 1e-3) / 1e12,
+                         "peak": VALU_PEAK / 1e12, "unit": "TVALU-op/s", "frac": w_b / (k_ms * 1e-3) / VALU_PEAK,
+                         "work_per_launch": w_b},
+            "graph_replay": {"value": total / dt_g, "ms_per_step": dt_g * 1e3,
+                             "same_coincidences_as_plain": bool(np.array_equal(sens_g, sens_p)),
+                             "note": "transport from the captured HIP graph (seed fixed at capture), digitizer eager"},
             "plain_one_by_one": {"value": total / dt_p, "ms": dt_p * 1e3},
             "speedup_vs_plain": dt_p / dt_b, "sensitivity_max_rel_diff": float(rel.max()),
             "coincidences": int(sens_b.sum()),
@@ -535,6 +625,13 @@ def surrogate_form(args):
         hist[mode] = in_window_per_crystal()
         out[mode] = {"value": n / dt, "ms": dt * 1e3, "coincidences": nc, "sensitivity": nc / n,
                      "transport_kernel_ms": ctx.timings()[0]}
+        if mode == "plain":
+            w3 = algorithmic_work(st, ring=True, source="rods")
+            k3 = ctx.timings()[0] * 1e-3
+            out[mode]["roofline"] = {"bound": "alu", "kernel": "k_transport (hot-rod phantom)",
+                                     "achieved": w3 / k3 / 1e12, "peak": VALU_PEAK / 1e12, "unit": "TVALU-op/s",
+                                     "frac": w3 / k3 / VALU_PEAK, "work_per_launch": w3,
+                                     "note": "phantom Woodcock steps priced at c_step"}
         if sst is not None:
             out[mode].update({"entries": sst["entries"], "photons_on_network": sst["entries"] / (2.0 * n),
                               "none_fraction": sst["none"] / max(1, sst["entries"]),
@@ -706,6 +803,13 @@ def main():
     }
     line["window_sweep"] = window_sweep(ctxs, n, 1000 + args.warmup + args.steps - 1,
                                         G.SWEEP_POSITIONS[(args.warmup + args.steps - 1) % len(G.SWEEP_POSITIONS)])
+    # design C with the source at the centre: one more timed launch whose work
+    # is also priced in the survey's form with the oracle's counts (below)
+    _, cC, hitsC, _, _ = ctxs[2]
+    cC.set_source(G.point_source((0.0, 0.0, 0.0), n))
+    cC.transport_into(hitsC, n, seed=1)
+    rcC, stC = cC.transport_into(hitsC, n, seed=1)
+    survey_probe = {"kernel_ms": cC.timings()[0], "stats": stC}
     for _, c, *_ in ctxs:
         c.close()
     del ctxs
@@ -721,6 +825,14 @@ def main():
         line["surrogate"] = surrogate_form(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
+        oracle_counts = line["cpu_baseline"]["counts_per_event"]
+    else:  # a small oracle sample of the same launch
+        from oracle import oracle as O
+        O.build(force=False)
+        so = O.OracleScene(G.small_animal_scene("C", (0.0, 0.0, 0.0), n_events=200_000_000))
+        _, oc = so.transport(200_000, seed=1)
+        oracle_counts = {k: v / 200_000 for k, v in oc.items()}
+    line["roofline_survey_form"] = survey_form_roofline(survey_probe, oracle_counts, n)
     print(json.dumps(line), flush=True)
 
 

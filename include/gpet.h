@@ -231,6 +231,8 @@ typedef struct {
   uint64_t panel_tests;     /* panel boxes tested by the searches */
   uint64_t pruned_searches; /* searches from inside a repeated ring that tested only the panels
                                whose azimuth range the ray sweeps */
+  uint64_t nonfinite;       /* photons ended because their position, direction or energy stopped
+                               being finite (checked after each scatter and panel entry; 0 expected) */
 } gpet_stats;
 
 /* Transport events [first_event, first_event + n_events) with key `seed`.
@@ -453,6 +455,15 @@ void gpet_mlp_destroy(gpet_mlp *mlp);
 /* Replaces the master weights (host, packed) and clears the Adam state. */
 gpet_status gpet_mlp_set_weights(gpet_mlp *mlp, const float *weights);
 gpet_status gpet_mlp_get_weights(gpet_mlp *mlp, float *weights);
+/* Training checkpoint: the packed master weights, Adam's first and second
+ * moments (host, n_params floats each, the weights' packing) and the number
+ * of Adam steps taken, which is also the training's data cursor (the batch of
+ * step t is drawn from (seed, t)).  gpet_mlp_set_state restores all four, so
+ * training resumed from a checkpoint continues exactly as an uninterrupted
+ * run; GPET_ERR_ARG for non-finite values or a negative second moment. */
+gpet_status gpet_mlp_get_state(gpet_mlp *mlp, float *weights, float *m, float *v, uint64_t *step);
+gpet_status gpet_mlp_set_state(gpet_mlp *mlp, const float *weights, const float *m, const float *v,
+                               uint64_t step);
 /* Logits (device, n x classes, FP32) of device inputs x (n x sizes[0], FP32;
  * rounded to BF16 on entry). */
 gpet_status gpet_mlp_forward(gpet_mlp *mlp, uint32_t n, const float *x, float *logits);

@@ -504,7 +504,7 @@ typedef struct {
   int64_t n, cap;
   or_vertex *v; /* trace mode */
   int64_t nv, vcap;
-  int64_t cnt[8]; /* events, panel entries, steps, real, trials, searches, blocks, capped */
+  int64_t cnt[9]; /* events, panel entries, steps, real, trials, searches, blocks, capped, scatters */
   int analog;     /* analog tracking instead of Woodcock (a check of the latter) */
 } sink_t;
 
@@ -711,6 +711,7 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
       double edep;
       int tr;
       int alive = interact(s, &r, proc, &e, d, 2.0 * PI * u[3], &edep, &tr);
+      k->cnt[8] += proc != 1; /* Compton or Rayleigh: a direction change */
       k->cnt[4] += tr;
       k->cnt[6] += tr + (proc == 3);
       vtx(k, ev, ph, OR_V_STEP, 0, -1, -1, m, 1, proc, tr, (int)r.n, x, e, edep, d);
@@ -749,6 +750,7 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
       double edep;
       int tr;
       int alive = interact(s, &r, proc, &e, d, 2.0 * PI * u[3], &edep, &tr);
+      k->cnt[8] += proc != 1; /* Compton or Rayleigh: a direction change */
       k->cnt[4] += tr;
       k->cnt[6] += tr + (proc == 3);
       vtx(k, ev, ph, OR_V_STEP, 0, -1, -1, m, 1, proc, tr, (int)r.n, x, e, edep, d);
@@ -820,6 +822,7 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
       double edep;
       int tr;
       int alive = interact(s, &r, proc, &e, dl, 2.0 * PI * u[3], &edep, &tr);
+      k->cnt[8] += proc != 1; /* Compton or Rayleigh: a direction change */
       k->cnt[4] += tr;
       k->cnt[6] += tr + (proc == 3);
       vtx(k, ev, ph, OR_V_STEP, 1, p, lc.gid, lc.mat, 1, proc, tr, (int)r.n, xl, e, edep, dl);
@@ -870,6 +873,7 @@ static void photon(const or_scene *s, sink_t *k, uint64_t seed, uint32_t ev, uin
       double edep;
       int tr;
       int alive = interact(s, &r, proc, &e, dl, 2.0 * PI * u[3], &edep, &tr);
+      k->cnt[8] += proc != 1; /* Compton or Rayleigh: a direction change */
       k->cnt[4] += tr;
       k->cnt[6] += tr + (proc == 3);
       vtx(k, ev, ph, OR_V_STEP, 1, p, lc.gid, lc.mat, 1, proc, tr, (int)r.n, xl, e, edep, dl);
@@ -991,7 +995,7 @@ static int64_t transport_mode(const or_scene *s, uint64_t first, uint64_t n, uin
     }
     tot += sk[t].n;
     if (counters)
-      for (int c = 0; c < 8; c++) counters[c] += sk[t].cnt[c];
+      for (int c = 0; c < 9; c++) counters[c] += sk[t].cnt[c];
     free(sk[t].hits);
   }
   free(sk);

@@ -160,6 +160,9 @@ void or_sample_rayleigh(int64_t n, uint64_t seed, double *cos_t);
 void or_locate(const or_scene *s, int64_t n, const double *xyz, int32_t *ids6, double *bdist);
 void or_ray_locate(const or_scene *s, int64_t n_rays, const double *o, const double *d,
                    int32_t n_samp, double step, double *t_in, int32_t *ids6, double *bdist);
+/* counters (9, added to): events, panel entries, Woodcock steps, real
+ * interactions, Kahn trials, panel searches, photon-stream Philox blocks,
+ * capped photons, scatters (Compton or Rayleigh) */
 int64_t or_transport(const or_scene *s, uint64_t first, uint64_t n, uint64_t seed,
                      uint32_t instance, or_hit *hits, int64_t cap, int64_t *counters);
 /* the same with analog tracking (flights from material boundary to boundary)

@@ -307,7 +307,7 @@ class OracleScene:
     def transport(self, n_events, seed=0, first=0, instance=0, analog=False):
         """Returns (hits structured array, counters dict); analog=True tracks
         from material boundary to boundary instead of Woodcock tracking."""
-        cnt = np.zeros(8, np.int64)
+        cnt = np.zeros(9, np.int64)
         cap = max(16, int(3 * n_events))
         fn = lib().or_transport_analog if analog else lib().or_transport
         while True:
@@ -319,7 +319,7 @@ class OracleScene:
             cnt[:] = 0
         arr = np.frombuffer(buf, dtype=np.dtype(Hit), count=n).copy()
         names = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks",
-                 "capped")
+                 "capped", "scatters")
         return arr, dict(zip(names, cnt.tolist()))
 
     def trace(self, n_events, seed=0, first=0, instance=0, cap=None, analog=False):

@@ -21,7 +21,7 @@ struct SurSpecD {
 
 // Device control words of a context (u64): [0] spare, [1] hit count, [2, 2 + kStatCount) work counters in gpet_stats order,
 // [kCtrlPairs] spare (pairs and surrogate entries are counted at kCtrlPairWord).
-constexpr int kStatCount = 12;
+constexpr int kStatCount = 13;
 constexpr int kCtrlPairs = 2 + kStatCount;
 constexpr int kCtrlWords = kCtrlPairs + 1;
 // the event-claim counter of the transport sits on a cache line of its own,

@@ -547,10 +547,10 @@ __global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int
 // positions that exist (inside their layer's array around the entry's
 // anchors) reaches u2 * total (word 2).  cls = the joint label.
 //
-// One pass over the position logits (n2 <= 64 B): lane l holds positions
-// [l B, (l + 1) B) in registers (masked where they do not exist), so the
-// wave's prefix sum of the lane sums runs in position order, and the lane
-// whose prefix crosses the target walks its own B values.
+// One pass over the position logits (n2 <= 64 B): chunk k of 64 positions is
+// loaded coalesced, position k 64 + lane into lane's register v[k] (masked
+// where the position does not exist); the draw walks the chunks in order with
+// one wave prefix sum each, so it equals the natural-order inverse CDF.
 template <int B>
 __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, int G,
                                                          const float *T, uint32_t n, const uint32_t *ev,
@@ -599,14 +599,14 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
   const float *z2 = zr + position_block(e, n1, n2, G);
   const float *t = T + (size_t)(e - 1) * n2;
   const int W = 2 * H + 1, WW = W * W;
-  const int j0 = lane * B;
-  int l = j0 / WW, rr = j0 - l * WW;
+  // (layer, t offset, a offset) of position lane, then stepped by 64
+  int l = lane / WW, rr = lane - l * WW;
   int dt = rr / W, da = rr - dt * W;
   float v[B];
   float m = -INFINITY;
 #pragma unroll
-  for (int i = 0; i < B; ++i) {
-    const int j = j0 + i;
+  for (int c = 0; c < B; ++c) {
+    const int j = c * 64 + lane;
     int ntl = nt[0], nal = na[0], atl = at[0], aal = aa[0];
 #pragma unroll
     for (int q = 1; q < kMaxLayers; ++q)
@@ -618,10 +618,11 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
       }
     const int it = atl + dt, ia = aal + da;
     const bool ok = j < n2 && it >= 0 && it < ntl && ia >= 0 && ia < nal;
-    v[i] = ok ? z2[j] + t[j] : -INFINITY;
-    m = fmaxf(m, v[i]);
-    if (++da == W) {
-      da = 0;
+    v[c] = ok ? z2[j] + t[j] : -INFINITY;
+    m = fmaxf(m, v[c]);
+    da += 64; // next chunk: position + 64
+    while (da >= W) {
+      da -= W;
       if (++dt == W) {
         dt = 0;
         ++l;
@@ -631,40 +632,36 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   float sl = 0.f;
+  int last = -1; // the last position that exists
 #pragma unroll
-  for (int i = 0; i < B; ++i) {
-    v[i] = v[i] > -INFINITY ? __expf(v[i] - m) : 0.f;
-    sl += v[i];
+  for (int c = 0; c < B; ++c) {
+    if (v[c] > -INFINITY) last = c * 64 + lane;
+    v[c] = v[c] > -INFINITY ? __expf(v[c] - m) : 0.f;
+    sl += v[c];
   }
-  float in2 = sl;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const float tt = __shfl_up(in2, o);
-    if (lane >= o) in2 += tt;
+  for (int o = 32; o > 0; o >>= 1) {
+    sl += __shfl_xor(sl, o);
+    last = max(last, __shfl_xor(last, o));
   }
-  const float target2 = to_unit(w.z) * __shfl(in2, 63);
-  const uint64_t cr = __ballot(in2 >= target2 && sl > 0.f);
-  const uint64_t has = __ballot(sl > 0.f);
-  // rounding left the target beyond the total: the last lane holding mass
-  const int L = cr ? __ffsll((unsigned long long)cr) - 1 : 63 - __clzll((long long)has);
-  int k = -1;
-  if (lane == L) { // the first position whose cumulative mass reaches the target (else, by rounding, the last)
-    float a = in2 - sl;
-    int last = -1;
+  const float target2 = to_unit(w.z) * sl;
+  int k = last; // rounding left the target beyond the total
+  float carry = 0.f;
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-      a += v[i];
-      if (v[i] > 0.f) {
-        last = j0 + i;
-        if (a >= target2) {
-          k = j0 + i;
-          break;
-        }
-      }
+  for (int c = 0; c < B; ++c) {
+    float in2 = v[c];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const float tt = __shfl_up(in2, o);
+      if (lane >= o) in2 += tt;
     }
-    if (k < 0) k = last;
+    const uint64_t cr = __ballot(carry + in2 >= target2 && v[c] > 0.f);
+    if (cr) {
+      k = c * 64 + __ffsll((unsigned long long)cr) - 1;
+      break;
+    }
+    carry += __shfl(in2, 63);
   }
-  k = __shfl(k, L);
   if (lane == 0) {
     cls[r] = 1u + (uint32_t)k * (uint32_t)(n1 - 1) + (uint32_t)(e - 1);
     nonzero[r] = 1u;
@@ -1078,7 +1075,7 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
       const float *T = q->master + q->tab_off;
       const uint32_t *an = Q.anchor + (size_t)kMaxLayers * off;
       const int n2 = q->n_second;
-      // the positions in registers: 64 lanes x B, B the smallest of 8, 20, 32 that holds them
+      // the positions in registers: B chunks of 64, B the smallest of 8, 20, 32 that holds them
       if (n2 <= 64 * 8)
         hipLaunchKernelGGL(k_sample_factored<8>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
                            q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
@@ -1247,6 +1244,34 @@ gpet_status gpet_mlp_get_weights(gpet_mlp *q, float *w) {
   if (hipStreamSynchronize(q->ctx->stream) != hipSuccess ||
       hipMemcpy(w, q->master, q->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess)
     return mlp_fail(q, GPET_ERR_HIP, "mlp: download failed");
+  return GPET_OK;
+}
+
+gpet_status gpet_mlp_get_state(gpet_mlp *q, float *w, float *m, float *v, uint64_t *step) {
+  if (!q || !w || !m || !v || !step) return GPET_ERR_ARG;
+  (void)hipSetDevice(q->device);
+  if (hipStreamSynchronize(q->ctx->stream) != hipSuccess ||
+      hipMemcpy(w, q->master, q->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(m, q->m, q->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(v, q->v, q->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp: state download failed");
+  *step = q->adam_t;
+  return GPET_OK;
+}
+
+gpet_status gpet_mlp_set_state(gpet_mlp *q, const float *w, const float *m, const float *v, uint64_t step) {
+  if (!q || !w || !m || !v) return GPET_ERR_ARG;
+  for (size_t i = 0; i < q->n_params; ++i)
+    if (!std::isfinite(m[i]) || !std::isfinite(v[i]) || v[i] < 0.0f)
+      return mlp_fail(q, GPET_ERR_ARG, "mlp: Adam moments must be finite (second moments >= 0)");
+  // the weights (and the BF16 copies and biases the kernels read), then the moments and the step
+  gpet_status s = gpet_mlp_set_weights(q, w);
+  if (s) return s;
+  (void)hipSetDevice(q->device);
+  if (hipMemcpy(q->m, m, q->n_params * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(q->v, v, q->n_params * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return mlp_fail(q, GPET_ERR_HIP, "mlp: state upload failed");
+  q->adam_t = step;
   return GPET_OK;
 }
 

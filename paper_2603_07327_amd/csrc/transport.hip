@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   bool have_pend = false, exhausted = false;
   // work counters: per-lane counts (summed over the wave at the end), trips per wave
   uint32_t c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0, c_blocks = 0,
-           c_capped = 0, c_scatter = 0, c_tests = 0, c_pruned = 0;
+           c_capped = 0, c_scatter = 0, c_tests = 0, c_pruned = 0, c_nonfinite = 0;
   unsigned long long c_trips = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
@@ -475,6 +475,15 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
       phase = q_back;
     }
 
+    // ---- guard: a photon whose state stopped being finite ends here
+    bool bad = false;
+    if ((scattered || entered) && nonfinite_state(x, d, e)) {
+      bad = ended = true;
+      hit = false;
+      push = false;
+    }
+    c_nonfinite += bad ? 1u : 0u;
+
     // ---- work counters (scalar)
     c_events += emitted ? 1u : 0u;
     c_steps += stepped ? 1u : 0u;
@@ -598,7 +607,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   flush_stage(A, st, staged, lane, inst);
 
   uint32_t lc[kStatCount] = {c_events, c_entries, c_steps,   c_real, c_trials, c_search,
-                             c_blocks, c_capped,  c_scatter, 0u,     c_tests,  c_pruned};
+                             c_blocks, c_capped,  c_scatter, 0u,     c_tests,  c_pruned, c_nonfinite};
   unsigned long long cnt[kStatCount];
 #pragma unroll
   for (int k = 0; k < kStatCount; ++k) {

@@ -91,4 +91,11 @@ __device__ __forceinline__ void flush_stage(const RunArgs &A, const Stage &st, u
 }
 
 
+// The photon's state is no longer finite (a NaN or an infinity out of the
+// arithmetic): checked after each direction change and panel entry, where such
+// values would first appear; the photon is then ended and counted.
+__device__ __forceinline__ bool nonfinite_state(const Vec &x, const Vec &d, float e) {
+  return !isfinite(x.x + x.y + x.z + d.x + d.y + d.z + e);
+}
+
 } // namespace gpet

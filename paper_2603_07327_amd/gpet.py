@@ -27,7 +27,7 @@ SRC_POINT, SRC_CYLINDERS, SRC_BEAM = 0, 1, 2
 V_STEP, V_ENTER_PANEL, V_EXIT, V_ESCAPE, V_DEAD, V_ENTER_PHANTOM, V_EMIT = range(7)
 
 STAT_NAMES = ("events", "panel_entries", "steps", "real", "kahn_trials", "searches", "blocks", "capped",
-              "scatters", "wave_trips", "panel_tests", "pruned_searches")
+              "scatters", "wave_trips", "panel_tests", "pruned_searches", "nonfinite")
 
 
 class GpetError(RuntimeError):
@@ -184,7 +184,8 @@ EXPORTS = ("gpet_ctx_create", "gpet_ctx_destroy", "gpet_last_error", "gpet_ctx_s
            "gpet_mlp_create", "gpet_mlp_destroy", "gpet_mlp_set_weights", "gpet_mlp_get_weights",
            "gpet_mlp_forward", "gpet_mlp_loss_grad", "gpet_mlp_train", "gpet_surrogate_pairs",
            "gpet_surrogate_transport", "gpet_batch_graph_capture", "gpet_batch_graph_launch",
-           "gpet_batch_read_counts", "gpet_digitize_noalloc", "gpet_mlp_create_factored")
+           "gpet_batch_read_counts", "gpet_digitize_noalloc", "gpet_mlp_create_factored", "gpet_mlp_get_state",
+           "gpet_mlp_set_state")
 
 _lib = None
 
@@ -235,6 +236,8 @@ def load_library(path: str = LIB_PATH):
     L.gpet_mlp_destroy.restype = None
     L.gpet_mlp_set_weights.argtypes = [vp, vp]
     L.gpet_mlp_get_weights.argtypes = [vp, vp]
+    L.gpet_mlp_get_state.argtypes = [vp, vp, vp, vp, P(C.c_uint64)]
+    L.gpet_mlp_set_state.argtypes = [vp, vp, vp, vp, C.c_uint64]
     L.gpet_mlp_forward.argtypes = [vp, C.c_uint32, vp, vp]
     L.gpet_mlp_loss_grad.argtypes = [vp, C.c_uint32, vp, vp, P(C.c_double), vp]
     L.gpet_mlp_train.argtypes = [vp, C.c_uint64, vp, vp, P(TrainParams), vp]
@@ -908,6 +911,20 @@ class Mlp:
         w = np.empty(self.n_params, np.float32)
         self.ctx._check(self.L.gpet_mlp_get_weights(self.h, w.ctypes.data_as(C.c_void_p)))
         return w
+
+    def get_state(self) -> dict:
+        """Training checkpoint: weights, Adam moments m and v, step count."""
+        w, m, v = (np.empty(self.n_params, np.float32) for _ in range(3))
+        step = C.c_uint64()
+        self.ctx._check(self.L.gpet_mlp_get_state(self.h, w.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
+                                                  v.ctypes.data_as(C.c_void_p), C.byref(step)))
+        return {"weights": w, "m": m, "v": v, "step": int(step.value)}
+
+    def set_state(self, state: dict):
+        w, m, v = (np.ascontiguousarray(state[k], np.float32) for k in ("weights", "m", "v"))
+        assert w.size == m.size == v.size == self.n_params
+        self.ctx._check(self.L.gpet_mlp_set_state(self.h, w.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
+                                                  v.ctypes.data_as(C.c_void_p), int(state["step"])))
 
     def _dev(self, a, dtype):
         t = self.ctx.torch

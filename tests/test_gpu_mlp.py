@@ -187,6 +187,41 @@ def test_training_lowers_the_loss(ctx):
     m.close()
 
 
+@pytest.mark.parametrize("factored", [False, True])
+def test_training_resumes_from_a_checkpoint(ctx, factored):
+    """60 Adam steps in one run equal 30 steps, a checkpoint (weights, moments,
+    step count) restored into a fresh network, and 30 more steps: the same
+    per-step losses and final weights, bit for bit."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    rng = np.random.default_rng(21)
+    x = rng.uniform(-1, 1, (20_000, 6)).astype(np.float32)
+    if factored:
+        sizes, kw = [6, 64, 64, 5 + 2 * 12], {"n_first": 5, "n_groups": 2}
+        y = S.factored_join(rng.integers(0, 5, 20_000), rng.integers(0, 12, 20_000), 5).astype(np.int32)
+        init = np.concatenate([pack_params(G.mlp_init(sizes, seed=4)), np.zeros(4 * 12, np.float32)])
+    else:
+        sizes, kw = [6, 64, 64, 16], {}
+        y = rng.integers(0, 16, 20_000).astype(np.int32)
+        init = pack_params(G.mlp_init(sizes, seed=4))
+    a = Mlp(ctx, sizes, init, **kw)
+    la = a.train(x, y, steps=60, batch=1024, lr=2e-3, seed=5)
+    b = Mlp(ctx, sizes, init, **kw)
+    lb1 = b.train(x, y, steps=30, batch=1024, lr=2e-3, seed=5)
+    state = b.get_state()
+    assert state["step"] == 30
+    c = Mlp(ctx, sizes, None, **kw)
+    c.set_state(state)
+    lc = c.train(x, y, steps=30, batch=1024, lr=2e-3, seed=5)
+    assert np.array_equal(np.concatenate([lb1, lc]), la)
+    assert np.array_equal(c.get_weights(), a.get_weights())
+    bad = dict(state, v=-np.abs(state["v"]) - 1.0)
+    from paper_2603_07327_amd.gpet import GpetError
+    with pytest.raises(GpetError):
+        c.set_state(bad)
+    for m in (a, b, c):
+        m.close()
+
+
 def test_mlp_rejects_bad_labels(ctx):
     from paper_2603_07327_amd.gpet import ERR_ARG, GpetError, Mlp
     m = Mlp(ctx, [6, 64, 10])

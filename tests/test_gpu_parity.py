@@ -303,6 +303,7 @@ def test_tallies_matched_seed(ctx, oracle_mod, case):
     print(case, "hits", hits.count, len(rh), "coinc", len(ca), len(rc), st, rst)
     assert abs(len(ca) - len(rc)) / len(rc) <= 0.005
     assert abs(hits.count - len(rh)) / len(rh) <= 0.002
+    assert st["nonfinite"] == 0  # the guard on non-finite photon states never fires on sane input
     for k in ("events", "steps", "real", "searches"):
         assert abs(st[k] - rst[k]) <= 0.002 * rst[k] + 2, k
 
