@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
 
     // ---- which lanes act this trip
     bool run;
-    if (A.schedule == 0) {
+    if (A.schedule == 0 || A.schedule == 2) { // (2: the pool schedule, here in the modes it does not cover)
       // every phase runs; panel searches run in batches: lanes that need one
       // wait until at least `search_batch` lanes of the wave do, or nothing
       // else can run
