@@ -572,9 +572,11 @@ gpet_status gpet_batch_read_counts(gpet_batch *batch, gpet_hits *hits, gpet_stat
 
 /* Launch shape of the transport kernel: blocks of 256 lanes per compute unit
  * (0 = as many as fit); the scheduling of lane actions within a wavefront
- * (0: every pending action runs each loop trip, with panel searches held until
- * `search_batch` lanes (1..64) need one; 1: only the action held by the most
- * lanes runs; 2: plain transport only -- each wavefront keeps a pool of 128
+ * (0: every pending action runs each loop trip, and the panel searches at the
+ * end of the trip, held until `search_batch` lanes (1..64) need one; 1: only
+ * the action held by the most lanes runs (a search, or one of the others
+ * followed by the searches it leads to); 2: plain transport only -- each
+ * wavefront keeps a pool of 128
  * photons in LDS and every loop trip gathers up to 64 photons waiting for the
  * same action onto its lanes; other calls run as schedule 0).  Results do not
  * depend on the shape (every random number is keyed by event id). */

@@ -62,7 +62,7 @@ struct RunArgs {
   int32_t *vcount;
   int max_vertices;
   uint32_t search_batch; // lanes of a wave that must wait for a panel search before it runs
-  uint32_t schedule;     // 0: all phases each trip; 1: the most-populated phase only;
+  uint32_t schedule;     // 0: all phases each trip (searches at its end); 1: the most-populated phase only;
                          // 2: plain runs use the per-wave photon pools (k_transport_pool)
   // record and surrogate modes: photons entering their first panel inside the
   // surrogate domain get an entry with features px (6 per entry).  Record:

@@ -1,11 +1,16 @@
 // transport.hip -- photon-pair transport kernel for gfx950.
 //
 // One lane owns one annihilation event at a time and runs it as a small state
-// machine, one action per loop trip: an emission step, a Woodcock step in the
-// phantom, a panel search, a Woodcock step inside a panel (paper Sec. 2.1:
-// line-plane projection to the panel, transform to the panel frame,
-// step-by-step transport with the layer chosen from the depth coordinate), a
-// Kahn trial or a Rayleigh angle.
+// machine.  A loop trip holds one action that draws random numbers -- an
+// emission step, a Woodcock step in the phantom, a Woodcock step inside a
+// panel (paper Sec. 2.1: step-by-step transport in the panel frame with the
+// layer chosen from the depth coordinate), a Kahn trial or a Rayleigh angle --
+// and then, at the end of the trip, the panel search (line-plane projection
+// to the panels, transform to the panel frame) of every photon that needs
+// one, including those that the trip's first action just emitted or sent out
+// of a panel or the phantom.  A search draws nothing, so folding it into the
+// trip that made it necessary saves a trip per search without changing any
+// photon's random numbers.
 //
 // Every action that needs random numbers takes one Philox block, drawn at a
 // single call site at the top of the trip, so the costliest primitive runs
@@ -13,7 +18,8 @@
 // branch.  The one exception: the emission draws its positron-range and time
 // blocks inside its last step (the direction step of point and beam sources,
 // the rod-point step of rod sources), so photon A starts one or two trips
-// earlier (a trip of every event saved costs less than the extra call sites).  The launch covers a table of instances (scanner + source; one for a
+// earlier (a trip of every event saved costs less than the extra call sites).
+// The launch covers a table of instances (scanner + source; one for a
 // plain run, many for a batched sweep): waves claim chunks of consecutive events
 // of one instance with one atomic and switch instance only once drained, so the
 // scene stays wave-uniform (scalar loads).
@@ -251,16 +257,10 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     ++c_trips;
     CScene &S = *sp;
 
-    // ---- which lanes act this trip
-    bool run;
+    // ---- which lanes act this trip (panel searches come at its end)
+    bool run, search_pick = true;
     if (A.schedule == 0 || A.schedule == 2) { // (2: the pool schedule, here in the modes it does not cover)
-      // every phase runs; panel searches run in batches: lanes that need one
-      // wait until at least `search_batch` lanes of the wave do, or nothing
-      // else can run
-      const uint64_t sm = __ballot(phase == P_SEARCH);
-      const uint64_t om = __ballot(phase != P_SEARCH && phase != P_DONE && phase != P_FETCH);
-      const bool search_now = sm && ((uint32_t)__popcll(sm) >= A.search_batch || om == 0);
-      run = phase != P_DONE && phase != P_FETCH && (phase != P_SEARCH || search_now);
+      run = phase != P_DONE && phase != P_FETCH && phase != P_SEARCH;
     } else {
       // only the phase held by the most lanes runs (ties to the later phase),
       // so each phase body executes with as many lanes as possible
@@ -274,11 +274,12 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
           best = q;
         }
       }
-      run = phase == best;
+      run = phase == best && best != P_SEARCH;
+      search_pick = best == P_SEARCH;
     }
 
     // ---- the one Philox block of this trip
-    const bool draw = run && phase != P_SEARCH;
+    const bool draw = run;
     uint4 w = make_uint4(0u, 0u, 0u, 0u);
     if (draw) {
       w = philox(A.k0, A.k1, make_uint4(n, ev, inst_rng, sid));
@@ -287,16 +288,11 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     const float4 r = to_unit4(w);
     c_blocks += (draw && sid != 0u) ? 1u : 0u;
 
-    bool hit = false, ended = false, push = false;
+    bool hit = false, ended = false;
     start_a = false;
-    int n_tested = 0;
-    float sf[6];
-    int s_module = 0;
-    uint32_t s_anchor[kMaxLayers] = {0u, 0u, 0u, 0u};
     float h_edep = 0.f;
     int h_proc = 0;
-    bool stepped = false, real = false, searched = false, entered = false, trial = false, scattered = false,
-         capped = false, emitted = false;
+    bool stepped = false, real = false, trial = false, scattered = false, capped = false, emitted = false;
 
     if (!run) {
       // waits for its phase to be scheduled (or for events)
@@ -362,31 +358,6 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
             }
           } else {
             vertex<TRACE>(A, ev, ph, V_STEP, 0, -1, -1, mat, 0, 0, 0, n, x, e, 0.f, d);
-          }
-        }
-      }
-    } else if (phase == P_SEARCH) {
-      searched = true;
-      float ti;
-      const int p = search_panels(S, x, d, last, ti, n_tested);
-      if (p < 0) {
-        vertex<TRACE>(A, ev, ph, V_ESCAPE, -1, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
-        ended = true;
-      } else {
-        x = Vec{x.x + ti * d.x, x.y + ti * d.y, x.z + ti * d.z};
-        L += ti;
-        entered = true;
-        vertex<TRACE>(A, ev, ph, V_ENTER_PANEL, 1, p, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
-        panel = p;
-        CFloat *P = (CFloat *)(S.pose + 12 * p);
-        x = to_local(P, x);
-        d = dir_to_local(P, d);
-        phase = P_PANEL;
-        if (++steps > kMaxSteps) capped = ended = true; // bounds panel-to-panel hops as well
-        if constexpr (REC || SUR) {
-          if (last < 0 && !capped && entry_domain(S, A.sur, x, d, e, sf, s_module, s_anchor)) {
-            push = true;
-            if constexpr (SUR) ended = true; // the network takes over from here
           }
         }
       }
@@ -477,10 +448,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
 
     // ---- guard: a photon whose state stopped being finite ends here
     bool bad = false;
-    if ((scattered || entered) && nonfinite_state(x, d, e)) {
+    if (scattered && nonfinite_state(x, d, e)) {
       bad = ended = true;
       hit = false;
-      push = false;
     }
     c_nonfinite += bad ? 1u : 0u;
 
@@ -488,49 +458,10 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     c_events += emitted ? 1u : 0u;
     c_steps += stepped ? 1u : 0u;
     c_real += real ? 1u : 0u;
-    c_search += searched ? 1u : 0u;
-    c_tests += (uint32_t)n_tested;
-    c_pruned += (searched && S.ring_reg) ? 1u : 0u;
-    c_entries += entered ? 1u : 0u;
     c_trials += trial ? 1u : 0u;
     c_scatter += scattered ? 1u : 0u;
     c_capped += capped ? 1u : 0u;
 
-    // ---- record / surrogate: one atomic per wave reserves the new entries
-    if constexpr (REC || SUR) {
-      const uint64_t pm = __ballot(push);
-      if (pm) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(A.pcount, (unsigned long long)__popcll(pm));
-        base = __shfl(base, 0);
-        if (push) {
-          const unsigned long long i = base + (unsigned long long)__popcll(pm & below);
-          const bool fits = i < A.pcap;
-          if (fits) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) A.px[6 * i + k] = sf[k];
-          }
-          if constexpr (REC) {
-            if (fits) A.pevent[i] = ev;
-            rec_idx = fits ? (uint32_t)i : ~0u;
-#pragma unroll
-            for (int l = 0; l < kMaxLayers; ++l) rec_anchor[l] = s_anchor[l];
-            rec_module = s_module;
-            rec_panel = panel;
-            rec_e = e;
-            rec_n = 0;
-            rec_ovf = false;
-          } else if (fits) {
-            A.qev[i] = ev;
-            A.qmeta[i] = (uint32_t)ph | ((uint32_t)panel << 1) | ((uint32_t)s_module << 8);
-#pragma unroll
-            for (int l = 0; l < kMaxLayers; ++l) A.qanchor[kMaxLayers * i + l] = s_anchor[l];
-            A.qe[i] = e;
-            A.qtime[i] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
-          }
-        }
-      }
-    }
     if constexpr (REC) {
       if (rec_idx != ~0u) {
         if (hit) { // per-crystal deposit sums of the photon's stay in its first panel
@@ -603,6 +534,102 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     // ---- photon starts: A after the emission, B once A has ended
     if (start_a || (ended && ph == 0)) start_photon(S, start_a ? 0 : 1);
     else if (ended) phase = P_FETCH;
+
+    // ---- panel searches, at the end of the trip, so that a photon just
+    //      emitted or just out of a panel or the phantom searches in the trip
+    //      that put it there; they run in batches: lanes that need one wait
+    //      until at least `search_batch` lanes of the wave do, or nothing else
+    //      can run.  A search draws no random numbers.
+    bool s_run;
+    if (A.schedule == 1) {
+      s_run = search_pick && phase == P_SEARCH;
+    } else {
+      const uint64_t sm = __ballot(phase == P_SEARCH);
+      const uint64_t om = __ballot(phase != P_SEARCH && phase != P_DONE && phase != P_FETCH);
+      s_run = phase == P_SEARCH && ((uint32_t)__popcll(sm) >= A.search_batch || om == 0);
+    }
+    ended = capped = false;
+    bool push = false, entered = false;
+    int n_tested = 0;
+    float sf[6];
+    int s_module = 0;
+    uint32_t s_anchor[kMaxLayers] = {0u, 0u, 0u, 0u};
+    if (s_run) {
+      float ti;
+      const int p = search_panels(S, x, d, last, ti, n_tested);
+      if (p < 0) {
+        vertex<TRACE>(A, ev, ph, V_ESCAPE, -1, -1, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
+        ended = true;
+      } else {
+        x = Vec{x.x + ti * d.x, x.y + ti * d.y, x.z + ti * d.z};
+        L += ti;
+        entered = true;
+        vertex<TRACE>(A, ev, ph, V_ENTER_PANEL, 1, p, -1, -1, 0, 0, 0, n, x, e, 0.f, d);
+        panel = p;
+        CFloat *P = (CFloat *)(S.pose + 12 * p);
+        x = to_local(P, x);
+        d = dir_to_local(P, d);
+        phase = P_PANEL;
+        if (++steps > kMaxSteps) capped = ended = true; // bounds panel-to-panel hops as well
+        if constexpr (REC || SUR) {
+          if (last < 0 && !capped && entry_domain(S, A.sur, x, d, e, sf, s_module, s_anchor)) {
+            push = true;
+            if constexpr (SUR) ended = true; // the network takes over from here
+          }
+        }
+      }
+    }
+    bad = false;
+    if (entered && nonfinite_state(x, d, e)) {
+      bad = ended = true;
+      push = false;
+    }
+    c_nonfinite += bad ? 1u : 0u;
+    c_search += s_run ? 1u : 0u;
+    c_tests += (uint32_t)n_tested;
+    c_pruned += (s_run && S.ring_reg) ? 1u : 0u;
+    c_entries += entered ? 1u : 0u;
+    c_capped += capped ? 1u : 0u;
+
+    // ---- record / surrogate: one atomic per wave reserves the new entries
+    if constexpr (REC || SUR) {
+      const uint64_t pm = __ballot(push);
+      if (pm) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(A.pcount, (unsigned long long)__popcll(pm));
+        base = __shfl(base, 0);
+        if (push) {
+          const unsigned long long i = base + (unsigned long long)__popcll(pm & below);
+          const bool fits = i < A.pcap;
+          if (fits) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) A.px[6 * i + k] = sf[k];
+          }
+          if constexpr (REC) {
+            if (fits) A.pevent[i] = ev;
+            rec_idx = fits ? (uint32_t)i : ~0u;
+#pragma unroll
+            for (int l = 0; l < kMaxLayers; ++l) rec_anchor[l] = s_anchor[l];
+            rec_module = s_module;
+            rec_panel = panel;
+            rec_e = e;
+            rec_n = 0;
+            rec_ovf = false;
+          } else if (fits) {
+            A.qev[i] = ev;
+            A.qmeta[i] = (uint32_t)ph | ((uint32_t)panel << 1) | ((uint32_t)s_module << 8);
+#pragma unroll
+            for (int l = 0; l < kMaxLayers; ++l) A.qanchor[kMaxLayers * i + l] = s_anchor[l];
+            A.qe[i] = e;
+            A.qtime[i] = t_event + (unsigned long long)floorf(L * kInvCmmPerPs + 0.5f);
+          }
+        }
+      }
+    }
+    if (ended) {
+      if (ph == 0) start_photon(S, 1);
+      else phase = P_FETCH;
+    }
   }
   flush_stage(A, st, staged, lane, inst);
 
