@@ -1071,14 +1071,15 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
     A.qe = Q.e;
     A.qtime = Q.time;
     A.pcount = c->d_ctrl + kCtrlPairWord;
+    A.pholes = c->d_ctrl + kCtrlPairWord + 1;
     A.pcap = Q.cap;
     launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlWorkWord), 0u, 2, c->stream); // event-chunk counter
-    launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairWord), 0u, 2, c->stream); // queue count
+    launch_fill_u32((uint32_t *)(c->d_ctrl + kCtrlPairWord), 0u, 4, c->stream); // queue slots, empty slots
     (void)hipEventRecord(ev[0], c->stream);
     launch_transport(A, c->shape, c->n_cu, c->stream, kModeSurrogate);
     (void)hipEventRecord(ev[1], c->stream);
     s = hip_check(c, hipGetLastError(), "surrogate: transport launch");
-    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairWord, c->d_ctrl + kCtrlPairWord, 8, hipMemcpyDeviceToHost, c->stream),
+    if (!s) s = hip_check(c, hipMemcpyAsync(c->h_ctrl + kCtrlPairWord, c->d_ctrl + kCtrlPairWord, 16, hipMemcpyDeviceToHost, c->stream),
                           "surrogate: readback");
     if (!s) s = hip_check(c, wait_stream(c->stream), "surrogate: transport");
     if (s) break;
@@ -1087,10 +1088,12 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
       s = fail(c, GPET_ERR_HIP, "surrogate: entry queue overflow");
       break;
     }
-    entries += nq;
+    const uint64_t holes = c->h_ctrl[kCtrlPairWord + 1];
+    entries += nq - holes;
     (void)hipEventRecord(ev[2], c->stream);
     const int r = surrogate_hits(q, (const DevScene *)c->d_plain, P, Q, (uint32_t)nq, A.k0, A.k1, instance, A,
                                  c->stream, c->err, &none);
+    none -= holes; // empty slots draw no class
     (void)hipEventRecord(ev[3], c->stream);
     if (r != GPET_OK) {
       s = r;

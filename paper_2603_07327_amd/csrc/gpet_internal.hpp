@@ -77,6 +77,7 @@ struct RunArgs {
   float *qe;
   unsigned long long *qtime;
   unsigned long long *pcount; // device: pairs / queue entries produced
+  unsigned long long *pholes = nullptr; // device (surrogate): queue slots reserved but left empty
   unsigned long long pcap;
 };
 
@@ -176,6 +177,12 @@ size_t scan_tmp_words(size_t n);
 void scan_exclusive_u32(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st, uint32_t *total = nullptr);
 
 // Surrogate entry queue (library scratch): SoA of `cap` entries
+// Surrogate queue: a wave reserves kQueueResv slots at a time (one atomic per
+// reservation); the slots its last reservation leaves unused are marked by
+// meta = kQueueHole (features zero) and carry no entry.
+constexpr uint32_t kQueueResv = 32;
+constexpr uint32_t kQueueHole = 0xFFFFFFFFu;
+
 struct SurQueue {
   size_t cap = 0;
   void *blob = nullptr;

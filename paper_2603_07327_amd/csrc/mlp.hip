@@ -560,6 +560,13 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
+  if (meta[r] == kQueueHole) { // an empty queue slot
+    if (lane == 0) {
+      cls[r] = 0u;
+      nonzero[r] = 0u;
+    }
+    return;
+  }
   const float *zr = z + (size_t)r * ldz;
   const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
   // energy class: one class per lane
@@ -753,6 +760,13 @@ __global__ void __launch_bounds__(256) k_sample_classes(const float *z, int ldz,
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
+  if (meta[r] == kQueueHole) { // an empty queue slot
+    if (lane == 0) {
+      cls[r] = 0u;
+      nonzero[r] = 0u;
+    }
+    return;
+  }
   const float *zr = z + (size_t)r * ldz;
   float mx, total;
   row_max_sum(zr, C, lane, mx, total);
@@ -814,6 +828,13 @@ __global__ void __launch_bounds__(256) k_sample_tiles(const float2 *stats, int n
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
+  if (meta[r] == kQueueHole) { // an empty queue slot
+    if (lane == 0) {
+      cls[r] = 0u;
+      nonzero[r] = 0u;
+    }
+    return;
+  }
   const float2 t = lane < n_tiles ? stats[(size_t)r * n_tiles + lane] : make_float2(-INFINITY, 0.0f);
   float mx = t.x;
 #pragma unroll

@@ -96,8 +96,11 @@ __device__ __forceinline__ bool entry_domain(SC &S, const SurSpecD &P, const Vec
   return true;
 }
 
+// The surrogate mode is held to 5 waves per SIMD (96 registers, one spilled),
+// as the plain mode reaches by itself; the trace and record modes are test and
+// training-data paths and keep the compiler's allocation.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
+__global__ void __launch_bounds__(kBlock, MODE == kModeSurrogate ? 5 : 1) k_transport(RunArgs A) {
   constexpr bool TRACE = MODE == kModeTrace, REC = MODE == kModeRecord, SUR = MODE == kModeSurrogate;
   extern __shared__ float4 lds4[];
   const int lane = (int)__lane_id();
@@ -145,6 +148,9 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
   uint32_t c_events = 0, c_entries = 0, c_steps = 0, c_real = 0, c_trials = 0, c_search = 0, c_blocks = 0,
            c_capped = 0, c_scatter = 0, c_tests = 0, c_pruned = 0, c_nonfinite = 0;
   unsigned long long c_trips = 0;
+  // surrogate mode: the wave's current queue reservation [q_base, q_base + q_left)
+  unsigned long long q_base = 0;
+  uint32_t q_left = 0;
 
   // start photon `which` of the current event (A: +d, B: -d)
   auto start_photon = [&](CScene &S, int which) {
@@ -313,8 +319,15 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     } else if (phase == P_EMIT_POS) {
       // block 1: point in the chosen rod (rod ~ volume, uniform in its disk and length)
       const float tgt = q_u0 * S.rod_total;
-      int i = 0;
-      while (i < S.n_rods - 1 && S.rod_cum[i] < tgt) ++i;
+      // the first rod whose cumulative weight reaches tgt, the last rod if no
+      // other does: a binary search over rod_cum[0 .. n_rods - 2] (rod_cum
+      // never decreases), the same rod as a scan from the first
+      int i = 0, hi = S.n_rods - 1;
+      while (i < hi) {
+        const int mid = (i + hi) >> 1;
+        if (S.rod_cum[mid] < tgt) i = mid + 1;
+        else hi = mid;
+      }
       const float *rd = S.rods + 5 * i;
       const float rr = rd[2] * hw_sqrt(q_u1);
       src = Vec{rd[0] + rr * cos_rev(r.x), rd[1] + rr * sin_rev(r.x), rd[3] + r.y * (rd[4] - rd[3])};
@@ -595,11 +608,31 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     if constexpr (REC || SUR) {
       const uint64_t pm = __ballot(push);
       if (pm) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(A.pcount, (unsigned long long)__popcll(pm));
-        base = __shfl(base, 0);
+        const uint32_t kp = (uint32_t)__popcll(pm), rank = (uint32_t)__popcll(pm & below);
+        unsigned long long i;
+        if constexpr (SUR) {
+          // entries fill the wave's reservation; a new one of kQueueResv slots
+          // (or as many as the rest needs) is claimed when it runs out
+          if (kp > q_left) {
+            const uint32_t rest = kp - q_left, need = rest > kQueueResv ? rest : kQueueResv;
+            unsigned long long nb = 0;
+            if (lane == 0) nb = atomicAdd(A.pcount, (unsigned long long)need);
+            nb = __shfl(nb, 0);
+            i = rank < q_left ? q_base + rank : nb + (rank - q_left);
+            q_base = nb + rest;
+            q_left = need - rest;
+          } else {
+            i = q_base + rank;
+            q_base += kp;
+            q_left -= kp;
+          }
+        } else {
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(A.pcount, (unsigned long long)kp);
+          base = __shfl(base, 0);
+          i = base + rank;
+        }
         if (push) {
-          const unsigned long long i = base + (unsigned long long)__popcll(pm & below);
           const bool fits = i < A.pcap;
           if (fits) {
 #pragma unroll
@@ -632,6 +665,18 @@ __global__ void __launch_bounds__(kBlock) k_transport(RunArgs A) {
     }
   }
   flush_stage(A, st, staged, lane, inst);
+  if constexpr (SUR) {
+    // the unused rest of the last reservation: empty slots (q_left < 64)
+    if ((uint32_t)lane < q_left) {
+      const unsigned long long i = q_base + (unsigned long long)lane;
+      if (i < A.pcap) {
+        A.qmeta[i] = kQueueHole;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) A.px[6 * i + k] = 0.0f;
+      }
+    }
+    if (lane == 0 && q_left) atomicAdd(A.pholes, (unsigned long long)q_left);
+  }
 
   uint32_t lc[kStatCount] = {c_events, c_entries, c_steps,   c_real, c_trials, c_search,
                              c_blocks, c_capped,  c_scatter, 0u,     c_tests,  c_pruned, c_nonfinite};

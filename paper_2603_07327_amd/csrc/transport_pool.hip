@@ -256,8 +256,15 @@ __global__ void __launch_bounds__(kBlock) k_transport_pool(RunArgs A) {
     } else if (best == P_EMIT_POS) {
       // block 1: point in the chosen rod (rod ~ volume, uniform in its disk and length)
       const float tgt = q_u0 * S.rod_total;
-      int i = 0;
-      while (i < S.n_rods - 1 && S.rod_cum[i] < tgt) ++i;
+      // the first rod whose cumulative weight reaches tgt, the last rod if no
+      // other does: a binary search over rod_cum[0 .. n_rods - 2] (rod_cum
+      // never decreases), the same rod as a scan from the first
+      int i = 0, hi = S.n_rods - 1;
+      while (i < hi) {
+        const int mid = (i + hi) >> 1;
+        if (S.rod_cum[mid] < tgt) i = mid + 1;
+        else hi = mid;
+      }
       const float *rd = S.rods + 5 * i;
       const float rr = rd[2] * hw_sqrt(L);
       x = Vec{rd[0] + rr * cos_rev(r.x), rd[1] + rr * sin_rev(r.x), rd[3] + r.y * (rd[4] - rd[3])};
