@@ -66,10 +66,23 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const uint32_t *a, s
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// thread t scans the 16 consecutive items [t 16, t 16 + 16) of its tile
+// thread t scans the 16 consecutive items [t 16, t 16 + 16) of its tile.
+// tile_offs: the tiles' offsets, or (raw) their sums, of which the block adds
+// up those before its own tile.
 __global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t *a, size_t n, const uint32_t *tile_offs,
-                                                           uint32_t *total) {
+                                                           uint32_t *total, int raw) {
   __shared__ uint32_t ws[kScanBlock / 64];
+  __shared__ uint32_t s_off;
+  if (raw) {
+    uint32_t t = 0;
+    for (uint32_t k = threadIdx.x; k < blockIdx.x; k += kScanBlock) t += tile_offs[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (__lane_id() == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) s_off = ws[0] + ws[1] + ws[2] + ws[3];
+    __syncthreads();
+  }
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   const bool full = base + kScanItems <= n && (((uintptr_t)a) & 15u) == 0;
@@ -94,7 +107,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t *a, size_t n
     v[k] = run;
     run += t;
   }
-  const uint32_t off = block_exclusive_256(run, ws) + (tile_offs ? tile_offs[blockIdx.x] : 0u);
+  const uint32_t off = block_exclusive_256(run, ws) + (raw ? s_off : tile_offs ? tile_offs[blockIdx.x] : 0u);
   if (full) {
     uint4 *q = (uint4 *)(a + base);
 #pragma unroll
@@ -118,18 +131,24 @@ static size_t scan_scratch_words(size_t n) {
   return w + 1;
 }
 
+// Tiles up to which each apply block adds up the sums of the tiles before its
+// own (at most 4096 words read per block, 16.7 M items) instead of a scan of
+// its own.
+constexpr size_t kScanRawTiles = 4096;
+
 // `total` (may be null) receives the sum
 static void exclusive_scan(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st, uint32_t *total = nullptr) {
   if (n == 0) return;
   const size_t tiles = (n + kScanTile - 1) / kScanTile;
   if (tiles == 1) {
-    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanBlock), 0, st, a, n, (const uint32_t *)nullptr, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanBlock), 0, st, a, n, (const uint32_t *)nullptr, total, 0);
     return;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, (const uint32_t *)a, n, tmp);
-  exclusive_scan(tmp, tiles, tmp + tiles, st);
+  const int raw = tiles <= kScanRawTiles ? 1 : 0;
+  if (!raw) exclusive_scan(tmp, tiles, tmp + tiles, st);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, a, n, (const uint32_t *)tmp,
-                     total);
+                     total, raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -141,20 +160,27 @@ static void exclusive_scan(uint32_t *a, size_t n, uint32_t *tmp, hipStream_t st,
 // key's local value v = (key >> local_shift) & local_mask (event index or time),
 // so every instance gets buckets in proportion to its item count.  A key whose
 // instance lies outside the map gets bucket nb.
+// With one instance its map travels in the kernel arguments (base0, count0,
+// scale0) and the arrays are not read.
 struct BucketMap {
   int inst_shift, local_shift;
   unsigned long long local_mask;
   const uint32_t *base, *count;
   const float *scale; // buckets per unit of v
   uint32_t n_inst, nb;
+  uint32_t base0, count0;
+  float scale0;
 };
 
 __device__ __forceinline__ uint32_t bucket_of(const BucketMap &M, unsigned long long key) {
   const uint32_t i = M.inst_shift < 64 ? (uint32_t)(key >> M.inst_shift) : 0u;
   if (i >= M.n_inst) return M.nb;
   const unsigned long long v = (key >> M.local_shift) & M.local_mask;
-  const uint32_t b = min((uint32_t)((float)v * M.scale[i]), M.count[i] - 1u);
-  return M.base[i] + b;
+  const bool one = M.n_inst == 1;
+  const float sc = one ? M.scale0 : M.scale[i];
+  const uint32_t cnt = one ? M.count0 : M.count[i], base = one ? M.base0 : M.base[i];
+  const uint32_t b = min((uint32_t)((float)v * sc), cnt - 1u);
+  return base + b;
 }
 
 // ---------------------------------------------------------------------------
@@ -719,11 +745,14 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
   // per-instance map arrays live behind the bucket counters
   uint32_t *d_base = bb.map, *d_cnt = bb.map + ni;
   float *d_scale = (float *)(bb.map + 2 * ni);
-  std::memcpy(bb.pinned_map, base.data(), ni * 4);
-  std::memcpy(bb.pinned_map + ni, cnt.data(), ni * 4);
-  std::memcpy(bb.pinned_map + 2 * ni, scale.data(), ni * 4);
-  (void)hipMemcpyAsync(bb.map, bb.pinned_map, 3 * ni * 4, hipMemcpyHostToDevice, st);
-  BucketMap M{inst_shift, local_shift, local_mask, d_base, d_cnt, d_scale, (uint32_t)ni, (uint32_t)nb};
+  if (ni > 1) {
+    std::memcpy(bb.pinned_map, base.data(), ni * 4);
+    std::memcpy(bb.pinned_map + ni, cnt.data(), ni * 4);
+    std::memcpy(bb.pinned_map + 2 * ni, scale.data(), ni * 4);
+    (void)hipMemcpyAsync(bb.map, bb.pinned_map, 3 * ni * 4, hipMemcpyHostToDevice, st);
+  }
+  BucketMap M{inst_shift, local_shift, local_mask, d_base, d_cnt, d_scale, (uint32_t)ni, (uint32_t)nb,
+              base[0], cnt[0], scale[0]};
   launch_fill_u32(bb.n_big, 0u, 1, st);
   const unsigned g = (unsigned)((n + 255) / 256);
   unsigned long long *ko = b.k1;
@@ -801,42 +830,6 @@ __global__ void k_heads(size_t n, const unsigned long long *key, uint32_t *flag)
   flag[i] = (i == 0 || (key[i] >> 8) != (key[i - 1] >> 8)) ? 1u : 0u;
 }
 
-// One single per run of equal (instance, event, crystal) in key order; the
-// event and crystal come out of the key.  e/d/t are the hits' energy, depth
-// and time, indexed by perm.
-__global__ void k_adder(size_t n, const unsigned long long *key, const uint32_t *perm, const uint32_t *seg,
-                        const float *edep, const float *depth, const unsigned long long *time, InstTab T,
-                        int gid_bits, unsigned long long ev_mask, int inst_shift, uint32_t *s_ev, uint32_t *s_gid,
-                        float *s_edep, float *s_depth, unsigned long long *s_time, uint32_t *s_inst_int,
-                        uint32_t *s_inst_out, uint64_t cap) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const unsigned long long k = key[i];
-  const unsigned long long run = k >> 8;
-  if (i > 0 && (key[i - 1] >> 8) == run) return;
-  unsigned long long se = 0, sd = 0, tm = ~0ull;
-  size_t j = i;
-  do {
-    const uint32_t h = perm[j];
-    const float e = edep[h];
-    se += (unsigned long long)(e * 4294967296.0f);
-    sd += (unsigned long long)((e * depth[h]) * 4294967296.0f);
-    tm = min(tm, time[h]);
-    ++j;
-  } while (j < n && (key[j] >> 8) == run);
-  const uint32_t s = seg[i];
-  if (s >= cap) return;
-  const double E = (double)se * 0x1p-32;
-  const uint32_t in = inst_shift < 64 ? (uint32_t)(k >> inst_shift) : 0u;
-  s_ev[s] = T.first[in] + (uint32_t)((run >> gid_bits) & ev_mask);
-  s_gid[s] = (uint32_t)(run & ((1ull << gid_bits) - 1));
-  s_edep[s] = (float)E;
-  s_depth[s] = se ? (float)((double)sd / (double)se) : 0.0f;
-  s_time[s] = tm;
-  s_inst_int[s] = in;
-  if (s_inst_out) s_inst_out[s] = in;
-}
-
 // light sharing: the crystal read instead of `gid` (one of its existing edge
 // neighbours in the same layer and module, in the order t-1, t+1, a-1, a+1,
 // picked by the high half of pick * count); geo holds per instance the
@@ -862,53 +855,61 @@ __device__ __forceinline__ uint32_t shared_crystal(uint32_t gid, const uint32_t 
   return cnt ? nb[((unsigned long long)pick * cnt) >> 32] : gid;
 }
 
-__global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, uint32_t *s_gid,
-                                              const uint32_t *s_inst, InstTab T, const float *s_edep,
-                                              float *s_energy, uint32_t *s_win, uint32_t *wflag, uint32_t k0,
-                                              uint32_t k1, float fwhm, float e_lo, float e_hi, uint32_t *spp,
-                                              uint32_t *spec, unsigned long long *s_time, float time_sigma,
-                                              float *s_depth, float doi_sigma, unsigned long long ls_thresh,
-                                              const uint32_t *geo, unsigned long long *block_max, uint32_t n_spp) {
-  __shared__ unsigned long long s_max[4];
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long tm = 0; // largest time stamp of all singles (every window's keys fit its width)
-  if (i < n) {
-    // normal deviates by Box-Muller from the digitizer stream of (gid, event,
-    // instance): words 0, 1 for the energy, 2, 3 for the time
-    const uint32_t in_i = s_inst[i], rng = T.rng[in_i];
-    const uint32_t w_gid = s_gid[i]; // the counters take the crystal that was hit
-    uint32_t gid = w_gid;
-    const uint4 w = philox(k0, k1, make_uint4(gid, s_ev[i], rng, 3u));
-    const float u0 = to_unit(w.x), u1 = to_unit(w.y);
-    const float g = sqrtf(-2.0f * logf(u0)) * cos_rev(u1);
-    const float E = s_edep[i];
-    const float sig = fwhm * sqrtf(511.0f * E) * (1.0f / 2.354820045f);
-    const float Eb = E + sig * g;
-    const uint32_t in = (Eb >= e_lo && Eb <= e_hi) ? 1u : 0u;
-    s_energy[i] = Eb;
-    s_win[i] = in;
-    wflag[i] = in;
-    if (ls_thresh) { // light sharing: stream 8 of (gid, event, instance)
-      const uint4 v = philox(k0, k1, make_uint4(gid, s_ev[i], rng, 8u));
-      if ((unsigned long long)v.x < ls_thresh) {
-        gid = shared_crystal(gid, geo, T.n_inst, in_i, v.y);
-        s_gid[i] = gid;
-      }
-    }
-    if (spp && in && gid < n_spp) atomicAdd(&spp[gid], 1u);
-    if (spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&spec[(int)Eb], 1u);
-    tm = s_time[i];
-    if (time_sigma > 0.0f) { // timing resolution: rounded to the ps, not below 0
-      const float gt = sqrtf(-2.0f * logf(to_unit(w.z))) * cos_rev(to_unit(w.w));
-      const long long tb = (long long)tm + (long long)rintf(time_sigma * gt);
-      tm = tb > 0 ? (unsigned long long)tb : 0ull;
-      s_time[i] = tm;
-    }
-    if (doi_sigma > 0.0f) { // DOI resolution: stream 6 of (gid, event, instance)
-      const uint4 v = philox(k0, k1, make_uint4(w_gid, s_ev[i], rng, 6u));
-      s_depth[i] += doi_sigma * (sqrtf(-2.0f * logf(to_unit(v.x))) * cos_rev(to_unit(v.y)));
-    }
+// parameters of the blur stage (energy and optional time / DOI resolution,
+// light sharing, window, tallies) and its outputs per single
+struct BlurArgs {
+  uint32_t k0, k1;
+  float fwhm, e_lo, e_hi;
+  uint32_t *spp, *spec; // tallies (null when not kept here)
+  uint32_t n_spp;
+  float time_sigma, doi_sigma;
+  unsigned long long ls_thresh;
+  const uint32_t *geo;
+  float *s_energy;
+  uint32_t *s_win, *wflag;
+  unsigned long long *block_max;
+};
+
+// Blur of single i (event ev, instance in_i, crystal gid hit, energy E): the
+// blurred energy and window flags are written here; the crystal read (light
+// sharing), the time and the depth are updated in place for the caller.
+// Normal deviates by Box-Muller from the digitizer stream of (gid, event,
+// instance): words 0, 1 for the energy, 2, 3 for the time.
+__device__ __forceinline__ void blur_single(const BlurArgs &B, const InstTab &T, size_t i, uint32_t in_i,
+                                            uint32_t ev, uint32_t &gid, float E, unsigned long long &tm,
+                                            float &depth) {
+  const uint32_t rng = T.rng[in_i];
+  const uint32_t w_gid = gid; // the counters take the crystal that was hit
+  const uint4 w = philox(B.k0, B.k1, make_uint4(gid, ev, rng, 3u));
+  const float u0 = to_unit(w.x), u1 = to_unit(w.y);
+  const float g = sqrtf(-2.0f * logf(u0)) * cos_rev(u1);
+  const float sig = B.fwhm * sqrtf(511.0f * E) * (1.0f / 2.354820045f);
+  const float Eb = E + sig * g;
+  const uint32_t in = (Eb >= B.e_lo && Eb <= B.e_hi) ? 1u : 0u;
+  B.s_energy[i] = Eb;
+  B.s_win[i] = in;
+  B.wflag[i] = in;
+  if (B.ls_thresh) { // light sharing: stream 8 of (gid, event, instance)
+    const uint4 v = philox(B.k0, B.k1, make_uint4(gid, ev, rng, 8u));
+    if ((unsigned long long)v.x < B.ls_thresh) gid = shared_crystal(gid, B.geo, T.n_inst, in_i, v.y);
   }
+  if (B.spp && in && gid < B.n_spp) atomicAdd(&B.spp[gid], 1u);
+  if (B.spec && Eb >= 0.0f && Eb < 700.0f) atomicAdd(&B.spec[(int)Eb], 1u);
+  if (B.time_sigma > 0.0f) { // timing resolution: rounded to the ps, not below 0
+    const float gt = sqrtf(-2.0f * logf(to_unit(w.z))) * cos_rev(to_unit(w.w));
+    const long long tb = (long long)tm + (long long)rintf(B.time_sigma * gt);
+    tm = tb > 0 ? (unsigned long long)tb : 0ull;
+  }
+  if (B.doi_sigma > 0.0f) { // DOI resolution: stream 6 of (gid, event, instance)
+    const uint4 v = philox(B.k0, B.k1, make_uint4(w_gid, ev, rng, 6u));
+    depth += B.doi_sigma * (sqrtf(-2.0f * logf(to_unit(v.x))) * cos_rev(to_unit(v.y)));
+  }
+}
+
+// the block's largest time stamp into B.block_max[blockIdx.x] (every window's
+// keys must fit its width)
+__device__ __forceinline__ void block_max_time(const BlurArgs &B, unsigned long long tm) {
+  __shared__ unsigned long long s_max[4];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long t = __shfl_xor(tm, o);
@@ -919,8 +920,89 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, ui
   if (threadIdx.x == 0) {
     unsigned long long b = s_max[0];
     for (int k = 1; k < 4; ++k) b = s_max[k] > b ? s_max[k] : b;
-    block_max[blockIdx.x] = b;
+    B.block_max[blockIdx.x] = b;
   }
+}
+
+// the blur over singles already in the output arrays (after a module or panel
+// readout merged them)
+__global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, uint32_t *s_gid,
+                                              const uint32_t *s_inst, InstTab T, const float *s_edep,
+                                              unsigned long long *s_time, float *s_depth, BlurArgs B) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long tm = 0;
+  if (i < n) {
+    const uint32_t g0 = s_gid[i];
+    uint32_t gid = g0;
+    tm = s_time[i];
+    float depth = B.doi_sigma > 0.0f ? s_depth[i] : 0.0f;
+    blur_single(B, T, i, s_inst[i], s_ev[i], gid, s_edep[i], tm, depth);
+    if (gid != g0) s_gid[i] = gid;
+    if (B.time_sigma > 0.0f) s_time[i] = tm;
+    if (B.doi_sigma > 0.0f) s_depth[i] = depth;
+  }
+  block_max_time(B, tm);
+}
+
+// One single per run of equal (instance, event, crystal) in key order; the
+// event and crystal come out of the key.  e/d/t are the hits' energy, depth
+// and time, indexed by perm.  BLUR: the blur stage of each single runs here
+// too (crystal readout), so the singles are read back by no separate pass.
+template <bool BLUR>
+__global__ void __launch_bounds__(256) k_adder(size_t n, const unsigned long long *key, const uint32_t *perm,
+                                               const uint32_t *seg, const float *edep, const float *depth,
+                                               const unsigned long long *time, InstTab T, int gid_bits,
+                                               unsigned long long ev_mask, int inst_shift, uint32_t *s_ev,
+                                               uint32_t *s_gid, float *s_edep, float *s_depth,
+                                               unsigned long long *s_time, uint32_t *s_inst_int,
+                                               uint32_t *s_inst_out, uint64_t cap, BlurArgs B) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long tmax = 0;
+  bool head = false;
+  unsigned long long k = 0, run = 0;
+  if (i < n) {
+    k = key[i];
+    run = k >> 8;
+    head = i == 0 || (key[i - 1] >> 8) != run;
+  }
+  if constexpr (BLUR) {
+    // the window flags past the singles are zero: the k-th non-head hit
+    // (k = i - seg[i]) clears position n - 1 - k, so [singles, n) is covered
+    if (i < n && !head) B.wflag[n - 1 - (i - seg[i])] = 0u;
+  }
+  if (head) {
+    unsigned long long se = 0, sd = 0, tm = ~0ull;
+    size_t j = i;
+    do {
+      const uint32_t h = perm[j];
+      const float e = edep[h];
+      se += (unsigned long long)(e * 4294967296.0f);
+      sd += (unsigned long long)((e * depth[h]) * 4294967296.0f);
+      tm = min(tm, time[h]);
+      ++j;
+    } while (j < n && (key[j] >> 8) == run);
+    const uint32_t s = seg[i];
+    if (s < cap) {
+      const double E = (double)se * 0x1p-32;
+      const uint32_t in = inst_shift < 64 ? (uint32_t)(k >> inst_shift) : 0u;
+      const uint32_t ev = T.first[in] + (uint32_t)((run >> gid_bits) & ev_mask);
+      uint32_t gid = (uint32_t)(run & ((1ull << gid_bits) - 1));
+      const float e_sum = (float)E;
+      float dep = se ? (float)((double)sd / (double)se) : 0.0f;
+      s_ev[s] = ev;
+      s_edep[s] = e_sum;
+      s_inst_int[s] = in;
+      if (s_inst_out) s_inst_out[s] = in;
+      if constexpr (BLUR) {
+        blur_single(B, T, s, in, ev, gid, e_sum, tm, dep);
+        tmax = tm;
+      }
+      s_gid[s] = gid;
+      s_depth[s] = dep;
+      s_time[s] = tm;
+    }
+  }
+  if constexpr (BLUR) block_max_time(B, tmax);
 }
 
 __global__ void __launch_bounds__(1024) k_max_u64(const unsigned long long *v, size_t n, unsigned long long *out) {
@@ -1431,32 +1513,64 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     hp = f1 ? sb.v1 : sb.v0;
   }
   run_heads();
-  if (!sync("after the hit sort")) return GPET_ERR_HIP;
-  if (rbh[13] & 2u) {
-    err = "digitize: a hit's instance, event or crystal id lies outside its declared range";
-    return GPET_ERR_ARG;
-  }
-  // hit tallies once every id is known to be in range
-  if (T && (T->hits_per_crystal || T->doi))
-    hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
-                       T->hits_per_crystal, n_tally, T->doi, T->doi_bins, D.panel_depth);
-  if (mapped && rbh[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
-    const bool f1 = radix_sort(sb, n, hit_bits, st);
-    hk = f1 ? sb.k1 : sb.k0;
-    hp = f1 ? sb.v1 : sb.v0;
-    run_heads();
+  // Without tallies, dead time or a module / panel readout nothing before the
+  // energy window needs the singles count on the host: the adder (with the
+  // blur) runs over every hit position, the window flags are scanned over n
+  // positions (the adder zeroes those beyond the singles), and the checks of
+  // the hit sort wait for the synchronization after the window.
+  const bool any_tally = T && (T->hits_per_crystal || T->doi || T->singles_per_crystal || T->energy_spectrum);
+  const bool defer = !any_tally && D.readout == GPET_READOUT_CRYSTAL && D.dead_mode == GPET_DEAD_NONE;
+  const char *range_msg = "digitize: a hit's instance, event or crystal id lies outside its declared range";
+  const char *cap_msg = "digitize: singles capacity too small (it must hold the crystal-level singles)";
+  uint64_t ns = 0;
+  if (!defer) {
     if (!sync("after the hit sort")) return GPET_ERR_HIP;
+    if (rbh[13] & 2u) {
+      err = range_msg;
+      return GPET_ERR_ARG;
+    }
+    // hit tallies once every id is known to be in range
+    if (T && (T->hits_per_crystal || T->doi))
+      hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
+                         T->hits_per_crystal, n_tally, T->doi, T->doi_bins, D.panel_depth);
+    if (mapped && rbh[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
+      const bool f1 = radix_sort(sb, n, hit_bits, st);
+      hk = f1 ? sb.k1 : sb.k0;
+      hp = f1 ? sb.v1 : sb.v0;
+      run_heads();
+      if (!sync("after the hit sort")) return GPET_ERR_HIP;
+    }
+    ns = rbh[1];
+    S->count = ns;
+    S->windowed = 0;
+    if (ns > S->capacity) { // the crystal singles pass through the output arrays
+      err = cap_msg;
+      return GPET_ERR_CAPACITY;
+    }
   }
-  uint64_t ns = rbh[1];
-  S->count = ns;
-  S->windowed = 0;
-  if (ns > S->capacity) { // the crystal singles pass through the output arrays
-    err = "digitize: singles capacity too small (it must hold the crystal-level singles)";
-    return GPET_ERR_CAPACITY;
-  }
-  hipLaunchKernelGGL(k_adder, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth, D.h_time, IT,
-                     D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
-                     (unsigned long long *)S->time_ps, s_inst, S->instance, S->capacity);
+  // 3. blur + window (fused into the adder at crystal readout); per-block
+  //    maxima of the time stamps go to the radix histogram (n / 4 bytes, free
+  //    here; the keys must stay intact for a fallback sort), and one block
+  //    reduces them.  With dead time the tallies wait until the
+  //    losses are known.
+  const bool dead = D.dead_mode != GPET_DEAD_NONE && ns > 0;
+  const bool fuse_blur = D.readout == GPET_READOUT_CRYSTAL;
+  unsigned long long *s_time = (unsigned long long *)S->time_ps;
+  BlurArgs BA{D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
+              (T && !dead) ? T->singles_per_crystal : nullptr, (T && !dead) ? T->energy_spectrum : nullptr,
+              n_tally, D.time_sigma, D.doi_sigma, D.ls_thresh, d_tab + 6 * ni, S->energy_kev, S->in_window,
+              wpos, (unsigned long long *)sb.hist}; // the radix histogram is free until the time sort
+  auto launch_adder = [&]() {
+    if (fuse_blur)
+      hipLaunchKernelGGL(k_adder<true>, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth,
+                         D.h_time, IT, D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
+                         s_time, s_inst, S->instance, S->capacity, BA);
+    else
+      hipLaunchKernelGGL(k_adder<false>, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth,
+                         D.h_time, IT, D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
+                         s_time, s_inst, S->instance, S->capacity, BA);
+  };
+  launch_adder();
   // 2b. module / panel readout: runs of (instance, event, unit) merge into the
   //     free sort buffers, then back into the output arrays
   if (D.readout != GPET_READOUT_CRYSTAL) {
@@ -1477,17 +1591,14 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                        o_depth, o_time, o_inst, S->event, S->gid, S->edep_kev, S->depth_mm,
                        (unsigned long long *)S->time_ps, s_inst, S->instance);
   }
-  // 3. blur + window; per-block maxima of the time stamps go to the (now
-  //    free) second key array, then one block reduces them.  With dead time
-  //    the tallies wait until the losses are known.
-  const bool dead = D.dead_mode != GPET_DEAD_NONE && ns > 0;
-  unsigned long long *s_time = (unsigned long long *)S->time_ps;
-  hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
-                     S->edep_kev, S->energy_kev, S->in_window, wpos, D.k0, D.k1, D.fwhm_511, D.e_lo, D.e_hi,
-                     (T && !dead) ? T->singles_per_crystal : nullptr, (T && !dead) ? T->energy_spectrum : nullptr,
-                     s_time, D.time_sigma, S->depth_mm, D.doi_sigma, D.ls_thresh, d_tab + 6 * ni, sb.k1, n_tally);
-  hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)sb.k1,
-                     (size_t)grid_for(ns), (unsigned long long *)(rb + 4));
+  if (!fuse_blur)
+    hipLaunchKernelGGL(k_blur, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, S->event, S->gid, s_inst, IT,
+                       S->edep_kev, s_time, S->depth_mm, BA);
+  auto reduce_max = [&]() {
+    hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)BA.block_max,
+                       (size_t)(fuse_blur ? grid_for(n) : grid_for(ns)), (unsigned long long *)(rb + 4));
+  };
+  reduce_max();
   if (dead) {
     // 3b. dead time per unit (free here: the key/value pairs, flag, wpos)
     if (!sync("after the blur")) return GPET_ERR_HIP;
@@ -1524,8 +1635,31 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                        S->gid, S->energy_kev, T ? T->singles_per_crystal : nullptr, n_tally,
                        T ? T->energy_spectrum : nullptr);
   }
-  exclusive_scan(wpos, ns, sb.scan_tmp, st, rb + 3);
+  exclusive_scan(wpos, defer ? n : ns, sb.scan_tmp, st, rb + 3);
   if (!sync("after the energy window")) return GPET_ERR_HIP;
+  if (defer) { // the checks of the hit sort
+    if (rbh[13] & 2u) {
+      err = range_msg;
+      return GPET_ERR_ARG;
+    }
+    if (mapped && rbh[12]) { // a bucket overflowed LDS: sort every key bit and redo the adder
+      const bool f1 = radix_sort(sb, n, hit_bits, st);
+      hk = f1 ? sb.k1 : sb.k0;
+      hp = f1 ? sb.v1 : sb.v0;
+      run_heads();
+      launch_adder();
+      reduce_max();
+      exclusive_scan(wpos, n, sb.scan_tmp, st, rb + 3);
+      if (!sync("after the energy window")) return GPET_ERR_HIP;
+    }
+    ns = rbh[1];
+    S->count = ns;
+    S->windowed = 0;
+    if (ns > S->capacity) {
+      err = cap_msg;
+      return GPET_ERR_CAPACITY;
+    }
+  }
   const size_t nw = rbh[3];
   S->windowed = nw;
   const unsigned long long tmax = (unsigned long long)rbh[4] | ((unsigned long long)rbh[5] << 32);
