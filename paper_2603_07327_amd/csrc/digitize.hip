@@ -469,36 +469,6 @@ __device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, un
   return ka < kb || (ka == kb && va < vb);
 }
 
-// Value of lane (lane ^ lx) for lx in {1, 2, 4, 8, 16, 32} without the LDS
-// crossbar: DPP quad permutes (1, 2), row shifts (4), a row rotation (8) and
-// the gfx950 half-row / half-wave swaps (16, 32).  lx must fold to a constant.
-__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lx) {
-  const uint32_t lane = __lane_id();
-  switch (lx) {
-  case 1:
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false); // quad_perm [1,0,3,2]
-  case 2:
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false); // quad_perm [2,3,0,1]
-  case 4: {
-    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, false); // lane + 4
-    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false); // lane - 4
-    return (lane & 4u) ? dn : up;
-  }
-  case 8:
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false); // row_ror:8
-  case 16: {
-    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-    return (lane & 16u) ? r[0] : r[1];
-  }
-  case 32: {
-    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-    return (lane & 32u) ? r[0] : r[1];
-  }
-  default:
-    return (uint32_t)__shfl_xor((int)x, lx);
-  }
-}
-
 __device__ __forceinline__ unsigned long long lane_xor_u64(unsigned long long x, int lx) {
   const uint32_t lo = lane_xor((uint32_t)x, lx), hi = lane_xor((uint32_t)(x >> 32), lx);
   return ((unsigned long long)hi << 32) | lo;

@@ -549,8 +549,10 @@ __global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int
 //
 // One pass over the position logits (n2 <= 64 B): chunk k of 64 positions is
 // loaded coalesced, position k 64 + lane into lane's register v[k] (masked
-// where the position does not exist); the draw walks the chunks in order with
-// one wave prefix sum each, so it equals the natural-order inverse CDF.
+// where the position does not exist); the chunk totals and their running sum
+// in natural order find the chunk, one wave prefix sum inside it the
+// position, so the draw is the natural-order inverse CDF (its sums rounded in
+// that order).
 template <int B>
 __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, int G,
                                                          const float *T, uint32_t n, const uint32_t *ev,
@@ -560,17 +562,30 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
   const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
-  if (meta[r] == kQueueHole) { // an empty queue slot
+  // the loads that do not wait for the energy class go out first (a wave is
+  // latency-bound here): entry words, energy logits, anchors, and with one
+  // position block (G = 1, the block is the same for every energy class) the
+  // position logits too
+  const float *zr = z + (size_t)r * ldz;
+  const uint32_t mt = meta[r], evr = ev[r];
+  const float v1 = lane < n1 ? zr[lane] : -INFINITY;
+  const int nl = S->n_layers;
+  uint32_t aw[kMaxLayers];
+#pragma unroll
+  for (int q = 0; q < kMaxLayers; ++q) aw[q] = q < nl ? anchor[(size_t)kMaxLayers * r + q] : 0u;
+  const bool early = G == 1;
+  float zp[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) zp[c] = early && c * 64 + lane < n2 ? zr[n1 + c * 64 + lane] : 0.f;
+  if (mt == kQueueHole) { // an empty queue slot
     if (lane == 0) {
       cls[r] = 0u;
       nonzero[r] = 0u;
     }
     return;
   }
-  const float *zr = z + (size_t)r * ldz;
-  const uint4 w = philox(k0, k1, make_uint4(0u, ev[r], inst_rng, 4u + (meta[r] & 1u)));
+  const uint4 w = philox(k0, k1, make_uint4(0u, evr, inst_rng, 4u + (mt & 1u)));
   // energy class: one class per lane
-  const float v1 = lane < n1 ? zr[lane] : -INFINITY;
   float m1 = v1;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m1 = fmaxf(m1, __shfl_xor(m1, o));
@@ -592,16 +607,14 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
     return;
   }
   // layer sizes and this entry's anchors (at most kMaxLayers), selected by value
-  const int nl = S->n_layers;
   int nt[kMaxLayers], na[kMaxLayers], at[kMaxLayers], aa[kMaxLayers];
 #pragma unroll
   for (int q = 0; q < kMaxLayers; ++q) {
     const bool on = q < nl;
     nt[q] = on ? S->layer[q].n_t : 0;
     na[q] = on ? S->layer[q].n_a : 0;
-    const uint32_t aw = on ? anchor[(size_t)kMaxLayers * r + q] : 0u;
-    at[q] = (int)(aw & 0xFFFFu) - H;
-    aa[q] = (int)(aw >> 16) - H;
+    at[q] = (int)(aw[q] & 0xFFFFu) - H;
+    aa[q] = (int)(aw[q] >> 16) - H;
   }
   const float *z2 = zr + position_block(e, n1, n2, G);
   const float *t = T + (size_t)(e - 1) * n2;
@@ -625,7 +638,7 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
       }
     const int it = atl + dt, ia = aal + da;
     const bool ok = j < n2 && it >= 0 && it < ntl && ia >= 0 && ia < nal;
-    v[c] = ok ? z2[j] + t[j] : -INFINITY;
+    v[c] = ok ? (early ? zp[c] : z2[j]) + t[j] : -INFINITY;
     m = fmaxf(m, v[c]);
     da += 64; // next chunk: position + 64
     while (da >= W) {
@@ -637,37 +650,57 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  float sl = 0.f;
-  int last = -1; // the last position that exists
+  for (int o = 1; o < 64; o <<= 1) m = fmaxf(m, lane_xor_f(m, o));
+  // chunk totals: B independent butterfly sums on the DPP / permlane paths
+  // (every lane ends with all of them), then the running sum over the chunks
+  // in natural order picks the chunk, and one wave prefix sum inside it the
+  // position -- a single LDS-crossbar scan per entry instead of one per chunk
+  float tot[B];
 #pragma unroll
   for (int c = 0; c < B; ++c) {
-    if (v[c] > -INFINITY) last = c * 64 + lane;
     v[c] = v[c] > -INFINITY ? __expf(v[c] - m) : 0.f;
-    sl += v[c];
+    tot[c] = v[c];
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sl += __shfl_xor(sl, o);
-    last = max(last, __shfl_xor(last, o));
-  }
+  for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+    for (int c = 0; c < B; ++c) tot[c] += lane_xor_f(tot[c], o);
+  float sl = 0.f;
+#pragma unroll
+  for (int c = 0; c < B; ++c) sl += tot[c];
   const float target2 = to_unit(w.z) * sl;
-  int k = last; // rounding left the target beyond the total
-  float carry = 0.f;
+  int cs = -1;      // the chunk whose running sum first reaches the target
+  float carry = 0.f; // the running sum before it
+  float vc = 0.f;    // this lane's value in it
 #pragma unroll
   for (int c = 0; c < B; ++c) {
-    float in2 = v[c];
+    const bool here = cs < 0 && carry + tot[c] >= target2;
+    vc = here ? v[c] : vc;
+    if (cs < 0) {
+      if (here) cs = c;
+      else carry += tot[c];
+    }
+  }
+  int k;
+  if (cs < 0) { // rounding left the target beyond the total: the last position that exists
+    int last = -1;
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+      if (v[c] > 0.f) last = c * 64 + lane;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) last = max(last, (int)lane_xor((uint32_t)last, o));
+    k = last;
+  } else {
+    float in2 = vc;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const float tt = __shfl_up(in2, o);
       if (lane >= o) in2 += tt;
     }
-    const uint64_t cr = __ballot(carry + in2 >= target2 && v[c] > 0.f);
-    if (cr) {
-      k = c * 64 + __ffsll((unsigned long long)cr) - 1;
-      break;
-    }
-    carry += __shfl(in2, 63);
+    const uint64_t cr = __ballot(carry + in2 >= target2 && vc > 0.f);
+    const uint64_t ex = __ballot(vc > 0.f);
+    // (rounding inside the chunk: its last position that exists)
+    k = cs * 64 + (cr ? __ffsll((unsigned long long)cr) - 1 : 63 - __clzll((long long)ex));
   }
   if (lane == 0) {
     cls[r] = 1u + (uint32_t)k * (uint32_t)(n1 - 1) + (uint32_t)(e - 1);
