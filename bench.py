@@ -83,10 +83,17 @@ def survey_form_work(counts: dict, n_panels: int, source: str = "point", cost=No
 # Bytes each digitizer stage moves per item, as built: hit keys 24, hit sort
 # 60 (count, scatter, wave sort), run heads and their scan 24, adder 32 per
 # hit (key, index, segment, energy / depth / time) and 28 per single written;
-# blur 36, window scan 12, time keys 20 per single; time keys written 12, time
-# sort 96 (two radix passes, bucket starts, wave sort) and pairing 40 per
-# windowed single; 8 per coincidence written.
-DIGI_BYTES = {"hit": 24 + 60 + 24 + 32, "single": 28 + 36 + 12 + 20, "windowed": 12 + 96 + 40, "coinc": 8}
+# the blur (inside the adder at crystal readout) 12 written, window scan 12,
+# time keys 20 per single; time keys written 12, time sort 96 (two radix
+# passes, bucket starts, wave sort) and pairing 40 per windowed single; 8 per
+# coincidence written.
+DIGI_BYTES = {"hit": 24 + 60 + 24 + 32, "single": 28 + 12 + 12 + 20, "windowed": 12 + 96 + 40, "coinc": 8}
+
+
+def digitizer_survey_bytes(hits: int, windowed: int) -> float:
+    """The sort traffic in the survey's form: 2 (8 + 4) bytes per item and
+    pass, 7 passes over the hits and 8 over the singles the sorter takes."""
+    return 24.0 * (7 * hits + 8 * windowed)
 HBM_PEAK = 8.0e12
 
 
@@ -740,7 +747,7 @@ def main():
         ctxs.append((d, c, hits, singles, coinc))
 
     kernel_ms, work, stats_last = [], [], None
-    digi_ms, digi_bytes = [], []
+    digi_ms, digi_bytes, digi_survey = [], [], []
 
     def step(i, record):
         nonlocal stats_last
@@ -761,6 +768,7 @@ def main():
                 stats_last = st
                 digi_ms.append(tm[1])
                 digi_bytes.append(digitizer_bytes(hits.count, singles.count, singles.windowed, nc))
+                digi_survey.append(digitizer_survey_bytes(hits.count, singles.windowed))
             out.append((d, hits.count, singles.count, nc))
         return out
 
@@ -799,7 +807,12 @@ def main():
                                / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                "frac": float(np.mean(digi_bytes)) / (float(np.mean(digi_ms)) * 1e-3) / HBM_PEAK,
                                "bytes_per_design": float(np.mean(digi_bytes)), "ms_per_design": float(np.mean(digi_ms)),
-                               "bytes_per_item": DIGI_BYTES},
+                               "bytes_per_item": DIGI_BYTES,
+                               "survey_form": {"bytes_per_design": float(np.mean(digi_survey)),
+                                               "frac": float(np.mean(digi_survey)) / (float(np.mean(digi_ms)) * 1e-3)
+                                               / HBM_PEAK,
+                                               "note": "24 B per item and pass, 7 passes over the hits, 8 over the "
+                                                       "windowed singles"}},
     }
     line["window_sweep"] = window_sweep(ctxs, n, 1000 + args.warmup + args.steps - 1,
                                         G.SWEEP_POSITIONS[(args.warmup + args.steps - 1) % len(G.SWEEP_POSITIONS)])
