@@ -395,36 +395,18 @@ template <class SC> __device__ __forceinline__ Loc locate(SC &S, int p, Vec l) {
   const float ua = l.z - S.mod_a0 - ma * S.mod_step_a;
   const bool in_mod = !(mt < 0.0f || mt >= (float)S.mod_n_t || ma < 0.0f || ma >= (float)S.mod_n_a ||
                         ut >= S.mod_t || ua >= S.mod_a);
-  // the layer holding the depth; its fields picked lane by lane from the
-  // (wave-uniform) layer table, the lowest matching layer winning
-  int L = -1, nt = 1, na = 1, mat_c = 0, slot_c = 0, mat_i = 0, slot_i = 0, base = 0;
-  float off_t = 0.0f, off_a = 0.0f, ipt = 0.0f, ipa = 0.0f, pt = 0.0f, pa = 0.0f, lo_t = 0.0f, hi_t = 0.0f,
-        lo_a = 0.0f, hi_a = 0.0f;
+  // the layer holding the depth (the lowest matching layer wins), then its
+  // fields, loaded lane by lane from the scene's layer table (those of layer 0
+  // where no layer matches: they are not used then)
+  int L = -1;
 #pragma unroll
-  for (int k = kMaxLayers - 1; k >= 0; --k) {
-    if (k < S.n_layers) {
-      const auto &y = S.layer[k];
-      const bool m = l.x >= y.d0 && l.x < y.d1;
-      L = m ? k : L;
-      nt = m ? y.n_t : nt;
-      na = m ? y.n_a : na;
-      mat_c = m ? y.mat_crystal : mat_c;
-      slot_c = m ? y.slot_crystal : slot_c;
-      mat_i = m ? y.mat_interval : mat_i;
-      slot_i = m ? y.slot_interval : slot_i;
-      base = m ? y.base : base;
-      off_t = m ? y.off_t : off_t;
-      off_a = m ? y.off_a : off_a;
-      ipt = m ? y.inv_pitch_t : ipt;
-      ipa = m ? y.inv_pitch_a : ipa;
-      pt = m ? y.pitch_t : pt;
-      pa = m ? y.pitch_a : pa;
-      lo_t = m ? y.lo_t : lo_t;
-      hi_t = m ? y.hi_t : hi_t;
-      lo_a = m ? y.lo_a : lo_a;
-      hi_a = m ? y.hi_a : hi_a;
-    }
-  }
+  for (int k = kMaxLayers - 1; k >= 0; --k)
+    if (k < S.n_layers) L = (l.x >= S.layer[k].d0 && l.x < S.layer[k].d1) ? k : L;
+  const auto &y = S.layer[L < 0 ? 0 : L];
+  const int nt = y.n_t, na = y.n_a, mat_c = y.mat_crystal, slot_c = y.slot_crystal, mat_i = y.mat_interval,
+            slot_i = y.slot_interval, base = y.base;
+  const float off_t = y.off_t, off_a = y.off_a, ipt = y.inv_pitch_t, ipa = y.inv_pitch_a, pt = y.pitch_t,
+              pa = y.pitch_a, lo_t = y.lo_t, hi_t = y.hi_t, lo_a = y.lo_a, hi_a = y.hi_a;
   const float it = floorf((ut - off_t) * ipt);
   const float ia = floorf((ua - off_a) * ipa);
   const float ct = ut - off_t - it * pt;

@@ -133,3 +133,38 @@ def test_tallies_reject_crystal_ids_outside_the_scanner(ctx, oracle_mod):
     torch.cuda.synchronize()
     for k, v in tl.items():
         assert int(v.sum()) == 0, k
+
+
+def test_digitize_same_with_and_without_the_early_wait(ctx):
+    """Without tallies the hit sort's checks wait for the synchronization after
+    the energy window (the adder runs without a host wait before it); with
+    tallies they come right after the sort.  Both orders give the same
+    singles and coincidences, bit for bit."""
+    n = 300_000
+    sc = G.small_animal_scene("C", pos=(5.0, 0.0, 0.0), n_events=n)
+    ctx.set_scene(sc)
+    hits, _ = ctx.transport(n, seed=12)
+    sg_a, (fa, sa) = ctx.digitize(hits, seed=3)
+    tl = ctx.alloc_tallies(doi_bins=DOI_BINS)
+    sg_b, (fb, sb) = ctx.digitize(hits, seed=3, tallies=tl)
+    a, b = sg_a.numpy(), sg_b.numpy()
+    assert sg_a.count == sg_b.count and sg_a.windowed == sg_b.windowed
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(fa.cpu().numpy(), fb.cpu().numpy())
+    assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
+
+
+def test_out_of_range_ids_rejected_without_tallies(ctx):
+    """The deferred checks still reject a crystal id past the scanner's last
+    crystal (the call fails at the synchronization after the window)."""
+    import torch
+    from paper_2603_07327_amd.gpet import GpetError, HitList
+    sc = G.small_animal_scene("C", n_events=10)
+    ctx.set_scene(sc)
+    nc = ctx.info.n_crystals
+    t = lambda a, dt: torch.tensor(a, dtype=dt, device=ctx.dev)  # noqa: E731
+    h = HitList(t([3, 5], torch.int32), t([1, nc], torch.int32), t([511.0, 511.0], torch.float32),
+                t([1.0, 2.0], torch.float32), t([0, 10], torch.int64), t([0, 0], torch.int32), 2, 0, 100)
+    with pytest.raises(GpetError):
+        ctx.digitize(h, seed=1)
