@@ -349,6 +349,50 @@ static bool radix_sort(SortBufs &b, size_t n, int bits, hipStream_t st) {
   return flip;
 }
 
+// Per-instance constants of the digitizer (device arrays of n_inst entries).
+struct InstTab {
+  const uint32_t *first, *n_events, *cpp, *rng;
+  const uint32_t *ncr; // crystals of the instance's scanner
+  uint32_t n_inst;
+};
+
+// The hits a sort key is built from.
+struct HitSrc {
+  const uint32_t *ev, *gid, *aux, *inst; // inst may be null (one instance)
+  InstTab T;
+  int gid_bits, inst_shift;
+  uint32_t *err; // set to 2 for a hit whose ids lie outside its instance
+};
+
+// key = instance | (event - first) | gid | photon | index of the hit within its
+// photon (7 bits, saturated): unique per hit, so the sorted order is fixed.
+// Hits outside their instance's event range or with a crystal id outside the
+// instance's scanner are flagged (*H.err = 2).
+__device__ __forceinline__ unsigned long long hit_key(const HitSrc &H, size_t i) {
+  const InstTab &T = H.T;
+  const uint32_t in = H.inst ? H.inst[i] : 0u;
+  const uint32_t a = H.aux[i];
+  const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
+  uint32_t e = 0;
+  const uint32_t g = H.gid[i];
+  if (in >= T.n_inst || H.ev[i] - T.first[in] >= T.n_events[in] || g >= T.ncr[in] ||
+      (H.gid_bits < 32 && (g >> H.gid_bits) != 0)) {
+    *H.err = 2u;
+  } else {
+    e = H.ev[i] - T.first[in];
+  }
+  const unsigned long long inst_bits =
+      H.inst_shift < 64 ? (unsigned long long)(in < T.n_inst ? in : 0u) << H.inst_shift : 0ull;
+  return inst_bits | ((((unsigned long long)e << H.gid_bits) | (g & ((1ull << H.gid_bits) - 1))) << 8) | low;
+}
+
+__global__ void k_hit_keys(size_t n, HitSrc H, unsigned long long *key, uint32_t *val) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = hit_key(H, i);
+  val[i] = (uint32_t)i;
+}
+
 // ---------------------------------------------------------------------------
 // Bucket sort of (u64 key, u32 value) by (key, value): order the items by
 // bucket, then sort each bucket: a wave per few buckets with a register
@@ -376,11 +420,14 @@ __device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
   return mine;
 }
 
-// keys whose bucket falls outside the map are skipped and flagged (*flag = 2)
-__global__ void k_bucket_count(const unsigned long long *key, size_t n, BucketMap M, uint32_t *count,
+// keys whose bucket falls outside the map are skipped and flagged (*flag = 2).
+// FROM_HITS: the keys are built from the hits here (and in the scatter), not
+// read from a key array, and the values are the hit indices.
+template <bool FROM_HITS>
+__global__ void k_bucket_count(const unsigned long long *key, HitSrc H, size_t n, BucketMap M, uint32_t *count,
                                uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t kb = i < n ? bucket_of(M, key[i]) : 0u;
+  const uint32_t kb = i < n ? bucket_of(M, FROM_HITS ? hit_key(H, i) : key[i]) : 0u;
   if (i < n && kb >= M.nb) *flag = 2u;
   const bool valid = i < n && kb < M.nb;
   const uint32_t b = valid ? kb : 0u;
@@ -389,10 +436,11 @@ __global__ void k_bucket_count(const unsigned long long *key, size_t n, BucketMa
 }
 
 // cursor holds bucket starts on entry and bucket ends on exit
-__global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *vin, size_t n, BucketMap M,
+template <bool FROM_HITS>
+__global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *vin, HitSrc H, size_t n, BucketMap M,
                                  uint32_t *cursor, unsigned long long *kout, uint32_t *vout) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned long long k = i < n ? kin[i] : 0ull;
+  const unsigned long long k = i < n ? (FROM_HITS ? hit_key(H, i) : kin[i]) : 0ull;
   const uint32_t kb = i < n ? bucket_of(M, k) : 0u;
   const bool valid = i < n && kb < M.nb;
   const uint32_t b = valid ? kb : 0u;
@@ -405,7 +453,7 @@ __global__ void k_bucket_scatter(const unsigned long long *kin, const uint32_t *
   const uint32_t pos = base + (uint32_t)__popcll(peers & below);
   if (valid && pos < n) {
     kout[pos] = k;
-    vout[pos] = vin[i];
+    vout[pos] = FROM_HITS ? (uint32_t)i : vin[i];
   }
 }
 
@@ -699,7 +747,7 @@ template <bool CLUSTERED>
 static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t value_bound, int inst_shift, int local_shift,
                             unsigned long long local_mask, const std::vector<uint64_t> &items,
                             const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp,
-                            const unsigned long long *&out_k, const uint32_t *&out_v) {
+                            const unsigned long long *&out_k, const uint32_t *&out_v, const HitSrc *hits = nullptr) {
   const size_t ni = items.size();
   std::vector<uint32_t> base(ni), cnt(ni);
   std::vector<float> scale(ni);
@@ -730,10 +778,22 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
   if constexpr (CLUSTERED) {
     // count[0] = 0 and count[1 + b] counts bucket b: after the scan and the
     // scatter, count[b] is the start of bucket b and count[b + 1] its end
+    // (with a hit source the keys come from the hits, and (k0, v0) are not read)
     launch_fill_u32(bb.count, 0u, nb + 1, st);
-    hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, b.k0, n, M, bb.count + 1, bb.pinned_flag);
+    const HitSrc H = hits ? *hits : HitSrc{};
+    if (hits)
+      hipLaunchKernelGGL(k_bucket_count<true>, dim3(g), dim3(256), 0, st, (const unsigned long long *)nullptr, H, n,
+                         M, bb.count + 1, bb.pinned_flag);
+    else
+      hipLaunchKernelGGL(k_bucket_count<false>, dim3(g), dim3(256), 0, st, b.k0, H, n, M, bb.count + 1,
+                         bb.pinned_flag);
     exclusive_scan(bb.count + 1, nb, scan_tmp, st);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(256), 0, st, b.k0, b.v0, n, M, bb.count + 1, b.k1, b.v1);
+    if (hits)
+      hipLaunchKernelGGL(k_bucket_scatter<true>, dim3(g), dim3(256), 0, st, (const unsigned long long *)nullptr,
+                         (const uint32_t *)nullptr, H, n, M, bb.count + 1, b.k1, b.v1);
+    else
+      hipLaunchKernelGGL(k_bucket_scatter<false>, dim3(g), dim3(256), 0, st, b.k0, b.v0, H, n, M, bb.count + 1,
+                         b.k1, b.v1);
   } else {
     // stable passes over the bucket number, low digit first, (k0, v0) -> (k1, v1) -> ...
     const int bits = std::max(1, log2_ceil(nb + 1));
@@ -761,38 +821,6 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
 // ---------------------------------------------------------------------------
 // digitizer stages
 // ---------------------------------------------------------------------------
-// Per-instance constants of the digitizer (device arrays of n_inst entries).
-struct InstTab {
-  const uint32_t *first, *n_events, *cpp, *rng;
-  const uint32_t *ncr; // crystals of the instance's scanner
-  uint32_t n_inst;
-};
-
-// key = instance | (event - first) | gid | photon | index of the hit within its
-// photon (7 bits, saturated): unique per hit, so the sorted order is fixed.
-// Hits outside their instance's event range or with a crystal id outside the
-// instance's scanner are flagged (*flag = 2).
-__global__ void k_hit_keys(size_t n, const uint32_t *ev, const uint32_t *gid, const uint32_t *aux,
-                           const uint32_t *hinst, InstTab T, int gid_bits, int inst_shift, unsigned long long *key,
-                           uint32_t *val, uint32_t *flag) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t in = hinst ? hinst[i] : 0u;
-  const uint32_t a = aux[i];
-  const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
-  uint32_t e = 0;
-  const uint32_t g = gid[i];
-  if (in >= T.n_inst || ev[i] - T.first[in] >= T.n_events[in] || g >= T.ncr[in] ||
-      (gid_bits < 32 && (g >> gid_bits) != 0)) {
-    *flag = 2u;
-  } else {
-    e = ev[i] - T.first[in];
-  }
-  const unsigned long long inst_bits = inst_shift < 64 ? (unsigned long long)(in < T.n_inst ? in : 0u) << inst_shift : 0ull;
-  key[i] = inst_bits | ((((unsigned long long)e << gid_bits) | (g & ((1ull << gid_bits) - 1))) << 8) | low;
-  val[i] = (uint32_t)i;
-}
-
 // first hit of each (instance, event, crystal) run
 __global__ void k_heads(size_t n, const unsigned long long *key, uint32_t *flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1444,10 +1472,18 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     return GPET_ERR_ARG;
   }
 
-  // 1. sort hits by (instance, event, gid, photon, index)
+  // 1. sort hits by (instance, event, gid, photon, index).  With one instance
+  //    the bucket count and scatter build the keys from the hits themselves;
+  //    the key array (k0, v0) is written only when a full radix sort needs it.
   uint32_t *err_flag = rb + 13; // checked at the next synchronization
-  hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_event, D.h_gid, D.h_aux, D.h_inst, IT,
-                     D.gid_bits, inst_shift, sb.k0, sb.v0, err_flag);
+  const HitSrc HS{D.h_event, D.h_gid, D.h_aux, D.h_inst, IT, D.gid_bits, inst_shift, err_flag};
+  bool keys_built = false;
+  auto build_keys = [&]() {
+    if (!keys_built)
+      hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, HS, sb.k0, sb.v0);
+    keys_built = true;
+  };
+  if (ni > 1) build_keys();
   std::vector<uint64_t> items(ni, n);
   if (ni > 1) { // per-instance counts size the bucket map
     launch_fill_u32(d_icount, 0u, ni, st);
@@ -1473,11 +1509,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     exclusive_scan(flag, n, sb.scan_tmp, st, rb + 1);
   };
   const bool mapped = bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st,
-                                        sb.scan_tmp, bk, bv) == 0;
+                                        sb.scan_tmp, bk, bv, keys_built ? nullptr : &HS) == 0;
   if (mapped) {
     hk = bk;
     hp = bv;
   } else { // too many buckets for the scratch: sort every key bit instead
+    build_keys();
     const bool f1 = radix_sort(sb, n, hit_bits, st);
     hk = f1 ? sb.k1 : sb.k0;
     hp = f1 ? sb.v1 : sb.v0;
@@ -1504,6 +1541,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       hipLaunchKernelGGL(k_hit_tallies, dim3(grid_for(n)), dim3(256), 0, st, n, D.h_gid, D.h_depth,
                          T->hits_per_crystal, n_tally, T->doi, T->doi_bins, D.panel_depth);
     if (mapped && rbh[12]) { // a bucket overflowed LDS: sort every key bit and redo the heads
+      build_keys();
       const bool f1 = radix_sort(sb, n, hit_bits, st);
       hk = f1 ? sb.k1 : sb.k0;
       hp = f1 ? sb.v1 : sb.v0;
@@ -1613,6 +1651,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       return GPET_ERR_ARG;
     }
     if (mapped && rbh[12]) { // a bucket overflowed LDS: sort every key bit and redo the adder
+      build_keys();
       const bool f1 = radix_sort(sb, n, hit_bits, st);
       hk = f1 ? sb.k1 : sb.k0;
       hp = f1 ? sb.v1 : sb.v0;
