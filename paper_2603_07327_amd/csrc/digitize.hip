@@ -747,7 +747,8 @@ template <bool CLUSTERED>
 static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t value_bound, int inst_shift, int local_shift,
                             unsigned long long local_mask, const std::vector<uint64_t> &items,
                             const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp,
-                            const unsigned long long *&out_k, const uint32_t *&out_v, const HitSrc *hits = nullptr) {
+                            const unsigned long long *&out_k, const uint32_t *&out_v, const HitSrc *hits = nullptr,
+                            uint32_t *zero_extra = nullptr, size_t n_extra = 0) {
   const size_t ni = items.size();
   std::vector<uint32_t> base(ni), cnt(ni);
   std::vector<float> scale(ni);
@@ -771,7 +772,9 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
   }
   BucketMap M{inst_shift, local_shift, local_mask, d_base, d_cnt, d_scale, (uint32_t)ni, (uint32_t)nb,
               base[0], cnt[0], scale[0]};
-  launch_fill_u32(bb.n_big, 0u, 1, st);
+  // one launch zeroes the big-bucket count, the bucket counters (clustered) and
+  // the caller's extra words (flags the kernels below may set)
+  launch_zero3(bb.n_big, 1, CLUSTERED ? bb.count : nullptr, nb + 1, zero_extra, n_extra, st);
   const unsigned g = (unsigned)((n + 255) / 256);
   unsigned long long *ko = b.k1;
   uint32_t *vo = b.v1;
@@ -779,7 +782,6 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
     // count[0] = 0 and count[1 + b] counts bucket b: after the scan and the
     // scatter, count[b] is the start of bucket b and count[b + 1] its end
     // (with a hit source the keys come from the hits, and (k0, v0) are not read)
-    launch_fill_u32(bb.count, 0u, nb + 1, st);
     const HitSrc H = hits ? *hits : HitSrc{};
     if (hits)
       hipLaunchKernelGGL(k_bucket_count<true>, dim3(g), dim3(256), 0, st, (const unsigned long long *)nullptr, H, n,
@@ -1366,6 +1368,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       if (scr.buf) (void)hipFree(scr.buf);
       scr.buf = nullptr;
       scr.bytes = 0;
+      scr.tab_at = nullptr; // the table went with the old buffer
       const size_t grow = need + need / 4;
       if (hipMalloc(&scr.buf, grow) != hipSuccess) {
         err = "digitize: device scratch allocation failed";
@@ -1424,7 +1427,6 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   bb.pinned_flag = rb + 12;
   bb.pinned_map = rbh + 16 + ni;
   uint32_t *tab = rbh + 16 + 4 * ni;
-  launch_fill_u32(rb + 12, 0u, 2, st); // bucket overflow and id-range flags
   auto sync = [&](const char *what) {
     if (wait_stream(st) != hipSuccess) {
       err = std::string("digitize: stream error ") + what;
@@ -1456,7 +1458,17 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       tab[(7 + k) * ni + i] = have_layers ? D.layers[i * kLayerWords + k] : (k == 0 || k > kMaxLayers ? 1u : 0u);
     tab[(7 + kLayerWords) * ni + i] = D.ncr[i];
   }
-  (void)hipMemcpyAsync(d_tab, tab, ni * 4 * kTabRows, hipMemcpyHostToDevice, st);
+  // (the upload is skipped when this scratch already holds the same table)
+  const size_t tab_words = ni * kTabRows;
+  const bool same_tab = !scr.fixed && scr.tab_at == (const void *)d_tab && scr.tab_last.size() == tab_words &&
+                        std::equal(tab, tab + tab_words, scr.tab_last.begin());
+  if (!same_tab) {
+    (void)hipMemcpyAsync(d_tab, tab, tab_words * 4, hipMemcpyHostToDevice, st);
+    if (!scr.fixed) {
+      scr.tab_at = d_tab;
+      scr.tab_last.assign(tab, tab + tab_words);
+    }
+  }
   const InstTab IT{d_tab, d_tab + ni, d_tab + 2 * ni, d_tab + 3 * ni, d_tab + (7 + kLayerWords) * ni, (uint32_t)ni};
   // per-crystal tallies are kept for one scanner (the plain entry point)
   const uint32_t n_tally = D.ncr[0];
@@ -1483,7 +1495,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
       hipLaunchKernelGGL(k_hit_keys, dim3(grid_for(n)), dim3(256), 0, st, n, HS, sb.k0, sb.v0);
     keys_built = true;
   };
-  if (ni > 1) build_keys();
+  // the bucket overflow and id-range flags (rb[12], rb[13]) start at zero: with
+  // one instance the bucket sort's first launch clears them, else this one
+  if (ni > 1) {
+    launch_fill_u32(rb + 12, 0u, 2, st);
+    build_keys();
+  }
   std::vector<uint64_t> items(ni, n);
   if (ni > 1) { // per-instance counts size the bucket map
     launch_fill_u32(d_icount, 0u, ni, st);
@@ -1509,11 +1526,13 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     exclusive_scan(flag, n, sb.scan_tmp, st, rb + 1);
   };
   const bool mapped = bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st,
-                                        sb.scan_tmp, bk, bv, keys_built ? nullptr : &HS) == 0;
+                                        sb.scan_tmp, bk, bv, keys_built ? nullptr : &HS,
+                                        keys_built ? nullptr : rb + 12, 2) == 0;
   if (mapped) {
     hk = bk;
     hp = bv;
   } else { // too many buckets for the scratch: sort every key bit instead
+    if (!keys_built) launch_fill_u32(rb + 12, 0u, 2, st);
     build_keys();
     const bool f1 = radix_sort(sb, n, hit_bits, st);
     hk = f1 ? sb.k1 : sb.k0;
@@ -1722,12 +1741,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
         (void)hipMemcpyAsync(rb_count, d_icount, ni * 4, hipMemcpyDefault, st);
       }
     };
-    bool mapped_t = false;
-    launch_fill_u32(rb + 12, 0u, 1, st);
+    bool mapped_t = false; // (the bucket sort clears the overflow flag rb[12] it may set)
     if (nwin == 1) {
       tk = sb.k0;
       ti = sb.v0;
-    } else if (bucket_sort<false>(sb, bb, nwin, ns, tb, 0, t_mask, witems, trange, st, sb.scan_tmp, bk, bv) == 0) {
+    } else if (bucket_sort<false>(sb, bb, nwin, ns, tb, 0, t_mask, witems, trange, st, sb.scan_tmp, bk, bv, nullptr,
+                                  rb + 12, 1) == 0) {
       mapped_t = true;
       tk = bk;
       ti = bv;
@@ -1839,6 +1858,8 @@ void free_scratch(DigitizeScratch &scr) {
   if (scr.buf) (void)hipFree(scr.buf);
   scr.buf = nullptr;
   scr.bytes = 0;
+  scr.tab_at = nullptr;
+  scr.tab_last.clear();
 }
 
 } // namespace gpet

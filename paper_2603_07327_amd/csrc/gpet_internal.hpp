@@ -95,6 +95,7 @@ void launch_transport(const RunArgs &A, const LaunchShape &L, int n_cu, hipStrea
 void launch_transport_pool(const RunArgs &A, const LaunchShape &L, int n_cu, hipStream_t st);
 void launch_trace(const RunArgs &A, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
+void launch_zero3(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t *c, size_t nc, hipStream_t st);
 void launch_philox(uint64_t seed, const uint32_t *ctr, uint32_t n, uint32_t *out, hipStream_t st);
 void launch_locate(const DevScene &S, uint32_t n, const float *xyz, int32_t *ids6, hipStream_t st);
 void launch_ray_locate(const DevScene &S, uint32_t n, const float *o, const float *d, int ns,
@@ -112,6 +113,10 @@ struct DigitizeScratch {
   // a fixed buffer (the library's static device scratch): never grown or
   // freed, no pinned words; calls that need more than `bytes` are refused
   bool fixed = false;
+  // the instance table last uploaded into buf, and where (not kept for the
+  // fixed buffer, which other contexts share)
+  const void *tab_at = nullptr;
+  std::vector<uint32_t> tab_last;
 };
 // host words a call on the fixed scratch stages its readbacks and uploads in
 constexpr size_t kFixedHostWords = 64;

@@ -747,6 +747,27 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
+// zeroes up to three word ranges in one launch (null or empty ranges skipped)
+__global__ void k_zero3(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t *c, size_t nc) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb + nc; i += stride) {
+    if (i < na) a[i] = 0u;
+    else if (i < na + nb) b[i - na] = 0u;
+    else c[i - na - nb] = 0u;
+  }
+}
+
+void launch_zero3(uint32_t *a, size_t na, uint32_t *b, size_t nb, uint32_t *c, size_t nc, hipStream_t st) {
+  if (!a) na = 0;
+  if (!b) nb = 0;
+  if (!c) nc = 0;
+  const size_t n = na + nb + nc;
+  if (!n) return;
+  size_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_zero3, dim3((unsigned)g), dim3(256), 0, st, a, na, b, nb, c, nc);
+}
+
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st) {
   if (!n) return;
   size_t g = (n + 255) / 256;
