@@ -617,9 +617,13 @@ __device__ __forceinline__ void wave_load_bucket(const unsigned long long *key, 
 // current one sorts; bucket b spans [start[b], start[b + 1]).  Buckets a wave
 // cannot take (over 128 items, keys spanning 2^32 or more) are listed in big[]
 // (count in *n_big) for the block sort.  Values are below 2^vbits (1..32).
+// heads (may be null): for keys whose runs of equal key >> head_shift never
+// cross a bucket, heads[i] = 1 where such a run starts (the run heads of the
+// adder), written here for the buckets sorted here.
 __global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *key, uint32_t *val,
                                                           const uint32_t *start, uint32_t nb, int vbits,
-                                                          uint32_t *big, uint32_t *n_big) {
+                                                          uint32_t *big, uint32_t *n_big, uint32_t *heads,
+                                                          int head_shift) {
   const uint32_t b0 = (blockIdx.x * 4u + (threadIdx.x >> 6)) * kWaveBuckets;
   if (b0 >= nb) return;
   const uint32_t lane = __lane_id();
@@ -639,15 +643,25 @@ __global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *ke
     }
     const uint32_t size = hi - lo;
     bool listed = size > (uint32_t)kWaveSort;
+    if (size == 1 && heads && lane == 0) heads[lo] = 1u;
     if (size > 1 && !listed) {
       const uint32_t e = size <= 64 ? 1u : 2u;
       if (e == 1 ? wave_sort_packed<1>(k, v, size, vbits) : wave_sort_packed<2>(k, v, size, vbits)) {
+        // the item before element r of this lane: element r - 1 of the lane, or
+        // the last element of the lane before
+        const unsigned long long last = e == 1 ? k[0] : k[1];
+        const unsigned long long up = ((unsigned long long)__shfl_up((uint32_t)(last >> 32), 1) << 32) |
+                                      __shfl_up((uint32_t)last, 1);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
           const uint32_t t = lane * e + r;
           if (r < (int)e && t < size) {
             key[lo + t] = k[r];
             val[lo + t] = v[r];
+            if (heads) {
+              const unsigned long long prev = r == 0 ? up : k[0];
+              heads[lo + t] = (t == 0 || (k[r] >> head_shift) != (prev >> head_shift)) ? 1u : 0u;
+            }
           }
         }
       } else {
@@ -668,7 +682,8 @@ __global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *ke
 // one block per listed bucket (grid-stride over the list), bitonic network in LDS
 __global__ void __launch_bounds__(256) k_bucket_block_sort(unsigned long long *key, uint32_t *val,
                                                            const uint32_t *start, const uint32_t *big,
-                                                           const uint32_t *n_big, uint32_t *overflow) {
+                                                           const uint32_t *n_big, uint32_t *overflow,
+                                                           uint32_t *heads, int head_shift) {
   __shared__ unsigned long long sk[kLocalSort];
   __shared__ uint32_t sv[kLocalSort];
   const uint32_t listed = *n_big;
@@ -678,6 +693,10 @@ __global__ void __launch_bounds__(256) k_bucket_block_sort(unsigned long long *k
     const uint32_t size = hi - lo;
     if (size > (uint32_t)kLocalSort) {
       if (threadIdx.x == 0) *overflow = 1u;
+      // (its heads are cleared, so every head flag stays 0 or 1 until the
+      // caller's fallback sort redoes them)
+      if (heads)
+        for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) heads[lo + t] = 0u;
       continue;
     }
     uint32_t P = 2;
@@ -710,6 +729,7 @@ __global__ void __launch_bounds__(256) k_bucket_block_sort(unsigned long long *k
     for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) {
       key[lo + t] = sk[t];
       val[lo + t] = sv[t];
+      if (heads) heads[lo + t] = (t == 0 || (sk[t] >> head_shift) != (sk[t - 1] >> head_shift)) ? 1u : 0u;
     }
     __syncthreads();
   }
@@ -748,7 +768,8 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
                             unsigned long long local_mask, const std::vector<uint64_t> &items,
                             const std::vector<double> &range, hipStream_t st, uint32_t *scan_tmp,
                             const unsigned long long *&out_k, const uint32_t *&out_v, const HitSrc *hits = nullptr,
-                            uint32_t *zero_extra = nullptr, size_t n_extra = 0) {
+                            uint32_t *zero_extra = nullptr, size_t n_extra = 0, uint32_t *heads = nullptr,
+                            int head_shift = 0) {
   const size_t ni = items.size();
   std::vector<uint32_t> base(ni), cnt(ni);
   std::vector<float> scale(ni);
@@ -812,9 +833,9 @@ static uint32_t bucket_sort(SortBufs &b, BucketBufs &bb, size_t n, uint64_t valu
   }
   const size_t sort_waves = (nb + kWaveBuckets - 1) / kWaveBuckets;
   hipLaunchKernelGGL(k_bucket_wave_sort, dim3((unsigned)((sort_waves + 3) / 4)), dim3(256), 0, st, ko, vo, bb.count,
-                     (uint32_t)nb, std::max(1, log2_ceil(value_bound)), bb.big, bb.n_big);
+                     (uint32_t)nb, std::max(1, log2_ceil(value_bound)), bb.big, bb.n_big, heads, head_shift);
   hipLaunchKernelGGL(k_bucket_block_sort, dim3(256), dim3(256), 0, st, ko, vo, bb.count, bb.big, bb.n_big,
-                     bb.pinned_flag);
+                     bb.pinned_flag, heads, head_shift);
   out_k = ko;
   out_v = vo;
   return 0u;
@@ -968,7 +989,10 @@ __global__ void __launch_bounds__(256) k_adder(size_t n, const unsigned long lon
   if constexpr (BLUR) {
     // the window flags past the singles are zero: the k-th non-head hit
     // (k = i - seg[i]) clears position n - 1 - k, so [singles, n) is covered
-    if (i < n && !head) B.wflag[n - 1 - (i - seg[i])] = 0u;
+    if (i < n && !head) {
+      const size_t z = n - 1 - (i - (size_t)seg[i]); // seg[i] <= i: head flags are 0 or 1
+      if (z < n) B.wflag[z] = 0u;
+    }
   }
   if (head) {
     unsigned long long se = 0, sd = 0, tm = ~0ull;
@@ -1008,6 +1032,7 @@ __global__ void __launch_bounds__(256) k_adder(size_t n, const unsigned long lon
 __global__ void __launch_bounds__(1024) k_max_u64(const unsigned long long *v, size_t n, unsigned long long *out) {
   __shared__ unsigned long long s[1024];
   unsigned long long m = 0;
+#pragma unroll 8
   for (size_t i = threadIdx.x; i < n; i += 1024) m = v[i] > m ? v[i] : m;
   s[threadIdx.x] = m;
   __syncthreads();
@@ -1520,14 +1545,19 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const uint32_t *hp = sb.v1;
   const unsigned long long *bk = nullptr;
   const uint32_t *bv = nullptr;
-  // 2. adder: single index of each run = exclusive scan of run heads
+  // 2. adder: single index of each run = exclusive scan of run heads (the
+  //    bucket sort marks them as it writes each bucket: an event's hits share a
+  //    bucket, so no run crosses one)
+  bool heads_done = false;
   auto run_heads = [&]() {
-    hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
+    if (!heads_done) hipLaunchKernelGGL(k_heads, dim3(grid_for(n)), dim3(256), 0, st, n, hk, flag);
+    heads_done = false;
     exclusive_scan(flag, n, sb.scan_tmp, st, rb + 1);
   };
   const bool mapped = bucket_sort<true>(sb, bb, n, n, inst_shift, hit_shift, ev_mask, items, range, st,
                                         sb.scan_tmp, bk, bv, keys_built ? nullptr : &HS,
-                                        keys_built ? nullptr : rb + 12, 2) == 0;
+                                        keys_built ? nullptr : rb + 12, 2, flag, 8) == 0;
+  heads_done = mapped;
   if (mapped) {
     hk = bk;
     hp = bv;
