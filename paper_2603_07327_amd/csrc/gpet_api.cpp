@@ -1047,7 +1047,10 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   if (n > 0x7fffffffull || first + n > 0x100000000ull) return fail(c, GPET_ERR_ARG, "surrogate: event range");
   if (!hits_ok(h)) return fail(c, GPET_ERR_ARG, "surrogate: null hit array");
   (void)hipSetDevice(c->device);
-  constexpr uint64_t kSlice = 32u << 20; // events per transport launch (queue of 2 per event, 72 B each)
+  constexpr uint64_t kSlice = 32u << 20; // most events per transport launch (queue of 2 per event, 72 B each)
+  // equal slices (no short last launch whose tail would leave the chip idle)
+  const uint64_t n_slices = std::max<uint64_t>(1, (n + kSlice - 1) / kSlice);
+  const uint64_t slice = (n + n_slices - 1) / n_slices;
   s = ensure_queue(c, (size_t)2 * std::min<uint64_t>(std::max<uint64_t>(n, 1), kSlice));
   if (s) return s;
   const SurQueue &Q = c->squeue;
@@ -1057,8 +1060,8 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   float ms_t = 0.f, ms_n = 0.f;
   uint64_t entries = 0, none = 0;
   reset_ctrl(c, c->stream);
-  for (uint64_t off = 0; off < n && !s; off += kSlice) {
-    const uint64_t len = std::min(kSlice, n - off);
+  for (uint64_t off = 0; off < n && !s; off += slice) {
+    const uint64_t len = std::min(slice, n - off);
     RunArgs A;
     s = run_args(c, first + off, len, seed, instance, A);
     if (s) break;
