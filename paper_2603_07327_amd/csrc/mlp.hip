@@ -182,16 +182,31 @@ constexpr size_t kNtLds = (size_t)(128 * kNtRowB + 2 * 256 * kLdsRow) * sizeof(u
 // EPI_BIAS_F32_STATS also writes, per row and 128-column block, the maximum
 // of the logits of the columns below n_valid and the sum of their exponentials
 // relative to it: stats[row * gridDim.x + block column] = (max, sum).
+// Blocks go to the 8 XCDs in turn (block L to XCD L mod 8), and each XCD has
+// its own L2: the 1-D grid is mapped so that the column blocks of one 256-row
+// block run on one XCD, one after the other, and its activation rows are
+// fetched from HBM once per XCD instead of once per column block.
+__device__ __forceinline__ void xcd_tile(uint32_t L, uint32_t total, uint32_t nbx, uint32_t &bx, uint32_t &by) {
+  const uint32_t x = L % 8u, slot = L / 8u;
+  uint32_t base = 0; // blocks of the XCDs before x: XCD y has (total + 7 - y) / 8
+  for (uint32_t y = 0; y < x; ++y) base += (total + 7u - y) / 8u;
+  const uint32_t v = base + slot;
+  by = v / nbx;
+  bx = v - by * nbx;
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a, int lda,
                                                  const uint16_t *__restrict__ b, int ldb, int K,
                                                  const float *__restrict__ bias, void *__restrict__ out, int ldc,
-                                                 float2 *__restrict__ stats, int n_valid) {
+                                                 float2 *__restrict__ stats, int n_valid, int nbx) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds_nt[];
   uint16_t *sbw = lds_nt;                   // 128 x kNtRowB weight slab
   uint16_t *sac = lds_nt + 128 * kNtRowB;   // 2 x 256 x kLdsRow activation stages
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * 256, n0 = blockIdx.x * 128;
+  uint32_t bx, by;
+  xcd_tile(blockIdx.x, gridDim.x, (uint32_t)nbx, bx, by);
+  const int m0 = (int)by * 256, n0 = (int)bx * 128;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int kc = K / 8; // 16-byte chunks per row
   for (int t = tid; t < 128 * kc; t += 512) {
@@ -284,7 +299,7 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
           const float m1 = rm[4 * i + qq], s1 = rs[4 * i + qq], m2 = sred[2 * rl], s2 = sred[2 * rl + 1];
           const float M = fmaxf(m1, m2);
           const float S = (m1 > -INFINITY ? s1 * __expf(m1 - M) : 0.0f) + (m2 > -INFINITY ? s2 * __expf(m2 - M) : 0.0f);
-          stats[(size_t)(m0 + rl) * gridDim.x + blockIdx.x] = make_float2(M, S);
+          stats[(size_t)(m0 + rl) * nbx + bx] = make_float2(M, S);
         }
     }
   } else {
@@ -312,8 +327,8 @@ static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, 
                  size_t a_lo = 0, int k_half = 0) {
   if constexpr (!AT && !BT && (EPI == EPI_BIAS_RELU_BF16 || EPI == EPI_BIAS_F32)) {
     if (M % 256 == 0 && N % 128 == 0 && K % kTk == 0 && K <= kNtKmax) {
-      hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3(N / 128, M / 256), dim3(512), kNtLds, st, a, lda, b, ldb, K, bias, out,
-                         ldc, (float2 *)nullptr, 0);
+      hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3((N / 128) * (M / 256)), dim3(512), kNtLds, st, a, lda, b, ldb, K, bias,
+                         out, ldc, (float2 *)nullptr, 0, N / 128);
       return;
     }
   }
@@ -1041,9 +1056,9 @@ void forward_sample(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
                                            nullptr, q->act[l + 1], N, st);
   }
   const int K = q->psize[L - 1], N = q->psize[L];
-  hipLaunchKernelGGL(k_gemm_nt<EPI_BIAS_F32_STATS>, dim3(N / 128, n_pad / 256), dim3(512), kNtLds, st, q->act[L - 1],
-                     K, q->wb[L - 1], K, K, q->bp + (L - 1) * q->bp_stride, (void *)q->logits, N, (float2 *)q->tstats,
-                     q->size[L]);
+  hipLaunchKernelGGL(k_gemm_nt<EPI_BIAS_F32_STATS>, dim3((N / 128) * (n_pad / 256)), dim3(512), kNtLds, st,
+                     q->act[L - 1], K, q->wb[L - 1], K, K, q->bp + (L - 1) * q->bp_stride, (void *)q->logits, N,
+                     (float2 *)q->tstats, q->size[L], N / 128);
 }
 
 // loss of the rows in act[0] / yb and the gradient of the mean loss into gw / gb.
