@@ -628,7 +628,9 @@ __global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *ke
   if (b0 >= nb) return;
   const uint32_t lane = __lane_id();
   const uint32_t nq = min((uint32_t)kWaveBuckets, nb - b0);
-  uint32_t lo = start[b0], hi = start[b0 + 1];
+  // the wave's bucket bounds, start[b0 + j] in lane j <= nq, all loaded at once
+  const uint32_t bound = lane <= nq ? start[b0 + lane] : 0u;
+  uint32_t lo = __shfl(bound, 0), hi = __shfl(bound, 1);
   unsigned long long k[2];
   uint32_t v[2];
   wave_load_bucket(key, val, lo, hi - lo, k, v);
@@ -638,7 +640,7 @@ __global__ void __launch_bounds__(256) k_bucket_wave_sort(unsigned long long *ke
     unsigned long long kn[2] = {~0ull, ~0ull};
     uint32_t vn[2] = {~0u, ~0u};
     if (q + 1 < nq) {
-      nhi = start[b0 + q + 2];
+      nhi = __shfl(bound, (int)q + 2);
       wave_load_bucket(key, val, hi, nhi - hi, kn, vn);
     }
     const uint32_t size = hi - lo;
@@ -969,6 +971,15 @@ __global__ void __launch_bounds__(256) k_blur(size_t n, const uint32_t *s_ev, ui
 // event and crystal come out of the key.  e/d/t are the hits' energy, depth
 // and time, indexed by perm.  BLUR: the blur stage of each single runs here
 // too (crystal readout), so the singles are read back by no separate pass.
+// Thread t of block g takes positions g 256 kAdderR + r 256 + t, r <
+// kAdderR.  Every position's key, run index, hit index and that hit's
+// payload are loaded before any run is summed (two dependent loads deep), so
+// a single of one hit -- most of them -- needs nothing more; a run's further
+// hits are loaded by its head.
+constexpr int kAdderR = 4;
+
+static inline unsigned adder_grid(size_t n) { return (unsigned)((n + 256 * kAdderR - 1) / (256 * kAdderR)); }
+
 template <bool BLUR>
 __global__ void __launch_bounds__(256) k_adder(size_t n, const unsigned long long *key, const uint32_t *perm,
                                                const uint32_t *seg, const float *edep, const float *depth,
@@ -977,49 +988,82 @@ __global__ void __launch_bounds__(256) k_adder(size_t n, const unsigned long lon
                                                uint32_t *s_gid, float *s_edep, float *s_depth,
                                                unsigned long long *s_time, uint32_t *s_inst_int,
                                                uint32_t *s_inst_out, uint64_t cap, BlurArgs B) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int R = kAdderR;
+  const uint32_t lane = __lane_id();
+  const size_t base = (size_t)blockIdx.x * blockDim.x * R + threadIdx.x;
+  size_t i[R];
+  unsigned long long k[R];
+  uint32_t sg[R], h[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    i[r] = base + (size_t)r * blockDim.x;
+    const bool in = i[r] < n;
+    k[r] = in ? key[i[r]] : ~0ull;
+    sg[r] = in ? seg[i[r]] : 0u;
+    h[r] = in ? perm[i[r]] : 0u;
+  }
+  float e[R], d[R];
+  unsigned long long t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool in = i[r] < n;
+    e[r] = in ? edep[h[r]] : 0.0f;
+    d[r] = in ? depth[h[r]] : 0.0f;
+    t[r] = in ? time[h[r]] : 0ull;
+  }
   unsigned long long tmax = 0;
-  bool head = false;
-  unsigned long long k = 0, run = 0;
-  if (i < n) {
-    k = key[i];
-    run = k >> 8;
-    head = i == 0 || (key[i - 1] >> 8) != run;
-  }
-  if constexpr (BLUR) {
-    // the window flags past the singles are zero: the k-th non-head hit
-    // (k = i - seg[i]) clears position n - 1 - k, so [singles, n) is covered
-    if (i < n && !head) {
-      const size_t z = n - 1 - (i - (size_t)seg[i]); // seg[i] <= i: head flags are 0 or 1
-      if (z < n) B.wflag[z] = 0u;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    // the keys before and after this position: the neighbouring lanes', or
+    // loaded at the wave's edges
+    unsigned long long kprev = ((unsigned long long)__shfl_up((uint32_t)(k[r] >> 32), 1) << 32) |
+                               __shfl_up((uint32_t)k[r], 1);
+    unsigned long long knext = ((unsigned long long)__shfl_down((uint32_t)(k[r] >> 32), 1) << 32) |
+                               __shfl_down((uint32_t)k[r], 1);
+    const size_t ir = i[r];
+    if (ir >= n) continue;
+    if (lane == 0 && ir > 0) kprev = key[ir - 1];
+    if (lane == 63 || ir + 1 >= n) knext = ir + 1 < n ? key[ir + 1] : ~0ull;
+    const unsigned long long run = k[r] >> 8;
+    const bool head = ir == 0 || (kprev >> 8) != run;
+    if constexpr (BLUR) {
+      // the window flags past the singles are zero: the k-th non-head hit
+      // (k = i - seg[i]) clears position n - 1 - k, so [singles, n) is covered
+      if (!head) {
+        const size_t z = n - 1 - (ir - (size_t)sg[r]); // seg[i] <= i: head flags are 0 or 1
+        if (z < n) B.wflag[z] = 0u;
+      }
     }
-  }
-  if (head) {
-    unsigned long long se = 0, sd = 0, tm = ~0ull;
-    size_t j = i;
-    do {
-      const uint32_t h = perm[j];
-      const float e = edep[h];
-      se += (unsigned long long)(e * 4294967296.0f);
-      sd += (unsigned long long)((e * depth[h]) * 4294967296.0f);
-      tm = min(tm, time[h]);
-      ++j;
-    } while (j < n && (key[j] >> 8) == run);
-    const uint32_t s = seg[i];
+    if (!head) continue;
+    unsigned long long se = (unsigned long long)(e[r] * 4294967296.0f);
+    unsigned long long sd = (unsigned long long)((e[r] * d[r]) * 4294967296.0f);
+    unsigned long long tm = t[r];
+    if (ir + 1 < n && (knext >> 8) == run) { // further hits of the run
+      size_t j = ir + 1;
+      do {
+        const uint32_t hj = perm[j];
+        const float ej = edep[hj];
+        se += (unsigned long long)(ej * 4294967296.0f);
+        sd += (unsigned long long)((ej * depth[hj]) * 4294967296.0f);
+        tm = min(tm, time[hj]);
+        ++j;
+      } while (j < n && (key[j] >> 8) == run);
+    }
+    const uint32_t s = sg[r];
     if (s < cap) {
       const double E = (double)se * 0x1p-32;
-      const uint32_t in = inst_shift < 64 ? (uint32_t)(k >> inst_shift) : 0u;
-      const uint32_t ev = T.first[in] + (uint32_t)((run >> gid_bits) & ev_mask);
+      const uint32_t inst = inst_shift < 64 ? (uint32_t)(k[r] >> inst_shift) : 0u;
+      const uint32_t ev = T.first[inst] + (uint32_t)((run >> gid_bits) & ev_mask);
       uint32_t gid = (uint32_t)(run & ((1ull << gid_bits) - 1));
       const float e_sum = (float)E;
       float dep = se ? (float)((double)sd / (double)se) : 0.0f;
       s_ev[s] = ev;
       s_edep[s] = e_sum;
-      s_inst_int[s] = in;
-      if (s_inst_out) s_inst_out[s] = in;
+      s_inst_int[s] = inst;
+      if (s_inst_out) s_inst_out[s] = inst;
       if constexpr (BLUR) {
-        blur_single(B, T, s, in, ev, gid, e_sum, tm, dep);
-        tmax = tm;
+        blur_single(B, T, s, inst, ev, gid, e_sum, tm, dep);
+        tmax = tm > tmax ? tm : tmax;
       }
       s_gid[s] = gid;
       s_depth[s] = dep;
@@ -1619,11 +1663,11 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
               wpos, (unsigned long long *)sb.hist}; // the radix histogram is free until the time sort
   auto launch_adder = [&]() {
     if (fuse_blur)
-      hipLaunchKernelGGL(k_adder<true>, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth,
+      hipLaunchKernelGGL(k_adder<true>, dim3(adder_grid(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth,
                          D.h_time, IT, D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
                          s_time, s_inst, S->instance, S->capacity, BA);
     else
-      hipLaunchKernelGGL(k_adder<false>, dim3(grid_for(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth,
+      hipLaunchKernelGGL(k_adder<false>, dim3(adder_grid(n)), dim3(256), 0, st, n, hk, hp, flag, D.h_edep, D.h_depth,
                          D.h_time, IT, D.gid_bits, ev_mask, inst_shift, S->event, S->gid, S->edep_kev, S->depth_mm,
                          s_time, s_inst, S->instance, S->capacity, BA);
   };
@@ -1653,7 +1697,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
                        S->edep_kev, s_time, S->depth_mm, BA);
   auto reduce_max = [&]() {
     hipLaunchKernelGGL(k_max_u64, dim3(1), dim3(1024), 0, st, (const unsigned long long *)BA.block_max,
-                       (size_t)(fuse_blur ? grid_for(n) : grid_for(ns)), (unsigned long long *)(rb + 4));
+                       (size_t)(fuse_blur ? adder_grid(n) : grid_for(ns)), (unsigned long long *)(rb + 4));
   };
   reduce_max();
   if (dead) {
