@@ -549,8 +549,9 @@ gpet_status gpet_surrogate_pairs(gpet_ctx *ctx, const gpet_surrogate_spec *spec,
  * factored network); every other photon is transported in full.  The
  * network must map 6 features to the spec's class count for this scanner
  * (factored: n_ebins + 2 energy classes and n_layers (2 H + 1)^2 positions
- * per block, at most 2048: GPET_ERR_UNSUPPORTED beyond).  Hits as gpet_transport (surrogate singles carry process 3 in
- * aux). */
+ * per block, with n_layers ceil((2 H + 1)^2 / 64) at most 32:
+ * GPET_ERR_UNSUPPORTED beyond).  Hits as gpet_transport (surrogate singles
+ * carry process 3 in aux). */
 gpet_status gpet_surrogate_transport(gpet_ctx *ctx, gpet_mlp *mlp, const gpet_surrogate_spec *spec,
                                      uint64_t first_event, uint64_t n_events, uint64_t seed, uint32_t instance,
                                      gpet_hits *hits, gpet_stats *stats, gpet_surrogate_stats *sstats);

@@ -1031,8 +1031,9 @@ gpet_status gpet_surrogate_transport(gpet_ctx *c, gpet_mlp *q, const gpet_surrog
   if (!q || q->ctx != c) return fail(c, GPET_ERR_ARG, "surrogate: network missing or made on another context");
   if (q->n_first) {
     const int W = 2 * P.chalf + 1;
-    if (q->n_second > 2048)
-      return fail(c, GPET_ERR_UNSUPPORTED, "surrogate: at most 2048 positions per block (layers x (2 H + 1)^2)");
+    if (c->scene.n_layers * ((W * W + 63) / 64) > 32)
+      return fail(c, GPET_ERR_UNSUPPORTED,
+                  "surrogate: at most 32 chunks of 64 positions per block (layers x ceil((2 H + 1)^2 / 64))");
     if (q->size[0] != 6 || q->n_first != spec->n_ebins + 2 || q->n_second != c->scene.n_layers * W * W)
       return fail(c, GPET_ERR_ARG, "surrogate: a factored network must map 6 features to " +
                                        std::to_string(spec->n_ebins + 2) + " energy classes and " +

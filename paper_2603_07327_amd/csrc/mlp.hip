@@ -562,19 +562,42 @@ __global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int
 // positions that exist (inside their layer's array around the entry's
 // anchors) reaches u2 * total (word 2).  cls = the joint label.
 //
-// One pass over the position logits (n2 <= 64 B): chunk k of 64 positions is
-// loaded coalesced, position k 64 + lane into lane's register v[k] (masked
-// where the position does not exist); the chunk totals and their running sum
-// in natural order find the chunk, one wave prefix sum inside it the
-// position, so the draw is the natural-order inverse CDF (its sums rounded in
-// that order).
+// The positions of layer l (W^2 of them, W = 2H + 1) sit in C = ceil(W^2 / 64)
+// chunks of 64 of their own, so a chunk never straddles two layers: chunk
+// l C + q holds positions l W^2 + 64 q + lane (none past W^2).  A chunk's
+// layer, anchors and first crystal offset are then the same for the whole
+// wave (scalar registers), and a lane's offset (dt, da) is that first offset
+// plus the lane's own, with one carry.  Chunk q of layer l goes to register
+// l C + q of every lane; the chunk totals are reduced over the lanes by
+// halving exchanges (each level keeps half of the chunks per lane and adds the
+// partner's copy of that half), so lane t ends with the total of chunk
+// t >> (6 - log2 P) (P = B rounded up to a power of two); a wave scan of the
+// totals in chunk order picks the chunk, one wave prefix sum inside it the
+// position: the draw is the natural-order inverse CDF.
+// x[i] for the lanes whose bit s is clear, x[i + h] for the others, plus the
+// partner lane's (lane ^ s) copy of the same element
+__device__ __forceinline__ float halve_pair(float lo, float hi, int s) {
+  const bool up = (__lane_id() & (uint32_t)s) != 0u;
+  if (s == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return up ? hi + __uint_as_float(r[0]) : lo + __uint_as_float(r[1]);
+  }
+  if (s == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return up ? hi + __uint_as_float(r[0]) : lo + __uint_as_float(r[1]);
+  }
+  return (up ? hi : lo) + lane_xor_f(up ? lo : hi, s);
+}
+
 template <int B>
 __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz, int n1, int n2, int G,
                                                          const float *T, uint32_t n, const uint32_t *ev,
                                                          const uint32_t *meta, const uint32_t *anchor,
                                                          const DevScene *S, int H, uint32_t k0, uint32_t k1,
                                                          uint32_t inst_rng, uint32_t *cls, uint32_t *nonzero) {
-  const uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  constexpr int P = B <= 8 ? 8 : B <= 16 ? 16 : 32; // chunks rounded up to a power of two
+  constexpr int KP = P == 8 ? 3 : P == 16 ? 4 : 5;  // its log2
+  const uint32_t r = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
   // the loads that do not wait for the energy class go out first (a wave is
@@ -585,13 +608,52 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
   const uint32_t mt = meta[r], evr = ev[r];
   const float v1 = lane < n1 ? zr[lane] : -INFINITY;
   const int nl = S->n_layers;
-  uint32_t aw[kMaxLayers];
+  int nt[kMaxLayers], na[kMaxLayers], at[kMaxLayers], aa[kMaxLayers];
 #pragma unroll
-  for (int q = 0; q < kMaxLayers; ++q) aw[q] = q < nl ? anchor[(size_t)kMaxLayers * r + q] : 0u;
+  for (int q = 0; q < kMaxLayers; ++q) {
+    const bool on = q < nl;
+    const uint32_t aw = on ? anchor[(size_t)kMaxLayers * r + q] : 0u;
+    nt[q] = on ? S->layer[q].n_t : 0;
+    na[q] = on ? S->layer[q].n_a : 0;
+    at[q] = (int)(aw & 0xFFFFu) - H;
+    aa[q] = (int)(aw >> 16) - H;
+  }
+  const int W = 2 * H + 1, WW = W * W, C = (WW + 63) / 64;
+  // offset (dt, da) of in-layer position p: dt = floor((p + 1/2) / W) in
+  // FP32, exact for p < 2^11 and W <= 64 (the rounding error stays below 1/(2W))
+  const float inv_w = 1.0f / (float)W;
   const bool early = G == 1;
-  float zp[B];
+  // chunk c: its positions' indices j[c] and whether each exists (ok[c])
+  uint32_t j[B];
+  bool ok[B];
+  float zp[B]; // with one position block: the position logits
+  {
+    // chunk c: layer L (its anchors and sizes in atL, aaL, ntL, naL; the
+    // layers after it queued behind), chunk q of it
+    int L = 0, q = 0;
+    int atL = at[0], aaL = aa[0], ntL = nt[0], naL = na[0];
+    int at1 = at[1], aa1 = aa[1], nt1 = nt[1], na1 = na[1];
+    int at2 = at[2], aa2 = aa[2], nt2 = nt[2], na2 = na[2];
+    int at3 = at[3], aa3 = aa[3], nt3 = nt[3], na3 = na[3];
+    static_assert(kMaxLayers == 4, "the layer queue holds four layers");
 #pragma unroll
-  for (int c = 0; c < B; ++c) zp[c] = early && c * 64 + lane < n2 ? zr[n1 + c * 64 + lane] : 0.f;
+    for (int c = 0; c < B; ++c) {
+      const uint32_t p = (uint32_t)(q * 64 + lane);
+      const int dt = (int)(((float)p + 0.5f) * inv_w);
+      const int da = (int)p - __mul24(dt, W);
+      const bool in = L < nl && p < (uint32_t)WW;
+      ok[c] = in & ((uint32_t)(atL + dt) < (uint32_t)ntL) & ((uint32_t)(aaL + da) < (uint32_t)naL);
+      j[c] = ok[c] ? (uint32_t)(L * WW) + p : 0u; // (position 0 stands in for none: every load is in the row)
+      zp[c] = early ? zr[n1 + j[c]] : 0.f;
+      if (++q == C) {
+        q = 0;
+        ++L;
+        atL = at1, aaL = aa1, ntL = nt1, naL = na1;
+        at1 = at2, aa1 = aa2, nt1 = nt2, na1 = na2;
+        at2 = at3, aa2 = aa3, nt2 = nt3, na2 = na3;
+      }
+    }
+  }
   if (mt == kQueueHole) { // an empty queue slot
     if (lane == 0) {
       cls[r] = 0u;
@@ -621,91 +683,77 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
     }
     return;
   }
-  // layer sizes and this entry's anchors (at most kMaxLayers), selected by value
-  int nt[kMaxLayers], na[kMaxLayers], at[kMaxLayers], aa[kMaxLayers];
-#pragma unroll
-  for (int q = 0; q < kMaxLayers; ++q) {
-    const bool on = q < nl;
-    nt[q] = on ? S->layer[q].n_t : 0;
-    na[q] = on ? S->layer[q].n_a : 0;
-    at[q] = (int)(aw[q] & 0xFFFFu) - H;
-    aa[q] = (int)(aw[q] >> 16) - H;
-  }
   const float *z2 = zr + position_block(e, n1, n2, G);
   const float *t = T + (size_t)(e - 1) * n2;
-  const int W = 2 * H + 1, WW = W * W;
-  // (layer, t offset, a offset) of position lane, then stepped by 64
-  int l = lane / WW, rr = lane - l * WW;
-  int dt = rr / W, da = rr - dt * W;
+  // (two loops: a select between the registers and a load would move the
+  // registers to memory)
   float v[B];
+  if (early) {
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] = zp[c] + t[j[c]];
+  } else {
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] = z2[j[c]] + t[j[c]];
+  }
   float m = -INFINITY;
 #pragma unroll
   for (int c = 0; c < B; ++c) {
-    const int j = c * 64 + lane;
-    int ntl = nt[0], nal = na[0], atl = at[0], aal = aa[0];
-#pragma unroll
-    for (int q = 1; q < kMaxLayers; ++q)
-      if (l == q) {
-        ntl = nt[q];
-        nal = na[q];
-        atl = at[q];
-        aal = aa[q];
-      }
-    const int it = atl + dt, ia = aal + da;
-    const bool ok = j < n2 && it >= 0 && it < ntl && ia >= 0 && ia < nal;
-    v[c] = ok ? (early ? zp[c] : z2[j]) + t[j] : -INFINITY;
+    v[c] = ok[c] ? v[c] : -INFINITY;
     m = fmaxf(m, v[c]);
-    da += 64; // next chunk: position + 64
-    while (da >= W) {
-      da -= W;
-      if (++dt == W) {
-        dt = 0;
-        ++l;
-      }
-    }
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) m = fmaxf(m, lane_xor_f(m, o));
-  // chunk totals: B independent butterfly sums on the DPP / permlane paths
-  // (every lane ends with all of them), then the running sum over the chunks
-  // in natural order picks the chunk, and one wave prefix sum inside it the
-  // position -- a single LDS-crossbar scan per entry instead of one per chunk
-  float tot[B];
+  float x[P];
 #pragma unroll
-  for (int c = 0; c < B; ++c) {
-    v[c] = v[c] > -INFINITY ? __expf(v[c] - m) : 0.f;
-    tot[c] = v[c];
+  for (int c = 0; c < P; ++c) {
+    if (c < B) v[c] = ok[c] ? __expf(v[c] - m) : 0.f;
+    x[c] = c < B ? v[c] : 0.f;
   }
+  // chunk totals: halving exchanges over the top KP lane bits, then plain
+  // butterflies over the rest; lane t holds the total of chunk t >> (6 - KP)
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1)
+  for (int h = P / 2, s = 32; h >= 1; h >>= 1, s >>= 1)
 #pragma unroll
-    for (int c = 0; c < B; ++c) tot[c] += lane_xor_f(tot[c], o);
-  float sl = 0.f;
+    for (int i = 0; i < h; ++i) x[i] = halve_pair(x[i], x[i + h], s);
 #pragma unroll
-  for (int c = 0; c < B; ++c) sl += tot[c];
+  for (int s = 32 >> KP; s >= 1; s >>= 1) x[0] += lane_xor_f(x[0], s);
+  constexpr int kGroup = 64 >> KP; // lanes per chunk total
+  const int chunk = lane / kGroup;
+  // running sum of the totals in chunk order (one lane per chunk counts)
+  float run = (lane % kGroup) == 0 && chunk < B ? x[0] : 0.f;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float tt = __shfl_up(run, o);
+    if (lane >= o) run += tt;
+  }
+  const float sl = __shfl(run, 63);
   const float target2 = to_unit(w.z) * sl;
-  int cs = -1;      // the chunk whose running sum first reaches the target
-  float carry = 0.f; // the running sum before it
-  float vc = 0.f;    // this lane's value in it
-#pragma unroll
-  for (int c = 0; c < B; ++c) {
-    const bool here = cs < 0 && carry + tot[c] >= target2;
-    vc = here ? v[c] : vc;
-    if (cs < 0) {
-      if (here) cs = c;
-      else carry += tot[c];
-    }
-  }
+  // (a chunk without mass cannot hold the draw, even when the target is 0)
+  const uint64_t reach = __ballot((lane % kGroup) == 0 && chunk < B && x[0] > 0.f && run >= target2);
   int k;
-  if (cs < 0) { // rounding left the target beyond the total: the last position that exists
+  if (!reach) { // rounding left the target beyond the total: the last position that exists
     int last = -1;
 #pragma unroll
     for (int c = 0; c < B; ++c)
-      if (v[c] > 0.f) last = c * 64 + lane;
+      if (v[c] > 0.f) last = (int)j[c];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) last = max(last, (int)lane_xor((uint32_t)last, o));
     k = last;
   } else {
+    const int cs = (__ffsll((unsigned long long)reach) - 1) / kGroup; // the chunk
+    const float carry = cs > 0 ? __shfl(run, cs * kGroup - 1) : 0.f; // the running sum before it
+    // its values: the first chunk whose bit is set in `reach` (a test of the
+    // mask itself, not of an index, which keeps the chunks in registers)
+    float vc = 0.f;
+    uint32_t jc = 0;
+    bool found = false;
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      const bool here = !found && ((reach >> (c * kGroup)) & 1u);
+      vc = here ? v[c] : vc;
+      jc = here ? j[c] : jc;
+      found = found || here;
+    }
     float in2 = vc;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -715,7 +763,8 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
     const uint64_t cr = __ballot(carry + in2 >= target2 && vc > 0.f);
     const uint64_t ex = __ballot(vc > 0.f);
     // (rounding inside the chunk: its last position that exists)
-    k = cs * 64 + (cr ? __ffsll((unsigned long long)cr) - 1 : 63 - __clzll((long long)ex));
+    const int kl = cr ? __ffsll((unsigned long long)cr) - 1 : 63 - __clzll((long long)ex);
+    k = (int)__shfl(jc, kl);
   }
   if (lane == 0) {
     cls[r] = 1u + (uint32_t)k * (uint32_t)(n1 - 1) + (uint32_t)(e - 1);
@@ -1144,16 +1193,19 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
       const float *T = q->master + q->tab_off;
       const uint32_t *an = Q.anchor + (size_t)kMaxLayers * off;
       const int n2 = q->n_second;
-      // the positions in registers: B chunks of 64, B the smallest of 8, 20, 32 that holds them
-      if (n2 <= 64 * 8)
+      // the positions in registers: each layer's W^2 in chunks of 64 of their
+      // own, B the smallest of 8, 20, 32 that holds them all
+      const int WW = (2 * P.chalf + 1) * (2 * P.chalf + 1);
+      const int chunks = n2 / WW * ((WW + 63) / 64);
+      if (chunks <= 8)
         hipLaunchKernelGGL(k_sample_factored<8>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
                            q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
                            Q.cls + off, Q.pos + off);
-      else if (n2 <= 64 * 20)
+      else if (chunks <= 20)
         hipLaunchKernelGGL(k_sample_factored<20>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
                            q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
                            Q.cls + off, Q.pos + off);
-      else // at most 64 x 32 positions (checked by the caller)
+      else // at most 32 chunks (checked by the caller)
         hipLaunchKernelGGL(k_sample_factored<32>, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, q->n_first, n2,
                            q->n_groups, T, n, Q.ev + off, Q.meta + off, an, d_scene, P.chalf, k0, k1, inst_rng,
                            Q.cls + off, Q.pos + off);
