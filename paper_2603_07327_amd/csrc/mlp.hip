@@ -574,18 +574,27 @@ __global__ void k_table_grad_part(const uint16_t *dz, size_t dz_lo, int ldz, int
 // t >> (6 - log2 P) (P = B rounded up to a power of two); a wave scan of the
 // totals in chunk order picks the chunk, one wave prefix sum inside it the
 // position: the draw is the natural-order inverse CDF.
-// x[i] for the lanes whose bit s is clear, x[i + h] for the others, plus the
-// partner lane's (lane ^ s) copy of the same element
+// base[i] through a 32-bit byte offset (i < 2^30), so that the load takes the
+// wave-uniform base from scalar registers and the offset alone per lane
+__device__ __forceinline__ float load_at(const float *base, uint32_t i) {
+  return *(const float *)((const char *)base + (i << 2));
+}
+
+// lo for the lanes whose bit s is clear, hi for the others, plus the partner
+// lane's (lane ^ s) copy of the same element.  For s = 32 (16) the swap of the
+// upper half-wave (odd rows) of lo with the lower half-wave (even rows) of hi
+// leaves each lane one register with its own kept value and one with its
+// partner's, so their sum is the result.
 __device__ __forceinline__ float halve_pair(float lo, float hi, int s) {
-  const bool up = (__lane_id() & (uint32_t)s) != 0u;
   if (s == 32) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
-    return up ? hi + __uint_as_float(r[0]) : lo + __uint_as_float(r[1]);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
   if (s == 16) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
-    return up ? hi + __uint_as_float(r[0]) : lo + __uint_as_float(r[1]);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
+  const bool up = (__lane_id() & (uint32_t)s) != 0u;
   return (up ? hi : lo) + lane_xor_f(up ? lo : hi, s);
 }
 
@@ -644,7 +653,7 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
       const bool in = L < nl && p < (uint32_t)WW;
       ok[c] = in & ((uint32_t)(atL + dt) < (uint32_t)ntL) & ((uint32_t)(aaL + da) < (uint32_t)naL);
       j[c] = ok[c] ? (uint32_t)(L * WW) + p : 0u; // (position 0 stands in for none: every load is in the row)
-      zp[c] = early ? zr[n1 + j[c]] : 0.f;
+      zp[c] = early ? load_at(zr, (uint32_t)n1 + j[c]) : 0.f;
       if (++q == C) {
         q = 0;
         ++L;
@@ -690,10 +699,10 @@ __global__ void __launch_bounds__(256) k_sample_factored(const float *z, int ldz
   float v[B];
   if (early) {
 #pragma unroll
-    for (int c = 0; c < B; ++c) v[c] = zp[c] + t[j[c]];
+    for (int c = 0; c < B; ++c) v[c] = zp[c] + load_at(t, j[c]);
   } else {
 #pragma unroll
-    for (int c = 0; c < B; ++c) v[c] = z2[j[c]] + t[j[c]];
+    for (int c = 0; c < B; ++c) v[c] = load_at(z2, j[c]) + load_at(t, j[c]);
   }
   float m = -INFINITY;
 #pragma unroll
