@@ -318,6 +318,102 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
   }
 }
 
+// The hidden layers of an inference pass in one kernel, for networks whose
+// hidden widths are all 256 (input width <= 256): a block of 128 rows keeps
+// its activations in LDS from the network input to the last hidden layer and
+// streams each layer's weights through a double-buffered 256 x 32 stage.  A
+// wave computes a 32 x 128 tile.  Every layer's products, bias, ReLU and BF16
+// rounding are those of the layer-by-layer products (same operand fragments,
+// same K order), so the result is bit-identical to them; only the last hidden
+// layer's activations go back to HBM.
+constexpr int kStackRows = 128;
+constexpr int kStackWidth = 256;
+constexpr int kStackRowA = kStackWidth + 8; // bf16 per activation row in LDS
+constexpr int kStackMax = 8;                // hidden layers
+constexpr size_t kStackLds = (size_t)(kStackRows * kStackRowA + 2 * kStackWidth * kLdsRow) * sizeof(uint16_t);
+
+struct StackArgs {
+  const uint16_t *w[kStackMax]; // layer l's weights [256][k[l]] (K-contiguous)
+  const float *bias[kStackMax];
+  int k[kStackMax];             // layer l's input width: a multiple of 32, at most 256
+  int n;                        // hidden layers
+};
+
+__global__ void __launch_bounds__(512) k_mlp_stack(const uint16_t *__restrict__ in, StackArgs P,
+                                                   uint16_t *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_stack[];
+  uint16_t *sa = lds_stack;                            // kStackRows x kStackRowA activations
+  uint16_t *sw = lds_stack + kStackRows * kStackRowA;  // 2 x 256 x kLdsRow weight stages
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t m0 = (size_t)blockIdx.x * kStackRows;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 128;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int cn = lane & 15, rb4 = (lane >> 4) * 4;
+  {
+    const int kc = P.k[0] / 8; // 16-byte chunks per input row
+    for (int t = tid; t < kStackRows * kc; t += 512) {
+      const int r = t / kc, c = (t - r * kc) * 8;
+      *(uint4 *)&sa[r * kStackRowA + c] = *(const uint4 *)&in[(m0 + r) * P.k[0] + c];
+    }
+  }
+  // thread t moves column t >> 1, half t & 1 (16 bf16) of each 32-wide weight chunk
+  const int wc = tid >> 1, wh = (tid & 1) * 16;
+  for (int l = 0; l < P.n; ++l) {
+    const int K = P.k[l];
+    const uint16_t *wrow = P.w[l] + (size_t)wc * K + wh;
+    uint4 w0 = *(const uint4 *)wrow, w1 = *(const uint4 *)(wrow + 8);
+    *(uint4 *)&sw[wc * kLdsRow + wh] = w0;
+    *(uint4 *)&sw[wc * kLdsRow + wh + 8] = w1;
+    __syncthreads(); // (also: the previous layer's activations are all in sa)
+    floatx4 acc[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int q = 0;
+    for (int k0 = 0; k0 < K; k0 += kTk) {
+      const bool more = k0 + kTk < K;
+      if (more) {
+        w0 = *(const uint4 *)(wrow + k0 + kTk);
+        w1 = *(const uint4 *)(wrow + k0 + kTk + 8);
+      }
+      const uint16_t *s = sw + q * kStackWidth * kLdsRow;
+      bf16x8 fa[2], fb[8];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        fa[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sa[(wm + 16 * i + fr) * kStackRowA + k0 + fk]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) fb[j] = __builtin_bit_cast(bf16x8, *(const uint4 *)&s[(wn + 16 * j + fr) * kLdsRow + fk]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      if (more) {
+        uint16_t *sn = sw + (q ^ 1) * kStackWidth * kLdsRow;
+        *(uint4 *)&sn[wc * kLdsRow + wh] = w0;
+        *(uint4 *)&sn[wc * kLdsRow + wh + 8] = w1;
+      }
+      __syncthreads(); // (after the last step: every wave has read sa for this layer)
+      q ^= 1;
+    }
+    const float *bias = P.bias[l];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = wn + 16 * j + cn;
+      const float b = bias[n];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) sa[(wm + 16 * i + rb4 + qq) * kStackRowA + n] = f2bf(fmaxf(acc[i][j][qq] + b, 0.0f));
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < kStackRows * (kStackWidth / 8); t += 512) {
+    const int r = t / (kStackWidth / 8), c = (t - r * (kStackWidth / 8)) * 8;
+    *(uint4 *)&out[(m0 + r) * kStackWidth + c] = *(const uint4 *)&sa[r * kStackRowA + c];
+  }
+}
+
 // 128 x 128 tiles where both sizes allow them (the wide layers), else 64 x 64;
 // `splits` K slices (K / splits a multiple of 32), partial products
 // split_stride elements apart
@@ -1103,6 +1199,30 @@ void forward(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
   }
 }
 
+// forward pass for inference (no activations kept for a backward pass): the
+// hidden layers in one kernel where the widths allow it, else layer by layer
+void forward_infer(gpet_mlp *q, uint32_t n_pad, hipStream_t st) {
+  const int L = q->n_layers;
+  bool stack = L >= 2 && L - 1 <= kStackMax && n_pad % kStackRows == 0 && q->psize[0] % kTk == 0 &&
+               q->psize[0] <= kStackWidth;
+  for (int l = 1; l < L; ++l) stack = stack && q->psize[l] == kStackWidth;
+  if (!stack) {
+    forward(q, n_pad, st);
+    return;
+  }
+  StackArgs P{};
+  for (int l = 0; l + 1 < L; ++l) {
+    P.w[l] = q->wb[l];
+    P.bias[l] = q->bp + l * q->bp_stride;
+    P.k[l] = q->psize[l];
+  }
+  P.n = L - 1;
+  hipLaunchKernelGGL(k_mlp_stack, dim3(n_pad / kStackRows), dim3(512), kStackLds, st, q->act[0], P, q->act[L - 1]);
+  const int K = q->psize[L - 1], N = q->psize[L];
+  gemm<false, false, EPI_BIAS_F32>(q->act[L - 1], K, q->wb[L - 1], K, (int)n_pad, N, K, q->bp + (L - 1) * q->bp_stride,
+                                   nullptr, q->logits, N, st);
+}
+
 // forward pass for sampling: the last product also leaves per-tile row
 // statistics in q->tstats (the forward product kernel always applies: rows
 // padded to 256, widths to 128, K <= 256 for the hidden layers)
@@ -1198,7 +1318,7 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
                        (const int32_t *)nullptr, (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad,
                        q->act[0], (int32_t *)nullptr);
     if (q->n_first) {
-      forward(q, n_pad, st);
+      forward_infer(q, n_pad, st);
       const float *T = q->master + q->tab_off;
       const uint32_t *an = Q.anchor + (size_t)kMaxLayers * off;
       const int n2 = q->n_second;
@@ -1223,7 +1343,7 @@ int gpet::surrogate_hits(gpet_mlp *q, const DevScene *d_scene, const SurSpecD &P
       hipLaunchKernelGGL(k_sample_tiles, dim3(cdiv(n, 4)), dim3(256), 0, st, (const float2 *)q->tstats, Cp / 128,
                          q->logits, Cp, C, n, Q.ev + off, Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
     } else {
-      forward(q, n_pad, st);
+      forward_infer(q, n_pad, st);
       hipLaunchKernelGGL(k_sample_classes, dim3(cdiv(n, 4)), dim3(256), 0, st, q->logits, Cp, C, n, Q.ev + off,
                          Q.meta + off, k0, k1, inst_rng, Q.cls + off, Q.pos + off);
     }
@@ -1416,7 +1536,7 @@ gpet_status gpet_mlp_forward(gpet_mlp *q, uint32_t n, const float *x, float *log
   const uint32_t n_pad = (uint32_t)pad_to((int)n, kRowPad);
   hipLaunchKernelGGL(k_pack_input, dim3(cdiv(n_pad, 8)), dim3(32, 8), 0, st, x, (const int32_t *)nullptr,
                      (const uint32_t *)nullptr, n, q->size[0], q->psize[0], n_pad, q->act[0], (int32_t *)nullptr);
-  forward(q, n_pad, st);
+  forward_infer(q, n_pad, st);
   const int C = q->size[q->n_layers], Cp = q->psize[q->n_layers];
   if (hipMemcpy2DAsync(logits, (size_t)C * 4, q->logits, (size_t)Cp * 4, (size_t)C * 4, n, hipMemcpyDeviceToDevice,
                        st) != hipSuccess ||

@@ -43,6 +43,32 @@ def test_single_layer_forward_matches_fp64(ctx, k, n, rows):
     m.close()
 
 
+@pytest.mark.parametrize("sizes", [[6, 256, 256, 256, 256, 300], [6, 128, 256, 300]])
+def test_deep_forward_matches_fp64(ctx, sizes):
+    """A whole network through the inference forward pass (with hidden widths
+    of 256 the hidden layers run as one kernel with the activations kept on
+    chip; other widths layer by layer): logits against the FP64 pass over
+    the same BF16 weights with every hidden activation rounded to BF16 as it
+    is stored, relative to each row's scale.  An FP32 sum now and then rounds
+    an activation to the neighbouring BF16 value (about one in 250 where a
+    sum of 256 terms cancels), and each layer spreads that step, so the
+    bound is on the distribution: mean below 2e-5, 99.9th percentile below
+    5e-3, every element below 5e-2 (a wrong row, column or K step moves the
+    mean by orders of magnitude).  1000 rows span several row blocks and a
+    ragged last one."""
+    from paper_2603_07327_amd.gpet import Mlp, pack_params
+    rng = np.random.default_rng(len(sizes))
+    P = [(W, rng.normal(0, 0.1, b.shape).astype(np.float32)) for W, b in G.mlp_init(sizes, seed=5)]
+    x = rng.normal(0, 1, (1000, sizes[0])).astype(np.float32)
+    m = Mlp(ctx, sizes, pack_params(P))
+    got = m.forward(x)
+    ref = S.forward([(S.bf16_round(W), b.astype(np.float64)) for W, b in P], S.bf16_round(x), store=S.bf16_round)[0]
+    scale = np.sqrt((ref ** 2).mean(1, keepdims=True))
+    e = np.abs(got - ref) / (scale + 1e-30)
+    assert e.mean() < 2e-5 and np.quantile(e, 0.999) < 5e-3 and e.max() < 5e-2, (e.mean(), e.max())
+    m.close()
+
+
 def test_gradient_matches_fp64_backprop(ctx):
     """Surrogate-sized network 6 -> 4 x 256 -> 1851 on a fixed batch, against
     FP64 backpropagation at the same BF16 weights and inputs, with the hidden
