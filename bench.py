@@ -648,10 +648,11 @@ def surrogate_form(args):
                                              "unit": "TFLOP/s", "frac": achieved / 2.5e15,
                                              "flop_per_entry": flop_per_entry}
             # the same time against HBM: FP32 logits written by the last
-            # product and read twice by the sampler (energy head, position
-            # head), BF16 activations of the hidden layers written and read
+            # product and read by the draw (energy head, position head and
+            # its offset row), the BF16 activations of the last hidden layer
+            # written and read (the hidden layers before it stay on chip)
             c_pad = (n1 + n2 + 127) // 128 * 128
-            bytes_per_entry = 4 * c_pad + 4 * (n1 + 2 * n2) + 2 * 2 * 4 * 256
+            bytes_per_entry = 4 * c_pad + 4 * (n1 + 2 * n2) + 2 * 2 * 256
             bw = sst["entries"] * bytes_per_entry / (sst["ms_network"] * 1e-3)
             out[mode]["network_hbm"] = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                         "frac": bw / HBM_PEAK, "bytes_per_entry": bytes_per_entry}
