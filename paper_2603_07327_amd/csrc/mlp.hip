@@ -218,22 +218,14 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // thread t moves rows (t >> 2) and (t >> 2) + 128, chunk t & 3, of each activation stage
+  // thread t moves rows (t >> 2) and (t >> 2) + 128, chunk t & 3, of each
+  // activation stage
   const int ar = tid >> 2, ac = (tid & 3) * 8;
   const uint16_t *pa = a + (size_t)(m0 + ar) * lda + ac;
   const size_t half = (size_t)128 * lda;
-  uint4 r0 = *(const uint4 *)pa, r1 = *(const uint4 *)(pa + half);
-  *(uint4 *)&sac[ar * kLdsRow + ac] = r0;
-  *(uint4 *)&sac[(ar + 128) * kLdsRow + ac] = r1;
-  __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
-  int q = 0;
-  for (int k0 = 0; k0 < K; k0 += kTk) {
-    const bool more = k0 + kTk < K;
-    if (more) {
-      r0 = *(const uint4 *)(pa + k0 + kTk);
-      r1 = *(const uint4 *)(pa + half + k0 + kTk);
-    }
+  // one K step on LDS stage q: fragments and the 16 products of this wave
+  auto step = [&](int q, int k0) {
     const uint16_t *sa = sac + q * 256 * kLdsRow;
     bf16x8 fa[4], fb[4];
 #pragma unroll
@@ -245,13 +237,47 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-    if (more) {
-      uint16_t *sn = sac + (q ^ 1) * 256 * kLdsRow;
-      *(uint4 *)&sn[ar * kLdsRow + ac] = r0;
-      *(uint4 *)&sn[(ar + 128) * kLdsRow + ac] = r1;
+  };
+  auto stage = [&](int q, uint4 x0, uint4 x1) {
+    uint16_t *sn = sac + q * 256 * kLdsRow;
+    *(uint4 *)&sn[ar * kLdsRow + ac] = x0;
+    *(uint4 *)&sn[(ar + 128) * kLdsRow + ac] = x1;
+  };
+  if (K == kNtKmax) {
+    // all eight chunks into registers at once (8 x 2 x 16 B per thread): the
+    // block waits on memory once instead of once per K step
+    constexpr int kSteps = kNtKmax / kTk;
+    uint4 r0[kSteps], r1[kSteps];
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+      r0[s] = *(const uint4 *)(pa + s * kTk);
+      r1[s] = *(const uint4 *)(pa + half + s * kTk);
     }
+    stage(0, r0[0], r1[0]);
     __syncthreads();
-    q ^= 1;
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+      step(s & 1, s * kTk);
+      if (s + 1 < kSteps) stage((s + 1) & 1, r0[s + 1 < kSteps ? s + 1 : s], r1[s + 1 < kSteps ? s + 1 : s]);
+      __syncthreads();
+    }
+  } else {
+    // the next stage's rows loaded into registers while the current one is multiplied
+    uint4 r0 = *(const uint4 *)pa, r1 = *(const uint4 *)(pa + half);
+    stage(0, r0, r1);
+    __syncthreads();
+    int q = 0;
+    for (int k0 = 0; k0 < K; k0 += kTk) {
+      const bool more = k0 + kTk < K;
+      if (more) {
+        r0 = *(const uint4 *)(pa + k0 + kTk);
+        r1 = *(const uint4 *)(pa + half + k0 + kTk);
+      }
+      step(q, k0);
+      if (more) stage(q ^ 1, r0, r1);
+      __syncthreads();
+      q ^= 1;
+    }
   }
   const int cn = lane & 15, rb4 = (lane >> 4) * 4;
   if constexpr (EPI == EPI_BIAS_F32_STATS) {
@@ -312,6 +338,116 @@ __global__ void __launch_bounds__(512) k_gemm_nt(const uint16_t *__restrict__ a,
           const int m = m0 + wm + 16 * i + rb4 + qq, n = n0 + wn + 16 * j + cn;
           const float v = acc[i][j][qq] + bias[n];
           const size_t o = (size_t)m * ldc + n;
+          if constexpr (EPI == EPI_BIAS_RELU_BF16) ((uint16_t *)out)[o] = f2bf(fmaxf(v, 0.0f));
+          else ((float *)out)[o] = v;
+        }
+  }
+}
+
+// The forward products with K = 256 on a persistent grid: a block keeps the
+// weight slab of one 128-column block in LDS and walks a sequence of 256-row
+// tiles, so the slab is loaded once per block instead of once per tile, and
+// the next tile's activation chunks are loaded into registers as the current
+// tile's are staged (each chunk register is refilled right after its stage
+// store), so the loads overlap the products and the epilogue.  Per XCD (the
+// blocks b = x mod 8) the first nbx * groups blocks form `groups` groups of
+// the nbx column blocks; group g of XCD x takes row tiles x groups + g,
+// stepping by 8 groups: the column blocks of a row tile run on one XCD at
+// about the same time, so its activation rows come from HBM once per XCD.
+// Same operand fragments, K order and epilogue as k_gemm_nt: same output.
+template <int EPI>
+__global__ void __launch_bounds__(512) k_gemm_nt_rows(const uint16_t *__restrict__ a, int lda,
+                                                      const uint16_t *__restrict__ b, int ldb,
+                                                      const float *__restrict__ bias, void *__restrict__ out,
+                                                      int ldc, int nbx, int groups, int row_tiles) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_nt[];
+  uint16_t *sbw = lds_nt;                   // 128 x kNtRowB weight slab
+  uint16_t *sac = lds_nt + 128 * kNtRowB;   // 2 x 256 x kLdsRow activation stages
+  const int x = (int)(blockIdx.x & 7u), kk = (int)(blockIdx.x >> 3);
+  if (kk >= nbx * groups) return; // (a whole block: no barrier is left waiting)
+  const int g = kk / nbx, bx = kk - g * nbx;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n0 = bx * 128;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  constexpr int K = kNtKmax, kc = K / 8;
+  for (int t = tid; t < 128 * kc; t += 512) {
+    const int r = t / kc, c = (t - r * kc) * 8;
+    *(uint4 *)&sbw[r * kNtRowB + c] = *(const uint4 *)&b[(size_t)(n0 + r) * ldb + c];
+  }
+  const int ar = tid >> 2, ac = (tid & 3) * 8;
+  const size_t half = (size_t)128 * lda;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int cn = lane & 15, rb4 = (lane >> 4) * 4;
+  const int stride = 8 * groups;
+  int by = x * groups + g;
+  if (by >= row_tiles) return; // (uniform per block; the slab loads above need no barrier)
+  constexpr int kSteps = K / kTk;
+  uint4 r0[kSteps], r1[kSteps];
+  {
+    const uint16_t *pa = a + (size_t)(by * 256 + ar) * lda + ac;
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+      r0[s] = *(const uint4 *)(pa + s * kTk);
+      r1[s] = *(const uint4 *)(pa + half + s * kTk);
+    }
+  }
+  for (; by < row_tiles; by += stride) {
+    const int nby = by + stride;
+    const bool next = nby < row_tiles;
+    const uint16_t *pn = a + (size_t)((next ? nby : by) * 256 + ar) * lda + ac;
+    auto stage = [&](int q, uint4 x0, uint4 x1) {
+      uint16_t *sn = sac + q * 256 * kLdsRow;
+      *(uint4 *)&sn[ar * kLdsRow + ac] = x0;
+      *(uint4 *)&sn[(ar + 128) * kLdsRow + ac] = x1;
+    };
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // each chunk register is refilled with the next tile's chunk right after its stage store
+    stage(0, r0[0], r1[0]);
+    if (next) {
+      r0[0] = *(const uint4 *)pn;
+      r1[0] = *(const uint4 *)(pn + half);
+    }
+    __syncthreads(); // (the first time: also the weight slab)
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+      const uint16_t *sa = sac + (s & 1) * 256 * kLdsRow;
+      bf16x8 fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        fa[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sa[(wm + 16 * i + fr) * kLdsRow + fk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        fb[j] = __builtin_bit_cast(bf16x8, *(const uint4 *)&sbw[(wn + 16 * j + fr) * kNtRowB + s * kTk + fk]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      if (s + 1 < kSteps) {
+        const int sn = s + 1 < kSteps ? s + 1 : s;
+        stage(sn & 1, r0[sn], r1[sn]);
+        if (next) {
+          r0[sn] = *(const uint4 *)(pn + sn * kTk);
+          r1[sn] = *(const uint4 *)(pn + half + sn * kTk);
+        }
+      }
+      __syncthreads();
+    }
+    const size_t m0 = (size_t)by * 256;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const size_t m = m0 + wm + 16 * i + rb4 + qq;
+          const int n = n0 + wn + 16 * j + cn;
+          const float v = acc[i][j][qq] + bias[n];
+          const size_t o = m * ldc + n;
           if constexpr (EPI == EPI_BIAS_RELU_BF16) ((uint16_t *)out)[o] = f2bf(fmaxf(v, 0.0f));
           else ((float *)out)[o] = v;
         }
@@ -423,6 +559,13 @@ static void gemm(const uint16_t *a, int lda, const uint16_t *b, int ldb, int M, 
                  size_t a_lo = 0, int k_half = 0) {
   if constexpr (!AT && !BT && (EPI == EPI_BIAS_RELU_BF16 || EPI == EPI_BIAS_F32)) {
     if (M % 256 == 0 && N % 128 == 0 && K % kTk == 0 && K <= kNtKmax) {
+      // many row tiles per column block and K = 256: the persistent grid
+      const int nbx = N / 128, row_tiles = M / 256, groups = nbx <= 32 ? 32 / nbx : 0;
+      if (K == kNtKmax && groups > 0 && row_tiles >= 4 * 8 * groups) {
+        hipLaunchKernelGGL(k_gemm_nt_rows<EPI>, dim3(256), dim3(512), kNtLds, st, a, lda, b, ldb, bias, out, ldc, nbx,
+                           groups, row_tiles);
+        return;
+      }
       hipLaunchKernelGGL(k_gemm_nt<EPI>, dim3((N / 128) * (M / 256)), dim3(512), kNtLds, st, a, lda, b, ldb, K, bias,
                          out, ldc, (float2 *)nullptr, 0, N / 128);
       return;
