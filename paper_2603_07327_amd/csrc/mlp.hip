@@ -26,7 +26,9 @@ constexpr int kTile = 64;     // input width padding
 constexpr int kRowPad = 256;   // padding of rows (256-row product tiles)
 constexpr int kWidthPad = 128; // padding of layer widths (128-column product tiles)
 constexpr int kTk = 32;
-constexpr int kLdsRow = kTk + 8; // bf16 per LDS row (padding against bank conflicts)
+// bf16 per LDS row: with 16 of padding the products' LDS bank-conflict
+// cycles are half those with 8 or 24
+constexpr int kLdsRow = kTk + 16;
 constexpr int kTableSlices = 16; // row slices of the offset-table gradient
 
 // float -> bfloat16 bits, round to nearest even
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t *__restrict__ a, in
 // double-buffered 256 x 32 LDS stage (one barrier per K step), the next
 // stage's rows loaded into registers while the current one is multiplied.
 constexpr int kNtKmax = 256;
-constexpr int kNtRowB = kNtKmax + 8; // bf16 per weight-slab row in LDS
+constexpr int kNtRowB = kNtKmax + 16; // bf16 per weight-slab row in LDS
 constexpr size_t kNtLds = (size_t)(128 * kNtRowB + 2 * 256 * kLdsRow) * sizeof(uint16_t);
 
 // EPI_BIAS_F32_STATS also writes, per row and 128-column block, the maximum
@@ -464,7 +466,7 @@ __global__ void __launch_bounds__(512) k_gemm_nt_rows(const uint16_t *__restrict
 // layer's activations go back to HBM.
 constexpr int kStackRows = 128;
 constexpr int kStackWidth = 256;
-constexpr int kStackRowA = kStackWidth + 8; // bf16 per activation row in LDS
+constexpr int kStackRowA = kStackWidth + 16; // bf16 per activation row in LDS
 constexpr int kStackMax = 8;                // hidden layers
 constexpr size_t kStackLds = (size_t)(kStackRows * kStackRowA + 2 * kStackWidth * kLdsRow) * sizeof(uint16_t);
 
