@@ -1157,12 +1157,17 @@ __global__ void k_window_flags(size_t n, const float *energy, const uint32_t *s_
   pos[i] = in;
 }
 
-__global__ void k_time_keys(size_t n, const uint32_t *win, const uint32_t *pos, const unsigned long long *s_time,
+// pos: the exclusive scan of the 0/1 window flags (in the window and not
+// lost) over the n singles, `total` their sum; single i is flagged exactly
+// when the scan steps by one after it, so the flags themselves are not read
+__global__ void k_time_keys(size_t n, const uint32_t *pos, uint32_t total, const unsigned long long *s_time,
                             const uint32_t *s_inst, int time_bits, unsigned long long *key, uint32_t *val) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || win[i] != 1u || pos[i] >= n) return; // in the window and not lost
-  key[pos[i]] = time_bits < 64 ? ((unsigned long long)s_inst[i] << time_bits) | s_time[i] : s_time[i];
-  val[pos[i]] = (uint32_t)i;
+  if (i >= n) return;
+  const uint32_t p = pos[i], q = i + 1 < n ? pos[i + 1] : total;
+  if (q - p != 1u || p >= total) return;
+  key[p] = time_bits < 64 ? ((unsigned long long)s_inst[i] << time_bits) | s_time[i] : s_time[i];
+  val[p] = (uint32_t)i;
 }
 
 // coincidences of the cluster starting at sorted position k (k must be a head)
@@ -1181,7 +1186,8 @@ __device__ __forceinline__ uint32_t resolve_cluster(size_t k, size_t n, const un
     while (j < end && t[j] - t[i] <= W) ++j;
     if (j - i == 2) {
       const uint32_t a = idx[i], b = idx[i + 1];
-      const uint32_t cpp = cpp_of[s_inst[a]]; // a window never spans two instances
+      // a window never spans two instances (s_inst null: one instance)
+      const uint32_t cpp = cpp_of[s_inst ? s_inst[a] : 0u];
       if (s_gid[a] / cpp != s_gid[b] / cpp) {
         if (WRITE && out + c < cap) {
           first[out + c] = a;
@@ -1782,14 +1788,15 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   const int tb = ni > 1 ? time_bits : 64;
   const unsigned long long t_mask = time_bits < 64 ? (1ull << time_bits) - 1 : ~0ull;
 
-  // 4-5. The singles flagged in `win` (exclusive scan of the flags in wpos,
+  // 4-5. The singles of a window (wpos: the exclusive scan of its flags,
   // nwin of them) in (instance, time, index) order, split into clusters and
   // paired.  list: write the coincidence list (count in rb[7]); otherwise
   // count the coincidences per instance into rb_count.  make_flags() rebuilds
-  // win and wpos if the pairing overwrote them (flag doubles as both).
-  auto pair_window = [&](const uint32_t *win, size_t nwin, bool list, auto &&make_flags) -> int {
-    hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, win, wpos,
-                       (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
+  // wpos if the pairing overwrote it (flag doubles as the window's flags and
+  // the pair counts).
+  auto pair_window = [&](size_t nwin, bool list, auto &&make_flags) -> int {
+    hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, (const uint32_t *)wpos,
+                       (uint32_t)nwin, (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
     std::vector<uint64_t> witems(ni, nwin);
     if (ni > 1) {
       launch_fill_u32(d_icount, 0u, ni, st);
@@ -1802,11 +1809,12 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     const unsigned long long *tk = sb.k1;
     const uint32_t *ti = sb.v1;
     auto count_pairs = [&]() {
-      hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nwin)), dim3(256), 0, st, nwin, tk, ti, S->gid, s_inst, IT.cpp,
+      const uint32_t *c_inst = ni > 1 ? s_inst : nullptr;
+      hipLaunchKernelGGL(k_coinc_count, dim3(grid_for(nwin)), dim3(256), 0, st, nwin, tk, ti, S->gid, c_inst, IT.cpp,
                          D.window_ps, flag);
       if (list) {
         exclusive_scan(flag, nwin, sb.scan_tmp, st, rb + 7);
-        hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nwin)), dim3(256), 0, st, nwin, tk, ti, S->gid, s_inst,
+        hipLaunchKernelGGL(k_coinc_write, dim3(grid_for(nwin)), dim3(256), 0, st, nwin, tk, ti, S->gid, c_inst,
                            IT.cpp, D.window_ps, flag, C->first, C->second, C->capacity);
       } else {
         launch_fill_u32(d_icount, 0u, ni, st);
@@ -1833,8 +1841,8 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     if (!sync("in coincidence sorting")) return GPET_ERR_HIP;
     if (mapped_t && rbh[12]) { // a bucket overflowed LDS: rebuild the keys, sort every bit, redo the pairing
       make_flags();
-      hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, win, wpos,
-                         (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
+      hipLaunchKernelGGL(k_time_keys, dim3(grid_for(ns)), dim3(256), 0, st, (size_t)ns, (const uint32_t *)wpos,
+                         (uint32_t)nwin, (const unsigned long long *)S->time_ps, s_inst, tb, sb.k0, sb.v0);
       const bool f2 = radix_sort(sb, nwin, time_bits + inst_bits, st);
       tk = f2 ? sb.k1 : sb.k0;
       ti = f2 ? sb.v1 : sb.v0;
@@ -1846,7 +1854,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
 
   // the main window: the coincidence list
   if (nw > 0) {
-    const int r = pair_window(S->in_window, nw, true, [] {});
+    const int r = pair_window(nw, true, [] {});
     if (r != GPET_OK) return r;
     C->count = rbh[7];
     if (C->count > C->capacity) {
@@ -1878,7 +1886,7 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
     if (!sync("in the window sweep")) return GPET_ERR_HIP;
     const size_t nsw = rbh[3];
     if (nsw == 0) continue;
-    const int r = pair_window(flag, nsw, false, make_flags);
+    const int r = pair_window(nsw, false, make_flags);
     if (r != GPET_OK) return r;
     for (size_t i = 0; i < ni; ++i) D.sweep_out[w * ni + i] = rbh_count[i];
   }
