@@ -179,7 +179,10 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &M, unsigned long 
   const bool one = M.n_inst == 1;
   const float sc = one ? M.scale0 : M.scale[i];
   const uint32_t cnt = one ? M.count0 : M.count[i], base = one ? M.base0 : M.base[i];
-  const uint32_t b = min((uint32_t)((float)v * sc), cnt - 1u);
+  // (a local value below 2^32, such as an event index, converts from 32 bits:
+  // the same float as from 64)
+  const float fv = M.local_mask >> 32 ? (float)v : (float)(uint32_t)v;
+  const uint32_t b = min((uint32_t)(fv * sc), cnt - 1u);
   return base + b;
 }
 
@@ -362,6 +365,10 @@ struct HitSrc {
   InstTab T;
   int gid_bits, inst_shift;
   uint32_t *err; // set to 2 for a hit whose ids lie outside its instance
+  // one: a single instance, whose first event, event count and crystal count
+  // come here, so that the checks take no per-lane table loads
+  bool one;
+  uint32_t first0, n_events0, ncr0;
 };
 
 // key = instance | (event - first) | gid | photon | index of the hit within its
@@ -369,6 +376,16 @@ struct HitSrc {
 // Hits outside their instance's event range or with a crystal id outside the
 // instance's scanner are flagged (*H.err = 2).
 __device__ __forceinline__ unsigned long long hit_key(const HitSrc &H, size_t i) {
+  if (H.one) { // the same checks and key with the table values in scalars
+    const uint32_t a = H.aux[i], g = H.gid[i], in = H.inst ? H.inst[i] : 0u;
+    const uint32_t low = ((a & 1u) << 7) | min(a >> 8, 127u);
+    uint32_t e = H.ev[i] - H.first0;
+    if (in != 0u || e >= H.n_events0 || g >= H.ncr0 || (H.gid_bits < 32 && (g >> H.gid_bits) != 0)) {
+      *H.err = 2u;
+      e = 0;
+    }
+    return ((((unsigned long long)e << H.gid_bits) | (g & ((1ull << H.gid_bits) - 1))) << 8) | low;
+  }
   const InstTab &T = H.T;
   const uint32_t in = H.inst ? H.inst[i] : 0u;
   const uint32_t a = H.aux[i];
@@ -1563,7 +1580,8 @@ int run_digitize(DigitizeArgs &D, DigitizeScratch &scr, hipStream_t st, std::str
   //    the bucket count and scatter build the keys from the hits themselves;
   //    the key array (k0, v0) is written only when a full radix sort needs it.
   uint32_t *err_flag = rb + 13; // checked at the next synchronization
-  const HitSrc HS{D.h_event, D.h_gid, D.h_aux, D.h_inst, IT, D.gid_bits, inst_shift, err_flag};
+  const HitSrc HS{D.h_event, D.h_gid, D.h_aux, D.h_inst, IT, D.gid_bits, inst_shift, err_flag,
+                  ni == 1, ni == 1 ? D.first[0] : 0u, ni == 1 ? D.n_events[0] : 0u, ni == 1 ? D.ncr[0] : 0u};
   bool keys_built = false;
   auto build_keys = [&]() {
     if (!keys_built)
