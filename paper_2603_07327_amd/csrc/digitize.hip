@@ -179,9 +179,14 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &M, unsigned long 
   const bool one = M.n_inst == 1;
   const float sc = one ? M.scale0 : M.scale[i];
   const uint32_t cnt = one ? M.count0 : M.count[i], base = one ? M.base0 : M.base[i];
-  // (a local value below 2^32, such as an event index, converts from 32 bits:
-  // the same float as from 64)
-  const float fv = M.local_mask >> 32 ? (float)v : (float)(uint32_t)v;
+  // The map only has to be non-decreasing in the key (each bucket is then
+  // sorted by key and value, so any such map gives the same order).  A value
+  // of 32 bits or more is taken as hi 2^32 + lo in one FMA of its two halves
+  // converted to FP32: below 2^56 the high half converts exactly, above it the
+  // low half is under half an ULP, and rounding is monotone either way.
+  const float fv = M.local_mask >> 32
+                       ? fmaf((float)(uint32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v)
+                       : (float)(uint32_t)v;
   const uint32_t b = min((uint32_t)(fv * sc), cnt - 1u);
   return base + b;
 }
@@ -424,14 +429,16 @@ __global__ void k_hit_keys(size_t n, HitSrc H, unsigned long long *key, uint32_t
 constexpr int kLocalSort = 1024; // largest bucket sorted in LDS
 constexpr int kBucketMean = 48;  // target items per bucket: most fit one per lane
 
-// lanes of the wave whose value equals this lane's (one ballot per distinct value)
+// lanes of the wave whose value equals this lane's (one ballot per distinct
+// value; the leader's value is read as a wave-uniform lane read)
 __device__ __forceinline__ uint64_t equal_peers(uint32_t v, bool valid) {
   uint64_t left = __ballot(valid), mine = 0;
   while (left) {
     const int leader = __ffsll((unsigned long long)left) - 1;
-    const uint32_t lv = __shfl(v, leader);
-    const uint64_t m = __ballot(valid && v == lv) & left;
-    if (valid && v == lv) mine = m;
+    const uint32_t lv = __builtin_amdgcn_readlane(v, leader);
+    const bool eq = valid && v == lv;
+    const uint64_t m = __ballot(eq); // (every lane of this value is still left)
+    if (eq) mine = m;
     left &= ~m;
   }
   return mine;
