@@ -541,8 +541,23 @@ __device__ __forceinline__ bool pair_less(unsigned long long ka, uint32_t va, un
   return ka < kb || (ka == kb && va < vb);
 }
 
+// lane_xor for the sorting networks: the DPP forms as plain DPP moves (every
+// lane reads a lane that exists, so no old value has to be set up first)
+__device__ __forceinline__ uint32_t lane_xor_mov(uint32_t x, int lx) {
+  switch (lx) {
+  case 1:
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false); // quad_perm [1,0,3,2]
+  case 2:
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false); // quad_perm [2,3,0,1]
+  case 8:
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false); // row_ror:8
+  default:
+    return lane_xor(x, lx);
+  }
+}
+
 __device__ __forceinline__ unsigned long long lane_xor_u64(unsigned long long x, int lx) {
-  const uint32_t lo = lane_xor((uint32_t)x, lx), hi = lane_xor((uint32_t)(x >> 32), lx);
+  const uint32_t lo = lane_xor_mov((uint32_t)x, lx), hi = lane_xor_mov((uint32_t)(x >> 32), lx);
   return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -620,7 +635,10 @@ __device__ __forceinline__ bool wave_sort_packed(unsigned long long (&k)[2], uin
 }
 
 constexpr int kWaveSort = 128;   // largest bucket sorted by one wave
-constexpr int kWaveBuckets = 4;  // consecutive buckets per wave
+// consecutive buckets per wave: with one, the network's constant lane masks
+// are made where they are used (a loop over several buckets kept them live
+// across it and spilled them to vector lanes)
+constexpr int kWaveBuckets = 1;
 
 // a bucket of up to 64 items goes one per lane, up to 128 two per lane
 __device__ __forceinline__ void wave_load_bucket(const unsigned long long *key, const uint32_t *val, uint32_t lo,
@@ -637,8 +655,8 @@ __device__ __forceinline__ void wave_load_bucket(const unsigned long long *key, 
   }
 }
 
-// kWaveBuckets consecutive buckets per wave, the next one loading while the
-// current one sorts; bucket b spans [start[b], start[b + 1]).  Buckets a wave
+// kWaveBuckets consecutive buckets per wave (with more than one, the next one
+// loading while the current one sorts); bucket b spans [start[b], start[b + 1]).  Buckets a wave
 // cannot take (over 128 items, keys spanning 2^32 or more) are listed in big[]
 // (count in *n_big) for the block sort.  Values are below 2^vbits (1..32).
 // heads (may be null): for keys whose runs of equal key >> head_shift never
